@@ -1,0 +1,248 @@
+"""Benchmark of the spectral-element Poisson hot path on one MI355X.
+
+Workload: 32 x 32 x 32 hexahedral elements of order N = 7 (512 GLL nodes per
+element, 16,777,216 local nodes, 11,390,625 unique nodes) on the unit cube
+mapped by x + 0.05 (sin 2 pi y sin 2 pi z, and cyclic).
+
+* value: FP64 sem_ax throughput in G local DOF/s (local nodes / s), inputs
+  resident in HBM; one step = one application of the local operator to the
+  whole mesh (the kernel the paper times in section 4.2.2).
+* roofline: the operator kernel's average launch duration from HIP events on
+  the launch stream; algorithmic bytes 64 B per local node (u 8 + six
+  geometric factors 48 + w 8) against the 8 TB/s HBM peak.
+* pcg: wall time to relative residual 1e-8 of plain FP64 Jacobi-PCG and of
+  FP64 refinement around FP32 / BF16-operator inner PCG, same mesh, RHS from
+  8 random Fourier modes (seed 0).
+* cpu_baseline: the FP64 CPU oracle's operator on a bounded sample of the
+  same mesh (test infrastructure, timed here only as a reported baseline).
+
+    python bench.py [--gpus 1] [--steps 100] [--warmup 10]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = {"f64": 64, "f32": 32, "bf16": 18}
+NE, ORDER = 32, 7
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ax_fp64_32x32x32_N7_traffic.txt")
+AX_SRC = os.path.join(ROOT, "paper_1403_0968_amd", "csrc", "ax.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def ax_source_hash():
+    with open(AX_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(n_local):
+    """HBM bytes per operator launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on another version of the kernel."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("ax_source_sha256_16") != ax_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_input(sem, torch, h, nL, nG, seed=0):
+    """Continuous random u_L = Q U, U ~ U[-1,1) on unique nodes."""
+    from seminputs import uniform
+    l2g = torch.empty(nL, dtype=torch.int32, device="cuda")
+    sem.sem_export(h, sem.SEM_ARR_L2G, l2g)
+    U = torch.as_tensor(uniform(nG, seed=seed), device="cuda")
+    return U[l2g.long()].contiguous()
+
+
+def time_ax(sem, torch, h, prec, u, w, steps, warmup):
+    for _ in range(warmup):
+        sem.sem_ax(h, prec, u, w)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sem.sem_ax(h, prec, u, w)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps  # ms per launch
+
+
+def bench_pcg(sem, torch, h, nL, rtol=1e-8):
+    from seminputs import fourier_modes
+    k, a, phi = fourier_modes(seed=0)
+    b = torch.empty(nL, dtype=torch.float64, device="cuda")
+    sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, (k, a, phi))
+    out = {}
+    for name, prec in (("fp64_jacobi_pcg", sem.SEM_FP64),
+                       ("fp32_ir_jacobi_pcg", sem.SEM_FP32),
+                       ("bf16_ir_jacobi_pcg", sem.SEM_BF16)):
+        best = None
+        for rep in range(2):  # first solve also instantiates graphs
+            x = torch.zeros_like(b)
+            st = sem.sem_pcg_solve(h, b, x, rtol=rtol, maxit=20000,
+                                   inner_prec=prec, inner_rtol=5e-2,
+                                   check_every=32, use_graph=1,
+                                   raise_on_fail=False)
+            torch.cuda.synchronize()
+            if best is None or st["seconds"] < best["seconds"]:
+                best = st
+        out[name] = {"time_to_rtol_s": best["seconds"], "iters": best["iters"],
+                     "outer": best["outer_iters"],
+                     "final_rel_res_fp64": best["final_rel_res"],
+                     "status": best["status"]}
+        log(f"[pcg] {name}: {out[name]}")
+    out["rtol"] = rtol
+    return out
+
+
+def cpu_baseline(budget_s=15.0):
+    """Oracle operator on the first elements of the same mesh, all host
+    threads the oracle uses; repeated until about budget_s of CPU time."""
+    import numpy as np
+    from oracle import oracle as orc
+    from seminputs import uniform
+    E_s = 2048
+    N = ORDER
+    xi, wq = orc.gll(N)
+    D = orc.dmat(N, xi)
+    X = orc.coords(N, NE, NE, NE, orc.MAP_SINE_CYCLIC, xi)
+    n3 = (N + 1) ** 3
+    Xs = np.ascontiguousarray(X[:, : E_s * n3])
+    G, _, _ = orc.geom(N, E_s, wq, D, Xs)
+    u = uniform(E_s * n3, seed=0)
+    orc.ax_raw(N, D, G, u)  # warm
+    reps, t = 0, 0.0
+    t0 = time.perf_counter()
+    while t < budget_s:
+        orc.ax_raw(N, D, G, u)
+        reps += 1
+        t = time.perf_counter() - t0
+    nodes = reps * E_s * n3
+    return {"value": nodes / t / 1e9, "unit": "GDOF/s", "cores": orc.num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 oracle operator on the first {E_s} of the 32768 "
+                      f"elements of the same mesh, {reps} repetitions, {t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-pcg", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ax-only", action="store_true",
+                    help="only the FP64 operator launches (for counter runs)")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="run a plain device copy of this many bytes instead")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not "
+              f"supported (the operator would shard by element slabs, see "
+              f"DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1403_0968_amd import sem
+    sem.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    if args.copy_bytes > 0:
+        n = args.copy_bytes // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(max(1, args.steps)):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[copy] {args.steps} copies of {n * 8} bytes")
+        return
+
+    log(f"[bench] setup {NE}^3 elements N={ORDER} sine-cyclic mapping")
+    t0 = time.perf_counter()
+    h = sem.sem_setup(ORDER, NE, NE, NE, mapping=sem.SEM_MAP_SINE_CYCLIC)
+    setup_s = time.perf_counter() - t0
+    E, nL, nG = sem.sem_query(h)
+    log(f"[bench] setup {setup_s:.2f} s: E={E} nL={nL} nG={nG}")
+    u = make_input(sem, torch, h, nL, nG)
+    w = torch.empty_like(u)
+
+    ms = time_ax(sem, torch, h, sem.SEM_FP64, u, w, args.steps, args.warmup)
+    log(f"[bench] fp64 sem_ax {ms * 1e3:.1f} us/launch")
+    if args.ax_only:
+        sem.sem_destroy(h)
+        return
+    gdofs = nL / (ms * 1e-3) / 1e9
+    achieved = BYTES_PER_NODE["f64"] * nL / (ms * 1e-3) / 1e9
+    traffic = read_traffic(nL)
+
+    extra = {}
+    u32 = u.float()
+    w32 = torch.empty_like(u32)
+    ms32 = time_ax(sem, torch, h, sem.SEM_FP32, u32, w32, args.steps, args.warmup)
+    ub = (u32.view(torch.int32) + 0x7FFF + ((u32.view(torch.int32) >> 16) & 1)) >> 16
+    ub = ub.to(torch.int16).contiguous()
+    msb = time_ax(sem, torch, h, sem.SEM_BF16, ub, w32, args.steps, args.warmup)
+    for name, t_ms, key in (("fp32", ms32, "f32"), ("bf16", msb, "bf16")):
+        extra[f"sem_ax_{name}"] = {
+            "us_per_launch": t_ms * 1e3, "gdofs": nL / (t_ms * 1e-3) / 1e9,
+            "alg_GBs": BYTES_PER_NODE[key] * nL / (t_ms * 1e-3) / 1e9,
+            "frac_hbm": BYTES_PER_NODE[key] * nL / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        log(f"[bench] {name} sem_ax {t_ms * 1e3:.1f} us/launch")
+
+    pcg = None if args.no_pcg else bench_pcg(sem, torch, h, nL)
+    sem.sem_destroy(h)
+    cpu = None if args.no_cpu else cpu_baseline()
+    if cpu:
+        log(f"[bench] cpu baseline {cpu}")
+
+    rec = {
+        "metric": "sem_ax GDOF/s & %HBM roofline; PCG time-to-1e-8: plain vs mixed+learned",
+        "value": gdofs,
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "sem_ax FP64, 32^3 hex elements, N=7, sine-cyclic "
+                               "mapped unit cube, random continuous input",
+                   "elements": E, "order": ORDER, "n_local": nL, "n_global": nG},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic},
+        "cpu_baseline": cpu,
+        "sem_ax_low_precision": extra,
+        "pcg": pcg,
+        "setup_s": setup_s,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * sem.h -- C ABI of libsem.so, an MI355X (gfx950) implementation of the
+ * spectral-element Poisson operator and its preconditioned CG solve from
+ * Medina, St-Cyr & Warburton, "OCCA: A unified approach to multi-threading
+ * languages" (arXiv 1403.0968), section 4.2.
+ *
+ * Problem (section 4.2, equation semPDE):  -div(kappa grad u) + alpha u = f
+ * on the image of the unit cube, discretised (section 4.2.1, equation
+ * semOperator) with continuous piecewise tensor-product polynomials of degree
+ * N on hexahedra, Lagrange basis on the (N+1) Gauss-Lobatto-Legendre points
+ * per direction, GLL quadrature, and homogeneous Dirichlet conditions imposed
+ * by masking.  alpha must be 0 in this version.
+ *
+ * Conventions shared by every call:
+ *   - n1 = N+1; element e = ex + Ex*(ey + Ey*ez); element-local node
+ *     (i,j,k), i fastest; local ("E-vector") index
+ *     l = e*n1^3 + i + n1*j + n1^2*k; n_local = E*n1^3.
+ *   - global (unique) node g = (ex*N+i) + Gx*((ey*N+j) + Gy*(ez*N+k)),
+ *     Gd = Ed*N+1; n_global = Gx*Gy*Gz.
+ *   - Vectors passed to the calls are DEVICE pointers owned by the caller,
+ *     contiguous, 256-byte aligned is recommended, in E-vector layout.
+ *     Their element type is set by the sem_precision argument:
+ *     SEM_FP64 -> double, SEM_FP32 -> float, SEM_BF16 -> bfloat16 stored as
+ *     uint16_t (round-to-nearest-even of the float), outputs in float.
+ *   - `stream` is a hipStream_t (cast to void*); NULL means the null
+ *     (default) stream.  Every call is asynchronous on that stream unless
+ *     stated otherwise.
+ *   - Every function returns a sem_status; nothing aborts or throws across
+ *     the ABI.  sem_last_error() returns the text of the last failure of the
+ *     calling thread.
+ *   - One handle must not be used by two host threads at once.
+ */
+#ifndef SEM_H
+#define SEM_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_ERR_ARG = 1,            /* invalid argument (null, size, range) */
+  SEM_ERR_HIP = 2,            /* a HIP runtime call failed */
+  SEM_ERR_OOM = 3,            /* device allocation failed */
+  SEM_ERR_NOT_CONVERGED = 4,  /* solver hit maxit */
+  SEM_ERR_BREAKDOWN = 5,      /* p^T A p <= 0, NaN or Inf in the solver */
+  SEM_ERR_STATE = 6           /* call not valid for this handle */
+} sem_status;
+
+typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_BF16 = 2 } sem_precision;
+typedef enum { SEM_PC_NONE = 0, SEM_PC_JACOBI = 1 } sem_precond;
+typedef enum {
+  SEM_MAP_AFFINE = 0,      /* the unit cube itself */
+  SEM_MAP_SINE_X = 1,      /* X = (x + 0.05 s(y)s(z), y, z), s(t) = sin(2 pi t) */
+  SEM_MAP_SINE_CYCLIC = 2  /* X = x + 0.05 (s(y)s(z), s(z)s(x), s(x)s(y)) */
+} sem_mapping;
+
+typedef struct sem_handle sem_handle; /* opaque, owned by the library */
+
+/* Mesh and coefficients.  All pointers here are HOST pointers, read during
+ * sem_setup only. */
+typedef struct {
+  int32_t N;            /* polynomial order, 1..8 */
+  int32_t ex, ey, ez;   /* elements per direction, >= 1 */
+  int32_t dirichlet;    /* 1: homogeneous Dirichlet on the 6 outer faces;
+                           0: pure Neumann (operator checks only) */
+  int32_t mapping;      /* a sem_mapping */
+  double alpha;         /* mass coefficient of semPDE; must be 0 */
+  /* kappa(X) = exp(sigma sqrt(2/M) sum_m cos(omega_m . X + b_m)) when
+   * kappa_nfeat = M > 0 (random Fourier features of a Gaussian field),
+   * kappa = 1 when kappa_nfeat == 0. */
+  int32_t kappa_nfeat;
+  const double *kappa_omega; /* [M][3] */
+  const double *kappa_b;     /* [M] */
+  double kappa_sigma;
+} sem_mesh_desc;
+
+/* Right-hand side f(X) for sem_rhs.  HOST pointers. */
+typedef enum {
+  SEM_SRC_FOURIER = 0, /* f = sum_m a_m cos(2 pi k_m . X + phi_m) */
+  SEM_SRC_SINE = 1     /* f = 3 pi^2 sin(pi x) sin(pi y) sin(pi z) */
+} sem_source_kind;
+typedef struct {
+  int32_t kind;
+  int32_t nmodes;      /* SEM_SRC_FOURIER: number of modes (<= 64) */
+  const double *k;     /* [nmodes][3] wave vectors */
+  const double *a;     /* [nmodes] amplitudes */
+  const double *phi;   /* [nmodes] phases */
+} sem_source;
+
+typedef struct {
+  double rtol;          /* stop when ||b - A x||_2 <= rtol ||b||_2, norms over
+                           unique nodes (Dirichlet entries are zero) */
+  int32_t maxit;        /* CG iterations (inner iterations summed for IR) */
+  int32_t pc;           /* a sem_precond */
+  int32_t inner_prec;   /* SEM_FP64: plain FP64 PCG.  SEM_FP32 / SEM_BF16:
+                           FP64 iterative refinement whose inner PCG uses
+                           FP32 vectors and an FP32 / BF16-stored operator,
+                           with FP64 dot products and scalars */
+  double inner_rtol;    /* inner relative tolerance for refinement */
+  int32_t check_every;  /* CG iterations between host convergence polls */
+  int32_t use_graph;    /* 1: replay a captured HIP graph of check_every
+                           iterations; 0: launch kernels directly */
+} sem_solve_opts;
+
+typedef struct {
+  int32_t iters;              /* CG iterations (all inner ones for IR) */
+  int32_t outer_iters;        /* refinement steps (0 for plain PCG) */
+  int32_t status;             /* sem_status of the solve */
+  int32_t reserved;
+  double final_rel_res;       /* recomputed FP64 ||b - A x|| / ||b|| */
+  double seconds;             /* wall time of the solve on the stream */
+} sem_solve_stats;
+
+/* Build a handle: reference element (GLL nodes, weights, derivative matrix),
+ * global-local maps (section 4.2.1, distinct global-local numbering),
+ * coordinates and the six geometric factors per node (G_ab =
+ * w_i w_j w_k J kappa grad r_a . grad r_b, the G^T G metric of section 4.2.1
+ * precomputed per elemental node, FP64 with FP32/BF16 copies), the lumped
+ * mass B = w_i w_j w_k J and the Jacobi diagonal.  Synchronises `stream`
+ * before returning.  On failure *out is NULL. */
+sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_handle **out);
+sem_status sem_destroy(sem_handle *h);
+
+/* Sizes of the discretisation. */
+sem_status sem_query(const sem_handle *h, int64_t *n_elements,
+                     int64_t *n_local, int64_t *n_global);
+
+/* Copy an internal array into caller device memory `dst` of `dst_bytes`
+ * bytes (SEM_ERR_ARG when too small).  Layouts:
+ *   SEM_ARR_L2G     int32 [n_local]   global id of each local node
+ *   SEM_ARR_PERM    int32 [n_local]   local ids sorted by (global id, local id)
+ *   SEM_ARR_OFFSETS int32 [n_global+1] start of each global id in PERM
+ *   SEM_ARR_MULT    int32 [n_local]   number of copies of the node
+ *   SEM_ARR_MASK    uint8 [n_local]   1 on Dirichlet nodes
+ *   SEM_ARR_COORDS  double [3][n_local] physical x, y, z blocks
+ *   SEM_ARR_GEOM    double [E][6][n1^3] (rr, rs, rt, ss, st, tt)
+ *   SEM_ARR_MASS    double [n_local]   lumped mass B (unassembled)
+ *   SEM_ARR_DIAG    double [n_local]   unassembled local-matrix diagonal
+ *   SEM_ARR_DINV    double [n_global]  inverse assembled diagonal, 0 on
+ *                                      Dirichlet nodes */
+typedef enum {
+  SEM_ARR_L2G = 0, SEM_ARR_PERM = 1, SEM_ARR_OFFSETS = 2, SEM_ARR_MULT = 3,
+  SEM_ARR_MASK = 4, SEM_ARR_COORDS = 5, SEM_ARR_GEOM = 6, SEM_ARR_MASS = 7,
+  SEM_ARR_DIAG = 8, SEM_ARR_DINV = 9
+} sem_array;
+sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
+                      int64_t dst_bytes, void *stream);
+
+/* Local stiffness action w_L = A_L u_L, element by element, unassembled and
+ * unmasked: the factored operator of section 4.2.1 (last display),
+ *   u_r = (I x I x D) u, u_s = (I x D x I) u, u_t = (D x I x I) u,
+ *   [w_r w_s w_t] = G [u_r u_s u_t],  w = D_r^T w_r + D_s^T w_s + D_t^T w_t,
+ * the kernel section 4.2.2 names as the dominant cost of PCG.
+ * p = SEM_FP64: u, w double.  SEM_FP32: u, w float (FP32 G).
+ * SEM_BF16: u bf16, w float (BF16 G, FP32 derivative matrix and FP32
+ * accumulation).  u_L and w_L must not overlap. */
+sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
+                  void *stream);
+
+/* Direct stiffness summation in place: v <- mask o Q Q^T v, where every copy
+ * of a global node receives the sum of all copies taken in ascending local
+ * index starting from +0.0 (no fused multiply-add), then Dirichlet copies
+ * are set to zero.  p = SEM_FP64 or SEM_FP32. */
+sem_status sem_gs(sem_handle *h, int32_t p, void *v_L, void *stream);
+
+/* Load vector b_L = mask o Q Q^T (B o f(X)) (weak-form right-hand side of
+ * semOperator with the lumped mass), FP64 E-vector. */
+sem_status sem_rhs(sem_handle *h, const sem_source *src, double *b_L,
+                   void *stream);
+
+/* z_L = P r_L on continuous E-vectors.  SEM_PC_JACOBI: z = dinv o r with the
+ * inverse of the assembled diagonal (0 on Dirichlet nodes); SEM_PC_NONE:
+ * z = mask o r.  p = SEM_FP64 or SEM_FP32. */
+sem_status sem_precond_apply(sem_handle *h, int32_t pc, int32_t p,
+                             const void *r_L, void *z_L, void *stream);
+
+/* Solve A x = b (section 4.2.2: preconditioned conjugate gradients) for a
+ * continuous, masked FP64 E-vector b_L (e.g. from sem_rhs).  x_L holds the
+ * initial guess on entry (continuous E-vector; use zeros) and the solution
+ * on return.  Synchronises `stream`.  Returns SEM_ERR_NOT_CONVERGED /
+ * SEM_ERR_BREAKDOWN with the stats filled in when the solve fails. */
+sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *opts,
+                         const double *b_L, double *x_L,
+                         sem_solve_stats *stats, void *stream);
+
+/* Text of the calling thread's last error ("" if none). */
+const char *sem_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

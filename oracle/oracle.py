@@ -50,6 +50,8 @@ def lib():
             mod.build()
         _lib = C.CDLL(_LIB_PATH)
         L = _lib
+        L.orc_num_threads.argtypes = []
+        L.orc_num_threads.restype = C.c_int
         L.orc_gll.argtypes = [C.c_int, _dp, _dp]
         L.orc_gll.restype = C.c_int
         L.orc_dmat.argtypes = [C.c_int, _dp, _dp]
@@ -78,6 +80,10 @@ def lib():
                               C.c_int, C.POINTER(C.c_int), _dp]
         L.orc_fcg.restype = C.c_int
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _f64(a):

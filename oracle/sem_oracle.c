@@ -25,8 +25,19 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PI 3.14159265358979323846
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void orc_legendre(int n, double x, double *P) {
   /* (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1} */

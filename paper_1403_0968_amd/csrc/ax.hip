@@ -1,0 +1,185 @@
+// Local stiffness action w = D^T G D u on hexahedral spectral elements
+// (paper section 4.2.1, factored stiffness operator with the G^T G metric
+// precomputed per elemental node; section 4.2.2 names it the dominant cost of
+// every PCG iteration).
+//
+// Kernel design for gfx950 (HBM-bound: 64 B per node in FP64 against ~111
+// flops per node at N=7):
+//   * one thread per (i,j) column of an element, holding the n1 values along
+//     k in registers: the t-direction contractions never leave registers;
+//   * the r- and s-direction contractions read the current k-slice from LDS
+//     (row pitch n1+1 so that the 8 distinct rows a wave reads at once sit in
+//     different banks);
+//   * the six geometric factors of a slice are read with one fully coalesced
+//     load per factor (consecutive lanes, consecutive nodes);
+//   * each workgroup holds floor(256 / n1^2) elements; u, the r-flux and the
+//     s-flux each have their own LDS array.
+// Storage/compute type combinations:
+//   FP64: u, G, w double; FP32: float everywhere;
+//   BF16: u and G bfloat16, D, arithmetic and w in FP32.
+// GATHER = true reads u from a unique-node vector through l2g (the Q of the
+// assembled operator), used inside the solvers.
+#include "common.h"
+#include "sem_internal.h"
+
+namespace sem {
+
+template <int N1> struct AxShape {
+  static constexpr int NP = N1 * N1;
+  static constexpr int EPB = (256 / NP) > 0 ? (256 / NP) : 1;
+  static constexpr int THREADS = EPB * NP;
+  static constexpr int N3 = N1 * NP;
+  static constexpr int PAD = N1 + 1;
+};
+
+template <int N1, class TU, class TG, class TW, class TC, bool GATHER>
+__global__ void __launch_bounds__(AxShape<N1>::THREADS)
+    k_ax(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
+         const TU *__restrict__ u, TW *__restrict__ w,
+         const int32_t *__restrict__ l2g, const int32_t *__restrict__ stop) {
+  using S = AxShape<N1>;
+  constexpr int NP = S::NP, N3 = S::N3, EPB = S::EPB, PAD = S::PAD;
+  __shared__ TC s_u[EPB][N1][N1][PAD];  // u
+  __shared__ TC s_r[EPB][N1][N1][PAD];  // r-flux
+  __shared__ TC s_s[EPB][N1][N1][PAD];  // s-flux
+
+  if (stop != nullptr && *stop != 0) return;  // uniform: solver finished
+
+  const int t = threadIdx.x;
+  const int el = t / NP;
+  const int c = t - el * NP;
+  const int i = c % N1, j = c / N1;
+  const int64_t e = (int64_t)blockIdx.x * EPB + el;
+  const bool act = e < E;
+  const int64_t base = e * N3 + c;
+
+  TC Di[N1], Dj[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    Di[m] = D[i * N1 + m];
+    Dj[m] = D[j * N1 + m];
+  }
+
+  TC uc[N1];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    TC v = TC(0);
+    if (act) {
+      if constexpr (GATHER)
+        v = Cvt<TU, TC>::ld(u[l2g[base + k * NP]]);
+      else
+        v = Cvt<TU, TC>::ld(u[base + k * NP]);
+    }
+    uc[k] = v;
+    s_u[el][k][j][i] = v;
+  }
+  __syncthreads();
+
+  // gradient (r, s from LDS; t from registers) and fluxes, slice by slice
+  TC wt[N1];
+  const TG *Ge = G + e * 6 * N3 + c;
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    TC ur = TC(0), us = TC(0), ut = TC(0);
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      ur += Di[m] * s_u[el][k][j][m];
+      us += Dj[m] * s_u[el][k][m][i];
+      ut += D[k * N1 + m] * uc[m];
+    }
+    TC g0 = TC(0), g1 = TC(0), g2 = TC(0), g3 = TC(0), g4 = TC(0), g5 = TC(0);
+    if (act) {
+      g0 = Cvt<TG, TC>::ld(Ge[0 * N3 + k * NP]);
+      g1 = Cvt<TG, TC>::ld(Ge[1 * N3 + k * NP]);
+      g2 = Cvt<TG, TC>::ld(Ge[2 * N3 + k * NP]);
+      g3 = Cvt<TG, TC>::ld(Ge[3 * N3 + k * NP]);
+      g4 = Cvt<TG, TC>::ld(Ge[4 * N3 + k * NP]);
+      g5 = Cvt<TG, TC>::ld(Ge[5 * N3 + k * NP]);
+    }
+    s_r[el][k][j][i] = g0 * ur + g1 * us + g2 * ut;
+    s_s[el][k][j][i] = g1 * ur + g3 * us + g4 * ut;
+    wt[k] = g2 * ur + g4 * us + g5 * ut;
+  }
+  __syncthreads();
+
+  // w = D_r^T w_r + D_s^T w_s + D_t^T w_t
+  TC DTi[N1], DTj[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    DTi[m] = D[m * N1 + i];
+    DTj[m] = D[m * N1 + j];
+  }
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    TC acc = TC(0);
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      acc += DTi[m] * s_r[el][k][j][m];
+      acc += DTj[m] * s_s[el][k][m][i];
+      acc += D[m * N1 + k] * wt[m];
+    }
+    if (act) w[base + k * NP] = (TW)acc;
+  }
+}
+
+template <int N1>
+static void launch_n(int prec, int64_t E, const void *D, const void *G,
+                     const void *u, void *w, const int32_t *l2g,
+                     const int32_t *stop, hipStream_t s) {
+  using S = AxShape<N1>;
+  const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+  if (blocks == 0) return;
+  dim3 grid((unsigned)blocks), block(S::THREADS);
+  const bool gather = l2g != nullptr;
+  if (prec == SEM_FP64) {
+    if (gather)
+      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, true>), grid,
+                         block, 0, s, E, (const double *)D, (const double *)G,
+                         (const double *)u, (double *)w, l2g, stop);
+    else
+      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, false>),
+                         grid, block, 0, s, E, (const double *)D,
+                         (const double *)G, (const double *)u, (double *)w, l2g,
+                         stop);
+  } else if (prec == SEM_FP32) {
+    if (gather)
+      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, true>), grid,
+                         block, 0, s, E, (const float *)D, (const float *)G,
+                         (const float *)u, (float *)w, l2g, stop);
+    else
+      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, false>), grid,
+                         block, 0, s, E, (const float *)D, (const float *)G,
+                         (const float *)u, (float *)w, l2g, stop);
+  } else {
+    // BF16 geometric factors.  Standalone: bf16 input; inside solvers the
+    // FP32 unique vector is gathered directly.
+    if (gather)
+      hipLaunchKernelGGL((k_ax<N1, float, uint16_t, float, float, true>), grid,
+                         block, 0, s, E, (const float *)D, (const uint16_t *)G,
+                         (const float *)u, (float *)w, l2g, stop);
+    else
+      hipLaunchKernelGGL((k_ax<N1, uint16_t, uint16_t, float, float, false>),
+                         grid, block, 0, s, E, (const float *)D,
+                         (const uint16_t *)G, (const uint16_t *)u, (float *)w,
+                         l2g, stop);
+  }
+}
+
+void launch_ax(int N, int prec, int64_t E, const void *D, const void *G,
+               const void *u, void *w, const int32_t *l2g, const int32_t *stop,
+               hipStream_t s) {
+  switch (N) {
+    case 1: launch_n<2>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 2: launch_n<3>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 3: launch_n<4>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 4: launch_n<5>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 5: launch_n<6>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 6: launch_n<7>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 7: launch_n<8>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 8: launch_n<9>(prec, E, D, G, u, w, l2g, stop, s); break;
+    default: fail(SEM_ERR_ARG, "sem_ax: N must be in 1..8");
+  }
+  SEM_HIP(hipGetLastError());
+}
+
+}  // namespace sem

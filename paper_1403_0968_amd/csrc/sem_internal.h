@@ -1,0 +1,115 @@
+// Internal declarations of libsem.so (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+
+namespace sem {
+
+// ---------------------------------------------------------------------------
+// error plumbing: internal code throws sem::Error, the C ABI converts it
+// ---------------------------------------------------------------------------
+struct Error {
+  sem_status code;
+  std::string msg;
+};
+[[noreturn]] void fail(sem_status code, const std::string &msg);
+void hip_check(hipError_t e, const char *what, const char *file, int line);
+#define SEM_HIP(x) ::sem::hip_check((x), #x, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------------------
+// reference element (host, FP64)
+// ---------------------------------------------------------------------------
+struct RefElem {
+  int N = 0, n1 = 0;
+  std::vector<double> xi, w, D;  // D[i*n1+m] = l_m'(xi_i)
+};
+RefElem make_ref_elem(int N);
+
+// ---------------------------------------------------------------------------
+// maps of the structured box (host)
+// ---------------------------------------------------------------------------
+struct HostMaps {
+  int64_t nL = 0, nG = 0;
+  std::vector<int32_t> l2g, perm, offsets, mult;
+  std::vector<uint8_t> bmask;   // per local node, 1 on Dirichlet nodes
+  std::vector<uint8_t> gmask;   // per global node
+  // gather-scatter work lists
+  std::vector<int32_t> masked_lids;         // every local copy of a Dirichlet node
+  std::vector<int32_t> seg_off, seg_ids;    // shared, non-Dirichlet nodes
+};
+HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet);
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf();
+  void alloc(size_t nbytes);
+  template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// device-side CG scalars (one struct per solve)
+struct CgState {
+  double rz;      // (r, z)
+  double pw;      // (p, A p)
+  double alpha, beta;
+  double rr;      // (r, r)
+  double bb;      // (b, b)
+  double tol2;    // rtol^2
+  double pad0;
+  int32_t it;     // iterations done
+  int32_t maxit;
+  int32_t done;   // 0 running, 1 converged, 2 breakdown, 3 maxit
+  int32_t pad1;
+};
+
+}  // namespace sem
+
+namespace sem {
+struct Workspace;  // solver buffers, graphs and streams (solver.hip)
+}
+
+struct sem_handle {
+  int N = 0, n1 = 0, ex = 0, ey = 0, ez = 0, dirichlet = 0, mapping = 0;
+  int64_t E = 0, nL = 0, nG = 0, n_masked = 0, n_seg = 0;
+  sem::RefElem ref;
+
+  // maps
+  sem::DevBuf l2g, perm, offsets, mult, bmask, gmask, masked_lids, seg_off,
+      seg_ids;
+  // reference element on device
+  sem::DevBuf D64, D32;
+  // geometry and preconditioner
+  sem::DevBuf coords, G64, G32, G16, mass, diag_L, dinv_G, dinv_G32;
+  // created on the first solve
+  sem::Workspace *ws = nullptr;
+};
+
+namespace sem {
+
+// kernels / launchers (ax.hip, gs.hip, cg.hip, setup.hip)
+void launch_ax(int N, int prec, int64_t E, const void *D, const void *G,
+               const void *u, void *w, const int32_t *l2g_gather,
+               const int32_t *stop, hipStream_t s);
+void launch_gs(sem_handle *h, int prec, void *v, hipStream_t s);
+void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s);
+void launch_rhs(sem_handle *h, const sem_source *src, double *b, hipStream_t s);
+void launch_precond(sem_handle *h, int pc, int prec, const void *r, void *z,
+                    hipStream_t s);
+// solver (solver.hip)
+void destroy_ws(sem_handle *h);
+sem_status pcg_solve(sem_handle *h, const sem_solve_opts *o, const double *b_L,
+                     double *x_L, sem_solve_stats *st, hipStream_t s);
+
+}  // namespace sem

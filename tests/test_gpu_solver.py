@@ -1,0 +1,126 @@
+"""GPU preconditioned CG and FP64 iterative refinement against the oracle.
+
+Several correct iteration counts exist (reductions are ordered differently
+from the oracle's), so the bar is on what is unique: the solution.  At
+tolerance 1e-10 the GPU and oracle solutions must agree to 1e-7 relative,
+the recomputed FP64 residual must meet the tolerance, and on the
+manufactured problem the nodal error must equal the oracle's."""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from seminputs import fourier_modes, grf_features
+
+from gpu_util import Pair, to_dev, to_host, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sem():
+    from paper_1403_0968_amd import sem as s
+    s.lib()
+    return s
+
+
+def _solve(sem, pair, b_L, **kw):
+    t = torch()
+    x = t.zeros_like(b_L)
+    st = sem.sem_pcg_solve(pair.h, b_L, x, **kw)
+    t.cuda.synchronize()
+    return to_host(x), st
+
+
+def test_manufactured_config_4x4x4_N4(sem):
+    """Plain FP64 Jacobi-PCG to 1e-10 on the 4^3 affine N=4 problem with
+    u = sin(pi x) sin(pi y) sin(pi z)."""
+    print("[gpu] manufactured 4^3 N=4", flush=True)
+    p = Pair(sem, 4, 4, 4, 4, mapping=orc.MAP_AFFINE)
+    try:
+        t = torch()
+        m = p.m
+        b = t.empty(m.nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(p.h, b, sem.SEM_SRC_SINE)
+        x, st = _solve(sem, p, b, rtol=1e-10, maxit=1000, check_every=4)
+        assert st["status"] == 0 and st["final_rel_res"] <= 1e-10
+        bo = orc.to_global(m, orc.rhs_local(m, orc.src_sine(m.X)))
+        xo, so, ito, _ = orc.pcg(m, bo, 1e-10, 1000)
+        assert so == 0 and abs(st["iters"] - ito) <= 2
+        xg = orc.to_global(m, x)
+        assert np.linalg.norm(xg - xo) <= 1e-7 * np.linalg.norm(xo)
+        Xg = np.zeros((3, m.nG))
+        Xg[:, m.l2g] = m.X
+        ue = np.sin(np.pi * Xg[0]) * np.sin(np.pi * Xg[1]) * np.sin(np.pi * Xg[2])
+        err_gpu, err_ora = np.max(np.abs(xg - ue)), np.max(np.abs(xo - ue))
+        print(f"[manufactured] iters gpu {st['iters']} oracle {ito}; "
+              f"nodal error gpu {err_gpu:.3e} oracle {err_ora:.3e}")
+        assert abs(err_gpu - err_ora) <= 1e-9
+        # the solution is continuous: every copy of a node holds one value
+        np.testing.assert_array_equal(x, xg[m.l2g])
+    finally:
+        p.close()
+
+
+@pytest.mark.parametrize("inner", ["fp64", "fp32", "bf16"])
+def test_curved_kappa_solve_matches_oracle(sem, inner):
+    print(f"[gpu] curved kappa solve inner={inner}", flush=True)
+    kap = grf_features(seed=7, M=64, ell=0.3, sigma=0.5)
+    p = Pair(sem, 5, 3, 3, 2, mapping=orc.MAP_SINE_CYCLIC, kappa=kap)
+    try:
+        t = torch()
+        m = p.m
+        k, a, phi = fourier_modes(seed=3)
+        b = t.empty(m.nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(p.h, b, sem.SEM_SRC_FOURIER, (k, a, phi))
+        prec = {"fp64": sem.SEM_FP64, "fp32": sem.SEM_FP32,
+                "bf16": sem.SEM_BF16}[inner]
+        x, st = _solve(sem, p, b, rtol=1e-10, maxit=5000, inner_prec=prec,
+                       inner_rtol=1e-2, check_every=8)
+        print(f"[solve {inner}] {st}")
+        assert st["status"] == 0 and st["final_rel_res"] <= 1e-10
+        bo = orc.to_global(m, orc.rhs_local(m, orc.src_fourier(m.X, k, a, phi)))
+        xo, so, ito, _ = orc.pcg(m, bo, 1e-12, 5000)
+        xg = orc.to_global(m, x)
+        rel = np.linalg.norm(xg - xo) / np.linalg.norm(xo)
+        print(f"[solve {inner}] ||x - x_oracle|| / ||x_oracle|| = {rel:.3e}")
+        assert rel <= 1e-7
+        assert orc.true_rel_residual(m, bo, xg) <= 2e-10
+        if inner != "fp64":
+            assert st["outer_iters"] >= 2
+    finally:
+        p.close()
+
+
+def test_graph_and_direct_launch_agree_bitwise(sem):
+    p = Pair(sem, 3, 4, 3, 3, mapping=orc.MAP_SINE_CYCLIC, oracle=False)
+    try:
+        t = torch()
+        k, a, phi = fourier_modes(seed=4)
+        b = t.empty(p.nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(p.h, b, sem.SEM_SRC_FOURIER, (k, a, phi))
+        x1, s1 = _solve(sem, p, b, rtol=1e-9, maxit=2000, use_graph=1, check_every=5)
+        x2, s2 = _solve(sem, p, b, rtol=1e-9, maxit=2000, use_graph=0, check_every=1)
+        x3, s3 = _solve(sem, p, b, rtol=1e-9, maxit=2000, use_graph=1, check_every=64)
+        assert s1["iters"] == s2["iters"] == s3["iters"]
+        np.testing.assert_array_equal(x1, x2)
+        np.testing.assert_array_equal(x1, x3)
+    finally:
+        p.close()
+
+
+def test_not_converged_and_argument_errors(sem):
+    p = Pair(sem, 3, 3, 3, 3, mapping=orc.MAP_SINE_CYCLIC, oracle=False)
+    try:
+        t = torch()
+        k, a, phi = fourier_modes(seed=5)
+        b = t.empty(p.nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(p.h, b, sem.SEM_SRC_FOURIER, (k, a, phi))
+        x, st = _solve(sem, p, b, rtol=1e-12, maxit=3, raise_on_fail=False)
+        assert st["status"] == sem.SEM_ERR_NOT_CONVERGED and st["iters"] == 3
+        with pytest.raises(sem.SemError) as ei:
+            _solve(sem, p, b, rtol=-1.0)
+        assert ei.value.code == sem.SEM_ERR_ARG
+        with pytest.raises(sem.SemError):
+            sem.sem_ax(p.h, 7, b, t.empty_like(b))
+    finally:
+        p.close()
