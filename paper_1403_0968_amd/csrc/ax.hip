@@ -12,8 +12,14 @@
 //     different banks);
 //   * the six geometric factors of a slice are read with one fully coalesced
 //     load per factor (consecutive lanes, consecutive nodes);
-//   * each workgroup holds floor(256 / n1^2) elements; u, the r-flux and the
-//     s-flux each have their own LDS array.
+//   * all loads of an element (its u column and the 6 n1 geometric factors of
+//     the column) are issued before any arithmetic, so each wave keeps its
+//     whole input in flight; the factors are read once per operator
+//     application and bypass the caches (non-temporal loads), and so do the
+//     outputs of the standalone operator;
+//   * u, the r-flux and the s-flux each have their own LDS array; FP64 uses
+//     128-thread workgroups, FP32/BF16 64-thread ones (two / one element at
+//     n1 = 8).
 // Storage/compute type combinations:
 //   FP64: u, G, w double; FP32: float everywhere;
 //   BF16: u and G bfloat16, D, arithmetic and w in FP32.
@@ -24,20 +30,26 @@
 
 namespace sem {
 
-template <int N1> struct AxShape {
+template <int N1, int BYTES> struct AxShape {
   static constexpr int NP = N1 * N1;
-  static constexpr int EPB = (256 / NP) > 0 ? (256 / NP) : 1;
+  // FP64: two 64-lane columns sets per workgroup at N1 = 8; FP32/BF16: one
+  static constexpr int TARGET = BYTES == 8 ? 128 : 64;
+  static constexpr int EPB = (TARGET / NP) > 0 ? (TARGET / NP) : 1;
   static constexpr int THREADS = EPB * NP;
   static constexpr int N3 = N1 * NP;
   static constexpr int PAD = N1 + 1;
 };
 
-template <int N1, class TU, class TG, class TW, class TC, bool GATHER>
-__global__ void __launch_bounds__(AxShape<N1>::THREADS)
+template <class T> __device__ inline T ld_stream(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
+template <int N1, class TU, class TG, class TW, class TC, bool GATHER, bool NTW>
+__global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
     k_ax(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
          const TU *__restrict__ u, TW *__restrict__ w,
          const int32_t *__restrict__ l2g, const int32_t *__restrict__ stop) {
-  using S = AxShape<N1>;
+  using S = AxShape<N1, sizeof(TC)>;
   constexpr int NP = S::NP, N3 = S::N3, EPB = S::EPB, PAD = S::PAD;
   __shared__ TC s_u[EPB][N1][N1][PAD];  // u
   __shared__ TC s_r[EPB][N1][N1][PAD];  // r-flux
@@ -53,31 +65,44 @@ __global__ void __launch_bounds__(AxShape<N1>::THREADS)
   const bool act = e < E;
   const int64_t base = e * N3 + c;
 
+  // every load of the element is issued before any arithmetic: the u column
+  // and all 6 x n1 geometric factors of the column (streamed, read once)
+  TU ucol[N1];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    TU v = TU(0);
+    if (act) {
+      if constexpr (GATHER)
+        v = u[l2g[base + k * NP]];
+      else
+        v = u[base + k * NP];
+    }
+    ucol[k] = v;
+  }
+  TG g[6][N1];
+  const TG *Ge = G + e * 6 * N3 + c;
+#pragma unroll
+  for (int k = 0; k < N1; ++k)
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+      g[q][k] = act ? ld_stream(Ge + q * N3 + k * NP) : TG(0);
+
+  TC uc[N1];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    uc[k] = Cvt<TU, TC>::ld(ucol[k]);
+    s_u[el][k][j][i] = uc[k];
+  }
   TC Di[N1], Dj[N1];
 #pragma unroll
   for (int m = 0; m < N1; ++m) {
     Di[m] = D[i * N1 + m];
     Dj[m] = D[j * N1 + m];
   }
-
-  TC uc[N1];
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    TC v = TC(0);
-    if (act) {
-      if constexpr (GATHER)
-        v = Cvt<TU, TC>::ld(u[l2g[base + k * NP]]);
-      else
-        v = Cvt<TU, TC>::ld(u[base + k * NP]);
-    }
-    uc[k] = v;
-    s_u[el][k][j][i] = v;
-  }
   __syncthreads();
 
   // gradient (r, s from LDS; t from registers) and fluxes, slice by slice
   TC wt[N1];
-  const TG *Ge = G + e * 6 * N3 + c;
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     TC ur = TC(0), us = TC(0), ut = TC(0);
@@ -87,15 +112,9 @@ __global__ void __launch_bounds__(AxShape<N1>::THREADS)
       us += Dj[m] * s_u[el][k][m][i];
       ut += D[k * N1 + m] * uc[m];
     }
-    TC g0 = TC(0), g1 = TC(0), g2 = TC(0), g3 = TC(0), g4 = TC(0), g5 = TC(0);
-    if (act) {
-      g0 = Cvt<TG, TC>::ld(Ge[0 * N3 + k * NP]);
-      g1 = Cvt<TG, TC>::ld(Ge[1 * N3 + k * NP]);
-      g2 = Cvt<TG, TC>::ld(Ge[2 * N3 + k * NP]);
-      g3 = Cvt<TG, TC>::ld(Ge[3 * N3 + k * NP]);
-      g4 = Cvt<TG, TC>::ld(Ge[4 * N3 + k * NP]);
-      g5 = Cvt<TG, TC>::ld(Ge[5 * N3 + k * NP]);
-    }
+    const TC g0 = Cvt<TG, TC>::ld(g[0][k]), g1 = Cvt<TG, TC>::ld(g[1][k]),
+             g2 = Cvt<TG, TC>::ld(g[2][k]), g3 = Cvt<TG, TC>::ld(g[3][k]),
+             g4 = Cvt<TG, TC>::ld(g[4][k]), g5 = Cvt<TG, TC>::ld(g[5][k]);
     s_r[el][k][j][i] = g0 * ur + g1 * us + g2 * ut;
     s_s[el][k][j][i] = g1 * ur + g3 * us + g4 * ut;
     wt[k] = g2 * ur + g4 * us + g5 * ut;
@@ -118,7 +137,12 @@ __global__ void __launch_bounds__(AxShape<N1>::THREADS)
       acc += DTj[m] * s_s[el][k][m][i];
       acc += D[m * N1 + k] * wt[m];
     }
-    if (act) w[base + k * NP] = (TW)acc;
+    if (act) {
+      if constexpr (NTW)
+        __builtin_nontemporal_store((TW)acc, w + base + k * NP);
+      else
+        w[base + k * NP] = (TW)acc;
+    }
   }
 }
 
@@ -126,39 +150,42 @@ template <int N1>
 static void launch_n(int prec, int64_t E, const void *D, const void *G,
                      const void *u, void *w, const int32_t *l2g,
                      const int32_t *stop, hipStream_t s) {
-  using S = AxShape<N1>;
-  const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+  using S8 = AxShape<N1, 8>;
+  using S4 = AxShape<N1, 4>;
+  const int epb = prec == SEM_FP64 ? S8::EPB : S4::EPB;
+  const int threads = prec == SEM_FP64 ? S8::THREADS : S4::THREADS;
+  const int64_t blocks = (E + epb - 1) / epb;
   if (blocks == 0) return;
-  dim3 grid((unsigned)blocks), block(S::THREADS);
+  dim3 grid((unsigned)blocks), block(threads);
   const bool gather = l2g != nullptr;
   if (prec == SEM_FP64) {
     if (gather)
-      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, true>), grid,
+      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, true, false>), grid,
                          block, 0, s, E, (const double *)D, (const double *)G,
                          (const double *)u, (double *)w, l2g, stop);
     else
-      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, false>),
+      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, false, true>),
                          grid, block, 0, s, E, (const double *)D,
                          (const double *)G, (const double *)u, (double *)w, l2g,
                          stop);
   } else if (prec == SEM_FP32) {
     if (gather)
-      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, true>), grid,
+      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, true, false>), grid,
                          block, 0, s, E, (const float *)D, (const float *)G,
                          (const float *)u, (float *)w, l2g, stop);
     else
-      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, false>), grid,
+      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, false, true>), grid,
                          block, 0, s, E, (const float *)D, (const float *)G,
                          (const float *)u, (float *)w, l2g, stop);
   } else {
     // BF16 geometric factors.  Standalone: bf16 input; inside solvers the
     // FP32 unique vector is gathered directly.
     if (gather)
-      hipLaunchKernelGGL((k_ax<N1, float, uint16_t, float, float, true>), grid,
+      hipLaunchKernelGGL((k_ax<N1, float, uint16_t, float, float, true, false>), grid,
                          block, 0, s, E, (const float *)D, (const uint16_t *)G,
                          (const float *)u, (float *)w, l2g, stop);
     else
-      hipLaunchKernelGGL((k_ax<N1, uint16_t, uint16_t, float, float, false>),
+      hipLaunchKernelGGL((k_ax<N1, uint16_t, uint16_t, float, float, false, true>),
                          grid, block, 0, s, E, (const float *)D,
                          (const uint16_t *)G, (const uint16_t *)u, (float *)w,
                          l2g, stop);
