@@ -154,8 +154,8 @@ sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
  *   [w_r w_s w_t] = G [u_r u_s u_t],  w = D_r^T w_r + D_s^T w_s + D_t^T w_t,
  * the kernel section 4.2.2 names as the dominant cost of PCG.
  * p = SEM_FP64: u, w double.  SEM_FP32: u, w float (FP32 G).
- * SEM_BF16: u bf16, w float (BF16 G, FP32 derivative matrix and FP32
- * accumulation).  u_L and w_L must not overlap. */
+ * SEM_BF16: u bf16 (16-byte aligned), w float (BF16 G, FP32 derivative
+ * matrix and FP32 accumulation).  u_L and w_L must not overlap. */
 sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
                   void *stream);
 

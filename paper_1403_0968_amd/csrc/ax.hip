@@ -22,7 +22,10 @@
 //     n1 = 8).
 // Storage/compute type combinations:
 //   FP64: u, G, w double; FP32: float everywhere;
-//   BF16: u and G bfloat16, D, arithmetic and w in FP32.
+//   BF16: u and G bfloat16, D, arithmetic and w in FP32.  At n1 = 8 the BF16
+//   factors are stored column-contiguous ([E][6][n1^2][n1]) so that a lane
+//   fetches the 8 values of one factor with a single 16-byte load, and the
+//   BF16 input is read in 16-byte rows and redistributed through LDS.
 // GATHER = true reads u from a unique-node vector through l2g (the Q of the
 // assembled operator), used inside the solvers.
 #include "common.h"
@@ -39,6 +42,8 @@ template <int N1, int BYTES> struct AxShape {
   static constexpr int N3 = N1 * NP;
   static constexpr int PAD = N1 + 1;
 };
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <class T> __device__ inline T ld_stream(const T *p) {
   return __builtin_nontemporal_load(p);
@@ -67,31 +72,68 @@ __global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
 
   // every load of the element is issued before any arithmetic: the u column
   // and all 6 x n1 geometric factors of the column (streamed, read once)
+  constexpr bool VEC16 = sizeof(TG) == 2 && N1 == 8;  // BF16 column layout
+  constexpr bool VECU = sizeof(TU) == 2 && N1 == 8 && !GATHER;
   TU ucol[N1];
+  u32x4 urow = {0u, 0u, 0u, 0u};
+  if constexpr (VECU) {
+    // lane c reads the 16-byte row (k, j) = (c / 8, c % 8) of the element
+    if (act) urow = *reinterpret_cast<const u32x4 *>(u + e * N3 + 8 * c);
+  } else {
 #pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    TU v = TU(0);
-    if (act) {
-      if constexpr (GATHER)
-        v = u[l2g[base + k * NP]];
-      else
-        v = u[base + k * NP];
+    for (int k = 0; k < N1; ++k) {
+      TU v = TU(0);
+      if (act) {
+        if constexpr (GATHER)
+          v = u[l2g[base + k * NP]];
+        else
+          v = u[base + k * NP];
+      }
+      ucol[k] = v;
     }
-    ucol[k] = v;
   }
   TG g[6][N1];
-  const TG *Ge = G + e * 6 * N3 + c;
+  if constexpr (VEC16) {
+    // layout [E][6][n1^2][n1]: the n1 values of one column are contiguous
 #pragma unroll
-  for (int k = 0; k < N1; ++k)
+    for (int q = 0; q < 6; ++q) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (act)
+        v = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4 *>(G + e * 6 * N3 + q * N3 + 8 * c));
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int q = 0; q < 6; ++q)
-      g[q][k] = act ? ld_stream(Ge + q * N3 + k * NP) : TG(0);
+      for (int h = 0; h < 4; ++h) {
+        g[q][2 * h] = (TG)(wv[h] & 0xffffu);
+        g[q][2 * h + 1] = (TG)(wv[h] >> 16);
+      }
+    }
+  } else {
+    const TG *Ge = G + e * 6 * N3 + c;
+#pragma unroll
+    for (int k = 0; k < N1; ++k)
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        g[q][k] = act ? ld_stream(Ge + q * N3 + k * NP) : TG(0);
+  }
 
   TC uc[N1];
+  if constexpr (VECU) {
+    const uint32_t wv[4] = {urow.x, urow.y, urow.z, urow.w};
 #pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    uc[k] = Cvt<TU, TC>::ld(ucol[k]);
-    s_u[el][k][j][i] = uc[k];
+    for (int h = 0; h < 4; ++h) {
+      s_u[el][c / 8][c % 8][2 * h] = Cvt<TU, TC>::ld((TU)(wv[h] & 0xffffu));
+      s_u[el][c / 8][c % 8][2 * h + 1] = Cvt<TU, TC>::ld((TU)(wv[h] >> 16));
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N1; ++k) uc[k] = s_u[el][k][j][i];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      uc[k] = Cvt<TU, TC>::ld(ucol[k]);
+      s_u[el][k][j][i] = uc[k];
+    }
   }
   TC Di[N1], Dj[N1];
 #pragma unroll

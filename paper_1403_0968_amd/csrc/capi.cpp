@@ -152,6 +152,8 @@ sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
     } else if (p == SEM_BF16) {
       G = h->G16.p;
       D = h->D32.p;
+      need(reinterpret_cast<uintptr_t>(u_L) % 16 == 0,
+           "sem_ax: BF16 input must be 16-byte aligned");
     } else {
       fail(SEM_ERR_ARG, "sem_ax: unknown precision");
     }

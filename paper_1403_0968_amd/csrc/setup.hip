@@ -159,13 +159,22 @@ __global__ void k_dinv(int64_t nG, const int32_t *__restrict__ off,
   dinv32[g] = (float)v;
 }
 
-__global__ void k_cast_geom(int64_t n, const double *__restrict__ G,
+// reduced-precision copies; at n1 = 8 the BF16 copy is column-contiguous
+// ([E][6][n1^2][n1], the layout the BF16 operator kernel reads)
+__global__ void k_cast_geom(int64_t n, int N1, const double *__restrict__ G,
                             float *__restrict__ G32, uint16_t *__restrict__ G16) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   const float f = (float)G[q];
   G32[q] = f;
-  G16[q] = f32_to_bf16(f);
+  int64_t d = q;
+  if (N1 == 8) {
+    const int64_t blk = q / 512;      // (element, factor)
+    const int p = (int)(q - blk * 512);  // node i + 8 j + 64 k
+    const int c = p % 64, k = p / 64;
+    d = blk * 512 + c * 8 + k;
+  }
+  G16[d] = f32_to_bf16(f);
 }
 
 template <class T>
@@ -254,7 +263,7 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
                      h->dinv_G.as<double>(), h->dinv_G32.as<float>());
   SEM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_cast_geom, dim3((unsigned)((nGeo + T - 1) / T)), dim3(T),
-                     0, s, nGeo, h->G64.as<double>(), h->G32.as<float>(),
+                     0, s, nGeo, N1, h->G64.as<double>(), h->G32.as<float>(),
                      h->G16.as<uint16_t>());
   SEM_HIP(hipGetLastError());
   std::vector<double> mj(gb);
