@@ -57,6 +57,7 @@ typedef enum {
 } sem_mapping;
 
 typedef struct sem_handle sem_handle; /* opaque, owned by the library */
+typedef struct sem_batch sem_batch;   /* opaque batch of independent solves */
 
 /* Mesh and coefficients.  All pointers here are HOST pointers, read during
  * sem_setup only. */
@@ -184,6 +185,34 @@ sem_status sem_precond_apply(sem_handle *h, int32_t pc, int32_t p,
 sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *opts,
                          const double *b_L, double *x_L,
                          sem_solve_stats *stats, void *stream);
+
+/* Batches of independent solves (uneven sizes, orders N in {3, 5, 7} may
+ * be mixed, or any single N).  A batch references existing handles (which
+ * must outlive it) and owns its work lists, per-solve device scalars and
+ * captured graphs.  One CG iteration of the whole batch is six launches of
+ * persistent kernels over (solve, element tile) and (solve, node chunk)
+ * work items, captured once in a HIP graph and replayed check_every
+ * iterations at a time; finished solves drop out on the device.  A solve
+ * gives bit-identical results alone (sem_pcg_solve) or inside any batch. */
+sem_status sem_batch_create(sem_handle *const *handles, int32_t n,
+                            sem_batch **out);
+sem_status sem_batch_destroy(sem_batch *b);
+/* Autotuner: times the batched operator kernel of precision p for every
+ * workgroup size (64, 128, 256 threads) and persistent grid (1 tile per
+ * workgroup, or 4, 8, 16, 32 workgroups per compute unit) and keeps the
+ * fastest for later solves.  With the environment variable
+ * SEM_AUTOTUNE_CACHE naming a JSON file, results are read from / added to
+ * it, keyed by GPU architecture, order set, precision and size bucket.
+ * Outputs may be NULL; *us is -1 when the value came from the cache. */
+sem_status sem_batch_tune(sem_batch *b, int32_t p, int32_t *block_size,
+                          int32_t *grid_mult, double *us);
+/* Solve every system of the batch: b_L[q], x_L[q] are the device E-vectors
+ * of solve q (as in sem_pcg_solve); stats[q] receives its statistics
+ * (seconds = wall time of the whole batch).  Synchronises `stream`.
+ * Returns SEM_OK when all converged, else the first failing status. */
+sem_status sem_batch_pcg_solve(sem_batch *b, const sem_solve_opts *opts,
+                               const double *const *b_L, double *const *x_L,
+                               sem_solve_stats *stats, void *stream);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *sem_last_error(void);

@@ -10,16 +10,12 @@
 //   * the r- and s-direction contractions read the current k-slice from LDS
 //     (row pitch n1+1 so that the 8 distinct rows a wave reads at once sit in
 //     different banks);
-//   * the six geometric factors of a slice are read with one fully coalesced
-//     load per factor (consecutive lanes, consecutive nodes);
 //   * all loads of an element (its u column and the 6 n1 geometric factors of
 //     the column) are issued before any arithmetic, so each wave keeps its
 //     whole input in flight; the factors are read once per operator
 //     application and bypass the caches (non-temporal loads), and so do the
 //     outputs of the standalone operator;
-//   * u, the r-flux and the s-flux each have their own LDS array; FP64 uses
-//     128-thread workgroups, FP32/BF16 64-thread ones (two / one element at
-//     n1 = 8).
+//   * u, the r-flux and the s-flux each have their own LDS array.
 // Storage/compute type combinations:
 //   FP64: u, G, w double; FP32: float everywhere;
 //   BF16: u and G bfloat16, D, arithmetic and w in FP32.  At n1 = 8 the BF16
@@ -28,20 +24,15 @@
 //   BF16 input is read in 16-byte rows and redistributed through LDS.
 // GATHER = true reads u from a unique-node vector through l2g (the Q of the
 // assembled operator), used inside the solvers.
+//
+// Two kernels share one element routine: k_ax (one tile of elements per
+// workgroup, the standalone operator) and k_bax (persistent workgroups
+// walking a list of (solve, element tile) items of a batch of independent
+// solves with mixed orders; one launch applies the operators of all solves).
 #include "common.h"
 #include "sem_internal.h"
 
 namespace sem {
-
-template <int N1, int BYTES> struct AxShape {
-  static constexpr int NP = N1 * N1;
-  // FP64: two 64-lane columns sets per workgroup at N1 = 8; FP32/BF16: one
-  static constexpr int TARGET = BYTES == 8 ? 128 : 64;
-  static constexpr int EPB = (TARGET / NP) > 0 ? (TARGET / NP) : 1;
-  static constexpr int THREADS = EPB * NP;
-  static constexpr int N3 = N1 * NP;
-  static constexpr int PAD = N1 + 1;
-};
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -49,29 +40,37 @@ template <class T> __device__ inline T ld_stream(const T *p) {
   return __builtin_nontemporal_load(p);
 }
 
-template <int N1, class TU, class TG, class TW, class TC, bool GATHER, bool NTW>
-__global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
-    k_ax(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
-         const TU *__restrict__ u, TW *__restrict__ w,
-         const int32_t *__restrict__ l2g, const int32_t *__restrict__ stop) {
-  using S = AxShape<N1, sizeof(TC)>;
-  constexpr int NP = S::NP, N3 = S::N3, EPB = S::EPB, PAD = S::PAD;
-  __shared__ TC s_u[EPB][N1][N1][PAD];  // u
-  __shared__ TC s_r[EPB][N1][N1][PAD];  // r-flux
-  __shared__ TC s_s[EPB][N1][N1][PAD];  // s-flux
+template <int N1> constexpr int lds_words(int epb) {
+  return 3 * epb * N1 * N1 * (N1 + 1);
+}
 
-  if (stop != nullptr && *stop != 0) return;  // uniform: solver finished
-
-  const int t = threadIdx.x;
+// Apply the operator to elements e0 .. e0 + EPB - 1 (those < E) with the
+// threads t = 0 .. of one workgroup; threads t >= EPB n1^2 only join the
+// barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC.
+template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
+          bool NTW>
+__device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
+                                        const TC *__restrict__ D,
+                                        const TG *__restrict__ G,
+                                        const TU *__restrict__ u,
+                                        TW *__restrict__ w,
+                                        const int32_t *__restrict__ l2g,
+                                        TC *__restrict__ smem) {
+  constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = N1 + 1;
+  constexpr int SL = N1 * N1 * PAD;  // one element's slice stack
   const int el = t / NP;
+  const bool lane_ok = el < EPB;
+  const int elc = lane_ok ? el : 0;
   const int c = t - el * NP;
   const int i = c % N1, j = c / N1;
-  const int64_t e = (int64_t)blockIdx.x * EPB + el;
-  const bool act = e < E;
+  const int64_t e = e0 + el;
+  const bool act = lane_ok && e < E;
   const int64_t base = e * N3 + c;
+  TC *s_u = smem + (0 * EPB + elc) * SL;
+  TC *s_r = smem + (1 * EPB + elc) * SL;
+  TC *s_s = smem + (2 * EPB + elc) * SL;
+#define AX_IDX(k, jj, ii) (((k) * N1 + (jj)) * PAD + (ii))
 
-  // every load of the element is issued before any arithmetic: the u column
-  // and all 6 x n1 geometric factors of the column (streamed, read once)
   constexpr bool VEC16 = sizeof(TG) == 2 && N1 == 8;  // BF16 column layout
   constexpr bool VECU = sizeof(TU) == 2 && N1 == 8 && !GATHER;
   TU ucol[N1];
@@ -94,7 +93,6 @@ __global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
   }
   TG g[6][N1];
   if constexpr (VEC16) {
-    // layout [E][6][n1^2][n1]: the n1 values of one column are contiguous
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       u32x4 v = {0u, 0u, 0u, 0u};
@@ -120,19 +118,21 @@ __global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
   TC uc[N1];
   if constexpr (VECU) {
     const uint32_t wv[4] = {urow.x, urow.y, urow.z, urow.w};
+    if (lane_ok) {
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      s_u[el][c / 8][c % 8][2 * h] = Cvt<TU, TC>::ld((TU)(wv[h] & 0xffffu));
-      s_u[el][c / 8][c % 8][2 * h + 1] = Cvt<TU, TC>::ld((TU)(wv[h] >> 16));
+      for (int h = 0; h < 4; ++h) {
+        s_u[AX_IDX(c / 8, c % 8, 2 * h)] = Cvt<TU, TC>::ld((TU)(wv[h] & 0xffffu));
+        s_u[AX_IDX(c / 8, c % 8, 2 * h + 1)] = Cvt<TU, TC>::ld((TU)(wv[h] >> 16));
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < N1; ++k) uc[k] = s_u[el][k][j][i];
+    for (int k = 0; k < N1; ++k) uc[k] = s_u[AX_IDX(k, j, i)];
   } else {
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       uc[k] = Cvt<TU, TC>::ld(ucol[k]);
-      s_u[el][k][j][i] = uc[k];
+      if (lane_ok) s_u[AX_IDX(k, j, i)] = uc[k];
     }
   }
   TC Di[N1], Dj[N1];
@@ -150,15 +150,17 @@ __global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
     TC ur = TC(0), us = TC(0), ut = TC(0);
 #pragma unroll
     for (int m = 0; m < N1; ++m) {
-      ur += Di[m] * s_u[el][k][j][m];
-      us += Dj[m] * s_u[el][k][m][i];
+      ur += Di[m] * s_u[AX_IDX(k, j, m)];
+      us += Dj[m] * s_u[AX_IDX(k, m, i)];
       ut += D[k * N1 + m] * uc[m];
     }
     const TC g0 = Cvt<TG, TC>::ld(g[0][k]), g1 = Cvt<TG, TC>::ld(g[1][k]),
              g2 = Cvt<TG, TC>::ld(g[2][k]), g3 = Cvt<TG, TC>::ld(g[3][k]),
              g4 = Cvt<TG, TC>::ld(g[4][k]), g5 = Cvt<TG, TC>::ld(g[5][k]);
-    s_r[el][k][j][i] = g0 * ur + g1 * us + g2 * ut;
-    s_s[el][k][j][i] = g1 * ur + g3 * us + g4 * ut;
+    if (lane_ok) {
+      s_r[AX_IDX(k, j, i)] = g0 * ur + g1 * us + g2 * ut;
+      s_s[AX_IDX(k, j, i)] = g1 * ur + g3 * us + g4 * ut;
+    }
     wt[k] = g2 * ur + g4 * us + g5 * ut;
   }
   __syncthreads();
@@ -175,8 +177,8 @@ __global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
     TC acc = TC(0);
 #pragma unroll
     for (int m = 0; m < N1; ++m) {
-      acc += DTi[m] * s_r[el][k][j][m];
-      acc += DTj[m] * s_s[el][k][m][i];
+      acc += DTi[m] * s_r[AX_IDX(k, j, m)];
+      acc += DTj[m] * s_s[AX_IDX(k, m, i)];
       acc += D[m * N1 + k] * wt[m];
     }
     if (act) {
@@ -186,12 +188,35 @@ __global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
         w[base + k * NP] = (TW)acc;
     }
   }
+#undef AX_IDX
+}
+
+// ---------------------------------------------------------------------------
+// standalone operator: one tile per workgroup
+// ---------------------------------------------------------------------------
+template <int N1, int BYTES> struct AxShape {
+  static constexpr int NP = N1 * N1;
+  // FP64: 128-thread workgroups (two elements at n1 = 8); FP32/BF16: 64
+  static constexpr int TARGET = BYTES == 8 ? 128 : 64;
+  static constexpr int EPB = (TARGET / NP) > 0 ? (TARGET / NP) : 1;
+  static constexpr int THREADS = EPB * NP;
+};
+
+template <int N1, class TU, class TG, class TW, class TC, bool GATHER, bool NTW>
+__global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
+    k_ax(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
+         const TU *__restrict__ u, TW *__restrict__ w,
+         const int32_t *__restrict__ l2g, const int32_t *__restrict__ stop) {
+  using S = AxShape<N1, sizeof(TC)>;
+  __shared__ TC smem[lds_words<N1>(S::EPB)];
+  if (stop != nullptr && *stop != 0) return;  // uniform: solver finished
+  ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW>(
+      threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, l2g, smem);
 }
 
 template <int N1>
 static void launch_n(int prec, int64_t E, const void *D, const void *G,
-                     const void *u, void *w, const int32_t *l2g,
-                     const int32_t *stop, hipStream_t s) {
+                     const void *u, void *w, hipStream_t s) {
   using S8 = AxShape<N1, 8>;
   using S4 = AxShape<N1, 4>;
   const int epb = prec == SEM_FP64 ? S8::EPB : S4::EPB;
@@ -199,56 +224,149 @@ static void launch_n(int prec, int64_t E, const void *D, const void *G,
   const int64_t blocks = (E + epb - 1) / epb;
   if (blocks == 0) return;
   dim3 grid((unsigned)blocks), block(threads);
-  const bool gather = l2g != nullptr;
-  if (prec == SEM_FP64) {
-    if (gather)
-      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, true, false>), grid,
-                         block, 0, s, E, (const double *)D, (const double *)G,
-                         (const double *)u, (double *)w, l2g, stop);
-    else
-      hipLaunchKernelGGL((k_ax<N1, double, double, double, double, false, true>),
-                         grid, block, 0, s, E, (const double *)D,
-                         (const double *)G, (const double *)u, (double *)w, l2g,
-                         stop);
-  } else if (prec == SEM_FP32) {
-    if (gather)
-      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, true, false>), grid,
-                         block, 0, s, E, (const float *)D, (const float *)G,
-                         (const float *)u, (float *)w, l2g, stop);
-    else
-      hipLaunchKernelGGL((k_ax<N1, float, float, float, float, false, true>), grid,
-                         block, 0, s, E, (const float *)D, (const float *)G,
-                         (const float *)u, (float *)w, l2g, stop);
-  } else {
-    // BF16 geometric factors.  Standalone: bf16 input; inside solvers the
-    // FP32 unique vector is gathered directly.
-    if (gather)
-      hipLaunchKernelGGL((k_ax<N1, float, uint16_t, float, float, true, false>), grid,
-                         block, 0, s, E, (const float *)D, (const uint16_t *)G,
-                         (const float *)u, (float *)w, l2g, stop);
-    else
-      hipLaunchKernelGGL((k_ax<N1, uint16_t, uint16_t, float, float, false, true>),
-                         grid, block, 0, s, E, (const float *)D,
-                         (const uint16_t *)G, (const uint16_t *)u, (float *)w,
-                         l2g, stop);
-  }
+  if (prec == SEM_FP64)
+    hipLaunchKernelGGL((k_ax<N1, double, double, double, double, false, true>),
+                       grid, block, 0, s, E, (const double *)D,
+                       (const double *)G, (const double *)u, (double *)w,
+                       (const int32_t *)nullptr, (const int32_t *)nullptr);
+  else if (prec == SEM_FP32)
+    hipLaunchKernelGGL((k_ax<N1, float, float, float, float, false, true>), grid,
+                       block, 0, s, E, (const float *)D, (const float *)G,
+                       (const float *)u, (float *)w, (const int32_t *)nullptr,
+                       (const int32_t *)nullptr);
+  else
+    hipLaunchKernelGGL((k_ax<N1, uint16_t, uint16_t, float, float, false, true>),
+                       grid, block, 0, s, E, (const float *)D,
+                       (const uint16_t *)G, (const uint16_t *)u, (float *)w,
+                       (const int32_t *)nullptr, (const int32_t *)nullptr);
 }
 
 void launch_ax(int N, int prec, int64_t E, const void *D, const void *G,
-               const void *u, void *w, const int32_t *l2g, const int32_t *stop,
-               hipStream_t s) {
+               const void *u, void *w, hipStream_t s) {
   switch (N) {
-    case 1: launch_n<2>(prec, E, D, G, u, w, l2g, stop, s); break;
-    case 2: launch_n<3>(prec, E, D, G, u, w, l2g, stop, s); break;
-    case 3: launch_n<4>(prec, E, D, G, u, w, l2g, stop, s); break;
-    case 4: launch_n<5>(prec, E, D, G, u, w, l2g, stop, s); break;
-    case 5: launch_n<6>(prec, E, D, G, u, w, l2g, stop, s); break;
-    case 6: launch_n<7>(prec, E, D, G, u, w, l2g, stop, s); break;
-    case 7: launch_n<8>(prec, E, D, G, u, w, l2g, stop, s); break;
-    case 8: launch_n<9>(prec, E, D, G, u, w, l2g, stop, s); break;
+    case 1: launch_n<2>(prec, E, D, G, u, w, s); break;
+    case 2: launch_n<3>(prec, E, D, G, u, w, s); break;
+    case 3: launch_n<4>(prec, E, D, G, u, w, s); break;
+    case 4: launch_n<5>(prec, E, D, G, u, w, s); break;
+    case 5: launch_n<6>(prec, E, D, G, u, w, s); break;
+    case 6: launch_n<7>(prec, E, D, G, u, w, s); break;
+    case 7: launch_n<8>(prec, E, D, G, u, w, s); break;
+    case 8: launch_n<9>(prec, E, D, G, u, w, s); break;
     default: fail(SEM_ERR_ARG, "sem_ax: N must be in 1..8");
   }
   SEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// persistent batched operator: work items are (solve, first element) tiles;
+// each workgroup walks items blockIdx.x, blockIdx.x + gridDim.x, ...
+// ---------------------------------------------------------------------------
+template <int BS, int N1> struct BTile {
+  static constexpr int EPB = (BS / (N1 * N1)) > 0 ? BS / (N1 * N1) : 1;
+};
+
+template <int BS, class TV, class TG, class TC, int N1>
+__device__ __forceinline__ void bax_one(const BatchSolve &sd, int64_t e0,
+                                        int src, int dst, TC *smem) {
+  const TV *u = (const TV *)(sizeof(TV) == 8 ? sd.v64[src] : sd.v32[src]);
+  TV *w = (TV *)(sizeof(TV) == 8 ? sd.v64[dst] : sd.v32[dst]);
+  const TG *G = (const TG *)(sizeof(TG) == 8   ? sd.G64
+                             : sizeof(TG) == 4 ? sd.G32
+                                               : sd.G16);
+  const TC *D = (const TC *)(sizeof(TC) == 8 ? sd.D64 : sd.D32);
+  ax_tile<N1, BTile<BS, N1>::EPB, TV, TG, TV, TC, true, false>(
+      threadIdx.x, e0, sd.E, D, G, u, w, sd.l2g, smem);
+}
+
+template <int BS, class TV, class TG, class TC, int... N1s>
+__global__ void __launch_bounds__(BS)
+    k_bax(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
+          const AxItem *__restrict__ items, int nitems, int src, int dst,
+          int skip_done) {
+  extern __shared__ unsigned char dyn_smem[];
+  TC *smem = reinterpret_cast<TC *>(dyn_smem);
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const AxItem it = items[q];
+    if (skip_done && st[it.solve].done != 0) continue;  // uniform per block
+    const BatchSolve &sd = sds[it.solve];
+    const int n1 = sd.N1;
+    // exactly one of the compiled orders matches the item's order
+    ((n1 == N1s ? bax_one<BS, TV, TG, TC, N1s>(sd, it.elem0, src, dst, smem)
+                : void()),
+     ...);
+    __syncthreads();  // the next item may use another LDS layout
+  }
+}
+
+template <int BS, int... N1s> constexpr int max_lds_words() {
+  int m = 0;
+  ((m = lds_words<N1s>(BTile<BS, N1s>::EPB) > m
+            ? lds_words<N1s>(BTile<BS, N1s>::EPB)
+            : m),
+   ...);
+  return m;
+}
+
+template <int BS, class TV, class TG, class TC, int... N1s>
+static void launch_bax_set(const BatchSolve *sds, const CgState *st,
+                           const AxItem *items, int nitems, int grid, int src,
+                           int dst, int skip_done, hipStream_t s) {
+  const size_t lds = (size_t)max_lds_words<BS, N1s...>() * sizeof(TC);
+  hipLaunchKernelGGL((k_bax<BS, TV, TG, TC, N1s...>), dim3(grid), dim3(BS), lds,
+                     s, sds, st, items, nitems, src, dst, skip_done);
+}
+
+template <int BS, class TV, class TG, class TC>
+static void launch_bax_bs(int nset, const BatchSolve *sds, const CgState *st,
+                          const AxItem *items, int nitems, int grid, int src,
+                          int dst, int skip_done, hipStream_t s) {
+  // order sets compiled: one order (n1 = 2..9) or the mixed set {4, 6, 8}
+  switch (nset) {
+    case 2: launch_bax_set<BS, TV, TG, TC, 2>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 3: launch_bax_set<BS, TV, TG, TC, 3>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 4: launch_bax_set<BS, TV, TG, TC, 4>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 5: launch_bax_set<BS, TV, TG, TC, 5>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 6: launch_bax_set<BS, TV, TG, TC, 6>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 7: launch_bax_set<BS, TV, TG, TC, 7>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 8: launch_bax_set<BS, TV, TG, TC, 8>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 9: launch_bax_set<BS, TV, TG, TC, 9>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case AX_SET_468: launch_bax_set<BS, TV, TG, TC, 4, 6, 8>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    default: fail(SEM_ERR_ARG, "batched operator: unsupported set of orders");
+  }
+}
+
+template <class TV, class TG, class TC>
+static void launch_bax_t(int bs, int nset, const BatchSolve *sds,
+                         const CgState *st, const AxItem *items, int nitems,
+                         int grid, int src, int dst, int skip_done,
+                         hipStream_t s) {
+  switch (bs) {
+    case 64: launch_bax_bs<64, TV, TG, TC>(nset, sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 128: launch_bax_bs<128, TV, TG, TC>(nset, sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    case 256: launch_bax_bs<256, TV, TG, TC>(nset, sds, st, items, nitems, grid, src, dst, skip_done, s); break;
+    default: fail(SEM_ERR_ARG, "batched operator: block size must be 64, 128 or 256");
+  }
+}
+
+void launch_bax(int prec, int bs, int nset, const BatchSolve *sds,
+                const CgState *st, const AxItem *items, int nitems, int grid,
+                int src, int dst, int skip_done, hipStream_t s) {
+  if (nitems <= 0) return;
+  if (prec == SEM_FP64)
+    launch_bax_t<double, double, double>(bs, nset, sds, st, items, nitems, grid,
+                                         src, dst, skip_done, s);
+  else if (prec == SEM_FP32)
+    launch_bax_t<float, float, float>(bs, nset, sds, st, items, nitems, grid, src,
+                                      dst, skip_done, s);
+  else
+    launch_bax_t<float, uint16_t, float>(bs, nset, sds, st, items, nitems, grid,
+                                         src, dst, skip_done, s);
+  SEM_HIP(hipGetLastError());
+}
+
+int bax_elements_per_tile(int bs, int n1) {
+  const int np = n1 * n1;
+  return bs / np > 0 ? bs / np : 1;
 }
 
 }  // namespace sem

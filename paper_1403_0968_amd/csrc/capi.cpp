@@ -157,7 +157,7 @@ sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
     } else {
       fail(SEM_ERR_ARG, "sem_ax: unknown precision");
     }
-    launch_ax(h->N, p, h->E, D, G, u_L, w_L, nullptr, nullptr, strm(stream));
+    launch_ax(h->N, p, h->E, D, G, u_L, w_L, strm(stream));
   });
 }
 
@@ -199,6 +199,54 @@ sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *o,
   if (result != SEM_OK)
     g_last_error = result == SEM_ERR_BREAKDOWN ? "sem_pcg_solve: breakdown"
                                                : "sem_pcg_solve: not converged";
+  return result;
+}
+
+sem_status sem_batch_create(sem_handle *const *handles, int32_t n,
+                            sem_batch **out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    need(handles != nullptr && out != nullptr && n >= 1,
+         "sem_batch_create: need handles, n >= 1 and an output");
+    *out = batch_create(handles, n);
+  });
+}
+
+sem_status sem_batch_destroy(sem_batch *b) {
+  return guarded([&] {
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    batch_destroy(b);
+  });
+}
+
+sem_status sem_batch_tune(sem_batch *b, int32_t p, int32_t *block_size,
+                          int32_t *grid_mult, double *us) {
+  return guarded([&] {
+    need(b != nullptr, "sem_batch_tune: null batch");
+    int bs = 0, gm = 0;
+    double t = 0.0;
+    batch_tune(b, p, &bs, &gm, &t);
+    if (block_size) *block_size = bs;
+    if (grid_mult) *grid_mult = gm;
+    if (us) *us = t;
+  });
+}
+
+sem_status sem_batch_pcg_solve(sem_batch *b, const sem_solve_opts *o,
+                               const double *const *b_L, double *const *x_L,
+                               sem_solve_stats *stats, void *stream) {
+  sem_status result = SEM_OK;
+  sem_status g = guarded([&] {
+    need(b != nullptr && o != nullptr && b_L != nullptr && x_L != nullptr,
+         "sem_batch_pcg_solve: null argument");
+    result = batch_solve(b, o, b_L, x_L, stats, strm(stream));
+  });
+  if (g != SEM_OK) return g;
+  if (result != SEM_OK)
+    g_last_error = result == SEM_ERR_BREAKDOWN
+                       ? "sem_batch_pcg_solve: breakdown in a solve"
+                       : "sem_batch_pcg_solve: a solve did not converge";
   return result;
 }
 

@@ -70,9 +70,37 @@ struct CgState {
   double pad0;
   int32_t it;     // iterations done
   int32_t maxit;
-  int32_t done;   // 0 running, 1 converged, 2 breakdown, 3 maxit
+  int32_t done;   // 0 running, 1 converged, 2 breakdown, 3 maxit, 4 idle
   int32_t pad1;
 };
+
+// vectors of one solve (unique-node layout except VWL, an E-vector)
+enum { VB = 0, VX, VR, VZ, VP, VW, VWL, NVEC };
+
+// one solve of a batch as the device kernels see it
+struct BatchSolve {
+  int32_t N1, solve;
+  int64_t E, nL, nG;
+  const int32_t *l2g, *off, *perm;
+  const uint8_t *gmask;
+  const void *G64, *G32, *G16, *D64, *D32;
+  const double *dinv64, *one64;   // Jacobi, and 1 off the Dirichlet boundary
+  const float *dinv32, *one32;
+  void *v64[NVEC];
+  void *v32[NVEC];
+};
+
+// work items of the persistent kernels
+struct AxItem {  // a tile of elements of one solve
+  int32_t solve, pad;
+  int64_t elem0;
+};
+struct VecItem {  // a chunk of unique nodes of one solve
+  int32_t solve, pad;
+  int64_t start;
+};
+constexpr int VCH = 2048;      // unique nodes per vector item
+constexpr int AX_SET_468 = 100;  // batched operator compiled for n1 in {4,6,8}
 
 }  // namespace sem
 
@@ -98,17 +126,29 @@ struct sem_handle {
 
 namespace sem {
 
-// kernels / launchers (ax.hip, gs.hip, cg.hip, setup.hip)
+// kernels / launchers (ax.hip, gs.hip, setup.hip)
 void launch_ax(int N, int prec, int64_t E, const void *D, const void *G,
-               const void *u, void *w, const int32_t *l2g_gather,
-               const int32_t *stop, hipStream_t s);
+               const void *u, void *w, hipStream_t s);
 void launch_gs(sem_handle *h, int prec, void *v, hipStream_t s);
 void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s);
 void launch_rhs(sem_handle *h, const sem_source *src, double *b, hipStream_t s);
 void launch_precond(sem_handle *h, int pc, int prec, const void *r, void *z,
                     hipStream_t s);
+// persistent batched operator over (solve, element tile) items; src / dst are
+// vector indices (VP, VX, ..., VWL) of the precision's vector set
+void launch_bax(int prec, int bs, int nset, const BatchSolve *sds,
+                const CgState *st, const AxItem *items, int nitems, int grid,
+                int src, int dst, int skip_done, hipStream_t s);
+int bax_elements_per_tile(int bs, int n1);
 // solver (solver.hip)
 void destroy_ws(sem_handle *h);
+sem_batch *batch_create(sem_handle *const *hs, int n);
+void batch_destroy(sem_batch *b);
+void batch_tune(sem_batch *b, int prec, int *best_bs, int *best_gm,
+                double *best_us);
+sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
+                       const double *const *bL, double *const *xL,
+                       sem_solve_stats *stats, hipStream_t caller);
 sem_status pcg_solve(sem_handle *h, const sem_solve_opts *o, const double *b_L,
                      double *x_L, sem_solve_stats *st, hipStream_t s);
 

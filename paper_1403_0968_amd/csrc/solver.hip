@@ -1,261 +1,362 @@
 // Preconditioned conjugate gradients for the assembled SEM system (paper
 // section 4.2.2: the system is solved by PCG, whose dominant cost is the
-// operator application), plus FP64 iterative refinement around an FP32 /
-// BF16-operator inner PCG.
+// operator application), FP64 iterative refinement around an FP32 /
+// BF16-operator inner PCG, and batches of independent solves of uneven size
+// and order.
 //
-// Vectors live on unique (global) nodes; the operator is applied as
+// Everything runs on batches: a single solve is a batch of one.  Vectors
+// live on unique (global) nodes; the operator is applied as
 //   w_G = mask o Q^T A_L Q p_G
 // with Q fused into the operator kernel (gather through l2g) and Q^T + mask
-// fused with the (p, w) dot product.  Iteration kernels:
-//   ax(gather) -> assemble+dot -> alpha -> x,r update + z = dinv r + dots
-//   -> beta/convergence -> p update.
-// Scalars stay on the device; each kernel returns at once when the device
-// flag says the solve has finished, so a captured graph of K iterations can
-// be replayed between host polls without changing the result.  Reductions
-// use a fixed grid and a fixed order: results are bit-reproducible.
+// fused with the (p, w) dot product.  One CG iteration of the whole batch is
+// six launches of persistent kernels that walk work lists of
+// (solve, element tile) or (solve, node chunk) items:
+//   operator -> assemble + dot -> alpha -> x, r update + z = dinv r + dots
+//   -> beta / convergence -> p update.
+// Scalars stay on the device, one CgState per solve; kernels skip items of
+// solves whose flag says they finished, so a captured HIP graph of K
+// iterations is replayed between host polls without changing any iterate.
+// Every reduction has a fixed partition (one partial per work item) and a
+// fixed summation order: results are bit-reproducible, and a solve gives the
+// same bits alone or inside any batch.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <fstream>
+#include <map>
+#include <set>
+#include <sstream>
+#include <string>
 
 #include "common.h"
 #include "sem_internal.h"
 
 namespace sem {
 
-constexpr int RT = 256;
-constexpr int RBLK_MAX = 2048;
-
-static int red_blocks(int64_t n) {
-  int64_t b = (n + RT - 1) / RT;
-  return (int)std::min<int64_t>(std::max<int64_t>(b, 1), RBLK_MAX);
-}
+constexpr int RT = 256;           // threads of the vector kernels
+static_assert(VCH % RT == 0, "chunk must be a multiple of the block");
 
 // --------------------------------------------------------------------------
-// kernels
+// vector kernels (persistent over VecItem lists)
 // --------------------------------------------------------------------------
-template <class TL, class TV, bool DOT>
+template <class TV> __device__ inline TV *vec(const BatchSolve &s, int v) {
+  return (TV *)(sizeof(TV) == 8 ? s.v64[v] : s.v32[v]);
+}
+template <class TD> __device__ inline const TD *dinv_of(const BatchSolve &s,
+                                                        int jac) {
+  if constexpr (sizeof(TD) == 8)
+    return (const TD *)(jac ? s.dinv64 : s.one64);
+  else
+    return (const TD *)(jac ? s.dinv32 : s.one32);
+}
+
+// w = mask o Q^T wL (sum of copies in ascending local index); optional
+// partial (p, w) per item
+template <class TV, bool DOT>
 __global__ void __launch_bounds__(RT)
-    k_assemble(int64_t nG, const int32_t *__restrict__ off,
-               const int32_t *__restrict__ perm,
-               const uint8_t *__restrict__ gmask, const TL *__restrict__ wL,
-               TV *__restrict__ wG, const TV *__restrict__ p,
-               double *__restrict__ part, const int32_t *__restrict__ stop) {
+    k_bassemble(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
+                const VecItem *__restrict__ items, int nitems,
+                double *__restrict__ part, int skip_done) {
   __shared__ double sm[RT / 64];
-  if (stop != nullptr && *stop != 0) return;
-  double acc = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * RT;
-  for (int64_t g = (int64_t)blockIdx.x * RT + threadIdx.x; g < nG; g += stride) {
-    TL s = TL(0);
-    const int a = off[g], b = off[g + 1];
-    for (int q = a; q < b; ++q) s = s + wL[perm[q]];
-    const TV v = gmask[g] ? TV(0) : (TV)s;
-    wG[g] = v;
-    if (DOT) acc += (double)p[g] * (double)v;
-  }
-  if (DOT) {
-    const double t = block_sum<RT>(acc, sm);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (skip_done && st[it.solve].done != 0) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const TV *wL = vec<TV>(sd, VWL);
+    TV *wG = vec<TV>(sd, VW);
+    const TV *p = vec<TV>(sd, VP);
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    double acc = 0.0;
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      TV s = TV(0);
+      const int a = sd.off[g], b = sd.off[g + 1];
+      for (int k = a; k < b; ++k) s = s + wL[sd.perm[k]];
+      const TV v = sd.gmask[g] ? TV(0) : s;
+      wG[g] = v;
+      if (DOT) acc += (double)p[g] * (double)v;
+    }
+    if (DOT) {
+      const double t = block_sum<RT>(acc, sm);
+      if (threadIdx.x == 0) part[q] = t;
+    }
   }
 }
 
+// alpha_s = rz_s / (p, A p)_s, one workgroup per solve
 __global__ void __launch_bounds__(RT)
-    k_alpha(CgState *st, const double *__restrict__ part, int nb) {
+    k_balpha(CgState *st, const double *__restrict__ part,
+             const int32_t *__restrict__ vbeg) {
   __shared__ double sm[RT / 64];
-  if (st->done != 0) return;
+  const int s = blockIdx.x;
+  if (st[s].done != 0) return;
   double a = 0.0;
-  for (int q = threadIdx.x; q < nb; q += RT) a += part[q];
+  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) a += part[q];
   const double pw = block_sum<RT>(a, sm);
   if (threadIdx.x == 0) {
-    st->pw = pw;
+    st[s].pw = pw;
     if (!(pw > 0.0) || !isfinite(pw))
-      st->done = 2;
+      st[s].done = 2;
     else
-      st->alpha = st->rz / pw;
+      st[s].alpha = st[s].rz / pw;
   }
 }
 
 template <class TV, class TD>
 __global__ void __launch_bounds__(RT)
-    k_update_xr(int64_t nG, const CgState *__restrict__ st, TV *__restrict__ x,
-                TV *__restrict__ r, const TV *__restrict__ p,
-                const TV *__restrict__ w, const TD *__restrict__ dinv,
-                TV *__restrict__ z, double *__restrict__ part, int nb) {
+    k_bupdate_xr(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
+                 const VecItem *__restrict__ items, int nitems,
+                 double *__restrict__ part, int jac) {
   __shared__ double sm[RT / 64];
-  if (st->done != 0) return;
-  const TV alpha = (TV)st->alpha;
-  double rz = 0.0, rr = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * RT;
-  for (int64_t g = (int64_t)blockIdx.x * RT + threadIdx.x; g < nG; g += stride) {
-    x[g] = x[g] + alpha * p[g];
-    const TV rn = r[g] - alpha * w[g];
-    r[g] = rn;
-    const TV zn = (TV)(dinv[g] * rn);
-    z[g] = zn;
-    rz += (double)rn * (double)zn;
-    rr += (double)rn * (double)rn;
-  }
-  const double trz = block_sum<RT>(rz, sm);
-  const double trr = block_sum<RT>(rr, sm);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = trz;
-    part[nb + blockIdx.x] = trr;
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (st[it.solve].done != 0) continue;
+    const BatchSolve &sd = sds[it.solve];
+    TV *x = vec<TV>(sd, VX), *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ);
+    const TV *p = vec<TV>(sd, VP), *w = vec<TV>(sd, VW);
+    const TD *dinv = dinv_of<TD>(sd, jac);
+    const TV alpha = (TV)st[it.solve].alpha;
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    double rz = 0.0, rr = 0.0;
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      x[g] = x[g] + alpha * p[g];
+      const TV rn = r[g] - alpha * w[g];
+      r[g] = rn;
+      const TV zn = (TV)(dinv[g] * rn);
+      z[g] = zn;
+      rz += (double)rn * (double)zn;
+      rr += (double)rn * (double)rn;
+    }
+    const double trz = block_sum<RT>(rz, sm);
+    const double trr = block_sum<RT>(rr, sm);
+    if (threadIdx.x == 0) {
+      part[q] = trz;
+      part[nitems + q] = trr;
+    }
   }
 }
 
+// rz, rr per solve -> convergence / beta
 __global__ void __launch_bounds__(RT)
-    k_beta(CgState *st, const double *__restrict__ part, int nb) {
+    k_bbeta(CgState *st, const double *__restrict__ part,
+            const int32_t *__restrict__ vbeg, int nitems) {
   __shared__ double sm[RT / 64];
-  if (st->done != 0) return;
+  const int s = blockIdx.x;
+  if (st[s].done != 0) return;
   double a = 0.0, b = 0.0;
-  for (int q = threadIdx.x; q < nb; q += RT) {
+  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
     a += part[q];
-    b += part[nb + q];
+    b += part[nitems + q];
   }
   const double rz = block_sum<RT>(a, sm);
   const double rr = block_sum<RT>(b, sm);
   if (threadIdx.x == 0) {
-    st->it += 1;
-    st->rr = rr;
+    CgState &c = st[s];
+    c.it += 1;
+    c.rr = rr;
     if (!isfinite(rr) || !isfinite(rz))
-      st->done = 2;
-    else if (rr <= st->tol2 * st->bb)
-      st->done = 1;
-    else if (st->it >= st->maxit)
-      st->done = 3;
+      c.done = 2;
+    else if (rr <= c.tol2 * c.bb)
+      c.done = 1;
+    else if (c.it >= c.maxit)
+      c.done = 3;
     else {
-      st->beta = rz / st->rz;
-      st->rz = rz;
+      c.beta = rz / c.rz;
+      c.rz = rz;
     }
   }
 }
 
 template <class TV>
 __global__ void __launch_bounds__(RT)
-    k_update_p(int64_t nG, const CgState *__restrict__ st,
-               const TV *__restrict__ z, TV *__restrict__ p) {
-  if (st->done != 0) return;
-  const TV beta = (TV)st->beta;
-  const int64_t stride = (int64_t)gridDim.x * RT;
-  for (int64_t g = (int64_t)blockIdx.x * RT + threadIdx.x; g < nG; g += stride)
-    p[g] = z[g] + beta * p[g];
+    k_bupdate_p(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
+                const VecItem *__restrict__ items, int nitems) {
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (st[it.solve].done != 0) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const TV *z = vec<TV>(sd, VZ);
+    TV *p = vec<TV>(sd, VP);
+    const TV beta = (TV)st[it.solve].beta;
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
+      p[g] = z[g] + beta * p[g];
+  }
 }
 
-// r = b - w (w == nullptr: x0 = 0, r = b and x is zeroed), z = dinv r, p = z
+// r = b - w (x0_zero: r = b and x = 0), z = dinv r, p = z; partials of
+// (r, z), (r, r), (b, b)
 template <class TV, class TD>
 __global__ void __launch_bounds__(RT)
-    k_init(int64_t nG, const TV *__restrict__ b, const TV *__restrict__ w,
-           TV *__restrict__ x, TV *__restrict__ r, TV *__restrict__ z,
-           TV *__restrict__ p, const TD *__restrict__ dinv,
-           double *__restrict__ part, int nb) {
+    k_binit(const BatchSolve *__restrict__ sds, const int32_t *__restrict__ active,
+            const VecItem *__restrict__ items, int nitems,
+            double *__restrict__ part, int x0_zero, int jac) {
   __shared__ double sm[RT / 64];
-  double rz = 0.0, rr = 0.0, bb = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * RT;
-  for (int64_t g = (int64_t)blockIdx.x * RT + threadIdx.x; g < nG; g += stride) {
-    const TV bv = b[g];
-    TV rv = bv;
-    if (w != nullptr)
-      rv = bv - w[g];
-    else
-      x[g] = TV(0);
-    const TV zv = (TV)(dinv[g] * rv);
-    r[g] = rv;
-    z[g] = zv;
-    p[g] = zv;
-    rz += (double)rv * (double)zv;
-    rr += (double)rv * (double)rv;
-    bb += (double)bv * (double)bv;
-  }
-  const double a = block_sum<RT>(rz, sm);
-  const double c = block_sum<RT>(rr, sm);
-  const double d = block_sum<RT>(bb, sm);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = a;
-    part[nb + blockIdx.x] = c;
-    part[2 * nb + blockIdx.x] = d;
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (!active[it.solve]) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const TV *b = vec<TV>(sd, VB), *w = vec<TV>(sd, VW);
+    TV *x = vec<TV>(sd, VX), *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ),
+       *p = vec<TV>(sd, VP);
+    const TD *dinv = dinv_of<TD>(sd, jac);
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    double rz = 0.0, rr = 0.0, bb = 0.0;
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      const TV bv = b[g];
+      TV rv = bv;
+      if (x0_zero)
+        x[g] = TV(0);
+      else
+        rv = bv - w[g];
+      const TV zv = (TV)(dinv[g] * rv);
+      r[g] = rv;
+      z[g] = zv;
+      p[g] = zv;
+      rz += (double)rv * (double)zv;
+      rr += (double)rv * (double)rv;
+      bb += (double)bv * (double)bv;
+    }
+    const double a = block_sum<RT>(rz, sm);
+    const double c = block_sum<RT>(rr, sm);
+    const double d = block_sum<RT>(bb, sm);
+    if (threadIdx.x == 0) {
+      part[q] = a;
+      part[nitems + q] = c;
+      part[2 * nitems + q] = d;
+    }
   }
 }
 
 __global__ void __launch_bounds__(RT)
-    k_init_reduce(CgState *st, const double *__restrict__ part, int nb,
-                  double tol2, int maxit) {
+    k_binit_reduce(CgState *st, const double *__restrict__ part,
+                   const int32_t *__restrict__ vbeg, int nitems,
+                   const int32_t *__restrict__ active,
+                   const int32_t *__restrict__ maxit, double tol2) {
   __shared__ double sm[RT / 64];
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int q = threadIdx.x; q < nb; q += RT) {
+  const int s = blockIdx.x;
+  CgState &c = st[s];
+  if (!active[s]) {
+    if (threadIdx.x == 0) {
+      c.done = 4;
+      c.it = 0;
+    }
+    return;
+  }
+  double a = 0.0, b = 0.0, d = 0.0;
+  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
     a += part[q];
-    b += part[nb + q];
-    c += part[2 * nb + q];
+    b += part[nitems + q];
+    d += part[2 * nitems + q];
   }
   const double rz = block_sum<RT>(a, sm);
   const double rr = block_sum<RT>(b, sm);
-  const double bb = block_sum<RT>(c, sm);
+  const double bb = block_sum<RT>(d, sm);
   if (threadIdx.x == 0) {
-    st->rz = rz;
-    st->rr = rr;
-    st->bb = bb;
-    st->tol2 = tol2;
-    st->it = 0;
-    st->maxit = maxit;
-    st->alpha = st->beta = st->pw = 0.0;
+    c.rz = rz;
+    c.rr = rr;
+    c.bb = bb;
+    c.tol2 = tol2;
+    c.it = 0;
+    c.maxit = maxit[s];
+    c.alpha = c.beta = c.pw = 0.0;
     if (!isfinite(rr) || !isfinite(rz))
-      st->done = 2;
+      c.done = 2;
     else if (rr <= tol2 * bb)
-      st->done = 1;
-    else if (maxit <= 0)
-      st->done = 3;
+      c.done = 1;
+    else if (c.maxit <= 0)
+      c.done = 3;
     else
-      st->done = 0;
+      c.done = 0;
   }
 }
 
-// rr partials of r = b - w (FP64); r is stored when r_out != nullptr
+// FP64 residual r = b - w (stored), partials (r, r), (b, b)
 __global__ void __launch_bounds__(RT)
-    k_residual(int64_t nG, const double *__restrict__ b,
-               const double *__restrict__ w, double *__restrict__ r_out,
-               double *__restrict__ part) {
+    k_bresidual(const BatchSolve *__restrict__ sds,
+                const int32_t *__restrict__ active,
+                const VecItem *__restrict__ items, int nitems,
+                double *__restrict__ part) {
   __shared__ double sm[RT / 64];
-  double rr = 0.0, bb = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * RT;
-  for (int64_t g = (int64_t)blockIdx.x * RT + threadIdx.x; g < nG; g += stride) {
-    const double rv = b[g] - w[g];
-    if (r_out != nullptr) r_out[g] = rv;
-    rr += rv * rv;
-    bb += b[g] * b[g];
-  }
-  const double a = block_sum<RT>(rr, sm);
-  const double c = block_sum<RT>(bb, sm);
-  if (threadIdx.x == 0) {
-    part[blockIdx.x] = a;
-    part[gridDim.x + blockIdx.x] = c;
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (!active[it.solve]) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const double *b = vec<double>(sd, VB), *w = vec<double>(sd, VW);
+    double *r = vec<double>(sd, VR);
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    double rr = 0.0, bb = 0.0;
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      const double rv = b[g] - w[g];
+      r[g] = rv;
+      rr += rv * rv;
+      bb += b[g] * b[g];
+    }
+    const double a = block_sum<RT>(rr, sm);
+    const double c = block_sum<RT>(bb, sm);
+    if (threadIdx.x == 0) {
+      part[q] = a;
+      part[nitems + q] = c;
+    }
   }
 }
 
-// out[0] = sum part[0..nb), out[1] = sum part[nb..2nb)
+// out[2 s], out[2 s + 1] = sums of the two partial rows over solve s
 __global__ void __launch_bounds__(RT)
-    k_reduce2(const double *__restrict__ part, int nb, double *out) {
+    k_breduce2(const double *__restrict__ part, const int32_t *__restrict__ vbeg,
+               int nitems, const int32_t *__restrict__ active, double *out) {
   __shared__ double sm[RT / 64];
+  const int s = blockIdx.x;
+  if (!active[s]) return;
   double a = 0.0, b = 0.0;
-  for (int q = threadIdx.x; q < nb; q += RT) {
+  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
     a += part[q];
-    b += part[nb + q];
+    b += part[nitems + q];
   }
   const double s0 = block_sum<RT>(a, sm);
   const double s1 = block_sum<RT>(b, sm);
   if (threadIdx.x == 0) {
-    out[0] = s0;
-    out[1] = s1;
+    out[2 * s] = s0;
+    out[2 * s + 1] = s1;
   }
 }
 
-__global__ void k_scale_cast(int64_t n, const double *__restrict__ r, double s,
-                             float *__restrict__ o) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < n) o[g] = (float)(r[g] * s);
+// inner right-hand side b32 = r64 * scale_s; x64 += d32 / scale_s
+__global__ void __launch_bounds__(RT)
+    k_bscale_cast(const BatchSolve *__restrict__ sds,
+                  const int32_t *__restrict__ active,
+                  const double *__restrict__ scale,
+                  const VecItem *__restrict__ items, int nitems) {
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (!active[it.solve]) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const double *r = vec<double>(sd, VR);
+    float *b = vec<float>(sd, VB);
+    const double sc = scale[it.solve];
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
+      b[g] = (float)(r[g] * sc);
+  }
 }
 
-__global__ void k_axpy_mixed(int64_t n, double *__restrict__ x,
-                             const float *__restrict__ d, double s) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g < n) x[g] += s * (double)d[g];
+__global__ void __launch_bounds__(RT)
+    k_baxpy_mixed(const BatchSolve *__restrict__ sds,
+                  const int32_t *__restrict__ active,
+                  const double *__restrict__ scale,
+                  const VecItem *__restrict__ items, int nitems) {
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (!active[it.solve]) continue;
+    const BatchSolve &sd = sds[it.solve];
+    double *x = vec<double>(sd, VX);
+    const float *d = vec<float>(sd, VX);
+    const double inv = 1.0 / scale[it.solve];
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
+      x[g] += inv * (double)d[g];
+  }
 }
 
 __global__ void k_first_copy(int64_t nG, const int32_t *__restrict__ off,
@@ -282,339 +383,602 @@ __global__ void k_unmask(int64_t nG, const uint8_t *__restrict__ gmask,
 }
 
 // --------------------------------------------------------------------------
-// host orchestration
+// per-handle solver vectors
 // --------------------------------------------------------------------------
+struct Workspace {
+  DevBuf v64[NVEC], v32[NVEC], one64, one32;
+  bool ready = false;
+  sem_batch *single = nullptr;  // the handle as a batch of one
+};
+
 static unsigned nblk(int64_t n) { return (unsigned)((n + RT - 1) / RT); }
 
-struct Workspace {
-  DevBuf x64, r64, z64, p64, w64, b64, wL64;
-  DevBuf b32, x32, r32, z32, p32, w32, wL32;
-  DevBuf one64, one32;       // preconditioner "none": 1 off the boundary
-  DevBuf part, st, red;      // partials, CgState, reduce outputs
-  CgState *host_st = nullptr;  // pinned
-  double *host_red = nullptr;  // pinned
-  hipStream_t hs = nullptr;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, fence = nullptr;
-  struct GraphEntry {
-    int prec, f32, k, jac;
-    hipGraphExec_t exec;
-  };
-  std::vector<GraphEntry> graphs;
-  ~Workspace() {
-    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
-    if (host_st) (void)hipHostFree(host_st);
-    if (host_red) (void)hipHostFree(host_red);
-    if (ev0) (void)hipEventDestroy(ev0);
-    if (ev1) (void)hipEventDestroy(ev1);
-    if (fence) (void)hipEventDestroy(fence);
-    if (hs) (void)hipStreamDestroy(hs);
+static void ensure_vectors(sem_handle *h) {
+  if (h->ws == nullptr) h->ws = new Workspace();
+  Workspace *W = h->ws;
+  if (W->ready) return;
+  for (int v = 0; v < NVEC; ++v) {
+    const int64_t n = v == VWL ? h->nL : h->nG;
+    W->v64[v].alloc(n * sizeof(double));
+    W->v32[v].alloc(n * sizeof(float));
   }
-};
-
-Workspace *get_ws(sem_handle *h);
-
-struct CgPlan {
-  int prec_ax;  // operator precision
-  bool f32;     // FP32 vectors
-  void *x, *r, *z, *p, *wG, *wL;
-  const void *b, *dinv, *G, *D;
-};
-
-static void launch_iteration(sem_handle *h, Workspace *W, const CgPlan &P,
-                             hipStream_t s) {
-  const int nb = red_blocks(h->nG);
-  CgState *st = W->st.as<CgState>();
-  double *part = W->part.as<double>();
-  const int32_t *stop = &st->done;
-  launch_ax(h->N, P.prec_ax, h->E, P.D, P.G, P.p, P.wL, h->l2g.as<int32_t>(),
-            stop, s);
-  if (!P.f32) {
-    hipLaunchKernelGGL((k_assemble<double, double, true>), dim3(nb), dim3(RT), 0,
-                       s, h->nG, h->offsets.as<int32_t>(), h->perm.as<int32_t>(),
-                       h->gmask.as<uint8_t>(), (const double *)P.wL,
-                       (double *)P.wG, (const double *)P.p, part, stop);
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(RT), 0, s, st, part, nb);
-    hipLaunchKernelGGL((k_update_xr<double, double>), dim3(nb), dim3(RT), 0, s,
-                       h->nG, st, (double *)P.x, (double *)P.r,
-                       (const double *)P.p, (const double *)P.wG,
-                       (const double *)P.dinv, (double *)P.z, part, nb);
-    hipLaunchKernelGGL(k_beta, dim3(1), dim3(RT), 0, s, st, part, nb);
-    hipLaunchKernelGGL((k_update_p<double>), dim3(nb), dim3(RT), 0, s, h->nG,
-                       st, (const double *)P.z, (double *)P.p);
-  } else {
-    hipLaunchKernelGGL((k_assemble<float, float, true>), dim3(nb), dim3(RT), 0,
-                       s, h->nG, h->offsets.as<int32_t>(), h->perm.as<int32_t>(),
-                       h->gmask.as<uint8_t>(), (const float *)P.wL,
-                       (float *)P.wG, (const float *)P.p, part, stop);
-    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(RT), 0, s, st, part, nb);
-    hipLaunchKernelGGL((k_update_xr<float, float>), dim3(nb), dim3(RT), 0, s,
-                       h->nG, st, (float *)P.x, (float *)P.r,
-                       (const float *)P.p, (const float *)P.wG,
-                       (const float *)P.dinv, (float *)P.z, part, nb);
-    hipLaunchKernelGGL(k_beta, dim3(1), dim3(RT), 0, s, st, part, nb);
-    hipLaunchKernelGGL((k_update_p<float>), dim3(nb), dim3(RT), 0, s, h->nG, st,
-                       (const float *)P.z, (float *)P.p);
-  }
-  SEM_HIP(hipGetLastError());
-}
-
-// A x for FP64 unique x into W->w64 (through W->wL64)
-static void apply_fp64(sem_handle *h, Workspace *W, const double *x,
-                       hipStream_t s) {
-  const int nb = red_blocks(h->nG);
-  launch_ax(h->N, SEM_FP64, h->E, h->D64.p, h->G64.p, x, W->wL64.p,
-            h->l2g.as<int32_t>(), nullptr, s);
-  hipLaunchKernelGGL((k_assemble<double, double, false>), dim3(nb), dim3(RT), 0,
-                     s, h->nG, h->offsets.as<int32_t>(), h->perm.as<int32_t>(),
-                     h->gmask.as<uint8_t>(), W->wL64.as<double>(),
-                     W->w64.as<double>(), (const double *)nullptr,
-                     (double *)nullptr, (const int32_t *)nullptr);
-  SEM_HIP(hipGetLastError());
-}
-
-// ||b - A x||^2 and ||b||^2 (FP64); r stored in W->r64 when store_r
-static void residual_fp64(sem_handle *h, Workspace *W, const double *x,
-                          bool store_r, hipStream_t s, double &rr, double &bb) {
-  apply_fp64(h, W, x, s);
-  const int nb = red_blocks(h->nG);
-  hipLaunchKernelGGL(k_residual, dim3(nb), dim3(RT), 0, s, h->nG,
-                     W->b64.as<double>(), W->w64.as<double>(),
-                     store_r ? W->r64.as<double>() : (double *)nullptr,
-                     W->part.as<double>());
-  hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(RT), 0, s, W->part.as<double>(), nb,
-                     W->red.as<double>());
-  SEM_HIP(hipGetLastError());
-  SEM_HIP(hipMemcpyAsync(W->host_red, W->red.p, 2 * sizeof(double),
-                         hipMemcpyDeviceToHost, s));
-  SEM_HIP(hipStreamSynchronize(s));
-  rr = W->host_red[0];
-  bb = W->host_red[1];
-}
-
-static void launch_init(sem_handle *h, Workspace *W, const CgPlan &P, bool x0_zero,
-                        double tol2, int maxit, hipStream_t s) {
-  const int nb = red_blocks(h->nG);
-  double *part = W->part.as<double>();
-  if (!P.f32) {
-    const double *w = nullptr;
-    if (!x0_zero) {
-      apply_fp64(h, W, (const double *)P.x, s);
-      w = W->w64.as<double>();
-    }
-    hipLaunchKernelGGL((k_init<double, double>), dim3(nb), dim3(RT), 0, s, h->nG,
-                       (const double *)P.b, w, (double *)P.x, (double *)P.r,
-                       (double *)P.z, (double *)P.p, (const double *)P.dinv,
-                       part, nb);
-  } else {
-    if (!x0_zero) fail(SEM_ERR_STATE, "internal: FP32 CG needs x0 = 0");
-    hipLaunchKernelGGL((k_init<float, float>), dim3(nb), dim3(RT), 0, s, h->nG,
-                       (const float *)P.b, (const float *)nullptr, (float *)P.x,
-                       (float *)P.r, (float *)P.z, (float *)P.p,
-                       (const float *)P.dinv, part, nb);
-  }
-  hipLaunchKernelGGL(k_init_reduce, dim3(1), dim3(RT), 0, s, W->st.as<CgState>(),
-                     part, nb, tol2, maxit);
-  SEM_HIP(hipGetLastError());
-}
-
-static hipGraphExec_t get_graph(sem_handle *h, Workspace *W, const CgPlan &P,
-                                int K, int jac, hipStream_t s) {
-  for (auto &g : W->graphs)
-    if (g.prec == P.prec_ax && g.f32 == (int)P.f32 && g.k == K && g.jac == jac)
-      return g.exec;
-  hipGraph_t graph;
-  SEM_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-  try {
-    for (int q = 0; q < K; ++q) launch_iteration(h, W, P, s);
-  } catch (...) {
-    hipGraph_t dummy;
-    (void)hipStreamEndCapture(s, &dummy);
-    throw;
-  }
-  SEM_HIP(hipStreamEndCapture(s, &graph));
-  hipGraphExec_t exec;
-  SEM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
-  SEM_HIP(hipGraphDestroy(graph));
-  W->graphs.push_back({P.prec_ax, (int)P.f32, K, jac, exec});
-  return exec;
-}
-
-// run CG iterations from an initialised state; returns iterations and the
-// device 'done' code
-static void run_cg(sem_handle *h, Workspace *W, const CgPlan &P,
-                   const sem_solve_opts *o, int jac, hipStream_t s, int &iters,
-                   int &done) {
-  const int K = std::max(1, o->check_every);
-  SEM_HIP(hipMemcpyAsync(W->host_st, W->st.p, sizeof(CgState),
-                         hipMemcpyDeviceToHost, s));
-  SEM_HIP(hipStreamSynchronize(s));
-  while (W->host_st->done == 0) {
-    if (o->use_graph) {
-      hipGraphExec_t ex = get_graph(h, W, P, K, jac, s);
-      SEM_HIP(hipGraphLaunch(ex, s));
-    } else {
-      for (int q = 0; q < K; ++q) launch_iteration(h, W, P, s);
-    }
-    SEM_HIP(hipMemcpyAsync(W->host_st, W->st.p, sizeof(CgState),
-                           hipMemcpyDeviceToHost, s));
-    SEM_HIP(hipStreamSynchronize(s));
-  }
-  iters = W->host_st->it;
-  done = W->host_st->done;
-}
-
-static void ensure_ws(sem_handle *h, Workspace *W) {
-  if (W->hs != nullptr) return;
-  const size_t g8 = h->nG * sizeof(double), g4 = h->nG * sizeof(float);
-  W->x64.alloc(g8);
-  W->r64.alloc(g8);
-  W->z64.alloc(g8);
-  W->p64.alloc(g8);
-  W->w64.alloc(g8);
-  W->b64.alloc(g8);
-  W->wL64.alloc(h->nL * sizeof(double));
-  W->b32.alloc(g4);
-  W->x32.alloc(g4);
-  W->r32.alloc(g4);
-  W->z32.alloc(g4);
-  W->p32.alloc(g4);
-  W->w32.alloc(g4);
-  W->wL32.alloc(h->nL * sizeof(float));
-  W->one64.alloc(g8);
-  W->one32.alloc(g4);
-  W->part.alloc(3 * RBLK_MAX * sizeof(double));
-  W->st.alloc(sizeof(CgState));
-  W->red.alloc(4 * sizeof(double));
-  SEM_HIP(hipHostMalloc((void **)&W->host_st, sizeof(CgState), 0));
-  SEM_HIP(hipHostMalloc((void **)&W->host_red, 4 * sizeof(double), 0));
-  SEM_HIP(hipEventCreate(&W->ev0));
-  SEM_HIP(hipEventCreate(&W->ev1));
-  SEM_HIP(hipEventCreateWithFlags(&W->fence, hipEventDisableTiming));
-  hipStream_t hs;
-  SEM_HIP(hipStreamCreateWithFlags(&hs, hipStreamNonBlocking));
-  W->hs = hs;
-  hipLaunchKernelGGL(k_unmask, dim3(nblk(h->nG)), dim3(RT), 0, hs, h->nG,
+  W->one64.alloc(h->nG * sizeof(double));
+  W->one32.alloc(h->nG * sizeof(float));
+  hipLaunchKernelGGL(k_unmask, dim3(nblk(h->nG)), dim3(RT), 0, 0, h->nG,
                      h->gmask.as<uint8_t>(), W->one64.as<double>(),
                      W->one32.as<float>());
   SEM_HIP(hipGetLastError());
+  SEM_HIP(hipDeviceSynchronize());
+  W->ready = true;
+}
+
+}  // namespace sem
+
+// --------------------------------------------------------------------------
+// batches
+// --------------------------------------------------------------------------
+struct sem_batch {
+  std::vector<sem_handle *> hs;
+  int n = 0;
+  int nset = 0;                 // order set the operator kernel is built for
+  std::vector<int> orders;      // n1 per solve
+  sem::DevBuf sds, st, vitems, vbeg, part, red, active, maxit, scale;
+  sem::DevBuf axitems[3];       // per block size 64 / 128 / 256
+  int n_ax[3] = {0, 0, 0};
+  int n_vi = 0;
+  int bs[3] = {128, 64, 64};    // operator block size per precision
+  int gmul[3] = {0, 0, 0};      // persistent grid = 256 CUs x gmul (0: 1 item/WG)
+  sem::CgState *host_st = nullptr;
+  double *host_red = nullptr;
+  int32_t *host_i = nullptr;    // staging for active / maxit
+  double *host_d = nullptr;     // staging for scale
+  hipStream_t s = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, fence = nullptr;
+  struct GraphEntry {
+    int prec, k, jac;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  bool tuned = false;
+  ~sem_batch() {
+    for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+    if (host_st) (void)hipHostFree(host_st);
+    if (host_red) (void)hipHostFree(host_red);
+    if (host_i) (void)hipHostFree(host_i);
+    if (host_d) (void)hipHostFree(host_d);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    if (fence) (void)hipEventDestroy(fence);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+namespace sem {
+
+static int bs_slot(int bs) { return bs == 64 ? 0 : bs == 128 ? 1 : 2; }
+
+sem_batch *batch_create(sem_handle *const *hs, int n) {
+  if (n < 1) fail(SEM_ERR_ARG, "batch: need at least one handle");
+  std::set<int> orders;
+  for (int q = 0; q < n; ++q) {
+    if (hs[q] == nullptr) fail(SEM_ERR_ARG, "batch: null handle");
+    if (hs[q]->nL >= (int64_t)INT32_MAX) fail(SEM_ERR_ARG, "batch: solve too large");
+    orders.insert(hs[q]->n1);
+    for (int r = 0; r < q; ++r)
+      if (hs[r] == hs[q]) fail(SEM_ERR_ARG, "batch: a handle appears twice");
+  }
+  int nset;
+  if (orders.size() == 1)
+    nset = *orders.begin();
+  else {
+    for (int o : orders)
+      if (o != 4 && o != 6 && o != 8)
+        fail(SEM_ERR_ARG, "batch: mixed orders must be within N in {3, 5, 7}");
+    nset = AX_SET_468;
+  }
+  sem_batch *b = new sem_batch();
+  try {
+    b->hs.assign(hs, hs + n);
+    b->n = n;
+    b->nset = nset;
+    std::vector<BatchSolve> sds(n);
+    std::vector<VecItem> vis;
+    std::vector<int32_t> vbeg(n + 1);
+    for (int q = 0; q < n; ++q) {
+      sem_handle *h = hs[q];
+      ensure_vectors(h);
+      Workspace *W = h->ws;
+      BatchSolve &d = sds[q];
+      memset(&d, 0, sizeof d);
+      d.N1 = h->n1;
+      d.solve = q;
+      d.E = h->E;
+      d.nL = h->nL;
+      d.nG = h->nG;
+      d.l2g = h->l2g.as<int32_t>();
+      d.off = h->offsets.as<int32_t>();
+      d.perm = h->perm.as<int32_t>();
+      d.gmask = h->gmask.as<uint8_t>();
+      d.G64 = h->G64.p;
+      d.G32 = h->G32.p;
+      d.G16 = h->G16.p;
+      d.D64 = h->D64.p;
+      d.D32 = h->D32.p;
+      d.dinv64 = h->dinv_G.as<double>();
+      d.dinv32 = h->dinv_G32.as<float>();
+      d.one64 = W->one64.as<double>();
+      d.one32 = W->one32.as<float>();
+      for (int v = 0; v < NVEC; ++v) {
+        d.v64[v] = W->v64[v].p;
+        d.v32[v] = W->v32[v].p;
+      }
+      vbeg[q] = (int32_t)vis.size();
+      for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({q, 0, g});
+      b->orders.push_back(h->n1);
+    }
+    vbeg[n] = (int32_t)vis.size();
+    b->n_vi = (int)vis.size();
+    const int bss[3] = {64, 128, 256};
+    for (int k = 0; k < 3; ++k) {
+      std::vector<AxItem> ax;
+      for (int q = 0; q < n; ++q) {
+        const int epb = bax_elements_per_tile(bss[k], hs[q]->n1);
+        for (int64_t e = 0; e < hs[q]->E; e += epb) ax.push_back({q, 0, e});
+      }
+      b->n_ax[k] = (int)ax.size();
+      b->axitems[k].alloc(ax.size() * sizeof(AxItem));
+      SEM_HIP(hipMemcpy(b->axitems[k].p, ax.data(), ax.size() * sizeof(AxItem),
+                        hipMemcpyHostToDevice));
+    }
+    b->sds.alloc(n * sizeof(BatchSolve));
+    SEM_HIP(hipMemcpy(b->sds.p, sds.data(), n * sizeof(BatchSolve),
+                      hipMemcpyHostToDevice));
+    b->vitems.alloc(vis.size() * sizeof(VecItem));
+    SEM_HIP(hipMemcpy(b->vitems.p, vis.data(), vis.size() * sizeof(VecItem),
+                      hipMemcpyHostToDevice));
+    b->vbeg.alloc((n + 1) * sizeof(int32_t));
+    SEM_HIP(hipMemcpy(b->vbeg.p, vbeg.data(), (n + 1) * sizeof(int32_t),
+                      hipMemcpyHostToDevice));
+    b->part.alloc(3 * (size_t)b->n_vi * sizeof(double));
+    b->st.alloc(n * sizeof(CgState));
+    b->red.alloc(2 * n * sizeof(double));
+    b->active.alloc(n * sizeof(int32_t));
+    b->maxit.alloc(n * sizeof(int32_t));
+    b->scale.alloc(n * sizeof(double));
+    SEM_HIP(hipHostMalloc((void **)&b->host_st, n * sizeof(CgState), 0));
+    SEM_HIP(hipHostMalloc((void **)&b->host_red, 2 * n * sizeof(double), 0));
+    SEM_HIP(hipHostMalloc((void **)&b->host_i, n * sizeof(int32_t), 0));
+    SEM_HIP(hipHostMalloc((void **)&b->host_d, n * sizeof(double), 0));
+    SEM_HIP(hipEventCreate(&b->ev0));
+    SEM_HIP(hipEventCreate(&b->ev1));
+    SEM_HIP(hipEventCreateWithFlags(&b->fence, hipEventDisableTiming));
+    SEM_HIP(hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking));
+    SEM_HIP(hipDeviceSynchronize());
+  } catch (...) {
+    delete b;
+    throw;
+  }
+  return b;
+}
+
+void batch_destroy(sem_batch *b) { delete b; }
+
+void destroy_ws(sem_handle *h) {
+  if (h->ws == nullptr) return;
+  delete h->ws->single;
+  delete h->ws;
+  h->ws = nullptr;
+}
+
+// --------------------------------------------------------------------------
+// launches of one batch
+// --------------------------------------------------------------------------
+static int vec_grid(const sem_batch *b) { return std::min(b->n_vi, 2048); }
+
+static void bax(sem_batch *b, int prec, int src, int dst, int skip_done) {
+  const int bs = b->bs[prec];
+  const int k = bs_slot(bs);
+  const int n = b->n_ax[k];
+  const int grid = b->gmul[prec] > 0 ? std::min(n, 256 * b->gmul[prec]) : n;
+  launch_bax(prec, bs, b->nset, b->sds.as<BatchSolve>(), b->st.as<CgState>(),
+             b->axitems[k].as<AxItem>(), n, grid, src, dst, skip_done, b->s);
+}
+
+template <class TV, class TD>
+static void iteration_t(sem_batch *b, int prec, int jac) {
+  const BatchSolve *sds = b->sds.as<BatchSolve>();
+  CgState *st = b->st.as<CgState>();
+  const VecItem *vi = b->vitems.as<VecItem>();
+  double *part = b->part.as<double>();
+  const int32_t *vbeg = b->vbeg.as<int32_t>();
+  const int g = vec_grid(b), nv = b->n_vi, n = b->n;
+  bax(b, prec, VP, VWL, 1);
+  hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds, st,
+                     vi, nv, part, 1);
+  hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
+  hipLaunchKernelGGL((k_bupdate_xr<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds, st,
+                     vi, nv, part, jac);
+  hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
+  hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
+                     nv);
+  SEM_HIP(hipGetLastError());
+}
+
+static void iteration(sem_batch *b, int prec, int jac) {
+  if (prec == SEM_FP64)
+    iteration_t<double, double>(b, prec, jac);
+  else
+    iteration_t<float, float>(b, prec, jac);
+}
+
+// initial residual and state for the active solves; the vector set of `prec`
+static void init(sem_batch *b, int prec, int jac, bool x0_zero, double tol2) {
+  const BatchSolve *sds = b->sds.as<BatchSolve>();
+  const VecItem *vi = b->vitems.as<VecItem>();
+  double *part = b->part.as<double>();
+  const int g = vec_grid(b), nv = b->n_vi;
+  const int32_t *act = b->active.as<int32_t>();
+  if (!x0_zero) {
+    // w = A x (FP64 only)
+    bax(b, SEM_FP64, VX, VWL, 0);
+    hipLaunchKernelGGL((k_bassemble<double, false>), dim3(g), dim3(RT), 0, b->s,
+                       sds, b->st.as<CgState>(), vi, nv, part, 0);
+  }
+  if (prec == SEM_FP64)
+    hipLaunchKernelGGL((k_binit<double, double>), dim3(g), dim3(RT), 0, b->s, sds,
+                       act, vi, nv, part, x0_zero ? 1 : 0, jac);
+  else
+    hipLaunchKernelGGL((k_binit<float, float>), dim3(g), dim3(RT), 0, b->s, sds,
+                       act, vi, nv, part, x0_zero ? 1 : 0, jac);
+  hipLaunchKernelGGL(k_binit_reduce, dim3(b->n), dim3(RT), 0, b->s,
+                     b->st.as<CgState>(), part, b->vbeg.as<int32_t>(), nv, act,
+                     b->maxit.as<int32_t>(), tol2);
+  SEM_HIP(hipGetLastError());
+}
+
+// FP64 true residuals of the active solves: host_red[2s] = ||b - A x||^2,
+// host_red[2s+1] = ||b||^2; r stored in VR
+static void residual(sem_batch *b) {
+  const BatchSolve *sds = b->sds.as<BatchSolve>();
+  const VecItem *vi = b->vitems.as<VecItem>();
+  double *part = b->part.as<double>();
+  const int g = vec_grid(b), nv = b->n_vi;
+  const int32_t *act = b->active.as<int32_t>();
+  bax(b, SEM_FP64, VX, VWL, 0);
+  hipLaunchKernelGGL((k_bassemble<double, false>), dim3(g), dim3(RT), 0, b->s, sds,
+                     b->st.as<CgState>(), vi, nv, part, 0);
+  hipLaunchKernelGGL(k_bresidual, dim3(g), dim3(RT), 0, b->s, sds, act, vi, nv,
+                     part);
+  hipLaunchKernelGGL(k_breduce2, dim3(b->n), dim3(RT), 0, b->s, part,
+                     b->vbeg.as<int32_t>(), nv, act, b->red.as<double>());
+  SEM_HIP(hipGetLastError());
+  SEM_HIP(hipMemcpyAsync(b->host_red, b->red.p, 2 * b->n * sizeof(double),
+                         hipMemcpyDeviceToHost, b->s));
+  SEM_HIP(hipStreamSynchronize(b->s));
+}
+
+static void upload_active(sem_batch *b, const std::vector<int> &act,
+                          const std::vector<int> &maxit) {
+  for (int q = 0; q < b->n; ++q) b->host_i[q] = act[q];
+  SEM_HIP(hipMemcpyAsync(b->active.p, b->host_i, b->n * sizeof(int32_t),
+                         hipMemcpyHostToDevice, b->s));
+  SEM_HIP(hipStreamSynchronize(b->s));
+  for (int q = 0; q < b->n; ++q) b->host_i[q] = maxit[q];
+  SEM_HIP(hipMemcpyAsync(b->maxit.p, b->host_i, b->n * sizeof(int32_t),
+                         hipMemcpyHostToDevice, b->s));
+  SEM_HIP(hipStreamSynchronize(b->s));
+}
+
+static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac) {
+  for (auto &g : b->graphs)
+    if (g.prec == prec && g.k == K && g.jac == jac) return g.exec;
+  hipGraph_t graph;
+  SEM_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
+  try {
+    for (int q = 0; q < K; ++q) iteration(b, prec, jac);
+  } catch (...) {
+    hipGraph_t dummy;
+    (void)hipStreamEndCapture(b->s, &dummy);
+    throw;
+  }
+  SEM_HIP(hipStreamEndCapture(b->s, &graph));
+  hipGraphExec_t exec;
+  SEM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  SEM_HIP(hipGraphDestroy(graph));
+  b->graphs.push_back({prec, K, jac, exec});
+  return exec;
+}
+
+// run CG iterations until every solve's flag is set
+static void run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o) {
+  const int K = std::max(1, o->check_every);
+  auto poll = [&]() {
+    SEM_HIP(hipMemcpyAsync(b->host_st, b->st.p, b->n * sizeof(CgState),
+                           hipMemcpyDeviceToHost, b->s));
+    SEM_HIP(hipStreamSynchronize(b->s));
+    for (int q = 0; q < b->n; ++q)
+      if (b->host_st[q].done == 0) return false;
+    return true;
+  };
+  while (!poll()) {
+    if (o->use_graph)
+      SEM_HIP(hipGraphLaunch(get_graph(b, prec, K, jac), b->s));
+    else
+      for (int q = 0; q < K; ++q) iteration(b, prec, jac);
+  }
+}
+
+// --------------------------------------------------------------------------
+// solve
+// --------------------------------------------------------------------------
+static void check_opts(const sem_solve_opts *o) {
+  if (!(o->rtol > 0.0) || o->maxit < 0 || o->check_every < 1)
+    fail(SEM_ERR_ARG, "solve: need rtol > 0, maxit >= 0, check_every >= 1");
+  if (o->pc != SEM_PC_NONE && o->pc != SEM_PC_JACOBI)
+    fail(SEM_ERR_ARG, "solve: unknown preconditioner");
+  if (o->inner_prec != SEM_FP64 && o->inner_prec != SEM_FP32 &&
+      o->inner_prec != SEM_BF16)
+    fail(SEM_ERR_ARG, "solve: unknown inner precision");
+  if (o->inner_prec != SEM_FP64 && !(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
+    fail(SEM_ERR_ARG, "solve: inner_rtol must be in (0, 1)");
+}
+
+sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
+                       const double *const *bL, double *const *xL,
+                       sem_solve_stats *stats, hipStream_t caller) {
+  check_opts(o);
+  for (int q = 0; q < b->n; ++q)
+    if (bL[q] == nullptr || xL[q] == nullptr || (const void *)bL[q] == xL[q])
+      fail(SEM_ERR_ARG, "solve: null or aliased b / x");
+  hipStream_t s = b->s;
+  SEM_HIP(hipEventRecord(b->fence, caller));
+  SEM_HIP(hipStreamWaitEvent(s, b->fence, 0));
+  SEM_HIP(hipEventRecord(b->ev0, s));
+  const int jac = o->pc == SEM_PC_JACOBI;
+  const int n = b->n;
+  for (int q = 0; q < n; ++q) {
+    sem_handle *h = b->hs[q];
+    Workspace *W = h->ws;
+    hipLaunchKernelGGL(k_first_copy, dim3(nblk(h->nG)), dim3(RT), 0, s, h->nG,
+                       h->offsets.as<int32_t>(), h->perm.as<int32_t>(), bL[q],
+                       W->v64[VB].as<double>());
+    hipLaunchKernelGGL(k_first_copy, dim3(nblk(h->nG)), dim3(RT), 0, s, h->nG,
+                       h->offsets.as<int32_t>(), h->perm.as<int32_t>(), xL[q],
+                       W->v64[VX].as<double>());
+  }
+  SEM_HIP(hipGetLastError());
+
+  std::vector<int> iters(n, 0), outer(n, 0), status(n, SEM_ERR_NOT_CONVERGED);
+  std::vector<int> act(n, 1), mx(n, o->maxit);
+  if (o->inner_prec == SEM_FP64) {
+    upload_active(b, act, mx);
+    init(b, SEM_FP64, jac, false, o->rtol * o->rtol);
+    run_cg(b, SEM_FP64, jac, o);
+    for (int q = 0; q < n; ++q) {
+      iters[q] = b->host_st[q].it;
+      const int d = b->host_st[q].done;
+      status[q] = d == 1 ? SEM_OK : d == 2 ? SEM_ERR_BREAKDOWN : SEM_ERR_NOT_CONVERGED;
+    }
+  } else {
+    // FP64 iterative refinement: r = b - A64 x; the inner PCG solves
+    // A_lo d = r / ||r|| with FP32 vectors and an FP32 or BF16-stored
+    // operator (FP64 dots and scalars); x += ||r|| d
+    const int prec = o->inner_prec;
+    std::vector<double> rel_prev(n, 1e300);
+    std::vector<int> stall(n, 0);
+    upload_active(b, act, mx);
+    residual(b);
+    while (true) {
+      int n_active = 0;
+      for (int q = 0; q < n; ++q) {
+        if (!act[q]) continue;
+        const double rr = b->host_red[2 * q], bb = b->host_red[2 * q + 1];
+        if (!std::isfinite(rr)) {
+          status[q] = SEM_ERR_BREAKDOWN;
+          act[q] = 0;
+          continue;
+        }
+        const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+        if (rel <= o->rtol) {
+          status[q] = SEM_OK;
+          act[q] = 0;
+          continue;
+        }
+        stall[q] = rel > 0.9 * rel_prev[q] ? stall[q] + 1 : 0;
+        rel_prev[q] = rel;
+        if (iters[q] >= o->maxit || stall[q] >= 3) {
+          act[q] = 0;  // not converged
+          continue;
+        }
+        b->host_d[q] = 1.0 / std::sqrt(rr);
+        mx[q] = o->maxit - iters[q];
+        ++n_active;
+      }
+      if (n_active == 0) break;
+      SEM_HIP(hipMemcpyAsync(b->scale.p, b->host_d, n * sizeof(double),
+                             hipMemcpyHostToDevice, s));
+      upload_active(b, act, mx);
+      const BatchSolve *sds = b->sds.as<BatchSolve>();
+      const VecItem *vi = b->vitems.as<VecItem>();
+      const int g = vec_grid(b);
+      hipLaunchKernelGGL(k_bscale_cast, dim3(g), dim3(RT), 0, s, sds,
+                         b->active.as<int32_t>(), b->scale.as<double>(), vi,
+                         b->n_vi);
+      SEM_HIP(hipGetLastError());
+      init(b, prec, jac, true, o->inner_rtol * o->inner_rtol);
+      run_cg(b, prec, jac, o);
+      for (int q = 0; q < n; ++q) {
+        if (!act[q]) continue;
+        iters[q] += b->host_st[q].it;
+        outer[q] += 1;
+        if (b->host_st[q].done == 2) {
+          status[q] = SEM_ERR_BREAKDOWN;
+          act[q] = 0;
+        }
+      }
+      upload_active(b, act, mx);
+      hipLaunchKernelGGL(k_baxpy_mixed, dim3(g), dim3(RT), 0, s, sds,
+                         b->active.as<int32_t>(), b->scale.as<double>(), vi,
+                         b->n_vi);
+      SEM_HIP(hipGetLastError());
+      residual(b);
+    }
+  }
+  for (int q = 0; q < n; ++q) {
+    sem_handle *h = b->hs[q];
+    hipLaunchKernelGGL(k_scatter, dim3(nblk(h->nL)), dim3(RT), 0, s, h->nL,
+                       h->l2g.as<int32_t>(), h->ws->v64[VX].as<double>(), xL[q]);
+  }
+  SEM_HIP(hipGetLastError());
+  SEM_HIP(hipEventRecord(b->ev1, s));
+  // recomputed FP64 residuals of every solve
+  std::vector<int> all(n, 1);
+  upload_active(b, all, mx);
+  residual(b);
+  float ms = 0.0f;
+  SEM_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  sem_status worst = SEM_OK;
+  for (int q = 0; q < n; ++q) {
+    if (stats != nullptr) {
+      const double rr = b->host_red[2 * q], bb = b->host_red[2 * q + 1];
+      stats[q].iters = iters[q];
+      stats[q].outer_iters = outer[q];
+      stats[q].status = status[q];
+      stats[q].reserved = 0;
+      stats[q].final_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+      stats[q].seconds = ms * 1e-3;
+    }
+    if (status[q] != SEM_OK && worst == SEM_OK) worst = (sem_status)status[q];
+  }
+  SEM_HIP(hipEventRecord(b->fence, s));
+  SEM_HIP(hipStreamWaitEvent(caller, b->fence, 0));
+  return worst;
 }
 
 sem_status pcg_solve(sem_handle *h, const sem_solve_opts *o, const double *b_L,
                      double *x_L, sem_solve_stats *st, hipStream_t caller) {
-  if (!(o->rtol > 0.0) || o->maxit < 0 || o->check_every < 1)
-    fail(SEM_ERR_ARG, "sem_pcg_solve: need rtol > 0, maxit >= 0, check_every >= 1");
-  if (o->pc != SEM_PC_NONE && o->pc != SEM_PC_JACOBI)
-    fail(SEM_ERR_ARG, "sem_pcg_solve: unknown preconditioner");
-  if (o->inner_prec != SEM_FP64 && o->inner_prec != SEM_FP32 &&
-      o->inner_prec != SEM_BF16)
-    fail(SEM_ERR_ARG, "sem_pcg_solve: unknown inner precision");
-  if (o->inner_prec != SEM_FP64 && !(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
-    fail(SEM_ERR_ARG, "sem_pcg_solve: inner_rtol must be in (0, 1)");
-  Workspace *W = get_ws(h);
-  ensure_ws(h, W);
-  hipStream_t s = W->hs;
-  // order after the caller's stream
-  SEM_HIP(hipEventRecord(W->fence, caller));
-  SEM_HIP(hipStreamWaitEvent(s, W->fence, 0));
-  SEM_HIP(hipEventRecord(W->ev0, s));
+  check_opts(o);
+  ensure_vectors(h);
+  if (h->ws->single == nullptr) {
+    sem_handle *one[1] = {h};
+    h->ws->single = batch_create(one, 1);
+  }
+  const double *bl[1] = {b_L};
+  double *xl[1] = {x_L};
+  return batch_solve(h->ws->single, o, bl, xl, st, caller);
+}
 
-  const int jac = o->pc == SEM_PC_JACOBI;
-  const int T = RT;
-  hipLaunchKernelGGL(k_first_copy, dim3(nblk(h->nG)), dim3(T), 0, s, h->nG,
-                     h->offsets.as<int32_t>(), h->perm.as<int32_t>(), b_L,
-                     W->b64.as<double>());
-  hipLaunchKernelGGL(k_first_copy, dim3(nblk(h->nG)), dim3(T), 0, s, h->nG,
-                     h->offsets.as<int32_t>(), h->perm.as<int32_t>(), x_L,
-                     W->x64.as<double>());
-  SEM_HIP(hipGetLastError());
+// --------------------------------------------------------------------------
+// autotuner: time the batched operator for each block size and persistent
+// grid, keep the fastest per precision; results cached in a JSON file named
+// by the SEM_AUTOTUNE_CACHE environment variable (if set)
+// --------------------------------------------------------------------------
+static std::string tune_key(const sem_batch *b, int prec) {
+  int64_t nodes = 0;
+  for (auto *h : b->hs) nodes += h->nL;
+  int bucket = 0;
+  while ((int64_t)1 << (bucket + 1) <= nodes) ++bucket;
+  hipDeviceProp_t p;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipGetDeviceProperties(&p, dev);
+  std::ostringstream k;
+  k << p.gcnArchName << "|set" << b->nset << "|prec" << prec << "|log2nodes"
+    << bucket;
+  std::string s = k.str();
+  for (auto &c : s)
+    if (c == '"' || c == '\\' || c == ':') c = '_';
+  return s;
+}
 
-  int iters = 0, outer = 0, done = 0;
-  sem_status status = SEM_OK;
-  if (o->inner_prec == SEM_FP64) {
-    CgPlan P{SEM_FP64, false, W->x64.p, W->r64.p, W->z64.p, W->p64.p, W->w64.p,
-             W->wL64.p, W->b64.p, jac ? h->dinv_G.p : W->one64.p, h->G64.p,
-             h->D64.p};
-    launch_init(h, W, P, false, o->rtol * o->rtol, o->maxit, s);
-    run_cg(h, W, P, o, jac, s, iters, done);
-    status = done == 1 ? SEM_OK
-             : done == 2 ? SEM_ERR_BREAKDOWN
-                         : SEM_ERR_NOT_CONVERGED;
-  } else {
-    // FP64 iterative refinement: r = b - A64 x; solve A_lo d = r / ||r|| in
-    // FP32 vectors with an FP32 or BF16-stored operator; x += ||r|| d
-    CgPlan P{o->inner_prec, true, W->x32.p, W->r32.p, W->z32.p, W->p32.p,
-             W->w32.p, W->wL32.p, W->b32.p, jac ? h->dinv_G32.p : W->one32.p,
-             o->inner_prec == SEM_FP32 ? h->G32.p : h->G16.p, h->D32.p};
-    double rr, bb;
-    residual_fp64(h, W, W->x64.as<double>(), true, s, rr, bb);
-    double rel_prev = 1e300;
-    int stall = 0;
-    status = SEM_ERR_NOT_CONVERGED;
-    while (true) {
-      if (!std::isfinite(rr)) {
-        status = SEM_ERR_BREAKDOWN;
-        break;
-      }
-      const double rel = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-      if (rel <= o->rtol) {
-        status = SEM_OK;
-        break;
-      }
-      if (iters >= o->maxit) break;
-      stall = rel > 0.9 * rel_prev ? stall + 1 : 0;
-      if (stall >= 3) break;
-      rel_prev = rel;
-      const double nr = std::sqrt(rr);
-      hipLaunchKernelGGL(k_scale_cast, dim3(nblk(h->nG)), dim3(T), 0, s, h->nG,
-                         W->r64.as<double>(), 1.0 / nr, W->b32.as<float>());
-      SEM_HIP(hipGetLastError());
-      launch_init(h, W, P, true, o->inner_rtol * o->inner_rtol,
-                  o->maxit - iters, s);
-      int it_in = 0, done_in = 0;
-      run_cg(h, W, P, o, jac, s, it_in, done_in);
-      iters += it_in;
-      outer += 1;
-      if (done_in == 2) {
-        status = SEM_ERR_BREAKDOWN;
-        break;
-      }
-      hipLaunchKernelGGL(k_axpy_mixed, dim3(nblk(h->nG)), dim3(T), 0, s, h->nG,
-                         W->x64.as<double>(), W->x32.as<float>(), nr);
-      SEM_HIP(hipGetLastError());
-      residual_fp64(h, W, W->x64.as<double>(), true, s, rr, bb);
+static std::map<std::string, std::pair<int, int>> read_cache(const char *path) {
+  std::map<std::string, std::pair<int, int>> m;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    // one entry per line: "key": [bs, gmul],
+    const size_t a = line.find('"'), b2 = line.find('"', a + 1);
+    const size_t l = line.find('['), c = line.find(',', l), r = line.find(']', l);
+    if (a == std::string::npos || b2 == std::string::npos ||
+        l == std::string::npos || c == std::string::npos || r == std::string::npos)
+      continue;
+    const int bs = atoi(line.substr(l + 1, c - l - 1).c_str());
+    const int gm = atoi(line.substr(c + 1, r - c - 1).c_str());
+    if (bs == 64 || bs == 128 || bs == 256) m[line.substr(a + 1, b2 - a - 1)] = {bs, gm};
+  }
+  return m;
+}
+
+static void write_cache(const char *path,
+                        const std::map<std::string, std::pair<int, int>> &m) {
+  std::ofstream f(std::string(path) + ".tmp");
+  f << "{\n";
+  size_t q = 0;
+  for (auto &kv : m) {
+    f << "  \"" << kv.first << "\": [" << kv.second.first << ", "
+      << kv.second.second << "]" << (++q < m.size() ? "," : "") << "\n";
+  }
+  f << "}\n";
+  f.close();
+  std::rename((std::string(path) + ".tmp").c_str(), path);
+}
+
+void batch_tune(sem_batch *b, int prec, int *best_bs, int *best_gm,
+                double *best_us) {
+  if (prec < SEM_FP64 || prec > SEM_BF16) fail(SEM_ERR_ARG, "tune: precision");
+  const char *path = getenv("SEM_AUTOTUNE_CACHE");
+  const std::string key = tune_key(b, prec);
+  if (path) {
+    auto m = read_cache(path);
+    auto it = m.find(key);
+    if (it != m.end()) {
+      b->bs[prec] = it->second.first;
+      b->gmul[prec] = it->second.second;
+      if (best_bs) *best_bs = b->bs[prec];
+      if (best_gm) *best_gm = b->gmul[prec];
+      if (best_us) *best_us = -1.0;
+      return;
     }
   }
-  // solution back to the caller's E-vector, true FP64 residual
-  hipLaunchKernelGGL(k_scatter, dim3(nblk(h->nL)), dim3(T), 0, s, h->nL,
-                     h->l2g.as<int32_t>(), W->x64.as<double>(), x_L);
-  SEM_HIP(hipGetLastError());
-  SEM_HIP(hipEventRecord(W->ev1, s));
-  double rr, bb;
-  residual_fp64(h, W, W->x64.as<double>(), false, s, rr, bb);
-  float ms = 0.0f;
-  SEM_HIP(hipEventElapsedTime(&ms, W->ev0, W->ev1));
-  if (st != nullptr) {
-    st->iters = iters;
-    st->outer_iters = outer;
-    st->status = status;
-    st->reserved = 0;
-    st->final_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-    st->seconds = ms * 1e-3;
+  // operator input: the p vectors hold whatever they hold; timing only
+  std::vector<int> all(b->n, 1), mx(b->n, 1);
+  upload_active(b, all, mx);
+  const int bss[3] = {64, 128, 256};
+  const int gms[5] = {0, 4, 8, 16, 32};
+  double best = 1e300;
+  int bbs = b->bs[prec], bgm = b->gmul[prec];
+  for (int bs : bss) {
+    for (int gm : gms) {
+      b->bs[prec] = bs;
+      b->gmul[prec] = gm;
+      bax(b, prec, VP, VWL, 0);  // warm
+      SEM_HIP(hipEventRecord(b->ev0, b->s));
+      const int reps = 3;
+      for (int r = 0; r < reps; ++r) bax(b, prec, VP, VWL, 0);
+      SEM_HIP(hipEventRecord(b->ev1, b->s));
+      SEM_HIP(hipEventSynchronize(b->ev1));
+      float ms = 0;
+      SEM_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+      const double us = ms * 1e3 / reps;
+      if (us < best) {
+        best = us;
+        bbs = bs;
+        bgm = gm;
+      }
+    }
   }
-  // the caller's stream waits for the solve
-  SEM_HIP(hipEventRecord(W->fence, s));
-  SEM_HIP(hipStreamWaitEvent(caller, W->fence, 0));
-  return status;
-}
-
-Workspace *get_ws(sem_handle *h) {
-  if (h->ws == nullptr) h->ws = new Workspace();
-  return h->ws;
-}
-
-void destroy_ws(sem_handle *h) {
-  delete h->ws;
-  h->ws = nullptr;
+  b->bs[prec] = bbs;
+  b->gmul[prec] = bgm;
+  for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+  if (path) {
+    auto m = read_cache(path);
+    m[key] = {bbs, bgm};
+    write_cache(path, m);
+  }
+  if (best_bs) *best_bs = bbs;
+  if (best_gm) *best_gm = bgm;
+  if (best_us) *best_us = best;
 }
 
 }  // namespace sem

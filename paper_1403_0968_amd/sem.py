@@ -26,7 +26,8 @@ SEM_SRC_FOURIER, SEM_SRC_SINE = 0, 1
 
 EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_gs", "sem_rhs", "sem_precond_apply", "sem_pcg_solve",
-            "sem_last_error"]
+            "sem_batch_create", "sem_batch_destroy", "sem_batch_tune",
+            "sem_batch_pcg_solve", "sem_last_error"]
 
 
 class sem_mesh_desc(C.Structure):
@@ -85,6 +86,13 @@ def lib():
     L.sem_precond_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     L.sem_pcg_solve.argtypes = [vp, C.POINTER(sem_solve_opts), vp, vp,
                                 C.POINTER(sem_solve_stats), vp]
+    L.sem_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
+    L.sem_batch_destroy.argtypes = [vp]
+    L.sem_batch_tune.argtypes = [vp, i32, C.POINTER(i32), C.POINTER(i32),
+                                 C.POINTER(C.c_double)]
+    L.sem_batch_pcg_solve.argtypes = [vp, C.POINTER(sem_solve_opts),
+                                      C.POINTER(vp), C.POINTER(vp),
+                                      C.POINTER(sem_solve_stats), vp]
     L.sem_last_error.argtypes = []
     L.sem_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -204,6 +212,51 @@ def sem_pcg_solve(h, b, x, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
         _check(code)
     return {"status": code, "iters": st.iters, "outer_iters": st.outer_iters,
             "final_rel_res": st.final_rel_res, "seconds": st.seconds}
+
+
+def _opts(rtol, maxit, pc, inner_prec, inner_rtol, check_every, use_graph):
+    o = sem_solve_opts()
+    o.rtol, o.maxit, o.pc = float(rtol), int(maxit), int(pc)
+    o.inner_prec, o.inner_rtol = int(inner_prec), float(inner_rtol)
+    o.check_every, o.use_graph = int(check_every), int(use_graph)
+    return o
+
+
+def sem_batch_create(handles):
+    arr = (C.c_void_p * len(handles))(*[h.value for h in handles])
+    b = C.c_void_p()
+    _check(lib().sem_batch_create(arr, len(handles), C.byref(b)))
+    return b
+
+
+def sem_batch_destroy(b):
+    _check(lib().sem_batch_destroy(b))
+
+
+def sem_batch_tune(b, prec):
+    bs, gm, us = C.c_int32(), C.c_int32(), C.c_double()
+    _check(lib().sem_batch_tune(b, int(prec), C.byref(bs), C.byref(gm),
+                                C.byref(us)))
+    return bs.value, gm.value, us.value
+
+
+def sem_batch_pcg_solve(b, bs, xs, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
+                        inner_prec=SEM_FP64, inner_rtol=1e-2, check_every=16,
+                        use_graph=1, stream=None, raise_on_fail=True):
+    """bs, xs: lists of device FP64 E-vectors (one per solve)."""
+    n = len(bs)
+    o = _opts(rtol, maxit, pc, inner_prec, inner_rtol, check_every, use_graph)
+    barr = (C.c_void_p * n)(*[t.data_ptr() for t in bs])
+    xarr = (C.c_void_p * n)(*[t.data_ptr() for t in xs])
+    st = (sem_solve_stats * n)()
+    code = lib().sem_batch_pcg_solve(b, C.byref(o), barr, xarr, st,
+                                     _stream(stream))
+    if raise_on_fail and code != SEM_OK:
+        _check(code)
+    return code, [{"status": st[q].status, "iters": st[q].iters,
+                   "outer_iters": st[q].outer_iters,
+                   "final_rel_res": st[q].final_rel_res,
+                   "seconds": st[q].seconds} for q in range(n)]
 
 
 def sem_last_error():
