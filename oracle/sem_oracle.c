@@ -469,14 +469,15 @@ done:
 }
 
 /* Flexible CG for a preconditioner that may change between iterations
- * (Notay 2000; Golub & Ye 1999): one search direction is kept and beta uses
- * the Polak-Ribiere form (z_{k+1}, r_{k+1} - r_k) / (z_k, r_k). */
+ * (Notay 2000, truncated to one previous direction): the new direction is
+ * z_{k+1} A-orthogonalised against p_k,
+ *   p_{k+1} = z_{k+1} + beta p_k,  beta = -(z_{k+1}, A p_k) / (p_k, A p_k),
+ * and alpha = (r_k, z_k) / (p_k, A p_k). */
 int orc_fcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
             const uint8_t *bmask, const double *D, const double *G,
             orc_precond_fn prec, void *ctx, const double *b, double *x,
             double rtol, int maxit, int *iters, double *hist) {
   double *r = (double *)malloc(nG * sizeof(double));
-  double *rold = (double *)malloc(nG * sizeof(double));
   double *z = (double *)malloc(nG * sizeof(double));
   double *p = (double *)malloc(nG * sizeof(double));
   double *w = (double *)malloc(nG * sizeof(double));
@@ -492,20 +493,17 @@ int orc_fcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
   }
   prec(r, z, ctx);
   for (int64_t g = 0; g < nG; ++g) p[g] = z[g];
-  double rz = dot(nG, r, z);
   for (k = 1; k <= maxit; ++k) {
     orc_apply_global(N, E, nG, l2g, bmask, D, G, p, w);
     double pw = dot(nG, p, w);
-    if (!(pw > 0) || !(rz > 0)) {
+    double rz = dot(nG, r, z);
+    if (!(pw > 0)) {
       status = 2;
       break;
     }
     double alpha = rz / pw;
     for (int64_t g = 0; g < nG; ++g) x[g] += alpha * p[g];
-    for (int64_t g = 0; g < nG; ++g) {
-      rold[g] = r[g];
-      r[g] -= alpha * w[g];
-    }
+    for (int64_t g = 0; g < nG; ++g) r[g] -= alpha * w[g];
     rnorm = sqrt(dot(nG, r, r));
     if (hist) hist[k] = rnorm / bnorm;
     if (rnorm <= rtol * bnorm) {
@@ -513,17 +511,13 @@ int orc_fcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
       break;
     }
     prec(r, z, ctx);
-    double num = 0;
-    for (int64_t g = 0; g < nG; ++g) num += z[g] * (r[g] - rold[g]);
-    double beta = num / rz;
-    rz = dot(nG, r, z);
+    double beta = -dot(nG, z, w) / pw;
     for (int64_t g = 0; g < nG; ++g) p[g] = z[g] + beta * p[g];
   }
   if (k > maxit) k = maxit;
 done:
   if (iters) *iters = k;
   free(r);
-  free(rold);
   free(z);
   free(p);
   free(w);

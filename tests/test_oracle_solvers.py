@@ -81,9 +81,9 @@ def test_fourier_source_is_smooth_sum_of_modes():
 
 @pytest.mark.parametrize("N", [3, 5])
 def test_fcg_with_fixed_jacobi_equals_pcg(N):
-    """With a fixed SPD preconditioner the Polak-Ribiere beta equals the
-    Fletcher-Reeves one in exact arithmetic (r_{k+1} is orthogonal to z_k),
-    so flexible CG reproduces PCG."""
+    """With a fixed SPD preconditioner, -(z_{k+1}, A p_k)/(p_k, A p_k) equals
+    (z_{k+1}, r_{k+1})/(z_k, r_k) in exact arithmetic (A p_k = (r_k -
+    r_{k+1})/alpha_k and (z_{k+1}, r_k) = 0), so flexible CG reproduces PCG."""
     m = orc.mesh(N, 3, 3, 2, orc.MAP_SINE_CYCLIC, dirichlet=1,
                  kappa_params=_kappa())
     k, a, phi = fourier_modes(seed=1)
