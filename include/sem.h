@@ -49,7 +49,13 @@ typedef enum {
 } sem_status;
 
 typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_BF16 = 2 } sem_precision;
-typedef enum { SEM_PC_NONE = 0, SEM_PC_JACOBI = 1 } sem_precond;
+typedef enum {
+  SEM_PC_NONE = 0,     /* z = r (off the Dirichlet boundary) */
+  SEM_PC_JACOBI = 1,   /* z = dinv o r */
+  SEM_PC_LEARNED = 2   /* z = dinv o r + learned coarse correction c(r), inside
+                          flexible CG; needs a network attached with
+                          sem_learn_attach; Jacobi-PCG is the fallback */
+} sem_precond;
 typedef enum {
   SEM_MAP_AFFINE = 0,      /* the unit cube itself */
   SEM_MAP_SINE_X = 1,      /* X = (x + 0.05 s(y)s(z), y, z), s(t) = sin(2 pi t) */
@@ -58,6 +64,7 @@ typedef enum {
 
 typedef struct sem_handle sem_handle; /* opaque, owned by the library */
 typedef struct sem_batch sem_batch;   /* opaque batch of independent solves */
+typedef struct sem_mlp sem_mlp;       /* opaque learned-correction network */
 
 /* Mesh and coefficients.  All pointers here are HOST pointers, read during
  * sem_setup only. */
@@ -109,7 +116,7 @@ typedef struct {
   int32_t iters;              /* CG iterations (all inner ones for IR) */
   int32_t outer_iters;        /* refinement steps (0 for plain PCG) */
   int32_t status;             /* sem_status of the solve */
-  int32_t reserved;
+  int32_t fell_back;          /* 1 when a learned solve switched to Jacobi */
   double final_rel_res;       /* recomputed FP64 ||b - A x|| / ||b|| */
   double seconds;             /* wall time of the solve on the stream */
 } sem_solve_stats;
@@ -173,7 +180,8 @@ sem_status sem_rhs(sem_handle *h, const sem_source *src, double *b_L,
 
 /* z_L = P r_L on continuous E-vectors.  SEM_PC_JACOBI: z = dinv o r with the
  * inverse of the assembled diagonal (0 on Dirichlet nodes); SEM_PC_NONE:
- * z = mask o r.  p = SEM_FP64 or SEM_FP32. */
+ * z = mask o r; SEM_PC_LEARNED (FP64 only, network attached): z = dinv o r +
+ * the averaged learned correction of r.  p = SEM_FP64 or SEM_FP32. */
 sem_status sem_precond_apply(sem_handle *h, int32_t pc, int32_t p,
                              const void *r_L, void *z_L, void *stream);
 
@@ -213,6 +221,103 @@ sem_status sem_batch_tune(sem_batch *b, int32_t p, int32_t *block_size,
 sem_status sem_batch_pcg_solve(sem_batch *b, const sem_solve_opts *opts,
                                const double *const *b_L, double *const *x_L,
                                sem_solve_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Learned per-element coarse correction (SEM_PC_LEARNED).  The paper leaves
+ * the PCG preconditioner open (section 4.2.2); this one adds to Jacobi a
+ * correction predicted element by element by a three-layer perceptron
+ *   z1 = x W1^T + b1, h1 = relu(z1), z2 = h1 W2^T + b2, h2 = relu(z2),
+ *   o = h2 W3^T + b3,
+ * hidden width 128, BF16 weights (FP32 master copy), FP32 accumulation on
+ * MFMA.  Element features x: the element's residual values divided by their
+ * 2-norm s_e, then log kappa at the 8 element vertices minus their mean, then
+ * zero padding to a multiple of 16.  Output: either the (N+1)^3 nodal values
+ * of the element or 8 trilinear vertex values prolonged to its GLL nodes;
+ * scaled by damping * s_e / (kappa_e h_e) (kappa_e the vertex mean, h_e the
+ * element size) and averaged over the copies of every node.  The damping
+ * and a Jacobi reference convergence rate are set by sem_learn_train and
+ * kept in checkpoints.  Fallback to Jacobi-PCG (stats.fell_back = 1) happens
+ * on NaN / breakdown, on stagnation (residual drop < 2x over 200
+ * iterations), when the learned solve converges at less than half the
+ * Jacobi rate after 100 iterations, when a refinement step fails to halve
+ * the FP64 true residual (the step is undone), or when the damping is 0.  Parameters are one FP32 vector: W1 [128][n_in], b1, W2
+ * [128][128], b2, W3 [n_out][128], b3 (row-major [out][in]).
+ * ------------------------------------------------------------------------ */
+/* He-initialised network (hidden width must be 128, n_out <= 1024). */
+sem_status sem_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out,
+                          uint64_t seed, sem_mlp **out);
+sem_status sem_mlp_destroy(sem_mlp *net);
+sem_status sem_mlp_info(const sem_mlp *net, int32_t *n_in, int32_t *n_hidden,
+                        int32_t *n_out, int32_t *n_in_padded,
+                        int64_t *n_params, int64_t *adam_steps);
+/* FP32 master parameters, HOST arrays of n_params floats; set resets Adam. */
+sem_status sem_mlp_get_params(const sem_mlp *net, float *params, int64_t n);
+sem_status sem_mlp_set_params(sem_mlp *net, const float *params, int64_t n);
+/* Forward pass of B samples: X device BF16 [B][ldx] (ldx >= n_in_padded, a
+ * multiple of 16; padding columns finite), Y device FP32 [B][n_out]. */
+sem_status sem_mlp_forward(sem_mlp *net, const uint16_t *X, int32_t ldx,
+                           int32_t B, float *Y, void *stream);
+/* Mean squared error between P o and targets T (device FP32 [B][(N+1)^3]):
+ * P is the trilinear prolongation to the GLL nodes of order N when n_out = 8,
+ * the identity when n_out = (N+1)^3
+ * and its gradient: grad device FP32 [n_params] (may be NULL: the network's
+ * own gradient buffer is used by sem_mlp_adam with grad NULL).  *loss is
+ * written on the host (synchronises the stream). */
+sem_status sem_mlp_loss_grad(sem_mlp *net, const uint16_t *X, int32_t ldx,
+                             const float *T, int32_t B, int32_t N, float *grad,
+                             double *loss, void *stream);
+/* One Adam step (Kingma & Ba 2015) on the master parameters with device
+ * gradient grad (NULL: the last sem_mlp_loss_grad gradient). */
+sem_status sem_mlp_adam(sem_mlp *net, const float *grad, double lr,
+                        double beta1, double beta2, double eps, void *stream);
+/* Correction scale and the Jacobi reference rate (log10 residual drop per
+ * Jacobi-PCG iteration, negative; 0 disables the progress judge). */
+sem_status sem_mlp_set_damping(sem_mlp *net, double damping, double jacobi_rate);
+sem_status sem_mlp_get_damping(const sem_mlp *net, double *damping,
+                               double *jacobi_rate);
+/* Checkpoint: magic, version, shapes, Adam step, FP32 parameters and Adam
+ * moments, CRC-32.  Load rejects truncated or altered files (SEM_ERR_ARG). */
+sem_status sem_mlp_save(const sem_mlp *net, const char *path);
+sem_status sem_mlp_load(const char *path, sem_mlp **out);
+
+/* Attach a network (NULL detaches) to a handle for SEM_PC_LEARNED; the
+ * network must outlive the attachment and have n_in = (N+1)^3 + 8 and
+ * n_out = 8 or (N+1)^3. */
+sem_status sem_learn_attach(sem_handle *h, sem_mlp *net);
+
+typedef struct {
+  int32_t n_pairs;          /* element residual/error pairs to sample */
+  int32_t snapshot_every;   /* solver iterations between snapshots */
+  int32_t max_snapshots;    /* per right-hand side */
+  int32_t epochs;
+  int32_t batch;            /* samples per Adam step */
+  int32_t reserved;
+  double lr;                /* Adam learning rate */
+  double solve_rtol;        /* FP64 Jacobi-PCG tolerance of the data solves */
+  uint64_t seed;            /* sampling and shuffling */
+} sem_train_opts;
+
+typedef struct {
+  int32_t pairs, epochs, snapshots, reserved;
+  double first_loss, last_loss;   /* mean loss of the first / last epoch */
+  double data_seconds, train_seconds, validate_seconds;
+  double damping;                 /* chosen correction scale (0: disabled) */
+  double jacobi_rate;             /* Jacobi-PCG log10 residual drop / iteration */
+  int32_t val_iters_jacobi, val_iters_learned;  /* validation solve to 1e-6 */
+  int32_t val_iters[4];   /* learned iterations for damping 0.2, 0.15, 0.1,
+                             0.05 (-1: not converged or fell back) */
+} sem_train_report;
+
+/* Generate training pairs with the FP64 solver and train the network on the
+ * GPU.  For every right-hand side b_L[q] (device FP64 E-vectors) a FP64
+ * Jacobi-PCG solve from x = 0 records snapshots x_k, r_k; once it converged,
+ * e_k = x* - x_k; pairs (r_k, e_k) restricted to random elements give the
+ * features and the targets e_e kappa_e h_e / s_e.  Training: epochs of
+ * shuffled minibatches of forward, loss, backward and Adam, all on the GPU.
+ * Then the damping is validated on the last right-hand side (see above). */
+sem_status sem_learn_train(sem_handle *h, sem_mlp *net, const double *const *b_L,
+                           int32_t n_rhs, const sem_train_opts *opts,
+                           sem_train_report *report, void *stream);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *sem_last_error(void);

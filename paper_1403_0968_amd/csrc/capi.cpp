@@ -1,5 +1,6 @@
 // C ABI of libsem.so: argument validation, error codes, handle lifetime.
 // No exception crosses this boundary.
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -96,6 +97,7 @@ sem_status sem_destroy(sem_handle *h) {
     if (!h) return;
     (void)hipDeviceSynchronize();
     destroy_ws(h);
+    learn_destroy(h);
     delete h;
   });
 }
@@ -248,6 +250,143 @@ sem_status sem_batch_pcg_solve(sem_batch *b, const sem_solve_opts *o,
                        ? "sem_batch_pcg_solve: breakdown in a solve"
                        : "sem_batch_pcg_solve: a solve did not converge";
   return result;
+}
+
+sem_status sem_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out,
+                          uint64_t seed, sem_mlp **out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    need(out != nullptr, "sem_mlp_create: null output");
+    *out = mlp_create(n_in, n_hidden, n_out, seed);
+  });
+}
+
+sem_status sem_mlp_destroy(sem_mlp *net) {
+  return guarded([&] {
+    if (!net) return;
+    (void)hipDeviceSynchronize();
+    mlp_destroy(net);
+  });
+}
+
+sem_status sem_mlp_info(const sem_mlp *net, int32_t *n_in, int32_t *n_hidden,
+                        int32_t *n_out, int32_t *n_in_padded, int64_t *n_params,
+                        int64_t *adam_steps) {
+  return guarded([&] {
+    need(net != nullptr, "sem_mlp_info: null network");
+    int a = 0, b = 0, c = 0;
+    int64_t np = 0, st = 0;
+    mlp_info(net, &a, &b, &c, &np, &st);
+    if (n_in) *n_in = a;
+    if (n_hidden) *n_hidden = b;
+    if (n_out) *n_out = c;
+    if (n_in_padded) *n_in_padded = mlp_padded_inputs(net);
+    if (n_params) *n_params = np;
+    if (adam_steps) *adam_steps = st;
+  });
+}
+
+sem_status sem_mlp_get_params(const sem_mlp *net, float *params, int64_t n) {
+  return guarded([&] {
+    need(net != nullptr && params != nullptr, "sem_mlp_get_params: null argument");
+    mlp_get_params(net, params, n);
+  });
+}
+
+sem_status sem_mlp_set_params(sem_mlp *net, const float *params, int64_t n) {
+  return guarded([&] {
+    need(net != nullptr && params != nullptr, "sem_mlp_set_params: null argument");
+    mlp_set_params(net, params, n);
+  });
+}
+
+sem_status sem_mlp_forward(sem_mlp *net, const uint16_t *X, int32_t ldx,
+                           int32_t B, float *Y, void *stream) {
+  return guarded([&] {
+    need(net != nullptr && X != nullptr && Y != nullptr && B >= 0,
+         "sem_mlp_forward: null argument or negative batch");
+    int n_out = 0;
+    mlp_info(net, nullptr, nullptr, &n_out, nullptr, nullptr);
+    mlp_forward(net, X, ldx, B, Y, n_out, false, strm(stream));
+  });
+}
+
+sem_status sem_mlp_loss_grad(sem_mlp *net, const uint16_t *X, int32_t ldx,
+                             const float *T, int32_t B, int32_t N, float *grad,
+                             double *loss, void *stream) {
+  return guarded([&] {
+    need(net != nullptr && X != nullptr && T != nullptr && B >= 1,
+         "sem_mlp_loss_grad: null argument or empty batch");
+    const double l = mlp_loss_grad(net, X, ldx, T, B, N, true, strm(stream));
+    if (loss) *loss = l;
+    if (grad) {
+      int64_t np = 0;
+      mlp_info(net, nullptr, nullptr, nullptr, &np, nullptr);
+      SEM_HIP(hipMemcpyAsync(grad, mlp_grad_ptr(net), np * 4,
+                             hipMemcpyDeviceToDevice, strm(stream)));
+    }
+  });
+}
+
+sem_status sem_mlp_adam(sem_mlp *net, const float *grad, double lr,
+                        double beta1, double beta2, double eps, void *stream) {
+  return guarded([&] {
+    need(net != nullptr, "sem_mlp_adam: null network");
+    need(lr > 0 && beta1 >= 0 && beta1 < 1 && beta2 >= 0 && beta2 < 1 && eps > 0,
+         "sem_mlp_adam: invalid hyper-parameters");
+    mlp_adam(net, grad, lr, beta1, beta2, eps, strm(stream));
+  });
+}
+
+sem_status sem_mlp_set_damping(sem_mlp *net, double damping, double jacobi_rate) {
+  return guarded([&] {
+    need(net != nullptr, "sem_mlp_set_damping: null network");
+    need(std::isfinite(damping) && damping >= 0 && std::isfinite(jacobi_rate) &&
+             jacobi_rate <= 0,
+         "sem_mlp_set_damping: damping >= 0 and jacobi_rate <= 0 required");
+    mlp_set_damping(net, damping, jacobi_rate);
+  });
+}
+
+sem_status sem_mlp_get_damping(const sem_mlp *net, double *damping,
+                               double *jacobi_rate) {
+  return guarded([&] {
+    need(net != nullptr, "sem_mlp_get_damping: null network");
+    if (damping) *damping = mlp_damping(net);
+    if (jacobi_rate) *jacobi_rate = mlp_ref_rate(net);
+  });
+}
+
+sem_status sem_mlp_save(const sem_mlp *net, const char *path) {
+  return guarded([&] {
+    need(net != nullptr && path != nullptr, "sem_mlp_save: null argument");
+    mlp_save(net, path);
+  });
+}
+
+sem_status sem_mlp_load(const char *path, sem_mlp **out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    need(path != nullptr && out != nullptr, "sem_mlp_load: null argument");
+    *out = mlp_load(path);
+  });
+}
+
+sem_status sem_learn_attach(sem_handle *h, sem_mlp *net) {
+  return guarded([&] {
+    need(h != nullptr, "sem_learn_attach: null handle");
+    learn_attach(h, net);
+  });
+}
+
+sem_status sem_learn_train(sem_handle *h, sem_mlp *net, const double *const *b_L,
+                           int32_t n_rhs, const sem_train_opts *opts,
+                           sem_train_report *report, void *stream) {
+  return guarded([&] {
+    need(h != nullptr && net != nullptr && b_L != nullptr && opts != nullptr,
+         "sem_learn_train: null argument");
+    learn_train(h, net, b_L, n_rhs, opts, report, strm(stream));
+  });
 }
 
 const char *sem_last_error(void) { return g_last_error.c_str(); }

@@ -77,9 +77,17 @@ __global__ void k_precond_local(int64_t nL, const int32_t *__restrict__ l2g,
     z[l] = bmask[l] ? T(0) : r[l];
 }
 
+void learn_precond_local(sem_handle *h, const double *r, double *z, hipStream_t s);
+
 void launch_precond(sem_handle *h, int pc, int prec, const void *r, void *z,
                     hipStream_t s) {
   const int T = 256;
+  if (pc == SEM_PC_LEARNED) {
+    if (prec != SEM_FP64)
+      fail(SEM_ERR_ARG, "sem_precond_apply: the learned preconditioner takes FP64");
+    learn_precond_local(h, (const double *)r, (double *)z, s);
+    return;
+  }
   if (pc != SEM_PC_NONE && pc != SEM_PC_JACOBI)
     fail(SEM_ERR_ARG, "sem_precond_apply: unknown preconditioner");
   const int jac = pc == SEM_PC_JACOBI;

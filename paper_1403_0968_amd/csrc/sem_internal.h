@@ -106,6 +106,7 @@ constexpr int AX_SET_468 = 100;  // batched operator compiled for n1 in {4,6,8}
 
 namespace sem {
 struct Workspace;  // solver buffers, graphs and streams (solver.hip)
+struct Learn;      // learned-correction buffers (learn.hip)
 }
 
 struct sem_handle {
@@ -120,8 +121,12 @@ struct sem_handle {
   sem::DevBuf D64, D32;
   // geometry and preconditioner
   sem::DevBuf coords, G64, G32, G16, mass, diag_L, dinv_G, dinv_G32;
+  sem::DevBuf kvert;            // kappa at the 8 vertices of each element
   // created on the first solve
   sem::Workspace *ws = nullptr;
+  // learned correction (attached network, element features and scratch)
+  sem_mlp *net = nullptr;
+  sem::Learn *learn = nullptr;
 };
 
 namespace sem {
@@ -149,6 +154,40 @@ void batch_tune(sem_batch *b, int prec, int *best_bs, int *best_gm,
 sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
                        const double *const *bL, double *const *xL,
                        sem_solve_stats *stats, hipStream_t caller);
+// network (mlp.hip)
+sem_mlp *mlp_create(int n_in, int H, int n_out, uint64_t seed);
+void mlp_destroy(sem_mlp *net);
+void mlp_set_params(sem_mlp *net, const float *host, int64_t n);
+void mlp_get_params(const sem_mlp *net, float *host, int64_t n);
+void mlp_info(const sem_mlp *net, int *n_in, int *H, int *n_out, int64_t *np,
+              int64_t *step);
+int mlp_padded_inputs(const sem_mlp *net);
+void mlp_refresh(sem_mlp *net, hipStream_t s);
+void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
+                 int ldo, bool train, hipStream_t s, uint16_t *h1x = nullptr,
+                 uint16_t *h2x = nullptr);
+double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
+                     int B, int N, bool host_loss, hipStream_t s);
+void mlp_adam(sem_mlp *net, const float *grad, double lr, double b1, double b2,
+              double eps, hipStream_t s);
+void mlp_save(const sem_mlp *net, const char *path);
+sem_mlp *mlp_load(const char *path);
+const float *mlp_grad_ptr(const sem_mlp *net);
+double mlp_damping(const sem_mlp *net);
+double mlp_ref_rate(const sem_mlp *net);
+void mlp_set_damping(sem_mlp *net, double damping, double ref_rate);
+const float *mlp_damping_dev(const sem_mlp *net);
+// learned correction on a mesh (learn.hip)
+void learn_attach(sem_handle *h, sem_mlp *net);
+void learn_destroy(sem_handle *h);
+// one application c = correction(r) for the batch's single solve: features
+// of r (vector index `rv` of precision set `f32`), network, prolongation
+// into the E-vector cL
+void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
+                 hipStream_t s);
+void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
+                 const sem_train_opts *o, sem_train_report *rep,
+                 hipStream_t caller);
 sem_status pcg_solve(sem_handle *h, const sem_solve_opts *o, const double *b_L,
                      double *x_L, sem_solve_stats *st, hipStream_t s);
 

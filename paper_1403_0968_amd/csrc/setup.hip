@@ -43,6 +43,7 @@ __device__ inline void map_point(int mapping, double x, double y, double z,
 __global__ void k_geom(int64_t nL, GeomParams P, const double *__restrict__ omega,
                        const double *__restrict__ bph, double *__restrict__ X,
                        double *__restrict__ G, double *__restrict__ B,
+                       double *__restrict__ kvert,
                        double *__restrict__ minJ_blk) {
   __shared__ double smin[256];
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -98,6 +99,12 @@ __global__ void k_geom(int64_t nL, GeomParams P, const double *__restrict__ omeg
         s += cos(omega[3 * q] * px + omega[3 * q + 1] * py +
                  omega[3 * q + 2] * pz + bph[q]);
       kap = exp(P.csig * s);
+    }
+    // kappa at the element's 8 vertices, vertex v = a + 2 b + 4 c
+    if ((i == 0 || i == N1 - 1) && (j == 0 || j == N1 - 1) &&
+        (k == 0 || k == N1 - 1)) {
+      const int v = (i ? 1 : 0) + (j ? 2 : 0) + (k ? 4 : 0);
+      kvert[e * 8 + v] = kap;
     }
     const double wq = P.w[i] * P.w[j] * P.w[k];
     const double f = wq * kap / J;
@@ -242,6 +249,7 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
   const int64_t nL = h->nL, nG = h->nG, nGeo = h->E * 6 * (int64_t)N1 * N1 * N1;
   h->coords.alloc(3 * nL * sizeof(double));
   h->G64.alloc(nGeo * sizeof(double));
+  h->kvert.alloc(h->E * 8 * sizeof(double));
   h->G32.alloc(nGeo * sizeof(float));
   h->G16.alloc(nGeo * sizeof(uint16_t));
   h->mass.alloc(nL * sizeof(double));
@@ -252,7 +260,8 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
   minj.alloc(gb * sizeof(double));
   hipLaunchKernelGGL(k_geom, dim3(gb), dim3(T), 0, s, nL, P, om.as<double>(),
                      bp.as<double>(), h->coords.as<double>(), h->G64.as<double>(),
-                     h->mass.as<double>(), minj.as<double>());
+                     h->mass.as<double>(), h->kvert.as<double>(),
+                     minj.as<double>());
   SEM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_diag, dim3(gb), dim3(T), 0, s, nL, N1, h->D64.as<double>(),
                      h->G64.as<double>(), h->diag_L.as<double>());

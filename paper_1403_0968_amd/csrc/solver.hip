@@ -359,6 +359,133 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
+// ---- flexible CG with the learned correction (single solve) -------------
+// x += alpha p, r -= alpha w (z comes from the correction below)
+template <class TV>
+__global__ void __launch_bounds__(RT)
+    k_bupdate_xr_only(const BatchSolve *__restrict__ sds,
+                      const CgState *__restrict__ st,
+                      const VecItem *__restrict__ items, int nitems) {
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (st[it.solve].done != 0) continue;
+    const BatchSolve &sd = sds[it.solve];
+    TV *x = vec<TV>(sd, VX), *r = vec<TV>(sd, VR);
+    const TV *p = vec<TV>(sd, VP), *w = vec<TV>(sd, VW);
+    const TV alpha = (TV)st[it.solve].alpha;
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      x[g] = x[g] + alpha * p[g];
+      r[g] = r[g] - alpha * w[g];
+    }
+  }
+}
+
+// z = dinv r + (average over the copies of the element corrections cL);
+// partials (r, z), (z, w), (r, r).  skip_done = 0 during initialisation.
+template <class TV, class TD>
+__global__ void __launch_bounds__(RT)
+    k_bprec_learned(const BatchSolve *__restrict__ sds,
+                    const CgState *__restrict__ st,
+                    const VecItem *__restrict__ items, int nitems,
+                    const float *__restrict__ cL, double *__restrict__ part,
+                    int skip_done) {
+  __shared__ double sm[RT / 64];
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (skip_done && st[it.solve].done != 0) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const TV *r = vec<TV>(sd, VR), *w = vec<TV>(sd, VW);
+    TV *z = vec<TV>(sd, VZ);
+    const TD *dinv = dinv_of<TD>(sd, 1);
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    double rz = 0.0, zw = 0.0, rr = 0.0;
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      const int a = sd.off[g], b = sd.off[g + 1];
+      float c = 0.f;
+      for (int k = a; k < b; ++k) c += cL[sd.perm[k]];
+      const TV rv = r[g];
+      const TV zv = sd.gmask[g] ? TV(0) : (TV)(dinv[g] * rv) + (TV)(c / (float)(b - a));
+      z[g] = zv;
+      rz += (double)rv * (double)zv;
+      zw += (double)zv * (double)w[g];
+      rr += (double)rv * (double)rv;
+    }
+    const double a1 = block_sum<RT>(rz, sm);
+    const double a2 = block_sum<RT>(zw, sm);
+    const double a3 = block_sum<RT>(rr, sm);
+    if (threadIdx.x == 0) {
+      part[q] = a1;
+      part[nitems + q] = a2;
+      part[2 * nitems + q] = a3;
+    }
+  }
+}
+
+// beta = -(z, A p) / (p, A p) (Notay's flexible CG with one stored
+// direction); convergence on (r, r)
+__global__ void __launch_bounds__(RT)
+    k_bbeta_fcg(CgState *st, const double *__restrict__ part,
+                const int32_t *__restrict__ vbeg, int nitems) {
+  __shared__ double sm[RT / 64];
+  const int s = blockIdx.x;
+  if (st[s].done != 0) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
+    a += part[q];
+    b += part[nitems + q];
+    c += part[2 * nitems + q];
+  }
+  const double rz = block_sum<RT>(a, sm);
+  const double zw = block_sum<RT>(b, sm);
+  const double rr = block_sum<RT>(c, sm);
+  if (threadIdx.x == 0) {
+    CgState &cs = st[s];
+    cs.it += 1;
+    cs.rr = rr;
+    if (!isfinite(rr) || !isfinite(rz) || !isfinite(zw))
+      cs.done = 2;
+    else if (rr <= cs.tol2 * cs.bb)
+      cs.done = 1;
+    else if (cs.it >= cs.maxit)
+      cs.done = 3;
+    else {
+      cs.beta = -zw / cs.pw;
+      cs.rz = rz;
+    }
+  }
+}
+
+// start of flexible CG: rz from the partials, p = z
+__global__ void __launch_bounds__(RT)
+    k_bfcg_start(CgState *st, const double *__restrict__ part,
+                 const int32_t *__restrict__ vbeg) {
+  __shared__ double sm[RT / 64];
+  const int s = blockIdx.x;
+  double a = 0.0;
+  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) a += part[q];
+  const double rz = block_sum<RT>(a, sm);
+  if (threadIdx.x == 0) {
+    st[s].rz = rz;
+    if (st[s].done == 0 && !isfinite(rz)) st[s].done = 2;
+  }
+}
+
+template <class TV>
+__global__ void __launch_bounds__(RT)
+    k_bcopy_zp(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
+               const VecItem *__restrict__ items, int nitems) {
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (st[it.solve].done != 0) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const TV *z = vec<TV>(sd, VZ);
+    TV *p = vec<TV>(sd, VP);
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) p[g] = z[g];
+  }
+}
+
 __global__ void k_first_copy(int64_t nG, const int32_t *__restrict__ off,
                              const int32_t *__restrict__ perm,
                              const double *__restrict__ vL,
@@ -435,9 +562,12 @@ struct sem_batch {
   hipStream_t s = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, fence = nullptr;
   struct GraphEntry {
-    int prec, k, jac;
+    int prec, k, jac, mode;
     hipGraphExec_t exec;
   };
+  // snapshot recording of solve 0 (training data), FP64 unique vectors
+  double *snap_x = nullptr, *snap_r = nullptr;
+  int snap_max = 0, snap_count = 0;
   std::vector<GraphEntry> graphs;
   bool tuned = false;
   ~sem_batch() {
@@ -604,11 +734,76 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   SEM_HIP(hipGetLastError());
 }
 
-static void iteration(sem_batch *b, int prec, int jac) {
+float *learn_cl(sem_handle *h);
+
+template <class TV, class TD>
+static void iteration_fcg_t(sem_batch *b, int prec) {
+  const BatchSolve *sds = b->sds.as<BatchSolve>();
+  CgState *st = b->st.as<CgState>();
+  const VecItem *vi = b->vitems.as<VecItem>();
+  double *part = b->part.as<double>();
+  const int32_t *vbeg = b->vbeg.as<int32_t>();
+  const int g = vec_grid(b), nv = b->n_vi, n = b->n;
+  sem_handle *h = b->hs[0];
+  const bool f32 = sizeof(TV) == 4;
+  bax(b, prec, VP, VWL, 1);
+  hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds, st,
+                     vi, nv, part, 1);
+  hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
+  hipLaunchKernelGGL((k_bupdate_xr_only<TV>), dim3(g), dim3(RT), 0, b->s, sds, st,
+                     vi, nv);
+  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, learn_cl(h),
+              b->s);
+  hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
+                     st, vi, nv, learn_cl(h), part, 1);
+  hipLaunchKernelGGL(k_bbeta_fcg, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
+  hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
+                     nv);
+  SEM_HIP(hipGetLastError());
+}
+
+// mode 0: PCG with the `jac` preconditioner; mode 1: flexible CG with the
+// learned correction
+static void iteration(sem_batch *b, int prec, int jac, int mode = 0) {
+  if (mode == 1) {
+    if (prec == SEM_FP64)
+      iteration_fcg_t<double, double>(b, prec);
+    else
+      iteration_fcg_t<float, float>(b, prec);
+    return;
+  }
   if (prec == SEM_FP64)
     iteration_t<double, double>(b, prec, jac);
   else
     iteration_t<float, float>(b, prec, jac);
+}
+
+// after init(): replace z by the learned preconditioner, p = z, rz
+static void init_fcg(sem_batch *b, int prec) {
+  const BatchSolve *sds = b->sds.as<BatchSolve>();
+  CgState *st = b->st.as<CgState>();
+  const VecItem *vi = b->vitems.as<VecItem>();
+  double *part = b->part.as<double>();
+  const int g = vec_grid(b), nv = b->n_vi;
+  sem_handle *h = b->hs[0];
+  const bool f32 = prec != SEM_FP64;
+  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, learn_cl(h), b->s);
+  if (f32) {
+    hipLaunchKernelGGL((k_bprec_learned<float, float>), dim3(g), dim3(RT), 0, b->s,
+                       sds, st, vi, nv, learn_cl(h), part, 0);
+  } else {
+    hipLaunchKernelGGL((k_bprec_learned<double, double>), dim3(g), dim3(RT), 0,
+                       b->s, sds, st, vi, nv, learn_cl(h), part, 0);
+  }
+  hipLaunchKernelGGL(k_bfcg_start, dim3(b->n), dim3(RT), 0, b->s, st, part,
+                     b->vbeg.as<int32_t>());
+  if (f32)
+    hipLaunchKernelGGL((k_bcopy_zp<float>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
+                       nv);
+  else
+    hipLaunchKernelGGL((k_bcopy_zp<double>), dim3(g), dim3(RT), 0, b->s, sds, st,
+                       vi, nv);
+  SEM_HIP(hipGetLastError());
 }
 
 // initial residual and state for the active solves; the vector set of `prec`
@@ -669,13 +864,15 @@ static void upload_active(sem_batch *b, const std::vector<int> &act,
   SEM_HIP(hipStreamSynchronize(b->s));
 }
 
-static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac) {
+static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac,
+                                int mode) {
   for (auto &g : b->graphs)
-    if (g.prec == prec && g.k == K && g.jac == jac) return g.exec;
+    if (g.prec == prec && g.k == K && g.jac == jac && g.mode == mode)
+      return g.exec;
   hipGraph_t graph;
   SEM_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
   try {
-    for (int q = 0; q < K; ++q) iteration(b, prec, jac);
+    for (int q = 0; q < K; ++q) iteration(b, prec, jac, mode);
   } catch (...) {
     hipGraph_t dummy;
     (void)hipStreamEndCapture(b->s, &dummy);
@@ -685,13 +882,18 @@ static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac) {
   hipGraphExec_t exec;
   SEM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   SEM_HIP(hipGraphDestroy(graph));
-  b->graphs.push_back({prec, K, jac, exec});
+  b->graphs.push_back({prec, K, jac, mode, exec});
   return exec;
 }
 
-// run CG iterations until every solve's flag is set
-static void run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o) {
+// Run CG iterations until every solve's flag is set.  Returns true when the
+// stagnation monitor stopped solve 0 (its residual norm fell by less than 2x
+// over the last >= 200 iterations), which the learned path treats as a
+// reason to fall back to Jacobi.
+static bool run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o,
+                   int mode = 0, bool monitor = false, double ref_rate = 0.0) {
   const int K = std::max(1, o->check_every);
+  std::vector<std::pair<int, double>> hist;
   auto poll = [&]() {
     SEM_HIP(hipMemcpyAsync(b->host_st, b->st.p, b->n * sizeof(CgState),
                            hipMemcpyDeviceToHost, b->s));
@@ -701,11 +903,38 @@ static void run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o) {
     return true;
   };
   while (!poll()) {
+    if (monitor) {
+      const CgState &c = b->host_st[0];
+      // progress judge: after 100 iterations the learned solve must have
+      // reduced log10 ||r|| / ||b|| by at least half as much as Jacobi-PCG
+      // does on this operator (ref_rate, measured on the training solves)
+      if (ref_rate < 0.0 && c.it >= 100 && c.bb > 0.0 && c.rr > 0.0 &&
+          0.5 * std::log10(c.rr / c.bb) > 0.5 * ref_rate * c.it)
+        return true;
+      hist.push_back({c.it, c.rr});
+      for (auto it = hist.rbegin(); it != hist.rend(); ++it)
+        if (c.it - it->first >= 200) {
+          if (c.rr > 0.25 * it->second) return true;
+          break;
+        }
+    }
     if (o->use_graph)
-      SEM_HIP(hipGraphLaunch(get_graph(b, prec, K, jac), b->s));
+      SEM_HIP(hipGraphLaunch(get_graph(b, prec, K, jac, mode), b->s));
     else
-      for (int q = 0; q < K; ++q) iteration(b, prec, jac);
+      for (int q = 0; q < K; ++q) iteration(b, prec, jac, mode);
+    if (b->snap_x != nullptr && b->snap_count < b->snap_max) {
+      sem_handle *h = b->hs[0];
+      const size_t bytes = (size_t)h->nG * sizeof(double);
+      SEM_HIP(hipMemcpyAsync(b->snap_x + (size_t)b->snap_count * h->nG,
+                             h->ws->v64[VX].p, bytes, hipMemcpyDeviceToDevice,
+                             b->s));
+      SEM_HIP(hipMemcpyAsync(b->snap_r + (size_t)b->snap_count * h->nG,
+                             h->ws->v64[VR].p, bytes, hipMemcpyDeviceToDevice,
+                             b->s));
+      b->snap_count += 1;
+    }
   }
+  return false;
 }
 
 // --------------------------------------------------------------------------
@@ -714,7 +943,7 @@ static void run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o) {
 static void check_opts(const sem_solve_opts *o) {
   if (!(o->rtol > 0.0) || o->maxit < 0 || o->check_every < 1)
     fail(SEM_ERR_ARG, "solve: need rtol > 0, maxit >= 0, check_every >= 1");
-  if (o->pc != SEM_PC_NONE && o->pc != SEM_PC_JACOBI)
+  if (o->pc != SEM_PC_NONE && o->pc != SEM_PC_JACOBI && o->pc != SEM_PC_LEARNED)
     fail(SEM_ERR_ARG, "solve: unknown preconditioner");
   if (o->inner_prec != SEM_FP64 && o->inner_prec != SEM_FP32 &&
       o->inner_prec != SEM_BF16)
@@ -734,7 +963,9 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
   SEM_HIP(hipEventRecord(b->fence, caller));
   SEM_HIP(hipStreamWaitEvent(s, b->fence, 0));
   SEM_HIP(hipEventRecord(b->ev0, s));
-  const int jac = o->pc == SEM_PC_JACOBI;
+  // the learned preconditioner is Jacobi plus a correction, and falls back
+  // to Jacobi
+  const int jac = o->pc == SEM_PC_JACOBI || o->pc == SEM_PC_LEARNED;
   const int n = b->n;
   for (int q = 0; q < n; ++q) {
     sem_handle *h = b->hs[q];
@@ -750,19 +981,48 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
 
   std::vector<int> iters(n, 0), outer(n, 0), status(n, SEM_ERR_NOT_CONVERGED);
   std::vector<int> act(n, 1), mx(n, o->maxit);
+  bool learned = o->pc == SEM_PC_LEARNED;
+  int fell_back = 0;
+  if (learned) {
+    if (n != 1) fail(SEM_ERR_ARG, "solve: the learned preconditioner needs a single solve");
+    if (b->hs[0]->net == nullptr)
+      fail(SEM_ERR_STATE, "solve: no network attached (sem_learn_attach)");
+    if (mlp_damping(b->hs[0]->net) == 0.0) {
+      // validation found no gain over Jacobi: the correction is disabled
+      learned = false;
+      fell_back = 1;
+    }
+  }
   if (o->inner_prec == SEM_FP64) {
     upload_active(b, act, mx);
-    init(b, SEM_FP64, jac, false, o->rtol * o->rtol);
-    run_cg(b, SEM_FP64, jac, o);
+    init(b, SEM_FP64, learned ? 1 : jac, false, o->rtol * o->rtol);
+    bool stagnated = false;
+    if (learned) {
+      init_fcg(b, SEM_FP64);
+      stagnated = run_cg(b, SEM_FP64, 1, o, 1, true, mlp_ref_rate(b->hs[0]->net));
+    } else {
+      run_cg(b, SEM_FP64, jac, o);
+    }
+    for (int q = 0; q < n; ++q) iters[q] = b->host_st[q].it;
+    if (learned && (stagnated || b->host_st[0].done != 1)) {
+      // fall back: Jacobi-PCG from the current iterate (x is only updated
+      // with finite steps), remaining iteration budget
+      fell_back = 1;
+      mx[0] = std::max(0, o->maxit - iters[0]);
+      upload_active(b, act, mx);
+      init(b, SEM_FP64, 1, false, o->rtol * o->rtol);
+      run_cg(b, SEM_FP64, 1, o);
+      iters[0] += b->host_st[0].it;
+    }
     for (int q = 0; q < n; ++q) {
-      iters[q] = b->host_st[q].it;
       const int d = b->host_st[q].done;
       status[q] = d == 1 ? SEM_OK : d == 2 ? SEM_ERR_BREAKDOWN : SEM_ERR_NOT_CONVERGED;
     }
   } else {
-    // FP64 iterative refinement: r = b - A64 x; the inner PCG solves
-    // A_lo d = r / ||r|| with FP32 vectors and an FP32 or BF16-stored
-    // operator (FP64 dots and scalars); x += ||r|| d
+    // FP64 iterative refinement: r = b - A64 x; the inner solve (PCG, or
+    // flexible CG with the learned correction) solves A_lo d = r / ||r|| with
+    // FP32 vectors and an FP32 or BF16-stored operator (FP64 dots and
+    // scalars); x += ||r|| d.  The FP64 true residual judges every step.
     const int prec = o->inner_prec;
     std::vector<double> rel_prev(n, 1e300);
     std::vector<int> stall(n, 0);
@@ -782,6 +1042,20 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
         if (rel <= o->rtol) {
           status[q] = SEM_OK;
           act[q] = 0;
+          continue;
+        }
+        if (learned && rel > 0.5 * rel_prev[q]) {
+          // the learned step did not halve the true residual: undo it and
+          // continue with Jacobi
+          hipLaunchKernelGGL(k_baxpy_mixed, dim3(vec_grid(b)), dim3(RT), 0, s,
+                             b->sds.as<BatchSolve>(), b->active.as<int32_t>(),
+                             b->scale.as<double>(), b->vitems.as<VecItem>(),
+                             b->n_vi);  // (scale holds -1/||r_old||)
+          SEM_HIP(hipGetLastError());
+          learned = false;
+          fell_back = 1;
+          residual(b);
+          q -= 1;  // re-evaluate this solve with the restored iterate
           continue;
         }
         stall[q] = rel > 0.9 * rel_prev[q] ? stall[q] + 1 : 0;
@@ -805,11 +1079,30 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
                          b->active.as<int32_t>(), b->scale.as<double>(), vi,
                          b->n_vi);
       SEM_HIP(hipGetLastError());
-      init(b, prec, jac, true, o->inner_rtol * o->inner_rtol);
-      run_cg(b, prec, jac, o);
+      bool bad = false;
+      if (learned) {
+        init(b, prec, 1, true, o->inner_rtol * o->inner_rtol);
+        init_fcg(b, prec);
+        const bool stag =
+            run_cg(b, prec, 1, o, 1, true, mlp_ref_rate(b->hs[0]->net));
+        bad = stag || b->host_st[0].done == 2;
+        iters[0] += b->host_st[0].it;
+        if (bad) {
+          // breakdown, NaN or stagnation of the learned inner solve: redo
+          // this step with Jacobi
+          learned = false;
+          fell_back = 1;
+        }
+      }
+      if (!learned && (bad || o->pc != SEM_PC_LEARNED || fell_back)) {
+        init(b, prec, jac || o->pc == SEM_PC_LEARNED, true,
+             o->inner_rtol * o->inner_rtol);
+        run_cg(b, prec, jac || o->pc == SEM_PC_LEARNED, o);
+        for (int q = 0; q < n; ++q)
+          if (act[q]) iters[q] += b->host_st[q].it;
+      }
       for (int q = 0; q < n; ++q) {
         if (!act[q]) continue;
-        iters[q] += b->host_st[q].it;
         outer[q] += 1;
         if (b->host_st[q].done == 2) {
           status[q] = SEM_ERR_BREAKDOWN;
@@ -821,6 +1114,12 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
                          b->active.as<int32_t>(), b->scale.as<double>(), vi,
                          b->n_vi);
       SEM_HIP(hipGetLastError());
+      if (learned) {
+        // keep -1/||r|| so that a rejected step can be undone
+        for (int q = 0; q < n; ++q) b->host_d[q] = -b->host_d[q];
+        SEM_HIP(hipMemcpyAsync(b->scale.p, b->host_d, n * sizeof(double),
+                               hipMemcpyHostToDevice, s));
+      }
       residual(b);
     }
   }
@@ -844,7 +1143,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
       stats[q].iters = iters[q];
       stats[q].outer_iters = outer[q];
       stats[q].status = status[q];
-      stats[q].reserved = 0;
+      stats[q].fell_back = fell_back;
       stats[q].final_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
       stats[q].seconds = ms * 1e-3;
     }
@@ -866,6 +1165,60 @@ sem_status pcg_solve(sem_handle *h, const sem_solve_opts *o, const double *b_L,
   const double *bl[1] = {b_L};
   double *xl[1] = {x_L};
   return batch_solve(h->ws->single, o, bl, xl, st, caller);
+}
+
+// FP64 Jacobi-PCG from x_L with snapshots of (x_k, r_k) every `every`
+// iterations (at most max_snaps); returns the number recorded.  The
+// converged solution stays in the handle's FP64 x vector.
+int solve_with_snapshots(sem_handle *h, const double *bL, double *xL, double rtol,
+                         int every, int max_snaps, double *xs, double *rs,
+                         int *iters, hipStream_t caller) {
+  ensure_vectors(h);
+  if (h->ws->single == nullptr) {
+    sem_handle *one[1] = {h};
+    h->ws->single = batch_create(one, 1);
+  }
+  sem_batch *b = h->ws->single;
+  sem_solve_opts o{};
+  o.rtol = rtol;
+  o.maxit = 1000000;
+  o.pc = SEM_PC_JACOBI;
+  o.inner_prec = SEM_FP64;
+  o.inner_rtol = 0.1;
+  o.check_every = every;
+  o.use_graph = 1;
+  b->snap_x = xs;
+  b->snap_r = rs;
+  b->snap_max = max_snaps;
+  b->snap_count = 0;
+  const double *bl[1] = {bL};
+  double *xl[1] = {xL};
+  sem_status st;
+  sem_solve_stats ss{};
+  try {
+    st = batch_solve(b, &o, bl, xl, &ss, caller);
+  } catch (...) {
+    b->snap_x = b->snap_r = nullptr;
+    throw;
+  }
+  const int n = b->snap_count;
+  if (iters) *iters = ss.iters;
+  b->snap_x = b->snap_r = nullptr;
+  b->snap_max = b->snap_count = 0;
+  if (st != SEM_OK) fail(st, "train: the FP64 data solve did not converge");
+  return n;
+}
+
+const double *solution_vector(sem_handle *h) { return h->ws->v64[VX].as<double>(); }
+
+// captured graphs hold the buffers of the network attached when they were
+// captured: drop them whenever the attachment changes
+void drop_graphs(sem_handle *h) {
+  if (h->ws == nullptr || h->ws->single == nullptr) return;
+  sem_batch *b = h->ws->single;
+  SEM_HIP(hipStreamSynchronize(b->s));
+  for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
 }
 
 // --------------------------------------------------------------------------

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libsem.so")
 SEM_OK, SEM_ERR_ARG, SEM_ERR_HIP, SEM_ERR_OOM = 0, 1, 2, 3
 SEM_ERR_NOT_CONVERGED, SEM_ERR_BREAKDOWN, SEM_ERR_STATE = 4, 5, 6
 SEM_FP64, SEM_FP32, SEM_BF16 = 0, 1, 2
-SEM_PC_NONE, SEM_PC_JACOBI = 0, 1
+SEM_PC_NONE, SEM_PC_JACOBI, SEM_PC_LEARNED = 0, 1, 2
 SEM_MAP_AFFINE, SEM_MAP_SINE_X, SEM_MAP_SINE_CYCLIC = 0, 1, 2
 SEM_SRC_FOURIER, SEM_SRC_SINE = 0, 1
 (SEM_ARR_L2G, SEM_ARR_PERM, SEM_ARR_OFFSETS, SEM_ARR_MULT, SEM_ARR_MASK,
@@ -27,7 +27,11 @@ SEM_SRC_FOURIER, SEM_SRC_SINE = 0, 1
 EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_gs", "sem_rhs", "sem_precond_apply", "sem_pcg_solve",
             "sem_batch_create", "sem_batch_destroy", "sem_batch_tune",
-            "sem_batch_pcg_solve", "sem_last_error"]
+            "sem_batch_pcg_solve", "sem_mlp_create", "sem_mlp_destroy",
+            "sem_mlp_info", "sem_mlp_get_params", "sem_mlp_set_params",
+            "sem_mlp_forward", "sem_mlp_loss_grad", "sem_mlp_adam",
+            "sem_mlp_set_damping", "sem_mlp_get_damping", "sem_mlp_save", "sem_mlp_load", "sem_learn_attach",
+            "sem_learn_train", "sem_last_error"]
 
 
 class sem_mesh_desc(C.Structure):
@@ -52,9 +56,27 @@ class sem_solve_opts(C.Structure):
                 ("check_every", C.c_int32), ("use_graph", C.c_int32)]
 
 
+class sem_train_opts(C.Structure):
+    _fields_ = [("n_pairs", C.c_int32), ("snapshot_every", C.c_int32),
+                ("max_snapshots", C.c_int32), ("epochs", C.c_int32),
+                ("batch", C.c_int32), ("reserved", C.c_int32),
+                ("lr", C.c_double), ("solve_rtol", C.c_double),
+                ("seed", C.c_uint64)]
+
+
+class sem_train_report(C.Structure):
+    _fields_ = [("pairs", C.c_int32), ("epochs", C.c_int32),
+                ("snapshots", C.c_int32), ("reserved", C.c_int32),
+                ("first_loss", C.c_double), ("last_loss", C.c_double),
+                ("data_seconds", C.c_double), ("train_seconds", C.c_double),
+                ("validate_seconds", C.c_double), ("damping", C.c_double),
+                ("jacobi_rate", C.c_double), ("val_iters_jacobi", C.c_int32),
+                ("val_iters_learned", C.c_int32), ("val_iters", C.c_int32 * 4)]
+
+
 class sem_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32),
-                ("status", C.c_int32), ("reserved", C.c_int32),
+                ("status", C.c_int32), ("fell_back", C.c_int32),
                 ("final_rel_res", C.c_double), ("seconds", C.c_double)]
 
 
@@ -93,6 +115,27 @@ def lib():
     L.sem_batch_pcg_solve.argtypes = [vp, C.POINTER(sem_solve_opts),
                                       C.POINTER(vp), C.POINTER(vp),
                                       C.POINTER(sem_solve_stats), vp]
+    L.sem_mlp_create.argtypes = [i32, i32, i32, C.c_uint64, C.POINTER(vp)]
+    L.sem_mlp_destroy.argtypes = [vp]
+    L.sem_mlp_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32),
+                               C.POINTER(i32), C.POINTER(i32), C.POINTER(i64),
+                               C.POINTER(i64)]
+    L.sem_mlp_get_params.argtypes = [vp, vp, i64]
+    L.sem_mlp_set_params.argtypes = [vp, vp, i64]
+    L.sem_mlp_forward.argtypes = [vp, vp, i32, i32, vp, vp]
+    L.sem_mlp_loss_grad.argtypes = [vp, vp, i32, vp, i32, i32, vp,
+                                    C.POINTER(C.c_double), vp]
+    L.sem_mlp_adam.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double,
+                               C.c_double, vp]
+    L.sem_mlp_set_damping.argtypes = [vp, C.c_double, C.c_double]
+    L.sem_mlp_get_damping.argtypes = [vp, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]
+    L.sem_mlp_save.argtypes = [vp, C.c_char_p]
+    L.sem_mlp_load.argtypes = [C.c_char_p, C.POINTER(vp)]
+    L.sem_learn_attach.argtypes = [vp, vp]
+    L.sem_learn_train.argtypes = [vp, vp, C.POINTER(vp), i32,
+                                  C.POINTER(sem_train_opts),
+                                  C.POINTER(sem_train_report), vp]
     L.sem_last_error.argtypes = []
     L.sem_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -211,6 +254,7 @@ def sem_pcg_solve(h, b, x, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
     if raise_on_fail and code != SEM_OK:
         _check(code)
     return {"status": code, "iters": st.iters, "outer_iters": st.outer_iters,
+            "fell_back": st.fell_back,
             "final_rel_res": st.final_rel_res, "seconds": st.seconds}
 
 
@@ -254,9 +298,109 @@ def sem_batch_pcg_solve(b, bs, xs, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
     if raise_on_fail and code != SEM_OK:
         _check(code)
     return code, [{"status": st[q].status, "iters": st[q].iters,
+                   "fell_back": st[q].fell_back,
                    "outer_iters": st[q].outer_iters,
                    "final_rel_res": st[q].final_rel_res,
                    "seconds": st[q].seconds} for q in range(n)]
+
+
+# ----------------------------------------------------------------------------
+# learned correction
+# ----------------------------------------------------------------------------
+
+def sem_mlp_create(n_in, n_hidden=128, n_out=8, seed=0):
+    """n_out: 8 (trilinear vertex values) or (N+1)^3 (nodal values)."""
+    net = C.c_void_p()
+    _check(lib().sem_mlp_create(int(n_in), int(n_hidden), int(n_out),
+                                int(seed), C.byref(net)))
+    return net
+
+
+def sem_mlp_destroy(net):
+    _check(lib().sem_mlp_destroy(net))
+
+
+def sem_mlp_info(net):
+    a, b, c, d = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    e, f = C.c_int64(), C.c_int64()
+    _check(lib().sem_mlp_info(net, C.byref(a), C.byref(b), C.byref(c),
+                              C.byref(d), C.byref(e), C.byref(f)))
+    return {"n_in": a.value, "n_hidden": b.value, "n_out": c.value,
+            "n_in_padded": d.value, "n_params": e.value, "adam_steps": f.value}
+
+
+def sem_mlp_get_params(net):
+    import numpy as np
+    n = sem_mlp_info(net)["n_params"]
+    out = np.zeros(n, dtype=np.float32)
+    _check(lib().sem_mlp_get_params(net, out.ctypes.data_as(C.c_void_p), n))
+    return out
+
+
+def sem_mlp_set_params(net, params):
+    import numpy as np
+    arr = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().sem_mlp_set_params(net, arr.ctypes.data_as(C.c_void_p),
+                                    arr.shape[0]))
+
+
+def sem_mlp_forward(net, X, ldx, B, Y, stream=None):
+    _check(lib().sem_mlp_forward(net, _ptr(X), int(ldx), int(B), _ptr(Y),
+                                 _stream(stream)))
+
+
+def sem_mlp_loss_grad(net, X, ldx, T, B, N, grad=None, stream=None):
+    loss = C.c_double()
+    _check(lib().sem_mlp_loss_grad(net, _ptr(X), int(ldx), _ptr(T), int(B),
+                                   int(N), _ptr(grad), C.byref(loss),
+                                   _stream(stream)))
+    return loss.value
+
+
+def sem_mlp_adam(net, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+                 stream=None):
+    _check(lib().sem_mlp_adam(net, _ptr(grad), float(lr), float(beta1),
+                              float(beta2), float(eps), _stream(stream)))
+
+
+def sem_mlp_set_damping(net, damping, jacobi_rate=0.0):
+    _check(lib().sem_mlp_set_damping(net, float(damping), float(jacobi_rate)))
+
+
+def sem_mlp_get_damping(net):
+    d, r = C.c_double(), C.c_double()
+    _check(lib().sem_mlp_get_damping(net, C.byref(d), C.byref(r)))
+    return d.value, r.value
+
+
+def sem_mlp_save(net, path):
+    _check(lib().sem_mlp_save(net, str(path).encode()))
+
+
+def sem_mlp_load(path):
+    net = C.c_void_p()
+    _check(lib().sem_mlp_load(str(path).encode(), C.byref(net)))
+    return net
+
+
+def sem_learn_attach(h, net):
+    _check(lib().sem_learn_attach(h, net))
+
+
+def sem_learn_train(h, net, bs, n_pairs=20000, snapshot_every=16,
+                    max_snapshots=64, epochs=20, batch=512, lr=1e-3,
+                    solve_rtol=1e-12, seed=0, stream=None):
+    o = sem_train_opts()
+    o.n_pairs, o.snapshot_every, o.max_snapshots = n_pairs, snapshot_every, max_snapshots
+    o.epochs, o.batch, o.lr, o.solve_rtol, o.seed = epochs, batch, lr, solve_rtol, seed
+    rep = sem_train_report()
+    arr = (C.c_void_p * len(bs))(*[t.data_ptr() for t in bs])
+    _check(lib().sem_learn_train(h, net, arr, len(bs), C.byref(o), C.byref(rep),
+                                 _stream(stream)))
+    out = {k: getattr(rep, k) for k, _ in sem_train_report._fields_
+           if k not in ("reserved", "val_iters")}
+    out["val_iters"] = list(rep.val_iters)
+    return out
 
 
 def sem_last_error():
