@@ -13,6 +13,19 @@ mapped by x + 0.05 (sin 2 pi y sin 2 pi z, and cyclic).
 * pcg: wall time to relative residual 1e-8 of plain FP64 Jacobi-PCG and of
   FP64 refinement around FP32 / BF16-operator inner PCG, same mesh, RHS from
   8 random Fourier modes (seed 0).
+* learned: variable-coefficient problem -div(kappa grad u) = f, kappa =
+  exp(Gaussian random field, correlation length 0.1, sigma 1, 4096 random
+  Fourier features, seed 7), 24^3 elements, N = 7, affine unit cube.  The
+  per-element correction network (hidden 128, BF16 weights) is trained on
+  the GPU on 20k residual/error pairs from FP64 Jacobi-PCG solves of 8
+  training right-hand sides (seeds 100..107); time to 1e-8 on held-out
+  right-hand sides (seeds 900..902) of plain FP64 Jacobi-PCG, FP64
+  refinement around FP32 Jacobi-PCG, and FP64 refinement around FP32
+  flexible CG with the learned correction.
+* batch: 256 independent solves, cubic grids n^3 with n ~ U{6..24}, orders
+  N ~ U{3, 5, 7}, sine-cyclic mapping, right-hand sides seeded 1000 + s,
+  FP32 operator inside FP64 refinement to 1e-10: one batched solve against a
+  loop of 256 individual solves.
 * cpu_baseline: the FP64 CPU oracle's operator on a bounded sample of the
   same mesh (test infrastructure, timed here only as a reported baseline).
 
@@ -101,7 +114,7 @@ def bench_pcg(sem, torch, h, nL, rtol=1e-8):
         for rep in range(2):  # first solve also instantiates graphs
             x = torch.zeros_like(b)
             st = sem.sem_pcg_solve(h, b, x, rtol=rtol, maxit=20000,
-                                   inner_prec=prec, inner_rtol=5e-2,
+                                   inner_prec=prec, inner_rtol=1e-3,
                                    check_every=32, use_graph=1,
                                    raise_on_fail=False)
             torch.cuda.synchronize()
@@ -113,6 +126,120 @@ def bench_pcg(sem, torch, h, nL, rtol=1e-8):
                      "status": best["status"]}
         log(f"[pcg] {name}: {out[name]}")
     out["rtol"] = rtol
+    return out
+
+
+def bench_learned(sem, torch):
+    from seminputs import fourier_modes, grf_features
+    n, N = 24, 7
+    t0 = time.perf_counter()
+    h = sem.sem_setup(N, n, n, n, mapping=sem.SEM_MAP_AFFINE,
+                      kappa=grf_features(seed=7, M=4096, ell=0.1, sigma=1.0))
+    E, nL, nG = sem.sem_query(h)
+    setup_s = time.perf_counter() - t0
+
+    def rhs(seed):
+        b = torch.empty(nL, dtype=torch.float64, device="cuda")
+        sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, fourier_modes(seed=seed))
+        return b
+
+    train = [rhs(100 + q) for q in range(8)]
+    net = sem.sem_mlp_create((N + 1) ** 3 + 8, 128, (N + 1) ** 3, seed=11)
+    rep = sem.sem_learn_train(h, net, train, n_pairs=20000, snapshot_every=16,
+                              max_snapshots=64, epochs=30, batch=256, lr=1e-3,
+                              solve_rtol=1e-11, seed=1)
+    log(f"[learned] trained: {rep}")
+    del train
+    sem.sem_learn_attach(h, net)
+    cases = [("fp64_jacobi_pcg", sem.SEM_PC_JACOBI, sem.SEM_FP64),
+             ("fp32_ir_jacobi", sem.SEM_PC_JACOBI, sem.SEM_FP32),
+             ("fp32_ir_learned", sem.SEM_PC_LEARNED, sem.SEM_FP32)]
+    out = {name: {"time_s": [], "iters": [], "fell_back": [], "final_rel_res": []}
+           for name, _, _ in cases}
+    for seed in (900, 901, 902):
+        b = rhs(seed)
+        for name, pc, prec in cases:
+            for rep_i in range(2):  # the first solve captures graphs
+                x = torch.zeros_like(b)
+                st = sem.sem_pcg_solve(h, b, x, rtol=1e-8, maxit=50000, pc=pc,
+                                       inner_prec=prec, inner_rtol=1e-3,
+                                       check_every=32, raise_on_fail=False)
+                torch.cuda.synchronize()
+            o = out[name]
+            o["time_s"].append(st["seconds"])
+            o["iters"].append(st["iters"])
+            o["fell_back"].append(st["fell_back"])
+            o["final_rel_res"].append(st["final_rel_res"])
+            log(f"[learned] rhs {seed} {name}: {st}")
+    for name in out:
+        ts = sorted(out[name]["time_s"])
+        out[name]["median_time_s"] = ts[len(ts) // 2]
+    out["speedup_learned_mixed_vs_fp64"] = (
+        out["fp64_jacobi_pcg"]["median_time_s"] /
+        out["fp32_ir_learned"]["median_time_s"])
+    out["train"] = rep
+    out["workload"] = ("24^3 elements, N=7, kappa=exp(GRF l=0.1 sigma=1), "
+                       f"{nL} local / {nG} unique nodes")
+    out["setup_s"] = setup_s
+    sem.sem_learn_attach(h, None)
+    sem.sem_mlp_destroy(net)
+    sem.sem_destroy(h)
+    return out
+
+
+def bench_batch(sem, torch, count=256):
+    from seminputs import batch_configs, fourier_modes
+    cfg = batch_configs(256, seed=0)[:count]
+    t0 = time.perf_counter()
+    hs, bs, n_loc = [], [], 0
+    for q, (n, N) in enumerate(cfg):
+        h = sem.sem_setup(N, n, n, n, mapping=sem.SEM_MAP_SINE_CYCLIC)
+        _, nL, _ = sem.sem_query(h)
+        n_loc += nL
+        b = torch.empty(nL, dtype=torch.float64, device="cuda")
+        sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, fourier_modes(seed=1000 + q))
+        hs.append(h)
+        bs.append(b)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    bt = sem.sem_batch_create(hs)
+    tune = sem.sem_batch_tune(bt, sem.SEM_FP32)
+    kw = dict(rtol=1e-10, maxit=50000, inner_prec=sem.SEM_FP32, inner_rtol=1e-3,
+              check_every=32)
+    best = None
+    for _ in range(2):
+        xs = [torch.zeros_like(b) for b in bs]
+        code, st = sem.sem_batch_pcg_solve(bt, bs, xs, raise_on_fail=False, **kw)
+        torch.cuda.synchronize()
+        if best is None or st[0]["seconds"] < best[1][0]["seconds"]:
+            best = (code, st)
+    code, st = best
+    batch_s = st[0]["seconds"]
+    loop_s = 0.0
+    loop_iters = []
+    for h, b in zip(hs, bs):
+        x = torch.zeros_like(b)
+        s1 = sem.sem_pcg_solve(h, b, x, raise_on_fail=False, **kw)
+        loop_s += s1["seconds"]
+        loop_iters.append(s1["iters"])
+    torch.cuda.synchronize()
+    same = all(a["iters"] == b for a, b in zip(st, loop_iters))
+    nG_it = 0
+    for h, s1 in zip(hs, st):
+        nG_it += sem.sem_query(h)[2] * s1["iters"]
+    sem.sem_batch_destroy(bt)
+    for h in hs:
+        sem.sem_destroy(h)
+    out = {"solves": count, "local_nodes": n_loc, "status": code,
+           "batch_time_s": batch_s, "loop_time_s": loop_s,
+           "speedup_vs_loop": loop_s / batch_s,
+           "aggregate_gdofs": nG_it / batch_s / 1e9,
+           "max_final_rel_res": max(s1["final_rel_res"] for s1 in st),
+           "iters_equal_to_individual_solves": same,
+           "autotune_fp32": {"block": tune[0], "grid_mult": tune[1],
+                             "operator_us": tune[2]},
+           "setup_s": setup_s}
+    log(f"[batch] {out}")
     return out
 
 
@@ -152,6 +279,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--ax-only", action="store_true",
                     help="only the FP64 operator launches (for counter runs)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -213,6 +342,8 @@ def main():
 
     pcg = None if args.no_pcg else bench_pcg(sem, torch, h, nL)
     sem.sem_destroy(h)
+    learned = None if args.no_learned else bench_learned(sem, torch)
+    batch = None if args.no_batch else bench_batch(sem, torch)
     cpu = None if args.no_cpu else cpu_baseline()
     if cpu:
         log(f"[bench] cpu baseline {cpu}")
@@ -239,6 +370,8 @@ def main():
         "cpu_baseline": cpu,
         "sem_ax_low_precision": extra,
         "pcg": pcg,
+        "learned": learned,
+        "batch": batch,
         "setup_s": setup_s,
     }
     print(json.dumps(rec), flush=True)
