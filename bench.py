@@ -48,7 +48,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"f64": 64, "f32": 32, "bf16": 18}
 NE, ORDER = 32, 7
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ax_fp64_32x32x32_N7_traffic.txt")
-AX_SRC = os.path.join(ROOT, "paper_1403_0968_amd", "csrc", "ax.hip")
+AX_SRC = [os.path.join(ROOT, "paper_1403_0968_amd", "csrc", f)
+          for f in ("ax.hip", "ax_tile.h")]
 
 
 def log(msg):
@@ -56,8 +57,12 @@ def log(msg):
 
 
 def ax_source_hash():
-    with open(AX_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the operator's sources (kernel file and element routine)."""
+    h = hashlib.sha256()
+    for p in AX_SRC:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(n_local):

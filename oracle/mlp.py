@@ -23,6 +23,16 @@ x = [r_e / s_e, log kappa at the 8 element vertices minus their mean, 0 pad];
 the correction is c_e = s_e / (kappa_mean_e h_e) * P o, summed over the
 copies of each node and divided by its multiplicity.
 
+Interior layout (the element-interior solve as target): the network sees
+only the residual at the element-interior nodes (1 <= i, j, k <= N-1),
+x = [r_I / s, log kappa vertex deviations], s = ||r_I||_2, and predicts the
+(N-1)^3 values t = (d - dinv_I r_I) kappa_mean h / s, where d solves
+A_II d = r_I with A_II the element stiffness restricted to its interior
+nodes (zero values on the element's faces) and dinv the assembled Jacobi
+inverse.  The preconditioner z = dinv r + c then reproduces the
+element-interior block solve where the network is exact.  Interior nodes
+belong to one element only, so no averaging is involved.
+
 Parity status: forward/backward pinned by central finite differences and by
 the linear-network closed form; Adam pinned by its first-step closed form;
 prolongation pinned by exact reproduction of trilinear functions.  Trained
@@ -145,3 +155,64 @@ def element_features(r_global, l2g, n1, e, kappa_vertices, n_in):
     lk = np.log(np.asarray(kappa_vertices, dtype=np.float64))
     x[n3:n3 + 8] = lk - lk.mean()
     return x, s
+
+
+def interior_nodes(N):
+    """Local indices i + n1 j + n1^2 k of the element-interior nodes
+    1 <= i, j, k <= N-1 in lexicographic order (i fastest)."""
+    n1, m = N + 1, N - 1
+    q = np.arange(max(m, 0) ** 3)
+    if m <= 0:
+        return q
+    i = q % m + 1
+    j = (q // m) % m + 1
+    k = q // (m * m) + 1
+    return i + n1 * (j + n1 * k)
+
+
+def interior_features(r_e, kappa_vertices, N, n_in=None):
+    """Features of the interior layout from the element's n1^3 nodal
+    residual values r_e: x = [r_I / s, log kappa vertex deviations], s."""
+    I = interior_nodes(N)
+    ni = I.shape[0]
+    r_I = np.asarray(r_e, dtype=np.float64)[I]
+    s = float(np.linalg.norm(r_I))
+    x = np.zeros(ni + 8 if n_in is None else n_in)
+    if s > 0:
+        x[:ni] = r_I / s
+    lk = np.log(np.asarray(kappa_vertices, dtype=np.float64))
+    x[ni:ni + 8] = lk - lk.mean()
+    return x, s
+
+
+def interior_solve(A_e, r_e, N):
+    """d = A_II^{-1} r_I: the element stiffness A_e (n1^3 x n1^3) restricted
+    to the interior nodes, solved densely."""
+    I = interior_nodes(N)
+    A_II = np.asarray(A_e, dtype=np.float64)[np.ix_(I, I)]
+    return np.linalg.solve(A_II, np.asarray(r_e, dtype=np.float64)[I])
+
+
+def interior_target(A_e, r_e, dinv_e, kappa_vertices, h, N):
+    """Target of the interior layout: (d - dinv_I r_I) kappa_mean h / s with
+    d = interior_solve(A_e, r_e, N); dinv_e holds the assembled Jacobi
+    inverse at the element's n1^3 nodes."""
+    I = interior_nodes(N)
+    r_I = np.asarray(r_e, dtype=np.float64)[I]
+    s = float(np.linalg.norm(r_I))
+    if s == 0:
+        return np.zeros(I.shape[0])
+    d = interior_solve(A_e, r_e, N)
+    kbar = float(np.mean(np.asarray(kappa_vertices, dtype=np.float64)))
+    return (d - np.asarray(dinv_e, dtype=np.float64)[I] * r_I) * kbar * h / s
+
+
+def interior_correction(o, s, kappa_vertices, h, N, damping=1.0):
+    """Correction on the element's n1^3 nodes from the network output o
+    ((N-1)^3 values): damping s / (kappa_mean h) o on the interior nodes,
+    zero on the faces."""
+    n1 = N + 1
+    c = np.zeros(n1 ** 3)
+    kbar = float(np.mean(np.asarray(kappa_vertices, dtype=np.float64)))
+    c[interior_nodes(N)] = damping * s / (kbar * h) * np.asarray(o, dtype=np.float64)
+    return c

@@ -1,0 +1,179 @@
+// Element routine of the local stiffness action w = D^T G D u (paper
+// section 4.2.1), shared by the operator kernels and the element-local
+// solves of the learned correction.
+//
+// One thread per (i,j) column of an element holds the n1 values along k in
+// registers (the t-direction contractions never leave registers); the r- and
+// s-direction contractions read the current k-slice from LDS (row pitch
+// n1+1, so the 8 distinct rows a wave reads at once sit in different banks).
+// All loads of an element (its u column and the 6 n1 geometric factors of
+// the column) are issued before any arithmetic.  Storage/compute types:
+// FP64 (double everywhere), FP32, and BF16 (u and G bfloat16, D, arithmetic
+// and w FP32; at n1 = 8 the BF16 factors are stored column-contiguous
+// [E][6][n1^2][n1] and the BF16 input is read in 16-byte rows and
+// redistributed through LDS).  GATHER = true reads u from a unique-node
+// vector through the closed-form box numbering.
+#pragma once
+
+#include "common.h"
+#include "sem_internal.h"
+
+namespace sem {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T> __device__ inline T ld_stream(const T *p) {
+  return __builtin_nontemporal_load(p);
+}
+
+template <int N1> constexpr int lds_words(int epb) {
+  return 3 * epb * N1 * N1 * (N1 + 1);
+}
+
+// Apply the operator to elements e0 .. e0 + EPB - 1 (those < E) with the
+// threads t = 0 .. of one workgroup; threads t >= EPB n1^2 only join the
+// barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC.
+template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
+          bool NTW>
+__device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
+                                        const TC *__restrict__ D,
+                                        const TG *__restrict__ G,
+                                        const TU *__restrict__ u,
+                                        TW *__restrict__ w,
+                                        const Box *__restrict__ box,
+                                        TC *__restrict__ smem) {
+  constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = N1 + 1;
+  constexpr int SL = N1 * N1 * PAD;  // one element's slice stack
+  const int el = t / NP;
+  const bool lane_ok = el < EPB;
+  const int elc = lane_ok ? el : 0;
+  const int c = t - el * NP;
+  const int i = c % N1, j = c / N1;
+  const int64_t e = e0 + el;
+  const bool act = lane_ok && e < E;
+  const int64_t base = e * N3 + c;
+  TC *s_u = smem + (0 * EPB + elc) * SL;
+  TC *s_r = smem + (1 * EPB + elc) * SL;
+  TC *s_s = smem + (2 * EPB + elc) * SL;
+#define AX_IDX(k, jj, ii) (((k) * N1 + (jj)) * PAD + (ii))
+
+  constexpr bool VEC16 = sizeof(TG) == 2 && N1 == 8;  // BF16 column layout
+  constexpr bool VECU = sizeof(TU) == 2 && N1 == 8 && !GATHER;
+  TU ucol[N1];
+  u32x4 urow = {0u, 0u, 0u, 0u};
+  if constexpr (VECU) {
+    // lane c reads the 16-byte row (k, j) = (c / 8, c % 8) of the element
+    if (act) urow = *reinterpret_cast<const u32x4 *>(u + e * N3 + 8 * c);
+  } else if constexpr (GATHER) {
+    int64_t gb = 0, gk = 0;
+    if (act) {
+      gb = box_origin(*box, (uint32_t)e) + i + (int64_t)box->Gx * j;
+      gk = box->Gxy;
+    }
+#pragma unroll
+    for (int k = 0; k < N1; ++k) ucol[k] = act ? u[gb + k * gk] : TU(0);
+  } else {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) ucol[k] = act ? u[base + k * NP] : TU(0);
+  }
+  TG g[6][N1];
+  if constexpr (VEC16) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (act)
+        v = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4 *>(G + e * 6 * N3 + q * N3 + 8 * c));
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        g[q][2 * h] = (TG)(wv[h] & 0xffffu);
+        g[q][2 * h + 1] = (TG)(wv[h] >> 16);
+      }
+    }
+  } else {
+    const TG *Ge = G + e * 6 * N3 + c;
+#pragma unroll
+    for (int k = 0; k < N1; ++k)
+#pragma unroll
+      for (int q = 0; q < 6; ++q)
+        g[q][k] = act ? ld_stream(Ge + q * N3 + k * NP) : TG(0);
+  }
+
+  TC uc[N1];
+  if constexpr (VECU) {
+    const uint32_t wv[4] = {urow.x, urow.y, urow.z, urow.w};
+    if (lane_ok) {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        s_u[AX_IDX(c / 8, c % 8, 2 * h)] = Cvt<TU, TC>::ld((TU)(wv[h] & 0xffffu));
+        s_u[AX_IDX(c / 8, c % 8, 2 * h + 1)] = Cvt<TU, TC>::ld((TU)(wv[h] >> 16));
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < N1; ++k) uc[k] = s_u[AX_IDX(k, j, i)];
+  } else {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      uc[k] = Cvt<TU, TC>::ld(ucol[k]);
+      if (lane_ok) s_u[AX_IDX(k, j, i)] = uc[k];
+    }
+  }
+  TC Di[N1], Dj[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    Di[m] = D[i * N1 + m];
+    Dj[m] = D[j * N1 + m];
+  }
+  __syncthreads();
+
+  // gradient (r, s from LDS; t from registers) and fluxes, slice by slice
+  TC wt[N1];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    TC ur = TC(0), us = TC(0), ut = TC(0);
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      ur += Di[m] * s_u[AX_IDX(k, j, m)];
+      us += Dj[m] * s_u[AX_IDX(k, m, i)];
+      ut += D[k * N1 + m] * uc[m];
+    }
+    const TC g0 = Cvt<TG, TC>::ld(g[0][k]), g1 = Cvt<TG, TC>::ld(g[1][k]),
+             g2 = Cvt<TG, TC>::ld(g[2][k]), g3 = Cvt<TG, TC>::ld(g[3][k]),
+             g4 = Cvt<TG, TC>::ld(g[4][k]), g5 = Cvt<TG, TC>::ld(g[5][k]);
+    if (lane_ok) {
+      s_r[AX_IDX(k, j, i)] = g0 * ur + g1 * us + g2 * ut;
+      s_s[AX_IDX(k, j, i)] = g1 * ur + g3 * us + g4 * ut;
+    }
+    wt[k] = g2 * ur + g4 * us + g5 * ut;
+  }
+  __syncthreads();
+
+  // w = D_r^T w_r + D_s^T w_s + D_t^T w_t
+  TC DTi[N1], DTj[N1];
+#pragma unroll
+  for (int m = 0; m < N1; ++m) {
+    DTi[m] = D[m * N1 + i];
+    DTj[m] = D[m * N1 + j];
+  }
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    TC acc = TC(0);
+#pragma unroll
+    for (int m = 0; m < N1; ++m) {
+      acc += DTi[m] * s_r[AX_IDX(k, j, m)];
+      acc += DTj[m] * s_s[AX_IDX(k, m, i)];
+      acc += D[m * N1 + k] * wt[m];
+    }
+    if (act) {
+      if constexpr (NTW)
+        __builtin_nontemporal_store((TW)acc, w + base + k * NP);
+      else
+        w[base + k * NP] = (TW)acc;
+    }
+  }
+#undef AX_IDX
+}
+
+}  // namespace sem

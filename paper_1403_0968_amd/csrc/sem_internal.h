@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/sem.h"
+#include "structured.h"
 
 namespace sem {
 
@@ -81,8 +82,7 @@ enum { VB = 0, VX, VR, VZ, VP, VW, VWL, NVEC };
 struct BatchSolve {
   int32_t N1, solve;
   int64_t E, nL, nG;
-  const int32_t *l2g, *off, *perm;
-  const uint8_t *gmask;
+  Box box;                        // closed-form numbering of the solve's mesh
   const void *G64, *G32, *G16, *D64, *D32;
   const double *dinv64, *one64;   // Jacobi, and 1 off the Dirichlet boundary
   const float *dinv32, *one32;

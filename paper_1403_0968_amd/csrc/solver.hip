@@ -52,8 +52,8 @@ template <class TD> __device__ inline const TD *dinv_of(const BatchSolve &s,
     return (const TD *)(jac ? s.dinv32 : s.one32);
 }
 
-// w = mask o Q^T wL (sum of copies in ascending local index); optional
-// partial (p, w) per item
+// w = mask o Q^T wL (sum of copies in ascending local index, from +0: the
+// summation order of sem_gs); optional partial (p, w) per item
 template <class TV, bool DOT>
 __global__ void __launch_bounds__(RT)
     k_bassemble(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
@@ -64,18 +64,21 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (skip_done && st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
+    const Box &bx = sd.box;
     const TV *wL = vec<TV>(sd, VWL);
     TV *wG = vec<TV>(sd, VW);
     const TV *p = vec<TV>(sd, VP);
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double acc = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      const NodeCopies nc = node_copies(bx, (uint32_t)g);
       TV s = TV(0);
-      const int a = sd.off[g], b = sd.off[g + 1];
-      for (int k = a; k < b; ++k) s = s + wL[sd.perm[k]];
-      const TV v = sd.gmask[g] ? TV(0) : s;
-      wG[g] = v;
-      if (DOT) acc += (double)p[g] * (double)v;
+      if (!nc.masked)
+        for (int a = 0; a < nc.z.cnt; ++a)
+          for (int b = 0; b < nc.y.cnt; ++b)
+            for (int c = 0; c < nc.x.cnt; ++c) s = s + wL[copy_lid(bx, nc, a, b, c)];
+      wG[g] = s;
+      if (DOT) acc += (double)p[g] * (double)s;
     }
     if (DOT) {
       const double t = block_sum<RT>(acc, sm);
@@ -401,11 +404,16 @@ __global__ void __launch_bounds__(RT)
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double rz = 0.0, zw = 0.0, rr = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
-      const int a = sd.off[g], b = sd.off[g + 1];
+      const NodeCopies nc = node_copies(sd.box, (uint32_t)g);
       float c = 0.f;
-      for (int k = a; k < b; ++k) c += cL[sd.perm[k]];
+      if (!nc.masked)
+        for (int a = 0; a < nc.z.cnt; ++a)
+          for (int b = 0; b < nc.y.cnt; ++b)
+            for (int cc = 0; cc < nc.x.cnt; ++cc)
+              c += cL[copy_lid(sd.box, nc, a, b, cc)];
+      const float mult = (float)(nc.x.cnt * nc.y.cnt * nc.z.cnt);
       const TV rv = r[g];
-      const TV zv = sd.gmask[g] ? TV(0) : (TV)(dinv[g] * rv) + (TV)(c / (float)(b - a));
+      const TV zv = nc.masked ? TV(0) : (TV)(dinv[g] * rv) + (TV)(c / mult);
       z[g] = zv;
       rz += (double)rv * (double)zv;
       zw += (double)zv * (double)w[g];
@@ -625,10 +633,7 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
       d.E = h->E;
       d.nL = h->nL;
       d.nG = h->nG;
-      d.l2g = h->l2g.as<int32_t>();
-      d.off = h->offsets.as<int32_t>();
-      d.perm = h->perm.as<int32_t>();
-      d.gmask = h->gmask.as<uint8_t>();
+      d.box = make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet);
       d.G64 = h->G64.p;
       d.G32 = h->G32.p;
       d.G16 = h->G16.p;

@@ -1,0 +1,99 @@
+"""Pins of the oracle's interior layout of the learned correction: the
+element-interior node list, the dense element-interior solve against the
+sum-factorised operator (an independent code path), the target's closed
+form on a known solution, and the reading that the exact element-interior
+block solve converges in fewer flexible-CG iterations than Jacobi."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from oracle import oracle as orc
+from seminputs import fourier_modes, grf_features, uniform
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 5, 7])
+def test_interior_nodes(N):
+    n1 = N + 1
+    I = mlp.interior_nodes(N)
+    assert I.shape[0] == max(N - 1, 0) ** 3
+    assert np.all(np.diff(I) > 0)
+    i, j, k = I % n1, (I // n1) % n1, I // (n1 * n1)
+    for c in (i, j, k):
+        assert np.all((c >= 1) & (c <= N - 1))
+    if N == 2:
+        assert list(I) == [1 + 3 * (1 + 3 * 1)]
+
+
+def _curved_mesh(N, n=2):
+    kap = grf_features(seed=3, M=256, ell=0.5, sigma=0.7)
+    return orc.mesh(N, n, n, n, orc.MAP_SINE_CYCLIC, 1, kap)
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_interior_solve_against_operator(N):
+    m = _curved_mesh(N)
+    n3 = m.n1 ** 3
+    I = mlp.interior_nodes(N)
+    for e in (0, m.E - 1):
+        A_e = orc.brute_element_matrix(N, m.xi, m.G[e])
+        r_e = uniform(n3, seed=10 + e)
+        d = mlp.interior_solve(A_e, r_e, N)
+        u = np.zeros(n3)
+        u[I] = d
+        w = orc.ax_raw(N, m.D, m.G[e:e + 1], u)
+        err = np.max(np.abs(w[I] - r_e[I])) / np.max(np.abs(r_e[I]))
+        assert err < 1e-10
+
+
+def test_interior_target_known_solution():
+    N = 5
+    m = _curved_mesh(N)
+    n3 = m.n1 ** 3
+    I = mlp.interior_nodes(N)
+    e = 3
+    A_e = orc.brute_element_matrix(N, m.xi, m.G[e])
+    v = uniform(I.shape[0], seed=4)
+    r_e = uniform(n3, seed=5)          # face values do not enter
+    r_e[I] = A_e[np.ix_(I, I)] @ v
+    dinv_e = 1.0 / np.abs(uniform(n3, seed=6) + 2.0)
+    kv = np.array([1.0, 2.0, 0.5, 1.5, 1.0, 1.0, 3.0, 0.25])
+    h = 0.5
+    s = np.linalg.norm(r_e[I])
+    t = mlp.interior_target(A_e, r_e, dinv_e, kv, h, N)
+    want = (v - dinv_e[I] * r_e[I]) * kv.mean() * h / s
+    assert np.max(np.abs(t - want)) < 1e-9 * np.max(np.abs(want))
+    # the correction undoes the scaling: dinv r + c = d on the interior
+    c = mlp.interior_correction(t, s, kv, h, N)
+    assert np.max(np.abs(dinv_e[I] * r_e[I] + c[I] - v)) < 1e-9 * np.max(np.abs(v))
+    assert np.all(c[np.setdiff1d(np.arange(n3), I)] == 0.0)
+    x, s2 = mlp.interior_features(r_e, kv, N)
+    assert s2 == s and np.allclose(x[:I.shape[0]] * s, r_e[I], rtol=0, atol=1e-14 * s)
+    assert np.allclose(x[I.shape[0]:], np.log(kv) - np.log(kv).mean())
+
+
+def test_exact_interior_block_beats_jacobi():
+    """The reading behind the interior layout: a perfect network reproduces
+    the element-interior block solve, which needs clearly fewer flexible-CG
+    iterations than Jacobi-PCG on a variable-coefficient problem."""
+    N, n = 5, 3
+    kap = grf_features(seed=7, M=512, ell=0.6, sigma=1.0)
+    m = orc.mesh(N, n, n, n, orc.MAP_AFFINE, 1, kap)
+    n3 = m.n1 ** 3
+    I = mlp.interior_nodes(N)
+    k, a, phi = fourier_modes(seed=900)
+    b = orc.to_global(m, orc.rhs_local(m, orc.src_fourier(m.X, k, a, phi)))
+    dinv = orc.jacobi_dinv_global(m)
+    AII = [np.linalg.inv(orc.brute_element_matrix(N, m.xi, m.G[e])[np.ix_(I, I)])
+           for e in range(m.E)]
+    gI = [m.l2g[e * n3 + I] for e in range(m.E)]
+
+    def block(r):
+        z = dinv * r
+        for e in range(m.E):
+            z[gI[e]] = AII[e] @ r[gI[e]]
+        return z
+
+    _, st_j, it_j, _ = orc.pcg(m, b, 1e-8, 5000)
+    _, st_b, it_b, _ = orc.fcg(m, b, block, 1e-8, 5000)
+    assert st_j == 0 and st_b == 0
+    assert it_b < 0.8 * it_j, (it_b, it_j)
