@@ -106,17 +106,20 @@ def time_ax(sem, torch, h, prec, u, w, steps, warmup):
     return e0.elapsed_time(e1) / steps  # ms per launch
 
 
-def bench_pcg(sem, torch, h, nL, rtol=1e-8):
+def bench_pcg(sem, torch, h, nL, nG, rtol=1e-8):
     from seminputs import fourier_modes
     k, a, phi = fourier_modes(seed=0)
     b = torch.empty(nL, dtype=torch.float64, device="cuda")
     sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, (k, a, phi))
     out = {}
-    for name, prec in (("fp64_jacobi_pcg", sem.SEM_FP64),
-                       ("fp32_ir_jacobi_pcg", sem.SEM_FP32),
-                       ("bf16_ir_jacobi_pcg", sem.SEM_BF16)):
+    for name, prec, reps in (("fp64_jacobi_pcg", sem.SEM_FP64, 2),
+                             ("fp32_ir_jacobi_pcg", sem.SEM_FP32, 2),
+                             ("bf16_ir_jacobi_pcg", sem.SEM_BF16, 2),
+                             ("bf16_mfma_ir_jacobi_pcg", sem.SEM_BF16_MFMA, 2),
+                             # BF16-rounded derivative matrix: expected to stall
+                             ("bf16_plain_d_ir_jacobi_pcg", sem.SEM_BF16_PLAIN_D, 1)):
         best = None
-        for rep in range(2):  # first solve also instantiates graphs
+        for rep in range(reps):  # the first solve also instantiates graphs
             x = torch.zeros_like(b)
             st = sem.sem_pcg_solve(h, b, x, rtol=rtol, maxit=20000,
                                    inner_prec=prec, inner_rtol=1e-3,
@@ -127,8 +130,10 @@ def bench_pcg(sem, torch, h, nL, rtol=1e-8):
                 best = st
         out[name] = {"time_to_rtol_s": best["seconds"], "iters": best["iters"],
                      "outer": best["outer_iters"],
+                     "outer_contraction": best["outer_contraction"],
                      "final_rel_res_fp64": best["final_rel_res"],
-                     "status": best["status"]}
+                     "status": best["status"],
+                     "gdofs": nG * best["iters"] / best["seconds"] / 1e9}
         log(f"[pcg] {name}: {out[name]}")
     out["rtol"] = rtol
     return out
@@ -345,7 +350,7 @@ def main():
             "frac_hbm": BYTES_PER_NODE[key] * nL / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         log(f"[bench] {name} sem_ax {t_ms * 1e3:.1f} us/launch")
 
-    pcg = None if args.no_pcg else bench_pcg(sem, torch, h, nL)
+    pcg = None if args.no_pcg else bench_pcg(sem, torch, h, nL, nG)
     sem.sem_destroy(h)
     learned = None if args.no_learned else bench_learned(sem, torch)
     batch = None if args.no_batch else bench_batch(sem, torch)

@@ -48,7 +48,19 @@ typedef enum {
   SEM_ERR_STATE = 6           /* call not valid for this handle */
 } sem_status;
 
-typedef enum { SEM_FP64 = 0, SEM_FP32 = 1, SEM_BF16 = 2 } sem_precision;
+typedef enum {
+  SEM_FP64 = 0,
+  SEM_FP32 = 1,
+  SEM_BF16 = 2,         /* BF16 u and G, FP32 derivative matrix, VALU */
+  SEM_BF16_PLAIN_D = 3, /* matrix-core operator with the derivative matrix
+                           rounded to BF16: its error does not vanish on
+                           smooth inputs, so refinement around it contracts
+                           poorly or diverges (kept to measure exactly that) */
+  SEM_BF16_MFMA = 4     /* matrix-core operator: BF16 u, G and fluxes, the
+                           derivative matrix as a two-term BF16 split
+                           D = D_hi + D_lo (two accumulating MFMAs per
+                           contraction), FP32 accumulation (N <= 7) */
+} sem_precision;
 typedef enum {
   SEM_PC_NONE = 0,     /* z = r (off the Dirichlet boundary) */
   SEM_PC_JACOBI = 1,   /* z = dinv o r */
@@ -102,10 +114,14 @@ typedef struct {
                            unique nodes (Dirichlet entries are zero) */
   int32_t maxit;        /* CG iterations (inner iterations summed for IR) */
   int32_t pc;           /* a sem_precond */
-  int32_t inner_prec;   /* SEM_FP64: plain FP64 PCG.  SEM_FP32 / SEM_BF16:
+  int32_t inner_prec;   /* SEM_FP64: plain FP64 PCG.  Any other precision:
                            FP64 iterative refinement whose inner PCG uses
-                           FP32 vectors and an FP32 / BF16-stored operator,
-                           with FP64 dot products and scalars */
+                           FP32 vectors and that operator (SEM_FP32, SEM_BF16,
+                           SEM_BF16_MFMA, SEM_BF16_PLAIN_D; the matrix-core
+                           ones for solves of one order N <= 7), with FP64
+                           dot products and scalars; refinement stops after
+                           3 steps that do not shrink the true residual by
+                           10% */
   double inner_rtol;    /* inner relative tolerance for refinement */
   int32_t check_every;  /* CG iterations between host convergence polls */
   int32_t use_graph;    /* 1: replay a captured HIP graph of check_every
@@ -119,6 +135,9 @@ typedef struct {
   int32_t fell_back;          /* 1 when a learned solve switched to Jacobi */
   double final_rel_res;       /* recomputed FP64 ||b - A x|| / ||b|| */
   double seconds;             /* wall time of the solve on the stream */
+  double outer_contraction;   /* largest ratio ||r_k+1|| / ||r_k|| of the FP64
+                                 true residual over refinement steps (0 for
+                                 plain PCG) */
 } sem_solve_stats;
 
 /* Build a handle: reference element (GLL nodes, weights, derivative matrix),
@@ -163,7 +182,10 @@ sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
  * the kernel section 4.2.2 names as the dominant cost of PCG.
  * p = SEM_FP64: u, w double.  SEM_FP32: u, w float (FP32 G).
  * SEM_BF16: u bf16 (16-byte aligned), w float (BF16 G, FP32 derivative
- * matrix and FP32 accumulation).  u_L and w_L must not overlap. */
+ * matrix and FP32 accumulation, VALU).  SEM_BF16_MFMA: u bf16 (16-byte
+ * aligned), w float; the six contractions on the matrix cores with the
+ * split derivative matrix (N <= 7).  SEM_BF16_PLAIN_D: the same with D
+ * rounded to BF16.  u_L and w_L must not overlap. */
 sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
                   void *stream);
 
@@ -257,9 +279,10 @@ sem_status sem_mlp_set_params(sem_mlp *net, const float *params, int64_t n);
  * multiple of 16; padding columns finite), Y device FP32 [B][n_out]. */
 sem_status sem_mlp_forward(sem_mlp *net, const uint16_t *X, int32_t ldx,
                            int32_t B, float *Y, void *stream);
-/* Mean squared error between P o and targets T (device FP32 [B][(N+1)^3]):
- * P is the trilinear prolongation to the GLL nodes of order N when n_out = 8,
- * the identity when n_out = (N+1)^3
+/* Mean squared error between P o and targets T: P is the trilinear
+ * prolongation to the GLL nodes of order N when n_in = (N+1)^3 + 8 and
+ * n_out = 8 (T device FP32 [B][(N+1)^3]), else the identity (T device FP32
+ * [B][n_out]: nodal and interior layouts);
  * and its gradient: grad device FP32 [n_params] (may be NULL: the network's
  * own gradient buffer is used by sem_mlp_adam with grad NULL).  *loss is
  * written on the host (synchronises the stream). */
@@ -281,8 +304,9 @@ sem_status sem_mlp_save(const sem_mlp *net, const char *path);
 sem_status sem_mlp_load(const char *path, sem_mlp **out);
 
 /* Attach a network (NULL detaches) to a handle for SEM_PC_LEARNED; the
- * network must outlive the attachment and have n_in = (N+1)^3 + 8 and
- * n_out = 8 or (N+1)^3. */
+ * network must outlive the attachment.  Its shape selects the layout:
+ * n_in = (N+1)^3 + 8 with n_out = 8 (Q1) or (N+1)^3 (nodal), or
+ * n_in = (N-1)^3 + 8 with n_out = (N-1)^3 (interior, N >= 2). */
 sem_status sem_learn_attach(sem_handle *h, sem_mlp *net);
 
 typedef struct {
@@ -298,26 +322,49 @@ typedef struct {
 } sem_train_opts;
 
 typedef struct {
-  int32_t pairs, epochs, snapshots, reserved;
+  int32_t pairs, epochs, snapshots;
+  int32_t local_iters_max;        /* interior layout: most element-interior CG
+                                     iterations of a target (0 otherwise) */
   double first_loss, last_loss;   /* mean loss of the first / last epoch */
   double data_seconds, train_seconds, validate_seconds;
   double damping;                 /* chosen correction scale (0: disabled) */
   double jacobi_rate;             /* Jacobi-PCG log10 residual drop / iteration */
   int32_t val_iters_jacobi, val_iters_learned;  /* validation solve to 1e-6 */
-  int32_t val_iters[4];   /* learned iterations for damping 0.2, 0.15, 0.1,
-                             0.05 (-1: not converged or fell back) */
+  int32_t val_iters[4];   /* learned iterations for the damping candidates
+                             1, 0.75, 0.5, 0.25 (interior layout) or 0.2,
+                             0.15, 0.1, 0.05 (Q1, nodal); -1: not converged
+                             or fell back */
 } sem_train_report;
 
 /* Generate training pairs with the FP64 solver and train the network on the
  * GPU.  For every right-hand side b_L[q] (device FP64 E-vectors) a FP64
- * Jacobi-PCG solve from x = 0 records snapshots x_k, r_k; once it converged,
- * e_k = x* - x_k; pairs (r_k, e_k) restricted to random elements give the
- * features and the targets e_e kappa_e h_e / s_e.  Training: epochs of
+ * Jacobi-PCG solve from x = 0 records snapshots x_k, r_k; residuals
+ * restricted to random elements give the features.  Targets: Q1 and nodal
+ * layouts, the element error (x* - x_k)_e kappa_e h_e / s_e of the
+ * converged solve; interior layout, the element-interior solve of
+ * sem_learn_interior_pairs.  Training: epochs of
  * shuffled minibatches of forward, loss, backward and Adam, all on the GPU.
  * Then the damping is validated on the last right-hand side (see above). */
 sem_status sem_learn_train(sem_handle *h, sem_mlp *net, const double *const *b_L,
                            int32_t n_rhs, const sem_train_opts *opts,
                            sem_train_report *report, void *stream);
+
+/* Training pairs of the interior layout for one residual (the definition
+ * of the training targets, exposed for checking): for each of the n
+ * elements elems[q] (device int32, each in [0, E)), features X[q] (device
+ * BF16 [n][ldx], ldx a multiple of 16 and >= (N-1)^3 + 8: r at the
+ * element-interior nodes 1 <= i, j, k <= N-1 in lexicographic order over
+ * their 2-norm s, then the 8 log-kappa vertex deviations) and targets T[q]
+ * (device FP32 [n][(N-1)^3]: (d - dinv r_I) kappa_e h_e / s, where d solves
+ * the element's interior problem A_II d = r_I, the element stiffness with
+ * zero values on the element's faces; Jacobi-CG in FP64 on the GPU to
+ * ||r_I - A_II d|| <= rtol ||r_I||, at most 2000 iterations).  r_L: device
+ * FP64 continuous E-vector.  iters (device int32 [n], may be NULL): CG
+ * iterations per element.  Synchronises the stream.  N >= 2. */
+sem_status sem_learn_interior_pairs(sem_handle *h, const double *r_L,
+                                    const int32_t *elems, int32_t n,
+                                    uint16_t *X, int32_t ldx, float *T,
+                                    double rtol, int32_t *iters, void *stream);
 
 /* Text of the calling thread's last error ("" if none). */
 const char *sem_last_error(void);

@@ -1,0 +1,366 @@
+// Local stiffness action w = D^T G D u (paper section 4.2.1) with the six
+// tensor contractions on the matrix cores: BF16 inputs u and G, FP32
+// accumulation, FP32 output.
+//
+// The derivative matrix cannot simply be rounded to BF16: its rounding error
+// does not vanish on smooth inputs (D 1 != 0, D x != 1), which the
+// refinement around the operator cannot undo.  It is split instead,
+// D = D_hi + D_lo with D_hi = bf16(D) and D_lo = bf16(D - D_hi) (a two-term
+// BF16 expansion, relative error ~2^-16), and every contraction runs as two
+// accumulating MFMAs.  SPLIT = false keeps only D_hi (the inaccurate
+// variant, kept for measurement).
+//
+// One wave per element, the element padded to 8^3 nodes (n1 <= 8; padded
+// entries of u and D are zero), four waves per workgroup.  MFMA tile
+// 16x16x16 (v_mfma_f32_16x16x16_bf16): lane l = 16 g + r holds A[r][4g + q],
+// B[4g + q][r] and C[4g + q][r], q = 0..3.  A length-8 contraction uses a
+// block-diagonal operand diag(D, D) so that one MFMA contracts two 8-blocks:
+//   t (over k):  C[(b,k)][c']   = sum_m D[k][m] u[m][cb + 16 b + c']
+//   r (over i):  C[rho'][(b,i)] = sum_m u[rb + 16 b + rho'][m] D[i][m]
+//   s (over j):  C[(b,j)][(h,i)] = sum_m D[j][m] u[kb + 2 b + h][m][i]
+// with c = (j,i) and rho = (k,j); two MFMAs (cb, rb, kb) cover the element.
+// The transposed contractions use D^T the same way and accumulate w through
+// the C operand (r, then s, then t), staged in LDS in [k][j][i] order.  The
+// metric step between them (fluxes = G grad u) is FP32 on the VALU, one lane
+// per (i,j) column, and the fluxes are rounded to BF16 for the MFMAs.
+#include "ax_tile.h"
+
+namespace sem {
+
+typedef short m16x4 __attribute__((ext_vector_type(4)));
+typedef float mf32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MW = 4;  // waves (elements) per workgroup
+
+struct alignas(16) MfmaLds {
+  uint16_t u[512];                  // u (BF16)
+  float gr[512], gs[512], gt[512];  // gradients; gr is reused for w
+  uint16_t fr[512], fs[512], ft[512];
+};
+
+__device__ inline m16x4 lds4_strided(const uint16_t *p, int stride) {
+  m16x4 v;
+  v[0] = (short)p[0];
+  v[1] = (short)p[stride];
+  v[2] = (short)p[2 * stride];
+  v[3] = (short)p[3 * stride];
+  return v;
+}
+
+__device__ inline mf32x4 mfma(m16x4 a, m16x4 b, mf32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// Operands of the derivative matrix held by lane l (constant per kernel):
+//   fwd[q] = D[r % 8][4 (g % 2) + q], bwd[q] = D[4 (g % 2) + q][r % 8],
+// zero off the diagonal blocks (r / 8 != g / 2) and outside n1.
+template <int N1>
+__device__ inline void d_operands(int l, const uint16_t *__restrict__ Dhi,
+                                  const uint16_t *__restrict__ Dlo, m16x4 &fh,
+                                  m16x4 &fl, m16x4 &bh, m16x4 &bl) {
+  const int r = l & 15, g = l >> 4;
+  const bool blk = (r >> 3) == (g >> 1);
+  const int a = r & 7;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = 4 * (g & 1) + q;
+    const bool okf = blk && a < N1 && m < N1;
+    fh[q] = okf ? (short)Dhi[a * N1 + m] : (short)0;
+    fl[q] = okf ? (short)Dlo[a * N1 + m] : (short)0;
+    bh[q] = okf ? (short)Dhi[m * N1 + a] : (short)0;
+    bl[q] = okf ? (short)Dlo[m * N1 + a] : (short)0;
+  }
+}
+
+// One element per wave.  The caller has placed the element's u (BF16,
+// padded [k][j][i] order, zeros outside n1) in L.u and holds in gq the six
+// BF16 factors of the lane's column (i, j) = (l % 8, l / 8) for k < 8 (zero
+// outside the element).  On return L.gr holds w in [k][j][i] order.
+template <int N1, bool SPLIT>
+__device__ inline void mfma_element(int l, MfmaLds &L, const uint16_t (&gq)[6][8],
+                                    m16x4 fh, m16x4 fl, m16x4 bh, m16x4 bl) {
+  const int r = l & 15, g = l >> 4;
+  const mf32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  // ---- gradient: three contractions ----
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {
+    {  // t: B from u[m][c], m = 4 (g % 2) + q, c = 32 h2 + 16 (g / 2) + r
+      const int c = 32 * h2 + 16 * (g >> 1) + r, m0 = 4 * (g & 1);
+      const m16x4 b = lds4_strided(&L.u[m0 * 64 + c], 64);
+      mf32x4 acc = mfma(fh, b, zero);
+      if (SPLIT) acc = mfma(fl, b, acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) L.gt[(m0 + q) * 64 + c] = acc[q];
+    }
+    {  // r: A from u[rho][m], rho = 32 h2 + 16 (g / 2) + r
+      const int rho = 32 * h2 + 16 * (g >> 1) + r, m0 = 4 * (g & 1);
+      const m16x4 a = *reinterpret_cast<const m16x4 *>(&L.u[rho * 8 + m0]);
+      mf32x4 acc = mfma(a, fh, zero);
+      if (SPLIT) acc = mfma(a, fl, acc);
+      const int i = r & 7, rho0 = 32 * h2 + 16 * (r >> 3) + 4 * g;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) L.gr[(rho0 + q) * 8 + i] = acc[q];
+    }
+    {  // s: B from u[k][m][i], k = 4 h2 + 2 (g / 2) + r / 8
+      const int k = 4 * h2 + 2 * (g >> 1) + (r >> 3), i = r & 7, m0 = 4 * (g & 1);
+      const m16x4 b = lds4_strided(&L.u[k * 64 + m0 * 8 + i], 8);
+      mf32x4 acc = mfma(fh, b, zero);
+      if (SPLIT) acc = mfma(fl, b, acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) L.gs[k * 64 + (m0 + q) * 8 + i] = acc[q];
+    }
+  }
+  __syncthreads();
+  // ---- metric step on the lane's column (FP32) ----
+  {
+    const int i = l & 7, j = l >> 3;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int p = k * 64 + j * 8 + i;
+      const float ur = L.gr[p], us = L.gs[p], ut = L.gt[p];
+      const float g0 = bf16_to_f32(gq[0][k]), g1 = bf16_to_f32(gq[1][k]),
+                  g2 = bf16_to_f32(gq[2][k]), g3 = bf16_to_f32(gq[3][k]),
+                  g4 = bf16_to_f32(gq[4][k]), g5 = bf16_to_f32(gq[5][k]);
+      L.fr[p] = f32_to_bf16(g0 * ur + g1 * us + g2 * ut);
+      L.fs[p] = f32_to_bf16(g1 * ur + g3 * us + g4 * ut);
+      L.ft[p] = f32_to_bf16(g2 * ur + g4 * us + g5 * ut);
+    }
+  }
+  __syncthreads();
+  // ---- divergence: w = D_r^T f_r + D_s^T f_s + D_t^T f_t into L.gr ----
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {  // r: A from f_r[rho][m], B = D^T blocks
+    const int rho = 32 * h2 + 16 * (g >> 1) + r, m0 = 4 * (g & 1);
+    const m16x4 a = *reinterpret_cast<const m16x4 *>(&L.fr[rho * 8 + m0]);
+    mf32x4 acc = mfma(a, bh, zero);
+    if (SPLIT) acc = mfma(a, bl, acc);
+    const int i = r & 7, rho0 = 32 * h2 + 16 * (r >> 3) + 4 * g;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L.gr[(rho0 + q) * 8 + i] = acc[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {  // s: A = diag(D^T), B from f_s[k][m][i]
+    const int k = 4 * h2 + 2 * (g >> 1) + (r >> 3), i = r & 7, m0 = 4 * (g & 1);
+    const m16x4 b = lds4_strided(&L.fs[k * 64 + m0 * 8 + i], 8);
+    mf32x4 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = L.gr[k * 64 + (m0 + q) * 8 + i];
+    acc = mfma(bh, b, acc);
+    if (SPLIT) acc = mfma(bl, b, acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L.gr[k * 64 + (m0 + q) * 8 + i] = acc[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h2 = 0; h2 < 2; ++h2) {  // t: A = diag(D^T), B from f_t[m][c]
+    const int c = 32 * h2 + 16 * (g >> 1) + r, m0 = 4 * (g & 1);
+    const m16x4 b = lds4_strided(&L.ft[m0 * 64 + c], 64);
+    mf32x4 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = L.gr[(m0 + q) * 64 + c];
+    acc = mfma(bh, b, acc);
+    if (SPLIT) acc = mfma(bl, b, acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) L.gr[(m0 + q) * 64 + c] = acc[q];
+  }
+  __syncthreads();
+}
+
+// the six BF16 factors of column (i, j) of element e: the column-contiguous
+// layout [E][6][64][8] at n1 = 8, [E][6][n1^3] otherwise
+template <int N1>
+__device__ inline void load_factors(int l, bool act, int64_t e,
+                                    const uint16_t *__restrict__ G,
+                                    uint16_t (&gq)[6][8]) {
+  constexpr int NP = N1 * N1, N3 = NP * N1;
+  const int i = l & 7, j = l >> 3;
+  if constexpr (N1 == 8) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (act)
+        v = __builtin_nontemporal_load(
+            reinterpret_cast<const u32x4 *>(G + e * 6 * N3 + q * N3 + 8 * l));
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        gq[q][2 * h] = (uint16_t)(wv[h] & 0xffffu);
+        gq[q][2 * h + 1] = (uint16_t)(wv[h] >> 16);
+      }
+    }
+  } else {
+    const bool col = act && i < N1 && j < N1;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        gq[q][k] = (col && k < N1)
+                       ? G[e * 6 * N3 + q * N3 + k * NP + j * N1 + i]
+                       : (uint16_t)0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// standalone operator: BF16 E-vector in, FP32 E-vector out
+// ---------------------------------------------------------------------------
+template <int N1, bool SPLIT>
+__global__ void __launch_bounds__(64 * MW)
+    k_ax_mfma(int64_t E, const uint16_t *__restrict__ Dhi,
+              const uint16_t *__restrict__ Dlo, const uint16_t *__restrict__ G,
+              const uint16_t *__restrict__ u, float *__restrict__ w) {
+  constexpr int NP = N1 * N1, N3 = NP * N1;
+  __shared__ MfmaLds lds[MW];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * MW + wv;
+  const bool act = e < E;
+  MfmaLds &L = lds[wv];
+  m16x4 fh, fl, bh, bl;
+  d_operands<N1>(l, Dhi, Dlo, fh, fl, bh, bl);
+  uint16_t gq[6][8];
+  load_factors<N1>(l, act, e, G, gq);
+  if constexpr (N1 == 8) {
+    u32x4 v = {0u, 0u, 0u, 0u};
+    if (act) v = *reinterpret_cast<const u32x4 *>(u + e * N3 + 8 * l);
+    *reinterpret_cast<u32x4 *>(&L.u[8 * l]) = v;
+  } else {
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int p = l + 64 * t, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+      L.u[p] = (act && i < N1 && j < N1 && k < N1) ? u[e * N3 + k * NP + j * N1 + i]
+                                                   : (uint16_t)0;
+    }
+  }
+  __syncthreads();
+  mfma_element<N1, SPLIT>(l, L, gq, fh, fl, bh, bl);
+  if (!act) return;  // no barrier follows
+  if constexpr (N1 == 8) {
+    const float *src = &L.gr[8 * l];
+#pragma unroll
+    for (int h = 0; h < 8; ++h) __builtin_nontemporal_store(src[h], w + e * N3 + 8 * l + h);
+  } else {
+    for (int p = l; p < N3; p += 64) {
+      const int i = p % N1, j = (p / N1) % N1, k = p / NP;
+      w[e * N3 + p] = L.gr[k * 64 + j * 8 + i];
+    }
+  }
+}
+
+template <bool SPLIT>
+static void launch_ax_mfma_s(int N, int64_t E, const uint16_t *Dhi,
+                             const uint16_t *Dlo, const uint16_t *G,
+                             const uint16_t *u, float *w, hipStream_t s) {
+  const int64_t blocks = (E + MW - 1) / MW;
+  if (blocks == 0) return;
+  const dim3 grid((unsigned)blocks), block(64 * MW);
+  switch (N) {
+#define SEM_AXM(NN)                                                          \
+  case NN:                                                                   \
+    hipLaunchKernelGGL((k_ax_mfma<NN + 1, SPLIT>), grid, block, 0, s, E, Dhi, \
+                       Dlo, G, u, w);                                        \
+    break;
+    SEM_AXM(1)
+    SEM_AXM(2)
+    SEM_AXM(3)
+    SEM_AXM(4)
+    SEM_AXM(5)
+    SEM_AXM(6)
+    SEM_AXM(7)
+#undef SEM_AXM
+    default:
+      fail(SEM_ERR_ARG, "sem_ax: the matrix-core operator needs N in 1..7");
+  }
+}
+
+void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
+                    const uint16_t *Dlo, const uint16_t *G, const uint16_t *u,
+                    float *w, hipStream_t s) {
+  if (split)
+    launch_ax_mfma_s<true>(N, E, Dhi, Dlo, G, u, w, s);
+  else
+    launch_ax_mfma_s<false>(N, E, Dhi, Dlo, G, u, w, s);
+  SEM_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// batched operator inside the solvers: FP32 unique-node input gathered
+// through the box numbering and rounded to BF16, FP32 E-vector output;
+// items are tiles of a single order (n1 = N1s), MW elements per workgroup
+// pass
+// ---------------------------------------------------------------------------
+template <int N1, bool SPLIT>
+__global__ void __launch_bounds__(64 * MW)
+    k_bax_mfma(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
+               const AxItem *__restrict__ items, int nitems, int epb, int src,
+               int dst, int skip_done) {
+  constexpr int NP = N1 * N1, N3 = NP * N1;
+  __shared__ MfmaLds lds[MW];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  MfmaLds &L = lds[wv];
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const AxItem it = items[q];
+    if (skip_done && st[it.solve].done != 0) continue;  // uniform per block
+    const BatchSolve &sd = sds[it.solve];
+    const float *u = (const float *)sd.v32[src];
+    float *w = (float *)sd.v32[dst];
+    const uint16_t *G = (const uint16_t *)sd.G16;
+    m16x4 fh, fl, bh, bl;
+    d_operands<N1>(l, (const uint16_t *)sd.D16hi, (const uint16_t *)sd.D16lo, fh,
+                   fl, bh, bl);
+    for (int e0 = 0; e0 < epb; e0 += MW) {  // uniform per block
+      const int64_t e = it.elem0 + e0 + wv;
+      const bool act = e0 + wv < epb && e < sd.E;
+      uint16_t gq[6][8];
+      load_factors<N1>(l, act, e, G, gq);
+      int64_t gb = 0;
+      if (act) gb = box_origin(sd.box, (uint32_t)e);
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int p = l + 64 * t, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+        const bool in = act && i < N1 && j < N1 && k < N1;
+        L.u[p] = in ? f32_to_bf16(u[gb + i + (int64_t)sd.box.Gx * j + sd.box.Gxy * k])
+                    : (uint16_t)0;
+      }
+      __syncthreads();
+      mfma_element<N1, SPLIT>(l, L, gq, fh, fl, bh, bl);
+      if (act) {
+        for (int p = l; p < N3; p += 64) {
+          const int i = p % N1, j = (p / N1) % N1, k = p / NP;
+          w[e * N3 + p] = L.gr[k * 64 + j * 8 + i];
+        }
+      }
+      __syncthreads();  // L is reused by the next element
+    }
+  }
+}
+
+void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *st,
+                     const AxItem *items, int nitems, int epb, int grid, int src,
+                     int dst, int skip_done, hipStream_t s) {
+  if (nitems <= 0) return;
+  const dim3 g((unsigned)grid), b(64 * MW);
+  switch (n1) {
+#define SEM_BAXM(NN)                                                            \
+  case NN:                                                                      \
+    if (split)                                                                  \
+      hipLaunchKernelGGL((k_bax_mfma<NN, true>), g, b, 0, s, sds, st, items,    \
+                         nitems, epb, src, dst, skip_done);                     \
+    else                                                                        \
+      hipLaunchKernelGGL((k_bax_mfma<NN, false>), g, b, 0, s, sds, st, items,   \
+                         nitems, epb, src, dst, skip_done);                     \
+    break;
+    SEM_BAXM(2)
+    SEM_BAXM(3)
+    SEM_BAXM(4)
+    SEM_BAXM(5)
+    SEM_BAXM(6)
+    SEM_BAXM(7)
+    SEM_BAXM(8)
+#undef SEM_BAXM
+    default:
+      fail(SEM_ERR_ARG, "batched operator: the matrix-core operator needs N in 1..7");
+  }
+  SEM_HIP(hipGetLastError());
+}
+
+}  // namespace sem

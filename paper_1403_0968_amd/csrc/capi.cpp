@@ -156,6 +156,13 @@ sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
       D = h->D32.p;
       need(reinterpret_cast<uintptr_t>(u_L) % 16 == 0,
            "sem_ax: BF16 input must be 16-byte aligned");
+    } else if (p == SEM_BF16_MFMA || p == SEM_BF16_PLAIN_D) {
+      need(reinterpret_cast<uintptr_t>(u_L) % 16 == 0,
+           "sem_ax: BF16 input must be 16-byte aligned");
+      launch_ax_mfma(h->N, p == SEM_BF16_MFMA, h->E, h->D16hi.as<uint16_t>(),
+                     h->D16lo.as<uint16_t>(), h->G16.as<uint16_t>(),
+                     (const uint16_t *)u_L, (float *)w_L, strm(stream));
+      return;
     } else {
       fail(SEM_ERR_ARG, "sem_ax: unknown precision");
     }
@@ -386,6 +393,16 @@ sem_status sem_learn_train(sem_handle *h, sem_mlp *net, const double *const *b_L
     need(h != nullptr && net != nullptr && b_L != nullptr && opts != nullptr,
          "sem_learn_train: null argument");
     learn_train(h, net, b_L, n_rhs, opts, report, strm(stream));
+  });
+}
+
+sem_status sem_learn_interior_pairs(sem_handle *h, const double *r_L,
+                                    const int32_t *elems, int32_t n,
+                                    uint16_t *X, int32_t ldx, float *T,
+                                    double rtol, int32_t *iters, void *stream) {
+  return guarded([&] {
+    need(h != nullptr, "sem_learn_interior_pairs: null handle");
+    learn_interior_pairs(h, r_L, elems, n, X, ldx, T, rtol, iters, strm(stream));
   });
 }
 

@@ -432,16 +432,15 @@ void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
   SEM_HIP(hipGetLastError());
 }
 
-// loss and gradient of B samples with targets T [B][n1^3] on the GLL nodes
-// of order N: the output is either 8 trilinear vertex values (prolonged) or
-// the n1^3 nodal values themselves; gradient into net->grad (flat order)
+// loss and gradient of B samples: with n_in = (N+1)^3 + 8 and n_out = 8 the
+// output is 8 trilinear vertex values prolonged to the GLL nodes of order N
+// and T is [B][(N+1)^3]; otherwise the output is compared with T [B][n_out]
+// directly (nodal and interior layouts); gradient into net->grad (flat order)
 double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
                      int B, int N, bool host_loss, hipStream_t s) {
   if (N < 1 || N > 16) fail(SEM_ERR_ARG, "mlp_loss_grad: N must be in 1..16");
   const int nn = (N + 1) * (N + 1) * (N + 1);
-  const bool q1 = net->n_out == 8;
-  if (!q1 && net->n_out != nn)
-    fail(SEM_ERR_ARG, "mlp_loss_grad: n_out must be 8 or (N+1)^3");
+  const bool q1 = net->n_out == 8 && net->n_in == nn + 8;
   ensure_scratch(net, B);  // before net->of is read below
   const int wo = net->n_out > 16 ? net->n_out : 16;
   mlp_forward(net, X, ldx, B, net->of.as<float>(), wo, true, s, nullptr, nullptr);

@@ -84,6 +84,7 @@ struct BatchSolve {
   int64_t E, nL, nG;
   Box box;                        // closed-form numbering of the solve's mesh
   const void *G64, *G32, *G16, *D64, *D32;
+  const void *D16hi, *D16lo;      // two-term BF16 split of D
   const double *dinv64, *one64;   // Jacobi, and 1 off the Dirichlet boundary
   const float *dinv32, *one32;
   void *v64[NVEC];
@@ -118,7 +119,7 @@ struct sem_handle {
   sem::DevBuf l2g, perm, offsets, mult, bmask, gmask, masked_lids, seg_off,
       seg_ids;
   // reference element on device
-  sem::DevBuf D64, D32;
+  sem::DevBuf D64, D32, D16hi, D16lo;  // D16hi + D16lo: BF16 split of D
   // geometry and preconditioner
   sem::DevBuf coords, G64, G32, G16, mass, diag_L, dinv_G, dinv_G32;
   sem::DevBuf kvert;            // kappa at the 8 vertices of each element
@@ -144,6 +145,12 @@ void launch_precond(sem_handle *h, int pc, int prec, const void *r, void *z,
 void launch_bax(int prec, int bs, int nset, const BatchSolve *sds,
                 const CgState *st, const AxItem *items, int nitems, int grid,
                 int src, int dst, int skip_done, hipStream_t s);
+void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
+                    const uint16_t *Dlo, const uint16_t *G, const uint16_t *u,
+                    float *w, hipStream_t s);
+void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *st,
+                     const AxItem *items, int nitems, int epb, int grid, int src,
+                     int dst, int skip_done, hipStream_t s);
 int bax_elements_per_tile(int bs, int n1);
 // solver (solver.hip)
 void destroy_ws(sem_handle *h);
@@ -185,6 +192,9 @@ void learn_destroy(sem_handle *h);
 // into the E-vector cL
 void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
                  hipStream_t s);
+void learn_interior_pairs(sem_handle *h, const double *rL, const int32_t *elems,
+                          int n, uint16_t *X, int ldx, float *T, double rtol,
+                          int32_t *iters, hipStream_t s);
 void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
                  const sem_train_opts *o, sem_train_report *rep,
                  hipStream_t caller);

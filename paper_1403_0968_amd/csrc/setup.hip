@@ -221,6 +221,14 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
   upload(h->D64, h->ref.D, s);
   std::vector<float> D32(h->ref.D.begin(), h->ref.D.end());
   upload(h->D32, D32, s);
+  // two-term BF16 split of D for the matrix-core operator
+  std::vector<uint16_t> Dhi(D32.size()), Dlo(D32.size());
+  for (size_t q = 0; q < D32.size(); ++q) {
+    Dhi[q] = f32_to_bf16((float)h->ref.D[q]);
+    Dlo[q] = f32_to_bf16((float)(h->ref.D[q] - (double)bf16_to_f32(Dhi[q])));
+  }
+  upload(h->D16hi, Dhi, s);
+  upload(h->D16lo, Dlo, s);
 
   const int N1 = h->n1;
   GeomParams P{};

@@ -561,8 +561,8 @@ struct sem_batch {
   sem::DevBuf axitems[3];       // per block size 64 / 128 / 256
   int n_ax[3] = {0, 0, 0};
   int n_vi = 0;
-  int bs[3] = {128, 64, 64};    // operator block size per precision
-  int gmul[3] = {0, 0, 0};      // persistent grid = 256 CUs x gmul (0: 1 item/WG)
+  int bs[5] = {128, 64, 64, 256, 256};  // operator block size per precision
+  int gmul[5] = {0, 0, 0, 0, 0};  // persistent grid = 256 CUs x gmul (0: 1 item/WG)
   sem::CgState *host_st = nullptr;
   double *host_red = nullptr;
   int32_t *host_i = nullptr;    // staging for active / maxit
@@ -639,6 +639,8 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
       d.G16 = h->G16.p;
       d.D64 = h->D64.p;
       d.D32 = h->D32.p;
+      d.D16hi = h->D16hi.p;
+      d.D16lo = h->D16lo.p;
       d.dinv64 = h->dinv_G.as<double>();
       d.dinv32 = h->dinv_G32.as<float>();
       d.one64 = W->one64.as<double>();
@@ -711,6 +713,18 @@ void destroy_ws(sem_handle *h) {
 static int vec_grid(const sem_batch *b) { return std::min(b->n_vi, 2048); }
 
 static void bax(sem_batch *b, int prec, int src, int dst, int skip_done) {
+  if (prec == SEM_BF16_MFMA || prec == SEM_BF16_PLAIN_D) {
+    // matrix-core operator: tiles of the 256-thread item list, one order
+    if (b->nset < 2 || b->nset > 8)
+      fail(SEM_ERR_ARG, "solve: the matrix-core operator needs solves of one "
+                        "order N <= 7");
+    const int k = bs_slot(256);
+    launch_bax_mfma(b->nset, prec == SEM_BF16_MFMA, b->sds.as<BatchSolve>(),
+                    b->st.as<CgState>(), b->axitems[k].as<AxItem>(), b->n_ax[k],
+                    bax_elements_per_tile(256, b->nset), b->n_ax[k], src, dst,
+                    skip_done, b->s);
+    return;
+  }
   const int bs = b->bs[prec];
   const int k = bs_slot(bs);
   const int n = b->n_ax[k];
@@ -951,7 +965,8 @@ static void check_opts(const sem_solve_opts *o) {
   if (o->pc != SEM_PC_NONE && o->pc != SEM_PC_JACOBI && o->pc != SEM_PC_LEARNED)
     fail(SEM_ERR_ARG, "solve: unknown preconditioner");
   if (o->inner_prec != SEM_FP64 && o->inner_prec != SEM_FP32 &&
-      o->inner_prec != SEM_BF16)
+      o->inner_prec != SEM_BF16 && o->inner_prec != SEM_BF16_PLAIN_D &&
+      o->inner_prec != SEM_BF16_MFMA)
     fail(SEM_ERR_ARG, "solve: unknown inner precision");
   if (o->inner_prec != SEM_FP64 && !(o->inner_rtol > 0.0 && o->inner_rtol < 1.0))
     fail(SEM_ERR_ARG, "solve: inner_rtol must be in (0, 1)");
@@ -985,6 +1000,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
   SEM_HIP(hipGetLastError());
 
   std::vector<int> iters(n, 0), outer(n, 0), status(n, SEM_ERR_NOT_CONVERGED);
+  std::vector<double> contraction(n, 0.0);
   std::vector<int> act(n, 1), mx(n, o->maxit);
   bool learned = o->pc == SEM_PC_LEARNED;
   int fell_back = 0;
@@ -1031,6 +1047,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
     const int prec = o->inner_prec;
     std::vector<double> rel_prev(n, 1e300);
     std::vector<int> stall(n, 0);
+    contraction.assign(n, 0.0);
     upload_active(b, act, mx);
     residual(b);
     while (true) {
@@ -1064,6 +1081,8 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
           continue;
         }
         stall[q] = rel > 0.9 * rel_prev[q] ? stall[q] + 1 : 0;
+        if (rel_prev[q] < 1e300)
+          contraction[q] = std::max(contraction[q], rel / rel_prev[q]);
         rel_prev[q] = rel;
         if (iters[q] >= o->maxit || stall[q] >= 3) {
           act[q] = 0;  // not converged
@@ -1151,6 +1170,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
       stats[q].fell_back = fell_back;
       stats[q].final_rel_res = bb > 0 ? std::sqrt(rr / bb) : 0.0;
       stats[q].seconds = ms * 1e-3;
+      stats[q].outer_contraction = contraction[q];
     }
     if (status[q] != SEM_OK && worst == SEM_OK) worst = (sem_status)status[q];
   }
@@ -1283,7 +1303,8 @@ static void write_cache(const char *path,
 
 void batch_tune(sem_batch *b, int prec, int *best_bs, int *best_gm,
                 double *best_us) {
-  if (prec < SEM_FP64 || prec > SEM_BF16) fail(SEM_ERR_ARG, "tune: precision");
+  if (prec < SEM_FP64 || prec > SEM_BF16)
+    fail(SEM_ERR_ARG, "tune: precision must be SEM_FP64, SEM_FP32 or SEM_BF16");
   const char *path = getenv("SEM_AUTOTUNE_CACHE");
   const std::string key = tune_key(b, prec);
   if (path) {

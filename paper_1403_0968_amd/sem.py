@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libsem.so")
 
 SEM_OK, SEM_ERR_ARG, SEM_ERR_HIP, SEM_ERR_OOM = 0, 1, 2, 3
 SEM_ERR_NOT_CONVERGED, SEM_ERR_BREAKDOWN, SEM_ERR_STATE = 4, 5, 6
-SEM_FP64, SEM_FP32, SEM_BF16 = 0, 1, 2
+SEM_FP64, SEM_FP32, SEM_BF16, SEM_BF16_PLAIN_D, SEM_BF16_MFMA = 0, 1, 2, 3, 4
 SEM_PC_NONE, SEM_PC_JACOBI, SEM_PC_LEARNED = 0, 1, 2
 SEM_MAP_AFFINE, SEM_MAP_SINE_X, SEM_MAP_SINE_CYCLIC = 0, 1, 2
 SEM_SRC_FOURIER, SEM_SRC_SINE = 0, 1
@@ -31,7 +31,7 @@ EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_mlp_info", "sem_mlp_get_params", "sem_mlp_set_params",
             "sem_mlp_forward", "sem_mlp_loss_grad", "sem_mlp_adam",
             "sem_mlp_set_damping", "sem_mlp_get_damping", "sem_mlp_save", "sem_mlp_load", "sem_learn_attach",
-            "sem_learn_train", "sem_last_error"]
+            "sem_learn_train", "sem_learn_interior_pairs", "sem_last_error"]
 
 
 class sem_mesh_desc(C.Structure):
@@ -66,7 +66,7 @@ class sem_train_opts(C.Structure):
 
 class sem_train_report(C.Structure):
     _fields_ = [("pairs", C.c_int32), ("epochs", C.c_int32),
-                ("snapshots", C.c_int32), ("reserved", C.c_int32),
+                ("snapshots", C.c_int32), ("local_iters_max", C.c_int32),
                 ("first_loss", C.c_double), ("last_loss", C.c_double),
                 ("data_seconds", C.c_double), ("train_seconds", C.c_double),
                 ("validate_seconds", C.c_double), ("damping", C.c_double),
@@ -77,7 +77,8 @@ class sem_train_report(C.Structure):
 class sem_solve_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("outer_iters", C.c_int32),
                 ("status", C.c_int32), ("fell_back", C.c_int32),
-                ("final_rel_res", C.c_double), ("seconds", C.c_double)]
+                ("final_rel_res", C.c_double), ("seconds", C.c_double),
+                ("outer_contraction", C.c_double)]
 
 
 _lib = None
@@ -133,6 +134,8 @@ def lib():
     L.sem_mlp_save.argtypes = [vp, C.c_char_p]
     L.sem_mlp_load.argtypes = [C.c_char_p, C.POINTER(vp)]
     L.sem_learn_attach.argtypes = [vp, vp]
+    L.sem_learn_interior_pairs.argtypes = [vp, vp, vp, i32, vp, i32, vp,
+                                           C.c_double, vp, vp]
     L.sem_learn_train.argtypes = [vp, vp, C.POINTER(vp), i32,
                                   C.POINTER(sem_train_opts),
                                   C.POINTER(sem_train_report), vp]
@@ -255,7 +258,8 @@ def sem_pcg_solve(h, b, x, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
         _check(code)
     return {"status": code, "iters": st.iters, "outer_iters": st.outer_iters,
             "fell_back": st.fell_back,
-            "final_rel_res": st.final_rel_res, "seconds": st.seconds}
+            "final_rel_res": st.final_rel_res, "seconds": st.seconds,
+            "outer_contraction": st.outer_contraction}
 
 
 def _opts(rtol, maxit, pc, inner_prec, inner_rtol, check_every, use_graph):
@@ -301,7 +305,9 @@ def sem_batch_pcg_solve(b, bs, xs, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
                    "fell_back": st[q].fell_back,
                    "outer_iters": st[q].outer_iters,
                    "final_rel_res": st[q].final_rel_res,
-                   "seconds": st[q].seconds} for q in range(n)]
+                   "seconds": st[q].seconds,
+                   "outer_contraction": st[q].outer_contraction}
+                  for q in range(n)]
 
 
 # ----------------------------------------------------------------------------
@@ -398,9 +404,21 @@ def sem_learn_train(h, net, bs, n_pairs=20000, snapshot_every=16,
     _check(lib().sem_learn_train(h, net, arr, len(bs), C.byref(o), C.byref(rep),
                                  _stream(stream)))
     out = {k: getattr(rep, k) for k, _ in sem_train_report._fields_
-           if k not in ("reserved", "val_iters")}
+           if k != "val_iters"}
     out["val_iters"] = list(rep.val_iters)
     return out
+
+
+def sem_learn_interior_pairs(h, r, elems, X, T, rtol=1e-10, iters=None,
+                             stream=None):
+    """r: device FP64 E-vector; elems: device int32 [n]; X: device int16
+    [n][ldx] (BF16 bits); T: device FP32 [n][(N-1)^3]; iters: device int32
+    [n] or None."""
+    n = int(elems.shape[0])
+    _check(lib().sem_learn_interior_pairs(
+        h, _ptr(r), _ptr(elems), n, _ptr(X), int(X.shape[1]), _ptr(T),
+        float(rtol), _ptr(iters) if iters is not None else None,
+        _stream(stream)))
 
 
 def sem_last_error():

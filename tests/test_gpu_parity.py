@@ -181,3 +181,39 @@ def test_determinism(sem, pair):
     sem.sem_gs(pair.h, sem.SEM_FP64, w2)
     t.cuda.synchronize()
     assert t.equal(w1, w2)
+
+
+def test_ax_matrix_core_against_oracle(sem, pair):
+    """Matrix-core BF16 operator (split derivative matrix) against the
+    oracle applied to the same BF16-rounded input: the remaining error is
+    the BF16 storage of G and of the fluxes (~2^-9 relative each)."""
+    m = pair.m
+    if m.N > 7:
+        pytest.skip("the matrix-core operator covers N <= 7")
+    u = uniform(m.nL, seed=14)
+    ub, _ = bf16_round(u)
+    refb = orc.ax(m, ub)
+    wm = _ax_gpu(sem, pair.h, u, sem.SEM_BF16_MFMA)
+    em = np.max(np.abs(wm - refb)) / np.max(np.abs(refb))
+    wv = _ax_gpu(sem, pair.h, u, sem.SEM_BF16)
+    ev = np.max(np.abs(wv - refb)) / np.max(np.abs(refb))
+    print(f"[ax bf16 N={m.N}] matrix cores {em:.3e}, VALU {ev:.3e}")
+    assert em <= 2e-2
+
+
+def test_ax_matrix_core_split_derivative(sem, pair):
+    """A constant is differentiated to zero exactly, so A_L 1 = 0: with the
+    two-term BF16 split of D the residue is at the split's 2^-16 level, with
+    D rounded to BF16 it is at 2^-9 (the error refinement cannot remove)."""
+    m = pair.m
+    if m.N > 7 or m.N < 2:
+        pytest.skip("the matrix-core operator covers N <= 7; N = 1 has D exact in BF16")
+    one = np.ones(m.nL)
+    scale = np.max(orc.ax_abs(m, one))
+    ws = _ax_gpu(sem, pair.h, one, sem.SEM_BF16_MFMA)
+    wp = _ax_gpu(sem, pair.h, one, sem.SEM_BF16_PLAIN_D)
+    wv = _ax_gpu(sem, pair.h, one, sem.SEM_BF16)
+    es, ep, ev = (np.max(np.abs(w)) / scale for w in (ws, wp, wv))
+    print(f"[A 1, N={m.N}] split {es:.2e}, plain {ep:.2e}, VALU FP32-D {ev:.2e}")
+    assert es <= 1e-4
+    assert ep >= 10 * es

@@ -124,3 +124,38 @@ def test_not_converged_and_argument_errors(sem):
             sem.sem_ax(p.h, 7, b, t.empty_like(b))
     finally:
         p.close()
+
+
+def test_bf16_plain_derivative_matrix_stalls_refinement(sem):
+    """Refinement around the BF16 operators contracts well when the
+    derivative matrix stays accurate (FP32 on the VALU, or the two-term BF16
+    split on the matrix cores), and much worse when it is rounded to BF16:
+    its error does not vanish on smooth inputs (the inaccurate variant is
+    kept to show exactly this)."""
+    t = torch()
+    n, Nq = 12, 7
+    h = sem.sem_setup(Nq, n, n, n, mapping=sem.SEM_MAP_SINE_CYCLIC)
+    try:
+        _, nL, _ = sem.sem_query(h)
+        b = t.empty(nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, fourier_modes(seed=0))
+        res = {}
+        for prec in (sem.SEM_FP32, sem.SEM_BF16, sem.SEM_BF16_MFMA,
+                     sem.SEM_BF16_PLAIN_D):
+            x = t.zeros_like(b)
+            st = sem.sem_pcg_solve(h, b, x, rtol=1e-10, maxit=20000,
+                                   inner_prec=prec, inner_rtol=1e-3,
+                                   check_every=16, raise_on_fail=False)
+            t.cuda.synchronize()
+            res[prec] = st
+            print(f"[refinement prec={prec}] status {st['status']} outer "
+                  f"{st['outer_iters']} contraction {st['outer_contraction']:.3e} "
+                  f"final {st['final_rel_res']:.2e}")
+        for prec in (sem.SEM_FP32, sem.SEM_BF16, sem.SEM_BF16_MFMA):
+            assert res[prec]["status"] == 0
+            assert res[prec]["outer_contraction"] < 0.1
+        plain = res[sem.SEM_BF16_PLAIN_D]
+        assert (plain["status"] != 0 or plain["outer_contraction"] >
+                5 * res[sem.SEM_BF16_MFMA]["outer_contraction"])
+    finally:
+        sem.sem_destroy(h)
