@@ -16,12 +16,14 @@ mapped by x + 0.05 (sin 2 pi y sin 2 pi z, and cyclic).
 * learned: variable-coefficient problem -div(kappa grad u) = f, kappa =
   exp(Gaussian random field, correlation length 0.1, sigma 1, 4096 random
   Fourier features, seed 7), 24^3 elements, N = 7, affine unit cube.  The
-  per-element correction network (hidden 128, BF16 weights) is trained on
-  the GPU on 20k residual/error pairs from FP64 Jacobi-PCG solves of 8
-  training right-hand sides (seeds 100..107); time to 1e-8 on held-out
-  right-hand sides (seeds 900..902) of plain FP64 Jacobi-PCG, FP64
-  refinement around FP32 Jacobi-PCG, and FP64 refinement around FP32
-  flexible CG with the learned correction.
+  per-element correction network (coarse layout: the element's coarse
+  operator in 27 interior bubble modes from its kappa features, hidden 128,
+  BF16 weights) is trained on the GPU on 20k element pairs from FP64 Jacobi-PCG
+  solves of 8 training right-hand sides (seeds 100..107); time to 1e-8 on 5
+  held-out right-hand sides (seeds 900..904) of plain FP64 Jacobi-PCG, FP64
+  flexible CG with the learned correction, FP64 refinement around FP32
+  Jacobi-PCG, and FP64 refinement around FP32 flexible CG with the trained
+  and with an untrained network (medians over the right-hand sides).
 * batch: 256 independent solves, cubic grids n^3 with n ~ U{6..24}, orders
   N ~ U{3, 5, 7}, sine-cyclic mapping, right-hand sides seeded 1000 + s,
   FP32 operator inside FP64 refinement to 1e-10: one batched solve against a
@@ -139,13 +141,14 @@ def bench_pcg(sem, torch, h, nL, nG, rtol=1e-8):
     return out
 
 
-def bench_learned(sem, torch):
+def bench_learned(sem, torch, n_test=5):
     from seminputs import fourier_modes, grf_features
     n, N = 24, 7
     t0 = time.perf_counter()
     h = sem.sem_setup(N, n, n, n, mapping=sem.SEM_MAP_AFFINE,
                       kappa=grf_features(seed=7, M=4096, ell=0.1, sigma=1.0))
     E, nL, nG = sem.sem_query(h)
+    torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
 
     def rhs(seed):
@@ -153,22 +156,29 @@ def bench_learned(sem, torch):
         sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, fourier_modes(seed=seed))
         return b
 
+    K = (min(2, N - 2) + 1) ** 3   # coarse layout: element coarse operator
+    net = sem.sem_mlp_create(8, 128, K * (K + 1) // 2, seed=11)
+    untrained = sem.sem_mlp_create(8, 128, K * (K + 1) // 2, seed=11)
     train = [rhs(100 + q) for q in range(8)]
-    net = sem.sem_mlp_create((N + 1) ** 3 + 8, 128, (N + 1) ** 3, seed=11)
     rep = sem.sem_learn_train(h, net, train, n_pairs=20000, snapshot_every=16,
                               max_snapshots=64, epochs=30, batch=256, lr=1e-3,
                               solve_rtol=1e-11, seed=1)
     log(f"[learned] trained: {rep}")
     del train
-    sem.sem_learn_attach(h, net)
-    cases = [("fp64_jacobi_pcg", sem.SEM_PC_JACOBI, sem.SEM_FP64),
-             ("fp32_ir_jacobi", sem.SEM_PC_JACOBI, sem.SEM_FP32),
-             ("fp32_ir_learned", sem.SEM_PC_LEARNED, sem.SEM_FP32)]
+    sem.sem_mlp_set_damping(untrained, *sem.sem_mlp_get_damping(net))
+    cases = [("fp64_jacobi_pcg", sem.SEM_PC_JACOBI, sem.SEM_FP64, net),
+             ("fp64_fcg_learned", sem.SEM_PC_LEARNED, sem.SEM_FP64, net),
+             ("fp32_ir_jacobi", sem.SEM_PC_JACOBI, sem.SEM_FP32, net),
+             ("fp32_ir_learned", sem.SEM_PC_LEARNED, sem.SEM_FP32, net),
+             ("fp32_ir_untrained", sem.SEM_PC_LEARNED, sem.SEM_FP32, untrained)]
     out = {name: {"time_s": [], "iters": [], "fell_back": [], "final_rel_res": []}
-           for name, _, _ in cases}
-    for seed in (900, 901, 902):
+           for name, *_ in cases}
+    diffs = []
+    for seed in range(900, 900 + n_test):
         b = rhs(seed)
-        for name, pc, prec in cases:
+        xref = None
+        for name, pc, prec, nw in cases:
+            sem.sem_learn_attach(h, nw)
             for rep_i in range(2):  # the first solve captures graphs
                 x = torch.zeros_like(b)
                 st = sem.sem_pcg_solve(h, b, x, rtol=1e-8, maxit=50000, pc=pc,
@@ -180,19 +190,31 @@ def bench_learned(sem, torch):
             o["iters"].append(st["iters"])
             o["fell_back"].append(st["fell_back"])
             o["final_rel_res"].append(st["final_rel_res"])
+            if xref is None:
+                xref = x
+            else:
+                diffs.append(float(torch.linalg.norm(x - xref) /
+                                   torch.linalg.norm(xref)))
             log(f"[learned] rhs {seed} {name}: {st}")
     for name in out:
         ts = sorted(out[name]["time_s"])
         out[name]["median_time_s"] = ts[len(ts) // 2]
-    out["speedup_learned_mixed_vs_fp64"] = (
-        out["fp64_jacobi_pcg"]["median_time_s"] /
-        out["fp32_ir_learned"]["median_time_s"])
+        its = sorted(out[name]["iters"])
+        out[name]["median_iters"] = its[len(its) // 2]
+    base = out["fp64_jacobi_pcg"]["median_time_s"]
+    out["speedup_vs_fp64_jacobi"] = {
+        name: base / out[name]["median_time_s"] for name, *_ in cases}
+    out["max_rel_diff_vs_fp64_jacobi_solution"] = max(diffs) if diffs else None
     out["train"] = rep
-    out["workload"] = ("24^3 elements, N=7, kappa=exp(GRF l=0.1 sigma=1), "
-                       f"{nL} local / {nG} unique nodes")
+    out["workload"] = ("24^3 elements, N=7, affine, kappa=exp(GRF l=0.1 sigma=1, "
+                       f"4096 RFF), {nL} local / {nG} unique nodes; coarse "
+                       f"layout network 8-128-128-{K * (K + 1) // 2} (K={K} "
+                       "bubble modes); 8 training RHS (seeds 100..107), "
+                       f"{n_test} held-out RHS (seeds 900..)")
     out["setup_s"] = setup_s
     sem.sem_learn_attach(h, None)
     sem.sem_mlp_destroy(net)
+    sem.sem_mlp_destroy(untrained)
     sem.sem_destroy(h)
     return out
 

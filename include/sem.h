@@ -289,6 +289,15 @@ sem_status sem_mlp_forward(sem_mlp *net, const uint16_t *X, int32_t ldx,
 sem_status sem_mlp_loss_grad(sem_mlp *net, const uint16_t *X, int32_t ldx,
                              const float *T, int32_t B, int32_t N, float *grad,
                              double *loss, void *stream);
+/* Loss and gradient of the coarse layout's factor output (n_out = K(K+1)/2,
+ * K in {1, 8, 27}): per sample, T (device FP32 [B][2K]) holds y and alpha*;
+ * the network output is the row-major packed lower triangle of L and the
+ * loss is the mean over samples and components of (L L^T y - alpha*)^2.
+ * grad and loss as for sem_mlp_loss_grad. */
+sem_status sem_mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X,
+                                    int32_t ldx, const float *T, int32_t K,
+                                    int32_t B, float *grad, double *loss,
+                                    void *stream);
 /* One Adam step (Kingma & Ba 2015) on the master parameters with device
  * gradient grad (NULL: the last sem_mlp_loss_grad gradient). */
 sem_status sem_mlp_adam(sem_mlp *net, const float *grad, double lr,
@@ -305,8 +314,16 @@ sem_status sem_mlp_load(const char *path, sem_mlp **out);
 
 /* Attach a network (NULL detaches) to a handle for SEM_PC_LEARNED; the
  * network must outlive the attachment.  Its shape selects the layout:
- * n_in = (N+1)^3 + 8 with n_out = 8 (Q1) or (N+1)^3 (nodal), or
- * n_in = (N-1)^3 + 8 with n_out = (N-1)^3 (interior, N >= 2). */
+ * n_in = (N+1)^3 + 8 with n_out = 8 (Q1) or (N+1)^3 (nodal);
+ * n_in = (N-1)^3 + 8 with n_out = (N-1)^3 (interior, N >= 2);
+ * n_in = 8 with n_out = K(K+1)/2, K = (min(2, N-2) + 1)^3 (coarse, N >= 2):
+ * the network maps the element's 8 log-kappa vertex deviations to a factor
+ * L of its coarse operator M_e = L L^T / (kappa_e h_e) in the interior
+ * bubble basis B (tensor products of (1 - x^2) P_a(x), a <= min(2, N-2), at
+ * the interior nodes), and the correction is damping B M_e B^T r_I on the
+ * interior nodes (symmetric positive semi-definite).  The coarse operators
+ * are computed from the network when it is attached and again before a
+ * solve when its parameters have changed. */
 sem_status sem_learn_attach(sem_handle *h, sem_mlp *net);
 
 typedef struct {
@@ -331,7 +348,7 @@ typedef struct {
   double jacobi_rate;             /* Jacobi-PCG log10 residual drop / iteration */
   int32_t val_iters_jacobi, val_iters_learned;  /* validation solve to 1e-6 */
   int32_t val_iters[4];   /* learned iterations for the damping candidates
-                             1, 0.75, 0.5, 0.25 (interior layout) or 0.2,
+                             1, 0.75, 0.5, 0.25 (interior, coarse) or 0.2,
                              0.15, 0.1, 0.05 (Q1, nodal); -1: not converged
                              or fell back */
 } sem_train_report;
@@ -339,15 +356,29 @@ typedef struct {
 /* Generate training pairs with the FP64 solver and train the network on the
  * GPU.  For every right-hand side b_L[q] (device FP64 E-vectors) a FP64
  * Jacobi-PCG solve from x = 0 records snapshots x_k, r_k; residuals
- * restricted to random elements give the features.  Targets: Q1 and nodal
+ * restricted to random elements give the pairs.  Targets: Q1 and nodal
  * layouts, the element error (x* - x_k)_e kappa_e h_e / s_e of the
  * converged solve; interior layout, the element-interior solve of
- * sem_learn_interior_pairs.  Training: epochs of
+ * sem_learn_interior_pairs; coarse layout, y = B^T r_I / ||B^T r_I|| (for
+ * half the pairs, chosen at random, a random unit direction instead, so that
+ * every direction of the operator is trained) and alpha* = M_e y with the
+ * exact M_e of sem_learn_coarse_exact; a coarse-layout network that has never
+ * taken an Adam step first starts from the identity factor (output bias =
+ * packed identity, output weights scaled by 0.01).  Training: epochs of
  * shuffled minibatches of forward, loss, backward and Adam, all on the GPU.
  * Then the damping is validated on the last right-hand side (see above). */
 sem_status sem_learn_train(sem_handle *h, sem_mlp *net, const double *const *b_L,
                            int32_t n_rhs, const sem_train_opts *opts,
                            sem_train_report *report, void *stream);
+
+/* Exact normalised coarse inverses of the coarse layout (the definition of
+ * its training targets, exposed for checking): M[e] (device FP64
+ * [E][K][K]) = kappa_e h_e (B^T A_II,e B)^{-1}, computed on the GPU by
+ * applying the element operator to the K bubble columns and inverting the
+ * K x K Galerkin matrix by Cholesky (NaN if it is not positive definite).
+ * *K receives K.  Synchronises the stream.  N in 2..8. */
+sem_status sem_learn_coarse_exact(sem_handle *h, double *M, int32_t *K,
+                                  void *stream);
 
 /* Training pairs of the interior layout for one residual (the definition
  * of the training targets, exposed for checking): for each of the n

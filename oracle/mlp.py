@@ -33,6 +33,21 @@ inverse.  The preconditioner z = dinv r + c then reproduces the
 element-interior block solve where the network is exact.  Interior nodes
 belong to one element only, so no averaging is involved.
 
+Coarse layout (a learned element coarse operator): with the interior
+"bubble" basis b_a(xi) = (1 - xi^2) P_a(xi), a = 0..p (P_a Legendre,
+p = min(2, N - 2)), B[(i,j,k)][(a,b,c)] = b_a(xi_i) b_b(xi_j) b_c(xi_k) on
+the interior nodes (K = (p+1)^3 columns, each scaled by the square root of
+the matching diagonal entry of the unit reference element's coarse inverse
+so that every mode is O(1)), the element's Galerkin coarse
+matrix is G_e = B^T A_II B and its exact coarse correction
+c_I = B G_e^{-1} B^T r_I.  The network sees only the 8 log-kappa vertex
+deviations and outputs a lower-triangular factor L (row-major packed,
+K(K+1)/2 values); M = L L^T approximates kappa_mean h G_e^{-1}, so the
+correction B (M / (kappa_mean h)) B^T r_I is symmetric positive
+semi-definite for any network.  Training pairs come from solver residuals:
+y = B^T r_I / ||B^T r_I||, target alpha* = kappa_mean h G_e^{-1} y, loss
+mean (L L^T y - alpha*)^2.
+
 Parity status: forward/backward pinned by central finite differences and by
 the linear-network closed form; Adam pinned by its first-step closed form;
 prolongation pinned by exact reproduction of trilinear functions.  Trained
@@ -109,6 +124,14 @@ def loss_and_grad(theta, X, T, P, n_in, n_hidden, n_out):
     loss = float(np.sum(diff * diff) / (B * nn))
     dY = 2.0 * diff / (B * nn)          # d loss / d (P o)
     do = dY @ P                          # B x n_out
+    return loss, backward(theta, (X, z1, h1, z2, h2), do, n_in, n_hidden, n_out)
+
+
+def backward(theta, acts, do, n_in, n_hidden, n_out):
+    """Parameter gradient from the output gradient do (B x n_out) and the
+    activations kept by forward(..., keep=True)."""
+    W1, b1, W2, b2, W3, b3 = unpack(theta, n_in, n_hidden, n_out)
+    X, z1, h1, z2, h2 = acts
     dW3 = do.T @ h2
     db3 = do.sum(axis=0)
     dh2 = do @ W3
@@ -119,7 +142,7 @@ def loss_and_grad(theta, X, T, P, n_in, n_hidden, n_out):
     dz1 = dh1 * (z1 > 0)
     dW1 = dz1.T @ X
     db1 = dz1.sum(axis=0)
-    return loss, pack([dW1, db1, dW2, db2, dW3, db3])
+    return pack([dW1, db1, dW2, db2, dW3, db3])
 
 
 def adam_step(theta, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -216,3 +239,97 @@ def interior_correction(o, s, kappa_vertices, h, N, damping=1.0):
     kbar = float(np.mean(np.asarray(kappa_vertices, dtype=np.float64)))
     c[interior_nodes(N)] = damping * s / (kbar * h) * np.asarray(o, dtype=np.float64)
     return c
+
+
+def coarse_degree(N):
+    """Polynomial degree p of the bubble basis (K = (p+1)^3 columns)."""
+    return min(2, N - 2)
+
+
+def bubble_basis(N, xi, scaled=True):
+    """B [(N-1)^3][(p+1)^3]: tensor products of b_a(x) = (1 - x^2) P_a(x) at
+    the interior GLL nodes; rows in interior lexicographic order (i fastest),
+    columns (a, b, c) with a fastest.  scaled: every column is multiplied by
+    sqrt of the matching diagonal entry of the reference coarse inverse
+    (G_ref^{-1} of the unit-cube element with kappa = 1, whose kappa h is 1),
+    which makes the normalised coarse inverses O(1) in every mode."""
+    from numpy.polynomial import legendre as leg
+    p = coarse_degree(N)
+    xin = np.asarray(xi, dtype=np.float64)[1:N]
+    B1 = np.stack([(1 - xin ** 2) * leg.legval(xin, np.eye(p + 1)[a])
+                   for a in range(p + 1)], 1)
+    # row (i, j, k) = i + m j + m^2 k and column (a, b, c) = a + q b + q^2 c
+    B = np.kron(B1, np.kron(B1, B1))
+    if not scaled:
+        return B
+    from . import oracle as orc
+    ref = orc.mesh(N, 1, 1, 1, orc.MAP_AFFINE, 0, None)
+    I = interior_nodes(N)
+    A_II = orc.brute_element_matrix(N, ref.xi, ref.G[0])[np.ix_(I, I)]
+    Mref = np.linalg.inv(B.T @ A_II @ B)
+    return B * np.sqrt(np.diag(Mref))[None, :]
+
+
+def coarse_galerkin(A_e, N, xi):
+    """G_e = B^T A_II B from the element stiffness A_e (n1^3 x n1^3)."""
+    I = interior_nodes(N)
+    B = bubble_basis(N, xi)
+    A_II = np.asarray(A_e, dtype=np.float64)[np.ix_(I, I)]
+    return B.T @ A_II @ B
+
+
+def coarse_target(A_e, N, xi, kappa_vertices, h):
+    """kappa_mean h G_e^{-1}: the normalised exact coarse inverse."""
+    G = coarse_galerkin(A_e, N, xi)
+    kbar = float(np.mean(np.asarray(kappa_vertices, dtype=np.float64)))
+    return np.linalg.inv(G) * kbar * h
+
+
+def factor_unpack(o, K):
+    """Lower-triangular L from K(K+1)/2 row-major packed values."""
+    L = np.zeros((K, K))
+    L[np.tril_indices(K)] = np.asarray(o, dtype=np.float64)
+    return L
+
+
+def factor_loss_and_grad(O, Y, Astar):
+    """Mean over samples and components of (L L^T y - alpha*)^2 and its
+    gradient with respect to the packed outputs O [S][K(K+1)/2]."""
+    O = np.asarray(O, dtype=np.float64)
+    S = O.shape[0]
+    K = Y.shape[1]
+    tri = np.tril_indices(K)
+    loss = 0.0
+    dO = np.zeros_like(O)
+    for s_ in range(S):
+        L = factor_unpack(O[s_], K)
+        y = Y[s_]
+        v = L.T @ y
+        a = L @ v
+        d = a - Astar[s_]
+        loss += float(d @ d)
+        g = 2.0 * d / (S * K)
+        dL = np.outer(g, v) + np.outer(y, L.T @ g)
+        dO[s_] = dL[tri]
+    return loss / (S * K), dO
+
+
+def coarse_correction(r_e, M_e, N, xi, kappa_vertices, h, damping=1.0):
+    """Correction on the element's n1^3 nodes: damping B (M / (kappa_mean
+    h)) B^T r_I on the interior nodes, zero on the faces."""
+    I = interior_nodes(N)
+    B = bubble_basis(N, xi)
+    kbar = float(np.mean(np.asarray(kappa_vertices, dtype=np.float64)))
+    c = np.zeros((N + 1) ** 3)
+    r_I = np.asarray(r_e, dtype=np.float64)[I]
+    c[I] = damping * (B @ (np.asarray(M_e) @ (B.T @ r_I))) / (kbar * h)
+    return c
+
+
+def factor_net_loss_and_grad(theta, X, Y, Astar, n_in, n_hidden, K):
+    """Factor loss of the coarse layout through the network: outputs
+    O = forward(X) are the packed factors; returns (loss, gradient)."""
+    n_out = K * (K + 1) // 2
+    O, acts = forward(theta, X, n_in, n_hidden, n_out, keep=True)
+    loss, dO = factor_loss_and_grad(O, Y, Astar)
+    return loss, backward(theta, acts, dO, n_in, n_hidden, n_out)

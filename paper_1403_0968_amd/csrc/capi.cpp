@@ -335,6 +335,24 @@ sem_status sem_mlp_loss_grad(sem_mlp *net, const uint16_t *X, int32_t ldx,
   });
 }
 
+sem_status sem_mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X,
+                                    int32_t ldx, const float *T, int32_t K,
+                                    int32_t B, float *grad, double *loss,
+                                    void *stream) {
+  return guarded([&] {
+    need(net != nullptr && X != nullptr && T != nullptr && B >= 1,
+         "sem_mlp_loss_grad_factor: null argument or empty batch");
+    const double l = mlp_loss_grad_factor(net, X, ldx, T, K, B, true, strm(stream));
+    if (loss) *loss = l;
+    if (grad) {
+      int64_t np = 0;
+      mlp_info(net, nullptr, nullptr, nullptr, &np, nullptr);
+      SEM_HIP(hipMemcpyAsync(grad, mlp_grad_ptr(net), np * 4,
+                             hipMemcpyDeviceToDevice, strm(stream)));
+    }
+  });
+}
+
 sem_status sem_mlp_adam(sem_mlp *net, const float *grad, double lr,
                         double beta1, double beta2, double eps, void *stream) {
   return guarded([&] {
@@ -403,6 +421,15 @@ sem_status sem_learn_interior_pairs(sem_handle *h, const double *r_L,
   return guarded([&] {
     need(h != nullptr, "sem_learn_interior_pairs: null handle");
     learn_interior_pairs(h, r_L, elems, n, X, ldx, T, rtol, iters, strm(stream));
+  });
+}
+
+sem_status sem_learn_coarse_exact(sem_handle *h, double *M, int32_t *K,
+                                  void *stream) {
+  return guarded([&] {
+    need(h != nullptr && M != nullptr, "sem_learn_coarse_exact: null argument");
+    const int k = learn_coarse_exact(h, M, strm(stream));
+    if (K) *K = k;
   });
 }
 

@@ -9,7 +9,10 @@
 //   nodal    n_in = n3 + 8, n_out = n3: one value per node; targets from the
 //            global error;
 //   interior n_in = ni + 8, n_out = ni: one value per element-interior node
-//            (1 <= i, j, k <= N-1); targets from the element-interior solve.
+//            (1 <= i, j, k <= N-1); targets from the element-interior solve;
+//   coarse   n_in = 8, n_out = K(K+1)/2: a lower-triangular factor L of the
+//            element's coarse operator in the interior bubble basis (below);
+//            trained on residual pairs against the exact Galerkin inverse.
 // Features of element e (residual r on unique nodes): r_f = r at the
 // feature nodes (all nodes, or the interior ones), s_e = ||r_f||_2,
 // x = [r_f / s_e, log kappa at the 8 vertices minus their mean, 0 ...].
@@ -17,6 +20,13 @@
 // the element's nodes (prolonged, nodal, or interior with zero faces),
 // kappa_e the mean of the vertex values and h_e the element size; the solver
 // averages c over the copies of every node (interior nodes have one).
+// Coarse layout: bubble basis b_a(x) = (1 - x^2) P_a(x), a = 0..p,
+// p = min(2, N-2), B = tensor products on the interior nodes (K = (p+1)^3
+// columns); the exact element coarse correction is B G_e^{-1} B^T r_I with
+// G_e = B^T A_II B.  The network maps the 8 log-kappa vertex deviations to
+// L with M_e = L L^T ~ kappa_e h_e G_e^{-1}, and the correction
+// c_I = damping B (M_e / (kappa_e h_e)) B^T r_I is symmetric positive
+// semi-definite whatever the network outputs.
 // Targets, scaled by kappa_e h_e / s_e so that input and target are O(1):
 //   global error: the element error x* - x_k of a snapshot;
 //   interior: d - dinv r_I, with d the solution of the element's interior
@@ -34,11 +44,18 @@
 
 namespace sem {
 
-enum { LM_Q1 = 0, LM_NODAL = 1, LM_INTERIOR = 2 };
+enum { LM_Q1 = 0, LM_NODAL = 1, LM_INTERIOR = 2, LM_COARSE = 3 };
 
 struct Learn {
   int ldx = 0, n3 = 0, n_out = 0, ldo = 0;
   int mode = LM_NODAL, nf = 0, nt = 0;  // layout, feature nodes, target width
+  // coarse layout: basis B [ni][K] (FP32 and FP64), kappa features of every
+  // element (BF16 [E][ldx]), element operators M_e / (kappa_e h_e) (FP32
+  // [E][K][K]) for the network of version mver
+  int K = 0, ni = 0;
+  DevBuf Bf, Bd, Xk, Ml;
+  const sem_mlp *mnet = nullptr;
+  uint64_t mver = 0;
   DevBuf X, s, O, kfeat, invkh, cL, h1, h2;  // h1, h2: hidden activations
 };
 
@@ -149,6 +166,235 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// sum over the workgroup, returned to every thread (fixed order: the wave
+// butterfly leaves identical bits in every lane, then the waves in order)
+template <int NT>
+__device__ inline double block_allsum(double v, double *red /* NT / 64 */) {
+  v = wave_sum(v);
+  if constexpr (NT == 64) return v;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();  // earlier readers of red are done
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) t += red[q];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// coarse layout kernels
+// ---------------------------------------------------------------------------
+// interior index q of local node (i, j, k), or -1 on the element's faces
+__device__ inline int interior_index(int i, int j, int k, int n1) {
+  const int N = n1 - 1, m = N - 1;
+  if (i < 1 || i >= N || j < 1 || j >= N || k < 1 || k >= N) return -1;
+  return (i - 1) + m * ((j - 1) + m * (k - 1));
+}
+
+// Exact normalised coarse inverses, one workgroup per element: for every
+// bubble column b_k the element operator (shared element routine, FP64,
+// zero face values) gives A_II b_k through the element's scratch rows U, W;
+// column k of G_e = B^T A_II B is reduced over the workgroup; thread 0 then
+// inverts the symmetrised G_e by Cholesky and stores kappa_e h_e G_e^{-1}.
+// A G_e that is not positive definite is stored as NaN.
+template <int N1, int NT>
+__global__ void __launch_bounds__(NT)
+    k_coarse_exact(int64_t E, const double *__restrict__ G,
+                   const double *__restrict__ D, const double *__restrict__ Bd,
+                   int K, double *__restrict__ U, double *__restrict__ W,
+                   const double *__restrict__ kv, double hsz,
+                   double *__restrict__ Mex) {
+  constexpr int NP = N1 * N1, N3 = NP * N1, N = N1 - 1;
+  __shared__ double smem[lds_words<N1>(1)];
+  __shared__ double red[NT / 64];
+  __shared__ double Gs[27 * 27];
+  const int64_t e = blockIdx.x;
+  if (e >= E) return;  // uniform
+  const int t = threadIdx.x;
+  const bool act = t < NP;
+  const int c = act ? t : 0;
+  const int i = c % N1, j = c / N1;
+  double *u = U + e * N3, *w = W + e * N3;
+  for (int kb = 0; kb < K; ++kb) {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      const int q = act ? interior_index(i, j, k, N1) : -1;
+      if (act) u[c + k * NP] = q >= 0 ? Bd[q * K + kb] : 0.0;
+    }
+    ax_tile<N1, 1, double, double, double, double, false, false>(
+        t, 0, 1, D, G + e * 6 * N3, u, w, nullptr, smem);
+    double wc[N1];
+    int qc[N1];
+#pragma unroll
+    for (int k = 0; k < N1; ++k) {
+      qc[k] = act ? interior_index(i, j, k, N1) : -1;
+      wc[k] = qc[k] >= 0 ? w[c + k * NP] : 0.0;  // this thread's own column
+    }
+    for (int jb = 0; jb < K; ++jb) {
+      double a = 0.0;
+#pragma unroll
+      for (int k = 0; k < N1; ++k)
+        if (qc[k] >= 0) a += Bd[qc[k] * K + jb] * wc[k];
+      a = block_allsum<NT>(a, red);
+      if (t == 0) Gs[jb * K + kb] = a;
+    }
+  }
+  __syncthreads();
+  if (t != 0) return;  // no barrier follows
+  (void)N;
+  // Cholesky of the symmetrised G_e in the lower triangle of Gs
+  bool ok = true;
+  for (int a = 0; a < K; ++a)
+    for (int b = 0; b < a; ++b) {
+      const double v = 0.5 * (Gs[a * K + b] + Gs[b * K + a]);
+      Gs[a * K + b] = v;
+      Gs[b * K + a] = v;
+    }
+  for (int jj = 0; jj < K && ok; ++jj) {
+    double d = Gs[jj * K + jj];
+    for (int k = 0; k < jj; ++k) d -= Gs[jj * K + k] * Gs[jj * K + k];
+    if (!(d > 0.0)) {
+      ok = false;
+      break;
+    }
+    const double ljj = sqrt(d);
+    Gs[jj * K + jj] = ljj;
+    for (int ii = jj + 1; ii < K; ++ii) {
+      double v = Gs[ii * K + jj];
+      for (int k = 0; k < jj; ++k) v -= Gs[ii * K + k] * Gs[jj * K + k];
+      Gs[ii * K + jj] = v / ljj;
+    }
+  }
+  double kbar = 0.0;
+  for (int v = 0; v < 8; ++v) kbar += kv[e * 8 + v] / 8.0;
+  const double scale = kbar * hsz;  // kappa_e h_e
+  double *Me = Mex + e * K * K;
+  for (int col = 0; col < K; ++col) {
+    double y[27];
+    for (int ii = 0; ii < K; ++ii) {  // L y = e_col
+      double v = ii == col ? 1.0 : 0.0;
+      for (int k = 0; k < ii; ++k) v -= Gs[ii * K + k] * y[k];
+      y[ii] = v / Gs[ii * K + ii];
+    }
+    for (int ii = K - 1; ii >= 0; --ii) {  // L^T x = y
+      double v = y[ii];
+      for (int k = ii + 1; k < K; ++k) v -= Gs[k * K + ii] * y[k];
+      y[ii] = v / Gs[ii * K + ii];
+    }
+    for (int ii = 0; ii < K; ++ii) Me[ii * K + col] = ok ? y[ii] * scale : NAN;
+  }
+}
+
+// coarse training pairs, one 64-thread workgroup per pair: y = B^T r_I /
+// ||B^T r_I|| from the snapshot residual or, where piso[p] is set, the
+// caller's random unit vector yr[p] (so that every direction of the K x K
+// operator is constrained, not only those the residuals excite);
+// alpha* = Mex_e y; T[p] = [y, alpha*] (FP32), X[p] = the element's kappa
+// features (BF16, zero padding)
+__global__ void __launch_bounds__(64)
+    k_coarse_pairs(int np, const int32_t *__restrict__ psnap,
+                   const int32_t *__restrict__ pelem, int64_t nG, int n1,
+                   const int32_t *__restrict__ l2g, const double *__restrict__ rs,
+                   const double *__restrict__ Bd, int K, int ni,
+                   const double *__restrict__ Mex, const float *__restrict__ kf,
+                   const int32_t *__restrict__ piso, const double *__restrict__ yr,
+                   uint16_t *__restrict__ X, int ldx, float *__restrict__ T) {
+  __shared__ double rI[343];
+  __shared__ double y[27];
+  const int p = blockIdx.x;
+  if (p >= np) return;
+  const int t = threadIdx.x;
+  const int n3 = n1 * n1 * n1, m = n1 - 2;
+  const int64_t e = pelem[p];
+  const double *r = rs + (int64_t)psnap[p] * nG;
+  const bool iso = piso[p] != 0;  // uniform per block
+  if (!iso)
+    for (int q = t; q < ni; q += 64) {
+      const int i = q % m + 1, j = (q / m) % m + 1, k = q / (m * m) + 1;
+      rI[q] = r[l2g[e * n3 + i + n1 * (j + n1 * k)]];
+    }
+  __syncthreads();
+  double yj = 0.0;
+  if (t < K) {
+    if (iso)
+      yj = yr[(size_t)p * K + t];
+    else
+      for (int q = 0; q < ni; ++q) yj += Bd[q * K + t] * rI[q];
+  }
+  const double nrm = sqrt(wave_sum(yj * yj));
+  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+  if (t < K) y[t] = yj * inv;
+  __syncthreads();
+  float *tp = T + (size_t)p * 2 * K;
+  if (t < K) {
+    double a = 0.0;
+    for (int jj = 0; jj < K; ++jj) a += Mex[(e * K + t) * K + jj] * y[jj];
+    tp[t] = (float)y[t];
+    tp[K + t] = (float)a;
+  }
+  uint16_t *xp = X + (size_t)p * ldx;
+  for (int q = t; q < ldx; q += 64)
+    xp[q] = q < 8 ? f32_to_bf16(kf[e * 8 + q]) : (uint16_t)0;
+}
+
+// element operators from the network outputs: M_e = invkh_e L L^T
+__global__ void __launch_bounds__(256)
+    k_factor_to_M(int64_t E, int K, const float *__restrict__ O, int ldo,
+                  const float *__restrict__ invkh, float *__restrict__ Ml) {
+  const int64_t e = blockIdx.x;
+  const float *o = O + e * ldo;
+  const float sc = invkh[e];
+  for (int ab = threadIdx.x; ab < K * K; ab += 256) {
+    const int a = ab / K, b = ab % K, lo = a < b ? a : b;
+    float v = 0.f;
+    for (int c = 0; c <= lo; ++c) v += o[a * (a + 1) / 2 + c] * o[b * (b + 1) / 2 + c];
+    Ml[e * K * K + ab] = sc * v;
+  }
+}
+
+// correction of the coarse layout on every element:
+// cL = damping B M_e B^T r_I on the interior nodes, 0 on the faces; r on
+// unique nodes (through l2g) or, with l2g NULL, a continuous E-vector
+template <class TV>
+__global__ void __launch_bounds__(64)
+    k_coarse_apply(int64_t E, int n1, int ni, int K,
+                   const int32_t *__restrict__ l2g, const TV *__restrict__ r,
+                   const float *__restrict__ Bf, const float *__restrict__ Ml,
+                   const float *__restrict__ damping, float *__restrict__ cL) {
+  __shared__ float rI[343];
+  __shared__ float y[27], al[27];
+  const int64_t e = blockIdx.x;
+  const int t = threadIdx.x;
+  const int n3 = n1 * n1 * n1, m = n1 - 2;
+  for (int q = t; q < ni; q += 64) {
+    const int i = q % m + 1, j = (q / m) % m + 1, k = q / (m * m) + 1;
+    const int64_t l = e * n3 + i + n1 * (j + n1 * k);
+    rI[q] = (float)r[l2g ? (int64_t)l2g[l] : l];
+  }
+  __syncthreads();
+  if (t < K) {
+    float a = 0.f;
+    for (int q = 0; q < ni; ++q) a += Bf[q * K + t] * rI[q];
+    y[t] = a;
+  }
+  __syncthreads();
+  if (t < K) {
+    float a = 0.f;
+    const float *Me = Ml + e * K * K + t * K;
+    for (int jj = 0; jj < K; ++jj) a += Me[jj] * y[jj];
+    al[t] = damping[0] * a;
+  }
+  __syncthreads();
+  for (int p = t; p < n3; p += 64) {
+    const int q = interior_index(p % n1, (p / n1) % n1, p / (n1 * n1), n1);
+    float c = 0.f;
+    if (q >= 0)
+      for (int jj = 0; jj < K; ++jj) c += Bf[q * K + jj] * al[jj];
+    cL[e * n3 + p] = c;
+  }
+}
+
 static double elem_size(const sem_handle *h) {
   return std::cbrt((1.0 / h->ex) * (1.0 / h->ey) * (1.0 / h->ez));
 }
@@ -168,13 +414,119 @@ static int layout_of(const sem_handle *h, const sem_mlp *net) {
   if (n_in == n3 + 8 && n_out == 8) return LM_Q1;
   if (n_in == n3 + 8 && n_out == n3) return LM_NODAL;
   if (ni > 0 && n_in == ni + 8 && n_out == ni) return LM_INTERIOR;
+  if (ni > 0) {
+    const int q = std::min(2, h->N - 2) + 1, K = q * q * q;
+    if (n_in == 8 && n_out == K * (K + 1) / 2) return LM_COARSE;
+  }
   fail(SEM_ERR_ARG, "learned correction: the network needs n_in = (N+1)^3 + 8 "
                     "and n_out = 8 or (N+1)^3, or n_in = (N-1)^3 + 8 and "
-                    "n_out = (N-1)^3 (N >= 2)");
+                    "n_out = (N-1)^3, or n_in = 8 and n_out = K(K+1)/2 with "
+                    "K = (min(2, N-2)+1)^3 (N >= 2)");
 }
 
 static void check_net(const sem_handle *h, const sem_mlp *net) {
   (void)layout_of(h, net);
+}
+
+// inverse of a small dense matrix (Gauss-Jordan with partial pivoting, FP64)
+static std::vector<double> small_inverse(std::vector<double> A, int n) {
+  std::vector<double> X((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) X[(size_t)i * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)piv * n + c])) piv = r;
+    if (!(std::fabs(A[(size_t)piv * n + c]) > 0.0))
+      fail(SEM_ERR_STATE, "coarse layout: singular reference coarse matrix");
+    for (int k = 0; k < n; ++k) {
+      std::swap(A[(size_t)c * n + k], A[(size_t)piv * n + k]);
+      std::swap(X[(size_t)c * n + k], X[(size_t)piv * n + k]);
+    }
+    const double d = A[(size_t)c * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[(size_t)c * n + k] /= d;
+      X[(size_t)c * n + k] /= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = A[(size_t)r * n + c];
+      for (int k = 0; k < n; ++k) {
+        A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+        X[(size_t)r * n + k] -= f * X[(size_t)c * n + k];
+      }
+    }
+  }
+  return X;
+}
+
+// bubble basis on the host (FP64): B[q][col], q = interior node (i fastest),
+// col = a + q1 b + q1^2 c, b_a(x) = (1 - x^2) P_a(x), a <= 2, every column
+// scaled by sqrt of the matching diagonal entry of the reference coarse
+// inverse.  Reference: the unit cube with kappa = 1 (kappa h = 1), whose
+// stiffness is (1/2)(A1 x W x W + W x A1 x W + W x W x A1) with the 1D
+// matrices W = diag(w) and A1 = D^T W D, so that in the bubble basis
+// G_ref = (1/2)(Kb x Mb x Mb + Mb x Kb x Mb + Mb x Mb x Kb), Mb = B1^T W B1,
+// Kb = B1^T A1 B1 (interior rows and columns).
+static std::vector<double> bubble_basis(const sem_handle *h, int &K) {
+  const int N = h->N, n1 = h->n1, m = N - 1, q1 = std::min(2, N - 2) + 1;
+  K = q1 * q1 * q1;
+  std::vector<double> B1((size_t)m * q1), B((size_t)m * m * m * K);
+  for (int i = 0; i < m; ++i) {
+    const double x = h->ref.xi[i + 1];
+    const double P[3] = {1.0, x, 0.5 * (3.0 * x * x - 1.0)};
+    for (int a = 0; a < q1; ++a) B1[(size_t)i * q1 + a] = (1.0 - x * x) * P[a];
+  }
+  std::vector<double> Mb((size_t)q1 * q1, 0.0), Kb((size_t)q1 * q1, 0.0);
+  for (int a = 0; a < q1; ++a)
+    for (int b = 0; b < q1; ++b) {
+      double mm = 0.0, kk = 0.0;
+      for (int i = 0; i < m; ++i)
+        mm += B1[(size_t)i * q1 + a] * h->ref.w[i + 1] * B1[(size_t)i * q1 + b];
+      for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+          double a1 = 0.0;  // (D^T W D)[i+1][j+1]
+          for (int r = 0; r < n1; ++r)
+            a1 += h->ref.D[(size_t)r * n1 + i + 1] * h->ref.w[r] *
+                  h->ref.D[(size_t)r * n1 + j + 1];
+          kk += B1[(size_t)i * q1 + a] * a1 * B1[(size_t)j * q1 + b];
+        }
+      Mb[(size_t)a * q1 + b] = mm;
+      Kb[(size_t)a * q1 + b] = kk;
+    }
+  std::vector<double> Gr((size_t)K * K);
+  for (int c = 0; c < q1; ++c)
+    for (int b = 0; b < q1; ++b)
+      for (int a = 0; a < q1; ++a)
+        for (int c2 = 0; c2 < q1; ++c2)
+          for (int b2 = 0; b2 < q1; ++b2)
+            for (int a2 = 0; a2 < q1; ++a2) {
+              const double ma = Mb[a * q1 + a2], mb = Mb[b * q1 + b2],
+                           mc = Mb[c * q1 + c2], ka = Kb[a * q1 + a2],
+                           kb = Kb[b * q1 + b2], kc = Kb[c * q1 + c2];
+              Gr[(size_t)(a + q1 * (b + q1 * c)) * K + a2 + q1 * (b2 + q1 * c2)] =
+                  0.5 * (ka * mb * mc + ma * kb * mc + ma * mb * kc);
+            }
+  const std::vector<double> Mr = small_inverse(Gr, K);
+  std::vector<double> sc(K);
+  for (int k = 0; k < K; ++k) sc[k] = std::sqrt(Mr[(size_t)k * K + k]);
+  for (int k = 0; k < m; ++k)
+    for (int j = 0; j < m; ++j)
+      for (int i = 0; i < m; ++i)
+        for (int c = 0; c < q1; ++c)
+          for (int b = 0; b < q1; ++b)
+            for (int a = 0; a < q1; ++a)
+              B[((size_t)(i + m * (j + m * k))) * K + a + q1 * (b + q1 * c)] =
+                  B1[(size_t)i * q1 + a] * B1[(size_t)j * q1 + b] *
+                  B1[(size_t)k * q1 + c] * sc[a + q1 * (b + q1 * c)];
+  return B;
+}
+
+// every element's kappa features as a network input row (BF16, zero padding)
+__global__ void k_kfeat_rows(int64_t E, const float *__restrict__ kf,
+                             uint16_t *__restrict__ X, int ldx) {
+  const int64_t e = blockIdx.x;
+  for (int q = threadIdx.x; q < ldx; q += blockDim.x)
+    X[e * ldx + q] = q < 8 ? f32_to_bf16(kf[e * 8 + q]) : (uint16_t)0;
 }
 
 static void kappa_features(const sem_handle *h, DevBuf &kfeat, DevBuf &invkh) {
@@ -204,6 +556,19 @@ static void ensure_learn(sem_handle *h, const sem_mlp *net) {
     L->mode = mode;
     L->nf = mode == LM_INTERIOR ? n_out : L->n3;
     L->nt = mode == LM_INTERIOR ? n_out : L->n3;
+    if (mode == LM_COARSE) {
+      const int m = h->N - 1;
+      L->ni = m * m * m;
+      std::vector<double> Bd = bubble_basis(h, L->K);
+      std::vector<float> Bf(Bd.begin(), Bd.end());
+      L->nf = 0;
+      L->nt = 2 * L->K;
+      L->Bd.alloc(Bd.size() * 8);
+      SEM_HIP(hipMemcpy(L->Bd.p, Bd.data(), Bd.size() * 8, hipMemcpyHostToDevice));
+      L->Bf.alloc(Bf.size() * 4);
+      SEM_HIP(hipMemcpy(L->Bf.p, Bf.data(), Bf.size() * 4, hipMemcpyHostToDevice));
+      L->Ml.alloc((size_t)h->E * L->K * L->K * 4);
+    }
     L->ldo = n_out > 16 ? n_out : 16;
     L->X.alloc((size_t)h->E * ldx * 2);
     SEM_HIP(hipMemset(L->X.p, 0, (size_t)h->E * ldx * 2));  // zero padding
@@ -213,6 +578,12 @@ static void ensure_learn(sem_handle *h, const sem_mlp *net) {
     L->h1.alloc((size_t)h->E * 128 * 2);
     L->h2.alloc((size_t)h->E * 128 * 2);
     kappa_features(h, L->kfeat, L->invkh);
+    if (mode == LM_COARSE) {
+      L->Xk.alloc((size_t)h->E * ldx * 2);
+      hipLaunchKernelGGL(k_kfeat_rows, dim3((unsigned)h->E), dim3(64), 0, 0, h->E,
+                         L->kfeat.as<float>(), L->Xk.as<uint16_t>(), ldx);
+      SEM_HIP(hipGetLastError());
+    }
     SEM_HIP(hipDeviceSynchronize());
   } catch (...) {
     delete L;
@@ -223,6 +594,23 @@ static void ensure_learn(sem_handle *h, const sem_mlp *net) {
 
 void drop_graphs(sem_handle *h);
 
+// coarse layout: (re)compute the element operators M_e from the attached
+// network when it or its parameters changed (outside any graph capture)
+void learn_refresh(sem_handle *h) {
+  Learn *L = h->learn;
+  if (L == nullptr || h->net == nullptr || L->mode != LM_COARSE) return;
+  if (L->mnet == h->net && L->mver == mlp_version(h->net)) return;
+  mlp_forward(h->net, L->Xk.as<uint16_t>(), L->ldx, (int)h->E, L->O.as<float>(),
+              L->ldo, false, 0, L->h1.as<uint16_t>(), L->h2.as<uint16_t>());
+  hipLaunchKernelGGL(k_factor_to_M, dim3((unsigned)h->E), dim3(256), 0, 0, h->E,
+                     L->K, L->O.as<float>(), L->ldo, L->invkh.as<float>(),
+                     L->Ml.as<float>());
+  SEM_HIP(hipGetLastError());
+  SEM_HIP(hipDeviceSynchronize());
+  L->mnet = h->net;
+  L->mver = mlp_version(h->net);
+}
+
 void learn_attach(sem_handle *h, sem_mlp *net) {
   drop_graphs(h);
   if (net == nullptr) {
@@ -232,6 +620,7 @@ void learn_attach(sem_handle *h, sem_mlp *net) {
   check_net(h, net);
   ensure_learn(h, net);
   h->net = net;
+  learn_refresh(h);
 }
 
 void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
@@ -239,6 +628,21 @@ void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
   Learn *L = h->learn;
   if (L == nullptr || h->net == nullptr)
     fail(SEM_ERR_STATE, "learned correction: no network attached");
+  if (L->mode == LM_COARSE) {
+    float *out = cL ? cL : L->cL.as<float>();
+    if (f32)
+      hipLaunchKernelGGL(k_coarse_apply<float>, dim3((unsigned)h->E), dim3(64), 0, s,
+                         h->E, h->n1, L->ni, L->K, h->l2g.as<int32_t>(),
+                         (const float *)r, L->Bf.as<float>(), L->Ml.as<float>(),
+                         mlp_damping_dev(h->net), out);
+    else
+      hipLaunchKernelGGL(k_coarse_apply<double>, dim3((unsigned)h->E), dim3(64), 0,
+                         s, h->E, h->n1, L->ni, L->K, h->l2g.as<int32_t>(),
+                         (const double *)r, L->Bf.as<float>(), L->Ml.as<float>(),
+                         mlp_damping_dev(h->net), out);
+    SEM_HIP(hipGetLastError());
+    return;
+  }
   const int interior = L->mode == LM_INTERIOR;
   if (f32)
     hipLaunchKernelGGL(k_features<float>, dim3((unsigned)h->E), dim3(256), 0, s,
@@ -289,6 +693,13 @@ void learn_precond_local(sem_handle *h, const double *r, double *z, hipStream_t 
   Learn *L = h->learn;
   if (L == nullptr || h->net == nullptr)
     fail(SEM_ERR_STATE, "learned correction: no network attached");
+  if (L->mode == LM_COARSE) {
+    learn_refresh(h);
+    hipLaunchKernelGGL(k_coarse_apply<double>, dim3((unsigned)h->E), dim3(64), 0, s,
+                       h->E, h->n1, L->ni, L->K, (const int32_t *)nullptr, r,
+                       L->Bf.as<float>(), L->Ml.as<float>(),
+                       mlp_damping_dev(h->net), L->cL.as<float>());
+  } else {
   hipLaunchKernelGGL(k_features<double>, dim3((unsigned)h->E), dim3(256), 0, s,
                      h->E, h->n1, L->mode == LM_INTERIOR ? 1 : 0, L->nf,
                      (const int32_t *)nullptr, r, L->kfeat.as<float>(),
@@ -300,6 +711,7 @@ void learn_precond_local(sem_handle *h, const double *r, double *z, hipStream_t 
                      lxi(h), L->mode, L->O.as<float>(), L->ldo,
                      L->s.as<float>(), L->invkh.as<float>(),
                      mlp_damping_dev(h->net), L->cL.as<float>());
+  }
   hipLaunchKernelGGL(k_precond_learned_local, dim3((unsigned)((h->nL + 255) / 256)),
                      dim3(256), 0, s, h->nL, h->l2g.as<int32_t>(),
                      h->offsets.as<int32_t>(), h->perm.as<int32_t>(),
@@ -359,22 +771,6 @@ __global__ void k_gather_rows(int B, const int32_t *__restrict__ idx,
     Xb[(int64_t)b * ldx + q] = X[src * ldx + q];
   for (int q = threadIdx.x; q < n3; q += blockDim.x)
     Tb[(int64_t)b * n3 + q] = T[src * n3 + q];
-}
-
-// sum over the workgroup, returned to every thread (fixed order: the wave
-// butterfly leaves identical bits in every lane, then the waves in order)
-template <int NT>
-__device__ inline double block_allsum(double v, double *red /* NT / 64 */) {
-  v = wave_sum(v);
-  if constexpr (NT == 64) return v;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __syncthreads();  // earlier readers of red are done
-  if (lane == 0) red[wid] = v;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int q = 0; q < NT / 64; ++q) t += red[q];
-  return t;
 }
 
 // Pairs of the interior layout, one workgroup per pair p: residual r (a
@@ -563,6 +959,53 @@ void learn_interior_pairs(sem_handle *h, const double *rL, const int32_t *elems,
   SEM_HIP(hipStreamSynchronize(s));
 }
 
+template <int N1>
+static void launch_coarse_exact_n(const sem_handle *h, const Learn *L, double *U,
+                                  double *W, double *Mex, hipStream_t s) {
+  constexpr int NT = N1 * N1 <= 64 ? 64 : 128;
+  hipLaunchKernelGGL((k_coarse_exact<N1, NT>), dim3((unsigned)h->E), dim3(NT), 0, s,
+                     h->E, h->G64.as<double>(), h->D64.as<double>(),
+                     L->Bd.as<double>(), L->K, U, W, h->kvert.as<double>(),
+                     elem_size(h), Mex);
+}
+
+// exact normalised coarse inverses of every element into Mex [E][K][K]
+static void coarse_exact(const sem_handle *h, const Learn *L, double *Mex,
+                         hipStream_t s) {
+  DevBuf U, W;
+  const size_t n = (size_t)h->E * h->n1 * h->n1 * h->n1 * 8;
+  U.alloc(n);
+  W.alloc(n);
+  switch (h->N) {
+    case 2: launch_coarse_exact_n<3>(h, L, U.as<double>(), W.as<double>(), Mex, s); break;
+    case 3: launch_coarse_exact_n<4>(h, L, U.as<double>(), W.as<double>(), Mex, s); break;
+    case 4: launch_coarse_exact_n<5>(h, L, U.as<double>(), W.as<double>(), Mex, s); break;
+    case 5: launch_coarse_exact_n<6>(h, L, U.as<double>(), W.as<double>(), Mex, s); break;
+    case 6: launch_coarse_exact_n<7>(h, L, U.as<double>(), W.as<double>(), Mex, s); break;
+    case 7: launch_coarse_exact_n<8>(h, L, U.as<double>(), W.as<double>(), Mex, s); break;
+    case 8: launch_coarse_exact_n<9>(h, L, U.as<double>(), W.as<double>(), Mex, s); break;
+    default: fail(SEM_ERR_ARG, "coarse layout: N must be in 2..8");
+  }
+  SEM_HIP(hipGetLastError());
+  SEM_HIP(hipStreamSynchronize(s));
+}
+
+int learn_coarse_exact(sem_handle *h, double *M, hipStream_t s) {
+  if (h->N < 2 || h->N > 8) fail(SEM_ERR_ARG, "coarse layout: N must be in 2..8");
+  if (M == nullptr) fail(SEM_ERR_ARG, "coarse layout: null output");
+  // a throwaway description of the layout (basis and kappa scaling only)
+  Learn L;
+  const int m = h->N - 1;
+  L.ni = m * m * m;
+  std::vector<double> Bd = bubble_basis(h, L.K);
+  L.Bd.alloc(Bd.size() * 8);
+  SEM_HIP(hipMemcpy(L.Bd.p, Bd.data(), Bd.size() * 8, hipMemcpyHostToDevice));
+  kappa_features(h, L.kfeat, L.invkh);
+  SEM_HIP(hipDeviceSynchronize());
+  coarse_exact(h, &L, M, s);
+  return L.K;
+}
+
 // snapshot-recording FP64 Jacobi-PCG (solver.hip)
 int solve_with_snapshots(sem_handle *h, const double *bL, double *xL, double rtol,
                          int every, int max_snaps, double *xs, double *rs,
@@ -591,6 +1034,29 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
   SEM_HIP(hipMemset(Xd.p, 0, (size_t)o->n_pairs * ldx * 2));
   const int nt = L->nt;
   const bool interior = L->mode == LM_INTERIOR;
+  const bool coarse = L->mode == LM_COARSE;
+  DevBuf Mex;
+  if (coarse) {
+    Mex.alloc((size_t)h->E * L->K * L->K * 8);
+    coarse_exact(h, L, Mex.as<double>(), 0);
+    int64_t np = 0, steps = 0;
+    int n_in = 0, H = 0, n_out = 0;
+    mlp_info(net, &n_in, &H, &n_out, &np, &steps);
+    if (steps == 0) {
+      // a network that has never been trained starts from the identity
+      // factor: output bias = packed identity (in the scaled basis the
+      // reference element's coarse inverse has unit diagonal), output
+      // weights scaled down so that the start is close to it
+      std::vector<float> th((size_t)np);
+      mlp_get_params(net, th.data(), np);
+      const int64_t w3 = (int64_t)H * n_in + H + (int64_t)H * H + H;
+      for (int64_t q = 0; q < (int64_t)n_out * H; ++q) th[w3 + q] *= 0.01f;
+      float *b3 = th.data() + w3 + (int64_t)n_out * H;
+      for (int q = 0; q < n_out; ++q) b3[q] = 0.f;
+      for (int i = 0; i < L->K; ++i) b3[i * (i + 1) / 2 + i] = 1.f;
+      mlp_set_params(net, th.data(), np);
+    }
+  }
   Td.alloc((size_t)o->n_pairs * nt * 4);
   DevBuf U, W, litn;
   int local_max = 0;
@@ -621,7 +1087,38 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
     }
     SEM_HIP(hipMemcpy(ps.p, hs.data(), want * 4, hipMemcpyHostToDevice));
     SEM_HIP(hipMemcpy(pe.p, he.data(), want * 4, hipMemcpyHostToDevice));
-    if (interior) {
+    if (coarse) {
+      // half the pairs take a random unit direction instead of the residual's
+      std::vector<int32_t> hiso(want);
+      std::vector<double> hyr((size_t)want * L->K, 0.0);
+      std::normal_distribution<double> nd(0.0, 1.0);
+      for (int p = 0; p < want; ++p) {
+        hiso[p] = (int32_t)(rng() & 1);
+        if (!hiso[p]) continue;
+        double ss = 0.0;
+        for (int k = 0; k < L->K; ++k) {
+          const double v = nd(rng);
+          hyr[(size_t)p * L->K + k] = v;
+          ss += v * v;
+        }
+        const double inv = ss > 0.0 ? 1.0 / std::sqrt(ss) : 0.0;
+        for (int k = 0; k < L->K; ++k) hyr[(size_t)p * L->K + k] *= inv;
+      }
+      DevBuf iso, yr;
+      iso.alloc((size_t)want * 4);
+      yr.alloc(hyr.size() * 8);
+      SEM_HIP(hipMemcpy(iso.p, hiso.data(), (size_t)want * 4, hipMemcpyHostToDevice));
+      SEM_HIP(hipMemcpy(yr.p, hyr.data(), hyr.size() * 8, hipMemcpyHostToDevice));
+      hipLaunchKernelGGL(k_coarse_pairs, dim3(want), dim3(64), 0, 0, want,
+                         ps.as<int32_t>(), pe.as<int32_t>(), nG, h->n1,
+                         h->l2g.as<int32_t>(), rs.as<double>(), L->Bd.as<double>(),
+                         L->K, L->ni, Mex.as<double>(), L->kfeat.as<float>(),
+                         iso.as<int32_t>(), yr.as<double>(),
+                         Xd.as<uint16_t>() + (int64_t)built * ldx, ldx,
+                         Td.as<float>() + (int64_t)built * nt);
+      SEM_HIP(hipGetLastError());
+      SEM_HIP(hipDeviceSynchronize());  // iso, yr are freed at scope end
+    } else if (interior) {
       if (U.p == nullptr) {
         const size_t rows = (size_t)(o->n_pairs / nrhs + o->n_pairs % nrhs);
         U.alloc(rows * n3 * 8);
@@ -672,8 +1169,10 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
                          idx.as<int32_t>() + b0, Xd.as<uint16_t>(), ldx,
                          Td.as<float>(), nt, Xb.as<uint16_t>(), Tb.as<float>());
       SEM_HIP(hipGetLastError());
-      sum += mlp_loss_grad(net, Xb.as<uint16_t>(), ldx, Tb.as<float>(), B, h->N,
-                           true, s);
+      sum += coarse ? mlp_loss_grad_factor(net, Xb.as<uint16_t>(), ldx,
+                                           Tb.as<float>(), L->K, B, true, s)
+                    : mlp_loss_grad(net, Xb.as<uint16_t>(), ldx, Tb.as<float>(),
+                                    B, h->N, true, s);
       mlp_adam(net, nullptr, o->lr, 0.9, 0.999, 1e-8, s);
       ++nb;
     }
@@ -686,9 +1185,9 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
 
   // Damping of the correction: the learned flexible-CG solve of the last
   // training right-hand side to 1e-6 is compared with Jacobi-PCG for a few
-  // damping values (around 1 for the interior layout, whose exact network
-  // reproduces the element-interior solve; small for the global-error
-  // layouts); the best one is kept if it needs fewer iterations than
+  // damping values (around 1 for the interior and coarse layouts, whose
+  // exact networks reproduce the element-interior solve and the element
+  // coarse correction; small for the global-error layouts); the best one is kept if it needs fewer iterations than
   // Jacobi, else the correction is disabled (damping 0).
   sem_mlp *prev = h->net;
   const double rate = rate_n ? rate_sum / rate_n : 0.0;
@@ -708,7 +1207,7 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
   const int it_jac = vs.iters;
   const double cand_int[4] = {1.0, 0.75, 0.5, 0.25};
   const double cand_glob[4] = {0.2, 0.15, 0.1, 0.05};
-  const double *cand = interior ? cand_int : cand_glob;
+  const double *cand = interior || coarse ? cand_int : cand_glob;
   double best_d = 0.0;
   int best_it = it_jac;
   int cand_it[4] = {-1, -1, -1, -1};

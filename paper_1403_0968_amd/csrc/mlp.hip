@@ -200,6 +200,41 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// coarse-operator factor: the output is a lower-triangular K x K factor L
+// (row-major packed); per sample, T holds y and alpha* (2K values) and the
+// loss is the mean of (L L^T y - alpha*)^2; dL = g v^T + y (L^T g)^T with
+// v = L^T y and g the loss gradient with respect to L L^T y.  One thread
+// per sample.
+template <int K>
+__global__ void __launch_bounds__(64)
+    k_loss_factor(int B, const float *__restrict__ O, int ldo,
+                  const float *__restrict__ T, float *__restrict__ dO, int lddo,
+                  double *__restrict__ lossp) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const float *o = O + (size_t)b * ldo;
+  const float *y = T + (size_t)b * 2 * K, *as = y + K;
+  float v[K], g[K], w[K];
+  for (int j = 0; j < K; ++j) v[j] = w[j] = 0.f;
+  for (int i = 0, q = 0; i < K; ++i)
+    for (int j = 0; j <= i; ++j, ++q) v[j] += o[q] * y[i];
+  double loss = 0.0;
+  const float sc = (float)(2.0 / ((double)B * K));
+  for (int i = 0, q = 0; i < K; ++i) {
+    float a = 0.f;
+    for (int j = 0; j <= i; ++j) a += o[q + j] * v[j];
+    q += i + 1;
+    const float d = a - as[i];
+    loss += (double)d * (double)d;
+    g[i] = sc * d;
+  }
+  for (int i = 0, q = 0; i < K; ++i)
+    for (int j = 0; j <= i; ++j, ++q) w[j] += o[q] * g[i];
+  for (int i = 0, q = 0; i < K; ++i)
+    for (int j = 0; j <= i; ++j, ++q) dO[(size_t)b * lddo + q] = g[i] * v[j] + y[i] * w[j];
+  lossp[b] = loss;
+}
+
 // nodal outputs: Yhat = o itself (n_out values per sample)
 __global__ void __launch_bounds__(256)
     k_loss_id(int B, int no, const float *__restrict__ O, int ldo,
@@ -273,6 +308,7 @@ struct sem_mlp {
   int n_in = 0, H = 0, n_out = 0, kin = 0;
   int nt3 = 1, gy3 = 1, w3rows = 16;  // output layer: tiles per wave, grid.y
   int64_t np = 0, step = 0;
+  uint64_t version = 1;     // changes whenever the parameters change
   double damping = 1.0;     // scale of the correction in the preconditioner
   double ref_rate = 0.0;    // Jacobi-PCG log10 residual drop per iteration
                             // on the training problem (0: unknown)
@@ -363,6 +399,7 @@ sem_mlp *mlp_create(int n_in, int H, int n_out, uint64_t seed) {
 }
 
 void mlp_set_params(sem_mlp *net, const float *host, int64_t n) {
+  net->version += 1;
   if (n != net->np) fail(SEM_ERR_ARG, "mlp_set_params: wrong parameter count");
   SEM_HIP(hipMemcpy(net->th.p, host, n * 4, hipMemcpyHostToDevice));
   SEM_HIP(hipMemset(net->m.p, 0, n * 4));
@@ -436,27 +473,12 @@ void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
 // output is 8 trilinear vertex values prolonged to the GLL nodes of order N
 // and T is [B][(N+1)^3]; otherwise the output is compared with T [B][n_out]
 // directly (nodal and interior layouts); gradient into net->grad (flat order)
-double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
-                     int B, int N, bool host_loss, hipStream_t s) {
-  if (N < 1 || N > 16) fail(SEM_ERR_ARG, "mlp_loss_grad: N must be in 1..16");
-  const int nn = (N + 1) * (N + 1) * (N + 1);
-  const bool q1 = net->n_out == 8 && net->n_in == nn + 8;
-  ensure_scratch(net, B);  // before net->of is read below
-  const int wo = net->n_out > 16 ? net->n_out : 16;
-  mlp_forward(net, X, ldx, B, net->of.as<float>(), wo, true, s, nullptr, nullptr);
+// backward pass from net->dO (written by a loss kernel) into net->grad,
+// then the mean loss over B samples of `count` terms each
+static double mlp_backward(sem_mlp *net, const uint16_t *X, int ldx, int B,
+                           int count, bool host_loss, hipStream_t s) {
   const int H = net->H;
-  if (q1) {
-    XiParams xp{};
-    xp.n1 = N + 1;
-    RefElem r = make_ref_elem(N);
-    for (int q = 0; q <= N; ++q) xp.xi[q] = (float)r.xi[q];
-    hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, s, B, net->of.as<float>(),
-                       wo, T, xp, net->dO.as<float>(), wo, net->lossp.as<double>());
-  } else {
-    hipLaunchKernelGGL(k_loss_id, dim3(B), dim3(256), 0, s, B, net->n_out,
-                       net->of.as<float>(), wo, T, net->dO.as<float>(), wo,
-                       net->lossp.as<double>());
-  }
+  const int wo = net->n_out > 16 ? net->n_out : 16;
   float *g = net->grad.as<float>();
   float *gW1 = g, *gb1 = gW1 + (int64_t)H * net->n_in, *gW2 = gb1 + H,
         *gb2 = gW2 + (int64_t)H * H, *gW3 = gb2 + H,
@@ -487,8 +509,7 @@ double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
   hipLaunchKernelGGL(k_grad_b, dim3(1), dim3(128), 0, s, B, H,
                      net->dz1.as<float>(), H, gb1);
   hipLaunchKernelGGL(k_sum_losses, dim3(1), dim3(256), 0, s, B,
-                     net->lossp.as<double>(), q1 ? nn : net->n_out,
-                     net->lossd.as<double>());
+                     net->lossp.as<double>(), count, net->lossd.as<double>());
   SEM_HIP(hipGetLastError());
   if (!host_loss) return 0.0;
   SEM_HIP(hipMemcpyAsync(net->host_loss, net->lossd.p, sizeof(double),
@@ -497,8 +518,58 @@ double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
   return *net->host_loss;
 }
 
+double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
+                     int B, int N, bool host_loss, hipStream_t s) {
+  if (N < 1 || N > 16) fail(SEM_ERR_ARG, "mlp_loss_grad: N must be in 1..16");
+  const int nn = (N + 1) * (N + 1) * (N + 1);
+  const bool q1 = net->n_out == 8 && net->n_in == nn + 8;
+  ensure_scratch(net, B);  // before net->of is read below
+  const int wo = net->n_out > 16 ? net->n_out : 16;
+  mlp_forward(net, X, ldx, B, net->of.as<float>(), wo, true, s, nullptr, nullptr);
+  if (q1) {
+    XiParams xp{};
+    xp.n1 = N + 1;
+    RefElem r = make_ref_elem(N);
+    for (int q = 0; q <= N; ++q) xp.xi[q] = (float)r.xi[q];
+    hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, s, B, net->of.as<float>(),
+                       wo, T, xp, net->dO.as<float>(), wo, net->lossp.as<double>());
+  } else {
+    hipLaunchKernelGGL(k_loss_id, dim3(B), dim3(256), 0, s, B, net->n_out,
+                       net->of.as<float>(), wo, T, net->dO.as<float>(), wo,
+                       net->lossp.as<double>());
+  }
+  return mlp_backward(net, X, ldx, B, q1 ? nn : net->n_out, host_loss, s);
+}
+
+// loss and gradient of the coarse-operator factor (n_out = K(K+1)/2,
+// K in {1, 8, 27}); T [B][2K] holds y and alpha* per sample
+double mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X, int ldx,
+                            const float *T, int K, int B, bool host_loss,
+                            hipStream_t s) {
+  if (net->n_out != K * (K + 1) / 2 || (K != 1 && K != 8 && K != 27))
+    fail(SEM_ERR_ARG, "mlp_loss_grad_factor: K must be 1, 8 or 27 and "
+                      "n_out = K(K+1)/2");
+  ensure_scratch(net, B);
+  const int wo = net->n_out > 16 ? net->n_out : 16;
+  mlp_forward(net, X, ldx, B, net->of.as<float>(), wo, true, s, nullptr, nullptr);
+  const dim3 g((unsigned)((B + 63) / 64)), t(64);
+  if (K == 1)
+    hipLaunchKernelGGL(k_loss_factor<1>, g, t, 0, s, B, net->of.as<float>(), wo, T,
+                       net->dO.as<float>(), wo, net->lossp.as<double>());
+  else if (K == 8)
+    hipLaunchKernelGGL(k_loss_factor<8>, g, t, 0, s, B, net->of.as<float>(), wo, T,
+                       net->dO.as<float>(), wo, net->lossp.as<double>());
+  else
+    hipLaunchKernelGGL(k_loss_factor<27>, g, t, 0, s, B, net->of.as<float>(), wo, T,
+                       net->dO.as<float>(), wo, net->lossp.as<double>());
+  return mlp_backward(net, X, ldx, B, K, host_loss, s);
+}
+
+uint64_t mlp_version(const sem_mlp *net) { return net->version; }
+
 void mlp_adam(sem_mlp *net, const float *grad, double lr, double b1, double b2,
               double eps, hipStream_t s) {
+  net->version += 1;
   net->step += 1;
   const double c1 = 1.0 - std::pow(b1, (double)net->step);
   const double c2 = 1.0 - std::pow(b2, (double)net->step);

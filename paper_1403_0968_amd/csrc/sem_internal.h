@@ -173,6 +173,10 @@ void mlp_refresh(sem_mlp *net, hipStream_t s);
 void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
                  int ldo, bool train, hipStream_t s, uint16_t *h1x = nullptr,
                  uint16_t *h2x = nullptr);
+double mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X, int ldx,
+                            const float *T, int K, int B, bool host_loss,
+                            hipStream_t s);
+uint64_t mlp_version(const sem_mlp *net);
 double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
                      int B, int N, bool host_loss, hipStream_t s);
 void mlp_adam(sem_mlp *net, const float *grad, double lr, double b1, double b2,
@@ -195,6 +199,8 @@ void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
 void learn_interior_pairs(sem_handle *h, const double *rL, const int32_t *elems,
                           int n, uint16_t *X, int ldx, float *T, double rtol,
                           int32_t *iters, hipStream_t s);
+void learn_refresh(sem_handle *h);
+int learn_coarse_exact(sem_handle *h, double *M, hipStream_t s);
 void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
                  const sem_train_opts *o, sem_train_report *rep,
                  hipStream_t caller);

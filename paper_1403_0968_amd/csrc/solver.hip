@@ -1008,6 +1008,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
     if (n != 1) fail(SEM_ERR_ARG, "solve: the learned preconditioner needs a single solve");
     if (b->hs[0]->net == nullptr)
       fail(SEM_ERR_STATE, "solve: no network attached (sem_learn_attach)");
+    learn_refresh(b->hs[0]);
     if (mlp_damping(b->hs[0]->net) == 0.0) {
       // validation found no gain over Jacobi: the correction is disabled
       learned = false;

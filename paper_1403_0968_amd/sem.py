@@ -31,7 +31,8 @@ EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_mlp_info", "sem_mlp_get_params", "sem_mlp_set_params",
             "sem_mlp_forward", "sem_mlp_loss_grad", "sem_mlp_adam",
             "sem_mlp_set_damping", "sem_mlp_get_damping", "sem_mlp_save", "sem_mlp_load", "sem_learn_attach",
-            "sem_learn_train", "sem_learn_interior_pairs", "sem_last_error"]
+            "sem_learn_train", "sem_learn_interior_pairs",
+            "sem_learn_coarse_exact", "sem_mlp_loss_grad_factor", "sem_last_error"]
 
 
 class sem_mesh_desc(C.Structure):
@@ -126,6 +127,9 @@ def lib():
     L.sem_mlp_forward.argtypes = [vp, vp, i32, i32, vp, vp]
     L.sem_mlp_loss_grad.argtypes = [vp, vp, i32, vp, i32, i32, vp,
                                     C.POINTER(C.c_double), vp]
+    L.sem_mlp_loss_grad_factor.argtypes = [vp, vp, i32, vp, i32, i32, vp,
+                                           C.POINTER(C.c_double), vp]
+    L.sem_learn_coarse_exact.argtypes = [vp, vp, C.POINTER(i32), vp]
     L.sem_mlp_adam.argtypes = [vp, vp, C.c_double, C.c_double, C.c_double,
                                C.c_double, vp]
     L.sem_mlp_set_damping.argtypes = [vp, C.c_double, C.c_double]
@@ -361,6 +365,21 @@ def sem_mlp_loss_grad(net, X, ldx, T, B, N, grad=None, stream=None):
                                    int(N), _ptr(grad), C.byref(loss),
                                    _stream(stream)))
     return loss.value
+
+
+def sem_mlp_loss_grad_factor(net, X, ldx, T, K, B, grad=None, stream=None):
+    loss = C.c_double()
+    _check(lib().sem_mlp_loss_grad_factor(net, _ptr(X), int(ldx), _ptr(T), int(K),
+                                          int(B), _ptr(grad), C.byref(loss),
+                                          _stream(stream)))
+    return loss.value
+
+
+def sem_learn_coarse_exact(h, M, stream=None):
+    """M: device FP64 tensor of E*K*K values; returns K."""
+    k = C.c_int32()
+    _check(lib().sem_learn_coarse_exact(h, _ptr(M), C.byref(k), _stream(stream)))
+    return k.value
 
 
 def sem_mlp_adam(net, grad=None, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
