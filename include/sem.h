@@ -259,9 +259,10 @@ sem_status sem_batch_pcg_solve(sem_batch *b, const sem_solve_opts *opts,
  * element size) and averaged over the copies of every node.  The damping
  * and a Jacobi reference convergence rate are set by sem_learn_train and
  * kept in checkpoints.  Fallback to Jacobi-PCG (stats.fell_back = 1) happens
- * on NaN / breakdown, on stagnation (residual drop < 2x over 200
- * iterations), when the learned solve converges at less than half the
- * Jacobi rate after 100 iterations, when a refinement step fails to halve
+ * on NaN / breakdown, on stagnation (the smallest residual so far drops
+ * less than 2x over 400 iterations), when the learned solve's smallest
+ * residual shows less than 30% of the average Jacobi rate after 300 or
+ * more iterations, when a refinement step fails to halve
  * the FP64 true residual (the step is undone), or when the damping is 0.  Parameters are one FP32 vector: W1 [128][n_in], b1, W2
  * [128][128], b2, W3 [n_out][128], b3 (row-major [out][in]).
  * ------------------------------------------------------------------------ */

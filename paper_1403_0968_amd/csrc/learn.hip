@@ -53,7 +53,7 @@ struct Learn {
   // element (BF16 [E][ldx]), element operators M_e / (kappa_e h_e) (FP32
   // [E][K][K]) for the network of version mver
   int K = 0, ni = 0;
-  DevBuf Bf, Bd, Xk, Ml;
+  DevBuf Bf, Bd, Xk, Ml, cG;  // cG: correction on unique nodes (FP32)
   const sem_mlp *mnet = nullptr;
   uint64_t mver = 0;
   DevBuf X, s, O, kfeat, invkh, cL, h1, h2;  // h1, h2: hidden activations
@@ -353,46 +353,117 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// correction of the coarse layout on every element:
-// cL = damping B M_e B^T r_I on the interior nodes, 0 on the faces; r on
-// unique nodes (through l2g) or, with l2g NULL, a continuous E-vector
-template <class TV>
-__global__ void __launch_bounds__(64)
-    k_coarse_apply(int64_t E, int n1, int ni, int K,
-                   const int32_t *__restrict__ l2g, const TV *__restrict__ r,
-                   const float *__restrict__ Bf, const float *__restrict__ Ml,
-                   const float *__restrict__ damping, float *__restrict__ cL) {
-  __shared__ float rI[343];
-  __shared__ float y[27], al[27];
-  const int64_t e = blockIdx.x;
-  const int t = threadIdx.x;
+// correction of the coarse layout: c = damping B M_e B^T r_I on the interior
+// nodes of every element.  UNIQUE: r on unique nodes (read through the box
+// numbering) and c written to the interior entries of the unique-node
+// vector out (its other entries stay zero); otherwise r is a continuous
+// E-vector and out the E-vector of element corrections, zero on the faces.
+// Persistent 256-thread workgroups hold B (ni x K) in LDS and walk groups
+// of four elements, one per wave: the wave stages r_I in LDS, lanes 2j and
+// 2j+1 sum half of B[:, j]^T r_I each (y = B^T r_I), lanes i < K form
+// alpha_i = sum_j M_e[j][i] y_j (M_e is symmetric, so the reads are
+// coalesced; they are issued with the gather of r_I) and every lane
+// expands c = B alpha on its interior nodes.
+constexpr int CA_WAVES = 4;
+
+template <class TV, bool UNIQUE, int K>
+__global__ void __launch_bounds__(64 * CA_WAVES)
+    k_coarse_apply(int64_t E, int n1, int ni, Box box,
+                   const TV *__restrict__ r, const float *__restrict__ Bf,
+                   const float *__restrict__ Ml, const float *__restrict__ damping,
+                   float *__restrict__ out) {
+  extern __shared__ float ca_lds[];
+  float *Bs = ca_lds;                                   // [ni][K]
+  const int wave = threadIdx.x >> 6, t = threadIdx.x & 63;
+  float *rI = ca_lds + ni * K + wave * (ni + 64);       // [ni]
+  float *yv = rI + ni;                                  // [K] then alpha [K]
+  float *al = yv + 32;
+  for (int q = threadIdx.x; q < ni * K; q += 64 * CA_WAVES) Bs[q] = Bf[q];
   const int n3 = n1 * n1 * n1, m = n1 - 2;
-  for (int q = t; q < ni; q += 64) {
-    const int i = q % m + 1, j = (q / m) % m + 1, k = q / (m * m) + 1;
-    const int64_t l = e * n3 + i + n1 * (j + n1 * k);
-    rI[q] = (float)r[l2g ? (int64_t)l2g[l] : l];
-  }
+  const int half = (ni + 1) / 2;
+  const float damp = damping[0];
   __syncthreads();
-  if (t < K) {
-    float a = 0.f;
-    for (int q = 0; q < ni; ++q) a += Bf[q * K + t] * rI[q];
-    y[t] = a;
+  for (int64_t e0 = (int64_t)blockIdx.x * CA_WAVES; e0 < E;
+       e0 += (int64_t)gridDim.x * CA_WAVES) {  // uniform over the workgroup
+    const int64_t e = e0 + wave;
+    const bool act = e < E;
+    float mcol[K];  // column t of M_e (= row t: M_e is symmetric)
+    if (act && t < K) {
+      const float *Me = Ml + e * K * K;
+#pragma unroll
+      for (int jj = 0; jj < K; ++jj) mcol[jj] = Me[jj * K + t];
+    }
+    int64_t g0 = 0;
+    if (UNIQUE && act) g0 = box_origin(box, (uint32_t)e);
+    auto index = [&](int q) -> int64_t {
+      const int i = q % m + 1, j = (q / m) % m + 1, k = q / (m * m) + 1;
+      return UNIQUE ? g0 + i + (int64_t)box.Gx * j + box.Gxy * k
+                    : e * n3 + i + n1 * (j + n1 * k);
+    };
+    if (act)
+      for (int q = t; q < ni; q += 64) rI[q] = (float)r[index(q)];
+    __syncthreads();
+    if (act && t < 2 * K) {
+      const int j = t >> 1, q0 = (t & 1) * half, q1 = min(ni, q0 + half);
+      float a = 0.f;
+      for (int q = q0; q < q1; ++q) a += Bs[q * K + j] * rI[q];
+      a += __shfl_xor(a, 1, 64);
+      if ((t & 1) == 0) yv[j] = a;
+    }
+    __syncthreads();
+    if (act && t < K) {
+      float a = 0.f;
+#pragma unroll
+      for (int jj = 0; jj < K; ++jj) a += mcol[jj] * yv[jj];
+      al[t] = damp * a;
+    }
+    __syncthreads();
+    if (act) {
+      for (int q = t; q < ni; q += 64) {
+        float c = 0.f;
+#pragma unroll
+        for (int jj = 0; jj < K; ++jj) c += Bs[q * K + jj] * al[jj];
+        out[index(q)] = c;
+      }
+      if (!UNIQUE)  // the faces of the element carry no correction
+        for (int p = t; p < n3; p += 64) {
+          const int i = p % n1, j = (p / n1) % n1, k = p / (n1 * n1);
+          if (interior_index(i, j, k, n1) < 0) out[e * n3 + p] = 0.f;
+        }
+    }
+    __syncthreads();  // rI, yv, al are reused by the next group
   }
-  __syncthreads();
-  if (t < K) {
-    float a = 0.f;
-    const float *Me = Ml + e * K * K + t * K;
-    for (int jj = 0; jj < K; ++jj) a += Me[jj] * y[jj];
-    al[t] = damping[0] * a;
+}
+
+template <class TV, bool UNIQUE>
+static void launch_coarse_apply(const sem_handle *h, const Learn *L, const TV *r,
+                                float *out, hipStream_t s) {
+  const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet) : Box{};
+  const size_t lds = ((size_t)L->ni * L->K + CA_WAVES * ((size_t)L->ni + 64)) * 4;
+  const int64_t groups = (h->E + CA_WAVES - 1) / CA_WAVES;
+  // workgroups that stay resident together (LDS-limited), 256 CUs
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, 160 * 1024 / (int64_t)lds));
+  const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * per_cu);
+  const dim3 g(grid), b(64 * CA_WAVES);
+  const float *Bf = L->Bf.as<float>(), *Ml = L->Ml.as<float>();
+  const float *damp = mlp_damping_dev(h->net);
+  switch (L->K) {
+    case 1:
+      hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, 1>), g, b, lds, s, h->E, h->n1,
+                         L->ni, box, r, Bf, Ml, damp, out);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, 8>), g, b, lds, s, h->E, h->n1,
+                         L->ni, box, r, Bf, Ml, damp, out);
+      break;
+    case 27:
+      hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, 27>), g, b, lds, s, h->E, h->n1,
+                         L->ni, box, r, Bf, Ml, damp, out);
+      break;
+    default:
+      fail(SEM_ERR_STATE, "coarse layout: K must be 1, 8 or 27");
   }
-  __syncthreads();
-  for (int p = t; p < n3; p += 64) {
-    const int q = interior_index(p % n1, (p / n1) % n1, p / (n1 * n1), n1);
-    float c = 0.f;
-    if (q >= 0)
-      for (int jj = 0; jj < K; ++jj) c += Bf[q * K + jj] * al[jj];
-    cL[e * n3 + p] = c;
-  }
+  SEM_HIP(hipGetLastError());
 }
 
 static double elem_size(const sem_handle *h) {
@@ -568,6 +639,8 @@ static void ensure_learn(sem_handle *h, const sem_mlp *net) {
       L->Bf.alloc(Bf.size() * 4);
       SEM_HIP(hipMemcpy(L->Bf.p, Bf.data(), Bf.size() * 4, hipMemcpyHostToDevice));
       L->Ml.alloc((size_t)h->E * L->K * L->K * 4);
+      L->cG.alloc((size_t)h->nG * 4);
+      SEM_HIP(hipMemset(L->cG.p, 0, (size_t)h->nG * 4));  // faces stay zero
     }
     L->ldo = n_out > 16 ? n_out : 16;
     L->X.alloc((size_t)h->E * ldx * 2);
@@ -628,19 +701,12 @@ void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
   Learn *L = h->learn;
   if (L == nullptr || h->net == nullptr)
     fail(SEM_ERR_STATE, "learned correction: no network attached");
-  if (L->mode == LM_COARSE) {
-    float *out = cL ? cL : L->cL.as<float>();
+  if (L->mode == LM_COARSE) {  // into the unique-node buffer cG
     if (f32)
-      hipLaunchKernelGGL(k_coarse_apply<float>, dim3((unsigned)h->E), dim3(64), 0, s,
-                         h->E, h->n1, L->ni, L->K, h->l2g.as<int32_t>(),
-                         (const float *)r, L->Bf.as<float>(), L->Ml.as<float>(),
-                         mlp_damping_dev(h->net), out);
+      launch_coarse_apply<float, true>(h, L, (const float *)r, L->cG.as<float>(), s);
     else
-      hipLaunchKernelGGL(k_coarse_apply<double>, dim3((unsigned)h->E), dim3(64), 0,
-                         s, h->E, h->n1, L->ni, L->K, h->l2g.as<int32_t>(),
-                         (const double *)r, L->Bf.as<float>(), L->Ml.as<float>(),
-                         mlp_damping_dev(h->net), out);
-    SEM_HIP(hipGetLastError());
+      launch_coarse_apply<double, true>(h, L, (const double *)r, L->cG.as<float>(),
+                                        s);
     return;
   }
   const int interior = L->mode == LM_INTERIOR;
@@ -665,6 +731,10 @@ void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
 }
 
 float *learn_cl(sem_handle *h) { return h->learn ? h->learn->cL.as<float>() : nullptr; }
+// the coarse layout's correction on unique nodes, or NULL for the others
+float *learn_cg(sem_handle *h) {
+  return h->learn && h->learn->mode == LM_COARSE ? h->learn->cG.as<float>() : nullptr;
+}
 
 // z_L = dinv o r_L + (average over copies of the correction) on continuous
 // E-vectors (FP64), for sem_precond_apply
@@ -695,10 +765,7 @@ void learn_precond_local(sem_handle *h, const double *r, double *z, hipStream_t 
     fail(SEM_ERR_STATE, "learned correction: no network attached");
   if (L->mode == LM_COARSE) {
     learn_refresh(h);
-    hipLaunchKernelGGL(k_coarse_apply<double>, dim3((unsigned)h->E), dim3(64), 0, s,
-                       h->E, h->n1, L->ni, L->K, (const int32_t *)nullptr, r,
-                       L->Bf.as<float>(), L->Ml.as<float>(),
-                       mlp_damping_dev(h->net), L->cL.as<float>());
+    launch_coarse_apply<double, false>(h, L, r, L->cL.as<float>(), s);
   } else {
   hipLaunchKernelGGL(k_features<double>, dim3((unsigned)h->E), dim3(256), 0, s,
                      h->E, h->n1, L->mode == LM_INTERIOR ? 1 : 0, L->nf,

@@ -384,15 +384,16 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
-// z = dinv r + (average over the copies of the element corrections cL);
-// partials (r, z), (z, w), (r, r).  skip_done = 0 during initialisation.
+// z = dinv r + c with c the correction on unique nodes (cG, when the layout
+// provides it) or the average over the copies of the element corrections
+// cL; partials (r, z), (z, w), (r, r).  skip_done = 0 during initialisation.
 template <class TV, class TD>
 __global__ void __launch_bounds__(RT)
     k_bprec_learned(const BatchSolve *__restrict__ sds,
                     const CgState *__restrict__ st,
                     const VecItem *__restrict__ items, int nitems,
-                    const float *__restrict__ cL, double *__restrict__ part,
-                    int skip_done) {
+                    const float *__restrict__ cL, const float *__restrict__ cG,
+                    double *__restrict__ part, int skip_done) {
   __shared__ double sm[RT / 64];
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
@@ -404,16 +405,21 @@ __global__ void __launch_bounds__(RT)
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double rz = 0.0, zw = 0.0, rr = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
-      const NodeCopies nc = node_copies(sd.box, (uint32_t)g);
-      float c = 0.f;
-      if (!nc.masked)
-        for (int a = 0; a < nc.z.cnt; ++a)
-          for (int b = 0; b < nc.y.cnt; ++b)
-            for (int cc = 0; cc < nc.x.cnt; ++cc)
-              c += cL[copy_lid(sd.box, nc, a, b, cc)];
-      const float mult = (float)(nc.x.cnt * nc.y.cnt * nc.z.cnt);
       const TV rv = r[g];
-      const TV zv = nc.masked ? TV(0) : (TV)(dinv[g] * rv) + (TV)(c / mult);
+      TV zv;
+      if (cG) {  // dinv is 0 on the Dirichlet boundary, where cG is 0 too
+        zv = (TV)(dinv[g] * rv) + (TV)cG[g];
+      } else {
+        const NodeCopies nc = node_copies(sd.box, (uint32_t)g);
+        float c = 0.f;
+        if (!nc.masked)
+          for (int a = 0; a < nc.z.cnt; ++a)
+            for (int b = 0; b < nc.y.cnt; ++b)
+              for (int cc = 0; cc < nc.x.cnt; ++cc)
+                c += cL[copy_lid(sd.box, nc, a, b, cc)];
+        const float mult = (float)(nc.x.cnt * nc.y.cnt * nc.z.cnt);
+        zv = nc.masked ? TV(0) : (TV)(dinv[g] * rv) + (TV)(c / mult);
+      }
       z[g] = zv;
       rz += (double)rv * (double)zv;
       zw += (double)zv * (double)w[g];
@@ -754,6 +760,7 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
 }
 
 float *learn_cl(sem_handle *h);
+float *learn_cg(sem_handle *h);
 
 template <class TV, class TD>
 static void iteration_fcg_t(sem_batch *b, int prec) {
@@ -774,7 +781,7 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
   learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, learn_cl(h),
               b->s);
   hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
-                     st, vi, nv, learn_cl(h), part, 1);
+                     st, vi, nv, learn_cl(h), learn_cg(h), part, 1);
   hipLaunchKernelGGL(k_bbeta_fcg, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
   hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
                      nv);
@@ -809,10 +816,10 @@ static void init_fcg(sem_batch *b, int prec) {
   learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, learn_cl(h), b->s);
   if (f32) {
     hipLaunchKernelGGL((k_bprec_learned<float, float>), dim3(g), dim3(RT), 0, b->s,
-                       sds, st, vi, nv, learn_cl(h), part, 0);
+                       sds, st, vi, nv, learn_cl(h), learn_cg(h), part, 0);
   } else {
     hipLaunchKernelGGL((k_bprec_learned<double, double>), dim3(g), dim3(RT), 0,
-                       b->s, sds, st, vi, nv, learn_cl(h), part, 0);
+                       b->s, sds, st, vi, nv, learn_cl(h), learn_cg(h), part, 0);
   }
   hipLaunchKernelGGL(k_bfcg_start, dim3(b->n), dim3(RT), 0, b->s, st, part,
                      b->vbeg.as<int32_t>());
@@ -912,7 +919,8 @@ static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac,
 static bool run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o,
                    int mode = 0, bool monitor = false, double ref_rate = 0.0) {
   const int K = std::max(1, o->check_every);
-  std::vector<std::pair<int, double>> hist;
+  std::vector<std::pair<int, double>> hist;  // (iteration, best rr so far)
+  double best = 0.0;
   auto poll = [&]() {
     SEM_HIP(hipMemcpyAsync(b->host_st, b->st.p, b->n * sizeof(CgState),
                            hipMemcpyDeviceToHost, b->s));
@@ -923,17 +931,25 @@ static bool run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o,
   };
   while (!poll()) {
     if (monitor) {
+      // The residual 2-norm of flexible CG is not monotone (CG minimises the
+      // energy norm), so both guards use the smallest residual so far.
       const CgState &c = b->host_st[0];
-      // progress judge: after 100 iterations the learned solve must have
-      // reduced log10 ||r|| / ||b|| by at least half as much as Jacobi-PCG
-      // does on this operator (ref_rate, measured on the training solves)
-      if (ref_rate < 0.0 && c.it >= 100 && c.bb > 0.0 && c.rr > 0.0 &&
-          0.5 * std::log10(c.rr / c.bb) > 0.5 * ref_rate * c.it)
+      best = hist.empty() ? c.rr : std::min(best, c.rr);
+      // progress judge: after 300 iterations the learned solve must have
+      // reduced log10 ||r|| / ||b|| by at least 30% as much as Jacobi-PCG
+      // does on average on this operator (ref_rate, measured on the
+      // training solves; CG's own rate is uneven, so the bar is low: it
+      // catches a network that stalls the solve, not one that is merely
+      // no better than Jacobi)
+      if (ref_rate < 0.0 && c.it >= 300 && c.bb > 0.0 && best > 0.0 &&
+          0.5 * std::log10(best / c.bb) > 0.3 * ref_rate * c.it)
         return true;
-      hist.push_back({c.it, c.rr});
+      // stagnation: less than a halving of the best residual over 400
+      // iterations
+      hist.push_back({c.it, best});
       for (auto it = hist.rbegin(); it != hist.rend(); ++it)
-        if (c.it - it->first >= 200) {
-          if (c.rr > 0.25 * it->second) return true;
+        if (c.it - it->first >= 400) {
+          if (best > 0.25 * it->second) return true;
           break;
         }
     }
