@@ -365,7 +365,9 @@ def main():
     ub = (u32.view(torch.int32) + 0x7FFF + ((u32.view(torch.int32) >> 16) & 1)) >> 16
     ub = ub.to(torch.int16).contiguous()
     msb = time_ax(sem, torch, h, sem.SEM_BF16, ub, w32, args.steps, args.warmup)
-    for name, t_ms, key in (("fp32", ms32, "f32"), ("bf16", msb, "bf16")):
+    msm = time_ax(sem, torch, h, sem.SEM_BF16_MFMA, ub, w32, args.steps, args.warmup)
+    for name, t_ms, key in (("fp32", ms32, "f32"), ("bf16", msb, "bf16"),
+                            ("bf16_mfma", msm, "bf16")):
         extra[f"sem_ax_{name}"] = {
             "us_per_launch": t_ms * 1e3, "gdofs": nL / (t_ms * 1e-3) / 1e9,
             "alg_GBs": BYTES_PER_NODE[key] * nL / (t_ms * 1e-3) / 1e9,
