@@ -731,6 +731,21 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done) {
                     skip_done, b->s);
     return;
   }
+  if (b->n == 1) {
+    // a single solve: the operator with every argument in registers
+    sem_handle *h = b->hs[0];
+    Workspace *W = h->ws;
+    const bool f64 = prec == SEM_FP64;
+    const void *G = f64 ? h->G64.p : prec == SEM_FP32 ? h->G32.p : h->G16.p;
+    const void *D = f64 ? h->D64.p : h->D32.p;
+    const void *u = f64 ? W->v64[src].p : W->v32[src].p;
+    void *w = f64 ? W->v64[dst].p : W->v32[dst].p;
+    const int32_t *stop =
+        skip_done ? &b->st.as<CgState>()[0].done : (const int32_t *)nullptr;
+    launch_ax_solve(h->N, prec, h->E, D, G, u, w,
+                    make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet), stop, b->s);
+    return;
+  }
   const int bs = b->bs[prec];
   const int k = bs_slot(bs);
   const int n = b->n_ax[k];
