@@ -404,9 +404,18 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
       for (int q = t; q < ni; q += 64) rI[q] = (float)r[index(q)];
     __syncthreads();
     if (act && t < 2 * K) {
+      // four independent partial sums keep several LDS reads in flight
       const int j = t >> 1, q0 = (t & 1) * half, q1 = min(ni, q0 + half);
-      float a = 0.f;
-      for (int q = q0; q < q1; ++q) a += Bs[q * K + j] * rI[q];
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+      int q = q0;
+      for (; q + 4 <= q1; q += 4) {
+        a0 += Bs[q * K + j] * rI[q];
+        a1 += Bs[(q + 1) * K + j] * rI[q + 1];
+        a2 += Bs[(q + 2) * K + j] * rI[q + 2];
+        a3 += Bs[(q + 3) * K + j] * rI[q + 3];
+      }
+      for (; q < q1; ++q) a0 += Bs[q * K + j] * rI[q];
+      float a = (a0 + a1) + (a2 + a3);
       a += __shfl_xor(a, 1, 64);
       if ((t & 1) == 0) yv[j] = a;
     }
@@ -419,11 +428,18 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
     }
     __syncthreads();
     if (act) {
-      for (int q = t; q < ni; q += 64) {
-        float c = 0.f;
+      float ar[K];
 #pragma unroll
-        for (int jj = 0; jj < K; ++jj) c += Bs[q * K + jj] * al[jj];
-        out[index(q)] = c;
+      for (int jj = 0; jj < K; ++jj) ar[jj] = al[jj];
+      for (int q = t; q < ni; q += 64) {
+        float c0 = 0.f, c1 = 0.f;
+#pragma unroll
+        for (int jj = 0; jj + 1 < K; jj += 2) {
+          c0 += Bs[q * K + jj] * ar[jj];
+          c1 += Bs[q * K + jj + 1] * ar[jj + 1];
+        }
+        if (K & 1) c0 += Bs[q * K + K - 1] * ar[K - 1];
+        out[index(q)] = c0 + c1;
       }
       if (!UNIQUE)  // the faces of the element carry no correction
         for (int p = t; p < n3; p += 64) {
@@ -441,8 +457,9 @@ static void launch_coarse_apply(const sem_handle *h, const Learn *L, const TV *r
   const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet) : Box{};
   const size_t lds = ((size_t)L->ni * L->K + CA_WAVES * ((size_t)L->ni + 64)) * 4;
   const int64_t groups = (h->E + CA_WAVES - 1) / CA_WAVES;
-  // workgroups that stay resident together (LDS-limited), 256 CUs
-  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(8, 160 * 1024 / (int64_t)lds));
+  // workgroups that stay resident together (LDS, and four per CU for the
+  // register use of the K = 27 kernel), 256 CUs
+  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, 160 * 1024 / (int64_t)lds));
   const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * per_cu);
   const dim3 g(grid), b(64 * CA_WAVES);
   const float *Bf = L->Bf.as<float>(), *Ml = L->Ml.as<float>();
