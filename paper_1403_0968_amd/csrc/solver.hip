@@ -39,6 +39,37 @@ constexpr int RT = 256;           // threads of the vector kernels
 static_assert(VCH % RT == 0, "chunk must be a multiple of the block");
 
 // --------------------------------------------------------------------------
+// per-solve sums of the per-item partials
+// --------------------------------------------------------------------------
+// Thread t of a workgroup adds part[a * stride + q] for q = begin + t,
+// begin + t + RT, ... < end into acc[a], in that order (the same order as a
+// plain loop, so the sums are unchanged); the loads are issued PF at a time,
+// so that the single workgroup of a scalar kernel does not wait for one load
+// after the other.
+template <int NA>
+__device__ inline void strided_sums(const double *__restrict__ part, int stride,
+                                    int begin, int end, double (&acc)[NA]) {
+  constexpr int PF = 8;
+#pragma unroll
+  for (int a = 0; a < NA; ++a) acc[a] = 0.0;
+  int q = begin + (int)threadIdx.x;
+  for (; q + (PF - 1) * RT < end; q += PF * RT) {
+    double v[NA][PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) v[a][u] = part[a * stride + q + u * RT];
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+#pragma unroll
+      for (int a = 0; a < NA; ++a) acc[a] += v[a][u];
+  }
+  for (; q < end; q += RT)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[a] += part[a * stride + q];
+}
+
+// --------------------------------------------------------------------------
 // vector kernels (persistent over VecItem lists)
 // --------------------------------------------------------------------------
 template <class TV> __device__ inline TV *vec(const BatchSolve &s, int v) {
@@ -94,9 +125,9 @@ __global__ void __launch_bounds__(RT)
   __shared__ double sm[RT / 64];
   const int s = blockIdx.x;
   if (st[s].done != 0) return;
-  double a = 0.0;
-  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) a += part[q];
-  const double pw = block_sum<RT>(a, sm);
+  double acc[1];
+  strided_sums<1>(part, 0, vbeg[s], vbeg[s + 1], acc);
+  const double pw = block_sum<RT>(acc[0], sm);
   if (threadIdx.x == 0) {
     st[s].pw = pw;
     if (!(pw > 0.0) || !isfinite(pw))
@@ -147,11 +178,9 @@ __global__ void __launch_bounds__(RT)
   __shared__ double sm[RT / 64];
   const int s = blockIdx.x;
   if (st[s].done != 0) return;
-  double a = 0.0, b = 0.0;
-  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
-    a += part[q];
-    b += part[nitems + q];
-  }
+  double acc[2];
+  strided_sums<2>(part, nitems, vbeg[s], vbeg[s + 1], acc);
+  const double a = acc[0], b = acc[1];
   const double rz = block_sum<RT>(a, sm);
   const double rr = block_sum<RT>(b, sm);
   if (threadIdx.x == 0) {
@@ -247,12 +276,9 @@ __global__ void __launch_bounds__(RT)
     }
     return;
   }
-  double a = 0.0, b = 0.0, d = 0.0;
-  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
-    a += part[q];
-    b += part[nitems + q];
-    d += part[2 * nitems + q];
-  }
+  double acc[3];
+  strided_sums<3>(part, nitems, vbeg[s], vbeg[s + 1], acc);
+  const double a = acc[0], b = acc[1], d = acc[2];
   const double rz = block_sum<RT>(a, sm);
   const double rr = block_sum<RT>(b, sm);
   const double bb = block_sum<RT>(d, sm);
@@ -312,11 +338,9 @@ __global__ void __launch_bounds__(RT)
   __shared__ double sm[RT / 64];
   const int s = blockIdx.x;
   if (!active[s]) return;
-  double a = 0.0, b = 0.0;
-  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
-    a += part[q];
-    b += part[nitems + q];
-  }
+  double acc[2];
+  strided_sums<2>(part, nitems, vbeg[s], vbeg[s + 1], acc);
+  const double a = acc[0], b = acc[1];
   const double s0 = block_sum<RT>(a, sm);
   const double s1 = block_sum<RT>(b, sm);
   if (threadIdx.x == 0) {
@@ -444,12 +468,9 @@ __global__ void __launch_bounds__(RT)
   __shared__ double sm[RT / 64];
   const int s = blockIdx.x;
   if (st[s].done != 0) return;
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) {
-    a += part[q];
-    b += part[nitems + q];
-    c += part[2 * nitems + q];
-  }
+  double acc[3];
+  strided_sums<3>(part, nitems, vbeg[s], vbeg[s + 1], acc);
+  const double a = acc[0], b = acc[1], c = acc[2];
   const double rz = block_sum<RT>(a, sm);
   const double zw = block_sum<RT>(b, sm);
   const double rr = block_sum<RT>(c, sm);
@@ -476,9 +497,9 @@ __global__ void __launch_bounds__(RT)
                  const int32_t *__restrict__ vbeg) {
   __shared__ double sm[RT / 64];
   const int s = blockIdx.x;
-  double a = 0.0;
-  for (int q = vbeg[s] + threadIdx.x; q < vbeg[s + 1]; q += RT) a += part[q];
-  const double rz = block_sum<RT>(a, sm);
+  double acc[1];
+  strided_sums<1>(part, 0, vbeg[s], vbeg[s + 1], acc);
+  const double rz = block_sum<RT>(acc[0], sm);
   if (threadIdx.x == 0) {
     st[s].rz = rz;
     if (st[s].done == 0 && !isfinite(rz)) st[s].done = 2;
