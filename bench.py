@@ -8,7 +8,8 @@ mapped by x + 0.05 (sin 2 pi y sin 2 pi z, and cyclic).
   resident in HBM; one step = one application of the local operator to the
   whole mesh (the kernel the paper times in section 4.2.2).
 * roofline: the operator kernel's average launch duration from HIP events on
-  the launch stream; algorithmic bytes 64 B per local node (u 8 + six
+  the launch stream after at least 0.2 s of warm-up launches; algorithmic
+  bytes 64 B per local node (u 8 + six
   geometric factors 48 + w 8) against the 8 TB/s HBM peak.
 * pcg: wall time to relative residual 1e-8 of plain FP64 Jacobi-PCG and of
   FP64 refinement around FP32 / BF16-operator inner PCG, same mesh, RHS from
@@ -94,9 +95,18 @@ def make_input(sem, torch, h, nL, nG, seed=0):
     return U[l2g.long()].contiguous()
 
 
-def time_ax(sem, torch, h, prec, u, w, steps, warmup):
-    for _ in range(warmup):
+def time_ax(sem, torch, h, prec, u, w, steps, warmup, min_warm_s=0.2):
+    """ms per launch of `steps` back-to-back launches, HIP events on the
+    launch stream (torch's current stream, which sem_ax uses).  Warm-up:
+    `warmup` launches, continued until at least min_warm_s of GPU time has
+    passed, so that the clocks have settled before the timed region."""
+    t0 = time.perf_counter()
+    n = 0
+    while n < warmup or time.perf_counter() - t0 < min_warm_s:
         sem.sem_ax(h, prec, u, w)
+        n += 1
+        if n % 50 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
