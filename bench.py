@@ -29,6 +29,11 @@ mapped by x + 0.05 (sin 2 pi y sin 2 pi z, and cyclic).
   N ~ U{3, 5, 7}, sine-cyclic mapping, right-hand sides seeded 1000 + s,
   FP32 operator inside FP64 refinement to 1e-10: one batched solve against a
   loop of 256 individual solves.
+* order_sweep: the FP64 operator at every order N = 1..8 (the x-axis of the
+  paper's operator figures, reported in GFLOP/s and GB/s as there) on cubic
+  sine-cyclic meshes of about 16.8M local nodes, flops 12(N+1)+15 per node;
+  and the screened operator (alpha = 1, the mass term of equation semPDE)
+  on the 32^3, N = 7 mesh, 72 B per node in FP64.
 * cpu_baseline: the FP64 CPU oracle's operator on a bounded sample of the
   same mesh (test infrastructure, timed here only as a reported baseline).
 
@@ -116,6 +121,47 @@ def time_ax(sem, torch, h, prec, u, w, steps, warmup, min_warm_s=0.2):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps  # ms per launch
+
+
+def bench_order_sweep(sem, torch, steps, warmup, target_nodes=NE ** 3 * 512):
+    """FP64 operator at N = 1..8 on cubic meshes of ~target_nodes local
+    nodes; then the screened operator on the benchmark mesh."""
+    out = {}
+    for N in range(1, 9):
+        n1 = N + 1
+        ne = max(1, round((target_nodes / n1 ** 3) ** (1.0 / 3.0)))
+        h = sem.sem_setup(N, ne, ne, ne, mapping=sem.SEM_MAP_SINE_CYCLIC)
+        E, nL, nG = sem.sem_query(h)
+        u = make_input(sem, torch, h, nL, nG)
+        w = torch.empty_like(u)
+        ms = time_ax(sem, torch, h, sem.SEM_FP64, u, w, steps, warmup)
+        sem.sem_destroy(h)
+        del u, w
+        t = ms * 1e-3
+        out[f"N{N}"] = {"elements": E, "n_local": nL, "us_per_launch": ms * 1e3,
+                        "gdofs": nL / t / 1e9,
+                        "gflops": (12 * n1 + 15) * nL / t / 1e9,
+                        "alg_GBs": 64 * nL / t / 1e9,
+                        "frac_hbm": 64 * nL / t / 1e9 / HBM_PEAK_GBS}
+        log(f"[sweep] N={N} {ne}^3: {ms * 1e3:.1f} us, "
+            f"{out[f'N{N}']['gflops']:.0f} GFLOP/s, {out[f'N{N}']['alg_GBs']:.0f} GB/s")
+    h = sem.sem_setup(ORDER, NE, NE, NE, mapping=sem.SEM_MAP_SINE_CYCLIC, alpha=1.0)
+    E, nL, nG = sem.sem_query(h)
+    u = make_input(sem, torch, h, nL, nG)
+    w = torch.empty_like(u)
+    ms = time_ax(sem, torch, h, sem.SEM_FP64, u, w, steps, warmup)
+    u32, w32 = u.float(), torch.empty(nL, dtype=torch.float32, device=u.device)
+    ms32 = time_ax(sem, torch, h, sem.SEM_FP32, u32, w32, steps, warmup)
+    sem.sem_destroy(h)
+    out["screened_N7_32cubed"] = {
+        "alpha": 1.0,
+        "fp64_us_per_launch": ms * 1e3, "fp64_alg_GBs": 72 * nL / (ms * 1e-3) / 1e9,
+        "fp64_frac_hbm": 72 * nL / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "fp32_us_per_launch": ms32 * 1e3,
+        "fp32_alg_GBs": 36 * nL / (ms32 * 1e-3) / 1e9,
+        "fp32_frac_hbm": 36 * nL / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    log(f"[sweep] screened 32^3 N=7: fp64 {ms * 1e3:.1f} us, fp32 {ms32 * 1e3:.1f} us")
+    return out
 
 
 def bench_pcg(sem, torch, h, nL, nG, rtol=1e-8):
@@ -323,6 +369,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--ax-only", action="store_true",
                     help="only the FP64 operator launches (for counter runs)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -386,6 +433,9 @@ def main():
 
     pcg = None if args.no_pcg else bench_pcg(sem, torch, h, nL, nG)
     sem.sem_destroy(h)
+    del u, w, u32, w32, ub
+    sweep = (None if args.no_sweep
+             else bench_order_sweep(sem, torch, args.steps, args.warmup))
     learned = None if args.no_learned else bench_learned(sem, torch)
     batch = None if args.no_batch else bench_batch(sem, torch)
     cpu = None if args.no_cpu else cpu_baseline()
@@ -413,6 +463,7 @@ def main():
                      "traffic": traffic},
         "cpu_baseline": cpu,
         "sem_ax_low_precision": extra,
+        "order_sweep": sweep,
         "pcg": pcg,
         "learned": learned,
         "batch": batch,

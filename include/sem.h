@@ -9,7 +9,11 @@
  * semOperator) with continuous piecewise tensor-product polynomials of degree
  * N on hexahedra, Lagrange basis on the (N+1) Gauss-Lobatto-Legendre points
  * per direction, GLL quadrature, and homogeneous Dirichlet conditions imposed
- * by masking.  alpha must be 0 in this version.
+ * by masking.  The mass term of equation semOperator is lumped by the GLL
+ * quadrature (section 4.2.1, discrete orthogonality): it adds
+ * H_l u_l with H_l = alpha(X_l) B_l, B_l = w_i w_j w_k J at local node l, to
+ * the local operator.  alpha(X) >= 0; with alpha > 0 the assembled operator
+ * is symmetric positive definite also without Dirichlet faces.
  *
  * Conventions shared by every call:
  *   - n1 = N+1; element e = ex + Ex*(ey + Ey*ez); element-local node
@@ -86,7 +90,9 @@ typedef struct {
   int32_t dirichlet;    /* 1: homogeneous Dirichlet on the 6 outer faces;
                            0: pure Neumann (operator checks only) */
   int32_t mapping;      /* a sem_mapping */
-  double alpha;         /* mass coefficient of semPDE; must be 0 */
+  double alpha;         /* mass coefficient alpha(X) of semPDE when
+                           alpha_nodal is NULL: finite, >= 0; 0 leaves the
+                           mass term out (no extra bytes per node) */
   /* kappa(X) = exp(sigma sqrt(2/M) sum_m cos(omega_m . X + b_m)) when
    * kappa_nfeat = M > 0 (random Fourier features of a Gaussian field),
    * kappa = 1 when kappa_nfeat == 0. */
@@ -94,6 +100,10 @@ typedef struct {
   const double *kappa_omega; /* [M][3] */
   const double *kappa_b;     /* [M] */
   double kappa_sigma;
+  /* alpha(X) at every local node, n_local values in E-vector order (equal
+   * on the copies of a global node), finite and >= 0; NULL: the constant
+   * alpha above.  Read during sem_setup only. */
+  const double *alpha_nodal;
 } sem_mesh_desc;
 
 /* Right-hand side f(X) for sem_rhs.  HOST pointers. */
@@ -145,7 +155,8 @@ typedef struct {
  * coordinates and the six geometric factors per node (G_ab =
  * w_i w_j w_k J kappa grad r_a . grad r_b, the G^T G metric of section 4.2.1
  * precomputed per elemental node, FP64 with FP32/BF16 copies), the lumped
- * mass B = w_i w_j w_k J and the Jacobi diagonal.  Synchronises `stream`
+ * mass B = w_i w_j w_k J, the mass factor H = alpha(X) B when alpha != 0
+ * and the Jacobi diagonal (stiffness plus H).  Synchronises `stream`
  * before returning.  On failure *out is NULL. */
 sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_handle **out);
 sem_status sem_destroy(sem_handle *h);
@@ -166,11 +177,13 @@ sem_status sem_query(const sem_handle *h, int64_t *n_elements,
  *   SEM_ARR_MASS    double [n_local]   lumped mass B (unassembled)
  *   SEM_ARR_DIAG    double [n_local]   unassembled local-matrix diagonal
  *   SEM_ARR_DINV    double [n_global]  inverse assembled diagonal, 0 on
- *                                      Dirichlet nodes */
+ *                                      Dirichlet nodes
+ *   SEM_ARR_HMASS   double [n_local]   mass factor H = alpha(X) B
+ *                                      (SEM_ERR_STATE when alpha = 0) */
 typedef enum {
   SEM_ARR_L2G = 0, SEM_ARR_PERM = 1, SEM_ARR_OFFSETS = 2, SEM_ARR_MULT = 3,
   SEM_ARR_MASK = 4, SEM_ARR_COORDS = 5, SEM_ARR_GEOM = 6, SEM_ARR_MASS = 7,
-  SEM_ARR_DIAG = 8, SEM_ARR_DINV = 9
+  SEM_ARR_DIAG = 8, SEM_ARR_DINV = 9, SEM_ARR_HMASS = 10
 } sem_array;
 sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
                       int64_t dst_bytes, void *stream);
@@ -185,7 +198,10 @@ sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
  * matrix and FP32 accumulation, VALU).  SEM_BF16_MFMA: u bf16 (16-byte
  * aligned), w float; the six contractions on the matrix cores with the
  * split derivative matrix (N <= 7).  SEM_BF16_PLAIN_D: the same with D
- * rounded to BF16.  u_L and w_L must not overlap. */
+ * rounded to BF16.  When the mesh has a mass term (alpha != 0) every
+ * precision adds H o u_L (H = alpha(X) B, stored in the precision of G; the
+ * lumped mass operator of equation semOperator), 8 / 4 / 2 more bytes per
+ * node.  u_L and w_L must not overlap. */
 sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
                   void *stream);
 
@@ -223,7 +239,9 @@ sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *opts,
  * persistent kernels over (solve, element tile) and (solve, node chunk)
  * work items, captured once in a HIP graph and replayed check_every
  * iterations at a time; finished solves drop out on the device.  A solve
- * gives bit-identical results alone (sem_pcg_solve) or inside any batch. */
+ * gives bit-identical results alone (sem_pcg_solve) or inside any batch.
+ * A batch of more than one solve needs meshes without a mass term
+ * (alpha = 0): SEM_ERR_ARG otherwise. */
 sem_status sem_batch_create(sem_handle *const *handles, int32_t n,
                             sem_batch **out);
 sem_status sem_batch_destroy(sem_batch *b);
@@ -324,7 +342,9 @@ sem_status sem_mlp_load(const char *path, sem_mlp **out);
  * the interior nodes), and the correction is damping B M_e B^T r_I on the
  * interior nodes (symmetric positive semi-definite).  The coarse operators
  * are computed from the network when it is attached and again before a
- * solve when its parameters have changed. */
+ * solve when its parameters have changed.  The coarse targets are those of
+ * the stiffness operator: meshes with a mass term (alpha != 0) are refused
+ * with SEM_ERR_STATE, here and in sem_learn_train. */
 sem_status sem_learn_attach(sem_handle *h, sem_mlp *net);
 
 typedef struct {

@@ -70,14 +70,14 @@ def lib():
         L.orc_kappa_rff.argtypes = [_i64, _dp, C.c_int, _dp, _dp, C.c_double,
                                     _dp]
         L.orc_apply_global.argtypes = [C.c_int, _i64, _i64, _ip, _up, _dp, _dp,
-                                       _dp, _dp]
+                                       C.c_void_p, _dp, _dp]
         L.orc_pcg.argtypes = [C.c_int, _i64, _i64, _ip, _up, _dp, _dp,
-                              C.c_void_p, _dp, _dp, C.c_double, C.c_int,
-                              C.POINTER(C.c_int), _dp]
-        L.orc_pcg.restype = C.c_int
-        L.orc_fcg.argtypes = [C.c_int, _i64, _i64, _ip, _up, _dp, _dp,
                               C.c_void_p, C.c_void_p, _dp, _dp, C.c_double,
                               C.c_int, C.POINTER(C.c_int), _dp]
+        L.orc_pcg.restype = C.c_int
+        L.orc_fcg.argtypes = [C.c_int, _i64, _i64, _ip, _up, _dp, _dp,
+                              C.c_void_p, C.c_void_p, C.c_void_p, _dp, _dp,
+                              C.c_double, C.c_int, C.POINTER(C.c_int), _dp]
         L.orc_fcg.restype = C.c_int
     return _lib
 
@@ -135,6 +135,9 @@ class Mesh:
     B: np.ndarray        # (nL,)
     minJ: float
     kappa: np.ndarray | None
+    # lumped mass term of the weak form (section 4.2.1): H = alpha(X) B per
+    # local node, or None when alpha = 0
+    H: np.ndarray | None = None
 
     @property
     def n1(self):
@@ -201,9 +204,12 @@ def geom(N, E, w, D, X, kappa=None):
     return G.reshape(E, 6, n3), B, mj.value
 
 
-def mesh(N, ex, ey, ez, mapping=MAP_AFFINE, dirichlet=1, kappa_params=None):
+def mesh(N, ex, ey, ez, mapping=MAP_AFFINE, dirichlet=1, kappa_params=None,
+         alpha=0.0, alpha_nodal=None):
     """Build everything the operator needs.  ``kappa_params`` is
-    ``(omega[M,3], b[M], sigma)`` for kappa = exp(GRF) or None (kappa = 1)."""
+    ``(omega[M,3], b[M], sigma)`` for kappa = exp(GRF) or None (kappa = 1).
+    The mass coefficient alpha(X) of the screened equation is the constant
+    ``alpha`` or, when given, the nodal array ``alpha_nodal`` (E-vector)."""
     xi, w = gll(N)
     D = dmat(N, xi)
     l2g, perm, offsets, mult, bmask = maps(N, ex, ey, ez, dirichlet)
@@ -212,8 +218,20 @@ def mesh(N, ex, ey, ez, mapping=MAP_AFFINE, dirichlet=1, kappa_params=None):
     if kappa_params is not None:
         kappa = kappa_rff(X, *kappa_params)
     G, B, mj = geom(N, ex * ey * ez, w, D, X, kappa)
+    H = None
+    if alpha_nodal is not None:
+        H = _f64(alpha_nodal).reshape(-1) * B
+    elif alpha != 0.0:
+        H = float(alpha) * B
     return Mesh(N, ex, ey, ez, int(dirichlet), int(mapping), xi, w, D, l2g,
-                perm, offsets, mult, bmask, X, G, B, mj, kappa)
+                perm, offsets, mult, bmask, X, G, B, mj, kappa, H)
+
+
+def _hptr(m: Mesh):
+    """C pointer to the mass factor (None without a mass term)."""
+    if m.H is None:
+        return None
+    return _f64(m.H).ctypes.data_as(C.c_void_p)
 
 
 # ----------------------------------------------------------------------------
@@ -228,6 +246,8 @@ def ax(m: Mesh, u, E=None):
     assert u.shape[0] == E * m.n1 ** 3
     w = np.zeros_like(u)
     lib().orc_ax(m.N, E, _f64(m.D).reshape(-1), _f64(m.G[:E]).reshape(-1), u, w)
+    if m.H is not None:
+        w += m.H[: u.shape[0]] * u
     return w
 
 
@@ -246,6 +266,8 @@ def ax_abs(m: Mesh, u):
     w = np.zeros_like(u)
     lib().orc_ax_abs(m.N, m.E, _f64(m.D).reshape(-1), _f64(m.G).reshape(-1), u,
                      w)
+    if m.H is not None:
+        w += np.abs(m.H) * np.abs(u)
     return w
 
 
@@ -259,6 +281,8 @@ def gs(m: Mesh, v):
 def local_diag(m: Mesh):
     d = np.zeros(m.nL)
     lib().orc_diag(m.N, m.E, _f64(m.D).reshape(-1), _f64(m.G).reshape(-1), d)
+    if m.H is not None:
+        d += m.H
     return d
 
 
@@ -316,7 +340,7 @@ def apply_global(m: Mesh, x):
     y = np.zeros(m.nG)
     lib().orc_apply_global(m.N, m.E, m.nG, m.l2g, m.bmask,
                            _f64(m.D).reshape(-1), _f64(m.G).reshape(-1),
-                           _f64(x), y)
+                           _hptr(m), _f64(x), y)
     return y
 
 
@@ -332,7 +356,7 @@ def pcg(m: Mesh, b_global, rtol, maxit, jacobi=True, x0=None):
         dinv = jacobi_dinv_global(m)
         dv = dinv.ctypes.data_as(C.c_void_p)
     st = lib().orc_pcg(m.N, m.E, m.nG, m.l2g, m.bmask, _f64(m.D).reshape(-1),
-                       _f64(m.G).reshape(-1), dv, _f64(b_global), x,
+                       _f64(m.G).reshape(-1), _hptr(m), dv, _f64(b_global), x,
                        float(rtol), int(maxit), C.byref(it), hist)
     return x, st, it.value, hist[: it.value + 1]
 
@@ -356,7 +380,8 @@ def fcg(m: Mesh, b_global, precond, rtol, maxit, x0=None):
 
     fn = _PREC_FN(cb)
     st = lib().orc_fcg(m.N, m.E, nG, m.l2g, m.bmask, _f64(m.D).reshape(-1),
-                       _f64(m.G).reshape(-1), C.cast(fn, C.c_void_p), None,
+                       _f64(m.G).reshape(-1), _hptr(m), C.cast(fn, C.c_void_p),
+                       None,
                        _f64(b_global), x, float(rtol), int(maxit),
                        C.byref(it), hist)
     return x, st, it.value, hist[: it.value + 1]
@@ -413,13 +438,39 @@ def brute_element_matrix(N, xi, Ge):
     return A
 
 
+def lagrange_values_at_nodes(xi):
+    """V[a][m] = l_a(xi_m), each Lagrange polynomial evaluated from its
+    monomial coefficients (the identity up to rounding)."""
+    n1 = len(xi)
+    out = np.zeros((n1, n1))
+    for a in range(n1):
+        c = np.polynomial.polynomial.polyfromroots(np.delete(xi, a))
+        c = c / np.polynomial.polynomial.polyval(xi[a], c)
+        out[a] = np.polynomial.polynomial.polyval(xi, c)
+    return out
+
+
+def brute_element_mass(N, xi, ae_wJ):
+    """(M_e)_{pq} = sum over quadrature nodes nu of alpha w J (nu) phi_p(nu)
+    phi_q(nu): the mass operator of the weak form under GLL quadrature, with
+    the basis values evaluated explicitly (its diagonal form is the lumping
+    the paper derives from discrete orthogonality, not assumed here).
+    ``ae_wJ`` holds alpha w_i w_j w_k J at the element's nodes."""
+    V = lagrange_values_at_nodes(np.asarray(xi))
+    Phi = np.kron(V.T, np.kron(V.T, V.T))  # [nu, p] = phi_p(nu)
+    return Phi.T @ (np.asarray(ae_wJ)[:, None] * Phi)
+
+
 def assemble_sparse(m: Mesh, masked=False):
-    """Global sparse stiffness from brute-force element matrices."""
+    """Global sparse operator (stiffness, plus the mass term when the mesh has
+    one) from brute-force element matrices."""
     import scipy.sparse as sp
     n3 = m.n1 ** 3
     rows, cols, vals = [], [], []
     for e in range(m.E):
         Ae = brute_element_matrix(m.N, m.xi, m.G[e])
+        if m.H is not None:
+            Ae = Ae + brute_element_mass(m.N, m.xi, m.H[e * n3:(e + 1) * n3])
         g = m.l2g[e * n3:(e + 1) * n3]
         rows.append(np.repeat(g, n3))
         cols.append(np.tile(g, n3))

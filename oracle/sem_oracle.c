@@ -393,12 +393,15 @@ void orc_kappa_rff(int64_t n, const double *X, int M, const double *omega,
 
 void orc_apply_global(int N, int64_t E, int64_t nG, const int32_t *l2g,
                       const uint8_t *bmask, const double *D, const double *G,
-                      const double *x, double *y) {
+                      const double *H, const double *x, double *y) {
   const int64_t n1 = N + 1, nL = E * n1 * n1 * n1;
-  double *xl = (double *)malloc(nL * sizeof(double));
+  double *xl = (double *)calloc((size_t)nL, sizeof(double));
   double *yl = (double *)malloc(nL * sizeof(double));
   for (int64_t l = 0; l < nL; ++l) xl[l] = bmask[l] ? 0.0 : x[l2g[l]];
   orc_ax(N, E, D, G, xl, yl);
+  /* lumped mass term of the weak form: alpha(X) w J at each local node */
+  if (H)
+    for (int64_t l = 0; l < nL; ++l) yl[l] += H[l] * xl[l];
   for (int64_t g = 0; g < nG; ++g) y[g] = 0.0;
   for (int64_t l = 0; l < nL; ++l) y[l2g[l]] += yl[l];
   for (int64_t l = 0; l < nL; ++l)
@@ -417,14 +420,14 @@ static double dot(int64_t n, const double *a, const double *b) {
  * Iterative Methods, Algorithm 9.1) with x0 taken from x. */
 int orc_pcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
             const uint8_t *bmask, const double *D, const double *G,
-            const double *dinv, const double *b, double *x, double rtol,
-            int maxit, int *iters, double *hist) {
+            const double *H, const double *dinv, const double *b, double *x,
+            double rtol, int maxit, int *iters, double *hist) {
   double *r = (double *)malloc(nG * sizeof(double));
   double *z = (double *)malloc(nG * sizeof(double));
   double *p = (double *)malloc(nG * sizeof(double));
   double *w = (double *)malloc(nG * sizeof(double));
   int status = 1, k = 0;
-  orc_apply_global(N, E, nG, l2g, bmask, D, G, x, w);
+  orc_apply_global(N, E, nG, l2g, bmask, D, G, H, x, w);
   for (int64_t g = 0; g < nG; ++g) r[g] = b[g] - w[g];
   const double bnorm = sqrt(dot(nG, b, b));
   double rnorm = sqrt(dot(nG, r, r));
@@ -437,7 +440,7 @@ int orc_pcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
   for (int64_t g = 0; g < nG; ++g) p[g] = z[g];
   double rz = dot(nG, r, z);
   for (k = 1; k <= maxit; ++k) {
-    orc_apply_global(N, E, nG, l2g, bmask, D, G, p, w);
+    orc_apply_global(N, E, nG, l2g, bmask, D, G, H, p, w);
     double pw = dot(nG, p, w);
     if (!(pw > 0)) {
       status = 2;
@@ -475,14 +478,14 @@ done:
  * and alpha = (r_k, z_k) / (p_k, A p_k). */
 int orc_fcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
             const uint8_t *bmask, const double *D, const double *G,
-            orc_precond_fn prec, void *ctx, const double *b, double *x,
-            double rtol, int maxit, int *iters, double *hist) {
+            const double *H, orc_precond_fn prec, void *ctx, const double *b,
+            double *x, double rtol, int maxit, int *iters, double *hist) {
   double *r = (double *)malloc(nG * sizeof(double));
   double *z = (double *)malloc(nG * sizeof(double));
   double *p = (double *)malloc(nG * sizeof(double));
   double *w = (double *)malloc(nG * sizeof(double));
   int status = 1, k = 0;
-  orc_apply_global(N, E, nG, l2g, bmask, D, G, x, w);
+  orc_apply_global(N, E, nG, l2g, bmask, D, G, H, x, w);
   for (int64_t g = 0; g < nG; ++g) r[g] = b[g] - w[g];
   const double bnorm = sqrt(dot(nG, b, b));
   double rnorm = sqrt(dot(nG, r, r));
@@ -494,7 +497,7 @@ int orc_fcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
   prec(r, z, ctx);
   for (int64_t g = 0; g < nG; ++g) p[g] = z[g];
   for (k = 1; k <= maxit; ++k) {
-    orc_apply_global(N, E, nG, l2g, bmask, D, G, p, w);
+    orc_apply_global(N, E, nG, l2g, bmask, D, G, H, p, w);
     double pw = dot(nG, p, w);
     double rz = dot(nG, r, z);
     if (!(pw > 0)) {

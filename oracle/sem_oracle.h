@@ -88,25 +88,27 @@ void orc_src_sine(int64_t n, const double *X, double *f);
 void orc_kappa_rff(int64_t n, const double *X, int M, const double *omega,
                    const double *b, double sigma, double *kappa);
 
-/* Unique-vector operator y = M Q^T A_L Q M x (x, y of length nG). */
+/* Unique-vector operator y = M Q^T A_L Q M x (x, y of length nG).  H, if
+ * not NULL, is the lumped mass term alpha(X) B per local node, added to the
+ * local operator (A_L = D^T G D + diag(H)). */
 void orc_apply_global(int N, int64_t E, int64_t nG, const int32_t *l2g,
                       const uint8_t *bmask, const double *D, const double *G,
-                      const double *x, double *y);
+                      const double *H, const double *x, double *y);
 
 /* Preconditioned CG on unique vectors (Jacobi when dinv != NULL).  hist, if
  * not NULL, receives ||r_k||/||b|| for k = 0..iters.  Returns 0 on
  * convergence, 1 when maxit is reached, 2 on breakdown. */
 int orc_pcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
             const uint8_t *bmask, const double *D, const double *G,
-            const double *dinv, const double *b, double *x, double rtol,
-            int maxit, int *iters, double *hist);
+            const double *H, const double *dinv, const double *b, double *x,
+            double rtol, int maxit, int *iters, double *hist);
 
 /* Flexible CG with an arbitrary preconditioner callback z = P(r). */
 typedef void (*orc_precond_fn)(const double *r, double *z, void *ctx);
 int orc_fcg(int N, int64_t E, int64_t nG, const int32_t *l2g,
             const uint8_t *bmask, const double *D, const double *G,
-            orc_precond_fn prec, void *ctx, const double *b, double *x,
-            double rtol, int maxit, int *iters, double *hist);
+            const double *H, orc_precond_fn prec, void *ctx, const double *b,
+            double *x, double rtol, int maxit, int *iters, double *hist);
 
 #ifdef __cplusplus
 }

@@ -25,7 +25,9 @@
 // GATHER = true reads u from a unique-node vector (the Q of the assembled
 // operator), used inside the solvers; the unique index of each node comes
 // from the closed-form box numbering, so the gather adds no index traffic
-// and its loads issue with the others.
+// and its loads issue with the others.  With a mass term (alpha != 0) the
+// standalone operator also streams H = alpha(X) B and adds H o u (the lumped
+// mass operator of equation semOperator): 72 B per node in FP64.
 //
 // Two kernels share one element routine: k_ax (one tile of elements per
 // workgroup, the standalone operator) and k_bax (persistent workgroups
@@ -46,56 +48,61 @@ template <int N1, int BYTES> struct AxShape {
   static constexpr int THREADS = EPB * NP;
 };
 
-template <int N1, class TU, class TG, class TW, class TC, bool GATHER, bool NTW>
+template <int N1, class TU, class TG, class TW, class TC, bool GATHER, bool NTW,
+          bool MASS>
 __global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
     k_ax(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
          const TU *__restrict__ u, TW *__restrict__ w,
-         const Box *__restrict__ box, const int32_t *__restrict__ stop) {
+         const Box *__restrict__ box, const int32_t *__restrict__ stop,
+         const TG *__restrict__ H) {
   using S = AxShape<N1, sizeof(TC)>;
   __shared__ TC smem[lds_words<N1>(S::EPB)];
   if (stop != nullptr && *stop != 0) return;  // uniform: solver finished
-  ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW>(
-      threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, box, smem);
+  ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW, MASS>(
+      threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, box, smem, H);
+}
+
+template <int N1, class TU, class TG, class TW, class TC>
+static void launch_nt(int64_t E, const void *D, const void *G, const void *H,
+                      const void *u, void *w, hipStream_t s) {
+  using S = AxShape<N1, sizeof(TC)>;
+  const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+  if (blocks == 0) return;
+  const dim3 grid((unsigned)blocks), block(S::THREADS);
+  if (H != nullptr)
+    hipLaunchKernelGGL((k_ax<N1, TU, TG, TW, TC, false, true, true>), grid, block,
+                       0, s, E, (const TC *)D, (const TG *)G, (const TU *)u,
+                       (TW *)w, (const Box *)nullptr, (const int32_t *)nullptr,
+                       (const TG *)H);
+  else
+    hipLaunchKernelGGL((k_ax<N1, TU, TG, TW, TC, false, true, false>), grid,
+                       block, 0, s, E, (const TC *)D, (const TG *)G,
+                       (const TU *)u, (TW *)w, (const Box *)nullptr,
+                       (const int32_t *)nullptr, (const TG *)nullptr);
 }
 
 template <int N1>
 static void launch_n(int prec, int64_t E, const void *D, const void *G,
-                     const void *u, void *w, hipStream_t s) {
-  using S8 = AxShape<N1, 8>;
-  using S4 = AxShape<N1, 4>;
-  const int epb = prec == SEM_FP64 ? S8::EPB : S4::EPB;
-  const int threads = prec == SEM_FP64 ? S8::THREADS : S4::THREADS;
-  const int64_t blocks = (E + epb - 1) / epb;
-  if (blocks == 0) return;
-  dim3 grid((unsigned)blocks), block(threads);
+                     const void *H, const void *u, void *w, hipStream_t s) {
   if (prec == SEM_FP64)
-    hipLaunchKernelGGL((k_ax<N1, double, double, double, double, false, true>),
-                       grid, block, 0, s, E, (const double *)D,
-                       (const double *)G, (const double *)u, (double *)w,
-                       (const Box *)nullptr, (const int32_t *)nullptr);
+    launch_nt<N1, double, double, double, double>(E, D, G, H, u, w, s);
   else if (prec == SEM_FP32)
-    hipLaunchKernelGGL((k_ax<N1, float, float, float, float, false, true>), grid,
-                       block, 0, s, E, (const float *)D, (const float *)G,
-                       (const float *)u, (float *)w, (const Box *)nullptr,
-                       (const int32_t *)nullptr);
+    launch_nt<N1, float, float, float, float>(E, D, G, H, u, w, s);
   else
-    hipLaunchKernelGGL((k_ax<N1, uint16_t, uint16_t, float, float, false, true>),
-                       grid, block, 0, s, E, (const float *)D,
-                       (const uint16_t *)G, (const uint16_t *)u, (float *)w,
-                       (const Box *)nullptr, (const int32_t *)nullptr);
+    launch_nt<N1, uint16_t, uint16_t, float, float>(E, D, G, H, u, w, s);
 }
 
 void launch_ax(int N, int prec, int64_t E, const void *D, const void *G,
-               const void *u, void *w, hipStream_t s) {
+               const void *H, const void *u, void *w, hipStream_t s) {
   switch (N) {
-    case 1: launch_n<2>(prec, E, D, G, u, w, s); break;
-    case 2: launch_n<3>(prec, E, D, G, u, w, s); break;
-    case 3: launch_n<4>(prec, E, D, G, u, w, s); break;
-    case 4: launch_n<5>(prec, E, D, G, u, w, s); break;
-    case 5: launch_n<6>(prec, E, D, G, u, w, s); break;
-    case 6: launch_n<7>(prec, E, D, G, u, w, s); break;
-    case 7: launch_n<8>(prec, E, D, G, u, w, s); break;
-    case 8: launch_n<9>(prec, E, D, G, u, w, s); break;
+    case 1: launch_n<2>(prec, E, D, G, H, u, w, s); break;
+    case 2: launch_n<3>(prec, E, D, G, H, u, w, s); break;
+    case 3: launch_n<4>(prec, E, D, G, H, u, w, s); break;
+    case 4: launch_n<5>(prec, E, D, G, H, u, w, s); break;
+    case 5: launch_n<6>(prec, E, D, G, H, u, w, s); break;
+    case 6: launch_n<7>(prec, E, D, G, H, u, w, s); break;
+    case 7: launch_n<8>(prec, E, D, G, H, u, w, s); break;
+    case 8: launch_n<9>(prec, E, D, G, H, u, w, s); break;
     default: fail(SEM_ERR_ARG, "sem_ax: N must be in 1..8");
   }
   SEM_HIP(hipGetLastError());

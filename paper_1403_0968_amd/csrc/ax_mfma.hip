@@ -22,7 +22,9 @@
 // The transposed contractions use D^T the same way and accumulate w through
 // the C operand (r, then s, then t), staged in LDS in [k][j][i] order.  The
 // metric step between them (fluxes = G grad u) is FP32 on the VALU, one lane
-// per (i,j) column, and the fluxes are rounded to BF16 for the MFMAs.
+// per (i,j) column, and the fluxes are rounded to BF16 for the MFMAs.  With a
+// mass term the lumped H o u (H = alpha(X) B in BF16) is added in FP32 as the
+// result leaves LDS.
 #include "ax_tile.h"
 
 namespace sem {
@@ -208,7 +210,8 @@ template <int N1, bool SPLIT>
 __global__ void __launch_bounds__(64 * MW)
     k_ax_mfma(int64_t E, const uint16_t *__restrict__ Dhi,
               const uint16_t *__restrict__ Dlo, const uint16_t *__restrict__ G,
-              const uint16_t *__restrict__ u, float *__restrict__ w) {
+              const uint16_t *__restrict__ H, const uint16_t *__restrict__ u,
+              float *__restrict__ w) {
   constexpr int NP = N1 * N1, N3 = NP * N1;
   __shared__ MfmaLds lds[MW];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -236,12 +239,28 @@ __global__ void __launch_bounds__(64 * MW)
   if (!act) return;  // no barrier follows
   if constexpr (N1 == 8) {
     const float *src = &L.gr[8 * l];
+    float hv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (H != nullptr) {  // uniform
+      const u32x4 v =
+          __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(H + e * N3 + 8 * l));
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int h = 0; h < 8; ++h) __builtin_nontemporal_store(src[h], w + e * N3 + 8 * l + h);
+      for (int h = 0; h < 4; ++h) {
+        hv[2 * h] = bf16_to_f32((uint16_t)(wv[h] & 0xffffu)) * bf16_to_f32(L.u[8 * l + 2 * h]);
+        hv[2 * h + 1] =
+            bf16_to_f32((uint16_t)(wv[h] >> 16)) * bf16_to_f32(L.u[8 * l + 2 * h + 1]);
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 8; ++h)
+      __builtin_nontemporal_store(src[h] + hv[h], w + e * N3 + 8 * l + h);
   } else {
     for (int p = l; p < N3; p += 64) {
       const int i = p % N1, j = (p / N1) % N1, k = p / NP;
-      w[e * N3 + p] = L.gr[k * 64 + j * 8 + i];
+      const int q = k * 64 + j * 8 + i;
+      float v = L.gr[q];
+      if (H != nullptr) v += bf16_to_f32(H[e * N3 + p]) * bf16_to_f32(L.u[q]);
+      w[e * N3 + p] = v;
     }
   }
 }
@@ -249,7 +268,8 @@ __global__ void __launch_bounds__(64 * MW)
 template <bool SPLIT>
 static void launch_ax_mfma_s(int N, int64_t E, const uint16_t *Dhi,
                              const uint16_t *Dlo, const uint16_t *G,
-                             const uint16_t *u, float *w, hipStream_t s) {
+                             const uint16_t *H, const uint16_t *u, float *w,
+                             hipStream_t s) {
   const int64_t blocks = (E + MW - 1) / MW;
   if (blocks == 0) return;
   const dim3 grid((unsigned)blocks), block(64 * MW);
@@ -257,7 +277,7 @@ static void launch_ax_mfma_s(int N, int64_t E, const uint16_t *Dhi,
 #define SEM_AXM(NN)                                                          \
   case NN:                                                                   \
     hipLaunchKernelGGL((k_ax_mfma<NN + 1, SPLIT>), grid, block, 0, s, E, Dhi, \
-                       Dlo, G, u, w);                                        \
+                       Dlo, G, H, u, w);                                     \
     break;
     SEM_AXM(1)
     SEM_AXM(2)
@@ -273,12 +293,12 @@ static void launch_ax_mfma_s(int N, int64_t E, const uint16_t *Dhi,
 }
 
 void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
-                    const uint16_t *Dlo, const uint16_t *G, const uint16_t *u,
-                    float *w, hipStream_t s) {
+                    const uint16_t *Dlo, const uint16_t *G, const uint16_t *H,
+                    const uint16_t *u, float *w, hipStream_t s) {
   if (split)
-    launch_ax_mfma_s<true>(N, E, Dhi, Dlo, G, u, w, s);
+    launch_ax_mfma_s<true>(N, E, Dhi, Dlo, G, H, u, w, s);
   else
-    launch_ax_mfma_s<false>(N, E, Dhi, Dlo, G, u, w, s);
+    launch_ax_mfma_s<false>(N, E, Dhi, Dlo, G, H, u, w, s);
   SEM_HIP(hipGetLastError());
 }
 
@@ -304,6 +324,7 @@ __global__ void __launch_bounds__(64 * MW)
     const float *u = (const float *)sd.v32[src];
     float *w = (float *)sd.v32[dst];
     const uint16_t *G = (const uint16_t *)sd.G16;
+    const uint16_t *H = (const uint16_t *)sd.H16;  // null without a mass term
     m16x4 fh, fl, bh, bl;
     d_operands<N1>(l, (const uint16_t *)sd.D16hi, (const uint16_t *)sd.D16lo, fh,
                    fl, bh, bl);
@@ -326,7 +347,10 @@ __global__ void __launch_bounds__(64 * MW)
       if (act) {
         for (int p = l; p < N3; p += 64) {
           const int i = p % N1, j = (p / N1) % N1, k = p / NP;
-          w[e * N3 + p] = L.gr[k * 64 + j * 8 + i];
+          const int q = k * 64 + j * 8 + i;
+          float v = L.gr[q];
+          if (H != nullptr) v += bf16_to_f32(H[e * N3 + p]) * bf16_to_f32(L.u[q]);
+          w[e * N3 + p] = v;
         }
       }
       __syncthreads();  // L is reused by the next element

@@ -12,7 +12,10 @@
 // and w FP32; at n1 = 8 the BF16 factors are stored column-contiguous
 // [E][6][n1^2][n1] and the BF16 input is read in 16-byte rows and
 // redistributed through LDS).  GATHER = true reads u from a unique-node
-// vector through the closed-form box numbering.
+// vector through the closed-form box numbering.  MASS = true adds the lumped
+// mass term H o u (H = alpha(X) B, one value per local node in the storage
+// type of G, natural [E][n1^3] layout: a wave's load of one k-slice is
+// contiguous).
 #pragma once
 
 #include "common.h"
@@ -34,14 +37,15 @@ template <int N1> constexpr int lds_words(int epb) {
 // threads t = 0 .. of one workgroup; threads t >= EPB n1^2 only join the
 // barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC.
 template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
-          bool NTW>
+          bool NTW, bool MASS = false>
 __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
                                         const TC *__restrict__ D,
                                         const TG *__restrict__ G,
                                         const TU *__restrict__ u,
                                         TW *__restrict__ w,
                                         const Box *__restrict__ box,
-                                        TC *__restrict__ smem) {
+                                        TC *__restrict__ smem,
+                                        const TG *__restrict__ H = nullptr) {
   constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = N1 + 1;
   constexpr int SL = N1 * N1 * PAD;  // one element's slice stack
   const int el = t / NP;
@@ -100,6 +104,12 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
         g[q][k] = act ? ld_stream(Ge + q * N3 + k * NP) : TG(0);
   }
 
+  TG hm[MASS ? N1 : 1];
+  if constexpr (MASS) {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) hm[k] = act ? ld_stream(H + base + k * NP) : TG(0);
+  }
+
   TC uc[N1];
   if constexpr (VECU) {
     const uint32_t wv[4] = {urow.x, urow.y, urow.z, urow.w};
@@ -119,6 +129,15 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
       uc[k] = Cvt<TU, TC>::ld(ucol[k]);
       if (lane_ok) s_u[AX_IDX(k, j, i)] = uc[k];
     }
+  }
+  // mass term H o u, formed while u is in registers; it starts the output sum
+  TC mv[N1];
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    if constexpr (MASS)
+      mv[k] = Cvt<TG, TC>::ld(hm[k]) * uc[k];
+    else
+      mv[k] = TC(0);
   }
   TC Di[N1], Dj[N1];
 #pragma unroll
@@ -159,7 +178,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   }
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
-    TC acc = TC(0);
+    TC acc = mv[k];
 #pragma unroll
     for (int m = 0; m < N1; ++m) {
       acc += DTi[m] * s_r[AX_IDX(k, j, m)];

@@ -74,7 +74,8 @@ sem_status sem_setup(const sem_mesh_desc *d, void *stream, sem_handle **out) {
     need(d->ex >= 1 && d->ey >= 1 && d->ez >= 1, "sem_setup: element counts >= 1");
     need(d->mapping >= SEM_MAP_AFFINE && d->mapping <= SEM_MAP_SINE_CYCLIC,
          "sem_setup: unknown mapping");
-    need(d->alpha == 0.0, "sem_setup: alpha must be 0 (mass term not supported)");
+    need(std::isfinite(d->alpha) && d->alpha >= 0.0,
+         "sem_setup: alpha must be finite and >= 0");
     need(d->kappa_nfeat >= 0, "sem_setup: kappa_nfeat must be >= 0");
     need(d->kappa_nfeat == 0 || (d->kappa_omega && d->kappa_b),
          "sem_setup: kappa features need omega and b");
@@ -131,6 +132,11 @@ sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
       case SEM_ARR_MASS: src = h->mass.p; n = nL * 8; break;
       case SEM_ARR_DIAG: src = h->diag_L.p; n = nL * 8; break;
       case SEM_ARR_DINV: src = h->dinv_G.p; n = nG * 8; break;
+      case SEM_ARR_HMASS:
+        if (!h->has_mass) fail(SEM_ERR_STATE, "sem_export: the mesh has no mass term");
+        src = h->H64.p;
+        n = nL * 8;
+        break;
       default: fail(SEM_ERR_ARG, "sem_export: unknown array");
     }
     need(dst_bytes >= n, "sem_export: destination too small");
@@ -144,16 +150,19 @@ sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
   return guarded([&] {
     need(h != nullptr && u_L != nullptr && w_L != nullptr, "sem_ax: null argument");
     need(u_L != w_L, "sem_ax: input and output must not alias");
-    const void *G = nullptr, *D = nullptr;
+    const void *G = nullptr, *D = nullptr, *H = nullptr;
     if (p == SEM_FP64) {
       G = h->G64.p;
       D = h->D64.p;
+      H = h->H64.p;
     } else if (p == SEM_FP32) {
       G = h->G32.p;
       D = h->D32.p;
+      H = h->H32.p;
     } else if (p == SEM_BF16) {
       G = h->G16.p;
       D = h->D32.p;
+      H = h->H16.p;
       need(reinterpret_cast<uintptr_t>(u_L) % 16 == 0,
            "sem_ax: BF16 input must be 16-byte aligned");
     } else if (p == SEM_BF16_MFMA || p == SEM_BF16_PLAIN_D) {
@@ -161,12 +170,14 @@ sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
            "sem_ax: BF16 input must be 16-byte aligned");
       launch_ax_mfma(h->N, p == SEM_BF16_MFMA, h->E, h->D16hi.as<uint16_t>(),
                      h->D16lo.as<uint16_t>(), h->G16.as<uint16_t>(),
-                     (const uint16_t *)u_L, (float *)w_L, strm(stream));
+                     h->H16.as<uint16_t>(), (const uint16_t *)u_L, (float *)w_L,
+                     strm(stream));
       return;
     } else {
       fail(SEM_ERR_ARG, "sem_ax: unknown precision");
     }
-    launch_ax(h->N, p, h->E, D, G, u_L, w_L, strm(stream));
+    launch_ax(h->N, p, h->E, D, G, h->has_mass ? H : nullptr, u_L, w_L,
+              strm(stream));
   });
 }
 

@@ -513,6 +513,11 @@ static int layout_of(const sem_handle *h, const sem_mlp *net) {
 }
 
 static void check_net(const sem_handle *h, const sem_mlp *net) {
+  // the element targets (local solves, coarse Galerkin operators) are those
+  // of the stiffness operator alone
+  if (h->has_mass)
+    fail(SEM_ERR_STATE, "learned correction: meshes with a mass term "
+                        "(alpha != 0) are not supported");
   (void)layout_of(h, net);
 }
 
@@ -1019,6 +1024,7 @@ constexpr double LOCAL_RTOL = 1e-10;  // element-interior CG tolerance
 void learn_interior_pairs(sem_handle *h, const double *rL, const int32_t *elems,
                           int n, uint16_t *X, int ldx, float *T, double rtol,
                           int32_t *iters, hipStream_t s) {
+  if (h->has_mass) fail(SEM_ERR_STATE, "interior pairs: mesh has a mass term");
   const int m = h->N - 1;
   if (m < 1) fail(SEM_ERR_ARG, "interior pairs: N must be at least 2");
   if (n < 0 || (n > 0 && (!rL || !elems || !X || !T)))
@@ -1077,6 +1083,7 @@ static void coarse_exact(const sem_handle *h, const Learn *L, double *Mex,
 int learn_coarse_exact(sem_handle *h, double *M, hipStream_t s) {
   if (h->N < 2 || h->N > 8) fail(SEM_ERR_ARG, "coarse layout: N must be in 2..8");
   if (M == nullptr) fail(SEM_ERR_ARG, "coarse layout: null output");
+  if (h->has_mass) fail(SEM_ERR_STATE, "coarse layout: mesh has a mass term");
   // a throwaway description of the layout (basis and kappa scaling only)
   Learn L;
   const int m = h->N - 1;

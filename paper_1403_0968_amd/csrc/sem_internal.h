@@ -85,6 +85,7 @@ struct BatchSolve {
   Box box;                        // closed-form numbering of the solve's mesh
   const void *G64, *G32, *G16, *D64, *D32;
   const void *D16hi, *D16lo;      // two-term BF16 split of D
+  const void *H16;                // BF16 mass factor alpha B, or null
   const double *dinv64, *one64;   // Jacobi, and 1 off the Dirichlet boundary
   const float *dinv32, *one32;
   void *v64[NVEC];
@@ -123,6 +124,10 @@ struct sem_handle {
   // geometry and preconditioner
   sem::DevBuf coords, G64, G32, G16, mass, diag_L, dinv_G, dinv_G32;
   sem::DevBuf kvert;            // kappa at the 8 vertices of each element
+  // mass term H = alpha(X) B (allocated only when alpha != 0), FP64 with
+  // FP32 / BF16 copies in the natural [E][n1^3] layout
+  bool has_mass = false;
+  sem::DevBuf H64, H32, H16;
   // created on the first solve
   sem::Workspace *ws = nullptr;
   // learned correction (attached network, element features and scratch)
@@ -133,8 +138,9 @@ struct sem_handle {
 namespace sem {
 
 // kernels / launchers (ax.hip, gs.hip, setup.hip)
+// H: mass factor in the precision of G, or null (no mass term)
 void launch_ax(int N, int prec, int64_t E, const void *D, const void *G,
-               const void *u, void *w, hipStream_t s);
+               const void *H, const void *u, void *w, hipStream_t s);
 void launch_gs(sem_handle *h, int prec, void *v, hipStream_t s);
 void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s);
 void launch_rhs(sem_handle *h, const sem_source *src, double *b, hipStream_t s);
@@ -146,11 +152,11 @@ void launch_bax(int prec, int bs, int nset, const BatchSolve *sds,
                 const CgState *st, const AxItem *items, int nitems, int grid,
                 int src, int dst, int skip_done, hipStream_t s);
 void launch_ax_solve(int N, int prec, int64_t E, const void *D, const void *G,
-                     const void *u, void *w, const Box &box, const int32_t *stop,
-                     hipStream_t s);
+                     const void *H, const void *u, void *w, const Box &box,
+                     const int32_t *stop, hipStream_t s);
 void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
-                    const uint16_t *Dlo, const uint16_t *G, const uint16_t *u,
-                    float *w, hipStream_t s);
+                    const uint16_t *Dlo, const uint16_t *G, const uint16_t *H,
+                    const uint16_t *u, float *w, hipStream_t s);
 void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *st,
                      const AxItem *items, int nitems, int epb, int grid, int src,
                      int dst, int skip_done, hipStream_t s);

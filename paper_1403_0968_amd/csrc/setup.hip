@@ -9,8 +9,11 @@
 //   grad r = (X_s x X_t)/J,  grad s = (X_t x X_r)/J,  grad t = (X_r x X_s)/J,
 //   J = X_r . (X_s x X_t),
 // the weighted metric is G_ab = w_i w_j w_k kappa (c_a . c_b) / J with c_a the
-// three cross products, and B = w_i w_j w_k J.
+// three cross products, and B = w_i w_j w_k J.  The mass term of equation
+// semOperator, lumped by the quadrature, is H = alpha(X) B per local node;
+// the Jacobi diagonal is that of the stiffness plus H.
 #include <algorithm>
+#include <cmath>
 
 #include "common.h"
 #include "sem_internal.h"
@@ -128,9 +131,26 @@ __global__ void k_geom(int64_t nL, GeomParams P, const double *__restrict__ omeg
   if (threadIdx.x == 0) minJ_blk[blockIdx.x] = smin[0];
 }
 
-// unassembled diagonal of the local stiffness matrices
+// mass factor H = alpha(X) B (alpha_l from the nodal array, or the constant)
+// with its FP32 and BF16 copies
+__global__ void k_mass_factor(int64_t nL, double alpha,
+                              const double *__restrict__ alpha_l,
+                              const double *__restrict__ B, double *__restrict__ H,
+                              float *__restrict__ H32, uint16_t *__restrict__ H16) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nL) return;
+  const double a = alpha_l != nullptr ? alpha_l[l] : alpha;
+  const double v = a * B[l];
+  H[l] = v;
+  H32[l] = (float)v;
+  H16[l] = f32_to_bf16((float)v);
+}
+
+// unassembled diagonal of the local matrices (stiffness, plus H when the
+// mesh has a mass term)
 __global__ void k_diag(int64_t nL, int N1, const double *__restrict__ Dm,
-                       const double *__restrict__ G, double *__restrict__ diag) {
+                       const double *__restrict__ G, const double *__restrict__ H,
+                       double *__restrict__ diag) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nL) return;
   const int N3 = N1 * N1 * N1;
@@ -148,6 +168,7 @@ __global__ void k_diag(int64_t nL, int N1, const double *__restrict__ Dm,
   const double di = Dm[i * N1 + i], dj = Dm[j * N1 + j], dk = Dm[k * N1 + k];
   s += 2.0 * di * dj * Ge[1 * N3 + p] + 2.0 * di * dk * Ge[2 * N3 + p] +
        2.0 * dj * dk * Ge[4 * N3 + p];
+  if (H != nullptr) s += H[l];
   diag[l] = s;
 }
 
@@ -203,6 +224,7 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
   h->ez = d->ez;
   h->dirichlet = d->dirichlet;
   h->mapping = d->mapping;
+  h->has_mass = d->alpha_nodal != nullptr || d->alpha != 0.0;
   h->E = (int64_t)d->ex * d->ey * d->ez;
   h->nL = M.nL;
   h->nG = M.nG;
@@ -271,8 +293,28 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
                      h->mass.as<double>(), h->kvert.as<double>(),
                      minj.as<double>());
   SEM_HIP(hipGetLastError());
+  DevBuf al;
+  std::vector<double> av;  // lives until the stream is synchronised below
+  if (h->has_mass) {
+    if (d->alpha_nodal != nullptr) {
+      av.assign(d->alpha_nodal, d->alpha_nodal + nL);
+      for (double a : av)
+        if (!(std::isfinite(a) && a >= 0.0))
+          fail(SEM_ERR_ARG, "sem_setup: alpha_nodal values must be finite and >= 0");
+      upload(al, av, s);
+    }
+    h->H64.alloc(nL * sizeof(double));
+    h->H32.alloc(nL * sizeof(float));
+    h->H16.alloc(nL * sizeof(uint16_t));
+    hipLaunchKernelGGL(k_mass_factor, dim3(gb), dim3(T), 0, s, nL, d->alpha,
+                       d->alpha_nodal != nullptr ? al.as<double>() : nullptr,
+                       h->mass.as<double>(), h->H64.as<double>(),
+                       h->H32.as<float>(), h->H16.as<uint16_t>());
+    SEM_HIP(hipGetLastError());
+  }
   hipLaunchKernelGGL(k_diag, dim3(gb), dim3(T), 0, s, nL, N1, h->D64.as<double>(),
-                     h->G64.as<double>(), h->diag_L.as<double>());
+                     h->G64.as<double>(), h->has_mass ? h->H64.as<double>() : nullptr,
+                     h->diag_L.as<double>());
   SEM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_dinv, dim3((unsigned)((nG + T - 1) / T)), dim3(T), 0, s,
                      nG, h->offsets.as<int32_t>(), h->perm.as<int32_t>(),

@@ -631,6 +631,11 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
     orders.insert(hs[q]->n1);
     for (int r = 0; r < q; ++r)
       if (hs[r] == hs[q]) fail(SEM_ERR_ARG, "batch: a handle appears twice");
+    // the persistent batched operator has no mass term; a single solve runs
+    // the gathered single-solve operator, which has
+    if (n > 1 && hs[q]->has_mass)
+      fail(SEM_ERR_ARG, "batch: solves with a mass term (alpha != 0) must be "
+                        "solved one at a time");
   }
   int nset;
   if (orders.size() == 1)
@@ -668,6 +673,7 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
       d.D32 = h->D32.p;
       d.D16hi = h->D16hi.p;
       d.D16lo = h->D16lo.p;
+      d.H16 = h->has_mass ? h->H16.p : nullptr;
       d.dinv64 = h->dinv_G.as<double>();
       d.dinv32 = h->dinv_G32.as<float>();
       d.one64 = W->one64.as<double>();
@@ -758,12 +764,16 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done) {
     Workspace *W = h->ws;
     const bool f64 = prec == SEM_FP64;
     const void *G = f64 ? h->G64.p : prec == SEM_FP32 ? h->G32.p : h->G16.p;
+    const void *H = !h->has_mass ? nullptr
+                    : f64        ? h->H64.p
+                    : prec == SEM_FP32 ? h->H32.p
+                                       : h->H16.p;
     const void *D = f64 ? h->D64.p : h->D32.p;
     const void *u = f64 ? W->v64[src].p : W->v32[src].p;
     void *w = f64 ? W->v64[dst].p : W->v32[dst].p;
     const int32_t *stop =
         skip_done ? &b->st.as<CgState>()[0].done : (const int32_t *)nullptr;
-    launch_ax_solve(h->N, prec, h->E, D, G, u, w,
+    launch_ax_solve(h->N, prec, h->E, D, G, H, u, w,
                     make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet), stop, b->s);
     return;
   }

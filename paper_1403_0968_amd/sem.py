@@ -22,7 +22,7 @@ SEM_MAP_AFFINE, SEM_MAP_SINE_X, SEM_MAP_SINE_CYCLIC = 0, 1, 2
 SEM_SRC_FOURIER, SEM_SRC_SINE = 0, 1
 (SEM_ARR_L2G, SEM_ARR_PERM, SEM_ARR_OFFSETS, SEM_ARR_MULT, SEM_ARR_MASK,
  SEM_ARR_COORDS, SEM_ARR_GEOM, SEM_ARR_MASS, SEM_ARR_DIAG,
- SEM_ARR_DINV) = range(10)
+ SEM_ARR_DINV, SEM_ARR_HMASS) = range(11)
 
 EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_gs", "sem_rhs", "sem_precond_apply", "sem_pcg_solve",
@@ -42,7 +42,8 @@ class sem_mesh_desc(C.Structure):
                 ("kappa_nfeat", C.c_int32),
                 ("kappa_omega", C.POINTER(C.c_double)),
                 ("kappa_b", C.POINTER(C.c_double)),
-                ("kappa_sigma", C.c_double)]
+                ("kappa_sigma", C.c_double),
+                ("alpha_nodal", C.POINTER(C.c_double))]
 
 
 class sem_source(C.Structure):
@@ -186,12 +187,22 @@ def _dptr(a):
 # ----------------------------------------------------------------------------
 
 def sem_setup(N, ex, ey, ez, mapping=SEM_MAP_AFFINE, dirichlet=1,
-              kappa=None, stream=None):
-    """kappa: None or (omega[M,3], b[M], sigma).  Returns an opaque handle."""
+              kappa=None, stream=None, alpha=0.0, alpha_nodal=None):
+    """kappa: None or (omega[M,3], b[M], sigma).  alpha: constant mass
+    coefficient; alpha_nodal: host array of n_local values (replaces the
+    constant).  Returns an opaque handle."""
     d = sem_mesh_desc()
     d.N, d.ex, d.ey, d.ez = N, ex, ey, ez
-    d.dirichlet, d.mapping, d.alpha = int(dirichlet), int(mapping), 0.0
+    d.dirichlet, d.mapping, d.alpha = int(dirichlet), int(mapping), float(alpha)
     keep = []
+    if alpha_nodal is not None:
+        al_a, al_p = _dptr(alpha_nodal)
+        n_local = ex * ey * ez * (N + 1) ** 3
+        if al_a.ndim != 1 or al_a.shape[0] != n_local:
+            raise ValueError(f"alpha_nodal needs {n_local} values (n_local), "
+                             f"got shape {al_a.shape}")
+        keep.append(al_a)
+        d.alpha_nodal = al_p
     if kappa is not None:
         om, b, sigma = kappa
         om_a, om_p = _dptr(om)

@@ -48,13 +48,15 @@ class Pair:
     """A library handle and the oracle mesh for the same discretisation."""
 
     def __init__(self, sem, N, ex, ey, ez, mapping=0, dirichlet=1, kappa=None,
-                 oracle=True):
+                 oracle=True, alpha=0.0, alpha_nodal=None):
         self.sem = sem
         self.N, self.ex, self.ey, self.ez = N, ex, ey, ez
         self.h = sem.sem_setup(N, ex, ey, ez, mapping=mapping,
-                               dirichlet=dirichlet, kappa=kappa)
+                               dirichlet=dirichlet, kappa=kappa, alpha=alpha,
+                               alpha_nodal=alpha_nodal)
         self.E, self.nL, self.nG = sem.sem_query(self.h)
-        self.m = (orc.mesh(N, ex, ey, ez, mapping, dirichlet, kappa)
+        self.m = (orc.mesh(N, ex, ey, ez, mapping, dirichlet, kappa,
+                           alpha=alpha, alpha_nodal=alpha_nodal)
                   if oracle else None)
 
     def close(self):
