@@ -40,32 +40,24 @@ namespace sem {
 // ---------------------------------------------------------------------------
 // standalone operator: one tile per workgroup
 // ---------------------------------------------------------------------------
-template <int N1, int BYTES> struct AxShape {
-  static constexpr int NP = N1 * N1;
-  // FP64: 128-thread workgroups (two elements at n1 = 8); FP32/BF16: 64
-  static constexpr int TARGET = BYTES == 8 ? 128 : 64;
-  static constexpr int EPB = (TARGET / NP) > 0 ? (TARGET / NP) : 1;
-  static constexpr int THREADS = EPB * NP;
-};
-
 template <int N1, class TU, class TG, class TW, class TC, bool GATHER, bool NTW,
           bool MASS>
-__global__ void __launch_bounds__((AxShape<N1, sizeof(TC)>::THREADS))
+__global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
     k_ax(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
          const TU *__restrict__ u, TW *__restrict__ w,
          const Box *__restrict__ box, const int32_t *__restrict__ stop,
          const TG *__restrict__ H) {
-  using S = AxShape<N1, sizeof(TC)>;
+  using S = OpShape<N1, sizeof(TC)>;
   __shared__ TC smem[lds_words<N1>(S::EPB)];
   if (stop != nullptr && *stop != 0) return;  // uniform: solver finished
-  ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW, MASS>(
+  ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW, MASS, S::NTG>(
       threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, box, smem, H);
 }
 
 template <int N1, class TU, class TG, class TW, class TC>
 static void launch_nt(int64_t E, const void *D, const void *G, const void *H,
                       const void *u, void *w, hipStream_t s) {
-  using S = AxShape<N1, sizeof(TC)>;
+  using S = OpShape<N1, sizeof(TC)>;
   const int64_t blocks = (E + S::EPB - 1) / S::EPB;
   if (blocks == 0) return;
   const dim3 grid((unsigned)blocks), block(S::THREADS);

@@ -6,29 +6,22 @@
 // kernel first has to fetch its work item and the solve's descriptor, a
 // chain of dependent loads that cost ~25 % of the operator time at 32^3,
 // N = 7 (measured with and without the gather: the gather itself costs
-// nothing in FP64).  Workgroup shapes as the standalone operator: 128
-// threads in FP64 (two elements at n1 = 8), 64 in FP32 / BF16.  A mesh with
+// nothing in FP64).  Workgroup shapes and load hints as the standalone
+// operator (OpShape).  A mesh with
 // a mass term passes H = alpha(X) B and the kernel adds H o u.
 #include "ax_tile.h"
 
 namespace sem {
 
-template <int N1, int BYTES> struct SolveShape {
-  static constexpr int NP = N1 * N1;
-  static constexpr int TARGET = BYTES == 8 ? 128 : 64;
-  static constexpr int EPB = (TARGET / NP) > 0 ? (TARGET / NP) : 1;
-  static constexpr int THREADS = EPB * NP;
-};
-
 template <int N1, class TV, class TG, class TC, bool MASS>
-__global__ void __launch_bounds__((SolveShape<N1, sizeof(TC)>::THREADS))
+__global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
     k_ax_solve(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
                const TV *__restrict__ u, TV *__restrict__ w, Box box,
                const int32_t *__restrict__ stop, const TG *__restrict__ H) {
-  using S = SolveShape<N1, sizeof(TC)>;
+  using S = OpShape<N1, sizeof(TC)>;
   __shared__ TC smem[lds_words<N1>(S::EPB)];
   if (stop != nullptr && *stop != 0) return;  // uniform: the solve finished
-  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS>(
+  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG>(
       threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, &box, smem, H);
 }
 
@@ -36,7 +29,7 @@ template <int N1, class TV, class TG, class TC>
 static void launch_solve_t(int64_t E, const void *D, const void *G,
                            const void *H, const void *u, void *w, const Box &box,
                            const int32_t *stop, hipStream_t s) {
-  using S = SolveShape<N1, sizeof(TC)>;
+  using S = OpShape<N1, sizeof(TC)>;
   const int64_t blocks = (E + S::EPB - 1) / S::EPB;
   if (blocks == 0) return;
   const dim3 grid((unsigned)blocks), block(S::THREADS);

@@ -33,11 +33,28 @@ template <int N1> constexpr int lds_words(int epb) {
   return 3 * epb * N1 * N1 * (N1 + 1);
 }
 
+// Workgroup shape of the operator kernels per order and value size (timed on
+// the 16.8M-node meshes at every order).  FP64: elements per workgroup chosen
+// so that EPB n1^2 fills whole waves (n1 = 8: four elements, 256 threads),
+// and the factors are read with non-temporal loads except at n1 = 2, 3, 5,
+// where one factor column is a short piece of a cache line and the
+// non-temporal hint makes the neighbouring pieces miss again.  FP32 / BF16:
+// 64-thread workgroups.
+template <int N1, int BYTES> struct OpShape {
+  static constexpr int NP = N1 * N1;
+  static constexpr int EPB64 = N1 == 2 ? 32 : N1 == 3 ? 7 : N1 == 4 ? 4
+                               : N1 == 5 ? 5 : N1 == 6 ? 7 : N1 == 7 ? 5
+                               : N1 == 8 ? 4 : 3;
+  static constexpr int EPB = BYTES == 8 ? EPB64 : ((64 / NP) > 0 ? 64 / NP : 1);
+  static constexpr int THREADS = EPB * NP;
+  static constexpr bool NTG = BYTES != 8 || !(N1 == 2 || N1 == 3 || N1 == 5);
+};
+
 // Apply the operator to elements e0 .. e0 + EPB - 1 (those < E) with the
 // threads t = 0 .. of one workgroup; threads t >= EPB n1^2 only join the
 // barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC.
 template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
-          bool NTW, bool MASS = false>
+          bool NTW, bool MASS = false, bool NTG = true>
 __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
                                         const TC *__restrict__ D,
                                         const TG *__restrict__ G,
@@ -101,7 +118,8 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
     for (int k = 0; k < N1; ++k)
 #pragma unroll
       for (int q = 0; q < 6; ++q)
-        g[q][k] = act ? ld_stream(Ge + q * N3 + k * NP) : TG(0);
+        g[q][k] = act ? (NTG ? ld_stream(Ge + q * N3 + k * NP) : Ge[q * N3 + k * NP])
+                      : TG(0);
   }
 
   TG hm[MASS ? N1 : 1];
