@@ -34,6 +34,10 @@ mapped by x + 0.05 (sin 2 pi y sin 2 pi z, and cyclic).
   sine-cyclic meshes of about 16.8M local nodes, flops 12(N+1)+15 per node;
   and the screened operator (alpha = 1, the mass term of equation semPDE)
   on the 32^3, N = 7 mesh, 72 B per node in FP64.
+* fd2d: the finite-difference wave step of the paper's section 4.1 on a
+  periodic 8192 x 8192 FP64 grid for stencil radii r = 1..7 (stencil sizes
+  3..15, the paper's x-axis), in MNodes/s as the paper reports it, with the
+  algorithmic traffic 24 B per node (u_n and u_{n-1} read, u_{n+1} written).
 * cpu_baseline: the FP64 CPU oracle's operator on a bounded sample of the
   same mesh (test infrastructure, timed here only as a reported baseline).
 
@@ -161,6 +165,56 @@ def bench_order_sweep(sem, torch, steps, warmup, target_nodes=NE ** 3 * 512):
         "fp32_alg_GBs": 36 * nL / (ms32 * 1e-3) / 1e9,
         "fp32_frac_hbm": 36 * nL / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS}
     log(f"[sweep] screened 32^3 N=7: fp64 {ms * 1e3:.1f} us, fp32 {ms32 * 1e3:.1f} us")
+    return out
+
+
+def time_launches(torch, launch, steps, min_warm_s=0.2):
+    """ms per launch of `steps` back-to-back launches on torch's current
+    stream (the stream the library launches on), after >= min_warm_s of
+    warm-up launches."""
+    t0 = time.perf_counter()
+    n = 0
+    while time.perf_counter() - t0 < min_warm_s:
+        launch()
+        n += 1
+        if n % 20 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(steps):
+        launch()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+FD_N = 8192
+
+
+def bench_fd2d(sem, torch, steps):
+    n = FD_N
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    uc = torch.rand((n, n), dtype=torch.float64, device="cuda", generator=g)
+    up = torch.rand((n, n), dtype=torch.float64, device="cuda", generator=g)
+    un = torch.empty_like(uc)
+    dx = 2.0 / n
+    dt = 0.25 * dx
+    out = {"grid": f"{n}x{n} periodic, FP64, random u_n and u_(n-1)",
+           "bytes_per_node": 24}
+    for r in range(1, 8):
+        ms = time_launches(torch, lambda: sem.fd2d_step(uc, up, un, r, dt, dx),
+                           steps)
+        t = ms * 1e-3
+        out[f"r{r}"] = {"stencil": 2 * r + 1, "us_per_step": ms * 1e3,
+                        "mnodes_per_s": n * n / t / 1e6,
+                        "alg_GBs": 24 * n * n / t / 1e9,
+                        "frac_hbm": 24 * n * n / t / 1e9 / HBM_PEAK_GBS}
+        log(f"[fd2d] r={r} (stencil {2 * r + 1}): {ms * 1e3:.1f} us/step, "
+            f"{n * n / t / 1e6:.0f} MNodes/s, {24 * n * n / t / 1e9:.0f} GB/s")
+    del uc, up, un
     return out
 
 
@@ -370,6 +424,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-fd", action="store_true")
+    ap.add_argument("--fd-only", action="store_true",
+                    help="only the finite-difference section (one JSON object)")
     ap.add_argument("--ax-only", action="store_true",
                     help="only the FP64 operator launches (for counter runs)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -378,8 +435,9 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not "
-              f"supported (the operator would shard by element slabs, see "
-              f"DESIGN.md)", file=sys.stderr)
+              f"supported (the operator would shard by contiguous element "
+              f"slabs with a face exchange in the gather-scatter; that path "
+              f"is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -387,6 +445,9 @@ def main():
     sem.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
 
+    if args.fd_only:
+        print(json.dumps({"fd2d": bench_fd2d(sem, torch, args.steps)}), flush=True)
+        return
     if args.copy_bytes > 0:
         n = args.copy_bytes // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda")
@@ -436,6 +497,7 @@ def main():
     del u, w, u32, w32, ub
     sweep = (None if args.no_sweep
              else bench_order_sweep(sem, torch, args.steps, args.warmup))
+    fd2d = None if args.no_fd else bench_fd2d(sem, torch, args.steps)
     learned = None if args.no_learned else bench_learned(sem, torch)
     batch = None if args.no_batch else bench_batch(sem, torch)
     cpu = None if args.no_cpu else cpu_baseline()
@@ -464,6 +526,7 @@ def main():
         "cpu_baseline": cpu,
         "sem_ax_low_precision": extra,
         "order_sweep": sweep,
+        "fd2d": fd2d,
         "pcg": pcg,
         "learned": learned,
         "batch": batch,

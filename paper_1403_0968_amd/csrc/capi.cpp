@@ -4,7 +4,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 
+#include "../../include/fd2d.h"
 #include "sem_internal.h"
 
 namespace sem {
@@ -441,6 +443,42 @@ sem_status sem_learn_coarse_exact(sem_handle *h, double *M, int32_t *K,
     need(h != nullptr && M != nullptr, "sem_learn_coarse_exact: null argument");
     const int k = learn_coarse_exact(h, M, strm(stream));
     if (K) *K = k;
+  });
+}
+
+sem_status fd2d_weights(int32_t r, double *w) {
+  return guarded([&] {
+    need(w != nullptr, "fd2d_weights: null output");
+    fd2d_weights_host(r, w);
+  });
+}
+
+static double fd2d_coefficient(double dt, double dx) {
+  need(std::isfinite(dt) && std::isfinite(dx) && dx > 0.0,
+       "fd2d: dt must be finite and dx finite and > 0");
+  return (dt * dt) / (dx * dx);
+}
+
+sem_status fd2d_step(const double *u_cur, const double *u_prev, double *u_next,
+                     int64_t nx, int64_t ny, int32_t r, double dt, double dx,
+                     void *stream) {
+  return guarded([&] {
+    launch_fd2d(u_cur, u_prev, u_next, nx, ny, r, fd2d_coefficient(dt, dx),
+                strm(stream));
+  });
+}
+
+sem_status fd2d_run(double *u_a, double *u_b, int64_t nx, int64_t ny, int32_t r,
+                    double dt, double dx, int32_t nsteps, void *stream) {
+  return guarded([&] {
+    need(nsteps >= 0, "fd2d_run: nsteps must be >= 0");
+    need(u_a != u_b, "fd2d_run: the two levels must be distinct buffers");
+    const double c = fd2d_coefficient(dt, dx);
+    double *older = u_a, *newer = u_b;
+    for (int32_t s = 0; s < nsteps; ++s) {
+      launch_fd2d(newer, older, older, nx, ny, r, c, strm(stream));
+      std::swap(older, newer);
+    }
   });
 }
 

@@ -161,6 +161,10 @@ void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *s
                      const AxItem *items, int nitems, int epb, int grid, int src,
                      int dst, int skip_done, hipStream_t s);
 int bax_elements_per_tile(int bs, int n1);
+// finite-difference wave step (fd2d.hip); c = dt^2 / dx^2
+void fd2d_weights_host(int r, double *w);
+void launch_fd2d(const double *u_cur, const double *u_prev, double *u_next,
+                 int64_t nx, int64_t ny, int r, double c, hipStream_t s);
 // solver (solver.hip)
 void destroy_ws(sem_handle *h);
 sem_batch *batch_create(sem_handle *const *hs, int n);

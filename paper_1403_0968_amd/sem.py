@@ -32,7 +32,8 @@ EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_mlp_forward", "sem_mlp_loss_grad", "sem_mlp_adam",
             "sem_mlp_set_damping", "sem_mlp_get_damping", "sem_mlp_save", "sem_mlp_load", "sem_learn_attach",
             "sem_learn_train", "sem_learn_interior_pairs",
-            "sem_learn_coarse_exact", "sem_mlp_loss_grad_factor", "sem_last_error"]
+            "sem_learn_coarse_exact", "sem_mlp_loss_grad_factor",
+            "fd2d_weights", "fd2d_step", "fd2d_run", "sem_last_error"]
 
 
 class sem_mesh_desc(C.Structure):
@@ -144,6 +145,11 @@ def lib():
     L.sem_learn_train.argtypes = [vp, vp, C.POINTER(vp), i32,
                                   C.POINTER(sem_train_opts),
                                   C.POINTER(sem_train_report), vp]
+    L.fd2d_weights.argtypes = [i32, C.POINTER(C.c_double)]
+    L.fd2d_step.argtypes = [vp, vp, vp, C.c_int64, C.c_int64, i32, C.c_double,
+                            C.c_double, vp]
+    L.fd2d_run.argtypes = [vp, vp, C.c_int64, C.c_int64, i32, C.c_double,
+                           C.c_double, i32, vp]
     L.sem_last_error.argtypes = []
     L.sem_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -453,3 +459,41 @@ def sem_learn_interior_pairs(h, r, elems, X, T, rtol=1e-10, iters=None,
 
 def sem_last_error():
     return lib().sem_last_error().decode()
+
+
+# ----------------------------------------------------------------------------
+# finite-difference wave step (include/fd2d.h)
+# ----------------------------------------------------------------------------
+
+def fd2d_weights(r):
+    """Unit-spacing second-derivative weights of order 2r (numpy, 2r+1)."""
+    import numpy as np
+    w = (C.c_double * (2 * int(r) + 1))()
+    _check(lib().fd2d_weights(int(r), w))
+    return np.array(list(w))
+
+
+def _grid_shape(t):
+    if t.dim() != 2 or not t.is_contiguous():
+        raise ValueError("fd2d grids are contiguous 2-D tensors [ny, nx]")
+    return int(t.shape[1]), int(t.shape[0])
+
+
+def fd2d_step(u_cur, u_prev, u_next, r, dt, dx, stream=None):
+    """Tensors [ny, nx] float64 on the device; u_next may be u_prev."""
+    nx, ny = _grid_shape(u_cur)
+    for t in (u_prev, u_next):
+        if tuple(t.shape) != tuple(u_cur.shape):
+            raise ValueError("fd2d grids must have equal shapes")
+    _check(lib().fd2d_step(_ptr(u_cur), _ptr(u_prev), _ptr(u_next), nx, ny,
+                           int(r), float(dt), float(dx), _stream(stream)))
+
+
+def fd2d_run(u_a, u_b, r, dt, dx, nsteps, stream=None):
+    """In place on two levels (u_a older, u_b newer); after an odd number of
+    steps u_a holds the newest level."""
+    nx, ny = _grid_shape(u_a)
+    if tuple(u_b.shape) != tuple(u_a.shape):
+        raise ValueError("fd2d grids must have equal shapes")
+    _check(lib().fd2d_run(_ptr(u_a), _ptr(u_b), nx, ny, int(r), float(dt),
+                          float(dx), int(nsteps), _stream(stream)))

@@ -16,8 +16,9 @@ def declared_functions():
     for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
         text = open(h).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-        for m in re.finditer(r"^\s*(?:const\s+)?\w+\s*\*?\s*(sem_\w+)\s*\(",
-                             text, flags=re.M):
+        for m in re.finditer(
+                r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:sem|fd2d)_\w+)\s*\(",
+                text, flags=re.M):
             names.add(m.group(1))
     return sorted(names)
 
@@ -26,7 +27,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("sem_setup", "sem_ax", "sem_gs", "sem_pcg_solve",
               "sem_precond_apply", "sem_rhs", "sem_destroy", "sem_query",
-              "sem_export", "sem_last_error"):
+              "sem_export", "sem_last_error", "fd2d_weights", "fd2d_step",
+              "fd2d_run"):
         assert n in names, n
 
 
@@ -53,3 +55,23 @@ def test_product_path_does_not_import_the_oracle():
             continue
         text = open(path).read()
         assert "oracle" not in text.lower(), path
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsem.so not built")
+def test_fd2d_weights_host_logic_bit_exact():
+    """fd2d_weights is host code (no device call): its correctly rounded
+    weights equal the oracle's exact rationals bit for bit, and r outside
+    1..7 is an argument error."""
+    import numpy as np
+    from oracle import fd
+    lib = ctypes.CDLL(LIB)
+    lib.fd2d_weights.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]
+    lib.fd2d_weights.restype = ctypes.c_int
+    for r in range(1, 8):
+        buf = (ctypes.c_double * (2 * r + 1))()
+        assert lib.fd2d_weights(r, buf) == 0
+        got = np.array(list(buf))
+        np.testing.assert_array_equal(got.view(np.uint64),
+                                      fd.weights(r).view(np.uint64))
+    buf = (ctypes.c_double * 32)()
+    assert lib.fd2d_weights(0, buf) == 1 and lib.fd2d_weights(8, buf) == 1

@@ -1,6 +1,6 @@
 """GPU parity of the HIP path (through the C ABI) against the FP64 CPU oracle.
 
-Bars (tolerances written here, derived in the design doc):
+Bars (tolerances written here; each follows from the arithmetic it checks):
   * maps (l2g, perm, offsets, mult, mask) and FP64 gather-scatter: bit-exact;
   * FP64 sem_ax: ||w_gpu - w_oracle||_inf / ||w_oracle||_inf <= 1e-12 on
     random continuous and discontinuous inputs, and componentwise
