@@ -38,6 +38,13 @@ mapped by x + 0.05 (sin 2 pi y sin 2 pi z, and cyclic).
   periodic 8192 x 8192 FP64 grid for stencil radii r = 1..7 (stencil sizes
   3..15, the paper's x-axis), in MNodes/s as the paper reports it, with the
   algorithmic traffic 24 B per node (u_n and u_{n-1} read, u_{n+1} written).
+* dg: the DG volume term of the shallow-water equations (section 4.3) on the
+  example's 212,800 triangles (266 x 400 jittered cells of the unit square,
+  the stand-in for its unpublished mesh), orders N = 1..8 (the paper's
+  x-axis), GFLOP/s with 12 Np^2 + 32 Np flops per element (the two
+  Np x Np products per component and the nodal flux, metric and source
+  work) and GB/s with (8 Np + 4) x 8 bytes per element (state read, result
+  written, bathymetry gradient and affine factors read).
 * cpu_baseline: the FP64 CPU oracle's operator on a bounded sample of the
   same mesh (test infrastructure, timed here only as a reported baseline).
 
@@ -215,6 +222,49 @@ def bench_fd2d(sem, torch, steps):
         log(f"[fd2d] r={r} (stencil {2 * r + 1}): {ms * 1e3:.1f} us/step, "
             f"{n * n / t / 1e6:.0f} MNodes/s, {24 * n * n / t / 1e9:.0f} GB/s")
     del uc, up, un
+    return out
+
+
+FP64_PEAK_TFLOPS = 78.6
+DG_CELLS = (266, 400)
+
+
+def bench_dg(sem, torch, steps):
+    import numpy as np
+    from seminputs import tri_mesh
+    vx, vy, etov = tri_mesh(*DG_CELLS, seed=0)
+    E = etov.shape[0]
+    out = {"mesh": f"{E} triangles ({DG_CELLS[0]} x {DG_CELLS[1]} jittered "
+                   f"cells of the unit square)", "g": 9.81}
+    for N in range(1, 9):
+        r, s = sem.dg_reference_nodes(N)
+        la, lb, lc = -(r + s) / 2, (1 + r) / 2, (1 + s) / 2
+        X = (np.outer(vx[etov[:, 0]], la) + np.outer(vx[etov[:, 1]], lb)
+             + np.outer(vx[etov[:, 2]], lc))
+        Y = (np.outer(vy[etov[:, 0]], la) + np.outer(vy[etov[:, 1]], lb)
+             + np.outer(vy[etov[:, 2]], lc))
+        B = 0.3 * np.exp(-((X - 0.4) ** 2 + (Y - 0.6) ** 2) / 0.05) + 0.1 * X * Y
+        hh = 2.0 + 0.3 * np.sin(2 * np.pi * X) * np.cos(np.pi * Y) - B
+        Q = np.stack([hh, 0.2 * np.cos(3 * X + Y) * hh,
+                      -0.1 * np.sin(X - 2 * Y) * hh], axis=1)
+        h = sem.dg_setup(N, vx, vy, etov, bathymetry=B, g=9.81)
+        dQ = torch.as_tensor(Q, device="cuda")
+        drhs = torch.empty_like(dQ)
+        ms = time_launches(torch, lambda: sem.dg_volume(h, dQ, drhs), steps)
+        sem.dg_destroy(h)
+        del dQ, drhs
+        Np = (N + 1) * (N + 2) // 2
+        t = ms * 1e-3
+        flops = (12 * Np * Np + 32 * Np) * E
+        byts = (8 * Np + 4) * 8 * E
+        out[f"N{N}"] = {"Np": Np, "us_per_launch": ms * 1e3,
+                        "gflops": flops / t / 1e9,
+                        "frac_fp64": flops / t / 1e12 / FP64_PEAK_TFLOPS,
+                        "alg_GBs": byts / t / 1e9,
+                        "frac_hbm": byts / t / 1e9 / HBM_PEAK_GBS}
+        log(f"[dg] N={N}: {ms * 1e3:.1f} us, {flops / t / 1e9:.0f} GFLOP/s "
+            f"({100 * flops / t / 1e12 / FP64_PEAK_TFLOPS:.0f} % FP64), "
+            f"{byts / t / 1e9:.0f} GB/s ({100 * byts / t / 1e9 / HBM_PEAK_GBS:.0f} % HBM)")
     return out
 
 
@@ -427,6 +477,9 @@ def main():
     ap.add_argument("--no-fd", action="store_true")
     ap.add_argument("--fd-only", action="store_true",
                     help="only the finite-difference section (one JSON object)")
+    ap.add_argument("--no-dg", action="store_true")
+    ap.add_argument("--dg-only", action="store_true",
+                    help="only the DG volume-term section (one JSON object)")
     ap.add_argument("--ax-only", action="store_true",
                     help="only the FP64 operator launches (for counter runs)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -447,6 +500,9 @@ def main():
 
     if args.fd_only:
         print(json.dumps({"fd2d": bench_fd2d(sem, torch, args.steps)}), flush=True)
+        return
+    if args.dg_only:
+        print(json.dumps({"dg": bench_dg(sem, torch, args.steps)}), flush=True)
         return
     if args.copy_bytes > 0:
         n = args.copy_bytes // 8
@@ -498,6 +554,7 @@ def main():
     sweep = (None if args.no_sweep
              else bench_order_sweep(sem, torch, args.steps, args.warmup))
     fd2d = None if args.no_fd else bench_fd2d(sem, torch, args.steps)
+    dgv = None if args.no_dg else bench_dg(sem, torch, args.steps)
     learned = None if args.no_learned else bench_learned(sem, torch)
     batch = None if args.no_batch else bench_batch(sem, torch)
     cpu = None if args.no_cpu else cpu_baseline()
@@ -527,6 +584,7 @@ def main():
         "sem_ax_low_precision": extra,
         "order_sweep": sweep,
         "fd2d": fd2d,
+        "dg": dgv,
         "pcg": pcg,
         "learned": learned,
         "batch": batch,

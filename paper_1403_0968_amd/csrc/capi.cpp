@@ -482,6 +482,96 @@ sem_status fd2d_run(double *u_a, double *u_b, int64_t nx, int64_t ny, int32_t r,
   });
 }
 
+sem_status dg_reference_nodes(int32_t N, double *r, double *s) {
+  return guarded([&] {
+    need(r != nullptr && s != nullptr, "dg_reference_nodes: null output");
+    const DgRef R = make_dg_ref(N);
+    for (int n = 0; n < R.Np; ++n) {
+      r[n] = R.r[n];
+      s[n] = R.s[n];
+    }
+  });
+}
+
+sem_status dg_setup(int32_t N, int64_t n_vertices, const double *vx,
+                    const double *vy, int64_t n_elements, const int32_t *etov,
+                    const double *bathymetry, double g, void *stream,
+                    dg_handle **out) {
+  if (out) *out = nullptr;
+  dg_handle *h = nullptr;
+  sem_status st = guarded([&] {
+    need(out != nullptr && vx != nullptr && vy != nullptr, "dg_setup: null argument");
+    need(n_vertices >= 3 && n_elements >= 0 && (n_elements == 0 || etov != nullptr),
+         "dg_setup: need vertices and element connectivity");
+    need(N >= 1 && N <= 8, "dg_setup: N must be in 1..8");
+    need(std::isfinite(g), "dg_setup: g must be finite");
+    need(n_elements < (int64_t)1 << 31, "dg_setup: too many elements");
+    h = new dg_handle();
+    h->N = N;
+    h->E = n_elements;
+    h->g = g;
+    dg_device_setup(h, n_vertices, vx, vy, etov, bathymetry, strm(stream));
+  });
+  if (st != SEM_OK) {
+    delete h;
+    return st;
+  }
+  *out = h;
+  return SEM_OK;
+}
+
+sem_status dg_destroy(dg_handle *h) {
+  return guarded([&] {
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    delete h;
+  });
+}
+
+sem_status dg_query(const dg_handle *h, int32_t *n_nodes, int64_t *n_elements) {
+  return guarded([&] {
+    need(h != nullptr, "dg_query: null handle");
+    if (n_nodes) *n_nodes = h->Np;
+    if (n_elements) *n_elements = h->E;
+  });
+}
+
+sem_status dg_export(const dg_handle *h, int32_t which, void *dst,
+                     int64_t dst_bytes, void *stream) {
+  return guarded([&] {
+    need(h != nullptr && dst != nullptr, "dg_export: null argument");
+    const int64_t E = h->E, Np = h->Np;
+    const void *src = nullptr;
+    bool host = false;
+    int64_t n = 0;
+    switch (which) {
+      case DG_ARR_X: src = h->X.p; n = E * Np * 8; break;
+      case DG_ARR_Y: src = h->Y.p; n = E * Np * 8; break;
+      case DG_ARR_GEO: src = h->geo.p; n = E * 4 * 8; break;
+      case DG_ARR_DB: src = h->dB.p; n = E * 2 * Np * 8; break;
+      case DG_ARR_DRW: src = h->ref.Drw.data(); n = Np * Np * 8; host = true; break;
+      case DG_ARR_DSW: src = h->ref.Dsw.data(); n = Np * Np * 8; host = true; break;
+      default: fail(SEM_ERR_ARG, "dg_export: unknown array");
+    }
+    need(dst_bytes >= n, "dg_export: destination too small");
+    if (n == 0) return;
+    SEM_HIP(hipMemcpyAsync(dst, src, (size_t)n,
+                           host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice,
+                           strm(stream)));
+    if (host) SEM_HIP(hipStreamSynchronize(strm(stream)));
+  });
+}
+
+sem_status dg_volume(dg_handle *h, const double *Q, double *rhs, void *stream) {
+  return guarded([&] {
+    need(h != nullptr && Q != nullptr && rhs != nullptr, "dg_volume: null argument");
+    const size_t bytes = (size_t)h->E * 3 * h->Np * sizeof(double);
+    const char *q0 = (const char *)Q, *r0 = (const char *)rhs;
+    need(r0 + bytes <= q0 || q0 + bytes <= r0, "dg_volume: rhs must not overlap Q");
+    launch_dg_volume(h, Q, rhs, strm(stream));
+  });
+}
+
 const char *sem_last_error(void) { return g_last_error.c_str(); }
 
 }  // extern "C"

@@ -1,0 +1,220 @@
+// DG volume term of the 2D shallow-water equations (paper section 4.3): for
+// every triangle, rhs = Dxw F + Dyw G + S with the nodal fluxes
+//   F = (hu, hu^2/h + g h^2/2, hu hv/h), G = (hv, hu hv/h, hv^2/h + g h^2/2),
+// source S = (0, -g h B_x, -g h B_y), and on an affine element
+//   Dxw F + Dyw G = Drw (rx F + ry G) + Dsw (sx F + sy G).
+//
+// The two weak derivative matrices are shared by all elements, so the term is
+// one dense product [Drw | Dsw] (Np x 2Np) times the stacked metric-weighted
+// fluxes (2Np x 3E), plus the nodal source.  It runs on the FP64 matrix
+// cores (v_mfma_f64_16x16x4): one wave takes 16 elements as the 16 columns
+// of the product, one component at a time; the row tiles cover the Np
+// output nodes (padded to 16), the K steps run over the nodes four at a time
+// (padded to 4) for Drw and Dsw together.  Lane l supplies the B operand for
+// (element l % 16, node 4 step + l / 16): it loads h, hu, hv there and forms
+// the fluxes itself, so the operand never passes through LDS, and reads its
+// A operand rows of Drw / Dsw (zero-padded, a few KB, cache-resident)
+// directly.  Output element v of lane l is row l / 16 + 4 v of the tile.
+// From N = 7 on, the Drw and Dsw products accumulate in separate registers
+// (summed at the end), so consecutive matrix instructions do not wait on
+// each other (timed on the 212,800-element mesh: N = 8 404 -> 315 us, no
+// change at N <= 5, where the extra registers would cost occupancy).
+// Measured limits: a dependency-free loop of these instructions reaches
+// about 48 TFLOP/s on this chip (FP64 FMA on the vector units about 66); at
+// high order the kernel is limited by the gathered loads of its operands
+// (16 elements x 4 nodes per instruction): giving each component its own
+// wave, which triples those loads, doubles the time.
+#include "common.h"
+#include "sem_internal.h"
+
+namespace sem {
+
+typedef double dg_d4 __attribute__((ext_vector_type(4)));
+
+constexpr int DG_WAVES = 4;  // waves per workgroup, 16 elements each
+
+template <int N> struct DgShape {
+  static constexpr bool SPLIT = N >= 7;  // separate Drw / Dsw accumulators
+  static constexpr int NP = (N + 1) * (N + 2) / 2;
+  static constexpr int NT = (NP + 15) / 16;  // output row tiles
+  static constexpr int NK = (NP + 3) / 4;    // K steps of four nodes
+  static constexpr int LDA = 4 * NK;         // padded row length of Drw, Dsw
+};
+
+template <int N>
+__global__ void __launch_bounds__(64 * DG_WAVES)
+    k_dg_volume(int64_t E, const double *__restrict__ Q, double *__restrict__ rhs,
+                const double *__restrict__ geo, const double *__restrict__ dB,
+                const double *__restrict__ Drw, const double *__restrict__ Dsw,
+                double g) {
+  using S = DgShape<N>;
+  constexpr int NP = S::NP, NT = S::NT, NK = S::NK, LDA = S::LDA;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, kq = lane >> 4;
+  const int64_t e = ((int64_t)blockIdx.x * DG_WAVES + wave) * 16 + col;
+  const bool act = e < E;
+  const double *Qe = Q + (act ? e : 0) * 3 * NP;
+  double rx = 0.0, sx = 0.0, ry = 0.0, sy = 0.0;
+  if (act) {
+    rx = geo[4 * e];
+    sx = geo[4 * e + 1];
+    ry = geo[4 * e + 2];
+    sy = geo[4 * e + 3];
+  }
+  constexpr bool SPLIT = S::SPLIT;
+  dg_d4 acc[3][NT], acs[3][SPLIT ? NT : 1];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[q][t] = dg_d4{0.0, 0.0, 0.0, 0.0};
+    if constexpr (SPLIT) {
+#pragma unroll
+      for (int t = 0; t < NT; ++t) acs[q][t] = dg_d4{0.0, 0.0, 0.0, 0.0};
+    }
+  }
+  const double hg = 0.5 * g;
+#pragma unroll
+  for (int ks = 0; ks < NK; ++ks) {
+    const int m = 4 * ks + kq;  // node of this lane's B operand
+    double xr[3] = {0.0, 0.0, 0.0}, xs[3] = {0.0, 0.0, 0.0};
+    if (act && m < NP) {
+      const double h = Qe[m], hu = Qe[NP + m], hv = Qe[2 * NP + m];
+      const double u = hu / h, v = hv / h, p = hg * h * h;
+      const double F[3] = {hu, hu * u + p, hu * v};
+      const double G[3] = {hv, hv * u, hv * v + p};
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        xr[q] = rx * F[q] + ry * G[q];
+        xs[q] = sx * F[q] + sy * G[q];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const double ar = Drw[(16 * t + col) * LDA + m];
+      const double as = Dsw[(16 * t + col) * LDA + m];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xr[q], acc[q][t], 0, 0, 0);
+        if constexpr (SPLIT)
+          acs[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, xs[q], acs[q][t], 0, 0, 0);
+        else
+          acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, xs[q], acc[q][t], 0, 0, 0);
+      }
+    }
+  }
+  if (!act) return;
+  double *Re = rhs + e * 3 * NP;
+  const double *Bx = dB + e * 2 * NP, *By = Bx + NP;
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int r = 16 * t + kq + 4 * v;
+      if (r < NP) {
+        double a0 = acc[0][t][v], a1 = acc[1][t][v], a2 = acc[2][t][v];
+        if constexpr (SPLIT) {
+          a0 += acs[0][t][v];
+          a1 += acs[1][t][v];
+          a2 += acs[2][t][v];
+        }
+        const double gh = g * Qe[r];
+        Re[r] = a0;
+        Re[NP + r] = a1 - gh * Bx[r];
+        Re[2 * NP + r] = a2 - gh * By[r];
+      }
+    }
+}
+
+template <int N>
+static void launch_n(const dg_handle *h, const double *Q, double *rhs, hipStream_t s) {
+  const int64_t per = 16 * DG_WAVES;
+  const int64_t blocks = (h->E + per - 1) / per;
+  if (blocks == 0) return;
+  hipLaunchKernelGGL(k_dg_volume<N>, dim3((unsigned)blocks), dim3(64 * DG_WAVES), 0, s,
+                     h->E, Q, rhs, h->geo.as<double>(), h->dB.as<double>(),
+                     h->Drw.as<double>(), h->Dsw.as<double>(), h->g);
+}
+
+void launch_dg_volume(const dg_handle *h, const double *Q, double *rhs,
+                      hipStream_t s) {
+  switch (h->N) {
+    case 1: launch_n<1>(h, Q, rhs, s); break;
+    case 2: launch_n<2>(h, Q, rhs, s); break;
+    case 3: launch_n<3>(h, Q, rhs, s); break;
+    case 4: launch_n<4>(h, Q, rhs, s); break;
+    case 5: launch_n<5>(h, Q, rhs, s); break;
+    case 6: launch_n<6>(h, Q, rhs, s); break;
+    case 7: launch_n<7>(h, Q, rhs, s); break;
+    case 8: launch_n<8>(h, Q, rhs, s); break;
+    default: fail(SEM_ERR_ARG, "dg: N must be in 1..8");
+  }
+  SEM_HIP(hipGetLastError());
+}
+
+int dg_padded_row_length(int N) { return 4 * (((N + 1) * (N + 2) / 2 + 3) / 4); }
+int dg_padded_rows(int N) { return 16 * (((N + 1) * (N + 2) / 2 + 15) / 16); }
+
+// Host setup: reference operators, affine factors, node coordinates and the
+// bathymetry gradient (derivative of B's nodal interpolant), uploaded once.
+void dg_device_setup(dg_handle *h, int64_t nv, const double *vx, const double *vy,
+                     const int32_t *etov, const double *B, hipStream_t s) {
+  const int N = h->N;
+  h->ref = make_dg_ref(N);
+  const int Np = h->ref.Np;
+  h->Np = Np;
+  const int64_t E = h->E;
+  const std::vector<double> &r = h->ref.r, &sn = h->ref.s;
+  std::vector<double> geo(4 * E), X(E * Np), Y(E * Np), dB(E * 2 * Np, 0.0);
+  for (int64_t e = 0; e < E; ++e) {
+    const int32_t a = etov[3 * e], b = etov[3 * e + 1], c = etov[3 * e + 2];
+    if (a < 0 || b < 0 || c < 0 || a >= nv || b >= nv || c >= nv)
+      fail(SEM_ERR_ARG, "dg_setup: element vertex index out of range");
+    const double xr = 0.5 * (vx[b] - vx[a]), xs = 0.5 * (vx[c] - vx[a]);
+    const double yr = 0.5 * (vy[b] - vy[a]), ys = 0.5 * (vy[c] - vy[a]);
+    const double J = xr * ys - xs * yr;
+    if (!(J > 0.0) || !std::isfinite(J))
+      fail(SEM_ERR_ARG, "dg_setup: elements must be non-degenerate and counterclockwise");
+    geo[4 * e] = ys / J;
+    geo[4 * e + 1] = -yr / J;
+    geo[4 * e + 2] = -xs / J;
+    geo[4 * e + 3] = xr / J;
+    for (int n = 0; n < Np; ++n) {
+      const double la = -0.5 * (r[n] + sn[n]), lb = 0.5 * (1.0 + r[n]), lc = 0.5 * (1.0 + sn[n]);
+      X[e * Np + n] = la * vx[a] + lb * vx[b] + lc * vx[c];
+      Y[e * Np + n] = la * vy[a] + lb * vy[b] + lc * vy[c];
+    }
+    if (B != nullptr) {
+      const double *Be = B + e * Np;
+      for (int n = 0; n < Np; ++n) {
+        double br = 0.0, bs = 0.0;
+        for (int m = 0; m < Np; ++m) {
+          br += h->ref.Dr[n * Np + m] * Be[m];
+          bs += h->ref.Ds[n * Np + m] * Be[m];
+        }
+        dB[e * 2 * Np + n] = geo[4 * e] * br + geo[4 * e + 1] * bs;
+        dB[e * 2 * Np + Np + n] = geo[4 * e + 2] * br + geo[4 * e + 3] * bs;
+      }
+    }
+  }
+  const int lda = dg_padded_row_length(N), rows = dg_padded_rows(N);
+  std::vector<double> Ar(rows * lda, 0.0), As(rows * lda, 0.0);
+  for (int i = 0; i < Np; ++i)
+    for (int k = 0; k < Np; ++k) {
+      Ar[i * lda + k] = h->ref.Drw[i * Np + k];
+      As[i * lda + k] = h->ref.Dsw[i * Np + k];
+    }
+  auto up = [&](DevBuf &d, const std::vector<double> &v) {
+    d.alloc(v.size() * sizeof(double));
+    SEM_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+  };
+  up(h->geo, geo);
+  up(h->dB, dB);
+  up(h->X, X);
+  up(h->Y, Y);
+  up(h->Drw, Ar);
+  up(h->Dsw, As);
+  SEM_HIP(hipStreamSynchronize(s));  // host vectors go out of scope
+}
+
+}  // namespace sem

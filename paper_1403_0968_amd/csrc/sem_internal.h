@@ -7,6 +7,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/dg.h"
 #include "../../include/sem.h"
 #include "structured.h"
 
@@ -31,6 +32,13 @@ struct RefElem {
   std::vector<double> xi, w, D;  // D[i*n1+m] = l_m'(xi_i)
 };
 RefElem make_ref_elem(int N);
+
+// reference triangle of the DG volume term (host, FP64, row-major Np x Np)
+struct DgRef {
+  int N = 0, Np = 0;
+  std::vector<double> r, s, Dr, Ds, Drw, Dsw;
+};
+DgRef make_dg_ref(int N);
 
 // ---------------------------------------------------------------------------
 // maps of the structured box (host)
@@ -106,6 +114,16 @@ constexpr int AX_SET_468 = 100;  // batched operator compiled for n1 in {4,6,8}
 
 }  // namespace sem
 
+struct dg_handle {
+  int N = 0, Np = 0;
+  int64_t E = 0;
+  double g = 0.0;
+  sem::DgRef ref;
+  // per element: (rx, sx, ry, sy); bathymetry gradient [E][2][Np]; node
+  // coordinates [E][Np]; Drw, Dsw zero-padded to whole MFMA tiles
+  sem::DevBuf geo, dB, X, Y, Drw, Dsw;
+};
+
 namespace sem {
 struct Workspace;  // solver buffers, graphs and streams (solver.hip)
 struct Learn;      // learned-correction buffers (learn.hip)
@@ -161,6 +179,11 @@ void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *s
                      const AxItem *items, int nitems, int epb, int grid, int src,
                      int dst, int skip_done, hipStream_t s);
 int bax_elements_per_tile(int bs, int n1);
+// DG volume term (dg.hip)
+void dg_device_setup(dg_handle *h, int64_t nv, const double *vx, const double *vy,
+                     const int32_t *etov, const double *B, hipStream_t s);
+void launch_dg_volume(const dg_handle *h, const double *Q, double *rhs,
+                      hipStream_t s);
 // finite-difference wave step (fd2d.hip); c = dt^2 / dx^2
 void fd2d_weights_host(int r, double *w);
 void launch_fd2d(const double *u_cur, const double *u_prev, double *u_next,

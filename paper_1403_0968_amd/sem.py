@@ -33,7 +33,9 @@ EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_mlp_set_damping", "sem_mlp_get_damping", "sem_mlp_save", "sem_mlp_load", "sem_learn_attach",
             "sem_learn_train", "sem_learn_interior_pairs",
             "sem_learn_coarse_exact", "sem_mlp_loss_grad_factor",
-            "fd2d_weights", "fd2d_step", "fd2d_run", "sem_last_error"]
+            "fd2d_weights", "fd2d_step", "fd2d_run", "dg_reference_nodes",
+            "dg_setup", "dg_destroy", "dg_query", "dg_export", "dg_volume",
+            "sem_last_error"]
 
 
 class sem_mesh_desc(C.Structure):
@@ -150,6 +152,15 @@ def lib():
                             C.c_double, vp]
     L.fd2d_run.argtypes = [vp, vp, C.c_int64, C.c_int64, i32, C.c_double,
                            C.c_double, i32, vp]
+    L.dg_reference_nodes.argtypes = [i32, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double)]
+    L.dg_setup.argtypes = [i32, C.c_int64, C.POINTER(C.c_double),
+                           C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_int32),
+                           C.POINTER(C.c_double), C.c_double, vp, C.POINTER(vp)]
+    L.dg_destroy.argtypes = [vp]
+    L.dg_query.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
+    L.dg_export.argtypes = [vp, i32, vp, C.c_int64, vp]
+    L.dg_volume.argtypes = [vp, vp, vp, vp]
     L.sem_last_error.argtypes = []
     L.sem_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -497,3 +508,61 @@ def fd2d_run(u_a, u_b, r, dt, dx, nsteps, stream=None):
         raise ValueError("fd2d grids must have equal shapes")
     _check(lib().fd2d_run(_ptr(u_a), _ptr(u_b), nx, ny, int(r), float(dt),
                           float(dx), int(nsteps), _stream(stream)))
+
+
+# ----------------------------------------------------------------------------
+# DG shallow-water volume term (include/dg.h)
+# ----------------------------------------------------------------------------
+
+DG_ARR_X, DG_ARR_Y, DG_ARR_GEO, DG_ARR_DB, DG_ARR_DRW, DG_ARR_DSW = range(6)
+
+
+def dg_reference_nodes(N):
+    import numpy as np
+    np_ = (N + 1) * (N + 2) // 2
+    r, s = (C.c_double * np_)(), (C.c_double * np_)()
+    _check(lib().dg_reference_nodes(int(N), r, s))
+    return np.array(list(r)), np.array(list(s))
+
+
+def dg_setup(N, vx, vy, etov, bathymetry=None, g=9.81, stream=None):
+    """vx, vy: host vertex coordinates; etov: int [E][3] counterclockwise;
+    bathymetry: host [E][Np] nodal B or None.  Returns a handle."""
+    import numpy as np
+    vx_a, vx_p = _dptr(vx)
+    vy_a, vy_p = _dptr(vy)
+    ev = np.ascontiguousarray(etov, dtype=np.int32)
+    keep = [vx_a, vy_a, ev]
+    b_p = None
+    if bathymetry is not None:
+        b_a, b_p = _dptr(bathymetry)
+        np_ = (N + 1) * (N + 2) // 2
+        if b_a.size != ev.shape[0] * np_:
+            raise ValueError(f"bathymetry needs {ev.shape[0] * np_} nodal values")
+        keep.append(b_a)
+    h = C.c_void_p()
+    _check(lib().dg_setup(int(N), int(vx_a.shape[0]), vx_p, vy_p,
+                          int(ev.shape[0]),
+                          ev.ctypes.data_as(C.POINTER(C.c_int32)), b_p,
+                          float(g), _stream(stream), C.byref(h)))
+    return h
+
+
+def dg_destroy(h):
+    _check(lib().dg_destroy(h))
+
+
+def dg_query(h):
+    n, e = C.c_int32(), C.c_int64()
+    _check(lib().dg_query(h, C.byref(n), C.byref(e)))
+    return n.value, e.value
+
+
+def dg_export(h, which, dst, stream=None):
+    _check(lib().dg_export(h, int(which), _ptr(dst),
+                           dst.numel() * dst.element_size(), _stream(stream)))
+
+
+def dg_volume(h, Q, rhs, stream=None):
+    """Q, rhs: device float64 tensors [E][3][Np]."""
+    _check(lib().dg_volume(h, _ptr(Q), _ptr(rhs), _stream(stream)))

@@ -19,6 +19,12 @@ for its spectral-element benchmark):
   on local nodes).
 * ``batch_configs(count, seed)``: uneven batched solves, cubic grids n^3 with
   n ~ U{6..24} and order N ~ U{3, 5, 7}.
+* ``tri_mesh(nx, ny, seed)``: the stand-in for the shallow-water example's
+  triangle mesh (its mesh and bathymetry are not published with the paper):
+  a rectangle of nx x ny cells, interior grid points moved by a uniform
+  random offset of up to 15 % of the cell size in each direction, every cell
+  split into two counterclockwise triangles with the diagonal alternating
+  from cell to cell (266 x 400 cells give the example's 212,800 triangles).
 """
 from __future__ import annotations
 
@@ -65,3 +71,26 @@ def batch_configs(count: int = 256, seed: int = 0, nmin: int = 6,
         N = int(rng.choice(orders))
         out.append((n, N))
     return out
+
+
+def tri_mesh(nx: int, ny: int, seed: int = 0, lx: float = 1.0,
+             ly: float = 1.0, jitter: float = 0.15):
+    """Vertex coordinates vx, vy and int32 connectivity [2 nx ny][3]."""
+    rng = np.random.default_rng(seed)
+    hx, hy = lx / nx, ly / ny
+    I, J = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1), indexing="xy")
+    vx = (I * hx).astype(np.float64)
+    vy = (J * hy).astype(np.float64)
+    inner = (I > 0) & (I < nx) & (J > 0) & (J < ny)
+    vx[inner] += rng.uniform(-jitter, jitter, inner.sum()) * hx
+    vy[inner] += rng.uniform(-jitter, jitter, inner.sum()) * hy
+    vid = lambda i, j: j * (nx + 1) + i
+    tris = []
+    for j in range(ny):
+        for i in range(nx):
+            a, b, c, d = vid(i, j), vid(i + 1, j), vid(i + 1, j + 1), vid(i, j + 1)
+            if (i + j) % 2 == 0:
+                tris += [(a, b, c), (a, c, d)]
+            else:
+                tris += [(a, b, d), (b, c, d)]
+    return vx.ravel(), vy.ravel(), np.array(tris, dtype=np.int32)

@@ -17,7 +17,7 @@ def declared_functions():
         text = open(h).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         for m in re.finditer(
-                r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:sem|fd2d)_\w+)\s*\(",
+                r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:sem|fd2d|dg)_\w+)\s*\(",
                 text, flags=re.M):
             names.add(m.group(1))
     return sorted(names)
@@ -75,3 +75,24 @@ def test_fd2d_weights_host_logic_bit_exact():
                                       fd.weights(r).view(np.uint64))
     buf = (ctypes.c_double * 32)()
     assert lib.fd2d_weights(0, buf) == 1 and lib.fd2d_weights(8, buf) == 1
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsem.so not built")
+def test_dg_reference_nodes_host_logic():
+    """dg_reference_nodes is host code: its warp-and-blend nodes equal the
+    oracle's (an independent implementation) to rounding, N = 1..8."""
+    import numpy as np
+    from oracle import dg
+    lib = ctypes.CDLL(LIB)
+    P = ctypes.POINTER(ctypes.c_double)
+    lib.dg_reference_nodes.argtypes = [ctypes.c_int32, P, P]
+    lib.dg_reference_nodes.restype = ctypes.c_int
+    for N in range(1, 9):
+        n = (N + 1) * (N + 2) // 2
+        r, s = (ctypes.c_double * n)(), (ctypes.c_double * n)()
+        assert lib.dg_reference_nodes(N, r, s) == 0
+        ro, so = dg.nodes(N)
+        np.testing.assert_allclose(np.array(list(r)), ro, rtol=0, atol=2e-15)
+        np.testing.assert_allclose(np.array(list(s)), so, rtol=0, atol=2e-15)
+    buf = (ctypes.c_double * 64)()
+    assert lib.dg_reference_nodes(9, buf, buf) == 1
