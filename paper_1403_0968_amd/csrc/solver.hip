@@ -104,10 +104,27 @@ __global__ void __launch_bounds__(RT)
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
       const NodeCopies nc = node_copies(bx, (uint32_t)g);
       TV s = TV(0);
-      if (!nc.masked)
-        for (int a = 0; a < nc.z.cnt; ++a)
-          for (int b = 0; b < nc.y.cnt; ++b)
-            for (int c = 0; c < nc.x.cnt; ++c) s = s + wL[copy_lid(bx, nc, a, b, c)];
+      if (!nc.masked) {
+        // all (up to 8) copies loaded at once, predicated on existence, then
+        // summed in ascending local index (z, y, x copy order); an absent
+        // copy adds +0.0, which leaves the sum unchanged bit for bit (the
+        // sum starts at +0.0 and so is never -0.0).  Loading them one after
+        // another cost 30 % more time; four nodes per thread at once, 30 %
+        // more again (registers)
+        TV v[8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const bool ok = a < nc.z.cnt && b < nc.y.cnt && c < nc.x.cnt;
+              const int64_t lid = ok ? copy_lid(bx, nc, a, b, c) : 0;
+              v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
+            }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s = s + v[k];
+      }
       wG[g] = s;
       if (DOT) acc += (double)p[g] * (double)s;
     }
