@@ -26,6 +26,7 @@ MESHES = [
     (1, 3, 2, 3, AFF), (2, 2, 3, 2, CYC), (3, 5, 3, 3, CYC),
     (4, 4, 4, 4, AFF), (5, 3, 3, 2, CYC), (6, 2, 2, 3, SX),
     (7, 3, 3, 5, CYC), (8, 2, 3, 2, CYC), (7, 1, 1, 1, CYC),
+    (8, 2, 1, 2, CYC),  # 4 elements: ragged last workgroup of 3 at N = 8
 ]
 
 
