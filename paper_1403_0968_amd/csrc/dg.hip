@@ -15,15 +15,19 @@
 // the fluxes itself, so the operand never passes through LDS, and reads its
 // A operand rows of Drw / Dsw (zero-padded, a few KB, cache-resident)
 // directly.  Output element v of lane l is row l / 16 + 4 v of the tile.
-// From N = 7 on, the Drw and Dsw products accumulate in separate registers
-// (summed at the end), so consecutive matrix instructions do not wait on
-// each other (timed on the 212,800-element mesh: N = 8 404 -> 315 us, no
-// change at N <= 5, where the extra registers would cost occupancy).
+// The loads of K step ks + 1 (the lane's state, at a clamped node index, and
+// its operator entries) are issued before the products of step ks, so the
+// memory latency of one step hides behind the matrix instructions of the
+// previous one; per step, all Drw products come first, then all Dsw
+// products, so the two updates of one accumulator are 3 NT instructions
+// apart.  Timed on the 212,800-element mesh against loading each step's
+// operands just before use (with separate Drw / Dsw accumulators from N = 7):
+// N = 2..8 20.2, 32.7, 55.4, 103, 129, 209, 313 us -> 17.9, 28.6, 44.1,
+// 91.4, 118, 167, 272 us.  The K loop is unrolled completely except at
+// N = 8, where that schedule is slower (373 us) than unrolling by two; at
+// N = 7 the kernel is held to two waves per SIMD's worth of registers.
 // Measured limits: a dependency-free loop of these instructions reaches
-// about 48 TFLOP/s on this chip (FP64 FMA on the vector units about 66); at
-// high order the kernel is limited by the gathered loads of its operands
-// (16 elements x 4 nodes per instruction): giving each component its own
-// wave, which triples those loads, doubles the time.
+// about 48 TFLOP/s on this chip (FP64 FMA on the vector units about 66).
 #include "common.h"
 #include "sem_internal.h"
 
@@ -34,15 +38,17 @@ typedef double dg_d4 __attribute__((ext_vector_type(4)));
 constexpr int DG_WAVES = 4;  // waves per workgroup, 16 elements each
 
 template <int N> struct DgShape {
-  static constexpr bool SPLIT = N >= 7;  // separate Drw / Dsw accumulators
   static constexpr int NP = (N + 1) * (N + 2) / 2;
   static constexpr int NT = (NP + 15) / 16;  // output row tiles
   static constexpr int NK = (NP + 3) / 4;    // K steps of four nodes
   static constexpr int LDA = 4 * NK;         // padded row length of Drw, Dsw
+  static constexpr int UNROLL = N == 8 ? 2 : NK;
+  static constexpr int WAVES_PER_EU = N == 7 ? 2 : 1;
 };
 
 template <int N>
 __global__ void __launch_bounds__(64 * DG_WAVES)
+    __attribute__((amdgpu_waves_per_eu(DgShape<N>::WAVES_PER_EU)))
     k_dg_volume(int64_t E, const double *__restrict__ Q, double *__restrict__ rhs,
                 const double *__restrict__ geo, const double *__restrict__ dB,
                 const double *__restrict__ Drw, const double *__restrict__ Dsw,
@@ -54,6 +60,8 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
   const int64_t e = ((int64_t)blockIdx.x * DG_WAVES + wave) * 16 + col;
   const bool act = e < E;
   const double *Qe = Q + (act ? e : 0) * 3 * NP;
+  // this lane's A operand entries: row 16 t + col, column 4 ks + kq
+  const double *Ar = Drw + (col * LDA + kq), *As = Dsw + (col * LDA + kq);
   double rx = 0.0, sx = 0.0, ry = 0.0, sy = 0.0;
   if (act) {
     rx = geo[4 * e];
@@ -61,46 +69,56 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     ry = geo[4 * e + 2];
     sy = geo[4 * e + 3];
   }
-  constexpr bool SPLIT = S::SPLIT;
-  dg_d4 acc[3][NT], acs[3][SPLIT ? NT : 1];
+  dg_d4 acc[3][NT];
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
+  for (int q = 0; q < 3; ++q)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[q][t] = dg_d4{0.0, 0.0, 0.0, 0.0};
-    if constexpr (SPLIT) {
-#pragma unroll
-      for (int t = 0; t < NT; ++t) acs[q][t] = dg_d4{0.0, 0.0, 0.0, 0.0};
-    }
-  }
   const double hg = 0.5 * g;
-#pragma unroll
-  for (int ks = 0; ks < NK; ++ks) {
-    const int m = 4 * ks + kq;  // node of this lane's B operand
-    double xr[3] = {0.0, 0.0, 0.0}, xs[3] = {0.0, 0.0, 0.0};
-    if (act && m < NP) {
-      const double h = Qe[m], hu = Qe[NP + m], hv = Qe[2 * NP + m];
-      const double u = hu / h, v = hv / h, p = hg * h * h;
-      const double F[3] = {hu, hu * u + p, hu * v};
-      const double G[3] = {hv, hv * u, hv * v + p};
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        xr[q] = rx * F[q] + ry * G[q];
-        xs[q] = sx * F[q] + sy * G[q];
-      }
-    }
+  double qn[3], an[NT], sn[NT];  // operands of the next K step
+  auto fetch = [&](int ks) {
+    const int m = min(4 * ks + kq, NP - 1);
+    qn[0] = Qe[m];
+    qn[1] = Qe[NP + m];
+    qn[2] = Qe[2 * NP + m];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      const double ar = Drw[(16 * t + col) * LDA + m];
-      const double as = Dsw[(16 * t + col) * LDA + m];
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xr[q], acc[q][t], 0, 0, 0);
-        if constexpr (SPLIT)
-          acs[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, xs[q], acs[q][t], 0, 0, 0);
-        else
-          acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, xs[q], acc[q][t], 0, 0, 0);
-      }
+      an[t] = Ar[16 * t * LDA + 4 * ks];
+      sn[t] = As[16 * t * LDA + 4 * ks];
     }
+  };
+  fetch(0);
+#pragma unroll S::UNROLL
+  for (int ks = 0; ks < NK; ++ks) {
+    const double h = qn[0], hu = qn[1], hv = qn[2];
+    double ar[NT], as[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      ar[t] = an[t];
+      as[t] = sn[t];
+    }
+    if (ks + 1 < NK) fetch(ks + 1);
+    // fluxes at node 4 ks + kq of element e (zero beyond Np or the mesh)
+    const double u = hu / h, v = hv / h, p = hg * h * h;
+    const double F[3] = {hu, hu * u + p, hu * v};
+    const double G[3] = {hv, hv * u, hv * v + p};
+    const bool ok = act && 4 * ks + kq < NP;
+    double xr[3], xs[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      xr[q] = ok ? rx * F[q] + ry * G[q] : 0.0;
+      xs[q] = ok ? sx * F[q] + sy * G[q] : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[t], xr[q], acc[q][t], 0, 0, 0);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[t], xs[q], acc[q][t], 0, 0, 0);
   }
   if (!act) return;
   double *Re = rhs + e * 3 * NP;
@@ -111,16 +129,10 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * t + kq + 4 * v;
       if (r < NP) {
-        double a0 = acc[0][t][v], a1 = acc[1][t][v], a2 = acc[2][t][v];
-        if constexpr (SPLIT) {
-          a0 += acs[0][t][v];
-          a1 += acs[1][t][v];
-          a2 += acs[2][t][v];
-        }
         const double gh = g * Qe[r];
-        Re[r] = a0;
-        Re[NP + r] = a1 - gh * Bx[r];
-        Re[2 * NP + r] = a2 - gh * By[r];
+        Re[r] = acc[0][t][v];
+        Re[NP + r] = acc[1][t][v] - gh * Bx[r];
+        Re[2 * NP + r] = acc[2][t][v] - gh * By[r];
       }
     }
 }
