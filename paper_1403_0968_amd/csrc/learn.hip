@@ -46,14 +46,21 @@ namespace sem {
 
 enum { LM_Q1 = 0, LM_NODAL = 1, LM_INTERIOR = 2, LM_COARSE = 3 };
 
+struct CoarseTab {
+  float B1[7][3];  // B1[i][a] = (1 - x_i^2) P_a(x_i) at interior GLL point i
+  float sc[27];    // column scale of B, column a + Q (b + Q c)
+};
+
 struct Learn {
   int ldx = 0, n3 = 0, n_out = 0, ldo = 0;
   int mode = LM_NODAL, nf = 0, nt = 0;  // layout, feature nodes, target width
-  // coarse layout: basis B [ni][K] (FP32 and FP64), kappa features of every
+  // coarse layout: basis B [ni][K] (FP64; FP32 factors B1 and the column
+  // scale sc for the apply kernel, sc also on the device), kappa features of every
   // element (BF16 [E][ldx]), element operators M_e / (kappa_e h_e) (FP32
   // [E][K][K]) for the network of version mver
   int K = 0, ni = 0;
-  DevBuf Bf, Bd, Xk, Ml, cG;  // cG: correction on unique nodes (FP32)
+  DevBuf Bd, Xk, Ml, cG, Sc;  // cG: correction on unique nodes (FP32)
+  CoarseTab tab{};            // factors of B for the apply kernel (FP32)
   const sem_mlp *mnet = nullptr;
   uint64_t mver = 0;
   DevBuf X, s, O, kfeat, invkh, cL, h1, h2;  // h1, h2: hidden activations
@@ -358,127 +365,194 @@ __global__ void __launch_bounds__(256)
 // numbering) and c written to the interior entries of the unique-node
 // vector out (its other entries stay zero); otherwise r is a continuous
 // E-vector and out the E-vector of element corrections, zero on the faces.
-// Persistent 256-thread workgroups hold B (ni x K) in LDS and walk groups
-// of four elements, one per wave: the wave stages r_I in LDS, lanes 2j and
-// 2j+1 sum half of B[:, j]^T r_I each (y = B^T r_I), lanes i < K form
-// alpha_i = sum_j M_e[j][i] y_j (M_e is symmetric, so the reads are
-// coalesced; they are issued with the gather of r_I) and every lane
-// expands c = B alpha on its interior nodes.
+// The basis is a tensor product with a column scale, B = (B1 x B1 x B1)
+// diag(sc) (B1: the Q 1D bubbles on the M interior points), so both
+// products are sum-factorised: y = sc o (B1^T x B1^T x B1^T) r_I in three
+// contractions of one direction each, then alpha = damping M_e y, then
+// c = (B1 x B1 x B1)(sc o alpha) in three more (M = 6, Q = 3: 1.1 k instead
+// of 5.8 k multiply-adds each way).  One wave per element, persistent, no workgroup barrier: lane
+// p < M^2 owns the pencil (j, k) of M contiguous interior nodes, the
+// intermediate tensors pass through the wave's LDS region, and the loads of
+// the wave's next element (its pencil values and M_e) are issued before the
+// current element's contractions.  (The dense form, one wave per element
+// with B in LDS: 43 us per apply at 24^3 elements, N = 7, bound by its LDS
+// and vector instruction count.)
 constexpr int CA_WAVES = 4;
 
-template <class TV, bool UNIQUE, int K>
+// orders the wave's LDS writes before its later LDS reads of other lanes'
+// entries (the lanes of one wave execute together; the fences keep the
+// compiler from moving accesses across this point)
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <class TV, bool UNIQUE, int M, int Q>
 __global__ void __launch_bounds__(64 * CA_WAVES)
-    k_coarse_apply(int64_t E, int n1, int ni, Box box,
-                   const TV *__restrict__ r, const float *__restrict__ Bf,
-                   const float *__restrict__ Ml, const float *__restrict__ damping,
-                   float *__restrict__ out) {
-  extern __shared__ float ca_lds[];
-  float *Bs = ca_lds;                                   // [ni][K]
+    k_coarse_apply(int64_t E, Box box, CoarseTab tb, const float *__restrict__ scg,
+                   const TV *__restrict__ r, const float *__restrict__ Ml,
+                   const float *__restrict__ damping, float *__restrict__ out) {
+  constexpr int K = Q * Q * Q, KK = K * K, MR = (KK + 63) / 64, P = M * M;
+  constexpr int N1 = M + 2, N3 = N1 * N1 * N1, Q2 = Q * Q;
+  constexpr int REG = Q * P + Q2 * M + 2 * 32 + KK;  // floats per wave
+  __shared__ float ca_lds[CA_WAVES * REG];
   const int wave = threadIdx.x >> 6, t = threadIdx.x & 63;
-  float *rI = ca_lds + ni * K + wave * (ni + 64);       // [ni]
-  float *yv = rI + ni;                                  // [K] then alpha [K]
-  float *al = yv + 32;
-  for (int q = threadIdx.x; q < ni * K; q += 64 * CA_WAVES) Bs[q] = Bf[q];
-  const int n3 = n1 * n1 * n1, m = n1 - 2;
-  const int half = (ni + 1) / 2;
+  float *s1 = ca_lds + wave * REG;  // [Q][P]  (a, pencil)
+  float *s2 = s1 + Q * P;           // [M][Q2] (k, a + Q b)
+  float *yv = s2 + Q2 * M;          // [K]
+  float *bv = yv + 32;              // [K]
+  float *Ms = bv + 32;              // [K][K]
   const float damp = damping[0];
-  __syncthreads();
-  for (int64_t e0 = (int64_t)blockIdx.x * CA_WAVES; e0 < E;
-       e0 += (int64_t)gridDim.x * CA_WAVES) {  // uniform over the workgroup
-    const int64_t e = e0 + wave;
-    const bool act = e < E;
-    float mcol[K];  // column t of M_e (= row t: M_e is symmetric)
-    if (act && t < K) {
-      const float *Me = Ml + e * K * K;
+  const float sct = t < K ? scg[t] : 0.f;
+  // first interior node of this lane's pencil (j, k) = (t % M, t / M)
+  const int pj = t % M + 1, pk = min(t / M, M - 1) + 1;
+  const int64_t offp = UNIQUE ? 1 + (int64_t)box.Gx * pj + box.Gxy * pk
+                              : 1 + (int64_t)N1 * (pj + N1 * pk);
+  auto base = [&](int64_t e) -> int64_t {
+    return UNIQUE ? box_origin(box, (uint32_t)e) : e * N3;
+  };
+  const int64_t stride = (int64_t)gridDim.x * CA_WAVES;
+  int64_t e = (int64_t)blockIdx.x * CA_WAVES + wave;
+  TV rv[M];
+  float mv[MR];
+  auto fetch = [&](int64_t en) {
+    const int64_t g = base(en) + offp;
 #pragma unroll
-      for (int jj = 0; jj < K; ++jj) mcol[jj] = Me[jj * K + t];
-    }
-    int64_t g0 = 0;
-    if (UNIQUE && act) g0 = box_origin(box, (uint32_t)e);
-    auto index = [&](int q) -> int64_t {
-      const int i = q % m + 1, j = (q / m) % m + 1, k = q / (m * m) + 1;
-      return UNIQUE ? g0 + i + (int64_t)box.Gx * j + box.Gxy * k
-                    : e * n3 + i + n1 * (j + n1 * k);
-    };
-    if (act)
-      for (int q = t; q < ni; q += 64) rI[q] = (float)r[index(q)];
-    __syncthreads();
-    if (act && t < 2 * K) {
-      // four independent partial sums keep several LDS reads in flight
-      const int j = t >> 1, q0 = (t & 1) * half, q1 = min(ni, q0 + half);
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-      int q = q0;
-      for (; q + 4 <= q1; q += 4) {
-        a0 += Bs[q * K + j] * rI[q];
-        a1 += Bs[(q + 1) * K + j] * rI[q + 1];
-        a2 += Bs[(q + 2) * K + j] * rI[q + 2];
-        a3 += Bs[(q + 3) * K + j] * rI[q + 3];
+    for (int i = 0; i < M; ++i) rv[i] = t < P ? r[g + i] : TV(0);
+    const float *Me = Ml + en * KK;
+#pragma unroll
+    for (int i = 0; i < MR; ++i) mv[i] = t + 64 * i < KK ? Me[t + 64 * i] : 0.f;
+  };
+  if (e < E) fetch(e);
+  for (; e < E; e += stride) {
+    // restriction, direction i (registers): s1[a][pencil]
+    if (t < P) {
+#pragma unroll
+      for (int a = 0; a < Q; ++a) {
+        float acc = 0.f;
+#pragma unroll
+        for (int i = 0; i < M; ++i) acc += tb.B1[i][a] * (float)rv[i];
+        s1[a * P + t] = acc;
       }
-      for (; q < q1; ++q) a0 += Bs[q * K + j] * rI[q];
-      float a = (a0 + a1) + (a2 + a3);
-      a += __shfl_xor(a, 1, 64);
-      if ((t & 1) == 0) yv[j] = a;
     }
-    __syncthreads();
-    if (act && t < K) {
-      float a = 0.f;
 #pragma unroll
-      for (int jj = 0; jj < K; ++jj) a += mcol[jj] * yv[jj];
-      al[t] = damp * a;
-    }
-    __syncthreads();
-    if (act) {
-      float ar[K];
+    for (int i = 0; i < MR; ++i)
+      if (t + 64 * i < KK) Ms[t + 64 * i] = mv[i];
+    wave_sync();
+    if (e + stride < E) fetch(e + stride);
+    // direction j: lane (a, k) -> s2[k][a + Q b]
+    if (t < Q * M) {
+      const int a = t % Q, k = t / Q;
+      float v[M];
 #pragma unroll
-      for (int jj = 0; jj < K; ++jj) ar[jj] = al[jj];
-      for (int q = t; q < ni; q += 64) {
-        float c0 = 0.f, c1 = 0.f;
+      for (int j = 0; j < M; ++j) v[j] = s1[a * P + j + M * k];
 #pragma unroll
-        for (int jj = 0; jj + 1 < K; jj += 2) {
-          c0 += Bs[q * K + jj] * ar[jj];
-          c1 += Bs[q * K + jj + 1] * ar[jj + 1];
-        }
-        if (K & 1) c0 += Bs[q * K + K - 1] * ar[K - 1];
-        out[index(q)] = c0 + c1;
+      for (int b = 0; b < Q; ++b) {
+        float acc = 0.f;
+#pragma unroll
+        for (int j = 0; j < M; ++j) acc += tb.B1[j][b] * v[j];
+        s2[k * Q2 + a + Q * b] = acc;
       }
-      if (!UNIQUE)  // the faces of the element carry no correction
-        for (int p = t; p < n3; p += 64) {
-          const int i = p % n1, j = (p / n1) % n1, k = p / (n1 * n1);
-          if (interior_index(i, j, k, n1) < 0) out[e * n3 + p] = 0.f;
-        }
     }
-    __syncthreads();  // rI, yv, al are reused by the next group
+    wave_sync();
+    // direction k: lane ab -> y[ab + Q2 c] (unscaled)
+    if (t < Q2) {
+      float v[M];
+#pragma unroll
+      for (int k = 0; k < M; ++k) v[k] = s2[k * Q2 + t];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < M; ++k) acc += tb.B1[k][c] * v[k];
+        yv[t + Q2 * c] = acc;
+      }
+    }
+    wave_sync();
+    // alpha = damping M_e (sc o y); beta = sc o alpha
+    if (t < K) {
+      float acc = 0.f;
+#pragma unroll
+      for (int jj = 0; jj < K; ++jj) acc += Ms[jj * K + t] * (tb.sc[jj] * yv[jj]);
+      bv[t] = sct * (damp * acc);
+    }
+    wave_sync();
+    // prolongation, direction k: lane ab -> s2[k][ab]
+    if (t < Q2) {
+      float v[Q];
+#pragma unroll
+      for (int c = 0; c < Q; ++c) v[c] = bv[t + Q2 * c];
+#pragma unroll
+      for (int k = 0; k < M; ++k) {
+        float acc = 0.f;
+#pragma unroll
+        for (int c = 0; c < Q; ++c) acc += tb.B1[k][c] * v[c];
+        s2[k * Q2 + t] = acc;
+      }
+    }
+    wave_sync();
+    // direction j: lane (a, k) -> s1[a][j + M k]
+    if (t < Q * M) {
+      const int a = t % Q, k = t / Q;
+      float v[Q];
+#pragma unroll
+      for (int b = 0; b < Q; ++b) v[b] = s2[k * Q2 + a + Q * b];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        float acc = 0.f;
+#pragma unroll
+        for (int b = 0; b < Q; ++b) acc += tb.B1[j][b] * v[b];
+        s1[a * P + j + M * k] = acc;
+      }
+    }
+    wave_sync();
+    // direction i: lane = pencil, M contiguous interior nodes
+    if (t < P) {
+      float v[Q];
+#pragma unroll
+      for (int a = 0; a < Q; ++a) v[a] = s1[a * P + t];
+      const int64_t g = base(e) + offp;
+#pragma unroll
+      for (int i = 0; i < M; ++i) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < Q; ++a) acc += tb.B1[i][a] * v[a];
+        out[g + i] = acc;
+      }
+    }
+    if (!UNIQUE)  // the faces of the element carry no correction
+      for (int p = t; p < N3; p += 64) {
+        const int i = p % N1, j = (p / N1) % N1, k = p / (N1 * N1);
+        if (interior_index(i, j, k, N1) < 0) out[e * N3 + p] = 0.f;
+      }
+    wave_sync();  // the LDS region is rewritten for the next element
   }
+}
+
+template <class TV, bool UNIQUE, int M, int Q>
+static void launch_ca(const sem_handle *h, const Learn *L, const TV *r, float *out,
+                      hipStream_t s) {
+  const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet) : Box{};
+  const int64_t groups = (h->E + CA_WAVES - 1) / CA_WAVES;
+  const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * 8);
+  hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, M, Q>), dim3(grid), dim3(64 * CA_WAVES),
+                     0, s, h->E, box, L->tab, L->Sc.as<float>(), r, L->Ml.as<float>(),
+                     mlp_damping_dev(h->net), out);
 }
 
 template <class TV, bool UNIQUE>
 static void launch_coarse_apply(const sem_handle *h, const Learn *L, const TV *r,
                                 float *out, hipStream_t s) {
-  const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet) : Box{};
-  const size_t lds = ((size_t)L->ni * L->K + CA_WAVES * ((size_t)L->ni + 64)) * 4;
-  const int64_t groups = (h->E + CA_WAVES - 1) / CA_WAVES;
-  // workgroups that stay resident together (LDS, and four per CU for the
-  // register use of the K = 27 kernel), 256 CUs
-  const int64_t per_cu = std::max<int64_t>(1, std::min<int64_t>(4, 160 * 1024 / (int64_t)lds));
-  const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * per_cu);
-  const dim3 g(grid), b(64 * CA_WAVES);
-  const float *Bf = L->Bf.as<float>(), *Ml = L->Ml.as<float>();
-  const float *damp = mlp_damping_dev(h->net);
-  switch (L->K) {
-    case 1:
-      hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, 1>), g, b, lds, s, h->E, h->n1,
-                         L->ni, box, r, Bf, Ml, damp, out);
-      break;
-    case 8:
-      hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, 8>), g, b, lds, s, h->E, h->n1,
-                         L->ni, box, r, Bf, Ml, damp, out);
-      break;
-    case 27:
-      hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, 27>), g, b, lds, s, h->E, h->n1,
-                         L->ni, box, r, Bf, Ml, damp, out);
-      break;
-    default:
-      fail(SEM_ERR_STATE, "coarse layout: K must be 1, 8 or 27");
+  switch (h->N) {
+    case 2: launch_ca<TV, UNIQUE, 1, 1>(h, L, r, out, s); break;
+    case 3: launch_ca<TV, UNIQUE, 2, 2>(h, L, r, out, s); break;
+    case 4: launch_ca<TV, UNIQUE, 3, 3>(h, L, r, out, s); break;
+    case 5: launch_ca<TV, UNIQUE, 4, 3>(h, L, r, out, s); break;
+    case 6: launch_ca<TV, UNIQUE, 5, 3>(h, L, r, out, s); break;
+    case 7: launch_ca<TV, UNIQUE, 6, 3>(h, L, r, out, s); break;
+    case 8: launch_ca<TV, UNIQUE, 7, 3>(h, L, r, out, s); break;
+    default: fail(SEM_ERR_STATE, "coarse layout: N must be in 2..8");
   }
   SEM_HIP(hipGetLastError());
 }
@@ -560,7 +634,8 @@ static std::vector<double> small_inverse(std::vector<double> A, int n) {
 // matrices W = diag(w) and A1 = D^T W D, so that in the bubble basis
 // G_ref = (1/2)(Kb x Mb x Mb + Mb x Kb x Mb + Mb x Mb x Kb), Mb = B1^T W B1,
 // Kb = B1^T A1 B1 (interior rows and columns).
-static std::vector<double> bubble_basis(const sem_handle *h, int &K) {
+static std::vector<double> bubble_basis(const sem_handle *h, int &K,
+                                        CoarseTab *tab = nullptr) {
   const int N = h->N, n1 = h->n1, m = N - 1, q1 = std::min(2, N - 2) + 1;
   K = q1 * q1 * q1;
   std::vector<double> B1((size_t)m * q1), B((size_t)m * m * m * K);
@@ -602,6 +677,12 @@ static std::vector<double> bubble_basis(const sem_handle *h, int &K) {
   const std::vector<double> Mr = small_inverse(Gr, K);
   std::vector<double> sc(K);
   for (int k = 0; k < K; ++k) sc[k] = std::sqrt(Mr[(size_t)k * K + k]);
+  if (tab != nullptr) {
+    *tab = CoarseTab{};
+    for (int i = 0; i < m; ++i)
+      for (int a = 0; a < q1; ++a) tab->B1[i][a] = (float)B1[(size_t)i * q1 + a];
+    for (int k = 0; k < K; ++k) tab->sc[k] = (float)sc[k];
+  }
   for (int k = 0; k < m; ++k)
     for (int j = 0; j < m; ++j)
       for (int i = 0; i < m; ++i)
@@ -652,14 +733,13 @@ static void ensure_learn(sem_handle *h, const sem_mlp *net) {
     if (mode == LM_COARSE) {
       const int m = h->N - 1;
       L->ni = m * m * m;
-      std::vector<double> Bd = bubble_basis(h, L->K);
-      std::vector<float> Bf(Bd.begin(), Bd.end());
+      std::vector<double> Bd = bubble_basis(h, L->K, &L->tab);
       L->nf = 0;
       L->nt = 2 * L->K;
       L->Bd.alloc(Bd.size() * 8);
       SEM_HIP(hipMemcpy(L->Bd.p, Bd.data(), Bd.size() * 8, hipMemcpyHostToDevice));
-      L->Bf.alloc(Bf.size() * 4);
-      SEM_HIP(hipMemcpy(L->Bf.p, Bf.data(), Bf.size() * 4, hipMemcpyHostToDevice));
+      L->Sc.alloc((size_t)L->K * 4);
+      SEM_HIP(hipMemcpy(L->Sc.p, L->tab.sc, (size_t)L->K * 4, hipMemcpyHostToDevice));
       L->Ml.alloc((size_t)h->E * L->K * L->K * 4);
       L->cG.alloc((size_t)h->nG * 4);
       SEM_HIP(hipMemset(L->cG.p, 0, (size_t)h->nG * 4));  // faces stay zero
