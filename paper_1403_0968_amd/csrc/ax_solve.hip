@@ -9,9 +9,23 @@
 // nothing in FP64).  Workgroup shapes and load hints as the standalone
 // operator (OpShape).  A mesh with
 // a mass term passes H = alpha(X) B and the kernel adds H o u.
+// Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD
+// b % 8), each with its own L2.  With FP32 / BF16 storage the kernel numbers
+// its element blocks so that every XCD gets one contiguous run of them, and
+// elements that share nodes of the gathered vector (neighbours along x, y
+// and z) read the shared cache lines through the same L2: 102 -> 94 us at
+// 32^3, N = 7, FP32.  In FP64 the same order was slower (181 -> 186 us), so
+// FP64 keeps the plain order.
 #include "ax_tile.h"
 
 namespace sem {
+
+// element block of workgroup b of nb: XCD x = b % 8 takes the run
+// [x q + min(x, r), ...) of q or q + 1 blocks (q = nb / 8, r = nb % 8)
+__device__ inline int64_t xcd_run_block(unsigned b, unsigned nb) {
+  const unsigned q = nb / 8, r = nb % 8, x = b % 8, k = b / 8;
+  return (int64_t)x * q + (x < r ? x : r) + k;
+}
 
 template <int N1, class TV, class TG, class TC, bool MASS>
 __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
@@ -22,7 +36,10 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
   __shared__ TC smem[lds_words<N1>(S::EPB)];
   if (stop != nullptr && *stop != 0) return;  // uniform: the solve finished
   ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG>(
-      threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, &box, smem, H);
+      threadIdx.x,
+      (sizeof(TV) == 4 ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x) *
+          S::EPB,
+      E, D, G, u, w, &box, smem, H);
 }
 
 template <int N1, class TV, class TG, class TC>
