@@ -56,8 +56,9 @@ struct Learn {
   int mode = LM_NODAL, nf = 0, nt = 0;  // layout, feature nodes, target width
   // coarse layout: basis B [ni][K] (FP64; FP32 factors B1 and the column
   // scale sc for the apply kernel, sc also on the device), kappa features of every
-  // element (BF16 [E][ldx]), element operators M_e / (kappa_e h_e) (FP32
-  // [E][K][K]) for the network of version mver
+  // element (BF16 [E][ldx]), element operators M_e / (kappa_e h_e) (FP32,
+  // symmetric, packed lower triangles [E][K(K+1)/2], row a holding columns
+  // 0..a) for the network of version mver
   int K = 0, ni = 0;
   DevBuf Bd, Xk, Ml, cG, Sc;  // cG: correction on unique nodes (FP32)
   CoarseTab tab{};            // factors of B for the apply kernel (FP32)
@@ -345,18 +346,23 @@ __global__ void __launch_bounds__(64)
     xp[q] = q < 8 ? f32_to_bf16(kf[e * 8 + q]) : (uint16_t)0;
 }
 
-// element operators from the network outputs: M_e = invkh_e L L^T
+// element operators from the network outputs: M_e = invkh_e L L^T, packed
+// lower triangle (entry (a, b) and (b, a) are the same sum of the same
+// products, so one copy loses nothing)
 __global__ void __launch_bounds__(256)
     k_factor_to_M(int64_t E, int K, const float *__restrict__ O, int ldo,
                   const float *__restrict__ invkh, float *__restrict__ Ml) {
   const int64_t e = blockIdx.x;
   const float *o = O + e * ldo;
   const float sc = invkh[e];
-  for (int ab = threadIdx.x; ab < K * K; ab += 256) {
-    const int a = ab / K, b = ab % K, lo = a < b ? a : b;
+  const int kp = K * (K + 1) / 2;
+  for (int ab = threadIdx.x; ab < kp; ab += 256) {  // packed row a, column b <= a
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= ab) ++a;
+    const int b = ab - a * (a + 1) / 2;
     float v = 0.f;
-    for (int c = 0; c <= lo; ++c) v += o[a * (a + 1) / 2 + c] * o[b * (b + 1) / 2 + c];
-    Ml[e * K * K + ab] = sc * v;
+    for (int c = 0; c <= b; ++c) v += o[a * (a + 1) / 2 + c] * o[b * (b + 1) / 2 + c];
+    Ml[e * kp + ab] = sc * v;
   }
 }
 
@@ -373,8 +379,8 @@ __global__ void __launch_bounds__(256)
 // of 5.8 k multiply-adds each way).  One wave per element, persistent, no workgroup barrier: lane
 // p < M^2 owns the pencil (j, k) of M contiguous interior nodes, the
 // intermediate tensors pass through the wave's LDS region, and the loads of
-// the wave's next element (its pencil values and M_e) are issued before the
-// current element's contractions.  (The dense form, one wave per element
+// the wave's next element (its pencil values and M_e, a packed triangle of
+// K(K+1)/2 words) are issued before the current element's contractions.  (The dense form, one wave per element
 // with B in LDS: 43 us per apply at 24^3 elements, N = 7, bound by its LDS
 // and vector instruction count.)
 constexpr int CA_WAVES = 4;
@@ -393,7 +399,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
     k_coarse_apply(int64_t E, Box box, CoarseTab tb, const float *__restrict__ scg,
                    const TV *__restrict__ r, const float *__restrict__ Ml,
                    const float *__restrict__ damping, float *__restrict__ out) {
-  constexpr int K = Q * Q * Q, KK = K * K, MR = (KK + 63) / 64, P = M * M;
+  constexpr int K = Q * Q * Q, KK = K * (K + 1) / 2, MR = (KK + 63) / 64, P = M * M;
   constexpr int N1 = M + 2, N3 = N1 * N1 * N1, Q2 = Q * Q;
   constexpr int REG = Q * P + Q2 * M + 2 * 32 + KK;  // floats per wave
   __shared__ float ca_lds[CA_WAVES * REG];
@@ -402,7 +408,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
   float *s2 = s1 + Q * P;           // [M][Q2] (k, a + Q b)
   float *yv = s2 + Q2 * M;          // [K]
   float *bv = yv + 32;              // [K]
-  float *Ms = bv + 32;              // [K][K]
+  float *Ms = bv + 32;              // M_e, packed lower triangle
   const float damp = damping[0];
   const float sct = t < K ? scg[t] : 0.f;
   // first interior node of this lane's pencil (j, k) = (t % M, t / M)
@@ -474,7 +480,9 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
     if (t < K) {
       float acc = 0.f;
 #pragma unroll
-      for (int jj = 0; jj < K; ++jj) acc += Ms[jj * K + t] * (tb.sc[jj] * yv[jj]);
+      for (int jj = 0; jj < K; ++jj)  // M_e[jj][t] (M_e is symmetric)
+        acc += Ms[jj >= t ? jj * (jj + 1) / 2 + t : t * (t + 1) / 2 + jj] *
+               (tb.sc[jj] * yv[jj]);
       bv[t] = sct * (damp * acc);
     }
     wave_sync();
@@ -740,7 +748,7 @@ static void ensure_learn(sem_handle *h, const sem_mlp *net) {
       SEM_HIP(hipMemcpy(L->Bd.p, Bd.data(), Bd.size() * 8, hipMemcpyHostToDevice));
       L->Sc.alloc((size_t)L->K * 4);
       SEM_HIP(hipMemcpy(L->Sc.p, L->tab.sc, (size_t)L->K * 4, hipMemcpyHostToDevice));
-      L->Ml.alloc((size_t)h->E * L->K * L->K * 4);
+      L->Ml.alloc((size_t)h->E * (L->K * (L->K + 1) / 2) * 4);
       L->cG.alloc((size_t)h->nG * 4);
       SEM_HIP(hipMemset(L->cG.p, 0, (size_t)h->nG * 4));  // faces stay zero
     }
