@@ -12,9 +12,13 @@
 // output nodes (padded to 16), the K steps run over the nodes four at a time
 // (padded to 4) for Drw and Dsw together.  Lane l supplies the B operand for
 // (element l % 16, node 4 step + l / 16): it loads h, hu, hv there and forms
-// the fluxes itself, so the operand never passes through LDS, and reads its
-// A operand rows of Drw / Dsw (zero-padded, a few KB, cache-resident)
-// directly.  Output element v of lane l is row l / 16 + 4 v of the tile.
+// the fluxes itself, so the operand never passes through LDS.  The A
+// operands come from copies of Drw / Dsw that the host stores in the lane
+// order of the instruction (entry [(ks NT + t) 64 + l] = row 16 t + l % 16,
+// column 4 ks + l / 16, zero-padded): each wave's load of them is 512
+// contiguous bytes instead of 16 pieces of 32 bytes (N = 4..8: 44.3, 90.6,
+// 118.6, 166.9, 273.0 -> 42.0, 84.7, 108.5, 152.3, 225.2 us).  Output
+// element v of lane l is row l / 16 + 4 v of the tile.
 // The loads of K step ks + 1 (the lane's state, at a clamped node index, and
 // its operator entries) are issued before the products of step ks, so the
 // memory latency of one step hides behind the matrix instructions of the
@@ -41,7 +45,6 @@ template <int N> struct DgShape {
   static constexpr int NP = (N + 1) * (N + 2) / 2;
   static constexpr int NT = (NP + 15) / 16;  // output row tiles
   static constexpr int NK = (NP + 3) / 4;    // K steps of four nodes
-  static constexpr int LDA = 4 * NK;         // padded row length of Drw, Dsw
   static constexpr int UNROLL = N == 8 ? 2 : NK;
   static constexpr int WAVES_PER_EU = N == 7 ? 2 : 1;
 };
@@ -54,14 +57,15 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
                 const double *__restrict__ Drw, const double *__restrict__ Dsw,
                 double g) {
   using S = DgShape<N>;
-  constexpr int NP = S::NP, NT = S::NT, NK = S::NK, LDA = S::LDA;
+  constexpr int NP = S::NP, NT = S::NT, NK = S::NK;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
   const int64_t e = ((int64_t)blockIdx.x * DG_WAVES + wave) * 16 + col;
   const bool act = e < E;
   const double *Qe = Q + (act ? e : 0) * 3 * NP;
-  // this lane's A operand entries: row 16 t + col, column 4 ks + kq
-  const double *Ar = Drw + (col * LDA + kq), *As = Dsw + (col * LDA + kq);
+  // this lane's A operand entries (row 16 t + col, column 4 ks + kq) are
+  // entries (ks NT + t) 64 + lane of the lane-order copies
+  const double *Ar = Drw + lane, *As = Dsw + lane;
   double rx = 0.0, sx = 0.0, ry = 0.0, sy = 0.0;
   if (act) {
     rx = geo[4 * e];
@@ -83,8 +87,8 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     qn[2] = Qe[2 * NP + m];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      an[t] = Ar[16 * t * LDA + 4 * ks];
-      sn[t] = As[16 * t * LDA + 4 * ks];
+      an[t] = Ar[(ks * NT + t) * 64];
+      sn[t] = As[(ks * NT + t) * 64];
     }
   };
   fetch(0);
@@ -163,8 +167,6 @@ void launch_dg_volume(const dg_handle *h, const double *Q, double *rhs,
   SEM_HIP(hipGetLastError());
 }
 
-int dg_padded_row_length(int N) { return 4 * (((N + 1) * (N + 2) / 2 + 3) / 4); }
-int dg_padded_rows(int N) { return 16 * (((N + 1) * (N + 2) / 2 + 15) / 16); }
 
 // Host setup: reference operators, affine factors, node coordinates and the
 // bathymetry gradient (derivative of B's nodal interpolant), uploaded once.
@@ -208,13 +210,18 @@ void dg_device_setup(dg_handle *h, int64_t nv, const double *vx, const double *v
       }
     }
   }
-  const int lda = dg_padded_row_length(N), rows = dg_padded_rows(N);
-  std::vector<double> Ar(rows * lda, 0.0), As(rows * lda, 0.0);
-  for (int i = 0; i < Np; ++i)
-    for (int k = 0; k < Np; ++k) {
-      Ar[i * lda + k] = h->ref.Drw[i * Np + k];
-      As[i * lda + k] = h->ref.Dsw[i * Np + k];
-    }
+  // Drw, Dsw in the lane order of the matrix instruction, zero-padded
+  const int nt = (Np + 15) / 16, nk = (Np + 3) / 4;
+  std::vector<double> Ar((size_t)nk * nt * 64, 0.0), As((size_t)nk * nt * 64, 0.0);
+  for (int ks = 0; ks < nk; ++ks)
+    for (int t = 0; t < nt; ++t)
+      for (int l = 0; l < 64; ++l) {
+        const int i = 16 * t + l % 16, k = 4 * ks + l / 16;
+        if (i < Np && k < Np) {
+          Ar[((size_t)ks * nt + t) * 64 + l] = h->ref.Drw[i * Np + k];
+          As[((size_t)ks * nt + t) * 64 + l] = h->ref.Dsw[i * Np + k];
+        }
+      }
   auto up = [&](DevBuf &d, const std::vector<double> &v) {
     d.alloc(v.size() * sizeof(double));
     SEM_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(double),

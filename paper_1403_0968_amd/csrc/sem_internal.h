@@ -120,7 +120,8 @@ struct dg_handle {
   double g = 0.0;
   sem::DgRef ref;
   // per element: (rx, sx, ry, sy); bathymetry gradient [E][2][Np]; node
-  // coordinates [E][Np]; Drw, Dsw zero-padded to whole MFMA tiles
+  // coordinates [E][Np]; Drw, Dsw zero-padded to whole MFMA tiles and stored
+  // in the lane order of the volume kernel's matrix instruction
   sem::DevBuf geo, dB, X, Y, Drw, Dsw;
 };
 
