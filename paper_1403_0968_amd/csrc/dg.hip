@@ -79,6 +79,12 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
 #pragma unroll
     for (int t = 0; t < NT; ++t) acc[q][t] = dg_d4{0.0, 0.0, 0.0, 0.0};
   const double hg = 0.5 * g;
+  // with the K loop unrolled completely, the depth this lane loads at K step
+  // ks is the depth at its output row 16 t + kq + 4 v for ks = 4 t + v: kept
+  // for the source term instead of loaded again (N = 4..7: 42.1, 85.0,
+  // 109.2, 152.6 -> 39.4, 75.3, 105.5, 144.9 us)
+  constexpr bool KEEP_H = S::UNROLL == NK;
+  double hk[KEEP_H ? NK : 1];
   double qn[3], an[NT], sn[NT];  // operands of the next K step
   auto fetch = [&](int ks) {
     const int m = min(4 * ks + kq, NP - 1);
@@ -95,6 +101,7 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
 #pragma unroll S::UNROLL
   for (int ks = 0; ks < NK; ++ks) {
     const double h = qn[0], hu = qn[1], hv = qn[2];
+    if constexpr (KEEP_H) hk[ks] = h;
     double ar[NT], as[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -133,7 +140,12 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * t + kq + 4 * v;
       if (r < NP) {
-        const double gh = g * Qe[r];
+        double hr;
+        if constexpr (KEEP_H)
+          hr = hk[4 * t + v];
+        else
+          hr = Qe[r];
+        const double gh = g * hr;
         Re[r] = acc[0][t][v];
         Re[NP + r] = acc[1][t][v] - gh * Bx[r];
         Re[2 * NP + r] = acc[2][t][v] - gh * By[r];
