@@ -28,7 +28,8 @@
 // operands just before use (with separate Drw / Dsw accumulators from N = 7):
 // N = 2..8 20.2, 32.7, 55.4, 103, 129, 209, 313 us -> 17.9, 28.6, 44.1,
 // 91.4, 118, 167, 272 us.  The K loop is unrolled completely except at
-// N = 8, where that schedule is slower (373 us) than unrolling by two; at
+// N = 8, where that schedule is slower (373 us, and 294 us against 225 us
+// with the lane-order operator copies) than unrolling by two; at
 // N = 7 the kernel is held to two waves per SIMD's worth of registers.
 // Measured limits: a dependency-free loop of these instructions reaches
 // about 48 TFLOP/s on this chip (FP64 FMA on the vector units about 66).
@@ -141,8 +142,10 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
       const int r = 16 * t + kq + 4 * v;
       if (r < NP) {
         double hr;
+        // r < Np puts 4 t + v below NK; the clamp only keeps the index in
+        // range in code for rows r >= Np, which never runs
         if constexpr (KEEP_H)
-          hr = hk[4 * t + v];
+          hr = hk[4 * t + v < NK ? 4 * t + v : NK - 1];
         else
           hr = Qe[r];
         const double gh = g * hr;
