@@ -86,6 +86,9 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
   // 109.2, 152.6 -> 39.4, 75.3, 105.5, 144.9 us)
   constexpr bool KEEP_H = S::UNROLL == NK;
   double hk[KEEP_H ? NK : 1];
+  // otherwise (N = 8) each lane parks them in LDS slots of its own (read back
+  // by the same lane only, so no barrier): 225 -> 211 us
+  __shared__ double hs[KEEP_H ? 1 : DG_WAVES * NK * 64];
   double qn[3], an[NT], sn[NT];  // operands of the next K step
   auto fetch = [&](int ks) {
     const int m = min(4 * ks + kq, NP - 1);
@@ -102,7 +105,10 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
 #pragma unroll S::UNROLL
   for (int ks = 0; ks < NK; ++ks) {
     const double h = qn[0], hu = qn[1], hv = qn[2];
-    if constexpr (KEEP_H) hk[ks] = h;
+    if constexpr (KEEP_H)
+      hk[ks] = h;
+    else
+      hs[(wave * NK + ks) * 64 + lane] = h;
     double ar[NT], as[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -144,10 +150,11 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
         double hr;
         // r < Np puts 4 t + v below NK; the clamp only keeps the index in
         // range in code for rows r >= Np, which never runs
+        const int KS = 4 * t + v < NK ? 4 * t + v : NK - 1;
         if constexpr (KEEP_H)
-          hr = hk[4 * t + v < NK ? 4 * t + v : NK - 1];
+          hr = hk[KS];
         else
-          hr = Qe[r];
+          hr = hs[(wave * NK + KS) * 64 + lane];
         const double gh = g * hr;
         Re[r] = acc[0][t][v];
         Re[NP + r] = acc[1][t][v] - gh * Bx[r];
