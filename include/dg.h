@@ -38,10 +38,12 @@ extern "C" {
 
 typedef struct dg_handle dg_handle; /* opaque, owned by the library */
 
-/* Reference nodes (r[Np], s[Np], HOST arrays) of order N in 1..8. */
+/* Reference nodes (r[Np], s[Np], HOST arrays) of order N in 1..8: the
+ * nodal basis points of section 4.3.2 (warp-and-blend construction).
+ * SEM_ERR_ARG for another N or a NULL array. */
 sem_status dg_reference_nodes(int32_t N, double *r, double *s);
 
-/* Build a handle from a triangle mesh: vx, vy (HOST, n_vertices each), etov
+/* Build a handle for the volume term of section 4.3.2 from a triangle mesh: vx, vy (HOST, n_vertices each), etov
  * (HOST int32 [n_elements][3], counterclockwise, indices < n_vertices),
  * bathymetry (HOST [n_elements][Np] nodal values of B, or NULL for a flat
  * bottom) and the gravity g.  Computes the reference operators, the affine
@@ -53,11 +55,15 @@ sem_status dg_setup(int32_t N, int64_t n_vertices, const double *vx,
                     const double *vy, int64_t n_elements, const int32_t *etov,
                     const double *bathymetry, double g, void *stream,
                     dg_handle **out);
+/* Release a handle of the section 4.3.2 volume term and its device
+ * buffers.  NULL is accepted. */
 sem_status dg_destroy(dg_handle *h);
+/* Nodes per element Np = (N+1)(N+2)/2 and the element count of the
+ * section 4.3.2 discretisation (HOST outputs, either may be NULL). */
 sem_status dg_query(const dg_handle *h, int32_t *n_nodes, int64_t *n_elements);
 
-/* Copy an internal array into caller DEVICE memory (SEM_ERR_ARG when
- * dst_bytes is too small):
+/* Copy an internal array of the section 4.3.2 discretisation into caller
+ * DEVICE memory, for checking (SEM_ERR_ARG when dst_bytes is too small):
  *   DG_ARR_X, DG_ARR_Y  double [E][Np]   physical node coordinates
  *   DG_ARR_GEO          double [E][4]    (rx, sx, ry, sy)
  *   DG_ARR_DB           double [E][2][Np] (B_x block, B_y block)
@@ -69,7 +75,8 @@ typedef enum {
 sem_status dg_export(const dg_handle *h, int32_t which, void *dst,
                      int64_t dst_bytes, void *stream);
 
-/* Volume term rhs = Dxw F + Dyw G + S for the state Q (DEVICE, [E][3][Np],
+/* Volume term of section 4.3.2 (the kernel section 4.3.3 profiles),
+ * rhs = Dxw F + Dyw G + S, for the state Q (DEVICE, [E][3][Np],
  * h > 0) into rhs (DEVICE, [E][3][Np], must not overlap Q).  FP64 on the
  * matrix cores; asynchronous on `stream`. */
 sem_status dg_volume(dg_handle *h, const double *Q, double *rhs, void *stream);

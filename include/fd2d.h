@@ -38,7 +38,8 @@ extern "C" {
  * (stencil sizes 3..15, the range of section 4.1.3); SEM_ERR_ARG otherwise. */
 sem_status fd2d_weights(int32_t r, double *w);
 
-/* One time step: u_next from u_cur (time level n) and u_prev (level n-1),
+/* One time step of the section 4.1.2 scheme (the paper's kernel fd2d):
+ * u_next from u_cur (time level n) and u_prev (level n-1),
  * each nx * ny doubles.  u_next may be the same buffer as u_prev (each node
  * of u_prev is read only to produce the same node of u_next) but must not
  * overlap u_cur.  nx, ny >= 1, r in 1..7, dx > 0, dt and dx finite;
@@ -47,7 +48,8 @@ sem_status fd2d_step(const double *u_cur, const double *u_prev, double *u_next,
                      int64_t nx, int64_t ny, int32_t r, double dt, double dx,
                      void *stream);
 
-/* nsteps time steps on two buffers, in place: on entry u_a holds level n-1
+/* nsteps time steps of the section 4.1.2 scheme on two buffers, in place
+ * (the paper's driver rotates three buffers, section 4.1.2): on entry u_a holds level n-1
  * and u_b level n; each step overwrites the older level.  On return, after
  * an even number of steps u_a holds level n+nsteps-1 and u_b level n+nsteps;
  * after an odd number the two are swapped (u_a holds the newest).  The same

@@ -159,14 +159,22 @@ typedef struct {
  * and the Jacobi diagonal (stiffness plus H).  Synchronises `stream`
  * before returning.  On failure *out is NULL. */
 sem_status sem_setup(const sem_mesh_desc *desc, void *stream, sem_handle **out);
+/* Release a handle and every device buffer it owns (the set-up / allocate /
+ * build / call / release host pattern of section 4.1.2's driver).  Batches
+ * and networks that reference the handle must be destroyed or detached
+ * first.  NULL is accepted. */
 sem_status sem_destroy(sem_handle *h);
 
-/* Sizes of the discretisation. */
+/* Sizes of the discretisation of section 4.2.1: elements E, local nodes
+ * E (N+1)^3 (the E-vector length) and unique global nodes of the distinct
+ * global-local numbering.  Outputs are HOST pointers, any may be NULL. */
 sem_status sem_query(const sem_handle *h, int64_t *n_elements,
                      int64_t *n_local, int64_t *n_global);
 
 /* Copy an internal array into caller device memory `dst` of `dst_bytes`
- * bytes (SEM_ERR_ARG when too small).  Layouts:
+ * bytes (SEM_ERR_ARG when too small): the maps of the distinct global-local
+ * numbering and the per-node factors of section 4.2.1, for checking.
+ * Asynchronous on `stream`.  Layouts:
  *   SEM_ARR_L2G     int32 [n_local]   global id of each local node
  *   SEM_ARR_PERM    int32 [n_local]   local ids sorted by (global id, local id)
  *   SEM_ARR_OFFSETS int32 [n_global+1] start of each global id in PERM
@@ -205,21 +213,36 @@ sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
 sem_status sem_ax(sem_handle *h, int32_t p, const void *u_L, void *w_L,
                   void *stream);
 
-/* Direct stiffness summation in place: v <- mask o Q Q^T v, where every copy
- * of a global node receives the sum of all copies taken in ascending local
- * index starting from +0.0 (no fused multiply-add), then Dirichlet copies
- * are set to zero.  p = SEM_FP64 or SEM_FP32. */
+/* Direct stiffness summation in place: v <- mask o Q Q^T v (section 4.2.1:
+ * the assembled operator follows from the element operators through the
+ * distinct global-local node numbering the paper takes from Fischer 1991).
+ * Every copy of a global node receives the sum of all copies taken in
+ * ascending local index starting from +0.0 (no fused multiply-add; a node
+ * with one copy receives +0.0 + v), then Dirichlet copies are set to zero.
+ * Atomic-free: a precomputed list sorted by (global id, local id) gives each
+ * shared node's copies.  p = SEM_FP64 (double) or SEM_FP32 (float); v_L is
+ * a caller-owned device E-vector of n_local values, updated in place.
+ * SEM_ERR_ARG for another precision or a null vector. */
 sem_status sem_gs(sem_handle *h, int32_t p, void *v_L, void *stream);
 
-/* Load vector b_L = mask o Q Q^T (B o f(X)) (weak-form right-hand side of
- * semOperator with the lumped mass), FP64 E-vector. */
+/* Load vector b_L = mask o Q Q^T (B o f(X)): the weak-form right-hand side
+ * <f, v> of equation semOperator (section 4.2.1) with the lumped GLL mass
+ * B = w_i w_j w_k J, evaluated at the physical node positions.  b_L is a
+ * caller-owned device FP64 E-vector of n_local values; src and its arrays
+ * are HOST pointers.  SEM_ERR_ARG for an unknown source kind or more than
+ * 64 Fourier modes. */
 sem_status sem_rhs(sem_handle *h, const sem_source *src, double *b_L,
                    void *stream);
 
-/* z_L = P r_L on continuous E-vectors.  SEM_PC_JACOBI: z = dinv o r with the
- * inverse of the assembled diagonal (0 on Dirichlet nodes); SEM_PC_NONE:
- * z = mask o r; SEM_PC_LEARNED (FP64 only, network attached): z = dinv o r +
- * the averaged learned correction of r.  p = SEM_FP64 or SEM_FP32. */
+/* z_L = P r_L on continuous E-vectors: the preconditioner of the PCG solve
+ * (section 4.2.2 solves the system by preconditioned conjugate gradients and
+ * leaves the choice of preconditioner open; these are this library's).
+ * SEM_PC_JACOBI: z = dinv o r with the inverse of the assembled diagonal (0
+ * on Dirichlet nodes); SEM_PC_NONE: z = mask o r; SEM_PC_LEARNED (FP64 only,
+ * network attached): z = dinv o r + the learned coarse correction of r.
+ * p = SEM_FP64 (double) or SEM_FP32 (float); r_L, z_L caller-owned device
+ * E-vectors of n_local values that must not overlap.  SEM_ERR_ARG for another
+ * precision, SEM_ERR_STATE for SEM_PC_LEARNED without a network. */
 sem_status sem_precond_apply(sem_handle *h, int32_t pc, int32_t p,
                              const void *r_L, void *z_L, void *stream);
 
@@ -232,8 +255,8 @@ sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *opts,
                          const double *b_L, double *x_L,
                          sem_solve_stats *stats, void *stream);
 
-/* Batches of independent solves (uneven sizes, orders N in {3, 5, 7} may
- * be mixed, or any single N).  A batch references existing handles (which
+/* Batches of independent solves of the system of section 4.2.2 (uneven
+ * sizes, orders N in {3, 5, 7} may be mixed, or any single N).  A batch references existing handles (which
  * must outlive it) and owns its work lists, per-solve device scalars and
  * captured graphs.  One CG iteration of the whole batch is six launches of
  * persistent kernels over (solve, element tile) and (solve, node chunk)
@@ -244,17 +267,25 @@ sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *opts,
  * (alpha = 0): SEM_ERR_ARG otherwise. */
 sem_status sem_batch_create(sem_handle *const *handles, int32_t n,
                             sem_batch **out);
+/* Release a batch of section 4.2.2 solves (its work lists, device scalars
+ * and graphs; the handles stay).  NULL is accepted. */
 sem_status sem_batch_destroy(sem_batch *b);
-/* Autotuner: times the batched operator kernel of precision p for every
- * workgroup size (64, 128, 256 threads) and persistent grid (1 tile per
- * workgroup, or 4, 8, 16, 32 workgroups per compute unit) and keeps the
- * fastest for later solves.  With the environment variable
- * SEM_AUTOTUNE_CACHE naming a JSON file, results are read from / added to
- * it, keyed by GPU architecture, order set, precision and size bucket.
- * Outputs may be NULL; *us is -1 when the value came from the cache. */
+/* Autotuner of the batched operator of section 4.2.1 (the paper's own
+ * measurements compare kernel tuning choices per platform, section 4.2.3):
+ * times the batched operator kernel of precision p for every
+ * workgroup size (64, 128, 256 threads) that holds the (N+1)^2 columns of
+ * an element of the batch's largest order (one thread per column: N = 8
+ * needs 128 or 256) and every persistent grid (1 tile per workgroup, or 4,
+ * 8, 16, 32 workgroups per compute unit) and keeps the fastest for later
+ * solves.  With the environment variable SEM_AUTOTUNE_CACHE naming a JSON
+ * file, results are read from / added to it, keyed by GPU architecture,
+ * order set, precision and size bucket; a cached block size too small for
+ * the batch is ignored and tuned again.  Outputs may be NULL; *us is -1
+ * when the value came from the cache. */
 sem_status sem_batch_tune(sem_batch *b, int32_t p, int32_t *block_size,
                           int32_t *grid_mult, double *us);
-/* Solve every system of the batch: b_L[q], x_L[q] are the device E-vectors
+/* Solve every system of the batch by PCG (section 4.2.2): b_L[q], x_L[q]
+ * (HOST arrays of n device pointers) are the device E-vectors
  * of solve q (as in sem_pcg_solve); stats[q] receives its statistics
  * (seconds = wall time of the whole batch).  Synchronises `stream`.
  * Returns SEM_OK when all converged, else the first failing status. */
@@ -263,92 +294,123 @@ sem_status sem_batch_pcg_solve(sem_batch *b, const sem_solve_opts *opts,
                                sem_solve_stats *stats, void *stream);
 
 /* ------------------------------------------------------------------------
- * Learned per-element coarse correction (SEM_PC_LEARNED).  The paper leaves
- * the PCG preconditioner open (section 4.2.2); this one adds to Jacobi a
- * correction predicted element by element by a three-layer perceptron
+ * Learned per-element coarse correction (SEM_PC_LEARNED).  Section 4.2.2
+ * solves the system by PCG and leaves the preconditioner open; this one adds
+ * to Jacobi a coarse correction per element,
+ *   c = damping B (M_e / (kappa_e h_e)) B^T r_I,
+ * on the element's interior nodes (zero on its faces): B holds the K
+ * interior "bubble" modes of the element, tensor products of
+ * (1 - x^2) P_a(x), a <= p = min(2, N-2), K = (p+1)^3, each scaled so that
+ * the unit reference element's coarse inverse has unit diagonal; r_I is the
+ * residual at the interior nodes; kappa_e is the mean of kappa at the 8
+ * element vertices and h_e the element size.  M_e = L L^T, where the packed
+ * lower-triangular factor L (K(K+1)/2 values, row-major) is the output of a
+ * three-layer perceptron
  *   z1 = x W1^T + b1, h1 = relu(z1), z2 = h1 W2^T + b2, h2 = relu(z2),
  *   o = h2 W3^T + b3,
- * hidden width 128, BF16 weights (FP32 master copy), FP32 accumulation on
- * MFMA.  Element features x: the element's residual values divided by their
- * 2-norm s_e, then log kappa at the 8 element vertices minus their mean, then
- * zero padding to a multiple of 16.  Output: either the (N+1)^3 nodal values
- * of the element or 8 trilinear vertex values prolonged to its GLL nodes;
- * scaled by damping * s_e / (kappa_e h_e) (kappa_e the vertex mean, h_e the
- * element size) and averaged over the copies of every node.  The damping
- * and a Jacobi reference convergence rate are set by sem_learn_train and
- * kept in checkpoints.  Fallback to Jacobi-PCG (stats.fell_back = 1) happens
- * on NaN / breakdown, on stagnation (the smallest residual so far drops
- * less than 2x over 400 iterations), when the learned solve's smallest
- * residual shows less than 30% of the average Jacobi rate after 300 or
- * more iterations, when a refinement step fails to halve
- * the FP64 true residual (the step is undone), or when the damping is 0.  Parameters are one FP32 vector: W1 [128][n_in], b1, W2
- * [128][128], b2, W3 [n_out][128], b3 (row-major [out][in]).
+ * hidden width 128, on the element's features x: log kappa at its 8
+ * vertices minus their mean (n_in = 8, padded with zeros to 16 columns).
+ * The correction is symmetric positive semi-definite whatever the network
+ * outputs.  Its target is the exact element coarse inverse
+ * M_e* = kappa_e h_e (B^T A_II,e B)^{-1} (sem_learn_coarse_exact), which can
+ * also be attached directly (sem_learn_attach_exact).  It is used inside
+ * flexible CG (Notay 2000) with z = dinv o r + c.  Fallback to Jacobi-PCG
+ * (stats.fell_back = 1) happens on NaN / breakdown, on stagnation (the
+ * smallest residual so far drops less than 2x over 400 iterations), when
+ * the learned solve's smallest residual shows less than 30% of the average
+ * Jacobi rate after 300 or more iterations, when a refinement step fails to
+ * halve the FP64 true residual (the step is undone), or when the damping is
+ * 0.  Parameters are one FP32 vector: W1 [128][n_in], b1, W2 [128][128],
+ * b2, W3 [n_out][128], b3 (row-major [out][in]).
  * ------------------------------------------------------------------------ */
-/* He-initialised network (hidden width must be 128, n_out <= 1024). */
+/* He-initialised network of the section 4.2.2 correction (hidden width must
+ * be 128, 1 <= n_in <= 4096, 1 <= n_out <= 1024; SEM_ERR_ARG otherwise),
+ * BF16 precision (below).  *out receives a network the caller releases with
+ * sem_mlp_destroy. */
 sem_status sem_mlp_create(int32_t n_in, int32_t n_hidden, int32_t n_out,
                           uint64_t seed, sem_mlp **out);
+/* Release a network of the section 4.2.2 correction (detach it from every
+ * handle first).  NULL is accepted. */
 sem_status sem_mlp_destroy(sem_mlp *net);
+/* Shapes of a section 4.2.2 correction network: inputs, hidden width,
+ * outputs, inputs padded to a multiple of 16 (the row stride of X), the
+ * parameter count and the number of Adam steps taken.  HOST outputs, any
+ * may be NULL. */
 sem_status sem_mlp_info(const sem_mlp *net, int32_t *n_in, int32_t *n_hidden,
                         int32_t *n_out, int32_t *n_in_padded,
                         int64_t *n_params, int64_t *adam_steps);
-/* FP32 master parameters, HOST arrays of n_params floats; set resets Adam. */
+/* FP32 master parameters of the section 4.2.2 correction network, HOST
+ * arrays of n_params floats (SEM_ERR_ARG for another n); set resets Adam. */
 sem_status sem_mlp_get_params(const sem_mlp *net, float *params, int64_t n);
+/* See sem_mlp_get_params (section 4.2.2 correction network). */
 sem_status sem_mlp_set_params(sem_mlp *net, const float *params, int64_t n);
-/* Forward pass of B samples: X device BF16 [B][ldx] (ldx >= n_in_padded, a
- * multiple of 16; padding columns finite), Y device FP32 [B][n_out]. */
+/* Arithmetic of the section 4.2.2 correction network.  SEM_BF16 (default):
+ * BF16 copies of the weights, BF16 hidden activations as layer inputs,
+ * forward layers on the matrix cores with FP32 accumulation, backward in
+ * FP32 on the same BF16 values.  SEM_FP32: FP32 weights and hidden
+ * activations, forward and backward in FP32 on the vector units (for
+ * element-by-element checks).  The input x is BF16 in both.  Any other p:
+ * SEM_ERR_ARG.  Synchronises the device. */
+sem_status sem_mlp_set_precision(sem_mlp *net, int32_t p);
+/* The precision set by sem_mlp_set_precision for a section 4.2.2
+ * correction network (HOST output). */
+sem_status sem_mlp_get_precision(const sem_mlp *net, int32_t *p);
+/* Forward pass of the section 4.2.2 correction network on B samples:
+ * X device BF16 [B][ldx] (ldx >= n_in_padded, a multiple of 16; padding
+ * columns finite), Y device FP32 [B][n_out]. */
 sem_status sem_mlp_forward(sem_mlp *net, const uint16_t *X, int32_t ldx,
                            int32_t B, float *Y, void *stream);
-/* Mean squared error between P o and targets T: P is the trilinear
- * prolongation to the GLL nodes of order N when n_in = (N+1)^3 + 8 and
- * n_out = 8 (T device FP32 [B][(N+1)^3]), else the identity (T device FP32
- * [B][n_out]: nodal and interior layouts);
- * and its gradient: grad device FP32 [n_params] (may be NULL: the network's
- * own gradient buffer is used by sem_mlp_adam with grad NULL).  *loss is
- * written on the host (synchronises the stream). */
-sem_status sem_mlp_loss_grad(sem_mlp *net, const uint16_t *X, int32_t ldx,
-                             const float *T, int32_t B, int32_t N, float *grad,
-                             double *loss, void *stream);
-/* Loss and gradient of the coarse layout's factor output (n_out = K(K+1)/2,
+/* Loss and gradient of the section 4.2.2 coarse factor (n_out = K(K+1)/2,
  * K in {1, 8, 27}): per sample, T (device FP32 [B][2K]) holds y and alpha*;
  * the network output is the row-major packed lower triangle of L and the
  * loss is the mean over samples and components of (L L^T y - alpha*)^2.
- * grad and loss as for sem_mlp_loss_grad. */
+ * grad: device FP32 [n_params] in parameter order (may be NULL: the
+ * network's own gradient buffer is used by sem_mlp_adam with grad NULL).
+ * *loss is written on the host (synchronises the stream). */
 sem_status sem_mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X,
                                     int32_t ldx, const float *T, int32_t K,
                                     int32_t B, float *grad, double *loss,
                                     void *stream);
-/* One Adam step (Kingma & Ba 2015) on the master parameters with device
- * gradient grad (NULL: the last sem_mlp_loss_grad gradient). */
+/* One Adam step (Kingma & Ba 2015) on the master parameters of a
+ * section 4.2.2 correction network with device gradient grad (NULL: the last
+ * sem_mlp_loss_grad_factor gradient); lr > 0, betas in [0, 1), eps > 0. */
 sem_status sem_mlp_adam(sem_mlp *net, const float *grad, double lr,
                         double beta1, double beta2, double eps, void *stream);
-/* Correction scale and the Jacobi reference rate (log10 residual drop per
- * Jacobi-PCG iteration, negative; 0 disables the progress judge). */
+/* Scale of the section 4.2.2 correction (damping >= 0) and the Jacobi
+ * reference rate of the progress judge (log10 residual drop per Jacobi-PCG
+ * iteration, <= 0; 0 disables the judge). */
 sem_status sem_mlp_set_damping(sem_mlp *net, double damping, double jacobi_rate);
+/* See sem_mlp_set_damping (section 4.2.2 correction). */
 sem_status sem_mlp_get_damping(const sem_mlp *net, double *damping,
                                double *jacobi_rate);
-/* Checkpoint: magic, version, shapes, Adam step, FP32 parameters and Adam
- * moments, CRC-32.  Load rejects truncated or altered files (SEM_ERR_ARG). */
+/* Checkpoint of a section 4.2.2 correction network: magic, version,
+ * shapes, Adam step, damping, FP32 parameters and Adam moments, CRC-32
+ * (the precision setting is not stored).  Load rejects truncated or
+ * altered files (SEM_ERR_ARG). */
 sem_status sem_mlp_save(const sem_mlp *net, const char *path);
+/* See sem_mlp_save (section 4.2.2 correction network). */
 sem_status sem_mlp_load(const char *path, sem_mlp **out);
 
-/* Attach a network (NULL detaches) to a handle for SEM_PC_LEARNED; the
- * network must outlive the attachment.  Its shape selects the layout:
- * n_in = (N+1)^3 + 8 with n_out = 8 (Q1) or (N+1)^3 (nodal);
- * n_in = (N-1)^3 + 8 with n_out = (N-1)^3 (interior, N >= 2);
- * n_in = 8 with n_out = K(K+1)/2, K = (min(2, N-2) + 1)^3 (coarse, N >= 2):
- * the network maps the element's 8 log-kappa vertex deviations to a factor
- * L of its coarse operator M_e = L L^T / (kappa_e h_e) in the interior
- * bubble basis B (tensor products of (1 - x^2) P_a(x), a <= min(2, N-2), at
- * the interior nodes), and the correction is damping B M_e B^T r_I on the
- * interior nodes (symmetric positive semi-definite).  The coarse operators
- * are computed from the network when it is attached and again before a
- * solve when its parameters have changed.  The coarse targets are those of
- * the stiffness operator: meshes with a mass term (alpha != 0) are refused
- * with SEM_ERR_STATE, here and in sem_learn_train. */
+/* Attach a network (NULL detaches) to a handle for SEM_PC_LEARNED, the
+ * section 4.2.2 correction; the network must outlive the attachment.  It
+ * needs n_in = 8 and n_out = K(K+1)/2 with K = (min(2, N-2)+1)^3 and
+ * N >= 2 (SEM_ERR_ARG otherwise).  The element operators M_e are computed
+ * from the network when it is attached and again before a solve when its
+ * parameters or precision have changed.  The targets are those of the
+ * stiffness operator: meshes with a mass term (alpha != 0) are refused with
+ * SEM_ERR_STATE, here and in sem_learn_train. */
 sem_status sem_learn_attach(sem_handle *h, sem_mlp *net);
 
+/* Attach the exact element coarse inverses M_e* (no network) for
+ * SEM_PC_LEARNED, with the given damping (finite, >= 0) and no progress
+ * judge: the section 4.2.2 correction that the network is trained to
+ * imitate, for measuring what the network itself gains or loses.  Replaces
+ * an attached network; sem_learn_attach (with a network or NULL) replaces
+ * it.  N >= 2, no mass term. */
+sem_status sem_learn_attach_exact(sem_handle *h, double damping);
+
 typedef struct {
-  int32_t n_pairs;          /* element residual/error pairs to sample */
+  int32_t n_pairs;          /* element residual pairs to sample */
   int32_t snapshot_every;   /* solver iterations between snapshots */
   int32_t max_snapshots;    /* per right-hand side */
   int32_t epochs;
@@ -361,64 +423,45 @@ typedef struct {
 
 typedef struct {
   int32_t pairs, epochs, snapshots;
-  int32_t local_iters_max;        /* interior layout: most element-interior CG
-                                     iterations of a target (0 otherwise) */
+  int32_t reserved;
   double first_loss, last_loss;   /* mean loss of the first / last epoch */
   double data_seconds, train_seconds, validate_seconds;
   double damping;                 /* chosen correction scale (0: disabled) */
   double jacobi_rate;             /* Jacobi-PCG log10 residual drop / iteration */
   int32_t val_iters_jacobi, val_iters_learned;  /* validation solve to 1e-6 */
   int32_t val_iters[4];   /* learned iterations for the damping candidates
-                             1, 0.75, 0.5, 0.25 (interior, coarse) or 0.2,
-                             0.15, 0.1, 0.05 (Q1, nodal); -1: not converged
-                             or fell back */
+                             1, 0.75, 0.5, 0.25; -1: not converged or fell
+                             back */
 } sem_train_report;
 
-/* Generate training pairs with the FP64 solver and train the network on the
- * GPU.  For every right-hand side b_L[q] (device FP64 E-vectors) a FP64
- * Jacobi-PCG solve from x = 0 records snapshots x_k, r_k; residuals
- * restricted to random elements give the pairs.  Targets: Q1 and nodal
- * layouts, the element error (x* - x_k)_e kappa_e h_e / s_e of the
- * converged solve; interior layout, the element-interior solve of
- * sem_learn_interior_pairs; coarse layout, y = B^T r_I / ||B^T r_I|| (for
- * half the pairs, chosen at random, a random unit direction instead, so that
- * every direction of the operator is trained) and alpha* = M_e y with the
- * exact M_e of sem_learn_coarse_exact; a coarse-layout network that has never
- * taken an Adam step first starts from the identity factor (output bias =
- * packed identity, output weights scaled by 0.01).  Training: epochs of
- * shuffled minibatches of forward, loss, backward and Adam, all on the GPU.
- * Then the damping is validated on the last right-hand side (see above). */
+/* Generate training pairs with the FP64 solver and train the section 4.2.2
+ * correction network on the GPU.  For every right-hand side b_L[q] (device
+ * FP64 E-vectors) a FP64 Jacobi-PCG solve from x = 0 records snapshots of
+ * the residual; residuals restricted to random elements give the pairs:
+ * y = B^T r_I / ||B^T r_I|| (for half the pairs, chosen at random, a random
+ * unit direction instead, so that every direction of the operator is
+ * trained) and alpha* = M_e* y with the exact M_e* of
+ * sem_learn_coarse_exact.  A network that has never taken an Adam step
+ * first starts from the identity factor (output bias = packed identity,
+ * output weights scaled by 0.01).  Training: epochs of shuffled minibatches
+ * of forward, loss, backward and Adam, all on the GPU.  Then the damping is
+ * chosen from {1, 0.75, 0.5, 0.25} on the last right-hand side (solves to
+ * 1e-6 against Jacobi-PCG; 0 when none helps). */
 sem_status sem_learn_train(sem_handle *h, sem_mlp *net, const double *const *b_L,
                            int32_t n_rhs, const sem_train_opts *opts,
                            sem_train_report *report, void *stream);
 
-/* Exact normalised coarse inverses of the coarse layout (the definition of
- * its training targets, exposed for checking): M[e] (device FP64
- * [E][K][K]) = kappa_e h_e (B^T A_II,e B)^{-1}, computed on the GPU by
+/* Exact normalised coarse inverses of the section 4.2.2 correction (the
+ * definition of its training targets, exposed for checking): M[e] (device
+ * FP64 [E][K][K]) = kappa_e h_e (B^T A_II,e B)^{-1}, computed on the GPU by
  * applying the element operator to the K bubble columns and inverting the
  * K x K Galerkin matrix by Cholesky (NaN if it is not positive definite).
  * *K receives K.  Synchronises the stream.  N in 2..8. */
 sem_status sem_learn_coarse_exact(sem_handle *h, double *M, int32_t *K,
                                   void *stream);
 
-/* Training pairs of the interior layout for one residual (the definition
- * of the training targets, exposed for checking): for each of the n
- * elements elems[q] (device int32, each in [0, E)), features X[q] (device
- * BF16 [n][ldx], ldx a multiple of 16 and >= (N-1)^3 + 8: r at the
- * element-interior nodes 1 <= i, j, k <= N-1 in lexicographic order over
- * their 2-norm s, then the 8 log-kappa vertex deviations) and targets T[q]
- * (device FP32 [n][(N-1)^3]: (d - dinv r_I) kappa_e h_e / s, where d solves
- * the element's interior problem A_II d = r_I, the element stiffness with
- * zero values on the element's faces; Jacobi-CG in FP64 on the GPU to
- * ||r_I - A_II d|| <= rtol ||r_I||, at most 2000 iterations).  r_L: device
- * FP64 continuous E-vector.  iters (device int32 [n], may be NULL): CG
- * iterations per element.  Synchronises the stream.  N >= 2. */
-sem_status sem_learn_interior_pairs(sem_handle *h, const double *r_L,
-                                    const int32_t *elems, int32_t n,
-                                    uint16_t *X, int32_t ldx, float *T,
-                                    double rtol, int32_t *iters, void *stream);
-
-/* Text of the calling thread's last error ("" if none). */
+/* Text of the calling thread's last error ("" if none): the error path of
+ * the set-up / build / call host pattern of section 4.1.2's driver. */
 const char *sem_last_error(void);
 
 #ifdef __cplusplus

@@ -2,55 +2,38 @@
 INFRASTRUCTURE ONLY; only tests, the smoke check and the benchmark's CPU
 baseline may import it).
 
-The paper leaves the PCG preconditioner open (section 4.2.2).  The learned
-correction is a per-element three-layer perceptron:
+The paper solves the system by PCG and leaves the preconditioner open
+(section 4.2.2).  The learned correction adds to Jacobi an element coarse
+correction whose operator a three-layer perceptron predicts:
 
     z1 = x W1^T + b1,  h1 = relu(z1)
     z2 = h1 W2^T + b2, h2 = relu(z2)
-    o  = h2 W3^T + b3                        (8 coarse vertex values)
+    o  = h2 W3^T + b3
 
-whose output is prolonged to the element's GLL nodes by the trilinear (Q1)
-basis, P[node(i,j,k)][v(a,b,c)] = phi_a(xi_i) phi_b(xi_j) phi_c(xi_k) with
-phi_0 = (1 - xi)/2, phi_1 = (1 + xi)/2 and v = a + 2b + 4c.  Training
-minimises the mean squared error between P o and the normalised element
-error with Adam (Kingma & Ba 2015).  Every function here is plain NumPy in
+trained with Adam (Kingma & Ba 2015).  Every function here is plain NumPy in
 FP64; parameters are one flat vector in the order W1, b1, W2, b2, W3, b3
 (row-major weights of shape [out][in]).
 
-Features of an element e (unique-node residual r, map l2g, coefficient
-kappa): r_e = r[l2g of e's nodes], s_e = ||r_e||_2;
-x = [r_e / s_e, log kappa at the 8 element vertices minus their mean, 0 pad];
-the correction is c_e = s_e / (kappa_mean_e h_e) * P o, summed over the
-copies of each node and divided by its multiplicity.
-
-Interior layout (the element-interior solve as target): the network sees
-only the residual at the element-interior nodes (1 <= i, j, k <= N-1),
-x = [r_I / s, log kappa vertex deviations], s = ||r_I||_2, and predicts the
-(N-1)^3 values t = (d - dinv_I r_I) kappa_mean h / s, where d solves
-A_II d = r_I with A_II the element stiffness restricted to its interior
-nodes (zero values on the element's faces) and dinv the assembled Jacobi
-inverse.  The preconditioner z = dinv r + c then reproduces the
-element-interior block solve where the network is exact.  Interior nodes
-belong to one element only, so no averaging is involved.
-
-Coarse layout (a learned element coarse operator): with the interior
-"bubble" basis b_a(xi) = (1 - xi^2) P_a(xi), a = 0..p (P_a Legendre,
-p = min(2, N - 2)), B[(i,j,k)][(a,b,c)] = b_a(xi_i) b_b(xi_j) b_c(xi_k) on
-the interior nodes (K = (p+1)^3 columns, each scaled by the square root of
-the matching diagonal entry of the unit reference element's coarse inverse
-so that every mode is O(1)), the element's Galerkin coarse
-matrix is G_e = B^T A_II B and its exact coarse correction
-c_I = B G_e^{-1} B^T r_I.  The network sees only the 8 log-kappa vertex
-deviations and outputs a lower-triangular factor L (row-major packed,
-K(K+1)/2 values); M = L L^T approximates kappa_mean h G_e^{-1}, so the
-correction B (M / (kappa_mean h)) B^T r_I is symmetric positive
-semi-definite for any network.  Training pairs come from solver residuals:
+Coarse space: the interior "bubble" basis b_a(xi) = (1 - xi^2) P_a(xi),
+a = 0..p (P_a Legendre, p = min(2, N - 2)), B[(i,j,k)][(a,b,c)] =
+b_a(xi_i) b_b(xi_j) b_c(xi_k) on the element-interior nodes (K = (p+1)^3
+columns, each scaled by the square root of the matching diagonal entry of
+the unit reference element's coarse inverse so that every mode is O(1)).
+The element's Galerkin coarse matrix is G_e = B^T A_II B (A_II the element
+stiffness on its interior nodes) and its exact coarse correction
+c_I = B G_e^{-1} B^T r_I.  The network sees the 8 log-kappa vertex
+deviations of the element and outputs a lower-triangular factor L
+(row-major packed, K(K+1)/2 values); M = L L^T approximates the normalised
+inverse kappa_mean h G_e^{-1}, so the correction B (M / (kappa_mean h)) B^T
+r_I is symmetric positive semi-definite for any network.  Training pairs:
 y = B^T r_I / ||B^T r_I||, target alpha* = kappa_mean h G_e^{-1} y, loss
 mean (L L^T y - alpha*)^2.
 
 Parity status: forward/backward pinned by central finite differences and by
-the linear-network closed form; Adam pinned by its first-step closed form;
-prolongation pinned by exact reproduction of trilinear functions.  Trained
+the linear-network closed form; Adam by its first-step closed form; the
+coarse target and correction by reproduction of coarse-space solutions,
+Galerkin orthogonality, zero face values and the invariance of the
+normalised inverse under scaling of kappa and of the element.  Trained
 weights are "parity unpinned" (non-convex, seed dependent).
 """
 from __future__ import annotations
@@ -97,36 +80,6 @@ def forward(theta, X, n_in, n_hidden, n_out, keep=False):
     return o
 
 
-def prolongation(xi):
-    """P[node][v] for the GLL nodes xi of one direction (n1^3 x 8)."""
-    xi = np.asarray(xi, dtype=np.float64)
-    phi = np.stack([(1.0 - xi) / 2.0, (1.0 + xi) / 2.0])  # [a][i]
-    n1 = xi.shape[0]
-    P = np.zeros((n1 ** 3, 8))
-    for k in range(n1):
-        for j in range(n1):
-            for i in range(n1):
-                node = i + n1 * j + n1 * n1 * k
-                for c in range(2):
-                    for b in range(2):
-                        for a in range(2):
-                            P[node, a + 2 * b + 4 * c] = (
-                                phi[a, i] * phi[b, j] * phi[c, k])
-    return P
-
-
-def loss_and_grad(theta, X, T, P, n_in, n_hidden, n_out):
-    """MSE between P o and the targets T (B x n_nodes) and its gradient."""
-    W1, b1, W2, b2, W3, b3 = unpack(theta, n_in, n_hidden, n_out)
-    o, (X, z1, h1, z2, h2) = forward(theta, X, n_in, n_hidden, n_out, keep=True)
-    B, nn = T.shape
-    diff = o @ P.T - T
-    loss = float(np.sum(diff * diff) / (B * nn))
-    dY = 2.0 * diff / (B * nn)          # d loss / d (P o)
-    do = dY @ P                          # B x n_out
-    return loss, backward(theta, (X, z1, h1, z2, h2), do, n_in, n_hidden, n_out)
-
-
 def backward(theta, acts, do, n_in, n_hidden, n_out):
     """Parameter gradient from the output gradient do (B x n_out) and the
     activations kept by forward(..., keep=True)."""
@@ -167,19 +120,6 @@ def he_init(n_in, n_hidden, n_out, seed):
     return pack(parts)
 
 
-def element_features(r_global, l2g, n1, e, kappa_vertices, n_in):
-    """Features x (n_in) and the scale s_e of element e."""
-    n3 = n1 ** 3
-    r_e = np.asarray(r_global, dtype=np.float64)[l2g[e * n3:(e + 1) * n3]]
-    s = float(np.linalg.norm(r_e))
-    x = np.zeros(n_in)
-    if s > 0:
-        x[:n3] = r_e / s
-    lk = np.log(np.asarray(kappa_vertices, dtype=np.float64))
-    x[n3:n3 + 8] = lk - lk.mean()
-    return x, s
-
-
 def interior_nodes(N):
     """Local indices i + n1 j + n1^2 k of the element-interior nodes
     1 <= i, j, k <= N-1 in lexicographic order (i fastest)."""
@@ -191,54 +131,6 @@ def interior_nodes(N):
     j = (q // m) % m + 1
     k = q // (m * m) + 1
     return i + n1 * (j + n1 * k)
-
-
-def interior_features(r_e, kappa_vertices, N, n_in=None):
-    """Features of the interior layout from the element's n1^3 nodal
-    residual values r_e: x = [r_I / s, log kappa vertex deviations], s."""
-    I = interior_nodes(N)
-    ni = I.shape[0]
-    r_I = np.asarray(r_e, dtype=np.float64)[I]
-    s = float(np.linalg.norm(r_I))
-    x = np.zeros(ni + 8 if n_in is None else n_in)
-    if s > 0:
-        x[:ni] = r_I / s
-    lk = np.log(np.asarray(kappa_vertices, dtype=np.float64))
-    x[ni:ni + 8] = lk - lk.mean()
-    return x, s
-
-
-def interior_solve(A_e, r_e, N):
-    """d = A_II^{-1} r_I: the element stiffness A_e (n1^3 x n1^3) restricted
-    to the interior nodes, solved densely."""
-    I = interior_nodes(N)
-    A_II = np.asarray(A_e, dtype=np.float64)[np.ix_(I, I)]
-    return np.linalg.solve(A_II, np.asarray(r_e, dtype=np.float64)[I])
-
-
-def interior_target(A_e, r_e, dinv_e, kappa_vertices, h, N):
-    """Target of the interior layout: (d - dinv_I r_I) kappa_mean h / s with
-    d = interior_solve(A_e, r_e, N); dinv_e holds the assembled Jacobi
-    inverse at the element's n1^3 nodes."""
-    I = interior_nodes(N)
-    r_I = np.asarray(r_e, dtype=np.float64)[I]
-    s = float(np.linalg.norm(r_I))
-    if s == 0:
-        return np.zeros(I.shape[0])
-    d = interior_solve(A_e, r_e, N)
-    kbar = float(np.mean(np.asarray(kappa_vertices, dtype=np.float64)))
-    return (d - np.asarray(dinv_e, dtype=np.float64)[I] * r_I) * kbar * h / s
-
-
-def interior_correction(o, s, kappa_vertices, h, N, damping=1.0):
-    """Correction on the element's n1^3 nodes from the network output o
-    ((N-1)^3 values): damping s / (kappa_mean h) o on the interior nodes,
-    zero on the faces."""
-    n1 = N + 1
-    c = np.zeros(n1 ** 3)
-    kbar = float(np.mean(np.asarray(kappa_vertices, dtype=np.float64)))
-    c[interior_nodes(N)] = damping * s / (kbar * h) * np.asarray(o, dtype=np.float64)
-    return c
 
 
 def coarse_degree(N):

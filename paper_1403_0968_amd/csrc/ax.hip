@@ -104,6 +104,7 @@ void launch_ax(int N, int prec, int64_t E, const void *D, const void *G,
 // persistent batched operator: work items are (solve, first element) tiles;
 // each workgroup walks items blockIdx.x, blockIdx.x + gridDim.x, ...
 // ---------------------------------------------------------------------------
+// elements per tile; launches with BS < N1^2 are refused (bax_min_block)
 template <int BS, int N1> struct BTile {
   static constexpr int EPB = (BS / (N1 * N1)) > 0 ? BS / (N1 * N1) : 1;
 };
@@ -163,6 +164,10 @@ template <int BS, class TV, class TG, class TC>
 static void launch_bax_bs(int nset, const BatchSolve *sds, const CgState *st,
                           const AxItem *items, int nitems, int grid, int src,
                           int dst, int skip_done, hipStream_t s) {
+  // a thread owns one (i, j) column: a workgroup must hold every column of
+  // the largest order of the set
+  if (BS < bax_min_block(nset))
+    fail(SEM_ERR_ARG, "batched operator: block size below n1^2 of an order");
   // order sets compiled: one order (n1 = 2..9) or the mixed set {4, 6, 8}
   switch (nset) {
     case 2: launch_bax_set<BS, TV, TG, TC, 2>(sds, st, items, nitems, grid, src, dst, skip_done, s); break;
@@ -205,6 +210,12 @@ void launch_bax(int prec, int bs, int nset, const BatchSolve *sds,
     launch_bax_t<float, uint16_t, float>(bs, nset, sds, st, items, nitems, grid,
                                          src, dst, skip_done, s);
   SEM_HIP(hipGetLastError());
+}
+
+int bax_min_block(int nset) {
+  const int n1 = nset == AX_SET_468 ? 8 : nset;
+  const int np = n1 * n1;
+  return np <= 64 ? 64 : np <= 128 ? 128 : 256;
 }
 
 int bax_elements_per_tile(int bs, int n1) {

@@ -327,24 +327,23 @@ sem_status sem_mlp_forward(sem_mlp *net, const uint16_t *X, int32_t ldx,
          "sem_mlp_forward: null argument or negative batch");
     int n_out = 0;
     mlp_info(net, nullptr, nullptr, &n_out, nullptr, nullptr);
-    mlp_forward(net, X, ldx, B, Y, n_out, false, strm(stream));
+    mlp_forward(net, X, ldx, B, Y, n_out, strm(stream));
   });
 }
 
-sem_status sem_mlp_loss_grad(sem_mlp *net, const uint16_t *X, int32_t ldx,
-                             const float *T, int32_t B, int32_t N, float *grad,
-                             double *loss, void *stream) {
+sem_status sem_mlp_set_precision(sem_mlp *net, int32_t p) {
   return guarded([&] {
-    need(net != nullptr && X != nullptr && T != nullptr && B >= 1,
-         "sem_mlp_loss_grad: null argument or empty batch");
-    const double l = mlp_loss_grad(net, X, ldx, T, B, N, true, strm(stream));
-    if (loss) *loss = l;
-    if (grad) {
-      int64_t np = 0;
-      mlp_info(net, nullptr, nullptr, nullptr, &np, nullptr);
-      SEM_HIP(hipMemcpyAsync(grad, mlp_grad_ptr(net), np * 4,
-                             hipMemcpyDeviceToDevice, strm(stream)));
-    }
+    need(net != nullptr, "sem_mlp_set_precision: null network");
+    need(p == SEM_BF16 || p == SEM_FP32,
+         "sem_mlp_set_precision: SEM_BF16 or SEM_FP32");
+    mlp_set_precision(net, p);
+  });
+}
+
+sem_status sem_mlp_get_precision(const sem_mlp *net, int32_t *p) {
+  return guarded([&] {
+    need(net != nullptr && p != nullptr, "sem_mlp_get_precision: null argument");
+    *p = mlp_precision(net);
   });
 }
 
@@ -427,13 +426,12 @@ sem_status sem_learn_train(sem_handle *h, sem_mlp *net, const double *const *b_L
   });
 }
 
-sem_status sem_learn_interior_pairs(sem_handle *h, const double *r_L,
-                                    const int32_t *elems, int32_t n,
-                                    uint16_t *X, int32_t ldx, float *T,
-                                    double rtol, int32_t *iters, void *stream) {
+sem_status sem_learn_attach_exact(sem_handle *h, double damping) {
   return guarded([&] {
-    need(h != nullptr, "sem_learn_interior_pairs: null handle");
-    learn_interior_pairs(h, r_L, elems, n, X, ldx, T, rtol, iters, strm(stream));
+    need(h != nullptr, "sem_learn_attach_exact: null handle");
+    need(std::isfinite(damping) && damping >= 0.0,
+         "sem_learn_attach_exact: damping must be finite and >= 0");
+    learn_attach_exact(h, damping);
   });
 }
 

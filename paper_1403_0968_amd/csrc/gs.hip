@@ -6,7 +6,9 @@
 // segment of a precomputed list of its local copies in ascending local
 // index; one thread sums the segment from +0.0 in that order and writes the
 // sum back to every copy.  Copies of Dirichlet nodes are zeroed from their
-// own list (no reads), and nodes with a single unmasked copy are left alone.
+// own list (no reads).  A node with a single unmasked copy receives
+// +0.0 + v, the same one-term sum: the value itself, except that -0.0
+// becomes +0.0.
 #include "common.h"
 #include "sem_internal.h"
 
@@ -17,6 +19,17 @@ __global__ void k_zero_ids(int64_t n, const int32_t *__restrict__ ids,
                            T *__restrict__ v) {
   const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (q < n) v[ids[q]] = T(0);
+}
+
+// single-copy nodes: v <- +0.0 + v (a sum of one term from +0.0)
+template <class T>
+__global__ void k_solo_sum(int64_t n, const int32_t *__restrict__ ids,
+                           T *__restrict__ v) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) {
+    const int32_t l = ids[q];
+    v[l] = T(0) + v[l];
+  }
 }
 
 template <class T>
@@ -41,6 +54,9 @@ void launch_gs(sem_handle *h, int prec, void *v, hipStream_t s) {
       hipLaunchKernelGGL(k_seg_sum<double>, dim3(nblk(h->n_seg, T)), dim3(T), 0,
                          s, h->n_seg, h->seg_off.as<int32_t>(),
                          h->seg_ids.as<int32_t>(), (double *)v);
+    if (h->n_solo > 0)
+      hipLaunchKernelGGL(k_solo_sum<double>, dim3(nblk(h->n_solo, T)), dim3(T), 0,
+                         s, h->n_solo, h->solo_lids.as<int32_t>(), (double *)v);
     if (h->n_masked > 0)
       hipLaunchKernelGGL(k_zero_ids<double>, dim3(nblk(h->n_masked, T)),
                          dim3(T), 0, s, h->n_masked,
@@ -50,6 +66,9 @@ void launch_gs(sem_handle *h, int prec, void *v, hipStream_t s) {
       hipLaunchKernelGGL(k_seg_sum<float>, dim3(nblk(h->n_seg, T)), dim3(T), 0,
                          s, h->n_seg, h->seg_off.as<int32_t>(),
                          h->seg_ids.as<int32_t>(), (float *)v);
+    if (h->n_solo > 0)
+      hipLaunchKernelGGL(k_solo_sum<float>, dim3(nblk(h->n_solo, T)), dim3(T), 0,
+                         s, h->n_solo, h->solo_lids.as<int32_t>(), (float *)v);
     if (h->n_masked > 0)
       hipLaunchKernelGGL(k_zero_ids<float>, dim3(nblk(h->n_masked, T)),
                          dim3(T), 0, s, h->n_masked,

@@ -173,6 +173,8 @@ HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet) {
         } else if (cnt > 1) {
           for (int64_t q = start; q < pos; ++q) M.seg_ids.push_back(M.perm[q]);
           M.seg_off.push_back((int32_t)M.seg_ids.size());
+        } else {
+          M.solo_lids.push_back(M.perm[start]);
         }
       }
     }

@@ -1,38 +1,26 @@
-// Learned per-element correction on a mesh: element features of a
-// residual, the network's outputs turned into nodal corrections, and the
-// generation of training pairs from FP64 solves followed by GPU training.
+// Learned per-element coarse correction on a mesh (the preconditioner slot
+// that section 4.2.2 leaves open): the element coarse operators that the
+// network predicts from the element's kappa, their application inside
+// flexible CG, and the generation of training pairs from FP64 solves
+// followed by GPU training.
 //
-// Three output layouts, fixed by the network's shape (n3 = (N+1)^3,
-// ni = (N-1)^3):
-//   Q1       n_in = n3 + 8, n_out = 8: trilinear vertex values prolonged to
-//            the GLL nodes; targets from the global error;
-//   nodal    n_in = n3 + 8, n_out = n3: one value per node; targets from the
-//            global error;
-//   interior n_in = ni + 8, n_out = ni: one value per element-interior node
-//            (1 <= i, j, k <= N-1); targets from the element-interior solve;
-//   coarse   n_in = 8, n_out = K(K+1)/2: a lower-triangular factor L of the
-//            element's coarse operator in the interior bubble basis (below);
-//            trained on residual pairs against the exact Galerkin inverse.
-// Features of element e (residual r on unique nodes): r_f = r at the
-// feature nodes (all nodes, or the interior ones), s_e = ||r_f||_2,
-// x = [r_f / s_e, log kappa at the 8 vertices minus their mean, 0 ...].
-// Correction: c_e = s_e / (kappa_e h_e) y_e, with y_e the network output on
-// the element's nodes (prolonged, nodal, or interior with zero faces),
-// kappa_e the mean of the vertex values and h_e the element size; the solver
-// averages c over the copies of every node (interior nodes have one).
-// Coarse layout: bubble basis b_a(x) = (1 - x^2) P_a(x), a = 0..p,
+// Coarse space: bubble basis b_a(x) = (1 - x^2) P_a(x), a = 0..p,
 // p = min(2, N-2), B = tensor products on the interior nodes (K = (p+1)^3
-// columns); the exact element coarse correction is B G_e^{-1} B^T r_I with
-// G_e = B^T A_II B.  The network maps the 8 log-kappa vertex deviations to
-// L with M_e = L L^T ~ kappa_e h_e G_e^{-1}, and the correction
-// c_I = damping B (M_e / (kappa_e h_e)) B^T r_I is symmetric positive
-// semi-definite whatever the network outputs.
-// Targets, scaled by kappa_e h_e / s_e so that input and target are O(1):
-//   global error: the element error x* - x_k of a snapshot;
-//   interior: d - dinv r_I, with d the solution of the element's interior
-//   problem A_II d = r_I (the element stiffness with zero values on the
-//   element's faces), so that z = dinv r + c is the element-interior block
-//   solve wherever the network is exact.
+// columns), every column scaled so that the reference element's coarse
+// inverse has unit diagonal.  The exact element coarse correction is
+// B G_e^{-1} B^T r_I with G_e = B^T A_II B (A_II the element stiffness on
+// its interior nodes).  The network (n_in = 8, n_out = K(K+1)/2) maps the 8
+// log-kappa vertex deviations of an element to a lower-triangular L with
+// M_e = L L^T ~ kappa_e h_e G_e^{-1}, and the correction
+//   c_I = damping B (M_e / (kappa_e h_e)) B^T r_I
+// is symmetric positive semi-definite whatever the network outputs
+// (kappa_e: mean of the vertex values, h_e: element size).  The exact
+// operators themselves (no network) can be attached instead, which gives
+// the correction the network is trained to imitate.
+// Training pairs: y = B^T r_I / ||B^T r_I|| from a snapshot residual of an
+// FP64 Jacobi-PCG solve (or, for a random half of the pairs, a random unit
+// direction) with target alpha* = kappa_e h_e G_e^{-1} y; the loss is the
+// mean of (L L^T y - alpha*)^2.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -44,40 +32,28 @@
 
 namespace sem {
 
-enum { LM_Q1 = 0, LM_NODAL = 1, LM_INTERIOR = 2, LM_COARSE = 3 };
-
 struct CoarseTab {
   float B1[7][3];  // B1[i][a] = (1 - x_i^2) P_a(x_i) at interior GLL point i
   float sc[27];    // column scale of B, column a + Q (b + Q c)
 };
 
+// Per-mesh state: basis B [ni][K] (FP64; its FP32 factors B1 and column
+// scale sc for the apply kernel, sc also on the device), kappa features of
+// every element (FP32 [E][8] and BF16 network input rows [E][ldx]), the
+// element operators M_e / (kappa_e h_e) (FP32, symmetric, packed lower
+// triangles [E][K(K+1)/2], row a holding columns 0..a) of the network of
+// version mver or of the exact inverses, and the corrections (unique-node
+// vector cG for the solver, E-vector cL for sem_precond_apply).
 struct Learn {
-  int ldx = 0, n3 = 0, n_out = 0, ldo = 0;
-  int mode = LM_NODAL, nf = 0, nt = 0;  // layout, feature nodes, target width
-  // coarse layout: basis B [ni][K] (FP64; FP32 factors B1 and the column
-  // scale sc for the apply kernel, sc also on the device), kappa features of every
-  // element (BF16 [E][ldx]), element operators M_e / (kappa_e h_e) (FP32,
-  // symmetric, packed lower triangles [E][K(K+1)/2], row a holding columns
-  // 0..a) for the network of version mver
-  int K = 0, ni = 0;
-  DevBuf Bd, Xk, Ml, cG, Sc;  // cG: correction on unique nodes (FP32)
-  CoarseTab tab{};            // factors of B for the apply kernel (FP32)
+  int K = 0, ni = 0, ldx = 16, ldo = 16;
+  DevBuf Bd, Xk, Ml, cG, cL, Sc, O, kfeat, invkh;
+  CoarseTab tab{};
   const sem_mlp *mnet = nullptr;
   uint64_t mver = 0;
-  DevBuf X, s, O, kfeat, invkh, cL, h1, h2;  // h1, h2: hidden activations
+  bool exact = false;          // Ml holds the exact inverses (no network)
+  double exact_damping = 0.0;  // damping of the exact correction
+  DevBuf exact_damp_dev;       // its device copy (float)
 };
-
-struct LXi {
-  float xi[17];
-  int n1;
-};
-
-static LXi lxi(const sem_handle *h) {
-  LXi p{};
-  p.n1 = h->n1;
-  for (int q = 0; q < h->n1; ++q) p.xi[q] = (float)h->ref.xi[q];
-  return p;
-}
 
 // per element: log-kappa vertex features and 1 / (kappa_e h_e)
 __global__ void k_kfeat(int64_t E, const double *__restrict__ kv, double h,
@@ -92,86 +68,6 @@ __global__ void k_kfeat(int64_t E, const double *__restrict__ kv, double h,
   }
   for (int v = 0; v < 8; ++v) kf[e * 8 + v] = (float)(lk[v] - mean);
   invkh[e] = (float)(1.0 / (kbar * h));
-}
-
-// local index of feature node q: every node, or the element-interior nodes
-// 1 <= i, j, k <= N-1 in lexicographic order
-__device__ inline int feat_node(int q, int n1, int interior) {
-  if (!interior) return q;
-  const int m = n1 - 2;
-  const int i = q % m, j = (q / m) % m, k = q / (m * m);
-  return (i + 1) + n1 * ((j + 1) + n1 * (k + 1));
-}
-
-// features of the residual r for every element: r on unique nodes (read
-// through l2g) or, with l2g NULL, a continuous E-vector
-template <class TV>
-__global__ void __launch_bounds__(256)
-    k_features(int64_t E, int n1, int interior, int nf,
-               const int32_t *__restrict__ l2g, const TV *__restrict__ r,
-               const float *__restrict__ kf, uint16_t *__restrict__ X, int ldx,
-               float *__restrict__ s) {
-  __shared__ double sm[4];
-  const int64_t e = blockIdx.x;
-  const int n3 = n1 * n1 * n1;
-  auto val = [&](int q) -> double {
-    const int64_t l = e * n3 + feat_node(q, n1, interior);
-    return (double)r[l2g ? (int64_t)l2g[l] : l];
-  };
-  double ss = 0.0;
-  for (int q = threadIdx.x; q < nf; q += 256) {
-    const double v = val(q);
-    ss += v * v;
-  }
-  ss = block_sum<256>(ss, sm);
-  if (threadIdx.x == 0) sm[0] = ss;
-  __syncthreads();
-  const double nrm = sqrt(sm[0]);
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  uint16_t *xe = X + e * (int64_t)ldx;
-  for (int q = threadIdx.x; q < nf; q += 256)
-    xe[q] = f32_to_bf16((float)(val(q) * inv));
-  if (threadIdx.x < 8) xe[nf + threadIdx.x] = f32_to_bf16(kf[e * 8 + threadIdx.x]);
-  if (threadIdx.x == 0) s[e] = (float)nrm;
-}
-
-// cL[e][node] = damping s_e invkh_e y(node), with y = sum_v P[node][v] O[e][v]
-// (Q1), y = O[e][node] (nodal) or y = O[e][interior index of node] and 0 on
-// the element's faces (interior)
-__global__ void __launch_bounds__(256)
-    k_correct(int64_t E, LXi xp, int mode, const float *__restrict__ O, int ldo,
-              const float *__restrict__ s, const float *__restrict__ invkh,
-              const float *__restrict__ damping, float *__restrict__ cL) {
-  const int64_t e = blockIdx.x;
-  const int n1 = xp.n1, n3 = n1 * n1 * n1, N = n1 - 1;
-  const float sc = damping[0] * s[e] * invkh[e];
-  if (mode == LM_NODAL) {
-    for (int p = threadIdx.x; p < n3; p += 256) cL[e * n3 + p] = sc * O[e * ldo + p];
-    return;
-  }
-  if (mode == LM_INTERIOR) {
-    const int m = N - 1;
-    for (int p = threadIdx.x; p < n3; p += 256) {
-      const int i = p % n1, j = (p / n1) % n1, k = p / (n1 * n1);
-      const bool in = i > 0 && i < N && j > 0 && j < N && k > 0 && k < N;
-      cL[e * n3 + p] =
-          in ? sc * O[e * ldo + (i - 1) + m * ((j - 1) + m * (k - 1))] : 0.f;
-    }
-    return;
-  }
-  float o[8];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) o[v] = O[e * ldo + v];
-  for (int p = threadIdx.x; p < n3; p += 256) {
-    const int i = p % n1, j = (p / n1) % n1, k = p / (n1 * n1);
-    const float px[2] = {0.5f * (1.f - xp.xi[i]), 0.5f * (1.f + xp.xi[i])};
-    const float py[2] = {0.5f * (1.f - xp.xi[j]), 0.5f * (1.f + xp.xi[j])};
-    const float pz[2] = {0.5f * (1.f - xp.xi[k]), 0.5f * (1.f + xp.xi[k])};
-    float y = 0.f;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) y += px[v & 1] * py[(v >> 1) & 1] * pz[v >> 2] * o[v];
-    cL[e * n3 + p] = sc * y;
-  }
 }
 
 // sum over the workgroup, returned to every thread (fixed order: the wave
@@ -366,6 +262,24 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// element operators from exact inverses: M_e / (kappa_e h_e) with
+// M_e = kappa_e h_e G_e^{-1} (Mex, FP64 [E][K][K], symmetrised), packed
+// lower triangle in FP32
+__global__ void __launch_bounds__(256)
+    k_exact_to_M(int64_t E, int K, const double *__restrict__ Mex,
+                 const float *__restrict__ invkh, float *__restrict__ Ml) {
+  const int64_t e = blockIdx.x;
+  const double *M = Mex + e * K * K;
+  const double sc = (double)invkh[e];
+  const int kp = K * (K + 1) / 2;
+  for (int ab = threadIdx.x; ab < kp; ab += 256) {
+    int a = 0;
+    while ((a + 1) * (a + 2) / 2 <= ab) ++a;
+    const int b = ab - a * (a + 1) / 2;
+    Ml[e * kp + ab] = (float)(sc * 0.5 * (M[a * K + b] + M[b * K + a]));
+  }
+}
+
 // correction of the coarse layout: c = damping B M_e B^T r_I on the interior
 // nodes of every element.  UNIQUE: r on unique nodes (read through the box
 // numbering) and c written to the interior entries of the unique-node
@@ -538,6 +452,12 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
   }
 }
 
+// device damping of the attached correction (network or exact operators)
+static const float *learn_damping_dev(const sem_handle *h) {
+  return h->learn->exact ? h->learn->exact_damp_dev.as<float>()
+                         : mlp_damping_dev(h->net);
+}
+
 template <class TV, bool UNIQUE, int M, int Q>
 static void launch_ca(const sem_handle *h, const Learn *L, const TV *r, float *out,
                       hipStream_t s) {
@@ -546,7 +466,7 @@ static void launch_ca(const sem_handle *h, const Learn *L, const TV *r, float *o
   const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * 8);
   hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, M, Q>), dim3(grid), dim3(64 * CA_WAVES),
                      0, s, h->E, box, L->tab, L->Sc.as<float>(), r, L->Ml.as<float>(),
-                     mlp_damping_dev(h->net), out);
+                     learn_damping_dev(h), out);
 }
 
 template <class TV, bool UNIQUE>
@@ -576,31 +496,30 @@ void learn_destroy(sem_handle *h) {
   h->net = nullptr;
 }
 
-// layout of a network on a mesh (fails when its shape fits none)
-static int layout_of(const sem_handle *h, const sem_mlp *net) {
-  int n_in = 0, n_out = 0;
-  mlp_info(net, &n_in, nullptr, &n_out, nullptr, nullptr);
-  const int n3 = h->n1 * h->n1 * h->n1, m = h->N - 1, ni = m * m * m;
-  if (n_in == n3 + 8 && n_out == 8) return LM_Q1;
-  if (n_in == n3 + 8 && n_out == n3) return LM_NODAL;
-  if (ni > 0 && n_in == ni + 8 && n_out == ni) return LM_INTERIOR;
-  if (ni > 0) {
-    const int q = std::min(2, h->N - 2) + 1, K = q * q * q;
-    if (n_in == 8 && n_out == K * (K + 1) / 2) return LM_COARSE;
-  }
-  fail(SEM_ERR_ARG, "learned correction: the network needs n_in = (N+1)^3 + 8 "
-                    "and n_out = 8 or (N+1)^3, or n_in = (N-1)^3 + 8 and "
-                    "n_out = (N-1)^3, or n_in = 8 and n_out = K(K+1)/2 with "
-                    "K = (min(2, N-2)+1)^3 (N >= 2)");
+// a network fits the coarse layout of this mesh when n_in = 8 and
+// n_out = K(K+1)/2 (N >= 2); the element targets are those of the stiffness
+// operator alone (no mass term)
+static int coarse_k(const sem_handle *h) {
+  const int q = std::min(2, h->N - 2) + 1;
+  return q * q * q;
 }
 
-static void check_net(const sem_handle *h, const sem_mlp *net) {
-  // the element targets (local solves, coarse Galerkin operators) are those
-  // of the stiffness operator alone
+static void check_mesh(const sem_handle *h) {
+  if (h->N < 2 || h->N > 8)
+    fail(SEM_ERR_ARG, "learned correction: N must be in 2..8");
   if (h->has_mass)
     fail(SEM_ERR_STATE, "learned correction: meshes with a mass term "
                         "(alpha != 0) are not supported");
-  (void)layout_of(h, net);
+}
+
+static void check_net(const sem_handle *h, const sem_mlp *net) {
+  check_mesh(h);
+  int n_in = 0, n_out = 0;
+  mlp_info(net, &n_in, nullptr, &n_out, nullptr, nullptr);
+  const int K = coarse_k(h);
+  if (n_in != 8 || n_out != K * (K + 1) / 2)
+    fail(SEM_ERR_ARG, "learned correction: the network needs n_in = 8 and "
+                      "n_out = K(K+1)/2 with K = (min(2, N-2)+1)^3");
 }
 
 // inverse of a small dense matrix (Gauss-Jordan with partial pivoting, FP64)
@@ -720,53 +639,31 @@ static void kappa_features(const sem_handle *h, DevBuf &kfeat, DevBuf &invkh) {
   SEM_HIP(hipGetLastError());
 }
 
-static void ensure_learn(sem_handle *h, const sem_mlp *net) {
-  const int ldx = mlp_padded_inputs(net);
-  const int mode = layout_of(h, net);
-  int n_out = 0;
-  mlp_info(net, nullptr, nullptr, &n_out, nullptr, nullptr);
-  if (h->learn && h->learn->ldx == ldx && h->learn->n_out == n_out &&
-      h->learn->mode == mode)
-    return;
-  delete h->learn;
-  h->learn = nullptr;
+static void ensure_learn(sem_handle *h) {
+  if (h->learn != nullptr) return;
   Learn *L = new Learn();
   try {
-    L->ldx = ldx;
-    L->n3 = h->n1 * h->n1 * h->n1;
-    L->n_out = n_out;
-    L->mode = mode;
-    L->nf = mode == LM_INTERIOR ? n_out : L->n3;
-    L->nt = mode == LM_INTERIOR ? n_out : L->n3;
-    if (mode == LM_COARSE) {
-      const int m = h->N - 1;
-      L->ni = m * m * m;
-      std::vector<double> Bd = bubble_basis(h, L->K, &L->tab);
-      L->nf = 0;
-      L->nt = 2 * L->K;
-      L->Bd.alloc(Bd.size() * 8);
-      SEM_HIP(hipMemcpy(L->Bd.p, Bd.data(), Bd.size() * 8, hipMemcpyHostToDevice));
-      L->Sc.alloc((size_t)L->K * 4);
-      SEM_HIP(hipMemcpy(L->Sc.p, L->tab.sc, (size_t)L->K * 4, hipMemcpyHostToDevice));
-      L->Ml.alloc((size_t)h->E * (L->K * (L->K + 1) / 2) * 4);
-      L->cG.alloc((size_t)h->nG * 4);
-      SEM_HIP(hipMemset(L->cG.p, 0, (size_t)h->nG * 4));  // faces stay zero
-    }
-    L->ldo = n_out > 16 ? n_out : 16;
-    L->X.alloc((size_t)h->E * ldx * 2);
-    SEM_HIP(hipMemset(L->X.p, 0, (size_t)h->E * ldx * 2));  // zero padding
-    L->s.alloc(h->E * 4);
+    const int m = h->N - 1;
+    L->ni = m * m * m;
+    std::vector<double> Bd = bubble_basis(h, L->K, &L->tab);
+    const int kp = L->K * (L->K + 1) / 2;
+    L->ldx = 16;                    // 8 features, zero padding
+    L->ldo = kp > 16 ? kp : 16;
+    L->Bd.alloc(Bd.size() * 8);
+    SEM_HIP(hipMemcpy(L->Bd.p, Bd.data(), Bd.size() * 8, hipMemcpyHostToDevice));
+    L->Sc.alloc((size_t)L->K * 4);
+    SEM_HIP(hipMemcpy(L->Sc.p, L->tab.sc, (size_t)L->K * 4, hipMemcpyHostToDevice));
+    L->Ml.alloc((size_t)h->E * kp * 4);
+    L->cG.alloc((size_t)h->nG * 4);
+    SEM_HIP(hipMemset(L->cG.p, 0, (size_t)h->nG * 4));  // faces stay zero
+    L->cL.alloc((size_t)h->nL * 4);
     L->O.alloc((size_t)h->E * L->ldo * 4);
-    L->cL.alloc(h->nL * 4);
-    L->h1.alloc((size_t)h->E * 128 * 2);
-    L->h2.alloc((size_t)h->E * 128 * 2);
+    L->exact_damp_dev.alloc(sizeof(float));
     kappa_features(h, L->kfeat, L->invkh);
-    if (mode == LM_COARSE) {
-      L->Xk.alloc((size_t)h->E * ldx * 2);
-      hipLaunchKernelGGL(k_kfeat_rows, dim3((unsigned)h->E), dim3(64), 0, 0, h->E,
-                         L->kfeat.as<float>(), L->Xk.as<uint16_t>(), ldx);
-      SEM_HIP(hipGetLastError());
-    }
+    L->Xk.alloc((size_t)h->E * L->ldx * 2);
+    hipLaunchKernelGGL(k_kfeat_rows, dim3((unsigned)h->E), dim3(64), 0, 0, h->E,
+                       L->kfeat.as<float>(), L->Xk.as<uint16_t>(), L->ldx);
+    SEM_HIP(hipGetLastError());
     SEM_HIP(hipDeviceSynchronize());
   } catch (...) {
     delete L;
@@ -777,14 +674,18 @@ static void ensure_learn(sem_handle *h, const sem_mlp *net) {
 
 void drop_graphs(sem_handle *h);
 
-// coarse layout: (re)compute the element operators M_e from the attached
-// network when it or its parameters changed (outside any graph capture)
+// (re)compute the element operators M_e from the attached network when it
+// or its parameters changed (outside any graph capture); exact operators
+// never change
 void learn_refresh(sem_handle *h) {
   Learn *L = h->learn;
-  if (L == nullptr || h->net == nullptr || L->mode != LM_COARSE) return;
+  if (L == nullptr || L->exact || h->net == nullptr) return;
   if (L->mnet == h->net && L->mver == mlp_version(h->net)) return;
-  mlp_forward(h->net, L->Xk.as<uint16_t>(), L->ldx, (int)h->E, L->O.as<float>(),
-              L->ldo, false, 0, L->h1.as<uint16_t>(), L->h2.as<uint16_t>());
+  sem_mlp *net = h->net;
+  int ldx_net = mlp_padded_inputs(net);
+  if (ldx_net != L->ldx) fail(SEM_ERR_STATE, "learned correction: input width");
+  mlp_forward(net, L->Xk.as<uint16_t>(), L->ldx, (int)h->E, L->O.as<float>(),
+              L->ldo, 0);
   hipLaunchKernelGGL(k_factor_to_M, dim3((unsigned)h->E), dim3(256), 0, 0, h->E,
                      L->K, L->O.as<float>(), L->ldo, L->invkh.as<float>(),
                      L->Ml.as<float>());
@@ -794,63 +695,50 @@ void learn_refresh(sem_handle *h) {
   L->mver = mlp_version(h->net);
 }
 
+bool learn_active(const sem_handle *h) {
+  return h->learn != nullptr && (h->learn->exact || h->net != nullptr);
+}
+
+double learn_damping(const sem_handle *h) {
+  return h->learn->exact ? h->learn->exact_damping : mlp_damping(h->net);
+}
+
+double learn_ref_rate(const sem_handle *h) {
+  return h->learn->exact ? 0.0 : mlp_ref_rate(h->net);
+}
+
 void learn_attach(sem_handle *h, sem_mlp *net) {
   drop_graphs(h);
+  if (h->learn) h->learn->exact = false;
   if (net == nullptr) {
     h->net = nullptr;
     return;
   }
   check_net(h, net);
-  ensure_learn(h, net);
+  ensure_learn(h);
   h->net = net;
+  h->learn->mnet = nullptr;  // recompute M_e for this network
   learn_refresh(h);
 }
 
-void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
-                 hipStream_t s) {
-  Learn *L = h->learn;
-  if (L == nullptr || h->net == nullptr)
+void learn_apply(sem_handle *h, const void *r, bool f32, hipStream_t s) {
+  if (!learn_active(h))
     fail(SEM_ERR_STATE, "learned correction: no network attached");
-  if (L->mode == LM_COARSE) {  // into the unique-node buffer cG
-    if (f32)
-      launch_coarse_apply<float, true>(h, L, (const float *)r, L->cG.as<float>(), s);
-    else
-      launch_coarse_apply<double, true>(h, L, (const double *)r, L->cG.as<float>(),
-                                        s);
-    return;
-  }
-  const int interior = L->mode == LM_INTERIOR;
+  Learn *L = h->learn;
   if (f32)
-    hipLaunchKernelGGL(k_features<float>, dim3((unsigned)h->E), dim3(256), 0, s,
-                       h->E, h->n1, interior, L->nf, h->l2g.as<int32_t>(),
-                       (const float *)r, L->kfeat.as<float>(), L->X.as<uint16_t>(),
-                       L->ldx, L->s.as<float>());
+    launch_coarse_apply<float, true>(h, L, (const float *)r, L->cG.as<float>(), s);
   else
-    hipLaunchKernelGGL(k_features<double>, dim3((unsigned)h->E), dim3(256), 0, s,
-                       h->E, h->n1, interior, L->nf, h->l2g.as<int32_t>(),
-                       (const double *)r, L->kfeat.as<float>(), L->X.as<uint16_t>(),
-                       L->ldx, L->s.as<float>());
-  SEM_HIP(hipGetLastError());
-  mlp_forward(h->net, L->X.as<uint16_t>(), L->ldx, (int)h->E, L->O.as<float>(),
-              L->ldo, false, s, L->h1.as<uint16_t>(), L->h2.as<uint16_t>());
-  hipLaunchKernelGGL(k_correct, dim3((unsigned)h->E), dim3(256), 0, s, h->E,
-                     lxi(h), L->mode, L->O.as<float>(), L->ldo,
-                     L->s.as<float>(), L->invkh.as<float>(),
-                     mlp_damping_dev(h->net), cL ? cL : L->cL.as<float>());
-  SEM_HIP(hipGetLastError());
+    launch_coarse_apply<double, true>(h, L, (const double *)r, L->cG.as<float>(),
+                                      s);
 }
 
-float *learn_cl(sem_handle *h) { return h->learn ? h->learn->cL.as<float>() : nullptr; }
-// the coarse layout's correction on unique nodes, or NULL for the others
-float *learn_cg(sem_handle *h) {
-  return h->learn && h->learn->mode == LM_COARSE ? h->learn->cG.as<float>() : nullptr;
-}
+// the correction on unique nodes (zero off the element interiors)
+float *learn_cg(sem_handle *h) { return h->learn ? h->learn->cG.as<float>() : nullptr; }
 
-// z_L = dinv o r_L + (average over copies of the correction) on continuous
-// E-vectors (FP64), for sem_precond_apply
+// z_L = dinv o r_L + c_L on continuous E-vectors (FP64), for
+// sem_precond_apply: the coarse correction lives on element-interior nodes,
+// each of which has a single copy, and is zero on the faces
 __global__ void k_precond_learned_local(int64_t nL, const int32_t *__restrict__ l2g,
-                                        const int32_t *__restrict__ off,
-                                        const int32_t *__restrict__ perm,
                                         const uint8_t *__restrict__ bmask,
                                         const double *__restrict__ dinv,
                                         const float *__restrict__ cL,
@@ -858,83 +746,20 @@ __global__ void k_precond_learned_local(int64_t nL, const int32_t *__restrict__ 
                                         double *__restrict__ z) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nL) return;
-  if (bmask[l]) {
-    z[l] = 0.0;
-    return;
-  }
-  const int64_t g = l2g[l];
-  const int a = off[g], b = off[g + 1];
-  float c = 0.f;
-  for (int k = a; k < b; ++k) c += cL[perm[k]];
-  z[l] = dinv[g] * r[l] + (double)(c / (float)(b - a));
+  z[l] = bmask[l] ? 0.0 : dinv[l2g[l]] * r[l] + (double)cL[l];
 }
 
 void learn_precond_local(sem_handle *h, const double *r, double *z, hipStream_t s) {
-  Learn *L = h->learn;
-  if (L == nullptr || h->net == nullptr)
+  if (!learn_active(h))
     fail(SEM_ERR_STATE, "learned correction: no network attached");
-  if (L->mode == LM_COARSE) {
-    learn_refresh(h);
-    launch_coarse_apply<double, false>(h, L, r, L->cL.as<float>(), s);
-  } else {
-  hipLaunchKernelGGL(k_features<double>, dim3((unsigned)h->E), dim3(256), 0, s,
-                     h->E, h->n1, L->mode == LM_INTERIOR ? 1 : 0, L->nf,
-                     (const int32_t *)nullptr, r, L->kfeat.as<float>(),
-                     L->X.as<uint16_t>(), L->ldx, L->s.as<float>());
-  SEM_HIP(hipGetLastError());
-  mlp_forward(h->net, L->X.as<uint16_t>(), L->ldx, (int)h->E, L->O.as<float>(),
-              L->ldo, false, s, L->h1.as<uint16_t>(), L->h2.as<uint16_t>());
-  hipLaunchKernelGGL(k_correct, dim3((unsigned)h->E), dim3(256), 0, s, h->E,
-                     lxi(h), L->mode, L->O.as<float>(), L->ldo,
-                     L->s.as<float>(), L->invkh.as<float>(),
-                     mlp_damping_dev(h->net), L->cL.as<float>());
-  }
+  Learn *L = h->learn;
+  learn_refresh(h);
+  launch_coarse_apply<double, false>(h, L, r, L->cL.as<float>(), s);
   hipLaunchKernelGGL(k_precond_learned_local, dim3((unsigned)((h->nL + 255) / 256)),
                      dim3(256), 0, s, h->nL, h->l2g.as<int32_t>(),
-                     h->offsets.as<int32_t>(), h->perm.as<int32_t>(),
                      h->bmask.as<uint8_t>(), h->dinv_G.as<double>(),
                      L->cL.as<float>(), r, z);
   SEM_HIP(hipGetLastError());
-}
-
-// ---------------------------------------------------------------------------
-// training pairs and training
-// ---------------------------------------------------------------------------
-// pair p: features of snapshot residual rs[snap] on element e and target
-// (x* - xs[snap]) kappa_e h_e / s_e on the element's nodes
-__global__ void __launch_bounds__(256)
-    k_build_pairs(int np, const int32_t *__restrict__ psnap,
-                  const int32_t *__restrict__ pelem, int64_t nG, int n1,
-                  const int32_t *__restrict__ l2g, const double *__restrict__ xs,
-                  const double *__restrict__ rs, const double *__restrict__ xstar,
-                  const float *__restrict__ kf, const float *__restrict__ invkh,
-                  uint16_t *__restrict__ X, int ldx, float *__restrict__ T) {
-  __shared__ double sm[4];
-  const int p = blockIdx.x;
-  if (p >= np) return;
-  const int n3 = n1 * n1 * n1;
-  const int64_t e = pelem[p];
-  const double *r = rs + (int64_t)psnap[p] * nG;
-  const double *x = xs + (int64_t)psnap[p] * nG;
-  double ss = 0.0;
-  for (int q = threadIdx.x; q < n3; q += 256) {
-    const double v = r[l2g[e * n3 + q]];
-    ss += v * v;
-  }
-  ss = block_sum<256>(ss, sm);
-  if (threadIdx.x == 0) sm[0] = ss;
-  __syncthreads();
-  const double nrm = sqrt(sm[0]);
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  const double tsc = nrm > 0.0 ? 1.0 / (nrm * (double)invkh[e]) : 0.0;
-  uint16_t *xp = X + (int64_t)p * ldx;
-  float *tp = T + (int64_t)p * n3;
-  for (int q = threadIdx.x; q < n3; q += 256) {
-    const int64_t g = l2g[e * n3 + q];
-    xp[q] = f32_to_bf16((float)(r[g] * inv));
-    tp[q] = (float)((xstar[g] - x[g]) * tsc);
-  }
-  if (threadIdx.x < 8) xp[n3 + threadIdx.x] = f32_to_bf16(kf[e * 8 + threadIdx.x]);
 }
 
 __global__ void k_gather_rows(int B, const int32_t *__restrict__ idx,
@@ -948,193 +773,6 @@ __global__ void k_gather_rows(int B, const int32_t *__restrict__ idx,
     Xb[(int64_t)b * ldx + q] = X[src * ldx + q];
   for (int q = threadIdx.x; q < n3; q += blockDim.x)
     Tb[(int64_t)b * n3 + q] = T[src * n3 + q];
-}
-
-// Pairs of the interior layout, one workgroup per pair p: residual r (a
-// snapshot rs[psnap[p]] on unique nodes read through l2g, or, with
-// local_r, the continuous E-vector rs) restricted to the interior nodes of
-// element pelem[p].  Features X[p] = [r_I / s, log kappa deviations] and
-// target T[p] = (d - dinv r_I) kappa_e h_e / s, where d solves the
-// element's interior problem A_II d = r_I by Jacobi-preconditioned CG
-// inside the workgroup: the element operator (the shared element routine,
-// zero values on the element's faces) through the pair's scratch rows U, W,
-// vectors of a column in the registers of its thread, FP64 throughout,
-// stopping at ||r_I - A_II d|| <= rtol ||r_I|| or after maxit iterations.
-template <int N1, int NT>
-__global__ void __launch_bounds__(NT)
-    k_interior_pairs(int np, const int32_t *__restrict__ psnap,
-                     const int32_t *__restrict__ pelem, int64_t nG, int local_r,
-                     const int32_t *__restrict__ l2g, const double *__restrict__ rs,
-                     const double *__restrict__ dinvG, const double *__restrict__ G,
-                     const double *__restrict__ D, const float *__restrict__ kf,
-                     const float *__restrict__ invkh, uint16_t *__restrict__ X,
-                     int ldx, float *__restrict__ T, double *__restrict__ U,
-                     double *__restrict__ W, int maxit, double rtol,
-                     int32_t *__restrict__ iters) {
-  constexpr int NP = N1 * N1, N3 = NP * N1, N = N1 - 1, M = N1 - 2;
-  constexpr int NI = M * M * M;
-  __shared__ double smem[lds_words<N1>(1)];
-  __shared__ double red[NT / 64];
-  const int p = blockIdx.x;
-  if (p >= np) return;  // uniform per block
-  const int t = threadIdx.x;
-  const bool act = t < NP;
-  const int c = act ? t : 0;
-  const int i = c % N1, j = c / N1;
-  const bool colI = act && i > 0 && i < N && j > 0 && j < N;
-  const int64_t e = pelem[p];
-  const double *r = local_r ? rs : rs + (int64_t)psnap[p] * nG;
-  double b[N1], dv[N1];
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    const bool in = colI && k > 0 && k < N;
-    const int64_t l = e * N3 + c + k * NP;
-    const int64_t g = in ? (int64_t)l2g[l] : 0;
-    b[k] = in ? r[local_r ? l : g] : 0.0;
-    dv[k] = in ? dinvG[g] : 0.0;
-  }
-  double ss = 0.0;
-#pragma unroll
-  for (int k = 0; k < N1; ++k) ss += b[k] * b[k];
-  ss = block_allsum<NT>(ss, red);
-  const double nrm = sqrt(ss);
-  const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
-  uint16_t *xe = X + (int64_t)p * ldx;
-  float *te = T + (int64_t)p * NI;
-#pragma unroll
-  for (int k = 1; k < N; ++k)
-    if (colI) xe[(i - 1) + M * ((j - 1) + M * (k - 1))] = f32_to_bf16((float)(b[k] * inv));
-  if (t < 8) xe[NI + t] = f32_to_bf16(kf[e * 8 + t]);
-
-  double x[N1], rr[N1], pp[N1];
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    x[k] = 0.0;
-    rr[k] = b[k];
-    pp[k] = dv[k] * b[k];
-  }
-  double rz = 0.0;
-#pragma unroll
-  for (int k = 0; k < N1; ++k) rz += rr[k] * pp[k];
-  rz = block_allsum<NT>(rz, red);
-  double *u = U + (int64_t)p * N3;
-  double *w = W + (int64_t)p * N3;
-  const double *Ge = G + e * 6 * N3;
-  const double stop2 = rtol * rtol * ss;
-  double rn2 = ss;
-  int it = 0;
-  while (it < maxit && rn2 > stop2) {  // uniform: reduced values
-#pragma unroll
-    for (int k = 0; k < N1; ++k)
-      if (act) u[c + k * NP] = pp[k];
-    // the element routine reads and writes the column of this thread
-    ax_tile<N1, 1, double, double, double, double, false, false>(
-        t, 0, 1, D, Ge, u, w, nullptr, smem);
-    double q[N1], pq = 0.0;
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      q[k] = (colI && k > 0 && k < N) ? w[c + k * NP] : 0.0;
-      pq += pp[k] * q[k];
-    }
-    pq = block_allsum<NT>(pq, red);
-    if (!(pq > 0.0)) break;
-    const double alpha = rz / pq;
-    double a2 = 0.0, a3 = 0.0;
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      x[k] += alpha * pp[k];
-      rr[k] -= alpha * q[k];
-      a2 += rr[k] * rr[k];
-      a3 += rr[k] * dv[k] * rr[k];
-    }
-    rn2 = block_allsum<NT>(a2, red);
-    const double rzn = block_allsum<NT>(a3, red);
-    const double beta = rzn / rz;
-    rz = rzn;
-#pragma unroll
-    for (int k = 0; k < N1; ++k) pp[k] = dv[k] * rr[k] + beta * pp[k];
-    ++it;
-  }
-  const double tsc = nrm > 0.0 ? 1.0 / (nrm * (double)invkh[e]) : 0.0;
-#pragma unroll
-  for (int k = 1; k < N; ++k)
-    if (colI)
-      te[(i - 1) + M * ((j - 1) + M * (k - 1))] =
-          (float)((x[k] - dv[k] * b[k]) * tsc);
-  if (t == 0 && iters) iters[p] = it;
-}
-
-template <int N1>
-static void launch_pairs_n(const sem_handle *h, int np, const int32_t *psnap,
-                           const int32_t *pelem, int local_r, const double *rs,
-                           const float *kf, const float *invkh, uint16_t *X,
-                           int ldx, float *T, double *U, double *W, int maxit,
-                           double rtol, int32_t *iters, hipStream_t s) {
-  constexpr int NT = N1 * N1 <= 64 ? 64 : 128;
-  hipLaunchKernelGGL((k_interior_pairs<N1, NT>), dim3(np), dim3(NT), 0, s, np,
-                     psnap, pelem, h->nG, local_r, h->l2g.as<int32_t>(), rs,
-                     h->dinv_G.as<double>(), h->G64.as<double>(),
-                     h->D64.as<double>(), kf, invkh, X, ldx, T, U, W, maxit, rtol,
-                     iters);
-}
-
-// interior pairs for np (snapshot, element) pairs; U, W: np (N+1)^3 doubles
-static void launch_interior_pairs(const sem_handle *h, int np,
-                                  const int32_t *psnap, const int32_t *pelem,
-                                  int local_r, const double *rs, const float *kf,
-                                  const float *invkh, uint16_t *X, int ldx,
-                                  float *T, double *U, double *W, int maxit,
-                                  double rtol, int32_t *iters, hipStream_t s) {
-  if (np <= 0) return;
-  switch (h->N) {
-#define SEM_PAIRS(NN)                                                          \
-  case NN:                                                                     \
-    launch_pairs_n<NN + 1>(h, np, psnap, pelem, local_r, rs, kf, invkh, X, ldx, \
-                           T, U, W, maxit, rtol, iters, s);                    \
-    break;
-    SEM_PAIRS(2)
-    SEM_PAIRS(3)
-    SEM_PAIRS(4)
-    SEM_PAIRS(5)
-    SEM_PAIRS(6)
-    SEM_PAIRS(7)
-    SEM_PAIRS(8)
-#undef SEM_PAIRS
-    default:
-      fail(SEM_ERR_ARG, "interior pairs: N must be in 2..8");
-  }
-  SEM_HIP(hipGetLastError());
-}
-
-constexpr int LOCAL_MAXIT = 2000;     // element-interior CG iteration cap
-constexpr double LOCAL_RTOL = 1e-10;  // element-interior CG tolerance
-
-void learn_interior_pairs(sem_handle *h, const double *rL, const int32_t *elems,
-                          int n, uint16_t *X, int ldx, float *T, double rtol,
-                          int32_t *iters, hipStream_t s) {
-  if (h->has_mass) fail(SEM_ERR_STATE, "interior pairs: mesh has a mass term");
-  const int m = h->N - 1;
-  if (m < 1) fail(SEM_ERR_ARG, "interior pairs: N must be at least 2");
-  if (n < 0 || (n > 0 && (!rL || !elems || !X || !T)))
-    fail(SEM_ERR_ARG, "interior pairs: null argument");
-  if (ldx < m * m * m + 8 || ldx % 16 != 0)
-    fail(SEM_ERR_ARG, "interior pairs: ldx must be a multiple of 16 and at "
-                      "least (N-1)^3 + 8");
-  if (!(rtol > 0.0)) fail(SEM_ERR_ARG, "interior pairs: rtol must be positive");
-  if (n == 0) return;
-  std::vector<int32_t> he(n);
-  SEM_HIP(hipMemcpy(he.data(), elems, (size_t)n * 4, hipMemcpyDeviceToHost));
-  for (int q = 0; q < n; ++q)
-    if (he[q] < 0 || he[q] >= h->E)
-      fail(SEM_ERR_ARG, "interior pairs: element index out of range");
-  DevBuf kf, ik, U, W;
-  kappa_features(h, kf, ik);
-  U.alloc((size_t)n * h->n1 * h->n1 * h->n1 * 8);
-  W.alloc((size_t)n * h->n1 * h->n1 * h->n1 * 8);
-  launch_interior_pairs(h, n, nullptr, elems, 1, rL, kf.as<float>(),
-                        ik.as<float>(), X, ldx, T, U.as<double>(), W.as<double>(),
-                        LOCAL_MAXIT, rtol, iters, s);
-  SEM_HIP(hipStreamSynchronize(s));
 }
 
 template <int N1>
@@ -1172,24 +810,37 @@ int learn_coarse_exact(sem_handle *h, double *M, hipStream_t s) {
   if (h->N < 2 || h->N > 8) fail(SEM_ERR_ARG, "coarse layout: N must be in 2..8");
   if (M == nullptr) fail(SEM_ERR_ARG, "coarse layout: null output");
   if (h->has_mass) fail(SEM_ERR_STATE, "coarse layout: mesh has a mass term");
-  // a throwaway description of the layout (basis and kappa scaling only)
-  Learn L;
-  const int m = h->N - 1;
-  L.ni = m * m * m;
-  std::vector<double> Bd = bubble_basis(h, L.K);
-  L.Bd.alloc(Bd.size() * 8);
-  SEM_HIP(hipMemcpy(L.Bd.p, Bd.data(), Bd.size() * 8, hipMemcpyHostToDevice));
-  kappa_features(h, L.kfeat, L.invkh);
+  ensure_learn(h);
+  coarse_exact(h, h->learn, M, s);
+  return h->learn->K;
+}
+
+// attach the exact element coarse inverses (no network) with the given
+// damping: the correction the network is trained to imitate
+void learn_attach_exact(sem_handle *h, double damping) {
+  drop_graphs(h);
+  check_mesh(h);
+  ensure_learn(h);
+  Learn *L = h->learn;
+  DevBuf Mex;
+  Mex.alloc((size_t)h->E * L->K * L->K * 8);
+  coarse_exact(h, L, Mex.as<double>(), 0);
+  hipLaunchKernelGGL(k_exact_to_M, dim3((unsigned)h->E), dim3(256), 0, 0, h->E,
+                     L->K, Mex.as<double>(), L->invkh.as<float>(), L->Ml.as<float>());
+  SEM_HIP(hipGetLastError());
+  const float f = (float)damping;
+  SEM_HIP(hipMemcpy(L->exact_damp_dev.p, &f, sizeof f, hipMemcpyHostToDevice));
   SEM_HIP(hipDeviceSynchronize());
-  coarse_exact(h, &L, M, s);
-  return L.K;
+  h->net = nullptr;
+  L->exact = true;
+  L->exact_damping = damping;
+  L->mnet = nullptr;
 }
 
 // snapshot-recording FP64 Jacobi-PCG (solver.hip)
 int solve_with_snapshots(sem_handle *h, const double *bL, double *xL, double rtol,
                          int every, int max_snaps, double *xs, double *rs,
                          int *iters, hipStream_t caller);
-const double *solution_vector(sem_handle *h);
 
 void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
                  const sem_train_opts *o, sem_train_report *rep,
@@ -1199,25 +850,24 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
   if (o->n_pairs < 1 || o->snapshot_every < 1 || o->max_snapshots < 1 ||
       o->epochs < 1 || o->batch < 1 || !(o->lr > 0) || !(o->solve_rtol > 0))
     fail(SEM_ERR_ARG, "train: invalid options");
-  ensure_learn(h, net);
+  if (mlp_padded_inputs(net) != 16)
+    fail(SEM_ERR_ARG, "train: the coarse layout takes 8 inputs");
+  ensure_learn(h);
   Learn *L = h->learn;
-  const int n3 = L->n3, ldx = L->ldx;
+  const int ldx = L->ldx, K = L->K, nt = 2 * K;
   const int64_t nG = h->nG;
   auto t0 = std::chrono::steady_clock::now();
 
-  DevBuf xs, rs, xL, Xd, Td, ps, pe, Xb, Tb, idx;
+  DevBuf xs, rs, xL, Xd, Td, ps, pe, Xb, Tb, idx, Mex;
   xs.alloc((size_t)o->max_snapshots * nG * 8);
   rs.alloc((size_t)o->max_snapshots * nG * 8);
   xL.alloc(h->nL * 8);
   Xd.alloc((size_t)o->n_pairs * ldx * 2);
   SEM_HIP(hipMemset(Xd.p, 0, (size_t)o->n_pairs * ldx * 2));
-  const int nt = L->nt;
-  const bool interior = L->mode == LM_INTERIOR;
-  const bool coarse = L->mode == LM_COARSE;
-  DevBuf Mex;
-  if (coarse) {
-    Mex.alloc((size_t)h->E * L->K * L->K * 8);
-    coarse_exact(h, L, Mex.as<double>(), 0);
+  Td.alloc((size_t)o->n_pairs * nt * 4);
+  Mex.alloc((size_t)h->E * K * K * 8);
+  coarse_exact(h, L, Mex.as<double>(), 0);
+  {
     int64_t np = 0, steps = 0;
     int n_in = 0, H = 0, n_out = 0;
     mlp_info(net, &n_in, &H, &n_out, &np, &steps);
@@ -1232,13 +882,10 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
       for (int64_t q = 0; q < (int64_t)n_out * H; ++q) th[w3 + q] *= 0.01f;
       float *b3 = th.data() + w3 + (int64_t)n_out * H;
       for (int q = 0; q < n_out; ++q) b3[q] = 0.f;
-      for (int i = 0; i < L->K; ++i) b3[i * (i + 1) / 2 + i] = 1.f;
+      for (int i = 0; i < K; ++i) b3[i * (i + 1) / 2 + i] = 1.f;
       mlp_set_params(net, th.data(), np);
     }
   }
-  Td.alloc((size_t)o->n_pairs * nt * 4);
-  DevBuf U, W, litn;
-  int local_max = 0;
   ps.alloc((size_t)o->n_pairs * 4);
   pe.alloc((size_t)o->n_pairs * 4);
   std::mt19937_64 rng(o->seed);
@@ -1266,65 +913,36 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
     }
     SEM_HIP(hipMemcpy(ps.p, hs.data(), want * 4, hipMemcpyHostToDevice));
     SEM_HIP(hipMemcpy(pe.p, he.data(), want * 4, hipMemcpyHostToDevice));
-    if (coarse) {
-      // half the pairs take a random unit direction instead of the residual's
-      std::vector<int32_t> hiso(want);
-      std::vector<double> hyr((size_t)want * L->K, 0.0);
-      std::normal_distribution<double> nd(0.0, 1.0);
-      for (int p = 0; p < want; ++p) {
-        hiso[p] = (int32_t)(rng() & 1);
-        if (!hiso[p]) continue;
-        double ss = 0.0;
-        for (int k = 0; k < L->K; ++k) {
-          const double v = nd(rng);
-          hyr[(size_t)p * L->K + k] = v;
-          ss += v * v;
-        }
-        const double inv = ss > 0.0 ? 1.0 / std::sqrt(ss) : 0.0;
-        for (int k = 0; k < L->K; ++k) hyr[(size_t)p * L->K + k] *= inv;
+    // half the pairs take a random unit direction instead of the residual's
+    std::vector<int32_t> hiso(want);
+    std::vector<double> hyr((size_t)want * K, 0.0);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    for (int p = 0; p < want; ++p) {
+      hiso[p] = (int32_t)(rng() & 1);
+      if (!hiso[p]) continue;
+      double ss = 0.0;
+      for (int k = 0; k < K; ++k) {
+        const double v = nd(rng);
+        hyr[(size_t)p * K + k] = v;
+        ss += v * v;
       }
-      DevBuf iso, yr;
-      iso.alloc((size_t)want * 4);
-      yr.alloc(hyr.size() * 8);
-      SEM_HIP(hipMemcpy(iso.p, hiso.data(), (size_t)want * 4, hipMemcpyHostToDevice));
-      SEM_HIP(hipMemcpy(yr.p, hyr.data(), hyr.size() * 8, hipMemcpyHostToDevice));
-      hipLaunchKernelGGL(k_coarse_pairs, dim3(want), dim3(64), 0, 0, want,
-                         ps.as<int32_t>(), pe.as<int32_t>(), nG, h->n1,
-                         h->l2g.as<int32_t>(), rs.as<double>(), L->Bd.as<double>(),
-                         L->K, L->ni, Mex.as<double>(), L->kfeat.as<float>(),
-                         iso.as<int32_t>(), yr.as<double>(),
-                         Xd.as<uint16_t>() + (int64_t)built * ldx, ldx,
-                         Td.as<float>() + (int64_t)built * nt);
-      SEM_HIP(hipGetLastError());
-      SEM_HIP(hipDeviceSynchronize());  // iso, yr are freed at scope end
-    } else if (interior) {
-      if (U.p == nullptr) {
-        const size_t rows = (size_t)(o->n_pairs / nrhs + o->n_pairs % nrhs);
-        U.alloc(rows * n3 * 8);
-        W.alloc(rows * n3 * 8);
-        litn.alloc(rows * 4);
-      }
-      launch_interior_pairs(h, want, ps.as<int32_t>(), pe.as<int32_t>(), 0,
-                            rs.as<double>(), L->kfeat.as<float>(),
-                            L->invkh.as<float>(),
-                            Xd.as<uint16_t>() + (int64_t)built * ldx, ldx,
-                            Td.as<float>() + (int64_t)built * nt, U.as<double>(),
-                            W.as<double>(), LOCAL_MAXIT, LOCAL_RTOL,
-                            litn.as<int32_t>(), 0);
-      std::vector<int32_t> hi(want);
-      SEM_HIP(hipMemcpy(hi.data(), litn.p, (size_t)want * 4, hipMemcpyDeviceToHost));
-      for (int v : hi) local_max = std::max(local_max, v);
-    } else {
-      hipLaunchKernelGGL(k_build_pairs, dim3(want), dim3(256), 0, 0, want,
-                         ps.as<int32_t>(), pe.as<int32_t>(), nG, h->n1,
-                         h->l2g.as<int32_t>(), xs.as<double>(), rs.as<double>(),
-                         solution_vector(h), L->kfeat.as<float>(),
-                         L->invkh.as<float>(),
-                         Xd.as<uint16_t>() + (int64_t)built * ldx, ldx,
-                         Td.as<float>() + (int64_t)built * n3);
-      SEM_HIP(hipGetLastError());
+      const double inv = ss > 0.0 ? 1.0 / std::sqrt(ss) : 0.0;
+      for (int k = 0; k < K; ++k) hyr[(size_t)p * K + k] *= inv;
     }
-    SEM_HIP(hipDeviceSynchronize());
+    DevBuf iso, yr;
+    iso.alloc((size_t)want * 4);
+    yr.alloc(hyr.size() * 8);
+    SEM_HIP(hipMemcpy(iso.p, hiso.data(), (size_t)want * 4, hipMemcpyHostToDevice));
+    SEM_HIP(hipMemcpy(yr.p, hyr.data(), hyr.size() * 8, hipMemcpyHostToDevice));
+    hipLaunchKernelGGL(k_coarse_pairs, dim3(want), dim3(64), 0, 0, want,
+                       ps.as<int32_t>(), pe.as<int32_t>(), nG, h->n1,
+                       h->l2g.as<int32_t>(), rs.as<double>(), L->Bd.as<double>(),
+                       K, L->ni, Mex.as<double>(), L->kfeat.as<float>(),
+                       iso.as<int32_t>(), yr.as<double>(),
+                       Xd.as<uint16_t>() + (int64_t)built * ldx, ldx,
+                       Td.as<float>() + (int64_t)built * nt);
+    SEM_HIP(hipGetLastError());
+    SEM_HIP(hipDeviceSynchronize());  // iso, yr are freed at scope end
     built += want;
   }
   auto t1 = std::chrono::steady_clock::now();
@@ -1348,10 +966,8 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
                          idx.as<int32_t>() + b0, Xd.as<uint16_t>(), ldx,
                          Td.as<float>(), nt, Xb.as<uint16_t>(), Tb.as<float>());
       SEM_HIP(hipGetLastError());
-      sum += coarse ? mlp_loss_grad_factor(net, Xb.as<uint16_t>(), ldx,
-                                           Tb.as<float>(), L->K, B, true, s)
-                    : mlp_loss_grad(net, Xb.as<uint16_t>(), ldx, Tb.as<float>(),
-                                    B, h->N, true, s);
+      sum += mlp_loss_grad_factor(net, Xb.as<uint16_t>(), ldx, Tb.as<float>(), K,
+                                  B, true, s);
       mlp_adam(net, nullptr, o->lr, 0.9, 0.999, 1e-8, s);
       ++nb;
     }
@@ -1363,12 +979,14 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
   auto t2 = std::chrono::steady_clock::now();
 
   // Damping of the correction: the learned flexible-CG solve of the last
-  // training right-hand side to 1e-6 is compared with Jacobi-PCG for a few
-  // damping values (around 1 for the interior and coarse layouts, whose
-  // exact networks reproduce the element-interior solve and the element
-  // coarse correction; small for the global-error layouts); the best one is kept if it needs fewer iterations than
-  // Jacobi, else the correction is disabled (damping 0).
+  // training right-hand side to 1e-6 is compared with Jacobi-PCG for the
+  // damping values 1, 0.75, 0.5, 0.25 (an exact network reproduces the
+  // element coarse correction, for which 1 is natural); the best one is
+  // kept if it needs fewer iterations than Jacobi, else the correction is
+  // disabled (damping 0).
   sem_mlp *prev = h->net;
+  const bool prev_exact = L->exact;
+  const double prev_exact_d = L->exact_damping;
   const double rate = rate_n ? rate_sum / rate_n : 0.0;
   mlp_set_damping(net, 1.0, 0.0);  // no progress judge while validating
   learn_attach(h, net);
@@ -1384,9 +1002,7 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
   SEM_HIP(hipMemset(xL.p, 0, h->nL * 8));
   pcg_solve(h, &vo, bL[nrhs - 1], xL.as<double>(), &vs, caller);
   const int it_jac = vs.iters;
-  const double cand_int[4] = {1.0, 0.75, 0.5, 0.25};
-  const double cand_glob[4] = {0.2, 0.15, 0.1, 0.05};
-  const double *cand = interior || coarse ? cand_int : cand_glob;
+  const double cand[4] = {1.0, 0.75, 0.5, 0.25};
   double best_d = 0.0;
   int best_it = it_jac;
   int cand_it[4] = {-1, -1, -1, -1};
@@ -1406,13 +1022,15 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
     }
   }
   mlp_set_damping(net, best_d, rate);
-  learn_attach(h, prev);
+  if (prev_exact)
+    learn_attach_exact(h, prev_exact_d);
+  else
+    learn_attach(h, prev);
   auto t3 = std::chrono::steady_clock::now();
   if (rep) {
     rep->pairs = built;
     rep->epochs = o->epochs;
     rep->snapshots = total_snaps;
-    rep->local_iters_max = local_max;
     rep->first_loss = first;
     rep->last_loss = last;
     rep->data_seconds = std::chrono::duration<double>(t1 - t0).count();

@@ -1,14 +1,19 @@
 // Learned per-element coarse correction: a three-layer perceptron
 //   z1 = x W1^T + b1, h1 = relu(z1); z2 = h1 W2^T + b2, h2 = relu(z2);
-//   o = h2 W3^T + b3  (8 trilinear vertex coefficients of the element)
+//   o = h2 W3^T + b3  (the packed factor of the element's coarse operator)
 // trained on the GPU by the kernels of this file (forward, loss and
 // backward, Adam of Kingma & Ba 2015).  The paper leaves the PCG
 // preconditioner open (section 4.2.2); this network is one choice of it.
 //
-// Precision: FP32 master parameters; BF16 copies of the weights feed the
-// forward layers, which run on MFMA (v_mfma_f32_16x16x16_bf16, FP32
-// accumulation) with BF16 layer inputs; the backward pass is FP32 on VALU
-// using the same BF16-rounded weights and layer inputs as the forward pass.
+// Precision (per network): BF16 (the default) keeps FP32 master parameters
+// and BF16 copies of the weights that feed the forward layers, which run on
+// MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulation) with BF16 layer
+// inputs; the backward pass is FP32 on VALU using the same BF16-rounded
+// weights and layer inputs as the forward pass.  FP32 runs the forward
+// layers on VALU with the FP32 master weights and FP32 hidden activations
+// (the network input stays BF16), and the backward pass on the same values:
+// it differs from an exact evaluation only by FP32 rounding, which makes
+// element-by-element checks of every parameter block possible.
 //
 // MFMA tile (16x16x16): lane l holds A[l % 16][4 (l / 16) + 0..3] and
 // B[4 (l / 16) + 0..3][l % 16] (4 BF16 values each); the result C[4 (l / 16) +
@@ -79,14 +84,47 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// ---------------------------------------------------------------------------
-// backward kernels (FP32)
-// ---------------------------------------------------------------------------
 template <class T> __device__ inline float asf(T v);
 template <> __device__ inline float asf<float>(float v) { return v; }
 template <> __device__ inline float asf<uint16_t>(uint16_t v) {
   return bf16_to_f32(v);
 }
+
+// ---------------------------------------------------------------------------
+// forward layer on VALU, FP32 weights (the FP32 precision of a network)
+// ---------------------------------------------------------------------------
+// Y[m][n] = act(sum_k X[m][k] W[n][k] + b[n]) for n < N, k < K: X [M][ldx]
+// (BF16 or FP32), W FP32 [N][ldw], Y FP32 [M][ldy].  16 x 16 output tiles,
+// 16-wide K slices through LDS; the sum runs over k in ascending order.
+template <class TX, bool RELU>
+__global__ void __launch_bounds__(256)
+    k_dense_f32(int M, int K, int N, const TX *__restrict__ X, int ldx,
+                const float *__restrict__ W, int ldw, const float *__restrict__ b,
+                float *__restrict__ Y, int ldy) {
+  __shared__ float sx[16][17], sw[16][17];
+  const int tm = threadIdx.x / 16, tn = threadIdx.x % 16;
+  const int m = blockIdx.x * 16 + tm, n = blockIdx.y * 16 + tn;
+  float acc = 0.f;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int r = threadIdx.x / 16, c = threadIdx.x % 16;
+    const int mi = blockIdx.x * 16 + r, ni = blockIdx.y * 16 + r, kc = k0 + c;
+    sx[r][c] = (mi < M && kc < K) ? asf<TX>(X[(size_t)mi * ldx + kc]) : 0.f;
+    sw[r][c] = (ni < N && kc < K) ? W[(size_t)ni * ldw + kc] : 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc += sx[tm][q] * sw[tn][q];
+    __syncthreads();
+  }
+  if (m < M && n < N) {
+    float v = acc + b[n];
+    if (RELU) v = fmaxf(v, 0.0f);
+    Y[(size_t)m * ldy + n] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward kernels (FP32)
+// ---------------------------------------------------------------------------
 
 // dW[n][k] = sum_b dY[b][n] X[b][k]  (n < N, k < Kv); dW row stride Kv
 template <class TX>
@@ -122,10 +160,12 @@ __global__ void k_grad_b(int B, int N, const float *__restrict__ dY, int lddy,
   db[n] = acc;
 }
 
-// dZ[b][k] = (sum_n dY[b][n] W[n][k]) * (H[b][k] > 0), W BF16 [>=N][ldw]
+// dZ[b][k] = (sum_n dY[b][n] W[n][k]) * (H[b][k] > 0), W BF16 or FP32
+// [>=N][ldw]
+template <class TW>
 __global__ void __launch_bounds__(256)
     k_grad_x(int B, int N, int K, const float *__restrict__ dY, int lddy,
-             const uint16_t *__restrict__ W, int ldw,
+             const TW *__restrict__ W, int ldw,
              const float *__restrict__ H, int ldh, float *__restrict__ dZ,
              int lddz) {
   __shared__ float sy[16][17], sw[16][17];
@@ -137,7 +177,7 @@ __global__ void __launch_bounds__(256)
     const int bi = blockIdx.x * 16 + r, ni = n0 + c;
     sy[r][c] = (bi < B && ni < N) ? dY[(size_t)bi * lddy + ni] : 0.f;
     const int nw = n0 + r, kw = blockIdx.y * 16 + c;
-    sw[r][c] = (nw < N && kw < K) ? bf16_to_f32(W[(size_t)nw * ldw + kw]) : 0.f;
+    sw[r][c] = (nw < N && kw < K) ? asf<TW>(W[(size_t)nw * ldw + kw]) : 0.f;
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc += sy[tb][q] * sw[q][tk];
@@ -145,59 +185,6 @@ __global__ void __launch_bounds__(256)
   }
   if (b < B && k < K)
     dZ[(size_t)b * lddz + k] = H[(size_t)b * ldh + k] > 0.f ? acc : 0.f;
-}
-
-// Loss of one sample: Yhat = P o (P the trilinear prolongation to the n1^3
-// GLL nodes), diff = Yhat - T; writes dO[b][v] = 2 / (B nn) sum diff P[.][v]
-// and the sample's sum of squared differences.
-struct XiParams {
-  float xi[17];
-  int n1;
-};
-__global__ void __launch_bounds__(256)
-    k_loss(int B, const float *__restrict__ O, int ldo,
-           const float *__restrict__ T, XiParams xp, float *__restrict__ dO,
-           int lddo, double *__restrict__ lossp) {
-  __shared__ double sm[9][4];
-  const int b = blockIdx.x;
-  const int n1 = xp.n1, nn = n1 * n1 * n1;
-  float o[8];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) o[v] = O[(size_t)b * ldo + v];
-  double acc[9];
-#pragma unroll
-  for (int v = 0; v < 9; ++v) acc[v] = 0.0;
-  for (int node = threadIdx.x; node < nn; node += 256) {
-    const int i = node % n1, j = (node / n1) % n1, k = node / (n1 * n1);
-    const float px[2] = {0.5f * (1.f - xp.xi[i]), 0.5f * (1.f + xp.xi[i])};
-    const float py[2] = {0.5f * (1.f - xp.xi[j]), 0.5f * (1.f + xp.xi[j])};
-    const float pz[2] = {0.5f * (1.f - xp.xi[k]), 0.5f * (1.f + xp.xi[k])};
-    float P[8], y = 0.f;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) {
-      P[v] = px[v & 1] * py[(v >> 1) & 1] * pz[v >> 2];
-      y += P[v] * o[v];
-    }
-    const float d = y - T[(size_t)b * nn + node];
-    acc[8] += (double)d * (double)d;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) acc[v] += (double)d * (double)P[v];
-  }
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-  for (int v = 0; v < 9; ++v) {
-    const double s = wave_sum(acc[v]);
-    if (lane == 0) sm[v][wid] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x < 9) {
-    const int v = threadIdx.x;
-    const double s = sm[v][0] + sm[v][1] + sm[v][2] + sm[v][3];
-    if (v == 8)
-      lossp[b] = s;
-    else
-      dO[(size_t)b * lddo + v] = (float)(2.0 * s / ((double)B * nn));
-  }
 }
 
 // coarse-operator factor: the output is a lower-triangular K x K factor L
@@ -233,24 +220,6 @@ __global__ void __launch_bounds__(64)
   for (int i = 0, q = 0; i < K; ++i)
     for (int j = 0; j <= i; ++j, ++q) dO[(size_t)b * lddo + q] = g[i] * v[j] + y[i] * w[j];
   lossp[b] = loss;
-}
-
-// nodal outputs: Yhat = o itself (n_out values per sample)
-__global__ void __launch_bounds__(256)
-    k_loss_id(int B, int no, const float *__restrict__ O, int ldo,
-              const float *__restrict__ T, float *__restrict__ dO, int lddo,
-              double *__restrict__ lossp) {
-  __shared__ double sm[4];
-  const int b = blockIdx.x;
-  double acc = 0.0;
-  const double sc = 2.0 / ((double)B * no);
-  for (int j = threadIdx.x; j < no; j += 256) {
-    const float d = O[(size_t)b * ldo + j] - T[(size_t)b * no + j];
-    acc += (double)d * (double)d;
-    dO[(size_t)b * lddo + j] = (float)(sc * d);
-  }
-  const double s = block_sum<256>(acc, sm);
-  if (threadIdx.x == 0) lossp[b] = s;
 }
 
 __global__ void k_sum_losses(int B, const double *__restrict__ lossp, int nn,
@@ -306,6 +275,7 @@ __global__ void k_refresh(int n_in, int kin, int H, int n_out, int w3rows,
 // ---------------------------------------------------------------------------
 struct sem_mlp {
   int n_in = 0, H = 0, n_out = 0, kin = 0;
+  int prec = SEM_BF16;      // SEM_BF16 (MFMA, BF16 weights) or SEM_FP32 (VALU)
   int nt3 = 1, gy3 = 1, w3rows = 16;  // output layer: tiles per wave, grid.y
   int64_t np = 0, step = 0;
   uint64_t version = 1;     // changes whenever the parameters change
@@ -433,31 +403,43 @@ static void ensure_scratch(sem_mlp *net, int B) {
 }
 
 // forward of B samples X [B][ldx] BF16 (ldx >= kin, padding columns zero)
-// into O [B][ldo] FP32; with train = true the hidden activations are kept in
-// the network's training scratch.  Inference may bring its own hidden
-// buffers (h1x, h2x: B x 128 BF16) so that graphs captured around it never
-// depend on the network's scratch, which training may reallocate.
+// into O [B][ldo] FP32; the hidden activations are kept in the network's
+// scratch (BF16 and FP32 copies in BF16 precision, FP32 in FP32 precision)
+// for a backward pass.
 void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
-                 int ldo, bool train, hipStream_t s, uint16_t *h1x,
-                 uint16_t *h2x) {
+                 int ldo, hipStream_t s) {
   if (B <= 0) return;
   if (ldx < net->kin || ldx % 16 != 0)
     fail(SEM_ERR_ARG, "mlp_forward: ldx must be >= padded n_in and a multiple of 16");
-  const bool ext = !train && h1x != nullptr && h2x != nullptr;
-  if (!ext) ensure_scratch(net, B);
-  uint16_t *h1b = ext ? h1x : net->h1b.as<uint16_t>();
-  uint16_t *h2b = ext ? h2x : net->h2b.as<uint16_t>();
+  ensure_scratch(net, B);
   const int H = net->H;
+  const float *W1 = net->th.as<float>();
+  const float *b1 = W1 + (int64_t)H * net->n_in;
+  const float *W2 = b1 + H;
+  const float *b2 = W2 + (int64_t)H * H;
+  const float *W3 = b2 + H;
+  const float *b3 = W3 + (int64_t)net->n_out * H;
+  float *h1f = net->h1f.as<float>(), *h2f = net->h2f.as<float>();
+  if (net->prec == SEM_FP32) {
+    const unsigned gm = (unsigned)((B + 15) / 16);
+    hipLaunchKernelGGL((k_dense_f32<uint16_t, true>), dim3(gm, H / 16), dim3(256),
+                       0, s, B, net->n_in, H, X, ldx, W1, net->n_in, b1, h1f, H);
+    hipLaunchKernelGGL((k_dense_f32<float, true>), dim3(gm, H / 16), dim3(256), 0,
+                       s, B, H, H, (const float *)h1f, H, W2, H, b2, h2f, H);
+    hipLaunchKernelGGL((k_dense_f32<float, false>),
+                       dim3(gm, (unsigned)((net->n_out + 15) / 16)), dim3(256), 0,
+                       s, B, H, net->n_out, (const float *)h2f, H, W3, H, b3, O,
+                       ldo);
+    SEM_HIP(hipGetLastError());
+    return;
+  }
+  uint16_t *h1b = net->h1b.as<uint16_t>(), *h2b = net->h2b.as<uint16_t>();
   const unsigned grid = (unsigned)((B + 63) / 64);
-  const float *b1 = net->th.as<float>() + (int64_t)H * net->n_in;
-  const float *b2 = b1 + H + (int64_t)H * H;
-  const float *b3 = b2 + H + (int64_t)net->n_out * H;
   hipLaunchKernelGGL((k_dense_mfma<8, true>), dim3(grid), dim3(256), 0, s, B,
                      net->kin, H, X, ldx, net->W1b.as<uint16_t>(), b1, h1b, H,
-                     train ? net->h1f.as<float>() : (float *)nullptr, H);
+                     h1f, H);
   hipLaunchKernelGGL((k_dense_mfma<8, true>), dim3(grid), dim3(256), 0, s, B, H,
-                     H, h1b, H, net->W2b.as<uint16_t>(), b2, h2b, H,
-                     train ? net->h2f.as<float>() : (float *)nullptr, H);
+                     H, h1b, H, net->W2b.as<uint16_t>(), b2, h2b, H, h2f, H);
   if (net->nt3 == 1)
     hipLaunchKernelGGL((k_dense_mfma<1, false>), dim3(grid), dim3(256), 0, s, B, H,
                        net->n_out, h2b, H, net->W3b.as<uint16_t>(), b3,
@@ -469,45 +451,64 @@ void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
   SEM_HIP(hipGetLastError());
 }
 
-// loss and gradient of B samples: with n_in = (N+1)^3 + 8 and n_out = 8 the
-// output is 8 trilinear vertex values prolonged to the GLL nodes of order N
-// and T is [B][(N+1)^3]; otherwise the output is compared with T [B][n_out]
-// directly (nodal and interior layouts); gradient into net->grad (flat order)
-// backward pass from net->dO (written by a loss kernel) into net->grad,
-// then the mean loss over B samples of `count` terms each
+// backward pass from net->dO (written by a loss kernel) into net->grad
+// (flat parameter order), on the weights and layer inputs the forward pass
+// used; then the mean loss over B samples of `count` terms each
 static double mlp_backward(sem_mlp *net, const uint16_t *X, int ldx, int B,
                            int count, bool host_loss, hipStream_t s) {
   const int H = net->H;
   const int wo = net->n_out > 16 ? net->n_out : 16;
+  const bool f32 = net->prec == SEM_FP32;
   float *g = net->grad.as<float>();
   float *gW1 = g, *gb1 = gW1 + (int64_t)H * net->n_in, *gW2 = gb1 + H,
         *gb2 = gW2 + (int64_t)H * H, *gW3 = gb2 + H,
         *gb3 = gW3 + (int64_t)net->n_out * H;
+  const float *W2 = net->th.as<float>() + (int64_t)H * net->n_in + H;
+  const float *W3 = W2 + (int64_t)H * H + H;
+  const float *dO = net->dO.as<float>(), *dz2 = net->dz2.as<float>(),
+              *dz1 = net->dz1.as<float>();
+  const float *h1f = net->h1f.as<float>(), *h2f = net->h2f.as<float>();
   // layer 3
-  hipLaunchKernelGGL((k_grad_w<uint16_t>), dim3((net->n_out + 15) / 16, H / 16),
-                     dim3(256), 0, s, B, net->n_out, H, net->dO.as<float>(), wo,
-                     net->h2b.as<uint16_t>(), H, gW3);
+  if (f32)
+    hipLaunchKernelGGL((k_grad_w<float>), dim3((net->n_out + 15) / 16, H / 16),
+                       dim3(256), 0, s, B, net->n_out, H, dO, wo, h2f, H, gW3);
+  else
+    hipLaunchKernelGGL((k_grad_w<uint16_t>), dim3((net->n_out + 15) / 16, H / 16),
+                       dim3(256), 0, s, B, net->n_out, H, dO, wo,
+                       (const uint16_t *)net->h2b.as<uint16_t>(), H, gW3);
   hipLaunchKernelGGL(k_grad_b, dim3((net->n_out + 127) / 128), dim3(128), 0, s, B,
-                     net->n_out, net->dO.as<float>(), wo, gb3);
-  hipLaunchKernelGGL(k_grad_x, dim3((B + 15) / 16, H / 16), dim3(256), 0, s, B,
-                     net->n_out, H, net->dO.as<float>(), wo,
-                     net->W3b.as<uint16_t>(), H, net->h2f.as<float>(), H,
-                     net->dz2.as<float>(), H);
+                     net->n_out, dO, wo, gb3);
+  if (f32)
+    hipLaunchKernelGGL((k_grad_x<float>), dim3((B + 15) / 16, H / 16), dim3(256), 0,
+                       s, B, net->n_out, H, dO, wo, W3, H, h2f, H,
+                       net->dz2.as<float>(), H);
+  else
+    hipLaunchKernelGGL((k_grad_x<uint16_t>), dim3((B + 15) / 16, H / 16),
+                       dim3(256), 0, s, B, net->n_out, H, dO, wo,
+                       (const uint16_t *)net->W3b.as<uint16_t>(), H, h2f, H,
+                       net->dz2.as<float>(), H);
   // layer 2
-  hipLaunchKernelGGL((k_grad_w<uint16_t>), dim3(H / 16, H / 16), dim3(256), 0, s,
-                     B, H, H, net->dz2.as<float>(), H, net->h1b.as<uint16_t>(), H,
-                     gW2);
-  hipLaunchKernelGGL(k_grad_b, dim3(1), dim3(128), 0, s, B, H,
-                     net->dz2.as<float>(), H, gb2);
-  hipLaunchKernelGGL(k_grad_x, dim3((B + 15) / 16, H / 16), dim3(256), 0, s, B, H,
-                     H, net->dz2.as<float>(), H, net->W2b.as<uint16_t>(), H,
-                     net->h1f.as<float>(), H, net->dz1.as<float>(), H);
-  // layer 1
+  if (f32)
+    hipLaunchKernelGGL((k_grad_w<float>), dim3(H / 16, H / 16), dim3(256), 0, s, B,
+                       H, H, dz2, H, h1f, H, gW2);
+  else
+    hipLaunchKernelGGL((k_grad_w<uint16_t>), dim3(H / 16, H / 16), dim3(256), 0, s,
+                       B, H, H, dz2, H, (const uint16_t *)net->h1b.as<uint16_t>(),
+                       H, gW2);
+  hipLaunchKernelGGL(k_grad_b, dim3(1), dim3(128), 0, s, B, H, dz2, H, gb2);
+  if (f32)
+    hipLaunchKernelGGL((k_grad_x<float>), dim3((B + 15) / 16, H / 16), dim3(256), 0,
+                       s, B, H, H, dz2, H, W2, H, h1f, H, net->dz1.as<float>(), H);
+  else
+    hipLaunchKernelGGL((k_grad_x<uint16_t>), dim3((B + 15) / 16, H / 16),
+                       dim3(256), 0, s, B, H, H, dz2, H,
+                       (const uint16_t *)net->W2b.as<uint16_t>(), H, h1f, H,
+                       net->dz1.as<float>(), H);
+  // layer 1 (the input X is BF16 in both precisions)
   hipLaunchKernelGGL((k_grad_w<uint16_t>),
                      dim3(H / 16, (net->n_in + 15) / 16), dim3(256), 0, s, B, H,
-                     net->n_in, net->dz1.as<float>(), H, X, ldx, gW1);
-  hipLaunchKernelGGL(k_grad_b, dim3(1), dim3(128), 0, s, B, H,
-                     net->dz1.as<float>(), H, gb1);
+                     net->n_in, dz1, H, X, ldx, gW1);
+  hipLaunchKernelGGL(k_grad_b, dim3(1), dim3(128), 0, s, B, H, dz1, H, gb1);
   hipLaunchKernelGGL(k_sum_losses, dim3(1), dim3(256), 0, s, B,
                      net->lossp.as<double>(), count, net->lossd.as<double>());
   SEM_HIP(hipGetLastError());
@@ -516,29 +517,6 @@ static double mlp_backward(sem_mlp *net, const uint16_t *X, int ldx, int B,
                          hipMemcpyDeviceToHost, s));
   SEM_HIP(hipStreamSynchronize(s));
   return *net->host_loss;
-}
-
-double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
-                     int B, int N, bool host_loss, hipStream_t s) {
-  if (N < 1 || N > 16) fail(SEM_ERR_ARG, "mlp_loss_grad: N must be in 1..16");
-  const int nn = (N + 1) * (N + 1) * (N + 1);
-  const bool q1 = net->n_out == 8 && net->n_in == nn + 8;
-  ensure_scratch(net, B);  // before net->of is read below
-  const int wo = net->n_out > 16 ? net->n_out : 16;
-  mlp_forward(net, X, ldx, B, net->of.as<float>(), wo, true, s, nullptr, nullptr);
-  if (q1) {
-    XiParams xp{};
-    xp.n1 = N + 1;
-    RefElem r = make_ref_elem(N);
-    for (int q = 0; q <= N; ++q) xp.xi[q] = (float)r.xi[q];
-    hipLaunchKernelGGL(k_loss, dim3(B), dim3(256), 0, s, B, net->of.as<float>(),
-                       wo, T, xp, net->dO.as<float>(), wo, net->lossp.as<double>());
-  } else {
-    hipLaunchKernelGGL(k_loss_id, dim3(B), dim3(256), 0, s, B, net->n_out,
-                       net->of.as<float>(), wo, T, net->dO.as<float>(), wo,
-                       net->lossp.as<double>());
-  }
-  return mlp_backward(net, X, ldx, B, q1 ? nn : net->n_out, host_loss, s);
 }
 
 // loss and gradient of the coarse-operator factor (n_out = K(K+1)/2,
@@ -551,7 +529,7 @@ double mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X, int ldx,
                       "n_out = K(K+1)/2");
   ensure_scratch(net, B);
   const int wo = net->n_out > 16 ? net->n_out : 16;
-  mlp_forward(net, X, ldx, B, net->of.as<float>(), wo, true, s, nullptr, nullptr);
+  mlp_forward(net, X, ldx, B, net->of.as<float>(), wo, s);
   const dim3 g((unsigned)((B + 63) / 64)), t(64);
   if (K == 1)
     hipLaunchKernelGGL(k_loss_factor<1>, g, t, 0, s, B, net->of.as<float>(), wo, T,
@@ -566,6 +544,16 @@ double mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X, int ldx,
 }
 
 uint64_t mlp_version(const sem_mlp *net) { return net->version; }
+
+void mlp_set_precision(sem_mlp *net, int prec) {
+  if (prec != SEM_BF16 && prec != SEM_FP32)
+    fail(SEM_ERR_ARG, "mlp_set_precision: SEM_BF16 or SEM_FP32");
+  SEM_HIP(hipDeviceSynchronize());  // no forward pass may be in flight
+  net->prec = prec;
+  net->version += 1;  // outputs derived from the network must be recomputed
+}
+
+int mlp_precision(const sem_mlp *net) { return net->prec; }
 
 void mlp_adam(sem_mlp *net, const float *grad, double lr, double b1, double b2,
               double eps, hipStream_t s) {

@@ -51,6 +51,7 @@ struct HostMaps {
   // gather-scatter work lists
   std::vector<int32_t> masked_lids;         // every local copy of a Dirichlet node
   std::vector<int32_t> seg_off, seg_ids;    // shared, non-Dirichlet nodes
+  std::vector<int32_t> solo_lids;           // single-copy, non-Dirichlet nodes
 };
 HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet);
 
@@ -132,12 +133,12 @@ struct Learn;      // learned-correction buffers (learn.hip)
 
 struct sem_handle {
   int N = 0, n1 = 0, ex = 0, ey = 0, ez = 0, dirichlet = 0, mapping = 0;
-  int64_t E = 0, nL = 0, nG = 0, n_masked = 0, n_seg = 0;
+  int64_t E = 0, nL = 0, nG = 0, n_masked = 0, n_seg = 0, n_solo = 0;
   sem::RefElem ref;
 
   // maps
   sem::DevBuf l2g, perm, offsets, mult, bmask, gmask, masked_lids, seg_off,
-      seg_ids;
+      seg_ids, solo_lids;
   // reference element on device
   sem::DevBuf D64, D32, D16hi, D16lo;  // D16hi + D16lo: BF16 split of D
   // geometry and preconditioner
@@ -180,6 +181,9 @@ void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *s
                      const AxItem *items, int nitems, int epb, int grid, int src,
                      int dst, int skip_done, hipStream_t s);
 int bax_elements_per_tile(int bs, int n1);
+// smallest workgroup (64, 128, 256) holding every (i, j) column of the
+// largest order of an order set
+int bax_min_block(int nset);
 // DG volume term (dg.hip)
 void dg_device_setup(dg_handle *h, int64_t nv, const double *vx, const double *vy,
                      const int32_t *etov, const double *B, hipStream_t s);
@@ -208,14 +212,13 @@ void mlp_info(const sem_mlp *net, int *n_in, int *H, int *n_out, int64_t *np,
 int mlp_padded_inputs(const sem_mlp *net);
 void mlp_refresh(sem_mlp *net, hipStream_t s);
 void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
-                 int ldo, bool train, hipStream_t s, uint16_t *h1x = nullptr,
-                 uint16_t *h2x = nullptr);
+                 int ldo, hipStream_t s);
+void mlp_set_precision(sem_mlp *net, int prec);
+int mlp_precision(const sem_mlp *net);
 double mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X, int ldx,
                             const float *T, int K, int B, bool host_loss,
                             hipStream_t s);
 uint64_t mlp_version(const sem_mlp *net);
-double mlp_loss_grad(sem_mlp *net, const uint16_t *X, int ldx, const float *T,
-                     int B, int N, bool host_loss, hipStream_t s);
 void mlp_adam(sem_mlp *net, const float *grad, double lr, double b1, double b2,
               double eps, hipStream_t s);
 void mlp_save(const sem_mlp *net, const char *path);
@@ -228,14 +231,13 @@ const float *mlp_damping_dev(const sem_mlp *net);
 // learned correction on a mesh (learn.hip)
 void learn_attach(sem_handle *h, sem_mlp *net);
 void learn_destroy(sem_handle *h);
-// one application c = correction(r) for the batch's single solve: features
-// of r (vector index `rv` of precision set `f32`), network, prolongation
-// into the E-vector cL
-void learn_apply(sem_handle *h, const void *r, bool f32, float *cL,
-                 hipStream_t s);
-void learn_interior_pairs(sem_handle *h, const double *rL, const int32_t *elems,
-                          int n, uint16_t *X, int ldx, float *T, double rtol,
-                          int32_t *iters, hipStream_t s);
+// one application c = damping B M_e B^T r_I for the batch's single solve
+// (r a unique-node vector, FP32 when f32), into the unique-node correction
+void learn_apply(sem_handle *h, const void *r, bool f32, hipStream_t s);
+void learn_attach_exact(sem_handle *h, double damping);
+bool learn_active(const sem_handle *h);
+double learn_damping(const sem_handle *h);
+double learn_ref_rate(const sem_handle *h);
 void learn_refresh(sem_handle *h);
 int learn_coarse_exact(sem_handle *h, double *M, hipStream_t s);
 void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,

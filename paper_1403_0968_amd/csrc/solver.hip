@@ -425,16 +425,15 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
-// z = dinv r + c with c the correction on unique nodes (cG, when the layout
-// provides it) or the average over the copies of the element corrections
-// cL; partials (r, z), (z, w), (r, r).  skip_done = 0 during initialisation.
+// z = dinv r + c with c the coarse correction on unique nodes (cG); partials
+// (r, z), (z, w), (r, r).  skip_done = 0 during initialisation.
 template <class TV, class TD>
 __global__ void __launch_bounds__(RT)
     k_bprec_learned(const BatchSolve *__restrict__ sds,
                     const CgState *__restrict__ st,
                     const VecItem *__restrict__ items, int nitems,
-                    const float *__restrict__ cL, const float *__restrict__ cG,
-                    double *__restrict__ part, int skip_done) {
+                    const float *__restrict__ cG, double *__restrict__ part,
+                    int skip_done) {
   __shared__ double sm[RT / 64];
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
@@ -447,20 +446,8 @@ __global__ void __launch_bounds__(RT)
     double rz = 0.0, zw = 0.0, rr = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
       const TV rv = r[g];
-      TV zv;
-      if (cG) {  // dinv is 0 on the Dirichlet boundary, where cG is 0 too
-        zv = (TV)(dinv[g] * rv) + (TV)cG[g];
-      } else {
-        const NodeCopies nc = node_copies(sd.box, (uint32_t)g);
-        float c = 0.f;
-        if (!nc.masked)
-          for (int a = 0; a < nc.z.cnt; ++a)
-            for (int b = 0; b < nc.y.cnt; ++b)
-              for (int cc = 0; cc < nc.x.cnt; ++cc)
-                c += cL[copy_lid(sd.box, nc, a, b, cc)];
-        const float mult = (float)(nc.x.cnt * nc.y.cnt * nc.z.cnt);
-        zv = nc.masked ? TV(0) : (TV)(dinv[g] * rv) + (TV)(c / mult);
-      }
+      // dinv is 0 on the Dirichlet boundary, where cG is 0 too
+      const TV zv = (TV)(dinv[g] * rv) + (TV)cG[g];
       z[g] = zv;
       rz += (double)rv * (double)zv;
       zw += (double)zv * (double)w[g];
@@ -668,6 +655,8 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
     b->hs.assign(hs, hs + n);
     b->n = n;
     b->nset = nset;
+    // default operator block sizes hold every column of an element
+    for (int &x : b->bs) x = std::max(x, bax_min_block(nset));
     std::vector<BatchSolve> sds(n);
     std::vector<VecItem> vis;
     std::vector<int32_t> vbeg(n + 1);
@@ -822,7 +811,6 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   SEM_HIP(hipGetLastError());
 }
 
-float *learn_cl(sem_handle *h);
 float *learn_cg(sem_handle *h);
 
 template <class TV, class TD>
@@ -841,10 +829,9 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
   hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
   hipLaunchKernelGGL((k_bupdate_xr_only<TV>), dim3(g), dim3(RT), 0, b->s, sds, st,
                      vi, nv);
-  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, learn_cl(h),
-              b->s);
+  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, b->s);
   hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
-                     st, vi, nv, learn_cl(h), learn_cg(h), part, 1);
+                     st, vi, nv, learn_cg(h), part, 1);
   hipLaunchKernelGGL(k_bbeta_fcg, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
   hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
                      nv);
@@ -876,13 +863,13 @@ static void init_fcg(sem_batch *b, int prec) {
   const int g = vec_grid(b), nv = b->n_vi;
   sem_handle *h = b->hs[0];
   const bool f32 = prec != SEM_FP64;
-  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, learn_cl(h), b->s);
+  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, b->s);
   if (f32) {
     hipLaunchKernelGGL((k_bprec_learned<float, float>), dim3(g), dim3(RT), 0, b->s,
-                       sds, st, vi, nv, learn_cl(h), learn_cg(h), part, 0);
+                       sds, st, vi, nv, learn_cg(h), part, 0);
   } else {
     hipLaunchKernelGGL((k_bprec_learned<double, double>), dim3(g), dim3(RT), 0,
-                       b->s, sds, st, vi, nv, learn_cl(h), learn_cg(h), part, 0);
+                       b->s, sds, st, vi, nv, learn_cg(h), part, 0);
   }
   hipLaunchKernelGGL(k_bfcg_start, dim3(b->n), dim3(RT), 0, b->s, st, part,
                      b->vbeg.as<int32_t>());
@@ -1085,10 +1072,10 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
   int fell_back = 0;
   if (learned) {
     if (n != 1) fail(SEM_ERR_ARG, "solve: the learned preconditioner needs a single solve");
-    if (b->hs[0]->net == nullptr)
+    if (!learn_active(b->hs[0]))
       fail(SEM_ERR_STATE, "solve: no network attached (sem_learn_attach)");
     learn_refresh(b->hs[0]);
-    if (mlp_damping(b->hs[0]->net) == 0.0) {
+    if (learn_damping(b->hs[0]) == 0.0) {
       // validation found no gain over Jacobi: the correction is disabled
       learned = false;
       fell_back = 1;
@@ -1100,7 +1087,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
     bool stagnated = false;
     if (learned) {
       init_fcg(b, SEM_FP64);
-      stagnated = run_cg(b, SEM_FP64, 1, o, 1, true, mlp_ref_rate(b->hs[0]->net));
+      stagnated = run_cg(b, SEM_FP64, 1, o, 1, true, learn_ref_rate(b->hs[0]));
     } else {
       run_cg(b, SEM_FP64, jac, o);
     }
@@ -1188,7 +1175,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
         init(b, prec, 1, true, o->inner_rtol * o->inner_rtol);
         init_fcg(b, prec);
         const bool stag =
-            run_cg(b, prec, 1, o, 1, true, mlp_ref_rate(b->hs[0]->net));
+            run_cg(b, prec, 1, o, 1, true, learn_ref_rate(b->hs[0]));
         bad = stag || b->host_st[0].done == 2;
         iters[0] += b->host_st[0].it;
         if (bad) {
@@ -1390,7 +1377,8 @@ void batch_tune(sem_batch *b, int prec, int *best_bs, int *best_gm,
   if (path) {
     auto m = read_cache(path);
     auto it = m.find(key);
-    if (it != m.end()) {
+    // an entry whose block cannot hold an element of this set is ignored
+    if (it != m.end() && it->second.first >= bax_min_block(b->nset)) {
       b->bs[prec] = it->second.first;
       b->gmul[prec] = it->second.second;
       if (best_bs) *best_bs = b->bs[prec];
@@ -1407,6 +1395,7 @@ void batch_tune(sem_batch *b, int prec, int *best_bs, int *best_gm,
   double best = 1e300;
   int bbs = b->bs[prec], bgm = b->gmul[prec];
   for (int bs : bss) {
+    if (bs < bax_min_block(b->nset)) continue;  // cannot hold an element
     for (int gm : gms) {
       b->bs[prec] = bs;
       b->gmul[prec] = gm;

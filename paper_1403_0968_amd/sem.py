@@ -29,9 +29,10 @@ EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_batch_create", "sem_batch_destroy", "sem_batch_tune",
             "sem_batch_pcg_solve", "sem_mlp_create", "sem_mlp_destroy",
             "sem_mlp_info", "sem_mlp_get_params", "sem_mlp_set_params",
-            "sem_mlp_forward", "sem_mlp_loss_grad", "sem_mlp_adam",
-            "sem_mlp_set_damping", "sem_mlp_get_damping", "sem_mlp_save", "sem_mlp_load", "sem_learn_attach",
-            "sem_learn_train", "sem_learn_interior_pairs",
+            "sem_mlp_set_precision", "sem_mlp_get_precision",
+            "sem_mlp_forward", "sem_mlp_adam", "sem_mlp_set_damping",
+            "sem_mlp_get_damping", "sem_mlp_save", "sem_mlp_load",
+            "sem_learn_attach", "sem_learn_attach_exact", "sem_learn_train",
             "sem_learn_coarse_exact", "sem_mlp_loss_grad_factor",
             "fd2d_weights", "fd2d_step", "fd2d_run", "dg_reference_nodes",
             "dg_setup", "dg_destroy", "dg_query", "dg_export", "dg_volume",
@@ -71,7 +72,7 @@ class sem_train_opts(C.Structure):
 
 class sem_train_report(C.Structure):
     _fields_ = [("pairs", C.c_int32), ("epochs", C.c_int32),
-                ("snapshots", C.c_int32), ("local_iters_max", C.c_int32),
+                ("snapshots", C.c_int32), ("reserved", C.c_int32),
                 ("first_loss", C.c_double), ("last_loss", C.c_double),
                 ("data_seconds", C.c_double), ("train_seconds", C.c_double),
                 ("validate_seconds", C.c_double), ("damping", C.c_double),
@@ -129,8 +130,8 @@ def lib():
     L.sem_mlp_get_params.argtypes = [vp, vp, i64]
     L.sem_mlp_set_params.argtypes = [vp, vp, i64]
     L.sem_mlp_forward.argtypes = [vp, vp, i32, i32, vp, vp]
-    L.sem_mlp_loss_grad.argtypes = [vp, vp, i32, vp, i32, i32, vp,
-                                    C.POINTER(C.c_double), vp]
+    L.sem_mlp_set_precision.argtypes = [vp, i32]
+    L.sem_mlp_get_precision.argtypes = [vp, C.POINTER(i32)]
     L.sem_mlp_loss_grad_factor.argtypes = [vp, vp, i32, vp, i32, i32, vp,
                                            C.POINTER(C.c_double), vp]
     L.sem_learn_coarse_exact.argtypes = [vp, vp, C.POINTER(i32), vp]
@@ -142,8 +143,7 @@ def lib():
     L.sem_mlp_save.argtypes = [vp, C.c_char_p]
     L.sem_mlp_load.argtypes = [C.c_char_p, C.POINTER(vp)]
     L.sem_learn_attach.argtypes = [vp, vp]
-    L.sem_learn_interior_pairs.argtypes = [vp, vp, vp, i32, vp, i32, vp,
-                                           C.c_double, vp, vp]
+    L.sem_learn_attach_exact.argtypes = [vp, C.c_double]
     L.sem_learn_train.argtypes = [vp, vp, C.POINTER(vp), i32,
                                   C.POINTER(sem_train_opts),
                                   C.POINTER(sem_train_report), vp]
@@ -387,12 +387,14 @@ def sem_mlp_forward(net, X, ldx, B, Y, stream=None):
                                  _stream(stream)))
 
 
-def sem_mlp_loss_grad(net, X, ldx, T, B, N, grad=None, stream=None):
-    loss = C.c_double()
-    _check(lib().sem_mlp_loss_grad(net, _ptr(X), int(ldx), _ptr(T), int(B),
-                                   int(N), _ptr(grad), C.byref(loss),
-                                   _stream(stream)))
-    return loss.value
+def sem_mlp_set_precision(net, p):
+    _check(lib().sem_mlp_set_precision(net, int(p)))
+
+
+def sem_mlp_get_precision(net):
+    p = C.c_int32()
+    _check(lib().sem_mlp_get_precision(net, C.byref(p)))
+    return p.value
 
 
 def sem_mlp_loss_grad_factor(net, X, ldx, T, K, B, grad=None, stream=None):
@@ -451,21 +453,13 @@ def sem_learn_train(h, net, bs, n_pairs=20000, snapshot_every=16,
     _check(lib().sem_learn_train(h, net, arr, len(bs), C.byref(o), C.byref(rep),
                                  _stream(stream)))
     out = {k: getattr(rep, k) for k, _ in sem_train_report._fields_
-           if k != "val_iters"}
+           if k not in ("val_iters", "reserved")}
     out["val_iters"] = list(rep.val_iters)
     return out
 
 
-def sem_learn_interior_pairs(h, r, elems, X, T, rtol=1e-10, iters=None,
-                             stream=None):
-    """r: device FP64 E-vector; elems: device int32 [n]; X: device int16
-    [n][ldx] (BF16 bits); T: device FP32 [n][(N-1)^3]; iters: device int32
-    [n] or None."""
-    n = int(elems.shape[0])
-    _check(lib().sem_learn_interior_pairs(
-        h, _ptr(r), _ptr(elems), n, _ptr(X), int(X.shape[1]), _ptr(T),
-        float(rtol), _ptr(iters) if iters is not None else None,
-        _stream(stream)))
+def sem_learn_attach_exact(h, damping=1.0):
+    _check(lib().sem_learn_attach_exact(h, float(damping)))
 
 
 def sem_last_error():

@@ -96,3 +96,32 @@ def test_dg_reference_nodes_host_logic():
         np.testing.assert_allclose(np.array(list(s)), so, rtol=0, atol=2e-15)
     buf = (ctypes.c_double * 64)()
     assert lib.dg_reference_nodes(9, buf, buf) == 1
+
+
+def declaration_comments():
+    """(name, comment text) for every function declared in include/*.h: the
+    text between the previous declaration (or the header start) and it."""
+    out = []
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        text = open(h).read()
+        prev = 0
+        pat = re.compile(
+            r"^\s*(?:const\s+)?\w+\s*\*?\s*((?:sem|fd2d|dg)_\w+)\s*\([^;]*;",
+            flags=re.M)
+        for m in pat.finditer(text):
+            block = text[prev:m.start()]
+            out.append((m.group(1), " ".join(re.findall(r"/\*(.*?)\*/", block,
+                                                        flags=re.S))))
+            prev = m.end()
+    return out
+
+
+def test_every_entry_point_cites_its_passage():
+    """Each exported call's own comment names the section of the paper whose
+    operation (or, for the library's own additions, whose open slot) it
+    implements."""
+    decls = declaration_comments()
+    assert len(decls) == len(declared_functions())
+    for name, comment in decls:
+        assert re.search(r"section \d(\.\d)*", comment), \
+            f"{name}: its comment cites no section of the paper"

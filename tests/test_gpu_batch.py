@@ -131,3 +131,63 @@ def test_batch_config_generator_is_uneven():
     ns = [n for n, _ in cfg]
     Ns = [N for _, N in cfg]
     assert min(ns) >= 6 and max(ns) <= 24 and set(Ns) == {3, 5, 7}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_order8_block_holds_an_element(sem, prec, tmp_path):
+    """N = 8 has 81 (i, j) columns per element, one thread each: a batch of
+    order-8 solves never runs the batched operator with 64-thread
+    workgroups, whether from its defaults, the tuner's candidates or a
+    cache entry that asks for them; its solves equal the single solves bit
+    for bit and agree with the oracle."""
+    print(f"[gpu] batch of order-8 solves, inner {prec}", flush=True)
+    t = torch()
+    p = {"fp64": sem.SEM_FP64, "fp32": sem.SEM_FP32}[prec]
+    sizes = [(2, 2, 2), (3, 2, 2)]
+    hs, bs = [], []
+    for q, (ex, ey, ez) in enumerate(sizes):
+        h = sem.sem_setup(8, ex, ey, ez, mapping=sem.SEM_MAP_SINE_CYCLIC)
+        _, nL, _ = sem.sem_query(h)
+        b = t.empty(nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, fourier_modes(seed=1100 + q))
+        hs.append(h)
+        bs.append(b)
+    bt = sem.sem_batch_create(hs)
+    path = str(tmp_path / "tune8.json")
+    os.environ["SEM_AUTOTUNE_CACHE"] = path
+    try:
+        kw = dict(rtol=1e-10, maxit=4000, inner_prec=p, inner_rtol=1e-2,
+                  check_every=8)
+        # defaults first, then a cache entry rewritten to 64 threads
+        for stage in ("default", "cache64"):
+            if stage == "cache64":
+                b1, g1, _ = sem.sem_batch_tune(bt, p)
+                assert b1 >= 128
+                text = open(path).read().replace(f"[{b1}, {g1}]", "[64, 0]")
+                open(path, "w").write(text)
+                b2, g2, us2 = sem.sem_batch_tune(bt, p)
+                assert b2 >= 128 and us2 > 0, (b2, g2, us2)
+            xs = [t.zeros_like(b) for b in bs]
+            code, stats = sem.sem_batch_pcg_solve(bt, bs, xs, **kw)
+            t.cuda.synchronize()
+            assert code == 0, stats
+            for q, (h, b) in enumerate(zip(hs, bs)):
+                x1 = t.zeros_like(b)
+                st1 = sem.sem_pcg_solve(h, b, x1, **kw)
+                t.cuda.synchronize()
+                assert stats[q]["iters"] == st1["iters"], (stage, q)
+                assert t.equal(xs[q], x1), (stage, q)
+        for q, (ex, ey, ez) in enumerate(sizes):
+            m = orc.mesh(8, ex, ey, ez, orc.MAP_SINE_CYCLIC)
+            k, a, phi = fourier_modes(seed=1100 + q)
+            bo = orc.to_global(m, orc.rhs_local(m, orc.src_fourier(m.X, k, a, phi)))
+            xo, _, _, _ = orc.pcg(m, bo, 1e-12, 5000)
+            rel = (np.linalg.norm(orc.to_global(m, to_host(xs[q])) - xo)
+                   / np.linalg.norm(xo))
+            print(f"[batch N=8 solve {q}] rel err {rel:.2e}")
+            assert rel <= 1e-7
+    finally:
+        del os.environ["SEM_AUTOTUNE_CACHE"]
+        sem.sem_batch_destroy(bt)
+        for h in hs:
+            sem.sem_destroy(h)

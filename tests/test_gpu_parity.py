@@ -139,6 +139,10 @@ def test_gs_bit_exact(sem, pair):
     t = torch()
     rng = np.random.default_rng(5)
     v = rng.choice([1e16, -1e16, 1.0, 3.0, -7.0, 0.1], size=m.nL) + uniform(m.nL, 6)
+    # negative zeros, on single-copy and on shared nodes: every sum starts
+    # from +0.0, so the result holds +0.0 wherever all copies are -0.0
+    v[::5] = -0.0
+    v[m.perm[m.offsets[m.l2g[m.nL // 2]]:m.offsets[m.l2g[m.nL // 2] + 1]]] = -0.0
     vd = to_dev(v)
     sem.sem_gs(pair.h, sem.SEM_FP64, vd)
     t.cuda.synchronize()

@@ -1,8 +1,13 @@
-"""Pins of the oracle's interior layout of the learned correction: the
-element-interior node list, the dense element-interior solve against the
-sum-factorised operator (an independent code path), the target's closed
-form on a known solution, and the reading that the exact element-interior
-block solve converges in fewer flexible-CG iterations than Jacobi."""
+"""Pins of the oracle's learned coarse correction: the element-interior
+node list, the bubble basis against its closed form and the reference
+scaling, the Galerkin coarse matrix from the dense element matrix against
+the sum-factorised operator (an independent code path), the factor loss and
+its backpropagation against central differences, the normalised coarse
+target and the correction against what they must reproduce (coarse-space
+solutions exactly, Galerkin orthogonality, zero face values, invariance of
+the normalised inverse under scaling of kappa and of the element), and the
+reading behind the layout: the exact element coarse correction needs
+clearly fewer flexible-CG iterations than Jacobi."""
 import numpy as np
 import pytest
 
@@ -27,76 +32,6 @@ def test_interior_nodes(N):
 def _curved_mesh(N, n=2):
     kap = grf_features(seed=3, M=256, ell=0.5, sigma=0.7)
     return orc.mesh(N, n, n, n, orc.MAP_SINE_CYCLIC, 1, kap)
-
-
-@pytest.mark.parametrize("N", [2, 4, 7])
-def test_interior_solve_against_operator(N):
-    m = _curved_mesh(N)
-    n3 = m.n1 ** 3
-    I = mlp.interior_nodes(N)
-    for e in (0, m.E - 1):
-        A_e = orc.brute_element_matrix(N, m.xi, m.G[e])
-        r_e = uniform(n3, seed=10 + e)
-        d = mlp.interior_solve(A_e, r_e, N)
-        u = np.zeros(n3)
-        u[I] = d
-        w = orc.ax_raw(N, m.D, m.G[e:e + 1], u)
-        err = np.max(np.abs(w[I] - r_e[I])) / np.max(np.abs(r_e[I]))
-        assert err < 1e-10
-
-
-def test_interior_target_known_solution():
-    N = 5
-    m = _curved_mesh(N)
-    n3 = m.n1 ** 3
-    I = mlp.interior_nodes(N)
-    e = 3
-    A_e = orc.brute_element_matrix(N, m.xi, m.G[e])
-    v = uniform(I.shape[0], seed=4)
-    r_e = uniform(n3, seed=5)          # face values do not enter
-    r_e[I] = A_e[np.ix_(I, I)] @ v
-    dinv_e = 1.0 / np.abs(uniform(n3, seed=6) + 2.0)
-    kv = np.array([1.0, 2.0, 0.5, 1.5, 1.0, 1.0, 3.0, 0.25])
-    h = 0.5
-    s = np.linalg.norm(r_e[I])
-    t = mlp.interior_target(A_e, r_e, dinv_e, kv, h, N)
-    want = (v - dinv_e[I] * r_e[I]) * kv.mean() * h / s
-    assert np.max(np.abs(t - want)) < 1e-9 * np.max(np.abs(want))
-    # the correction undoes the scaling: dinv r + c = d on the interior
-    c = mlp.interior_correction(t, s, kv, h, N)
-    assert np.max(np.abs(dinv_e[I] * r_e[I] + c[I] - v)) < 1e-9 * np.max(np.abs(v))
-    assert np.all(c[np.setdiff1d(np.arange(n3), I)] == 0.0)
-    x, s2 = mlp.interior_features(r_e, kv, N)
-    assert s2 == s and np.allclose(x[:I.shape[0]] * s, r_e[I], rtol=0, atol=1e-14 * s)
-    assert np.allclose(x[I.shape[0]:], np.log(kv) - np.log(kv).mean())
-
-
-def test_exact_interior_block_beats_jacobi():
-    """The reading behind the interior layout: a perfect network reproduces
-    the element-interior block solve, which needs clearly fewer flexible-CG
-    iterations than Jacobi-PCG on a variable-coefficient problem."""
-    N, n = 5, 3
-    kap = grf_features(seed=7, M=512, ell=0.6, sigma=1.0)
-    m = orc.mesh(N, n, n, n, orc.MAP_AFFINE, 1, kap)
-    n3 = m.n1 ** 3
-    I = mlp.interior_nodes(N)
-    k, a, phi = fourier_modes(seed=900)
-    b = orc.to_global(m, orc.rhs_local(m, orc.src_fourier(m.X, k, a, phi)))
-    dinv = orc.jacobi_dinv_global(m)
-    AII = [np.linalg.inv(orc.brute_element_matrix(N, m.xi, m.G[e])[np.ix_(I, I)])
-           for e in range(m.E)]
-    gI = [m.l2g[e * n3 + I] for e in range(m.E)]
-
-    def block(r):
-        z = dinv * r
-        for e in range(m.E):
-            z[gI[e]] = AII[e] @ r[gI[e]]
-        return z
-
-    _, st_j, it_j, _ = orc.pcg(m, b, 1e-8, 5000)
-    _, st_b, it_b, _ = orc.fcg(m, b, block, 1e-8, 5000)
-    assert st_j == 0 and st_b == 0
-    assert it_b < 0.8 * it_j, (it_b, it_j)
 
 
 # ---------------------------------------------------------------------------
@@ -218,3 +153,82 @@ def test_factor_network_gradient_matches_central_differences():
         fd[q] = (mlp.factor_net_loss_and_grad(tp, X, Y, A, nin, nh, K)[0]
                  - mlp.factor_net_loss_and_grad(tm, X, Y, A, nin, nh, K)[0]) / (2 * hh)
     assert np.max(np.abs(fd - g)) <= 1e-7 * max(1.0, np.max(np.abs(g)))
+
+
+def _vertex_kappa(m, e):
+    n1, N, n3 = m.n1, m.N, m.n1 ** 3
+    return np.array([m.kappa[e * n3 + (v & 1) * N + n1 * ((v >> 1) & 1) * N
+                             + n1 * n1 * (v >> 2) * N] for v in range(8)])
+
+
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_coarse_correction_reproduces_coarse_space_solutions(N):
+    """If the element-interior solution of A_II d = r_I lies in the coarse
+    space (d = B y), the exact coarse correction returns it: c_I = B y, zero
+    on the faces.  The kappa_mean h of the target and the 1 / (kappa_mean h)
+    of the correction cancel for any vertex values and element size; a
+    swapped B / B^T, a dropped factor or a wrong index fails this."""
+    m = _curved_mesh(N)
+    n3 = m.n1 ** 3
+    I = mlp.interior_nodes(N)
+    B = mlp.bubble_basis(N, m.xi)
+    rng = np.random.default_rng(N)
+    for e in (0, m.E - 1):
+        A_e = orc.brute_element_matrix(N, m.xi, m.G[e])
+        A_II = A_e[np.ix_(I, I)]
+        y = rng.standard_normal(B.shape[1])
+        r_e = uniform(n3, seed=40 + e)     # face values must not enter
+        r_e[I] = A_II @ (B @ y)
+        kv = np.exp(rng.standard_normal(8))
+        h = 0.37
+        M = mlp.coarse_target(A_e, N, m.xi, kv, h)
+        c = mlp.coarse_correction(r_e, M, N, m.xi, kv, h)
+        faces = np.setdiff1d(np.arange(n3), I)
+        assert np.all(c[faces] == 0.0)
+        err = np.max(np.abs(c[I] - B @ y)) / np.max(np.abs(B @ y))
+        assert err <= 1e-10, err
+        # damping scales the correction
+        c2 = mlp.coarse_correction(r_e, M, N, m.xi, kv, h, damping=0.25)
+        np.testing.assert_allclose(c2, 0.25 * c, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_coarse_correction_galerkin_orthogonality(N):
+    """For any residual, c_I is in the coarse space and the interior
+    residual left by it is orthogonal to the coarse space:
+    B^T (r_I - A_II c_I) = 0 (the defining property of the Galerkin
+    projection of A_II^{-1} r_I onto span B)."""
+    m = _curved_mesh(N)
+    n3 = m.n1 ** 3
+    I = mlp.interior_nodes(N)
+    B0 = mlp.bubble_basis(N, m.xi, scaled=False)
+    e = 2
+    A_e = orc.brute_element_matrix(N, m.xi, m.G[e])
+    A_II = A_e[np.ix_(I, I)]
+    r_e = uniform(n3, seed=7)
+    kv = _vertex_kappa(m, e)
+    c = mlp.coarse_correction(r_e, mlp.coarse_target(A_e, N, m.xi, kv, 0.5),
+                              N, m.xi, kv, 0.5)
+    res = B0.T @ (r_e[I] - A_II @ c[I])
+    assert np.max(np.abs(res)) <= 1e-11 * np.max(np.abs(B0.T @ r_e[I]))
+    coef, *_ = np.linalg.lstsq(B0, c[I], rcond=None)
+    assert np.max(np.abs(B0 @ coef - c[I])) <= 1e-11 * np.max(np.abs(c[I]))
+
+
+@pytest.mark.parametrize("N", [2, 4, 7])
+def test_normalised_target_is_scale_invariant(N):
+    """On affine cube elements with constant kappa the stiffness is
+    kappa h times that of the unit reference cube, so the normalised
+    inverse kappa h G_e^{-1} equals the reference one for every kappa and
+    every element size -- and the reference has unit diagonal in the
+    scaled basis."""
+    ref = None
+    for n, kap in ((1, 1.0), (3, 1.0), (2, 7.5), (4, 0.2)):
+        m = orc.mesh(N, n, n, n, orc.MAP_AFFINE, 1, None)
+        e = m.E // 2
+        A_e = kap * orc.brute_element_matrix(N, m.xi, m.G[e])
+        M = mlp.coarse_target(A_e, N, m.xi, np.full(8, kap), 1.0 / n)
+        if ref is None:
+            ref = M
+            np.testing.assert_allclose(np.diag(M), 1.0, rtol=1e-11)
+        np.testing.assert_allclose(M, ref, rtol=1e-10, atol=1e-12)

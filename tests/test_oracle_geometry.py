@@ -102,3 +102,27 @@ def test_kappa_scales_flux_metric_not_mass():
     np.testing.assert_array_equal(B, base.B)
     np.testing.assert_allclose(
         G, base.G * kap.reshape(base.E, 1, -1), rtol=1e-15, atol=0)
+
+
+def test_kappa_field_has_the_squared_exponential_covariance():
+    """g = log kappa from orc_kappa_rff, over independent feature draws:
+    mean 0 and covariance sigma^2 exp(-|x - y|^2 / (2 l^2)) (random Fourier
+    features of that kernel, Rahimi & Recht 2007), within the sampling error
+    of the draws.  A wrong amplitude factor (sqrt(2 / M), sigma vs
+    sigma^2) or length scale moves some of these by far more."""
+    from seminputs import grf_features
+    ell, sigma, M, S = 0.3, 0.8, 64, 3000
+    x0 = np.array([0.4, 0.5, 0.6])
+    d = np.array([0.0, 0.5, 1.0, 2.0]) * ell
+    pts = np.stack([x0 + np.array([dd, 0.0, 0.0]) for dd in d])
+    X = np.ascontiguousarray(pts.T)            # [3][n] blocks
+    g = np.empty((S, len(d)))
+    for s in range(S):
+        om, b, sg = grf_features(seed=10_000 + s, M=M, ell=ell, sigma=sigma)
+        g[s] = np.log(orc.kappa_rff(X, om, b, sg))
+    mean = g.mean(0)
+    cov = (g * g[:, :1]).mean(0)               # E[g(x0) g(x0 + d e1)]
+    want = sigma ** 2 * np.exp(-d ** 2 / (2 * ell ** 2))
+    se = sigma ** 2 * np.sqrt(2.0 / S)         # standard error of a product mean
+    assert np.all(np.abs(mean) <= 5 * sigma / np.sqrt(S)), mean
+    assert np.all(np.abs(cov - want) <= 5 * se), (cov, want)
