@@ -134,6 +134,40 @@ def time_ax(sem, torch, h, prec, u, w, steps, warmup, min_warm_s=0.2):
     return e0.elapsed_time(e1) / steps  # ms per launch
 
 
+def launch_stats(torch, launch, n=200):
+    """Median, 10th and 90th percentile and mean of n single launches, each
+    bracketed by its own pair of HIP events on torch's current stream (the
+    stream the library launches on), in microseconds."""
+    s = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True),
+            torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for e0, e1 in evs:
+        e0.record(s)
+        launch()
+        e1.record(s)
+    torch.cuda.synchronize()
+    us = sorted(1e3 * e0.elapsed_time(e1) for e0, e1 in evs)
+    q = lambda f: us[min(n - 1, int(f * n))]
+    return {"launches": n, "median_us": q(0.5), "p10_us": q(0.1),
+            "p90_us": q(0.9), "mean_us": sum(us) / n}
+
+
+def host_cores():
+    """Physical cores of the host (distinct core/socket pairs of lscpu) and
+    the CPUs this process may run on."""
+    import subprocess
+    phys = None
+    try:
+        out = subprocess.run(["lscpu", "-p=CORE,SOCKET"], capture_output=True,
+                             text=True, timeout=10).stdout
+        pairs = {tuple(l.split(",")[:2]) for l in out.splitlines()
+                 if l and not l.startswith("#")}
+        phys = len(pairs) or None
+    except Exception:
+        phys = None
+    return {"physical_cores": phys, "cpus_available": len(os.sched_getaffinity(0))}
+
+
 def bench_order_sweep(sem, torch, steps, warmup, target_nodes=NE ** 3 * 512):
     """FP64 operator at N = 1..8 on cubic meshes of ~target_nodes local
     nodes; then the screened operator on the benchmark mesh."""
@@ -268,36 +302,183 @@ def bench_dg(sem, torch, steps):
     return out
 
 
-def bench_pcg(sem, torch, h, nL, nG, rtol=1e-8):
+# algorithmic bytes of one CG iteration per local node (operator: factors,
+# E-vector output written and read back by the assembling r update) and per
+# unique node (gathered p, r read and written, dinv, z written; x and p
+# updated from z and p), by the precision of the operator's factors
+ITER_BYTES = {"fp64": (48 + 8 + 8, 8 + 16 + 8 + 8 + 40),
+              "fp32": (24 + 4 + 4, 4 + 8 + 4 + 4 + 20),
+              "bf16": (12 + 4 + 4, 4 + 8 + 4 + 4 + 20)}
+
+
+def oracle_reference(name):
+    """The oracle's reference solution of a solve workload at sampled nodes
+    (tests/golden, written by a script that runs the oracle only)."""
+    import importlib.util
+    path = os.path.join(ROOT, "tests", "golden", "make_oracle_pcg_samples.py")
+    spec = importlib.util.spec_from_file_location("oracle_samples", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    if not os.path.exists(mod.path_of(name)):
+        return None
+    return mod.read(name)
+
+
+class SampledError:
+    """||x - x_oracle|| / ||x_oracle|| over the reference's sampled unique
+    nodes (one local copy of each read from the E-vector x)."""
+
+    def __init__(self, sem, torch, h, nL, nG, ref):
+        self.ref = ref
+        if ref is None:
+            return
+        hdr, idx, val = ref
+        off = torch.empty(nG + 1, dtype=torch.int32, device="cuda")
+        perm = torch.empty(nL, dtype=torch.int32, device="cuda")
+        sem.sem_export(h, sem.SEM_ARR_OFFSETS, off)
+        sem.sem_export(h, sem.SEM_ARR_PERM, perm)
+        g = torch.as_tensor(idx, device="cuda")
+        self.lid = perm[off[g].long()].long()
+        self.val = torch.as_tensor(val, device="cuda")
+
+    def __call__(self, x):
+        if self.ref is None:
+            return None
+        d = x[self.lid] - self.val
+        return float(torch_norm(d) / torch_norm(self.val))
+
+
+def torch_norm(t):
+    return (t * t).sum().sqrt()
+
+
+def bench_pcg(sem, torch, h, nL, nG):
+    """Config 2 and 3 solves on the benchmark mesh (RHS seed 0): time to
+    1e-8 of FP64 Jacobi-PCG and of FP64 refinement around each inner
+    operator; refinement to 1e-10 for every inner precision; FP32-only PCG
+    to 1e-6; per-iteration time against the iteration's algorithmic bytes;
+    every solution's error against the oracle's reference solution."""
     from seminputs import fourier_modes
     k, a, phi = fourier_modes(seed=0)
     b = torch.empty(nL, dtype=torch.float64, device="cuda")
     sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, (k, a, phi))
-    out = {}
-    for name, prec, reps in (("fp64_jacobi_pcg", sem.SEM_FP64, 2),
-                             ("fp32_ir_jacobi_pcg", sem.SEM_FP32, 2),
-                             ("bf16_ir_jacobi_pcg", sem.SEM_BF16, 2),
-                             ("bf16_mfma_ir_jacobi_pcg", sem.SEM_BF16_MFMA, 2),
-                             # BF16-rounded derivative matrix: expected to stall
-                             ("bf16_plain_d_ir_jacobi_pcg", sem.SEM_BF16_PLAIN_D, 1)):
+    ref = oracle_reference("pcg_32x32x32_N7_sinecyclic_fourier0")
+    err = SampledError(sem, torch, h, nL, nG, ref)
+    out = {"oracle_reference": None if ref is None else {
+        "rtol": 1e-12, "iters_1e-8": int(ref[0]["iters_1e-8"]),
+        "iters_1e-10": int(ref[0]["iters_1e-10"]),
+        "sampled_nodes": int(len(ref[1]))}}
+
+    def run(name, prec, rtol, reps, inner_rtol=1e-3, key="fp64"):
         best = None
-        for rep in range(reps):  # the first solve also instantiates graphs
+        for _ in range(reps):  # the first solve also instantiates graphs
             x = torch.zeros_like(b)
             st = sem.sem_pcg_solve(h, b, x, rtol=rtol, maxit=20000,
-                                   inner_prec=prec, inner_rtol=1e-3,
+                                   inner_prec=prec, inner_rtol=inner_rtol,
                                    check_every=32, use_graph=1,
                                    raise_on_fail=False)
             torch.cuda.synchronize()
-            if best is None or st["seconds"] < best["seconds"]:
-                best = st
-        out[name] = {"time_to_rtol_s": best["seconds"], "iters": best["iters"],
-                     "outer": best["outer_iters"],
-                     "outer_contraction": best["outer_contraction"],
-                     "final_rel_res_fp64": best["final_rel_res"],
-                     "status": best["status"],
-                     "gdofs": nG * best["iters"] / best["seconds"] / 1e9}
-        log(f"[pcg] {name}: {out[name]}")
-    out["rtol"] = rtol
+            if best is None or st["seconds"] < best[0]["seconds"]:
+                best = (st, x)
+        st, x = best
+        it = max(1, st["iters"])
+        us = st["seconds"] / it * 1e6
+        bl, bg = ITER_BYTES[key]
+        byts = bl * nL + bg * nG
+        o = {"rtol": rtol, "time_s": st["seconds"], "iters": st["iters"],
+             "outer": st["outer_iters"],
+             "outer_contraction": st["outer_contraction"],
+             "final_rel_res_fp64": st["final_rel_res"], "status": st["status"],
+             "gdofs": nG * st["iters"] / st["seconds"] / 1e9,
+             "us_per_iter": us, "alg_bytes_per_iter": byts,
+             "iter_frac_hbm": byts / (us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+             "rel_err_vs_oracle": err(x)}
+        out[name] = o
+        log(f"[pcg] {name}: {o}")
+
+    run("fp64_jacobi_pcg", sem.SEM_FP64, 1e-8, 2)
+    run("fp32_ir_jacobi_pcg", sem.SEM_FP32, 1e-8, 2, key="fp32")
+    run("bf16g_ir_jacobi_pcg", sem.SEM_BF16, 1e-8, 2, key="bf16")
+    run("bf16_mfma_ir_jacobi_pcg", sem.SEM_BF16_MFMA, 1e-8, 2, key="bf16")
+    # config 3: refinement to 1e-10 for every inner operator
+    run("fp64_jacobi_pcg_1e-10", sem.SEM_FP64, 1e-10, 1)
+    run("fp32_ir_1e-10", sem.SEM_FP32, 1e-10, 1, key="fp32")
+    run("bf16g_ir_1e-10", sem.SEM_BF16, 1e-10, 1, key="bf16")
+    run("bf16_mfma_ir_1e-10", sem.SEM_BF16_MFMA, 1e-10, 1, key="bf16")
+    # BF16-rounded derivative matrix: expected to stall (kept to show it)
+    run("bf16_plain_d_ir_1e-10", sem.SEM_BF16_PLAIN_D, 1e-10, 1, key="bf16")
+    # config 2: FP32-only PCG to 1e-6 (one refinement step whose inner solve
+    # goes to 1e-6), its FP64 true residual and its error
+    run("fp32_pcg_1e-6", sem.SEM_FP32, 1e-6, 2, inner_rtol=1e-6, key="fp32")
+    out["notes"] = ("bf16g: FP32 p gathered and FP32 vectors, BF16 geometric "
+                    "factors, FP32 derivative matrix (VALU); bf16_mfma: BF16 "
+                    "p, factors and fluxes on the matrix cores with the "
+                    "two-term BF16 split of D; rel_err_vs_oracle over the "
+                    "oracle reference's sampled unique nodes")
+    return out
+
+
+def bench_config1(sem, torch):
+    """Config 1: 4^3 affine elements, N = 4, f = 3 pi^2 sin sin sin,
+    Jacobi-PCG to 1e-10; microseconds per iteration with and without the
+    captured graph, and the nodal error against the exact solution."""
+    h = sem.sem_setup(4, 4, 4, 4, mapping=sem.SEM_MAP_AFFINE)
+    try:
+        E, nL, nG = sem.sem_query(h)
+        b = torch.empty(nL, dtype=torch.float64, device="cuda")
+        sem.sem_rhs(h, b, sem.SEM_SRC_SINE, None)
+        X = torch.empty(3 * nL, dtype=torch.float64, device="cuda")
+        sem.sem_export(h, sem.SEM_ARR_COORDS, X)
+        X = X.view(3, nL)
+        exact = (torch.sin(torch.pi * X[0]) * torch.sin(torch.pi * X[1])
+                 * torch.sin(torch.pi * X[2]))
+        out = {"mesh": "4^3 affine, N=4", "n_local": nL, "n_global": nG}
+        for graph in (1, 0):
+            best = None
+            for _ in range(3):
+                x = torch.zeros_like(b)
+                st = sem.sem_pcg_solve(h, b, x, rtol=1e-10, maxit=2000,
+                                       check_every=32, use_graph=graph)
+                torch.cuda.synchronize()
+                if best is None or st["seconds"] < best[0]["seconds"]:
+                    best = (st, x)
+            st, x = best
+            key = "graph" if graph else "no_graph"
+            out[key] = {"iters": st["iters"], "time_s": st["seconds"],
+                        "us_per_iter": st["seconds"] / max(1, st["iters"]) * 1e6,
+                        "max_nodal_error": float((x - exact).abs().max())}
+        log(f"[config1] {out}")
+        return out
+    finally:
+        sem.sem_destroy(h)
+
+
+def bench_gs(sem, torch, h, nL, n=200):
+    """sem_gs (FP64) on the benchmark mesh: per-launch statistics and the
+    algorithmic bytes of the gather-scatter lists (shared copies: id 4, read
+    8, write 8; single-copy nodes the same; Dirichlet copies: id 4, write 8;
+    segment offsets 4 per shared node)."""
+    mult = torch.empty(nL, dtype=torch.int32, device="cuda")
+    mask = torch.empty(nL, dtype=torch.uint8, device="cuda")
+    sem.sem_export(h, sem.SEM_ARR_MULT, mult)
+    sem.sem_export(h, sem.SEM_ARR_MASK, mask)
+    masked = int(mask.sum())
+    free = mask == 0
+    shared = int((free & (mult > 1)).sum())
+    solo = int((free & (mult == 1)).sum())
+    segs = int(((free & (mult > 1)).double() / mult.double()).sum().round())
+    byts = 20 * shared + 20 * solo + 12 * masked + 4 * segs
+    v = torch.rand(nL, dtype=torch.float64, device="cuda")
+    for _ in range(20):
+        sem.sem_gs(h, sem.SEM_FP64, v)
+    torch.cuda.synchronize()
+    stt = launch_stats(torch, lambda: sem.sem_gs(h, sem.SEM_FP64, v), n)
+    out = {"shared_copies": shared, "single_copies": solo,
+           "dirichlet_copies": masked, "shared_nodes": segs,
+           "alg_bytes": byts, **stt,
+           "alg_GBs_median": byts / (stt["median_us"] * 1e-6) / 1e9,
+           "frac_hbm_median": byts / (stt["median_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    log(f"[gs] {out}")
     return out
 
 
@@ -325,20 +506,30 @@ def bench_learned(sem, torch, n_test=5):
                               solve_rtol=1e-11, seed=1)
     log(f"[learned] trained: {rep}")
     del train
+    damping = sem.sem_mlp_get_damping(net)[0]
     sem.sem_mlp_set_damping(untrained, *sem.sem_mlp_get_damping(net))
+    # "exact": the exact element coarse inverses the network is trained to
+    # imitate, attached without a network (same damping)
     cases = [("fp64_jacobi_pcg", sem.SEM_PC_JACOBI, sem.SEM_FP64, net),
              ("fp64_fcg_learned", sem.SEM_PC_LEARNED, sem.SEM_FP64, net),
+             ("fp64_fcg_exact_coarse", sem.SEM_PC_LEARNED, sem.SEM_FP64, "exact"),
              ("fp32_ir_jacobi", sem.SEM_PC_JACOBI, sem.SEM_FP32, net),
              ("fp32_ir_learned", sem.SEM_PC_LEARNED, sem.SEM_FP32, net),
+             ("fp32_ir_exact_coarse", sem.SEM_PC_LEARNED, sem.SEM_FP32, "exact"),
              ("fp32_ir_untrained", sem.SEM_PC_LEARNED, sem.SEM_FP32, untrained)]
     out = {name: {"time_s": [], "iters": [], "fell_back": [], "final_rel_res": []}
            for name, *_ in cases}
+    ref = oracle_reference("learned_24x24x24_N7_grf7_fourier900")
+    err = SampledError(sem, torch, h, nL, nG, ref)
     diffs = []
     for seed in range(900, 900 + n_test):
         b = rhs(seed)
         xref = None
         for name, pc, prec, nw in cases:
-            sem.sem_learn_attach(h, nw)
+            if nw == "exact":
+                sem.sem_learn_attach_exact(h, damping)
+            else:
+                sem.sem_learn_attach(h, nw)
             for rep_i in range(2):  # the first solve captures graphs
                 x = torch.zeros_like(b)
                 st = sem.sem_pcg_solve(h, b, x, rtol=1e-8, maxit=50000, pc=pc,
@@ -350,6 +541,8 @@ def bench_learned(sem, torch, n_test=5):
             o["iters"].append(st["iters"])
             o["fell_back"].append(st["fell_back"])
             o["final_rel_res"].append(st["final_rel_res"])
+            if seed == 900 and ref is not None:
+                o["rel_err_vs_oracle_rhs900"] = err(x)
             if xref is None:
                 xref = x
             else:
@@ -366,6 +559,13 @@ def bench_learned(sem, torch, n_test=5):
         name: base / out[name]["median_time_s"] for name, *_ in cases}
     out["max_rel_diff_vs_fp64_jacobi_solution"] = max(diffs) if diffs else None
     out["train"] = rep
+    out["learned_vs_exact_coarse_iters"] = (
+        out["fp64_fcg_learned"]["median_iters"]
+        / max(1, out["fp64_fcg_exact_coarse"]["median_iters"]))
+    if ref is not None:
+        out["oracle_reference_rhs900"] = {
+            "rtol": 1e-12, "iters_1e-8": int(ref[0]["iters_1e-8"]),
+            "sampled_nodes": int(len(ref[1]))}
     out["workload"] = ("24^3 elements, N=7, affine, kappa=exp(GRF l=0.1 sigma=1, "
                        f"4096 RFF), {nL} local / {nG} unique nodes; coarse "
                        f"layout network 8-128-128-{K * (K + 1) // 2} (K={K} "
@@ -435,12 +635,17 @@ def bench_batch(sem, torch, count=256):
     return out
 
 
-def cpu_baseline(budget_s=15.0):
-    """Oracle operator on the first elements of the same mesh, all host
-    threads the oracle uses; repeated until about budget_s of CPU time."""
+def cpu_baseline(cores, budget_s=15.0):
+    """The FP64 oracle (test infrastructure, timed here as a reported
+    baseline only), as it stands, on the GPU machine's host:
+      * its operator on the first 2048 of the 32768 elements of the
+        benchmark mesh, all threads (value) and one thread;
+      * its Jacobi-PCG: config 1 solved to 1e-8 and 1e-10; configs 2 and 5
+        timed over a few iterations on the full meshes and extrapolated to
+        the oracle's own iteration counts (from its reference solutions)."""
     import numpy as np
     from oracle import oracle as orc
-    from seminputs import uniform
+    from seminputs import fourier_modes, grf_features, uniform
     E_s = 2048
     N = ORDER
     xi, wq = orc.gll(N)
@@ -448,26 +653,82 @@ def cpu_baseline(budget_s=15.0):
     X = orc.coords(N, NE, NE, NE, orc.MAP_SINE_CYCLIC, xi)
     n3 = (N + 1) ** 3
     Xs = np.ascontiguousarray(X[:, : E_s * n3])
+    del X
     G, _, _ = orc.geom(N, E_s, wq, D, Xs)
     u = uniform(E_s * n3, seed=0)
-    orc.ax_raw(N, D, G, u)  # warm
-    reps, t = 0, 0.0
-    t0 = time.perf_counter()
-    while t < budget_s:
-        orc.ax_raw(N, D, G, u)
-        reps += 1
-        t = time.perf_counter() - t0
-    nodes = reps * E_s * n3
-    return {"value": nodes / t / 1e9, "unit": "GDOF/s", "cores": orc.num_threads(),
-            "kind": "oracle",
-            "sample": f"FP64 oracle operator on the first {E_s} of the 32768 "
-                      f"elements of the same mesh, {reps} repetitions, {t:.1f} s"}
+    nthreads = orc.num_threads()
+
+    def time_ax(budget):
+        orc.ax_raw(N, D, G, u)  # warm
+        reps, t = 0, 0.0
+        t0 = time.perf_counter()
+        while t < budget:
+            orc.ax_raw(N, D, G, u)
+            reps += 1
+            t = time.perf_counter() - t0
+        return reps * E_s * n3 / t / 1e9, reps, t
+
+    gd, reps, t = time_ax(budget_s)
+    orc.set_num_threads(1)
+    gd1, reps1, t1 = time_ax(budget_s / 3)
+    orc.set_num_threads(nthreads)
+    out = {"value": gd, "unit": "GDOF/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"FP64 oracle operator on the first {E_s} of the 32768 "
+                     f"elements of the same mesh, {reps} repetitions, {t:.1f} s",
+           "host": cores,
+           "one_thread": {"value": gd1, "unit": "GDOF/s", "cores": 1,
+                          "sample": f"same, {reps1} repetitions, {t1:.1f} s"},
+           "alg_GBs": gd * 64, "alg_GBs_one_thread": gd1 * 64}
+    log(f"[cpu] operator {gd:.3f} GDOF/s ({nthreads} threads), "
+        f"{gd1:.3f} GDOF/s (1 thread)")
+
+    pcg = {}
+    # config 1: solved in full
+    m = orc.mesh(4, 4, 4, 4, orc.MAP_AFFINE)
+    bo = orc.to_global(m, orc.rhs_local(m, orc.src_sine(m.X)))
+    for tol in (1e-8, 1e-10):
+        t0 = time.perf_counter()
+        _, st, it, _ = orc.pcg(m, bo, tol, 5000)
+        dt = time.perf_counter() - t0
+        pcg[f"config1_to_{tol:.0e}"] = {"seconds": dt, "iters": it, "status": st}
+
+    def per_iter(m, bo, k=4):
+        orc.pcg(m, bo, 1e-30, 1)  # warm
+        t0 = time.perf_counter()
+        orc.pcg(m, bo, 1e-30, k)
+        return (time.perf_counter() - t0) / k
+
+    for name, ref_name, mk in (
+            ("config2", "pcg_32x32x32_N7_sinecyclic_fourier0",
+             lambda: orc.mesh(7, 32, 32, 32, orc.MAP_SINE_CYCLIC)),
+            # kappa is folded into the factors: the iteration cost does not
+            # depend on its number of Fourier features (64 here, 4096 in the
+            # benchmark problem, whose setup alone would take minutes)
+            ("config5", "learned_24x24x24_N7_grf7_fourier900",
+             lambda: orc.mesh(7, 24, 24, 24, orc.MAP_AFFINE, 1,
+                              grf_features(seed=7, M=64, ell=0.1, sigma=1.0)))):
+        ref = oracle_reference(ref_name)
+        m = mk()
+        k_, a_, p_ = fourier_modes(seed=0)
+        bo = orc.to_global(m, orc.rhs_local(m, orc.src_fourier(m.X, k_, a_, p_)))
+        spi = per_iter(m, bo)
+        rec = {"seconds_per_iter": spi, "timed_iters": 4, "threads": nthreads}
+        if ref is not None:
+            for tol in ("1e-8", "1e-10"):
+                its = int(ref[0][f"iters_{tol}"])
+                rec[f"to_{tol}_extrapolated_s"] = spi * its
+                rec[f"iters_{tol}"] = its
+        pcg[name] = rec
+        del m, bo
+        log(f"[cpu] oracle PCG {name}: {rec}")
+    out["oracle_pcg"] = pcg
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-pcg", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
@@ -493,6 +754,7 @@ def main():
               f"is not built)", file=sys.stderr)
         sys.exit(2)
 
+    cores = host_cores()  # before the GPU is touched (runs lscpu)
     import torch
     from paper_1403_0968_amd import sem
     sem.lib()
@@ -531,6 +793,10 @@ def main():
     gdofs = nL / (ms * 1e-3) / 1e9
     achieved = BYTES_PER_NODE["f64"] * nL / (ms * 1e-3) / 1e9
     traffic = read_traffic(nL)
+    ax_stats = launch_stats(torch, lambda: sem.sem_ax(h, sem.SEM_FP64, u, w),
+                            max(200, args.steps))
+    log(f"[bench] fp64 sem_ax single launches: {ax_stats}")
+    gs = bench_gs(sem, torch, h, nL)
 
     extra = {}
     u32 = u.float()
@@ -550,6 +816,7 @@ def main():
 
     pcg = None if args.no_pcg else bench_pcg(sem, torch, h, nL, nG)
     sem.sem_destroy(h)
+    config1 = None if args.no_pcg else bench_config1(sem, torch)
     del u, w, u32, w32, ub
     sweep = (None if args.no_sweep
              else bench_order_sweep(sem, torch, args.steps, args.warmup))
@@ -557,7 +824,7 @@ def main():
     dgv = None if args.no_dg else bench_dg(sem, torch, args.steps)
     learned = None if args.no_learned else bench_learned(sem, torch)
     batch = None if args.no_batch else bench_batch(sem, torch)
-    cpu = None if args.no_cpu else cpu_baseline()
+    cpu = None if args.no_cpu else cpu_baseline(cores)
     if cpu:
         log(f"[bench] cpu baseline {cpu}")
 
@@ -581,6 +848,13 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic},
         "cpu_baseline": cpu,
+        "sem_ax_fp64_launches": {
+            **ax_stats,
+            "gdofs_median": nL / (ax_stats["median_us"] * 1e-6) / 1e9,
+            "frac_hbm_median": 64 * nL / (ax_stats["median_us"] * 1e-6) / 1e9
+            / HBM_PEAK_GBS},
+        "sem_gs_fp64": gs,
+        "config1": config1,
         "sem_ax_low_precision": extra,
         "order_sweep": sweep,
         "fd2d": fd2d,

@@ -52,18 +52,29 @@ typedef enum {
   SEM_ERR_STATE = 6           /* call not valid for this handle */
 } sem_status;
 
+/* Operator precisions.  The input is used at the precision it is given in:
+ * sem_ax takes it in the storage type listed under sem_ax; inside the
+ * refinement's inner solves it is the FP32 search direction p.
+ *   SEM_BF16: BF16 geometric factors, FP32 derivative matrix, arithmetic
+ *     and output, VALU.  sem_ax: BF16 u (18 B per local node: u 2, G 12,
+ *     w 4).  Solver: FP32 p, not rounded (G 12 + w 4 per local node, p 4
+ *     per unique node).
+ *   SEM_BF16_MFMA: the six contractions on the matrix cores with FP32
+ *     accumulation, BF16 G and fluxes, the derivative matrix as a two-term
+ *     BF16 split D = D_hi + D_lo (two accumulating MFMAs per contraction).
+ *     sem_ax: BF16 u, N <= 7.  Solver: FP32 p as a two-term BF16 split
+ *     p = p_hi + p_lo, each gradient contraction accumulating D_hi p_hi,
+ *     D_lo p_hi and D_hi p_lo (rounding p to BF16 alone leaves an input
+ *     error whose effect on refinement grows with the mesh).
+ *   SEM_BF16_PLAIN_D: as SEM_BF16_MFMA with D rounded to BF16 (D_lo
+ *     dropped): its error does not vanish on smooth inputs, so refinement
+ *     around it contracts poorly or diverges (kept to measure exactly that). */
 typedef enum {
   SEM_FP64 = 0,
   SEM_FP32 = 1,
-  SEM_BF16 = 2,         /* BF16 u and G, FP32 derivative matrix, VALU */
-  SEM_BF16_PLAIN_D = 3, /* matrix-core operator with the derivative matrix
-                           rounded to BF16: its error does not vanish on
-                           smooth inputs, so refinement around it contracts
-                           poorly or diverges (kept to measure exactly that) */
-  SEM_BF16_MFMA = 4     /* matrix-core operator: BF16 u, G and fluxes, the
-                           derivative matrix as a two-term BF16 split
-                           D = D_hi + D_lo (two accumulating MFMAs per
-                           contraction), FP32 accumulation (N <= 7) */
+  SEM_BF16 = 2,
+  SEM_BF16_PLAIN_D = 3,
+  SEM_BF16_MFMA = 4
 } sem_precision;
 typedef enum {
   SEM_PC_NONE = 0,     /* z = r (off the Dirichlet boundary) */
@@ -126,12 +137,13 @@ typedef struct {
   int32_t pc;           /* a sem_precond */
   int32_t inner_prec;   /* SEM_FP64: plain FP64 PCG.  Any other precision:
                            FP64 iterative refinement whose inner PCG uses
-                           FP32 vectors and that operator (SEM_FP32, SEM_BF16,
-                           SEM_BF16_MFMA, SEM_BF16_PLAIN_D; the matrix-core
-                           ones for solves of one order N <= 7), with FP64
-                           dot products and scalars; refinement stops after
-                           3 steps that do not shrink the true residual by
-                           10% */
+                           FP32 vectors and that operator applied to the
+                           FP32 search direction (SEM_FP32, SEM_BF16,
+                           SEM_BF16_MFMA, SEM_BF16_PLAIN_D as described at
+                           sem_precision; the matrix-core ones for solves of
+                           one order N <= 7), with FP64 dot products and
+                           scalars; refinement stops after 3 steps that do
+                           not shrink the true residual by 10% */
   double inner_rtol;    /* inner relative tolerance for refinement */
   int32_t check_every;  /* CG iterations between host convergence polls */
   int32_t use_graph;    /* 1: replay a captured HIP graph of check_every

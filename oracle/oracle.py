@@ -52,6 +52,7 @@ def lib():
         L = _lib
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_gll.argtypes = [C.c_int, _dp, _dp]
         L.orc_gll.restype = C.c_int
         L.orc_dmat.argtypes = [C.c_int, _dp, _dp]
@@ -84,6 +85,10 @@ def lib():
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    lib().orc_set_num_threads(int(n))
 
 
 def _f64(a):

@@ -39,6 +39,16 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Threads of the parallel loops that follow (harness control for timing;
+ * no result depends on it: every parallel loop writes disjoint outputs). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 void orc_legendre(int n, double x, double *P) {
   /* (k+1) P_{k+1} = (2k+1) x P_k - k P_{k-1} */
   P[0] = 1.0;

@@ -31,6 +31,7 @@ enum { ORC_MAP_AFFINE = 0, ORC_MAP_SINE_X = 1, ORC_MAP_SINE_CYCLIC = 2 };
 
 /* OpenMP threads the parallel loops use. */
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 /* Legendre P_0..P_n at x by the three-term recurrence; P has n+1 entries. */
 void orc_legendre(int n, double x, double *P);

@@ -32,7 +32,8 @@
 // Two kernels share one element routine: k_ax (one tile of elements per
 // workgroup, the standalone operator) and k_bax (persistent workgroups
 // walking a list of (solve, element tile) items of a batch of independent
-// solves with mixed orders; one launch applies the operators of all solves).
+// solves with mixed orders; one launch applies the operators of all solves,
+// and stores every element's energy p_e^T w_e for the solvers' (p, A p)).
 #include "ax_tile.h"
 
 namespace sem {
@@ -118,8 +119,9 @@ __device__ __forceinline__ void bax_one(const BatchSolve &sd, int64_t e0,
                              : sizeof(TG) == 4 ? sd.G32
                                                : sd.G16);
   const TC *D = (const TC *)(sizeof(TC) == 8 ? sd.D64 : sd.D32);
-  ax_tile<N1, BTile<BS, N1>::EPB, TV, TG, TV, TC, true, false>(
-      threadIdx.x, e0, sd.E, D, G, u, w, &sd.box, smem);
+  // the element energies (p, A p) terms are stored with every application
+  ax_tile<N1, BTile<BS, N1>::EPB, TV, TG, TV, TC, true, false, false, true, true>(
+      threadIdx.x, e0, sd.E, D, G, u, w, &sd.box, smem, nullptr, sd.edot);
 }
 
 template <int BS, class TV, class TG, class TC, int... N1s>
@@ -127,7 +129,7 @@ __global__ void __launch_bounds__(BS)
     k_bax(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
           const AxItem *__restrict__ items, int nitems, int src, int dst,
           int skip_done) {
-  extern __shared__ unsigned char dyn_smem[];
+  extern __shared__ __align__(16) unsigned char dyn_smem[];
   TC *smem = reinterpret_cast<TC *>(dyn_smem);
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const AxItem it = items[q];

@@ -35,9 +35,13 @@ typedef float mf32x4 __attribute__((ext_vector_type(4)));
 constexpr int MW = 4;  // waves (elements) per workgroup
 
 struct alignas(16) MfmaLds {
-  uint16_t u[512];                  // u (BF16)
+  uint16_t u[512];                  // u (BF16), or the high term of its split
   float gr[512], gs[512], gt[512];  // gradients; gr is reused for w
   uint16_t fr[512], fs[512], ft[512];
+};
+// with the low term of a split input: ul = bf16(u - bf16(u))
+struct alignas(16) MfmaLdsSplit : MfmaLds {
+  uint16_t ul[512];
 };
 
 __device__ inline m16x4 lds4_strided(const uint16_t *p, int stride) {
@@ -75,11 +79,14 @@ __device__ inline void d_operands(int l, const uint16_t *__restrict__ Dhi,
 }
 
 // One element per wave.  The caller has placed the element's u (BF16,
-// padded [k][j][i] order, zeros outside n1) in L.u and holds in gq the six
-// BF16 factors of the lane's column (i, j) = (l % 8, l / 8) for k < 8 (zero
-// outside the element).  On return L.gr holds w in [k][j][i] order.
-template <int N1, bool SPLIT>
-__device__ inline void mfma_element(int l, MfmaLds &L, const uint16_t (&gq)[6][8],
+// padded [k][j][i] order, zeros outside n1) in L.u -- with ULO, an FP32 u
+// as the two-term split u = L.u + L.ul -- and holds in gq the six BF16
+// factors of the lane's column (i, j) = (l % 8, l / 8) for k < 8 (zero
+// outside the element).  On return L.gr holds w in [k][j][i] order.  With
+// ULO each gradient contraction accumulates D_hi u_hi, D_lo u_hi and
+// D_hi u_lo (the D_lo u_lo term is below the FP32 accumulation's rounding).
+template <int N1, bool SPLIT, bool ULO = false, class Lds = MfmaLds>
+__device__ inline void mfma_element(int l, Lds &L, const uint16_t (&gq)[6][8],
                                     m16x4 fh, m16x4 fl, m16x4 bh, m16x4 bl) {
   const int r = l & 15, g = l >> 4;
   const mf32x4 zero = {0.f, 0.f, 0.f, 0.f};
@@ -91,6 +98,7 @@ __device__ inline void mfma_element(int l, MfmaLds &L, const uint16_t (&gq)[6][8
       const m16x4 b = lds4_strided(&L.u[m0 * 64 + c], 64);
       mf32x4 acc = mfma(fh, b, zero);
       if (SPLIT) acc = mfma(fl, b, acc);
+      if constexpr (ULO) acc = mfma(fh, lds4_strided(&L.ul[m0 * 64 + c], 64), acc);
 #pragma unroll
       for (int q = 0; q < 4; ++q) L.gt[(m0 + q) * 64 + c] = acc[q];
     }
@@ -99,6 +107,8 @@ __device__ inline void mfma_element(int l, MfmaLds &L, const uint16_t (&gq)[6][8
       const m16x4 a = *reinterpret_cast<const m16x4 *>(&L.u[rho * 8 + m0]);
       mf32x4 acc = mfma(a, fh, zero);
       if (SPLIT) acc = mfma(a, fl, acc);
+      if constexpr (ULO)
+        acc = mfma(*reinterpret_cast<const m16x4 *>(&L.ul[rho * 8 + m0]), fh, acc);
       const int i = r & 7, rho0 = 32 * h2 + 16 * (r >> 3) + 4 * g;
 #pragma unroll
       for (int q = 0; q < 4; ++q) L.gr[(rho0 + q) * 8 + i] = acc[q];
@@ -108,6 +118,7 @@ __device__ inline void mfma_element(int l, MfmaLds &L, const uint16_t (&gq)[6][8
       const m16x4 b = lds4_strided(&L.u[k * 64 + m0 * 8 + i], 8);
       mf32x4 acc = mfma(fh, b, zero);
       if (SPLIT) acc = mfma(fl, b, acc);
+      if constexpr (ULO) acc = mfma(fh, lds4_strided(&L.ul[k * 64 + m0 * 8 + i], 8), acc);
 #pragma unroll
       for (int q = 0; q < 4; ++q) L.gs[k * 64 + (m0 + q) * 8 + i] = acc[q];
     }
@@ -304,9 +315,13 @@ void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
 
 // ---------------------------------------------------------------------------
 // batched operator inside the solvers: FP32 unique-node input gathered
-// through the box numbering and rounded to BF16, FP32 E-vector output;
-// items are tiles of a single order (n1 = N1s), MW elements per workgroup
-// pass
+// through the box numbering and split into two BF16 terms (u_hi = bf16(u),
+// u_lo = bf16(u - u_hi)), FP32 E-vector output; items are tiles of a single
+// order (n1 = N1s), MW elements per workgroup pass.  Rounding the input to
+// BF16 alone leaves an input error that refinement cannot remove at scale:
+// A (I + Delta) p with |Delta| ~ 2^-9 amplifies rough components by the
+// operator's spread of eigenvalues, and the refinement's contraction grew
+// with the mesh (0.36 per step at 32^3 elements, N = 7).
 // ---------------------------------------------------------------------------
 template <int N1, bool SPLIT>
 __global__ void __launch_bounds__(64 * MW)
@@ -314,9 +329,9 @@ __global__ void __launch_bounds__(64 * MW)
                const AxItem *__restrict__ items, int nitems, int epb, int src,
                int dst, int skip_done) {
   constexpr int NP = N1 * N1, N3 = NP * N1;
-  __shared__ MfmaLds lds[MW];
+  __shared__ MfmaLdsSplit lds[MW];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
-  MfmaLds &L = lds[wv];
+  MfmaLdsSplit &L = lds[wv];
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const AxItem it = items[q];
     if (skip_done && st[it.solve].done != 0) continue;  // uniform per block
@@ -339,17 +354,21 @@ __global__ void __launch_bounds__(64 * MW)
       for (int t = 0; t < 8; ++t) {
         const int p = l + 64 * t, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
         const bool in = act && i < N1 && j < N1 && k < N1;
-        L.u[p] = in ? f32_to_bf16(u[gb + i + (int64_t)sd.box.Gx * j + sd.box.Gxy * k])
-                    : (uint16_t)0;
+        const float v = in ? u[gb + i + (int64_t)sd.box.Gx * j + sd.box.Gxy * k] : 0.f;
+        const uint16_t hi = f32_to_bf16(v);
+        L.u[p] = hi;
+        L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
       }
       __syncthreads();
-      mfma_element<N1, SPLIT>(l, L, gq, fh, fl, bh, bl);
+      mfma_element<N1, SPLIT, true, MfmaLdsSplit>(l, L, gq, fh, fl, bh, bl);
       if (act) {
         for (int p = l; p < N3; p += 64) {
           const int i = p % N1, j = (p / N1) % N1, k = p / NP;
           const int q = k * 64 + j * 8 + i;
           float v = L.gr[q];
-          if (H != nullptr) v += bf16_to_f32(H[e * N3 + p]) * bf16_to_f32(L.u[q]);
+          if (H != nullptr)
+            v += bf16_to_f32(H[e * N3 + p]) *
+                 (bf16_to_f32(L.u[q]) + bf16_to_f32(L.ul[q]));
           w[e * N3 + p] = v;
         }
       }

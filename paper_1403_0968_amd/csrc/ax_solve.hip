@@ -8,7 +8,9 @@
 // N = 7 (measured with and without the gather: the gather itself costs
 // nothing in FP64).  Workgroup shapes and load hints as the standalone
 // operator (OpShape).  A mesh with
-// a mass term passes H = alpha(X) B and the kernel adds H o u.
+// a mass term passes H = alpha(X) B and the kernel adds H o u.  With edot
+// non-null the kernel also stores every element's energy p_e^T w_e (the
+// element terms of (p, A p), in an order fixed by the node indices).
 // Workgroups are dealt to the 8 XCDs in turn (workgroup b runs on XCD
 // b % 8), each with its own L2.  With FP32 / BF16 storage the kernel numbers
 // its element blocks so that every XCD gets one contiguous run of them, and
@@ -27,63 +29,74 @@ __device__ inline int64_t xcd_run_block(unsigned b, unsigned nb) {
   return (int64_t)x * q + (x < r ? x : r) + k;
 }
 
-template <int N1, class TV, class TG, class TC, bool MASS>
+template <int N1, class TV, class TG, class TC, bool MASS, bool EDOT>
 __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
     k_ax_solve(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
                const TV *__restrict__ u, TV *__restrict__ w, Box box,
-               const int32_t *__restrict__ stop, const TG *__restrict__ H) {
+               const int32_t *__restrict__ stop, const TG *__restrict__ H,
+               double *__restrict__ edot) {
   using S = OpShape<N1, sizeof(TC)>;
-  __shared__ TC smem[lds_words<N1>(S::EPB)];
+  __shared__ __align__(16) TC smem[lds_words<N1>(S::EPB)];
   if (stop != nullptr && *stop != 0) return;  // uniform: the solve finished
-  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG>(
+  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG, EDOT>(
       threadIdx.x,
       (sizeof(TV) == 4 ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x) *
           S::EPB,
-      E, D, G, u, w, &box, smem, H);
+      E, D, G, u, w, &box, smem, H, edot);
+}
+
+template <int N1, class TV, class TG, class TC, bool MASS>
+static void launch_solve_m(int64_t E, const void *D, const void *G,
+                           const void *H, const void *u, void *w, const Box &box,
+                           const int32_t *stop, double *edot, hipStream_t s) {
+  using S = OpShape<N1, sizeof(TC)>;
+  const int64_t blocks = (E + S::EPB - 1) / S::EPB;
+  if (blocks == 0) return;
+  const dim3 grid((unsigned)blocks), block(S::THREADS);
+  if (edot != nullptr)
+    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, MASS, true>), grid, block, 0, s,
+                       E, (const TC *)D, (const TG *)G, (const TV *)u, (TV *)w,
+                       box, stop, (const TG *)H, edot);
+  else
+    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, MASS, false>), grid, block, 0,
+                       s, E, (const TC *)D, (const TG *)G, (const TV *)u, (TV *)w,
+                       box, stop, (const TG *)H, edot);
 }
 
 template <int N1, class TV, class TG, class TC>
 static void launch_solve_t(int64_t E, const void *D, const void *G,
                            const void *H, const void *u, void *w, const Box &box,
-                           const int32_t *stop, hipStream_t s) {
-  using S = OpShape<N1, sizeof(TC)>;
-  const int64_t blocks = (E + S::EPB - 1) / S::EPB;
-  if (blocks == 0) return;
-  const dim3 grid((unsigned)blocks), block(S::THREADS);
+                           const int32_t *stop, double *edot, hipStream_t s) {
   if (H != nullptr)
-    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, true>), grid, block, 0, s, E,
-                       (const TC *)D, (const TG *)G, (const TV *)u, (TV *)w, box,
-                       stop, (const TG *)H);
+    launch_solve_m<N1, TV, TG, TC, true>(E, D, G, H, u, w, box, stop, edot, s);
   else
-    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, false>), grid, block, 0, s, E,
-                       (const TC *)D, (const TG *)G, (const TV *)u, (TV *)w, box,
-                       stop, (const TG *)nullptr);
+    launch_solve_m<N1, TV, TG, TC, false>(E, D, G, H, u, w, box, stop, edot, s);
 }
 
 template <int N1>
 static void launch_solve_n(int prec, int64_t E, const void *D, const void *G,
                            const void *H, const void *u, void *w, const Box &box,
-                           const int32_t *stop, hipStream_t s) {
+                           const int32_t *stop, double *edot, hipStream_t s) {
   if (prec == SEM_FP64)
-    launch_solve_t<N1, double, double, double>(E, D, G, H, u, w, box, stop, s);
+    launch_solve_t<N1, double, double, double>(E, D, G, H, u, w, box, stop, edot, s);
   else if (prec == SEM_FP32)
-    launch_solve_t<N1, float, float, float>(E, D, G, H, u, w, box, stop, s);
+    launch_solve_t<N1, float, float, float>(E, D, G, H, u, w, box, stop, edot, s);
   else
-    launch_solve_t<N1, float, uint16_t, float>(E, D, G, H, u, w, box, stop, s);
+    launch_solve_t<N1, float, uint16_t, float>(E, D, G, H, u, w, box, stop, edot, s);
 }
 
 void launch_ax_solve(int N, int prec, int64_t E, const void *D, const void *G,
                      const void *H, const void *u, void *w, const Box &box,
-                     const int32_t *stop, hipStream_t s) {
+                     const int32_t *stop, double *edot, hipStream_t s) {
   switch (N) {
-    case 1: launch_solve_n<2>(prec, E, D, G, H, u, w, box, stop, s); break;
-    case 2: launch_solve_n<3>(prec, E, D, G, H, u, w, box, stop, s); break;
-    case 3: launch_solve_n<4>(prec, E, D, G, H, u, w, box, stop, s); break;
-    case 4: launch_solve_n<5>(prec, E, D, G, H, u, w, box, stop, s); break;
-    case 5: launch_solve_n<6>(prec, E, D, G, H, u, w, box, stop, s); break;
-    case 6: launch_solve_n<7>(prec, E, D, G, H, u, w, box, stop, s); break;
-    case 7: launch_solve_n<8>(prec, E, D, G, H, u, w, box, stop, s); break;
-    case 8: launch_solve_n<9>(prec, E, D, G, H, u, w, box, stop, s); break;
+    case 1: launch_solve_n<2>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 2: launch_solve_n<3>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 3: launch_solve_n<4>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 4: launch_solve_n<5>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 5: launch_solve_n<6>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 6: launch_solve_n<7>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 7: launch_solve_n<8>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 8: launch_solve_n<9>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
     default: fail(SEM_ERR_ARG, "solve: N must be in 1..8");
   }
   SEM_HIP(hipGetLastError());

@@ -52,9 +52,15 @@ template <int N1, int BYTES> struct OpShape {
 
 // Apply the operator to elements e0 .. e0 + EPB - 1 (those < E) with the
 // threads t = 0 .. of one workgroup; threads t >= EPB n1^2 only join the
-// barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC.
+// barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC (8-byte aligned).
+// EDOT = true also stores the element energy edot[e] = u_e^T w_e in FP64,
+// summed in an order fixed by the node indices alone (each (i, j) column
+// over k, then the columns of a row j over i, then the rows over j), so
+// that every tile shape gives the same bits.  Inside the solvers u is the
+// search direction p, which vanishes on Dirichlet nodes, and the sum of the
+// element energies is (p, A p) of the assembled operator.
 template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
-          bool NTW, bool MASS = false, bool NTG = true>
+          bool NTW, bool MASS = false, bool NTG = true, bool EDOT = false>
 __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
                                         const TC *__restrict__ D,
                                         const TG *__restrict__ G,
@@ -62,7 +68,8 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
                                         TW *__restrict__ w,
                                         const Box *__restrict__ box,
                                         TC *__restrict__ smem,
-                                        const TG *__restrict__ H = nullptr) {
+                                        const TG *__restrict__ H = nullptr,
+                                        double *__restrict__ edot = nullptr) {
   constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = N1 + 1;
   constexpr int SL = N1 * N1 * PAD;  // one element's slice stack
   const int el = t / NP;
@@ -194,6 +201,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
     DTi[m] = D[m * N1 + i];
     DTj[m] = D[m * N1 + j];
   }
+  double cdot = 0.0;  // EDOT: this column's u^T w
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     TC acc = mv[k];
@@ -203,11 +211,32 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
       acc += DTj[m] * s_s[AX_IDX(k, m, i)];
       acc += D[m * N1 + k] * wt[m];
     }
+    if constexpr (EDOT) cdot += (double)uc[k] * (double)(TW)acc;
     if (act) {
       if constexpr (NTW)
         __builtin_nontemporal_store((TW)acc, w + base + k * NP);
       else
         w[base + k * NP] = (TW)acc;
+    }
+  }
+  if constexpr (EDOT) {
+    // s_u is no longer read after the barrier above: it holds the column
+    // sums red[c] (c = i + n1 j) and then the row sums red[NP + j]
+    double *red = reinterpret_cast<double *>(s_u);
+    if (lane_ok) red[c] = cdot;
+    __syncthreads();
+    if (lane_ok && i == 0) {
+      double r = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < N1; ++ii) r += red[ii + N1 * j];
+      red[NP + j] = r;
+    }
+    __syncthreads();
+    if (act && c == 0) {
+      double r = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < N1; ++jj) r += red[NP + jj];
+      edot[e] = r;
     }
   }
 #undef AX_IDX

@@ -403,15 +403,15 @@ static void ensure_scratch(sem_mlp *net, int B) {
 }
 
 // forward of B samples X [B][ldx] BF16 (ldx >= kin, padding columns zero)
-// into O [B][ldo] FP32; the hidden activations are kept in the network's
-// scratch (BF16 and FP32 copies in BF16 precision, FP32 in FP32 precision)
-// for a backward pass.
-void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
-                 int ldo, hipStream_t s) {
-  if (B <= 0) return;
+// into O [B][ldo] FP32 with the hidden activations in the given buffers:
+// BF16 precision writes h1b, h2b (BF16 [B][H], the next layer's inputs) and,
+// when non-null, their FP32 values h1f, h2f (for a backward pass); FP32
+// precision writes h1f, h2f (FP32 [B][H]) only.
+static void forward_into(sem_mlp *net, const uint16_t *X, int ldx, int B,
+                         float *O, int ldo, uint16_t *h1b, uint16_t *h2b,
+                         float *h1f, float *h2f, hipStream_t s) {
   if (ldx < net->kin || ldx % 16 != 0)
     fail(SEM_ERR_ARG, "mlp_forward: ldx must be >= padded n_in and a multiple of 16");
-  ensure_scratch(net, B);
   const int H = net->H;
   const float *W1 = net->th.as<float>();
   const float *b1 = W1 + (int64_t)H * net->n_in;
@@ -419,7 +419,6 @@ void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
   const float *b2 = W2 + (int64_t)H * H;
   const float *W3 = b2 + H;
   const float *b3 = W3 + (int64_t)net->n_out * H;
-  float *h1f = net->h1f.as<float>(), *h2f = net->h2f.as<float>();
   if (net->prec == SEM_FP32) {
     const unsigned gm = (unsigned)((B + 15) / 16);
     hipLaunchKernelGGL((k_dense_f32<uint16_t, true>), dim3(gm, H / 16), dim3(256),
@@ -433,7 +432,6 @@ void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
     SEM_HIP(hipGetLastError());
     return;
   }
-  uint16_t *h1b = net->h1b.as<uint16_t>(), *h2b = net->h2b.as<uint16_t>();
   const unsigned grid = (unsigned)((B + 63) / 64);
   hipLaunchKernelGGL((k_dense_mfma<8, true>), dim3(grid), dim3(256), 0, s, B,
                      net->kin, H, X, ldx, net->W1b.as<uint16_t>(), b1, h1b, H,
@@ -449,6 +447,17 @@ void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
                        s, B, H, net->n_out, h2b, H, net->W3b.as<uint16_t>(), b3,
                        (uint16_t *)nullptr, 0, O, ldo);
   SEM_HIP(hipGetLastError());
+}
+
+// forward with the hidden activations kept in the network's scratch (grown
+// to B samples when needed) for a backward pass
+void mlp_forward(sem_mlp *net, const uint16_t *X, int ldx, int B, float *O,
+                 int ldo, hipStream_t s) {
+  if (B <= 0) return;
+  ensure_scratch(net, B);
+  forward_into(net, X, ldx, B, O, ldo, net->h1b.as<uint16_t>(),
+               net->h2b.as<uint16_t>(), net->h1f.as<float>(), net->h2f.as<float>(),
+               s);
 }
 
 // backward pass from net->dO (written by a loss kernel) into net->grad

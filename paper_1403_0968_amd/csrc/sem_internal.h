@@ -81,7 +81,7 @@ struct CgState {
   int32_t it;     // iterations done
   int32_t maxit;
   int32_t done;   // 0 running, 1 converged, 2 breakdown, 3 maxit, 4 idle
-  int32_t pad1;
+  int32_t xupd;   // 1: this iteration's x += alpha p is still to be applied
 };
 
 // vectors of one solve (unique-node layout except VWL, an E-vector)
@@ -99,6 +99,7 @@ struct BatchSolve {
   const float *dinv32, *one32;
   void *v64[NVEC];
   void *v32[NVEC];
+  double *edot;                   // [E] element energies p_e^T (A p)_e
 };
 
 // work items of the persistent kernels
@@ -173,7 +174,7 @@ void launch_bax(int prec, int bs, int nset, const BatchSolve *sds,
                 int src, int dst, int skip_done, hipStream_t s);
 void launch_ax_solve(int N, int prec, int64_t E, const void *D, const void *G,
                      const void *H, const void *u, void *w, const Box &box,
-                     const int32_t *stop, hipStream_t s);
+                     const int32_t *stop, double *edot, hipStream_t s);
 void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
                     const uint16_t *Dlo, const uint16_t *G, const uint16_t *H,
                     const uint16_t *u, float *w, hipStream_t s);

@@ -7,12 +7,18 @@
 // Everything runs on batches: a single solve is a batch of one.  Vectors
 // live on unique (global) nodes; the operator is applied as
 //   w_G = mask o Q^T A_L Q p_G
-// with Q fused into the operator kernel (gather through l2g) and Q^T + mask
-// fused with the (p, w) dot product.  One CG iteration of the whole batch is
-// six launches of persistent kernels that walk work lists of
-// (solve, element tile) or (solve, node chunk) items:
-//   operator -> assemble + dot -> alpha -> x, r update + z = dinv r + dots
-//   -> beta / convergence -> p update.
+// with Q fused into the operator kernel (gather through the closed-form
+// numbering).  p vanishes on Dirichlet nodes, so (p, w_G) = sum_e p_e^T w_e:
+// the operator stores the element energies and the assembled w_G is never
+// stored -- the r update sums the copies of each node itself (Q^T + mask).
+// One CG iteration of the whole batch is five launches of persistent
+// kernels that walk work lists of (solve, element tile) or (solve, node
+// chunk) items:
+//   operator + element energies -> alpha -> assembly + r update +
+//   z = dinv r + dots -> beta / convergence -> x and p update.
+// (The matrix-core operator has no energy output: with it the iteration
+// keeps a separate assembly with the (p, w) dot, and r, z and the dots in
+// one more pass.)
 // Scalars stay on the device, one CgState per solve; kernels skip items of
 // solves whose flag says they finished, so a captured HIP graph of K
 // iterations is replayed between host polls without changing any iterate.
@@ -141,6 +147,7 @@ __global__ void __launch_bounds__(RT)
              const int32_t *__restrict__ vbeg) {
   __shared__ double sm[RT / 64];
   const int s = blockIdx.x;
+  if (threadIdx.x == 0) st[s].xupd = 0;  // no x update from an earlier step
   if (st[s].done != 0) return;
   double acc[1];
   strided_sums<1>(part, 0, vbeg[s], vbeg[s + 1], acc);
@@ -154,6 +161,96 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
+// alpha_s = rz_s / (p, A p)_s with (p, A p) the sum of the solve's element
+// energies in element order (strided over the workgroup's threads, then the
+// fixed workgroup sum), one workgroup of AT threads per solve
+constexpr int AT = 1024;
+__global__ void __launch_bounds__(AT)
+    k_balpha_e(const BatchSolve *__restrict__ sds, CgState *st) {
+  __shared__ double sm[AT / 64];
+  const int s = blockIdx.x;
+  if (threadIdx.x == 0) st[s].xupd = 0;  // no x update from an earlier step
+  if (st[s].done != 0) return;
+  const double *ed = sds[s].edot;
+  const int64_t E = sds[s].E;
+  constexpr int PF = 8;
+  double acc = 0.0;
+  int64_t q = threadIdx.x;
+  for (; q + (PF - 1) * AT < E; q += PF * AT) {
+    double v[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) v[u] = ed[q + u * AT];
+#pragma unroll
+    for (int u = 0; u < PF; ++u) acc += v[u];
+  }
+  for (; q < E; q += AT) acc += ed[q];
+  const double pw = block_sum<AT>(acc, sm);
+  if (threadIdx.x == 0) {
+    st[s].pw = pw;
+    if (!(pw > 0.0) || !isfinite(pw))
+      st[s].done = 2;
+    else
+      st[s].alpha = st[s].rz / pw;
+  }
+}
+
+// r -= alpha w_G with w_G = mask o Q^T w_L formed here (the copies of each
+// node summed from +0.0 in ascending local index, as the assembly and
+// sem_gs sum them), z = dinv r; partials (r, z), (r, r)
+template <class TV, class TD>
+__global__ void __launch_bounds__(RT)
+    k_bupdate_xr_asm(const BatchSolve *__restrict__ sds,
+                     const CgState *__restrict__ st,
+                     const VecItem *__restrict__ items, int nitems,
+                     double *__restrict__ part, int jac) {
+  __shared__ double sm[RT / 64];
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const VecItem it = items[q];
+    if (st[it.solve].done != 0) continue;
+    const BatchSolve &sd = sds[it.solve];
+    const Box &bx = sd.box;
+    const TV *wL = vec<TV>(sd, VWL);
+    TV *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ);
+    const TD *dinv = dinv_of<TD>(sd, jac);
+    const TV alpha = (TV)st[it.solve].alpha;
+    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
+    double rz = 0.0, rr = 0.0;
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+      const NodeCopies nc = node_copies(bx, (uint32_t)g);
+      TV sw = TV(0);
+      if (!nc.masked) {
+        TV v[8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              const bool ok = a < nc.z.cnt && b < nc.y.cnt && c < nc.x.cnt;
+              const int64_t lid = ok ? copy_lid(bx, nc, a, b, c) : 0;
+              v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
+            }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sw = sw + v[k];
+      }
+      const TV rn = r[g] - alpha * sw;
+      r[g] = rn;
+      const TV zn = (TV)(dinv[g] * rn);
+      z[g] = zn;
+      rz += (double)rn * (double)zn;
+      rr += (double)rn * (double)rn;
+    }
+    const double trz = block_sum<RT>(rz, sm);
+    const double trr = block_sum<RT>(rr, sm);
+    if (threadIdx.x == 0) {
+      part[q] = trz;
+      part[nitems + q] = trr;
+    }
+  }
+}
+
+// r -= alpha w, z = dinv r (w the stored assembled vector); partials (r, z),
+// (r, r).  The x update waits for k_bupdate_p.
 template <class TV, class TD>
 __global__ void __launch_bounds__(RT)
     k_bupdate_xr(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
@@ -164,14 +261,13 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    TV *x = vec<TV>(sd, VX), *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ);
-    const TV *p = vec<TV>(sd, VP), *w = vec<TV>(sd, VW);
+    TV *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ);
+    const TV *w = vec<TV>(sd, VW);
     const TD *dinv = dinv_of<TD>(sd, jac);
     const TV alpha = (TV)st[it.solve].alpha;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double rz = 0.0, rr = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
-      x[g] = x[g] + alpha * p[g];
       const TV rn = r[g] - alpha * w[g];
       r[g] = rn;
       const TV zn = (TV)(dinv[g] * rn);
@@ -202,6 +298,7 @@ __global__ void __launch_bounds__(RT)
   const double rr = block_sum<RT>(b, sm);
   if (threadIdx.x == 0) {
     CgState &c = st[s];
+    c.xupd = 1;  // this step's alpha is finite: x += alpha p follows
     c.it += 1;
     c.rr = rr;
     if (!isfinite(rr) || !isfinite(rz))
@@ -217,20 +314,32 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
+// x += alpha p with this step's alpha (when k_bbeta found it finite, also
+// on the step that converged), then p = z + beta p while the solve runs
 template <class TV>
 __global__ void __launch_bounds__(RT)
     k_bupdate_p(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
                 const VecItem *__restrict__ items, int nitems) {
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
-    if (st[it.solve].done != 0) continue;
+    const CgState &c = st[it.solve];
+    if (c.xupd == 0) continue;  // uniform per item
     const BatchSolve &sd = sds[it.solve];
     const TV *z = vec<TV>(sd, VZ);
-    TV *p = vec<TV>(sd, VP);
-    const TV beta = (TV)st[it.solve].beta;
+    TV *p = vec<TV>(sd, VP), *x = vec<TV>(sd, VX);
+    const TV alpha = (TV)c.alpha;
+    const TV beta = (TV)c.beta;
+    const bool run = c.done == 0;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
-      p[g] = z[g] + beta * p[g];
+    if (run)
+      for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+        const TV pv = p[g];
+        x[g] = x[g] + alpha * pv;
+        p[g] = z[g] + beta * pv;
+      }
+    else
+      for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
+        x[g] = x[g] + alpha * p[g];
   }
 }
 
@@ -290,6 +399,7 @@ __global__ void __launch_bounds__(RT)
     if (threadIdx.x == 0) {
       c.done = 4;
       c.it = 0;
+      c.xupd = 0;
     }
     return;
   }
@@ -306,6 +416,7 @@ __global__ void __launch_bounds__(RT)
     c.tol2 = tol2;
     c.it = 0;
     c.maxit = maxit[s];
+    c.xupd = 0;
     c.alpha = c.beta = c.pw = 0.0;
     if (!isfinite(rr) || !isfinite(rz))
       c.done = 2;
@@ -404,24 +515,22 @@ __global__ void __launch_bounds__(RT)
 }
 
 // ---- flexible CG with the learned correction (single solve) -------------
-// x += alpha p, r -= alpha w (z comes from the correction below)
+// r -= alpha w (z comes from the correction below, x from k_bupdate_p)
 template <class TV>
 __global__ void __launch_bounds__(RT)
-    k_bupdate_xr_only(const BatchSolve *__restrict__ sds,
-                      const CgState *__restrict__ st,
-                      const VecItem *__restrict__ items, int nitems) {
+    k_bupdate_r_only(const BatchSolve *__restrict__ sds,
+                     const CgState *__restrict__ st,
+                     const VecItem *__restrict__ items, int nitems) {
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    TV *x = vec<TV>(sd, VX), *r = vec<TV>(sd, VR);
-    const TV *p = vec<TV>(sd, VP), *w = vec<TV>(sd, VW);
+    TV *r = vec<TV>(sd, VR);
+    const TV *w = vec<TV>(sd, VW);
     const TV alpha = (TV)st[it.solve].alpha;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
-      x[g] = x[g] + alpha * p[g];
+    for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
       r[g] = r[g] - alpha * w[g];
-    }
   }
 }
 
@@ -480,6 +589,7 @@ __global__ void __launch_bounds__(RT)
   const double rr = block_sum<RT>(c, sm);
   if (threadIdx.x == 0) {
     CgState &cs = st[s];
+    cs.xupd = 1;  // this step's alpha is finite: x += alpha p follows
     cs.it += 1;
     cs.rr = rr;
     if (!isfinite(rr) || !isfinite(rz) || !isfinite(zw))
@@ -553,6 +663,7 @@ __global__ void k_unmask(int64_t nG, const uint8_t *__restrict__ gmask,
 // --------------------------------------------------------------------------
 struct Workspace {
   DevBuf v64[NVEC], v32[NVEC], one64, one32;
+  DevBuf edot;  // element energies of the last operator application
   bool ready = false;
   sem_batch *single = nullptr;  // the handle as a batch of one
 };
@@ -570,6 +681,7 @@ static void ensure_vectors(sem_handle *h) {
   }
   W->one64.alloc(h->nG * sizeof(double));
   W->one32.alloc(h->nG * sizeof(float));
+  W->edot.alloc(h->E * sizeof(double));
   hipLaunchKernelGGL(k_unmask, dim3(nblk(h->nG)), dim3(RT), 0, 0, h->nG,
                      h->gmask.as<uint8_t>(), W->one64.as<double>(),
                      W->one32.as<float>());
@@ -688,6 +800,7 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
         d.v64[v] = W->v64[v].p;
         d.v32[v] = W->v32[v].p;
       }
+      d.edot = W->edot.as<double>();
       vbeg[q] = (int32_t)vis.size();
       for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({q, 0, g});
       b->orders.push_back(h->n1);
@@ -751,7 +864,11 @@ void destroy_ws(sem_handle *h) {
 // --------------------------------------------------------------------------
 static int vec_grid(const sem_batch *b) { return std::min(b->n_vi, 2048); }
 
-static void bax(sem_batch *b, int prec, int src, int dst, int skip_done) {
+// the operator of every solve of the batch, w_L = A_L Q v_src into VWL;
+// edot: the single-solve kernel also stores the element energies (the
+// batched kernel always does)
+static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
+                bool edot = false) {
   if (prec == SEM_BF16_MFMA || prec == SEM_BF16_PLAIN_D) {
     // matrix-core operator: tiles of the 256-thread item list, one order
     if (b->nset < 2 || b->nset > 8)
@@ -780,7 +897,8 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done) {
     const int32_t *stop =
         skip_done ? &b->st.as<CgState>()[0].done : (const int32_t *)nullptr;
     launch_ax_solve(h->N, prec, h->E, D, G, H, u, w,
-                    make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet), stop, b->s);
+                    make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet), stop,
+                    edot ? W->edot.as<double>() : nullptr, b->s);
     return;
   }
   const int bs = b->bs[prec];
@@ -799,12 +917,21 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   double *part = b->part.as<double>();
   const int32_t *vbeg = b->vbeg.as<int32_t>();
   const int g = vec_grid(b), nv = b->n_vi, n = b->n;
-  bax(b, prec, VP, VWL, 1);
-  hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds, st,
-                     vi, nv, part, 1);
-  hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
-  hipLaunchKernelGGL((k_bupdate_xr<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds, st,
-                     vi, nv, part, jac);
+  if (prec == SEM_BF16_MFMA || prec == SEM_BF16_PLAIN_D) {
+    // no element energies from the matrix-core operator: assembled w and
+    // (p, w) first
+    bax(b, prec, VP, VWL, 1);
+    hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds,
+                       st, vi, nv, part, 1);
+    hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
+    hipLaunchKernelGGL((k_bupdate_xr<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
+                       st, vi, nv, part, jac);
+  } else {
+    bax(b, prec, VP, VWL, 1, true);
+    hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
+    hipLaunchKernelGGL((k_bupdate_xr_asm<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
+                       st, vi, nv, part, jac);
+  }
   hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
   hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
                      nv);
@@ -827,7 +954,7 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
   hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds, st,
                      vi, nv, part, 1);
   hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
-  hipLaunchKernelGGL((k_bupdate_xr_only<TV>), dim3(g), dim3(RT), 0, b->s, sds, st,
+  hipLaunchKernelGGL((k_bupdate_r_only<TV>), dim3(g), dim3(RT), 0, b->s, sds, st,
                      vi, nv);
   learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, b->s);
   hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,

@@ -222,3 +222,27 @@ def test_ax_matrix_core_split_derivative(sem, pair):
     print(f"[A 1, N={m.N}] split {es:.2e}, plain {ep:.2e}, VALU FP32-D {ev:.2e}")
     assert es <= 1e-4
     assert ep >= 10 * es
+
+
+def test_ax_matrix_core_transposed_split(sem, pair):
+    """The transposed contractions sum to zero over each element for any
+    input: sum_i (D^T f)_i = f . (D 1) = 0 for every flux f, so the element
+    sums of w vanish whatever the BF16 rounding of u, G and the fluxes.
+    With the split derivative matrix the residue is at the split's 2^-16
+    level; with D rounded to BF16 (whose rows no longer sum to zero) at
+    2^-9 -- this exercises the transposed stage, where A 1 (zero fluxes)
+    cannot."""
+    m = pair.m
+    if m.N > 7 or m.N < 3:
+        pytest.skip("the matrix-core operator covers N <= 7; at N <= 2 every "
+                    "entry of D is exact in BF16")
+    u = uniform(m.nL, seed=15)
+    n3 = m.n1 ** 3
+    scale = orc.ax_abs(m, np.abs(bf16_round(u)[0])).reshape(m.E, n3).sum(1)
+    ws = _ax_gpu(sem, pair.h, u, sem.SEM_BF16_MFMA).reshape(m.E, n3).sum(1)
+    wp = _ax_gpu(sem, pair.h, u, sem.SEM_BF16_PLAIN_D).reshape(m.E, n3).sum(1)
+    es = float(np.max(np.abs(ws) / scale))
+    ep = float(np.max(np.abs(wp) / scale))
+    print(f"[element sums of w, N={m.N}] split {es:.2e}, plain {ep:.2e}")
+    assert es <= 1e-4
+    assert ep >= 10 * es
