@@ -192,6 +192,11 @@ def bench_order_sweep(sem, torch, steps, warmup, target_nodes=NE ** 3 * 512):
             f"{out[f'N{N}']['gflops']:.0f} GFLOP/s, {out[f'N{N}']['alg_GBs']:.0f} GB/s")
     h = sem.sem_setup(ORDER, NE, NE, NE, mapping=sem.SEM_MAP_SINE_CYCLIC, alpha=1.0)
     E, nL, nG = sem.sem_query(h)
+    if args.pcg_only:
+        print(json.dumps({"pcg": bench_pcg(sem, torch, h, nL, nG, quick=True)}),
+              flush=True)
+        sem.sem_destroy(h)
+        return
     u = make_input(sem, torch, h, nL, nG)
     w = torch.empty_like(u)
     ms = time_ax(sem, torch, h, sem.SEM_FP64, u, w, steps, warmup)
@@ -282,21 +287,31 @@ def bench_dg(sem, torch, steps):
         Q = np.stack([hh, 0.2 * np.cos(3 * X + Y) * hh,
                       -0.1 * np.sin(X - 2 * Y) * hh], axis=1)
         h = sem.dg_setup(N, vx, vy, etov, bathymetry=B, g=9.81)
+        Np = (N + 1) * (N + 2) // 2
+        nb = (E + 15) // 16
+        Qb = np.zeros((nb * 16, 3, Np))
+        Qb[:E] = Q
+        Qb = np.ascontiguousarray(Qb.reshape(nb, 16, 3, Np).transpose(0, 2, 3, 1))
         dQ = torch.as_tensor(Q, device="cuda")
         drhs = torch.empty_like(dQ)
-        ms = time_launches(torch, lambda: sem.dg_volume(h, dQ, drhs), steps)
+        dQb = torch.as_tensor(Qb, device="cuda")
+        drb = torch.empty_like(dQb)
+        ms_em = time_launches(torch, lambda: sem.dg_volume(h, dQ, drhs), steps)
+        ms = time_launches(torch, lambda: sem.dg_volume_blocked(h, dQb, drb), steps)
         sem.dg_destroy(h)
-        del dQ, drhs
-        Np = (N + 1) * (N + 2) // 2
+        del dQ, drhs, dQb, drb
         t = ms * 1e-3
         flops = (12 * Np * Np + 32 * Np) * E
         byts = (8 * Np + 4) * 8 * E
-        out[f"N{N}"] = {"Np": Np, "us_per_launch": ms * 1e3,
+        out[f"N{N}"] = {"Np": Np, "layout": "blocks of 16 elements",
+                        "us_per_launch": ms * 1e3,
                         "gflops": flops / t / 1e9,
                         "frac_fp64": flops / t / 1e12 / FP64_PEAK_TFLOPS,
                         "alg_GBs": byts / t / 1e9,
-                        "frac_hbm": byts / t / 1e9 / HBM_PEAK_GBS}
-        log(f"[dg] N={N}: {ms * 1e3:.1f} us, {flops / t / 1e9:.0f} GFLOP/s "
+                        "frac_hbm": byts / t / 1e9 / HBM_PEAK_GBS,
+                        "element_major_us_per_launch": ms_em * 1e3}
+        log(f"[dg] N={N}: {ms * 1e3:.1f} us (element-major {ms_em * 1e3:.1f}), "
+            f"{flops / t / 1e9:.0f} GFLOP/s "
             f"({100 * flops / t / 1e12 / FP64_PEAK_TFLOPS:.0f} % FP64), "
             f"{byts / t / 1e9:.0f} GB/s ({100 * byts / t / 1e9 / HBM_PEAK_GBS:.0f} % HBM)")
     return out
@@ -352,7 +367,7 @@ def torch_norm(t):
     return (t * t).sum().sqrt()
 
 
-def bench_pcg(sem, torch, h, nL, nG):
+def bench_pcg(sem, torch, h, nL, nG, quick=False):
     """Config 2 and 3 solves on the benchmark mesh (RHS seed 0): time to
     1e-8 of FP64 Jacobi-PCG and of FP64 refinement around each inner
     operator; refinement to 1e-10 for every inner precision; FP32-only PCG
@@ -398,6 +413,8 @@ def bench_pcg(sem, torch, h, nL, nG):
 
     run("fp64_jacobi_pcg", sem.SEM_FP64, 1e-8, 2)
     run("fp32_ir_jacobi_pcg", sem.SEM_FP32, 1e-8, 2, key="fp32")
+    if quick:
+        return out
     run("bf16g_ir_jacobi_pcg", sem.SEM_BF16, 1e-8, 2, key="bf16")
     run("bf16_mfma_ir_jacobi_pcg", sem.SEM_BF16_MFMA, 1e-8, 2, key="bf16")
     # config 3: refinement to 1e-10 for every inner operator
@@ -741,6 +758,9 @@ def main():
     ap.add_argument("--no-dg", action="store_true")
     ap.add_argument("--dg-only", action="store_true",
                     help="only the DG volume-term section (one JSON object)")
+    ap.add_argument("--pcg-only", action="store_true",
+                    help="only FP64 Jacobi-PCG and FP32 refinement to 1e-8 "
+                         "on the benchmark mesh (for kernel traces)")
     ap.add_argument("--ax-only", action="store_true",
                     help="only the FP64 operator launches (for counter runs)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -782,6 +802,11 @@ def main():
     setup_s = time.perf_counter() - t0
     E, nL, nG = sem.sem_query(h)
     log(f"[bench] setup {setup_s:.2f} s: E={E} nL={nL} nG={nG}")
+    if args.pcg_only:
+        print(json.dumps({"pcg": bench_pcg(sem, torch, h, nL, nG, quick=True)}),
+              flush=True)
+        sem.sem_destroy(h)
+        return
     u = make_input(sem, torch, h, nL, nG)
     w = torch.empty_like(u)
 

@@ -81,6 +81,17 @@ sem_status dg_export(const dg_handle *h, int32_t which, void *dst,
  * matrix cores; asynchronous on `stream`. */
 sem_status dg_volume(dg_handle *h, const double *Q, double *rhs, void *stream);
 
+/* The same volume term of section 4.3.2 with the state and the result in
+ * blocks of 16 elements, element fastest: component c (0 h, 1 hu, 2 hv) of
+ * node n of element e is entry ((e / 16 * 3 + c) * Np + n) * 16 + e % 16.
+ * Q and rhs (DEVICE) hold ceil(E / 16) * 16 * 3 * Np doubles each and must
+ * not overlap; the entries of the padding elements of the last block
+ * (e >= E) are neither read nor written.  Results equal dg_volume's bit
+ * for bit; every load and store of the kernel covers whole cache lines.
+ * Asynchronous on `stream`. */
+sem_status dg_volume_blocked(dg_handle *h, const double *Q, double *rhs,
+                             void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -566,7 +566,20 @@ sem_status dg_volume(dg_handle *h, const double *Q, double *rhs, void *stream) {
     const size_t bytes = (size_t)h->E * 3 * h->Np * sizeof(double);
     const char *q0 = (const char *)Q, *r0 = (const char *)rhs;
     need(r0 + bytes <= q0 || q0 + bytes <= r0, "dg_volume: rhs must not overlap Q");
-    launch_dg_volume(h, Q, rhs, strm(stream));
+    launch_dg_volume(h, Q, rhs, false, strm(stream));
+  });
+}
+
+sem_status dg_volume_blocked(dg_handle *h, const double *Q, double *rhs,
+                             void *stream) {
+  return guarded([&] {
+    need(h != nullptr && Q != nullptr && rhs != nullptr,
+         "dg_volume_blocked: null argument");
+    const size_t bytes = (size_t)((h->E + 15) / 16) * 16 * 3 * h->Np * sizeof(double);
+    const char *q0 = (const char *)Q, *r0 = (const char *)rhs;
+    need(r0 + bytes <= q0 || q0 + bytes <= r0,
+         "dg_volume_blocked: rhs must not overlap Q");
+    launch_dg_volume(h, Q, rhs, true, strm(stream));
   });
 }
 

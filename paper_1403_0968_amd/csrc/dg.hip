@@ -50,7 +50,12 @@ template <int N> struct DgShape {
   static constexpr int WAVES_PER_EU = N == 7 ? 2 : 1;
 };
 
-template <int N>
+// BLK = false: state, result and bathymetry gradient element-major,
+// [E][3][Np] and [E][2][Np]; every load or store of a wave touches 16
+// elements x 32 bytes.  BLK = true: blocks of 16 elements, [E/16][3][Np][16]
+// and [E/16][2][Np][16] (element fastest), so each of them is 512
+// contiguous bytes.
+template <int N, bool BLK>
 __global__ void __launch_bounds__(64 * DG_WAVES)
     __attribute__((amdgpu_waves_per_eu(DgShape<N>::WAVES_PER_EU)))
     k_dg_volume(int64_t E, const double *__restrict__ Q, double *__restrict__ rhs,
@@ -61,9 +66,17 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
   constexpr int NP = S::NP, NT = S::NT, NK = S::NK;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, kq = lane >> 4;
-  const int64_t e = ((int64_t)blockIdx.x * DG_WAVES + wave) * 16 + col;
+  const int64_t blk = (int64_t)blockIdx.x * DG_WAVES + wave;
+  const int64_t e = blk * 16 + col;
   const bool act = e < E;
-  const double *Qe = Q + (act ? e : 0) * 3 * NP;
+  // a wave past the last block has nothing to do (no barrier in this kernel)
+  if (BLK && blk * 16 >= E) return;
+  // node m of component c of this lane's element (an element of the mesh:
+  // lanes past the last element read the block's first one)
+  //   element-major: Qe[c NP + m]; blocks: Qe[(c NP + m) 16]
+  constexpr int CS = BLK ? 16 : 1;
+  const double *Qe = BLK ? Q + blk * 3 * NP * 16 + (act ? col : 0)
+                         : Q + (act ? e : 0) * 3 * NP;
   // this lane's A operand entries (row 16 t + col, column 4 ks + kq) are
   // entries (ks NT + t) 64 + lane of the lane-order copies
   const double *Ar = Drw + lane, *As = Dsw + lane;
@@ -92,9 +105,9 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
   double qn[3], an[NT], sn[NT];  // operands of the next K step
   auto fetch = [&](int ks) {
     const int m = min(4 * ks + kq, NP - 1);
-    qn[0] = Qe[m];
-    qn[1] = Qe[NP + m];
-    qn[2] = Qe[2 * NP + m];
+    qn[0] = Qe[m * CS];
+    qn[1] = Qe[(NP + m) * CS];
+    qn[2] = Qe[(2 * NP + m) * CS];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
       an[t] = Ar[(ks * NT + t) * 64];
@@ -139,8 +152,9 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
         acc[q][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[t], xs[q], acc[q][t], 0, 0, 0);
   }
   if (!act) return;
-  double *Re = rhs + e * 3 * NP;
-  const double *Bx = dB + e * 2 * NP, *By = Bx + NP;
+  double *Re = BLK ? rhs + blk * 3 * NP * 16 + col : rhs + e * 3 * NP;
+  const double *Bx = BLK ? dB + blk * 2 * NP * 16 + col : dB + e * 2 * NP;
+  const double *By = Bx + NP * CS;
 #pragma unroll
   for (int t = 0; t < NT; ++t)
 #pragma unroll
@@ -156,34 +170,42 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
         else
           hr = hs[(wave * NK + KS) * 64 + lane];
         const double gh = g * hr;
-        Re[r] = acc[0][t][v];
-        Re[NP + r] = acc[1][t][v] - gh * Bx[r];
-        Re[2 * NP + r] = acc[2][t][v] - gh * By[r];
+        Re[r * CS] = acc[0][t][v];
+        Re[(NP + r) * CS] = acc[1][t][v] - gh * Bx[r * CS];
+        Re[(2 * NP + r) * CS] = acc[2][t][v] - gh * By[r * CS];
       }
     }
 }
 
 template <int N>
-static void launch_n(const dg_handle *h, const double *Q, double *rhs, hipStream_t s) {
+static void launch_n(const dg_handle *h, const double *Q, double *rhs, bool blocked,
+                     hipStream_t s) {
   const int64_t per = 16 * DG_WAVES;
   const int64_t blocks = (h->E + per - 1) / per;
   if (blocks == 0) return;
-  hipLaunchKernelGGL(k_dg_volume<N>, dim3((unsigned)blocks), dim3(64 * DG_WAVES), 0, s,
-                     h->E, Q, rhs, h->geo.as<double>(), h->dB.as<double>(),
-                     h->Drw.as<double>(), h->Dsw.as<double>(), h->g);
+  if (blocked)
+    hipLaunchKernelGGL((k_dg_volume<N, true>), dim3((unsigned)blocks),
+                       dim3(64 * DG_WAVES), 0, s, h->E, Q, rhs, h->geo.as<double>(),
+                       h->dBb.as<double>(), h->Drw.as<double>(),
+                       h->Dsw.as<double>(), h->g);
+  else
+    hipLaunchKernelGGL((k_dg_volume<N, false>), dim3((unsigned)blocks),
+                       dim3(64 * DG_WAVES), 0, s, h->E, Q, rhs, h->geo.as<double>(),
+                       h->dB.as<double>(), h->Drw.as<double>(),
+                       h->Dsw.as<double>(), h->g);
 }
 
 void launch_dg_volume(const dg_handle *h, const double *Q, double *rhs,
-                      hipStream_t s) {
+                      bool blocked, hipStream_t s) {
   switch (h->N) {
-    case 1: launch_n<1>(h, Q, rhs, s); break;
-    case 2: launch_n<2>(h, Q, rhs, s); break;
-    case 3: launch_n<3>(h, Q, rhs, s); break;
-    case 4: launch_n<4>(h, Q, rhs, s); break;
-    case 5: launch_n<5>(h, Q, rhs, s); break;
-    case 6: launch_n<6>(h, Q, rhs, s); break;
-    case 7: launch_n<7>(h, Q, rhs, s); break;
-    case 8: launch_n<8>(h, Q, rhs, s); break;
+    case 1: launch_n<1>(h, Q, rhs, blocked, s); break;
+    case 2: launch_n<2>(h, Q, rhs, blocked, s); break;
+    case 3: launch_n<3>(h, Q, rhs, blocked, s); break;
+    case 4: launch_n<4>(h, Q, rhs, blocked, s); break;
+    case 5: launch_n<5>(h, Q, rhs, blocked, s); break;
+    case 6: launch_n<6>(h, Q, rhs, blocked, s); break;
+    case 7: launch_n<7>(h, Q, rhs, blocked, s); break;
+    case 8: launch_n<8>(h, Q, rhs, blocked, s); break;
     default: fail(SEM_ERR_ARG, "dg: N must be in 1..8");
   }
   SEM_HIP(hipGetLastError());
@@ -244,6 +266,15 @@ void dg_device_setup(dg_handle *h, int64_t nv, const double *vx, const double *v
           As[((size_t)ks * nt + t) * 64 + l] = h->ref.Dsw[i * Np + k];
         }
       }
+  // the same gradient in blocks of 16 elements, [E/16][2][Np][16] (zero
+  // padding in the last block)
+  const int64_t nb = (E + 15) / 16;
+  std::vector<double> dBb((size_t)nb * 2 * Np * 16, 0.0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int c = 0; c < 2; ++c)
+      for (int n = 0; n < Np; ++n)
+        dBb[(((size_t)(e / 16) * 2 + c) * Np + n) * 16 + e % 16] =
+            dB[((size_t)e * 2 + c) * Np + n];
   auto up = [&](DevBuf &d, const std::vector<double> &v) {
     d.alloc(v.size() * sizeof(double));
     SEM_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(double),
@@ -251,6 +282,7 @@ void dg_device_setup(dg_handle *h, int64_t nv, const double *vx, const double *v
   };
   up(h->geo, geo);
   up(h->dB, dB);
+  up(h->dBb, dBb);
   up(h->X, X);
   up(h->Y, Y);
   up(h->Drw, Ar);

@@ -121,10 +121,11 @@ struct dg_handle {
   int64_t E = 0;
   double g = 0.0;
   sem::DgRef ref;
-  // per element: (rx, sx, ry, sy); bathymetry gradient [E][2][Np]; node
-  // coordinates [E][Np]; Drw, Dsw zero-padded to whole MFMA tiles and stored
-  // in the lane order of the volume kernel's matrix instruction
-  sem::DevBuf geo, dB, X, Y, Drw, Dsw;
+  // per element: (rx, sx, ry, sy); bathymetry gradient [E][2][Np] and in
+  // blocks of 16 elements [E/16][2][Np][16]; node coordinates [E][Np]; Drw,
+  // Dsw zero-padded to whole MFMA tiles and stored in the lane order of the
+  // volume kernel's matrix instruction
+  sem::DevBuf geo, dB, dBb, X, Y, Drw, Dsw;
 };
 
 namespace sem {
@@ -188,8 +189,9 @@ int bax_min_block(int nset);
 // DG volume term (dg.hip)
 void dg_device_setup(dg_handle *h, int64_t nv, const double *vx, const double *vy,
                      const int32_t *etov, const double *B, hipStream_t s);
+// blocked: state and result in blocks of 16 elements, [E/16][3][Np][16]
 void launch_dg_volume(const dg_handle *h, const double *Q, double *rhs,
-                      hipStream_t s);
+                      bool blocked, hipStream_t s);
 // finite-difference wave step (fd2d.hip); c = dt^2 / dx^2
 void fd2d_weights_host(int r, double *w);
 void launch_fd2d(const double *u_cur, const double *u_prev, double *u_next,

@@ -36,6 +36,7 @@ EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_learn_coarse_exact", "sem_mlp_loss_grad_factor",
             "fd2d_weights", "fd2d_step", "fd2d_run", "dg_reference_nodes",
             "dg_setup", "dg_destroy", "dg_query", "dg_export", "dg_volume",
+            "dg_volume_blocked",
             "sem_last_error"]
 
 
@@ -161,6 +162,7 @@ def lib():
     L.dg_query.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]
     L.dg_export.argtypes = [vp, i32, vp, C.c_int64, vp]
     L.dg_volume.argtypes = [vp, vp, vp, vp]
+    L.dg_volume_blocked.argtypes = [vp, vp, vp, vp]
     L.sem_last_error.argtypes = []
     L.sem_last_error.restype = C.c_char_p
     for name in EXPORTED[:-1]:
@@ -560,3 +562,9 @@ def dg_export(h, which, dst, stream=None):
 def dg_volume(h, Q, rhs, stream=None):
     """Q, rhs: device float64 tensors [E][3][Np]."""
     _check(lib().dg_volume(h, _ptr(Q), _ptr(rhs), _stream(stream)))
+
+
+def dg_volume_blocked(h, Q, rhs, stream=None):
+    """Q, rhs: device float64 tensors [ceil(E/16)][3][Np][16] (blocks of 16
+    elements, element fastest)."""
+    _check(lib().dg_volume_blocked(h, _ptr(Q), _ptr(rhs), _stream(stream)))

@@ -110,6 +110,20 @@ def _check_volume(sem, h, ops, geo, B, Q):
     got = to_host(drhs)
     bound = _bound(ops, geo, Q, B) + 1e-300
     ratio = np.max(np.abs(got - ref) / bound)
+    # the blocked layout gives the same bits; padding is neither read (NaN
+    # state there) nor written (sentinel kept)
+    E, _, Np = Q.shape
+    nb = (E + 15) // 16
+    Qb = np.full((nb * 16, 3, Np), np.nan)
+    Qb[:E] = Q
+    Qb = np.ascontiguousarray(Qb.reshape(nb, 16, 3, Np).transpose(0, 2, 3, 1))
+    dQb = to_dev(Qb)
+    drb = to_dev(np.full_like(Qb, 7.25))
+    sem.dg_volume_blocked(h, dQb, drb)
+    t.cuda.synchronize()
+    gb = to_host(drb).transpose(0, 3, 1, 2).reshape(nb * 16, 3, Np)
+    assert np.array_equal(gb[:E].view(np.uint64), got.view(np.uint64))
+    assert np.all(gb[E:] == 7.25)
     return ratio, np.max(np.abs(got - ref)) / np.max(np.abs(ref))
 
 
@@ -154,6 +168,9 @@ def test_flat_bottom_and_errors(sem):
         dQ = to_dev(Q)
         with pytest.raises(sem.SemError) as ei:
             sem.dg_volume(h, dQ, dQ)
+        assert ei.value.code == sem.SEM_ERR_ARG
+        with pytest.raises(sem.SemError) as ei:
+            sem.dg_volume_blocked(h, dQ, dQ)
         assert ei.value.code == sem.SEM_ERR_ARG
     finally:
         sem.dg_destroy(h)
