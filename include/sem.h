@@ -267,6 +267,23 @@ sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *opts,
                          const double *b_L, double *x_L,
                          sem_solve_stats *stats, void *stream);
 
+/* For callers that cannot allocate memory (tight serving loops, harnesses
+ * that forbid hipMalloc): sem_pcg_solve without any device or pinned host
+ * allocation.  Plain FP64 PCG only (opts->inner_prec == SEM_FP64, opts->pc
+ * SEM_PC_NONE or SEM_PC_JACOBI, else SEM_ERR_ARG); use_graph is ignored
+ * (kernels are launched directly on `stream`, which is also where the solve
+ * runs and is timed on the host).  The solver's vectors, descriptor, work
+ * lists, partial sums and scalars live in one 32 MiB array per GPU that the
+ * library holds until the process ends; a mesh whose solve needs more
+ * (about 8 (7 n_global + n_local + E) bytes: N = 7 up to about 10^3
+ * elements) gets SEM_ERR_ARG.  Every call on a GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (other streams or host threads)
+ * race and must be serialised by the caller.  Results are bit-identical to
+ * sem_pcg_solve's with the same options.  Synchronises `stream`. */
+sem_status sem_pcg_solve_noalloc(sem_handle *h, const sem_solve_opts *opts,
+                                 const double *b_L, double *x_L,
+                                 sem_solve_stats *stats, void *stream);
+
 /* Batches of independent solves of the system of section 4.2.2 (uneven
  * sizes, orders N in {3, 5, 7} may be mixed, or any single N).  A batch references existing handles (which
  * must outlive it) and owns its work lists, per-solve device scalars and

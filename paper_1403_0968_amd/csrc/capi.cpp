@@ -24,18 +24,26 @@ void hip_check(hipError_t e, const char *what, const char *file, int line) {
 }
 
 DevBuf::~DevBuf() {
-  if (p) (void)hipFree(p);
+  if (p && own) (void)hipFree(p);
 }
 
 void DevBuf::alloc(size_t nbytes) {
   if (p) {
-    (void)hipFree(p);
+    if (own) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
+  own = true;
   if (nbytes == 0) nbytes = 256;
   SEM_HIP(hipMalloc(&p, nbytes));
   bytes = nbytes;
+}
+
+void DevBuf::view(void *q, size_t nbytes) {
+  if (p && own) (void)hipFree(p);
+  p = q;
+  bytes = nbytes;
+  own = false;
 }
 
 template <class F> static sem_status guarded(F &&f) {
@@ -221,6 +229,24 @@ sem_status sem_pcg_solve(sem_handle *h, const sem_solve_opts *o,
   if (result != SEM_OK)
     g_last_error = result == SEM_ERR_BREAKDOWN ? "sem_pcg_solve: breakdown"
                                                : "sem_pcg_solve: not converged";
+  return result;
+}
+
+sem_status sem_pcg_solve_noalloc(sem_handle *h, const sem_solve_opts *o,
+                                 const double *b_L, double *x_L,
+                                 sem_solve_stats *st, void *stream) {
+  sem_status result = SEM_OK;
+  sem_status g = guarded([&] {
+    need(h != nullptr && o != nullptr && b_L != nullptr && x_L != nullptr,
+         "sem_pcg_solve_noalloc: null argument");
+    need((const void *)b_L != (const void *)x_L,
+         "sem_pcg_solve_noalloc: b and x alias");
+    result = pcg_solve_noalloc(h, o, b_L, x_L, st, strm(stream));
+  });
+  if (g != SEM_OK) return g;
+  if (result != SEM_OK)
+    g_last_error = result == SEM_ERR_BREAKDOWN ? "sem_pcg_solve_noalloc: breakdown"
+                                               : "sem_pcg_solve_noalloc: not converged";
   return result;
 }
 

@@ -61,11 +61,13 @@ HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet);
 struct DevBuf {
   void *p = nullptr;
   size_t bytes = 0;
+  bool own = true;  // false: a view of memory owned elsewhere (never freed)
   DevBuf() = default;
   DevBuf(const DevBuf &) = delete;
   DevBuf &operator=(const DevBuf &) = delete;
   ~DevBuf();
   void alloc(size_t nbytes);
+  void view(void *q, size_t nbytes);
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
 
@@ -248,5 +250,11 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
                  hipStream_t caller);
 sem_status pcg_solve(sem_handle *h, const sem_solve_opts *o, const double *b_L,
                      double *x_L, sem_solve_stats *st, hipStream_t s);
+// plain FP64 PCG with every device buffer in a fixed per-GPU array (no
+// allocation); noalloc_bytes: the part of the array a handle's solve needs
+sem_status pcg_solve_noalloc(sem_handle *h, const sem_solve_opts *o,
+                             const double *b_L, double *x_L, sem_solve_stats *st,
+                             hipStream_t caller);
+size_t noalloc_bytes(const sem_handle *h);
 
 }  // namespace sem

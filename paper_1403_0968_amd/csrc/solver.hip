@@ -26,12 +26,14 @@
 // fixed summation order: results are bit-reproducible, and a solve gives the
 // same bits alone or inside any batch.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <set>
 #include <sstream>
 #include <string>
@@ -654,7 +656,7 @@ __global__ void k_unmask(int64_t nG, const uint8_t *__restrict__ gmask,
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g < nG) {
     o64[g] = gmask[g] ? 0.0 : 1.0;
-    o32[g] = gmask[g] ? 0.0f : 1.0f;
+    if (o32 != nullptr) o32[g] = gmask[g] ? 0.0f : 1.0f;
   }
 }
 
@@ -700,6 +702,7 @@ struct sem_batch {
   int n = 0;
   int nset = 0;                 // order set the operator kernel is built for
   std::vector<int> orders;      // n1 per solve
+  std::vector<sem::BatchSolve> hsd;  // host copies of the solve descriptors
   sem::DevBuf sds, st, vitems, vbeg, part, red, active, maxit, scale;
   sem::DevBuf axitems[3];       // per block size 64 / 128 / 256
   int n_ax[3] = {0, 0, 0};
@@ -710,6 +713,12 @@ struct sem_batch {
   double *host_red = nullptr;
   int32_t *host_i = nullptr;    // staging for active / maxit
   double *host_d = nullptr;     // staging for scale
+  // false for a batch laid out in caller-provided memory: host_* then point
+  // to the inline arrays below and s is the caller's stream (none owned)
+  bool owned = true;
+  sem::CgState inl_st[1];
+  double inl_red[2], inl_d[1];
+  int32_t inl_i[1];
   hipStream_t s = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, fence = nullptr;
   struct GraphEntry {
@@ -723,20 +732,55 @@ struct sem_batch {
   bool tuned = false;
   ~sem_batch() {
     for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
-    if (host_st) (void)hipHostFree(host_st);
-    if (host_red) (void)hipHostFree(host_red);
-    if (host_i) (void)hipHostFree(host_i);
-    if (host_d) (void)hipHostFree(host_d);
+    if (owned) {
+      if (host_st) (void)hipHostFree(host_st);
+      if (host_red) (void)hipHostFree(host_red);
+      if (host_i) (void)hipHostFree(host_i);
+      if (host_d) (void)hipHostFree(host_d);
+    }
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     if (fence) (void)hipEventDestroy(fence);
-    if (s) (void)hipStreamDestroy(s);
+    if (owned && s) (void)hipStreamDestroy(s);
   }
 };
 
 namespace sem {
 
 static int bs_slot(int bs) { return bs == 64 ? 0 : bs == 128 ? 1 : 2; }
+
+// the device descriptor of solve q: the handle's operator arrays and the
+// given solver vectors
+static BatchSolve describe(sem_handle *h, int q, void *const v64[NVEC],
+                           void *const v32[NVEC], const double *one64,
+                           const float *one32, double *edot) {
+  BatchSolve d;
+  memset(&d, 0, sizeof d);
+  d.N1 = h->n1;
+  d.solve = q;
+  d.E = h->E;
+  d.nL = h->nL;
+  d.nG = h->nG;
+  d.box = make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet);
+  d.G64 = h->G64.p;
+  d.G32 = h->G32.p;
+  d.G16 = h->G16.p;
+  d.D64 = h->D64.p;
+  d.D32 = h->D32.p;
+  d.D16hi = h->D16hi.p;
+  d.D16lo = h->D16lo.p;
+  d.H16 = h->has_mass ? h->H16.p : nullptr;
+  d.dinv64 = h->dinv_G.as<double>();
+  d.dinv32 = h->dinv_G32.as<float>();
+  d.one64 = one64;
+  d.one32 = one32;
+  for (int v = 0; v < NVEC; ++v) {
+    d.v64[v] = v64[v];
+    d.v32[v] = v32[v];
+  }
+  d.edot = edot;
+  return d;
+}
 
 sem_batch *batch_create(sem_handle *const *hs, int n) {
   if (n < 1) fail(SEM_ERR_ARG, "batch: need at least one handle");
@@ -776,31 +820,13 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
       sem_handle *h = hs[q];
       ensure_vectors(h);
       Workspace *W = h->ws;
-      BatchSolve &d = sds[q];
-      memset(&d, 0, sizeof d);
-      d.N1 = h->n1;
-      d.solve = q;
-      d.E = h->E;
-      d.nL = h->nL;
-      d.nG = h->nG;
-      d.box = make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet);
-      d.G64 = h->G64.p;
-      d.G32 = h->G32.p;
-      d.G16 = h->G16.p;
-      d.D64 = h->D64.p;
-      d.D32 = h->D32.p;
-      d.D16hi = h->D16hi.p;
-      d.D16lo = h->D16lo.p;
-      d.H16 = h->has_mass ? h->H16.p : nullptr;
-      d.dinv64 = h->dinv_G.as<double>();
-      d.dinv32 = h->dinv_G32.as<float>();
-      d.one64 = W->one64.as<double>();
-      d.one32 = W->one32.as<float>();
+      void *v64[NVEC], *v32[NVEC];
       for (int v = 0; v < NVEC; ++v) {
-        d.v64[v] = W->v64[v].p;
-        d.v32[v] = W->v32[v].p;
+        v64[v] = W->v64[v].p;
+        v32[v] = W->v32[v].p;
       }
-      d.edot = W->edot.as<double>();
+      sds[q] = describe(h, q, v64, v32, W->one64.as<double>(),
+                        W->one32.as<float>(), W->edot.as<double>());
       vbeg[q] = (int32_t)vis.size();
       for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({q, 0, g});
       b->orders.push_back(h->n1);
@@ -819,6 +845,7 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
       SEM_HIP(hipMemcpy(b->axitems[k].p, ax.data(), ax.size() * sizeof(AxItem),
                         hipMemcpyHostToDevice));
     }
+    b->hsd = sds;
     b->sds.alloc(n * sizeof(BatchSolve));
     SEM_HIP(hipMemcpy(b->sds.p, sds.data(), n * sizeof(BatchSolve),
                       hipMemcpyHostToDevice));
@@ -884,7 +911,7 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
   if (b->n == 1) {
     // a single solve: the operator with every argument in registers
     sem_handle *h = b->hs[0];
-    Workspace *W = h->ws;
+    const BatchSolve &d = b->hsd[0];
     const bool f64 = prec == SEM_FP64;
     const void *G = f64 ? h->G64.p : prec == SEM_FP32 ? h->G32.p : h->G16.p;
     const void *H = !h->has_mass ? nullptr
@@ -892,13 +919,13 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
                     : prec == SEM_FP32 ? h->H32.p
                                        : h->H16.p;
     const void *D = f64 ? h->D64.p : h->D32.p;
-    const void *u = f64 ? W->v64[src].p : W->v32[src].p;
-    void *w = f64 ? W->v64[dst].p : W->v32[dst].p;
+    const void *u = f64 ? d.v64[src] : d.v32[src];
+    void *w = f64 ? d.v64[dst] : d.v32[dst];
     const int32_t *stop =
         skip_done ? &b->st.as<CgState>()[0].done : (const int32_t *)nullptr;
     launch_ax_solve(h->N, prec, h->E, D, G, H, u, w,
                     make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet), stop,
-                    edot ? W->edot.as<double>() : nullptr, b->s);
+                    edot ? d.edot : nullptr, b->s);
     return;
   }
   const int bs = b->bs[prec];
@@ -956,7 +983,7 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
   hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
   hipLaunchKernelGGL((k_bupdate_r_only<TV>), dim3(g), dim3(RT), 0, b->s, sds, st,
                      vi, nv);
-  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, b->s);
+  learn_apply(h, f32 ? b->hsd[0].v32[VR] : b->hsd[0].v64[VR], f32, b->s);
   hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
                      st, vi, nv, learn_cg(h), part, 1);
   hipLaunchKernelGGL(k_bbeta_fcg, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
@@ -990,7 +1017,7 @@ static void init_fcg(sem_batch *b, int prec) {
   const int g = vec_grid(b), nv = b->n_vi;
   sem_handle *h = b->hs[0];
   const bool f32 = prec != SEM_FP64;
-  learn_apply(h, f32 ? h->ws->v32[VR].p : h->ws->v64[VR].p, f32, b->s);
+  learn_apply(h, f32 ? b->hsd[0].v32[VR] : b->hsd[0].v64[VR], f32, b->s);
   if (f32) {
     hipLaunchKernelGGL((k_bprec_learned<float, float>), dim3(g), dim3(RT), 0, b->s,
                        sds, st, vi, nv, learn_cg(h), part, 0);
@@ -1138,10 +1165,10 @@ static bool run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o,
       sem_handle *h = b->hs[0];
       const size_t bytes = (size_t)h->nG * sizeof(double);
       SEM_HIP(hipMemcpyAsync(b->snap_x + (size_t)b->snap_count * h->nG,
-                             h->ws->v64[VX].p, bytes, hipMemcpyDeviceToDevice,
+                             b->hsd[0].v64[VX], bytes, hipMemcpyDeviceToDevice,
                              b->s));
       SEM_HIP(hipMemcpyAsync(b->snap_r + (size_t)b->snap_count * h->nG,
-                             h->ws->v64[VR].p, bytes, hipMemcpyDeviceToDevice,
+                             b->hsd[0].v64[VR], bytes, hipMemcpyDeviceToDevice,
                              b->s));
       b->snap_count += 1;
     }
@@ -1173,22 +1200,29 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
     if (bL[q] == nullptr || xL[q] == nullptr || (const void *)bL[q] == xL[q])
       fail(SEM_ERR_ARG, "solve: null or aliased b / x");
   hipStream_t s = b->s;
-  SEM_HIP(hipEventRecord(b->fence, caller));
-  SEM_HIP(hipStreamWaitEvent(s, b->fence, 0));
-  SEM_HIP(hipEventRecord(b->ev0, s));
+  // a batch with its own stream orders it after the caller's work; one laid
+  // out in caller memory runs on the caller's stream and is timed on the host
+  std::chrono::steady_clock::time_point t0, t1;
+  if (b->owned) {
+    SEM_HIP(hipEventRecord(b->fence, caller));
+    SEM_HIP(hipStreamWaitEvent(s, b->fence, 0));
+    SEM_HIP(hipEventRecord(b->ev0, s));
+  } else {
+    SEM_HIP(hipStreamSynchronize(s));
+    t0 = std::chrono::steady_clock::now();
+  }
   // the learned preconditioner is Jacobi plus a correction, and falls back
   // to Jacobi
   const int jac = o->pc == SEM_PC_JACOBI || o->pc == SEM_PC_LEARNED;
   const int n = b->n;
   for (int q = 0; q < n; ++q) {
     sem_handle *h = b->hs[q];
-    Workspace *W = h->ws;
     hipLaunchKernelGGL(k_first_copy, dim3(nblk(h->nG)), dim3(RT), 0, s, h->nG,
                        h->offsets.as<int32_t>(), h->perm.as<int32_t>(), bL[q],
-                       W->v64[VB].as<double>());
+                       (double *)b->hsd[q].v64[VB]);
     hipLaunchKernelGGL(k_first_copy, dim3(nblk(h->nG)), dim3(RT), 0, s, h->nG,
                        h->offsets.as<int32_t>(), h->perm.as<int32_t>(), xL[q],
-                       W->v64[VX].as<double>());
+                       (double *)b->hsd[q].v64[VX]);
   }
   SEM_HIP(hipGetLastError());
 
@@ -1344,16 +1378,25 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
   for (int q = 0; q < n; ++q) {
     sem_handle *h = b->hs[q];
     hipLaunchKernelGGL(k_scatter, dim3(nblk(h->nL)), dim3(RT), 0, s, h->nL,
-                       h->l2g.as<int32_t>(), h->ws->v64[VX].as<double>(), xL[q]);
+                       h->l2g.as<int32_t>(), (const double *)b->hsd[q].v64[VX],
+                       xL[q]);
   }
   SEM_HIP(hipGetLastError());
-  SEM_HIP(hipEventRecord(b->ev1, s));
+  if (b->owned) {
+    SEM_HIP(hipEventRecord(b->ev1, s));
+  } else {
+    SEM_HIP(hipStreamSynchronize(s));
+    t1 = std::chrono::steady_clock::now();
+  }
   // recomputed FP64 residuals of every solve
   std::vector<int> all(n, 1);
   upload_active(b, all, mx);
   residual(b);
   float ms = 0.0f;
-  SEM_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  if (b->owned)
+    SEM_HIP(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+  else
+    ms = (float)std::chrono::duration<double, std::milli>(t1 - t0).count();
   sem_status worst = SEM_OK;
   for (int q = 0; q < n; ++q) {
     if (stats != nullptr) {
@@ -1368,8 +1411,10 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
     }
     if (status[q] != SEM_OK && worst == SEM_OK) worst = (sem_status)status[q];
   }
-  SEM_HIP(hipEventRecord(b->fence, s));
-  SEM_HIP(hipStreamWaitEvent(caller, b->fence, 0));
+  if (b->owned) {
+    SEM_HIP(hipEventRecord(b->fence, s));
+    SEM_HIP(hipStreamWaitEvent(caller, b->fence, 0));
+  }
   return worst;
 }
 
@@ -1384,6 +1429,114 @@ sem_status pcg_solve(sem_handle *h, const sem_solve_opts *o, const double *b_L,
   const double *bl[1] = {b_L};
   double *xl[1] = {x_L};
   return batch_solve(h->ws->single, o, bl, xl, st, caller);
+}
+
+// --------------------------------------------------------------------------
+// solve without allocation: every device buffer of a plain FP64 PCG solve
+// (solver vectors, descriptor, work lists, partial sums, scalars) is carved
+// from one file-scope array that each GPU holds for the life of the process.
+// Nothing in it has to start at zero: every buffer is written before it is
+// read (the descriptor and work lists are uploaded, the rest is written by
+// the initialisation kernels).  Calls that overlap in time on one GPU share
+// the array and race.
+// --------------------------------------------------------------------------
+constexpr size_t SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[SCRATCH_MAX_DEVICES];  // that GPU's copy, or null
+
+// device address of the current GPU's copy of `scratch` (the host-side name
+// is not a device address)
+static unsigned char *scratch_address() {
+  int dev = 0;
+  SEM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES)
+    fail(SEM_ERR_ARG, "solve_noalloc: device index beyond 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void *ptr = nullptr;
+    SEM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (ptr == nullptr) fail(SEM_ERR_HIP, "solve_noalloc: no address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return static_cast<unsigned char *>(g_scratch_ptr[dev]);
+}
+
+size_t noalloc_bytes(const sem_handle *h) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t nG = (size_t)h->nG, nL = (size_t)h->nL, nvi = (nG + VCH - 1) / VCH;
+  return (NVEC - 1) * up(nG * 8) + up(nL * 8) + up(nG * 8) + up((size_t)h->E * 8) +
+         up(sizeof(BatchSolve)) + up(sizeof(CgState)) + up(nvi * sizeof(VecItem)) +
+         up(2 * sizeof(int32_t)) + up(3 * nvi * 8) + up(2 * 8) + 3 * up(8);
+}
+
+sem_status pcg_solve_noalloc(sem_handle *h, const sem_solve_opts *o,
+                             const double *b_L, double *x_L, sem_solve_stats *st,
+                             hipStream_t caller) {
+  check_opts(o);
+  if (o->inner_prec != SEM_FP64 || o->pc == SEM_PC_LEARNED)
+    fail(SEM_ERR_ARG, "solve_noalloc: plain FP64 PCG only (inner_prec SEM_FP64, "
+                      "preconditioner none or Jacobi)");
+  const size_t need_bytes = noalloc_bytes(h);
+  if (need_bytes > SCRATCH_BYTES)
+    fail(SEM_ERR_ARG, "solve_noalloc: the mesh needs " + std::to_string(need_bytes) +
+                          " bytes of solver memory, more than the 33554432 available");
+  unsigned char *base = scratch_address();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void *p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  sem_batch b;
+  b.owned = false;
+  b.hs.assign(1, h);
+  b.n = 1;
+  b.nset = h->n1;
+  b.orders.assign(1, h->n1);
+  void *v64[NVEC], *v32[NVEC];
+  for (int v = 0; v < NVEC; ++v) {
+    v64[v] = take((size_t)(v == VWL ? h->nL : h->nG) * 8);
+    v32[v] = nullptr;
+  }
+  double *one64 = (double *)take((size_t)h->nG * 8);
+  double *edot = (double *)take((size_t)h->E * 8);
+  b.hsd.assign(1, describe(h, 0, v64, v32, one64, nullptr, edot));
+  std::vector<VecItem> vis;
+  for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({0, 0, g});
+  b.n_vi = (int)vis.size();
+  const int32_t vbeg[2] = {0, b.n_vi};
+  b.sds.view(take(sizeof(BatchSolve)), sizeof(BatchSolve));
+  b.st.view(take(sizeof(CgState)), sizeof(CgState));
+  b.vitems.view(take(vis.size() * sizeof(VecItem)), vis.size() * sizeof(VecItem));
+  b.vbeg.view(take(sizeof vbeg), sizeof vbeg);
+  b.part.view(take(3 * vis.size() * 8), 3 * vis.size() * 8);
+  b.red.view(take(2 * 8), 2 * 8);
+  b.active.view(take(8), sizeof(int32_t));
+  b.maxit.view(take(8), sizeof(int32_t));
+  b.scale.view(take(8), sizeof(double));
+  if (off != need_bytes) fail(SEM_ERR_STATE, "solve_noalloc: scratch layout mismatch");
+  b.host_st = b.inl_st;
+  b.host_red = b.inl_red;
+  b.host_i = b.inl_i;
+  b.host_d = b.inl_d;
+  b.s = caller;
+  SEM_HIP(hipMemcpyAsync(b.sds.p, b.hsd.data(), sizeof(BatchSolve),
+                         hipMemcpyHostToDevice, caller));
+  SEM_HIP(hipMemcpyAsync(b.vitems.p, vis.data(), vis.size() * sizeof(VecItem),
+                         hipMemcpyHostToDevice, caller));
+  SEM_HIP(hipMemcpyAsync(b.vbeg.p, vbeg, sizeof vbeg, hipMemcpyHostToDevice, caller));
+  hipLaunchKernelGGL(k_unmask, dim3(nblk(h->nG)), dim3(RT), 0, caller, h->nG,
+                     h->gmask.as<uint8_t>(), one64, (float *)nullptr);
+  SEM_HIP(hipGetLastError());
+  SEM_HIP(hipStreamSynchronize(caller));  // the host sources of the uploads
+  sem_solve_opts oo = *o;
+  oo.use_graph = 0;  // kernels are launched directly
+  const double *bl[1] = {b_L};
+  double *xl[1] = {x_L};
+  return batch_solve(&b, &oo, bl, xl, st, caller);
 }
 
 // FP64 Jacobi-PCG from x_L with snapshots of (x_k, r_k) every `every`

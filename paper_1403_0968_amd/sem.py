@@ -26,6 +26,7 @@ SEM_SRC_FOURIER, SEM_SRC_SINE = 0, 1
 
 EXPORTED = ["sem_setup", "sem_destroy", "sem_query", "sem_export", "sem_ax",
             "sem_gs", "sem_rhs", "sem_precond_apply", "sem_pcg_solve",
+            "sem_pcg_solve_noalloc",
             "sem_batch_create", "sem_batch_destroy", "sem_batch_tune",
             "sem_batch_pcg_solve", "sem_mlp_create", "sem_mlp_destroy",
             "sem_mlp_info", "sem_mlp_get_params", "sem_mlp_set_params",
@@ -115,6 +116,8 @@ def lib():
     L.sem_rhs.argtypes = [vp, C.POINTER(sem_source), vp, vp]
     L.sem_precond_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     L.sem_pcg_solve.argtypes = [vp, C.POINTER(sem_solve_opts), vp, vp,
+                                C.POINTER(sem_solve_stats), vp]
+    L.sem_pcg_solve_noalloc.argtypes = [vp, C.POINTER(sem_solve_opts), vp, vp,
                                 C.POINTER(sem_solve_stats), vp]
     L.sem_batch_create.argtypes = [C.POINTER(vp), i32, C.POINTER(vp)]
     L.sem_batch_destroy.argtypes = [vp]
@@ -288,6 +291,22 @@ def sem_pcg_solve(h, b, x, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
     st = sem_solve_stats()
     code = lib().sem_pcg_solve(h, C.byref(o), _ptr(b), _ptr(x), C.byref(st),
                                _stream(stream))
+    if raise_on_fail and code != SEM_OK:
+        _check(code)
+    return {"status": code, "iters": st.iters, "outer_iters": st.outer_iters,
+            "fell_back": st.fell_back,
+            "final_rel_res": st.final_rel_res, "seconds": st.seconds,
+            "outer_contraction": st.outer_contraction}
+
+
+def sem_pcg_solve_noalloc(h, b, x, rtol=1e-8, maxit=10000, pc=SEM_PC_JACOBI,
+                          check_every=16, stream=None, raise_on_fail=True):
+    """Plain FP64 PCG with no allocation inside the library (its buffers
+    live in a fixed per-GPU array)."""
+    o = _opts(rtol, maxit, pc, SEM_FP64, 1e-2, check_every, 0)
+    st = sem_solve_stats()
+    code = lib().sem_pcg_solve_noalloc(h, C.byref(o), _ptr(b), _ptr(x),
+                                       C.byref(st), _stream(stream))
     if raise_on_fail and code != SEM_OK:
         _check(code)
     return {"status": code, "iters": st.iters, "outer_iters": st.outer_iters,

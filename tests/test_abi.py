@@ -123,5 +123,9 @@ def test_every_entry_point_cites_its_passage():
     decls = declaration_comments()
     assert len(decls) == len(declared_functions())
     for name, comment in decls:
+        if name == "sem_pcg_solve_noalloc":
+            # not an operation of the paper: its comment names its callers
+            assert "cannot allocate" in comment, name
+            continue
         assert re.search(r"section \d(\.\d)*", comment), \
             f"{name}: its comment cites no section of the paper"
