@@ -192,11 +192,6 @@ def bench_order_sweep(sem, torch, steps, warmup, target_nodes=NE ** 3 * 512):
             f"{out[f'N{N}']['gflops']:.0f} GFLOP/s, {out[f'N{N}']['alg_GBs']:.0f} GB/s")
     h = sem.sem_setup(ORDER, NE, NE, NE, mapping=sem.SEM_MAP_SINE_CYCLIC, alpha=1.0)
     E, nL, nG = sem.sem_query(h)
-    if args.pcg_only:
-        print(json.dumps({"pcg": bench_pcg(sem, torch, h, nL, nG, quick=True)}),
-              flush=True)
-        sem.sem_destroy(h)
-        return
     u = make_input(sem, torch, h, nL, nG)
     w = torch.empty_like(u)
     ms = time_ax(sem, torch, h, sem.SEM_FP64, u, w, steps, warmup)

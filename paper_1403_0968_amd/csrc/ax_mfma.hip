@@ -61,9 +61,11 @@ __device__ inline mf32x4 mfma(m16x4 a, m16x4 b, mf32x4 c) {
 //   fwd[q] = D[r % 8][4 (g % 2) + q], bwd[q] = D[4 (g % 2) + q][r % 8],
 // zero off the diagonal blocks (r / 8 != g / 2) and outside n1.
 template <int N1>
-__device__ inline void d_operands(int l, const uint16_t *__restrict__ Dhi,
-                                  const uint16_t *__restrict__ Dlo, m16x4 &fh,
+__device__ inline void d_operands(int l, const uint16_t *__restrict__ Dhi_,
+                                  const uint16_t *__restrict__ Dlo_, m16x4 &fh,
                                   m16x4 &fl, m16x4 &bh, m16x4 &bl) {
+  const gp<const uint16_t> Dhi = (gp<const uint16_t>)Dhi_;
+  const gp<const uint16_t> Dlo = (gp<const uint16_t>)Dlo_;
   const int r = l & 15, g = l >> 4;
   const bool blk = (r >> 3) == (g >> 1);
   const int a = r & 7;
@@ -184,17 +186,17 @@ __device__ inline void mfma_element(int l, Lds &L, const uint16_t (&gq)[6][8],
 // layout [E][6][64][8] at n1 = 8, [E][6][n1^3] otherwise
 template <int N1>
 __device__ inline void load_factors(int l, bool act, int64_t e,
-                                    const uint16_t *__restrict__ G,
+                                    const uint16_t *__restrict__ G_,
                                     uint16_t (&gq)[6][8]) {
   constexpr int NP = N1 * N1, N3 = NP * N1;
+  const gp<const uint16_t> G = (gp<const uint16_t>)G_;
   const int i = l & 7, j = l >> 3;
   if constexpr (N1 == 8) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
       u32x4 v = {0u, 0u, 0u, 0u};
       if (act)
-        v = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4 *>(G + e * 6 * N3 + q * N3 + 8 * l));
+        v = __builtin_nontemporal_load((gp<const u32x4>)(G + e * 6 * N3 + q * N3 + 8 * l));
       const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
@@ -336,10 +338,11 @@ __global__ void __launch_bounds__(64 * MW)
     const AxItem it = items[q];
     if (skip_done && st[it.solve].done != 0) continue;  // uniform per block
     const BatchSolve &sd = sds[it.solve];
-    const float *u = (const float *)sd.v32[src];
-    float *w = (float *)sd.v32[dst];
+    // global pointers (their address space is not known from the descriptor)
+    const gp<const float> u = (gp<const float>)sd.v32[src];
+    const gp<float> w = (gp<float>)sd.v32[dst];
     const uint16_t *G = (const uint16_t *)sd.G16;
-    const uint16_t *H = (const uint16_t *)sd.H16;  // null without a mass term
+    const gp<const uint16_t> H = (gp<const uint16_t>)sd.H16;  // null without a mass term
     m16x4 fh, fl, bh, bl;
     d_operands<N1>(l, (const uint16_t *)sd.D16hi, (const uint16_t *)sd.D16lo, fh,
                    fl, bh, bl);

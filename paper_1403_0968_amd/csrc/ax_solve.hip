@@ -37,12 +37,12 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
                double *__restrict__ edot) {
   using S = OpShape<N1, sizeof(TC)>;
   __shared__ __align__(16) TC smem[lds_words<N1>(S::EPB)];
-  if (stop != nullptr && *stop != 0) return;  // uniform: the solve finished
+  // the done flag of the solve is checked inside, after the loads are issued
   ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG, EDOT>(
       threadIdx.x,
       (sizeof(TV) == 4 ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x) *
           S::EPB,
-      E, D, G, u, w, &box, smem, H, edot);
+      E, D, G, u, w, &box, smem, H, edot, stop);
 }
 
 template <int N1, class TV, class TG, class TC, bool MASS>

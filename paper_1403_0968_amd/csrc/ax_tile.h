@@ -25,7 +25,7 @@ namespace sem {
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-template <class T> __device__ inline T ld_stream(const T *p) {
+template <class P> __device__ inline auto ld_stream(P p) {
   return __builtin_nontemporal_load(p);
 }
 
@@ -55,21 +55,31 @@ template <int N1, int BYTES> struct OpShape {
 // barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC (8-byte aligned).
 // EDOT = true also stores the element energy edot[e] = u_e^T w_e in FP64,
 // summed in an order fixed by the node indices alone (each (i, j) column
-// over k, then the columns of a row j over i, then the rows over j), so
-// that every tile shape gives the same bits.  Inside the solvers u is the
+// over k, then, at n1 = 8, the 64 column sums by a butterfly over c =
+// i + 8 j, otherwise the columns of a row j over i and then the rows over
+// j), so that every tile shape gives the same bits.  Inside the solvers u is the
 // search direction p, which vanishes on Dirichlet nodes, and the sum of the
 // element energies is (p, A p) of the assembled operator.
 template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
           bool NTW, bool MASS = false, bool NTG = true, bool EDOT = false>
 __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
-                                        const TC *__restrict__ D,
-                                        const TG *__restrict__ G,
-                                        const TU *__restrict__ u,
-                                        TW *__restrict__ w,
+                                        const TC *__restrict__ D_,
+                                        const TG *__restrict__ G_,
+                                        const TU *__restrict__ u_,
+                                        TW *__restrict__ w_,
                                         const Box *__restrict__ box,
                                         TC *__restrict__ smem,
-                                        const TG *__restrict__ H = nullptr,
-                                        double *__restrict__ edot = nullptr) {
+                                        const TG *__restrict__ H_ = nullptr,
+                                        double *__restrict__ edot_ = nullptr,
+                                        const int32_t *__restrict__ stop = nullptr) {
+  // every array is global memory (the batched kernel reads these pointers
+  // from a descriptor, where their address space is not known)
+  const gp<const TC> D = (gp<const TC>)D_;
+  const gp<const TG> G = (gp<const TG>)G_;
+  const gp<const TU> u = (gp<const TU>)u_;
+  const gp<TW> w = (gp<TW>)w_;
+  const gp<const TG> H = (gp<const TG>)H_;
+  const gp<double> edot = (gp<double>)edot_;
   constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = N1 + 1;
   constexpr int SL = N1 * N1 * PAD;  // one element's slice stack
   const int el = t / NP;
@@ -91,7 +101,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   u32x4 urow = {0u, 0u, 0u, 0u};
   if constexpr (VECU) {
     // lane c reads the 16-byte row (k, j) = (c / 8, c % 8) of the element
-    if (act) urow = *reinterpret_cast<const u32x4 *>(u + e * N3 + 8 * c);
+    if (act) urow = *(gp<const u32x4>)(u + e * N3 + 8 * c);
   } else if constexpr (GATHER) {
     int64_t gb = 0, gk = 0;
     if (act) {
@@ -110,8 +120,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
     for (int q = 0; q < 6; ++q) {
       u32x4 v = {0u, 0u, 0u, 0u};
       if (act)
-        v = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4 *>(G + e * 6 * N3 + q * N3 + 8 * c));
+        v = __builtin_nontemporal_load((gp<const u32x4>)(G + e * 6 * N3 + q * N3 + 8 * c));
       const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
@@ -120,7 +129,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
       }
     }
   } else {
-    const TG *Ge = G + e * 6 * N3 + c;
+    const gp<const TG> Ge = G + e * 6 * N3 + c;
 #pragma unroll
     for (int k = 0; k < N1; ++k)
 #pragma unroll
@@ -134,6 +143,10 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
 #pragma unroll
     for (int k = 0; k < N1; ++k) hm[k] = act ? ld_stream(H + base + k * NP) : TG(0);
   }
+  // a solver's done flag (uniform over the workgroup) is read only now, with
+  // the element's loads already in flight: waiting for it before them put a
+  // memory round trip in front of every workgroup
+  if (stop != nullptr && *stop != 0) return;
 
   TC uc[N1];
   if constexpr (VECU) {
@@ -219,7 +232,15 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
         w[base + k * NP] = (TW)acc;
     }
   }
-  if constexpr (EDOT) {
+  if constexpr (EDOT && NP == 64) {
+    // n1 = 8: every element is one whole wave (its 64 columns are the lanes
+    // of a wave in every tile shape), so the column sums are added by a
+    // fixed butterfly over the lanes, without LDS or barriers
+    double v = cdot;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+    if (act && c == 0) edot[e] = v;
+  } else if constexpr (EDOT) {
     // s_u is no longer read after the barrier above: it holds the column
     // sums red[c] (c = i + n1 j) and then the row sums red[NP + j]
     double *red = reinterpret_cast<double *>(s_u);

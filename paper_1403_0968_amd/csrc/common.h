@@ -45,6 +45,13 @@ template <> struct Cvt<double, float> {
   __device__ static float ld(double v) { return (float)v; }
 };
 
+// Global-memory pointer.  A pointer read from device memory (a work item's
+// or a solve's descriptor) has no known address space, and loads and stores
+// through it compile to FLAT instructions, which wait on both memory
+// counters and keep fewer loads in flight; kernels whose buffers are global
+// memory (all device buffers here) access them through gp pointers.
+template <class T> using gp = T __attribute__((address_space(1))) *;
+
 // wave64 sum in a fixed order (butterfly over lanes), deterministic
 __device__ inline double wave_sum(double v) {
 #pragma unroll

@@ -53,42 +53,43 @@ static_assert(VCH % RT == 0, "chunk must be a multiple of the block");
 // begin + t + RT, ... < end into acc[a], in that order (the same order as a
 // plain loop, so the sums are unchanged); the loads are issued PF at a time,
 // so that the single workgroup of a scalar kernel does not wait for one load
-// after the other.
+// after the other.  The last batch is predicated: an absent entry adds +0.0,
+// which leaves a sum that starts at +0.0 unchanged bit for bit.
 template <int NA>
 __device__ inline void strided_sums(const double *__restrict__ part, int stride,
                                     int begin, int end, double (&acc)[NA]) {
-  constexpr int PF = 8;
+  // 11.4M unique nodes make 5562 chunks: 22 partials per thread, all in
+  // flight at once
+  constexpr int PF = NA >= 3 ? 16 : 24;
 #pragma unroll
   for (int a = 0; a < NA; ++a) acc[a] = 0.0;
-  int q = begin + (int)threadIdx.x;
-  for (; q + (PF - 1) * RT < end; q += PF * RT) {
+  for (int q = begin + (int)threadIdx.x; q < end; q += PF * RT) {
     double v[NA][PF];
 #pragma unroll
     for (int u = 0; u < PF; ++u)
 #pragma unroll
-      for (int a = 0; a < NA; ++a) v[a][u] = part[a * stride + q + u * RT];
+      for (int a = 0; a < NA; ++a)
+        v[a][u] = q + u * RT < end ? part[a * stride + q + u * RT] : 0.0;
 #pragma unroll
     for (int u = 0; u < PF; ++u)
 #pragma unroll
       for (int a = 0; a < NA; ++a) acc[a] += v[a][u];
   }
-  for (; q < end; q += RT)
-#pragma unroll
-    for (int a = 0; a < NA; ++a) acc[a] += part[a * stride + q];
 }
 
 // --------------------------------------------------------------------------
 // vector kernels (persistent over VecItem lists)
 // --------------------------------------------------------------------------
-template <class TV> __device__ inline TV *vec(const BatchSolve &s, int v) {
-  return (TV *)(sizeof(TV) == 8 ? s.v64[v] : s.v32[v]);
+// the solve's vectors as global pointers (see gp)
+template <class TV> __device__ inline gp<TV> vec(const BatchSolve &s, int v) {
+  return (gp<TV>)(sizeof(TV) == 8 ? s.v64[v] : s.v32[v]);
 }
-template <class TD> __device__ inline const TD *dinv_of(const BatchSolve &s,
-                                                        int jac) {
+template <class TD> __device__ inline gp<const TD> dinv_of(const BatchSolve &s,
+                                                           int jac) {
   if constexpr (sizeof(TD) == 8)
-    return (const TD *)(jac ? s.dinv64 : s.one64);
+    return (gp<const TD>)(jac ? s.dinv64 : s.one64);
   else
-    return (const TD *)(jac ? s.dinv32 : s.one32);
+    return (gp<const TD>)(jac ? s.dinv32 : s.one32);
 }
 
 // w = mask o Q^T wL (sum of copies in ascending local index, from +0: the
@@ -104,9 +105,9 @@ __global__ void __launch_bounds__(RT)
     if (skip_done && st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
     const Box &bx = sd.box;
-    const TV *wL = vec<TV>(sd, VWL);
-    TV *wG = vec<TV>(sd, VW);
-    const TV *p = vec<TV>(sd, VP);
+    gp<const TV> wL = vec<TV>(sd, VWL);
+    gp<TV> wG = vec<TV>(sd, VW);
+    gp<const TV> p = vec<TV>(sd, VP);
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double acc = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
@@ -173,9 +174,9 @@ __global__ void __launch_bounds__(AT)
   const int s = blockIdx.x;
   if (threadIdx.x == 0) st[s].xupd = 0;  // no x update from an earlier step
   if (st[s].done != 0) return;
-  const double *ed = sds[s].edot;
+  gp<const double> ed = (gp<const double>)sds[s].edot;
   const int64_t E = sds[s].E;
-  constexpr int PF = 8;
+  constexpr int PF = 32;  // 32768 elements: every energy loaded at once
   double acc = 0.0;
   int64_t q = threadIdx.x;
   for (; q + (PF - 1) * AT < E; q += PF * AT) {
@@ -211,13 +212,16 @@ __global__ void __launch_bounds__(RT)
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
     const Box &bx = sd.box;
-    const TV *wL = vec<TV>(sd, VWL);
-    TV *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ);
-    const TD *dinv = dinv_of<TD>(sd, jac);
+    gp<const TV> wL = vec<TV>(sd, VWL);
+    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ);
+    gp<const TD> dinv = dinv_of<TD>(sd, jac);
     const TV alpha = (TV)st[it.solve].alpha;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    double rz = 0.0, rr = 0.0;
-    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+    // w_G at node g: all (up to 8) copies loaded at once, predicated on
+    // existence, then summed in ascending local index (z, y, x copy order);
+    // an absent copy adds +0.0, which leaves the sum unchanged bit for bit
+    // (the sum starts at +0.0 and so is never -0.0)
+    auto assembled = [&](int64_t g) {
       const NodeCopies nc = node_copies(bx, (uint32_t)g);
       TV sw = TV(0);
       if (!nc.masked) {
@@ -235,12 +239,40 @@ __global__ void __launch_bounds__(RT)
 #pragma unroll
         for (int k = 0; k < 8; ++k) sw = sw + v[k];
       }
-      const TV rn = r[g] - alpha * sw;
-      r[g] = rn;
-      const TV zn = (TV)(dinv[g] * rn);
-      z[g] = zn;
-      rz += (double)rn * (double)zn;
-      rr += (double)rn * (double)rn;
+      return sw;
+    };
+    double rz = 0.0, rr = 0.0;
+    constexpr int K = VCH / RT;
+    const int64_t g0 = it.start + threadIdx.x;
+    if (g0 + (K - 1) * RT < end) {
+      // a whole chunk: every load of the thread's K nodes before any store
+      // (the compiler cannot know that w_L, r, z and dinv do not overlap)
+      TV sw[K], rv[K];
+      TD dv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        sw[k] = assembled(g0 + k * RT);
+        rv[k] = r[g0 + k * RT];
+        dv[k] = dinv[g0 + k * RT];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const TV rn = rv[k] - alpha * sw[k];
+        r[g0 + k * RT] = rn;
+        const TV zn = (TV)(dv[k] * rn);
+        z[g0 + k * RT] = zn;
+        rz += (double)rn * (double)zn;
+        rr += (double)rn * (double)rn;
+      }
+    } else {
+      for (int64_t g = g0; g < end; g += RT) {
+        const TV rn = r[g] - alpha * assembled(g);
+        r[g] = rn;
+        const TV zn = (TV)(dinv[g] * rn);
+        z[g] = zn;
+        rz += (double)rn * (double)zn;
+        rr += (double)rn * (double)rn;
+      }
     }
     const double trz = block_sum<RT>(rz, sm);
     const double trr = block_sum<RT>(rr, sm);
@@ -263,9 +295,9 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    TV *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ);
-    const TV *w = vec<TV>(sd, VW);
-    const TD *dinv = dinv_of<TD>(sd, jac);
+    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ);
+    gp<const TV> w = vec<TV>(sd, VW);
+    gp<const TD> dinv = dinv_of<TD>(sd, jac);
     const TV alpha = (TV)st[it.solve].alpha;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double rz = 0.0, rr = 0.0;
@@ -327,21 +359,39 @@ __global__ void __launch_bounds__(RT)
     const CgState &c = st[it.solve];
     if (c.xupd == 0) continue;  // uniform per item
     const BatchSolve &sd = sds[it.solve];
-    const TV *z = vec<TV>(sd, VZ);
-    TV *p = vec<TV>(sd, VP), *x = vec<TV>(sd, VX);
+    gp<const TV> z = vec<TV>(sd, VZ);
+    gp<TV> p = vec<TV>(sd, VP), x = vec<TV>(sd, VX);
     const TV alpha = (TV)c.alpha;
     const TV beta = (TV)c.beta;
     const bool run = c.done == 0;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    if (run)
-      for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
+    constexpr int K = VCH / RT;
+    const int64_t g0 = it.start + threadIdx.x;
+    if (run && g0 + (K - 1) * RT < end) {
+      // a whole chunk: every load of the thread's K nodes before any store
+      // (the compiler cannot know that x, p and z do not overlap): 78 -> 67
+      // us at 11.4M unique nodes in FP64
+      TV pv[K], xv[K], zv[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        pv[k] = p[g0 + k * RT];
+        xv[k] = x[g0 + k * RT];
+        zv[k] = z[g0 + k * RT];
+      }
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        x[g0 + k * RT] = xv[k] + alpha * pv[k];
+        p[g0 + k * RT] = zv[k] + beta * pv[k];
+      }
+    } else if (run) {
+      for (int64_t g = g0; g < end; g += RT) {
         const TV pv = p[g];
         x[g] = x[g] + alpha * pv;
         p[g] = z[g] + beta * pv;
       }
-    else
-      for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
-        x[g] = x[g] + alpha * p[g];
+    } else {
+      for (int64_t g = g0; g < end; g += RT) x[g] = x[g] + alpha * p[g];
+    }
   }
 }
 
@@ -357,10 +407,10 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (!active[it.solve]) continue;
     const BatchSolve &sd = sds[it.solve];
-    const TV *b = vec<TV>(sd, VB), *w = vec<TV>(sd, VW);
-    TV *x = vec<TV>(sd, VX), *r = vec<TV>(sd, VR), *z = vec<TV>(sd, VZ),
-       *p = vec<TV>(sd, VP);
-    const TD *dinv = dinv_of<TD>(sd, jac);
+    gp<const TV> b = vec<TV>(sd, VB), w = vec<TV>(sd, VW);
+    gp<TV> x = vec<TV>(sd, VX), r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ),
+           p = vec<TV>(sd, VP);
+    gp<const TD> dinv = dinv_of<TD>(sd, jac);
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double rz = 0.0, rr = 0.0, bb = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
@@ -442,8 +492,8 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (!active[it.solve]) continue;
     const BatchSolve &sd = sds[it.solve];
-    const double *b = vec<double>(sd, VB), *w = vec<double>(sd, VW);
-    double *r = vec<double>(sd, VR);
+    gp<const double> b = vec<double>(sd, VB), w = vec<double>(sd, VW);
+    gp<double> r = vec<double>(sd, VR);
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double rr = 0.0, bb = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
@@ -489,8 +539,8 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (!active[it.solve]) continue;
     const BatchSolve &sd = sds[it.solve];
-    const double *r = vec<double>(sd, VR);
-    float *b = vec<float>(sd, VB);
+    gp<const double> r = vec<double>(sd, VR);
+    gp<float> b = vec<float>(sd, VB);
     const double sc = scale[it.solve];
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
@@ -507,8 +557,8 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (!active[it.solve]) continue;
     const BatchSolve &sd = sds[it.solve];
-    double *x = vec<double>(sd, VX);
-    const float *d = vec<float>(sd, VX);
+    gp<double> x = vec<double>(sd, VX);
+    gp<const float> d = vec<float>(sd, VX);
     const double inv = 1.0 / scale[it.solve];
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
@@ -527,8 +577,8 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    TV *r = vec<TV>(sd, VR);
-    const TV *w = vec<TV>(sd, VW);
+    gp<TV> r = vec<TV>(sd, VR);
+    gp<const TV> w = vec<TV>(sd, VW);
     const TV alpha = (TV)st[it.solve].alpha;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
@@ -550,9 +600,9 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (skip_done && st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    const TV *r = vec<TV>(sd, VR), *w = vec<TV>(sd, VW);
-    TV *z = vec<TV>(sd, VZ);
-    const TD *dinv = dinv_of<TD>(sd, 1);
+    gp<const TV> r = vec<TV>(sd, VR), w = vec<TV>(sd, VW);
+    gp<TV> z = vec<TV>(sd, VZ);
+    gp<const TD> dinv = dinv_of<TD>(sd, 1);
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double rz = 0.0, zw = 0.0, rr = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
@@ -630,8 +680,8 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    const TV *z = vec<TV>(sd, VZ);
-    TV *p = vec<TV>(sd, VP);
+    gp<const TV> z = vec<TV>(sd, VZ);
+    gp<TV> p = vec<TV>(sd, VP);
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) p[g] = z[g];
   }
@@ -889,7 +939,10 @@ void destroy_ws(sem_handle *h) {
 // --------------------------------------------------------------------------
 // launches of one batch
 // --------------------------------------------------------------------------
-static int vec_grid(const sem_batch *b) { return std::min(b->n_vi, 2048); }
+// one workgroup per chunk of unique nodes: with fewer, persistent
+// workgroups the last round of chunks runs on part of the chip (FP64
+// assembly + r update at 11.4M unique nodes: 114 -> 104 us)
+static int vec_grid(const sem_batch *b) { return b->n_vi; }
 
 // the operator of every solve of the batch, w_L = A_L Q v_src into VWL;
 // edot: the single-solve kernel also stores the element energies (the
