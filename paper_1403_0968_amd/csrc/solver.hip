@@ -199,8 +199,9 @@ __global__ void __launch_bounds__(AT)
 
 // r -= alpha w_G with w_G = mask o Q^T w_L formed here (the copies of each
 // node summed from +0.0 in ascending local index, as the assembly and
-// sem_gs sum them), z = dinv r; partials (r, z), (r, r)
-template <class TV, class TD>
+// sem_gs sum them), z = dinv r; partials (r, z), (r, r).  FCG: r -= alpha
+// w_G and w_G stored (flexible CG needs it for beta); no z, no partials.
+template <class TV, class TD, bool FCG>
 __global__ void __launch_bounds__(RT)
     k_bupdate_xr_asm(const BatchSolve *__restrict__ sds,
                      const CgState *__restrict__ st,
@@ -213,7 +214,7 @@ __global__ void __launch_bounds__(RT)
     const BatchSolve &sd = sds[it.solve];
     const Box &bx = sd.box;
     gp<const TV> wL = vec<TV>(sd, VWL);
-    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ);
+    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ), wG = vec<TV>(sd, VW);
     gp<const TD> dinv = dinv_of<TD>(sd, jac);
     const TV alpha = (TV)st[it.solve].alpha;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
@@ -253,27 +254,37 @@ __global__ void __launch_bounds__(RT)
       for (int k = 0; k < K; ++k) {
         sw[k] = assembled(g0 + k * RT);
         rv[k] = r[g0 + k * RT];
-        dv[k] = dinv[g0 + k * RT];
+        dv[k] = FCG ? TD(0) : dinv[g0 + k * RT];
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const TV rn = rv[k] - alpha * sw[k];
         r[g0 + k * RT] = rn;
-        const TV zn = (TV)(dv[k] * rn);
-        z[g0 + k * RT] = zn;
-        rz += (double)rn * (double)zn;
-        rr += (double)rn * (double)rn;
+        if constexpr (FCG) {
+          wG[g0 + k * RT] = sw[k];
+        } else {
+          const TV zn = (TV)(dv[k] * rn);
+          z[g0 + k * RT] = zn;
+          rz += (double)rn * (double)zn;
+          rr += (double)rn * (double)rn;
+        }
       }
     } else {
       for (int64_t g = g0; g < end; g += RT) {
-        const TV rn = r[g] - alpha * assembled(g);
+        const TV sg = assembled(g);
+        const TV rn = r[g] - alpha * sg;
         r[g] = rn;
-        const TV zn = (TV)(dinv[g] * rn);
-        z[g] = zn;
-        rz += (double)rn * (double)zn;
-        rr += (double)rn * (double)rn;
+        if constexpr (FCG) {
+          wG[g] = sg;
+        } else {
+          const TV zn = (TV)(dinv[g] * rn);
+          z[g] = zn;
+          rz += (double)rn * (double)zn;
+          rr += (double)rn * (double)rn;
+        }
       }
     }
+    if constexpr (FCG) continue;
     const double trz = block_sum<RT>(rz, sm);
     const double trr = block_sum<RT>(rr, sm);
     if (threadIdx.x == 0) {
@@ -1009,8 +1020,8 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   } else {
     bax(b, prec, VP, VWL, 1, true);
     hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
-    hipLaunchKernelGGL((k_bupdate_xr_asm<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
-                       st, vi, nv, part, jac);
+    hipLaunchKernelGGL((k_bupdate_xr_asm<TV, TD, false>), dim3(g), dim3(RT), 0, b->s,
+                       sds, st, vi, nv, part, jac);
   }
   hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
   hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
@@ -1030,12 +1041,23 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
   const int g = vec_grid(b), nv = b->n_vi, n = b->n;
   sem_handle *h = b->hs[0];
   const bool f32 = sizeof(TV) == 4;
-  bax(b, prec, VP, VWL, 1);
-  hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds, st,
-                     vi, nv, part, 1);
-  hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
-  hipLaunchKernelGGL((k_bupdate_r_only<TV>), dim3(g), dim3(RT), 0, b->s, sds, st,
-                     vi, nv);
+  if (prec == SEM_BF16_MFMA || prec == SEM_BF16_PLAIN_D) {
+    // no element energies from the matrix-core operator: assembled w and
+    // (p, w) first
+    bax(b, prec, VP, VWL, 1);
+    hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds,
+                       st, vi, nv, part, 1);
+    hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
+    hipLaunchKernelGGL((k_bupdate_r_only<TV>), dim3(g), dim3(RT), 0, b->s, sds,
+                       st, vi, nv);
+  } else {
+    // (p, A p) from the operator's element energies; the r update forms and
+    // stores the assembled w (needed for beta)
+    bax(b, prec, VP, VWL, 1, true);
+    hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
+    hipLaunchKernelGGL((k_bupdate_xr_asm<TV, TD, true>), dim3(g), dim3(RT), 0,
+                       b->s, sds, st, vi, nv, part, 1);
+  }
   learn_apply(h, f32 ? b->hsd[0].v32[VR] : b->hsd[0].v64[VR], f32, b->s);
   hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
                      st, vi, nv, learn_cg(h), part, 1);
