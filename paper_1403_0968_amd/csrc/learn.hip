@@ -47,6 +47,7 @@ struct CoarseTab {
 struct Learn {
   int K = 0, ni = 0, ldx = 16, ldo = 16;
   DevBuf Bd, Xk, Ml, cG, cL, Sc, O, kfeat, invkh;
+  DevBuf ep;  // flexible CG: element terms of (r, c) and (c, w), [2][E]
   CoarseTab tab{};
   const sem_mlp *mnet = nullptr;
   uint64_t mver = 0;
@@ -308,11 +309,22 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <class TV, bool UNIQUE, int M, int Q>
+// FUSE (with UNIQUE): the flexible-CG iteration's preconditioner step.  out
+// is the search vector z of the solve, holding dinv o r on entry; the
+// correction is added to it in place (z = dinv o r + c, as the separate
+// correction-then-sum order gives: c is rounded to FP32 first), and every
+// element stores its terms of the two dot products that involve c,
+// epart[e] = (r_I, c) and epart[E + e] = (c, w_I), with w_I the element's
+// interior values of the operator output wL (single copies: the assembled
+// values), summed by a fixed butterfly over the wave.
+template <class TV, bool UNIQUE, int M, int Q, bool FUSE = false>
 __global__ void __launch_bounds__(64 * CA_WAVES)
     k_coarse_apply(int64_t E, Box box, CoarseTab tb, const float *__restrict__ scg,
                    const TV *__restrict__ r, const float *__restrict__ Ml,
-                   const float *__restrict__ damping, float *__restrict__ out) {
+                   const float *__restrict__ damping, float *__restrict__ out,
+                   TV *__restrict__ zf = nullptr, const TV *__restrict__ wL = nullptr,
+                   double *__restrict__ epart = nullptr) {
+  static_assert(!FUSE || UNIQUE, "the fused step works on unique-node vectors");
   constexpr int K = Q * Q * Q, KK = K * (K + 1) / 2, MR = (KK + 63) / 64, P = M * M;
   constexpr int N1 = M + 2, N3 = N1 * N1 * N1, Q2 = Q * Q;
   constexpr int REG = Q * P + Q2 * M + 2 * 32 + KK;  // floats per wave
@@ -346,6 +358,11 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
   };
   if (e < E) fetch(e);
   for (; e < E; e += stride) {
+    TV rcur[FUSE ? M : 1];  // this element's r (rv is refilled by the prefetch)
+    if constexpr (FUSE) {
+#pragma unroll
+      for (int i = 0; i < M; ++i) rcur[i] = rv[i];
+    }
     // restriction, direction i (registers): s1[a][pencil]
     if (t < P) {
 #pragma unroll
@@ -430,17 +447,42 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
     }
     wave_sync();
     // direction i: lane = pencil, M contiguous interior nodes
+    double prc = 0.0, pcw = 0.0;  // FUSE: this lane's (r_I, c), (c, w_I) terms
     if (t < P) {
       float v[Q];
 #pragma unroll
       for (int a = 0; a < Q; ++a) v[a] = s1[a * P + t];
       const int64_t g = base(e) + offp;
+      TV zv[FUSE ? M : 1], wv[FUSE ? M : 1];
+      if constexpr (FUSE) {
+        const int64_t l = e * N3 + 1 + (int64_t)N1 * (pj + N1 * pk);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          zv[i] = zf[g + i];
+          wv[i] = wL[l + i];
+        }
+      }
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         float acc = 0.f;
 #pragma unroll
         for (int a = 0; a < Q; ++a) acc += tb.B1[i][a] * v[a];
-        out[g + i] = acc;
+        if constexpr (FUSE) {
+          const TV c = (TV)acc;
+          zf[g + i] = zv[i] + c;
+          prc += (double)rcur[i] * (double)c;
+          pcw += (double)c * (double)wv[i];
+        } else {
+          out[g + i] = acc;
+        }
+      }
+    }
+    if constexpr (FUSE) {
+      prc = wave_sum(prc);
+      pcw = wave_sum(pcw);
+      if (t == 0) {
+        epart[e] = prc;
+        epart[E + e] = pcw;
       }
     }
     if (!UNIQUE)  // the faces of the element carry no correction
@@ -458,28 +500,34 @@ static const float *learn_damping_dev(const sem_handle *h) {
                          : mlp_damping_dev(h->net);
 }
 
-template <class TV, bool UNIQUE, int M, int Q>
+template <class TV, bool UNIQUE, int M, int Q, bool FUSE>
 static void launch_ca(const sem_handle *h, const Learn *L, const TV *r, float *out,
-                      hipStream_t s) {
+                      TV *zf, const TV *wL, double *epart, hipStream_t s) {
   const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet) : Box{};
   const int64_t groups = (h->E + CA_WAVES - 1) / CA_WAVES;
   const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * 8);
-  hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, M, Q>), dim3(grid), dim3(64 * CA_WAVES),
-                     0, s, h->E, box, L->tab, L->Sc.as<float>(), r, L->Ml.as<float>(),
-                     learn_damping_dev(h), out);
+  hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, M, Q, FUSE>), dim3(grid),
+                     dim3(64 * CA_WAVES), 0, s, h->E, box, L->tab, L->Sc.as<float>(), r,
+                     L->Ml.as<float>(), learn_damping_dev(h), out, zf, wL, epart);
 }
 
-template <class TV, bool UNIQUE>
+template <class TV, bool UNIQUE, bool FUSE = false>
 static void launch_coarse_apply(const sem_handle *h, const Learn *L, const TV *r,
-                                float *out, hipStream_t s) {
+                                float *out, hipStream_t s, TV *zf = nullptr,
+                                const TV *wL = nullptr, double *epart = nullptr) {
   switch (h->N) {
-    case 2: launch_ca<TV, UNIQUE, 1, 1>(h, L, r, out, s); break;
-    case 3: launch_ca<TV, UNIQUE, 2, 2>(h, L, r, out, s); break;
-    case 4: launch_ca<TV, UNIQUE, 3, 3>(h, L, r, out, s); break;
-    case 5: launch_ca<TV, UNIQUE, 4, 3>(h, L, r, out, s); break;
-    case 6: launch_ca<TV, UNIQUE, 5, 3>(h, L, r, out, s); break;
-    case 7: launch_ca<TV, UNIQUE, 6, 3>(h, L, r, out, s); break;
-    case 8: launch_ca<TV, UNIQUE, 7, 3>(h, L, r, out, s); break;
+#define SEM_CA(NN, MM, QQ)                                                      \
+  case NN:                                                                      \
+    launch_ca<TV, UNIQUE, MM, QQ, FUSE>(h, L, r, out, zf, wL, epart, s);       \
+    break;
+    SEM_CA(2, 1, 1)
+    SEM_CA(3, 2, 2)
+    SEM_CA(4, 3, 3)
+    SEM_CA(5, 4, 3)
+    SEM_CA(6, 5, 3)
+    SEM_CA(7, 6, 3)
+    SEM_CA(8, 7, 3)
+#undef SEM_CA
     default: fail(SEM_ERR_STATE, "coarse layout: N must be in 2..8");
   }
   SEM_HIP(hipGetLastError());
@@ -657,6 +705,7 @@ static void ensure_learn(sem_handle *h) {
     L->cG.alloc((size_t)h->nG * 4);
     SEM_HIP(hipMemset(L->cG.p, 0, (size_t)h->nG * 4));  // faces stay zero
     L->cL.alloc((size_t)h->nL * 4);
+    L->ep.alloc((size_t)h->E * 2 * sizeof(double));
     L->O.alloc((size_t)h->E * L->ldo * 4);
     L->exact_damp_dev.alloc(sizeof(float));
     kappa_features(h, L->kfeat, L->invkh);
@@ -731,6 +780,25 @@ void learn_apply(sem_handle *h, const void *r, bool f32, hipStream_t s) {
     launch_coarse_apply<double, true>(h, L, (const double *)r, L->cG.as<float>(),
                                       s);
 }
+
+// flexible CG: z (holding dinv o r) += c(r) on the element interiors, and
+// the element terms of (r, c) and (c, w) into epart ([2][E], learn_epart)
+void learn_apply_fused(sem_handle *h, const void *r, void *z, const void *wL,
+                       bool f32, hipStream_t s) {
+  if (!learn_active(h))
+    fail(SEM_ERR_STATE, "learned correction: no network attached");
+  Learn *L = h->learn;
+  if (f32)
+    launch_coarse_apply<float, true, true>(h, L, (const float *)r, nullptr, s,
+                                           (float *)z, (const float *)wL,
+                                           L->ep.as<double>());
+  else
+    launch_coarse_apply<double, true, true>(h, L, (const double *)r, nullptr, s,
+                                            (double *)z, (const double *)wL,
+                                            L->ep.as<double>());
+}
+
+double *learn_epart(sem_handle *h) { return h->learn ? h->learn->ep.as<double>() : nullptr; }
 
 // the correction on unique nodes (zero off the element interiors)
 float *learn_cg(sem_handle *h) { return h->learn ? h->learn->cG.as<float>() : nullptr; }

@@ -239,6 +239,9 @@ void learn_destroy(sem_handle *h);
 // one application c = damping B M_e B^T r_I for the batch's single solve
 // (r a unique-node vector, FP32 when f32), into the unique-node correction
 void learn_apply(sem_handle *h, const void *r, bool f32, hipStream_t s);
+void learn_apply_fused(sem_handle *h, const void *r, void *z, const void *wL,
+                       bool f32, hipStream_t s);
+double *learn_epart(sem_handle *h);
 void learn_attach_exact(sem_handle *h, double damping);
 bool learn_active(const sem_handle *h);
 double learn_damping(const sem_handle *h);

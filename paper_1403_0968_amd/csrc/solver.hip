@@ -199,8 +199,9 @@ __global__ void __launch_bounds__(AT)
 
 // r -= alpha w_G with w_G = mask o Q^T w_L formed here (the copies of each
 // node summed from +0.0 in ascending local index, as the assembly and
-// sem_gs sum them), z = dinv r; partials (r, z), (r, r).  FCG: r -= alpha
-// w_G and w_G stored (flexible CG needs it for beta); no z, no partials.
+// sem_gs sum them), z = dinv r; partials (r, z), (r, r).  FCG (flexible CG
+// with the learned correction, which the next kernel adds to z): partials
+// (r, z), (z, w_G), (r, r).
 template <class TV, class TD, bool FCG>
 __global__ void __launch_bounds__(RT)
     k_bupdate_xr_asm(const BatchSolve *__restrict__ sds,
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(RT)
     const BatchSolve &sd = sds[it.solve];
     const Box &bx = sd.box;
     gp<const TV> wL = vec<TV>(sd, VWL);
-    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ), wG = vec<TV>(sd, VW);
+    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ);
     gp<const TD> dinv = dinv_of<TD>(sd, jac);
     const TV alpha = (TV)st[it.solve].alpha;
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(RT)
       }
       return sw;
     };
-    double rz = 0.0, rr = 0.0;
+    double rz = 0.0, rr = 0.0, zw = 0.0;
     constexpr int K = VCH / RT;
     const int64_t g0 = it.start + threadIdx.x;
     if (g0 + (K - 1) * RT < end) {
@@ -254,42 +255,41 @@ __global__ void __launch_bounds__(RT)
       for (int k = 0; k < K; ++k) {
         sw[k] = assembled(g0 + k * RT);
         rv[k] = r[g0 + k * RT];
-        dv[k] = FCG ? TD(0) : dinv[g0 + k * RT];
+        dv[k] = dinv[g0 + k * RT];
       }
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         const TV rn = rv[k] - alpha * sw[k];
         r[g0 + k * RT] = rn;
-        if constexpr (FCG) {
-          wG[g0 + k * RT] = sw[k];
-        } else {
-          const TV zn = (TV)(dv[k] * rn);
-          z[g0 + k * RT] = zn;
-          rz += (double)rn * (double)zn;
-          rr += (double)rn * (double)rn;
-        }
+        const TV zn = (TV)(dv[k] * rn);
+        z[g0 + k * RT] = zn;
+        rz += (double)rn * (double)zn;
+        rr += (double)rn * (double)rn;
+        if constexpr (FCG) zw += (double)zn * (double)sw[k];
       }
     } else {
       for (int64_t g = g0; g < end; g += RT) {
         const TV sg = assembled(g);
         const TV rn = r[g] - alpha * sg;
         r[g] = rn;
-        if constexpr (FCG) {
-          wG[g] = sg;
-        } else {
-          const TV zn = (TV)(dinv[g] * rn);
-          z[g] = zn;
-          rz += (double)rn * (double)zn;
-          rr += (double)rn * (double)rn;
-        }
+        const TV zn = (TV)(dinv[g] * rn);
+        z[g] = zn;
+        rz += (double)rn * (double)zn;
+        rr += (double)rn * (double)rn;
+        if constexpr (FCG) zw += (double)zn * (double)sg;
       }
     }
-    if constexpr (FCG) continue;
     const double trz = block_sum<RT>(rz, sm);
     const double trr = block_sum<RT>(rr, sm);
+    const double tzw = FCG ? block_sum<RT>(zw, sm) : 0.0;
     if (threadIdx.x == 0) {
       part[q] = trz;
-      part[nitems + q] = trr;
+      if constexpr (FCG) {
+        part[nitems + q] = tzw;
+        part[2 * nitems + q] = trr;
+      } else {
+        part[nitems + q] = trr;
+      }
     }
   }
 }
@@ -652,6 +652,37 @@ __global__ void __launch_bounds__(RT)
   const double rr = block_sum<RT>(c, sm);
   if (threadIdx.x == 0) {
     CgState &cs = st[s];
+    cs.xupd = 1;  // this step's alpha is finite: x += alpha p follows
+    cs.it += 1;
+    cs.rr = rr;
+    if (!isfinite(rr) || !isfinite(rz) || !isfinite(zw))
+      cs.done = 2;
+    else if (rr <= cs.tol2 * cs.bb)
+      cs.done = 1;
+    else if (cs.it >= cs.maxit)
+      cs.done = 3;
+    else {
+      cs.beta = -zw / cs.pw;
+      cs.rz = rz;
+    }
+  }
+}
+
+// as k_bbeta_fcg for one solve whose correction step stored its element
+// terms of (r, c) and (c, w) in epart ([2][E]): (r, z) and (z, w) add them
+__global__ void __launch_bounds__(RT)
+    k_bbeta_fcg_e(CgState *st, const double *__restrict__ part, int nitems,
+                  const double *__restrict__ epart, int E) {
+  __shared__ double sm[RT / 64];
+  CgState &cs = st[0];
+  if (cs.done != 0) return;
+  double acc[3], ea[2];
+  strided_sums<3>(part, nitems, 0, nitems, acc);
+  strided_sums<2>(epart, E, 0, E, ea);
+  const double rz = block_sum<RT>(acc[0] + ea[0], sm);
+  const double zw = block_sum<RT>(acc[1] + ea[1], sm);
+  const double rr = block_sum<RT>(acc[2], sm);
+  if (threadIdx.x == 0) {
     cs.xupd = 1;  // this step's alpha is finite: x += alpha p follows
     cs.it += 1;
     cs.rr = rr;
@@ -1051,12 +1082,23 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
     hipLaunchKernelGGL((k_bupdate_r_only<TV>), dim3(g), dim3(RT), 0, b->s, sds,
                        st, vi, nv);
   } else {
-    // (p, A p) from the operator's element energies; the r update forms and
-    // stores the assembled w (needed for beta)
+    // (p, A p) from the operator's element energies; the r update forms the
+    // assembled w, z = dinv r and the partials of (r, z), (z, w), (r, r);
+    // the correction step adds c to z on the element interiors and stores
+    // the element terms of (r, c) and (c, w)
     bax(b, prec, VP, VWL, 1, true);
     hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
     hipLaunchKernelGGL((k_bupdate_xr_asm<TV, TD, true>), dim3(g), dim3(RT), 0,
                        b->s, sds, st, vi, nv, part, 1);
+    const BatchSolve &d = b->hsd[0];
+    learn_apply_fused(h, f32 ? d.v32[VR] : d.v64[VR], f32 ? d.v32[VZ] : d.v64[VZ],
+                      f32 ? d.v32[VWL] : d.v64[VWL], f32, b->s);
+    hipLaunchKernelGGL(k_bbeta_fcg_e, dim3(1), dim3(RT), 0, b->s, st, part, nv,
+                       learn_epart(h), (int)h->E);
+    hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
+                       nv);
+    SEM_HIP(hipGetLastError());
+    return;
   }
   learn_apply(h, f32 ? b->hsd[0].v32[VR] : b->hsd[0].v64[VR], f32, b->s);
   hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
