@@ -62,7 +62,7 @@ typedef enum {
  *   SEM_BF16_MFMA: the six contractions on the matrix cores with FP32
  *     accumulation, BF16 G and fluxes, the derivative matrix as a two-term
  *     BF16 split D = D_hi + D_lo (two accumulating MFMAs per contraction).
- *     sem_ax: BF16 u, N <= 7.  Solver: FP32 p as a two-term BF16 split
+ *     sem_ax: BF16 u.  Solver: FP32 p as a two-term BF16 split
  *     p = p_hi + p_lo, each gradient contraction accumulating D_hi p_hi,
  *     D_lo p_hi and D_hi p_lo (rounding p to BF16 alone leaves an input
  *     error whose effect on refinement grows with the mesh).
@@ -141,7 +141,7 @@ typedef struct {
                            FP32 search direction (SEM_FP32, SEM_BF16,
                            SEM_BF16_MFMA, SEM_BF16_PLAIN_D as described at
                            sem_precision; the matrix-core ones for solves of
-                           one order N <= 7), with FP64 dot products and
+                           one order), with FP64 dot products and
                            scalars; refinement stops after 3 steps that do
                            not shrink the true residual by 10% */
   double inner_rtol;    /* inner relative tolerance for refinement */
@@ -217,7 +217,8 @@ sem_status sem_export(const sem_handle *h, int32_t which, void *dst,
  * SEM_BF16: u bf16 (16-byte aligned), w float (BF16 G, FP32 derivative
  * matrix and FP32 accumulation, VALU).  SEM_BF16_MFMA: u bf16 (16-byte
  * aligned), w float; the six contractions on the matrix cores with the
- * split derivative matrix (N <= 7).  SEM_BF16_PLAIN_D: the same with D
+ * split derivative matrix (N <= 7 in blocks of 8, N = 8 on 16-padded
+ * operands).  SEM_BF16_PLAIN_D: the same with D
  * rounded to BF16.  When the mesh has a mass term (alpha != 0) every
  * precision adds H o u_L (H = alpha(X) B, stored in the precision of G; the
  * lumped mass operator of equation semOperator), 8 / 4 / 2 more bytes per

@@ -217,6 +217,223 @@ __device__ inline void load_factors(int l, bool act, int64_t e,
 }
 
 // ---------------------------------------------------------------------------
+// n1 = 9 (N = 8): the element does not fit the 8-block form.  Every
+// contraction runs on 16-padded operands instead: the derivative operand is
+// D (or D^T) padded to 16 x 16 with zeros, the node operand is read from the
+// element's natural [k][j][i] layout in LDS with every index beyond 8
+// predicated to zero, and one 16x16x16 MFMA contracts a whole length-9
+// line:
+//   t (over k):  C[k'][c]    = sum_m D[k'][m] u[m][c],  c = (j, i) in 6
+//                tiles of 16 of the 81 columns
+//   r (over i):  C[rho][i']  = sum_m u[rho][m] D[i'][m], rho = (k, j) in 6
+//                tiles of 16 of the 81 rows
+//   s (over j):  C[j'][i]    = sum_m D[j'][m] u[k][m][i], one MFMA per k
+// (21 MFMAs per derivative term and direction set, against 6 with the
+// block-diagonal 8-form; the matrix cores are far from busy either way).
+// The transposed contractions use D^T the same way and accumulate w through
+// the C operand (r, then s, then t).  The metric step is FP32 on the VALU,
+// lane l taking the columns l and l + 64 (< 81).
+// ---------------------------------------------------------------------------
+constexpr int MW9 = 2;  // waves (elements) per workgroup at n1 = 9
+constexpr int E9 = 729;
+
+struct alignas(16) MfmaLds9 {
+  uint16_t u[E9];
+  uint16_t ul[E9];                  // low term of a split input (solver)
+  float gr[E9], gs[E9], gt[E9];     // gradients; gr is reused for w
+  uint16_t fr[E9], fs[E9], ft[E9];
+};
+
+// D[r][4g + q] (fwd) and D[4g + q][r] (bwd), zero outside 9 x 9
+__device__ inline void d_operands9(int l, const uint16_t *__restrict__ Dhi_,
+                                   const uint16_t *__restrict__ Dlo_, m16x4 &fh,
+                                   m16x4 &fl, m16x4 &bh, m16x4 &bl) {
+  const gp<const uint16_t> Dhi = (gp<const uint16_t>)Dhi_;
+  const gp<const uint16_t> Dlo = (gp<const uint16_t>)Dlo_;
+  const int r = l & 15, g = l >> 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int m = 4 * g + q;
+    const bool ok = r < 9 && m < 9;
+    fh[q] = ok ? (short)Dhi[r * 9 + m] : (short)0;
+    fl[q] = ok ? (short)Dlo[r * 9 + m] : (short)0;
+    bh[q] = ok ? (short)Dhi[m * 9 + r] : (short)0;
+    bl[q] = ok ? (short)Dlo[m * 9 + r] : (short)0;
+  }
+}
+
+// four BF16 values p[off(q)], q = 0..3, zero where ok(q) fails
+template <class F, class O>
+__device__ inline m16x4 lds4_pred(const uint16_t *p, F off, O ok) {
+  m16x4 v;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) v[q] = ok(q) ? (short)p[off(q)] : (short)0;
+  return v;
+}
+
+// One element per wave, u (BF16, [k][j][i], with ULO the FP32 split u =
+// L.u + L.ul) in LDS; gq holds the BF16 factors of the lane's columns l and
+// l + 64 for k = 0..8.  On return L.gr holds w in [k][j][i] order.
+template <bool SPLIT, bool ULO>
+__device__ inline void mfma_element9(int l, MfmaLds9 &L, const uint16_t (&gq)[2][6][9],
+                                     m16x4 fh, m16x4 fl, m16x4 bh, m16x4 bl) {
+  const int r = l & 15, g = l >> 4;
+  const mf32x4 zero = {0.f, 0.f, 0.f, 0.f};
+  // ---- gradient ----
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {  // t: columns c = 16 t + r
+    const int c = 16 * t + r;
+    auto off = [&](int q) { return (4 * g + q) * 81 + c; };
+    auto ok = [&](int q) { return 4 * g + q < 9 && c < 81; };
+    const m16x4 b = lds4_pred(L.u, off, ok);
+    mf32x4 acc = mfma(fh, b, zero);
+    if (SPLIT) acc = mfma(fl, b, acc);
+    if constexpr (ULO) acc = mfma(fh, lds4_pred(L.ul, off, ok), acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4 * g + q < 9 && c < 81) L.gt[(4 * g + q) * 81 + c] = acc[q];
+  }
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {  // r: rows rho = 16 t + r of u[rho][m]
+    const int rho = 16 * t + r;
+    auto off = [&](int q) { return rho * 9 + 4 * g + q; };
+    auto ok = [&](int q) { return rho < 81 && 4 * g + q < 9; };
+    const m16x4 a = lds4_pred(L.u, off, ok);
+    mf32x4 acc = mfma(a, fh, zero);
+    if (SPLIT) acc = mfma(a, fl, acc);
+    if constexpr (ULO) acc = mfma(lds4_pred(L.ul, off, ok), fh, acc);
+    // C[rho'][i'] with rho' = 16 t + 4 g + q, i' = r
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = 16 * t + 4 * g + q;
+      if (rr < 81 && r < 9) L.gr[rr * 9 + r] = acc[q];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {  // s: B[m][i] = u[k][m][i]
+    auto off = [&](int q) { return k * 81 + (4 * g + q) * 9 + r; };
+    auto ok = [&](int q) { return 4 * g + q < 9 && r < 9; };
+    const m16x4 b = lds4_pred(L.u, off, ok);
+    mf32x4 acc = mfma(fh, b, zero);
+    if (SPLIT) acc = mfma(fl, b, acc);
+    if constexpr (ULO) acc = mfma(fh, lds4_pred(L.ul, off, ok), acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4 * g + q < 9 && r < 9) L.gs[k * 81 + (4 * g + q) * 9 + r] = acc[q];
+  }
+  __syncthreads();
+  // ---- metric step on the lane's columns (FP32) ----
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = l + 64 * h;
+    if (c < 81) {
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const int p = k * 81 + c;
+        const float ur = L.gr[p], us = L.gs[p], ut = L.gt[p];
+        const float g0 = bf16_to_f32(gq[h][0][k]), g1 = bf16_to_f32(gq[h][1][k]),
+                    g2 = bf16_to_f32(gq[h][2][k]), g3 = bf16_to_f32(gq[h][3][k]),
+                    g4 = bf16_to_f32(gq[h][4][k]), g5 = bf16_to_f32(gq[h][5][k]);
+        L.fr[p] = f32_to_bf16(g0 * ur + g1 * us + g2 * ut);
+        L.fs[p] = f32_to_bf16(g1 * ur + g3 * us + g4 * ut);
+        L.ft[p] = f32_to_bf16(g2 * ur + g4 * us + g5 * ut);
+      }
+    }
+  }
+  __syncthreads();
+  // ---- divergence into L.gr ----
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {  // r: A = f_r[rho][m], B[m][i] = D[m][i]
+    const int rho = 16 * t + r;
+    auto off = [&](int q) { return rho * 9 + 4 * g + q; };
+    auto ok = [&](int q) { return rho < 81 && 4 * g + q < 9; };
+    const m16x4 a = lds4_pred(L.fr, off, ok);
+    mf32x4 acc = mfma(a, bh, zero);
+    if (SPLIT) acc = mfma(a, bl, acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int rr = 16 * t + 4 * g + q;
+      if (rr < 81 && r < 9) L.gr[rr * 9 + r] = acc[q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {  // s: A[j][m] = D[m][j], B[m][i] = f_s[k][m][i]
+    auto off = [&](int q) { return k * 81 + (4 * g + q) * 9 + r; };
+    auto ok = [&](int q) { return 4 * g + q < 9 && r < 9; };
+    const m16x4 b = lds4_pred(L.fs, off, ok);
+    mf32x4 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = ok(q) ? L.gr[off(q)] : 0.f;
+    acc = mfma(bh, b, acc);
+    if (SPLIT) acc = mfma(bl, b, acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (ok(q)) L.gr[off(q)] = acc[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int t = 0; t < 6; ++t) {  // t: A[k][m] = D[m][k], B[m][c] = f_t[m][c]
+    const int c = 16 * t + r;
+    auto off = [&](int q) { return (4 * g + q) * 81 + c; };
+    auto ok = [&](int q) { return 4 * g + q < 9 && c < 81; };
+    const m16x4 b = lds4_pred(L.ft, off, ok);
+    mf32x4 acc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = ok(q) ? L.gr[off(q)] : 0.f;
+    acc = mfma(bh, b, acc);
+    if (SPLIT) acc = mfma(bl, b, acc);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (ok(q)) L.gr[off(q)] = acc[q];
+  }
+  __syncthreads();
+}
+
+// the BF16 factors of columns l and l + 64 of element e ([E][6][729])
+__device__ inline void load_factors9(int l, bool act, int64_t e,
+                                     const uint16_t *__restrict__ G_,
+                                     uint16_t (&gq)[2][6][9]) {
+  const gp<const uint16_t> G = (gp<const uint16_t>)G_;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = l + 64 * h;
+    const bool col = act && c < 81;
+#pragma unroll
+    for (int q = 0; q < 6; ++q)
+#pragma unroll
+      for (int k = 0; k < 9; ++k)
+        gq[h][q][k] = col ? G[e * 6 * E9 + q * E9 + k * 81 + c] : (uint16_t)0;
+  }
+}
+
+template <bool SPLIT>
+__global__ void __launch_bounds__(64 * MW9)
+    k_ax_mfma9(int64_t E, const uint16_t *__restrict__ Dhi,
+               const uint16_t *__restrict__ Dlo, const uint16_t *__restrict__ G,
+               const uint16_t *__restrict__ H, const uint16_t *__restrict__ u,
+               float *__restrict__ w) {
+  __shared__ MfmaLds9 lds[MW9];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t e = (int64_t)blockIdx.x * MW9 + wv;
+  const bool act = e < E;
+  MfmaLds9 &L = lds[wv];
+  m16x4 fh, fl, bh, bl;
+  d_operands9(l, Dhi, Dlo, fh, fl, bh, bl);
+  uint16_t gq[2][6][9];
+  load_factors9(l, act, e, G, gq);
+  for (int p = l; p < E9; p += 64) L.u[p] = act ? u[e * E9 + p] : (uint16_t)0;
+  __syncthreads();
+  mfma_element9<SPLIT, false>(l, L, gq, fh, fl, bh, bl);
+  if (!act) return;  // no barrier follows
+  for (int p = l; p < E9; p += 64) {
+    float v = L.gr[p];
+    if (H != nullptr) v += bf16_to_f32(H[e * E9 + p]) * bf16_to_f32(L.u[p]);
+    w[e * E9 + p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // standalone operator: BF16 E-vector in, FP32 E-vector out
 // ---------------------------------------------------------------------------
 template <int N1, bool SPLIT>
@@ -300,8 +517,12 @@ static void launch_ax_mfma_s(int N, int64_t E, const uint16_t *Dhi,
     SEM_AXM(6)
     SEM_AXM(7)
 #undef SEM_AXM
+    case 8:
+      hipLaunchKernelGGL((k_ax_mfma9<SPLIT>), dim3((unsigned)((E + MW9 - 1) / MW9)),
+                         dim3(64 * MW9), 0, s, E, Dhi, Dlo, G, H, u, w);
+      break;
     default:
-      fail(SEM_ERR_ARG, "sem_ax: the matrix-core operator needs N in 1..7");
+      fail(SEM_ERR_ARG, "sem_ax: the matrix-core operator needs N in 1..8");
   }
 }
 
@@ -380,6 +601,56 @@ __global__ void __launch_bounds__(64 * MW)
   }
 }
 
+// the batched solver operator at n1 = 9: as k_bax_mfma, MW9 elements per
+// workgroup pass
+template <bool SPLIT>
+__global__ void __launch_bounds__(64 * MW9)
+    k_bax_mfma9(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
+                const AxItem *__restrict__ items, int nitems, int epb, int src,
+                int dst, int skip_done) {
+  __shared__ MfmaLds9 lds[MW9];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  MfmaLds9 &L = lds[wv];
+  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
+    const AxItem it = items[q];
+    if (skip_done && st[it.solve].done != 0) continue;  // uniform per block
+    const BatchSolve &sd = sds[it.solve];
+    const gp<const float> u = (gp<const float>)sd.v32[src];
+    const gp<float> w = (gp<float>)sd.v32[dst];
+    const uint16_t *G = (const uint16_t *)sd.G16;
+    const gp<const uint16_t> H = (gp<const uint16_t>)sd.H16;  // null without a mass term
+    m16x4 fh, fl, bh, bl;
+    d_operands9(l, (const uint16_t *)sd.D16hi, (const uint16_t *)sd.D16lo, fh, fl,
+                bh, bl);
+    for (int e0 = 0; e0 < epb; e0 += MW9) {  // uniform per block
+      const int64_t e = it.elem0 + e0 + wv;
+      const bool act = e0 + wv < epb && e < sd.E;
+      uint16_t gq[2][6][9];
+      load_factors9(l, act, e, G, gq);
+      int64_t gb = 0;
+      if (act) gb = box_origin(sd.box, (uint32_t)e);
+      for (int p = l; p < E9; p += 64) {
+        const int i = p % 9, j = (p / 9) % 9, k = p / 81;
+        const float v = act ? u[gb + i + (int64_t)sd.box.Gx * j + sd.box.Gxy * k] : 0.f;
+        const uint16_t hi = f32_to_bf16(v);
+        L.u[p] = hi;
+        L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
+      }
+      __syncthreads();
+      mfma_element9<SPLIT, true>(l, L, gq, fh, fl, bh, bl);
+      if (act) {
+        for (int p = l; p < E9; p += 64) {
+          float v = L.gr[p];
+          if (H != nullptr)
+            v += bf16_to_f32(H[e * E9 + p]) * (bf16_to_f32(L.u[p]) + bf16_to_f32(L.ul[p]));
+          w[e * E9 + p] = v;
+        }
+      }
+      __syncthreads();  // L is reused by the next element
+    }
+  }
+}
+
 void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *st,
                      const AxItem *items, int nitems, int epb, int grid, int src,
                      int dst, int skip_done, hipStream_t s) {
@@ -403,8 +674,18 @@ void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *s
     SEM_BAXM(7)
     SEM_BAXM(8)
 #undef SEM_BAXM
+    case 9: {
+      const dim3 b9(64 * MW9);
+      if (split)
+        hipLaunchKernelGGL((k_bax_mfma9<true>), g, b9, 0, s, sds, st, items, nitems,
+                           epb, src, dst, skip_done);
+      else
+        hipLaunchKernelGGL((k_bax_mfma9<false>), g, b9, 0, s, sds, st, items, nitems,
+                           epb, src, dst, skip_done);
+      break;
+    }
     default:
-      fail(SEM_ERR_ARG, "batched operator: the matrix-core operator needs N in 1..7");
+      fail(SEM_ERR_ARG, "batched operator: the matrix-core operator needs N in 1..8");
   }
   SEM_HIP(hipGetLastError());
 }

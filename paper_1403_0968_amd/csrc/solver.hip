@@ -993,9 +993,9 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
                 bool edot = false) {
   if (prec == SEM_BF16_MFMA || prec == SEM_BF16_PLAIN_D) {
     // matrix-core operator: tiles of the 256-thread item list, one order
-    if (b->nset < 2 || b->nset > 8)
+    if (b->nset < 2 || b->nset > 9)
       fail(SEM_ERR_ARG, "solve: the matrix-core operator needs solves of one "
-                        "order N <= 7");
+                        "order N <= 8");
     const int k = bs_slot(256);
     launch_bax_mfma(b->nset, prec == SEM_BF16_MFMA, b->sds.as<BatchSolve>(),
                     b->st.as<CgState>(), b->axitems[k].as<AxItem>(), b->n_ax[k],

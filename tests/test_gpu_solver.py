@@ -159,3 +159,30 @@ def test_bf16_plain_derivative_matrix_stalls_refinement(sem):
                 5 * res[sem.SEM_BF16_MFMA]["outer_contraction"])
     finally:
         sem.sem_destroy(h)
+
+
+@pytest.mark.parametrize("N", [7, 8])
+def test_matrix_core_refinement_matches_oracle(sem, N):
+    """FP64 refinement around the matrix-core inner operator (split D, split
+    search direction) at N = 7 (8-block form) and N = 8 (16-padded form) to
+    1e-10 against the oracle's FP64 solution."""
+    print(f"[gpu] matrix-core refinement N={N}", flush=True)
+    p = Pair(sem, N, 3, 2, 2, mapping=orc.MAP_SINE_CYCLIC)
+    try:
+        t = torch()
+        m = p.m
+        k, a, phi = fourier_modes(seed=5)
+        b = t.empty(m.nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(p.h, b, sem.SEM_SRC_FOURIER, (k, a, phi))
+        x, st = _solve(sem, p, b, rtol=1e-10, maxit=5000,
+                       inner_prec=sem.SEM_BF16_MFMA, inner_rtol=1e-3, check_every=8)
+        print(f"[matrix-core refinement N={N}] {st}")
+        assert st["status"] == 0 and st["final_rel_res"] <= 1e-10
+        assert st["outer_contraction"] < 0.1
+        bo = orc.to_global(m, orc.rhs_local(m, orc.src_fourier(m.X, k, a, phi)))
+        xo, so, _, _ = orc.pcg(m, bo, 1e-12, 5000)
+        rel = np.linalg.norm(orc.to_global(m, x) - xo) / np.linalg.norm(xo)
+        print(f"[matrix-core refinement N={N}] ||x - x_oracle|| / ||x_oracle|| = {rel:.3e}")
+        assert rel <= 1e-7
+    finally:
+        p.close()
