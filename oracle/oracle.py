@@ -56,9 +56,9 @@ def lib():
         L.orc_gll.argtypes = [C.c_int, _dp, _dp]
         L.orc_gll.restype = C.c_int
         L.orc_dmat.argtypes = [C.c_int, _dp, _dp]
-        L.orc_num_global.argtypes = [C.c_int] * 4
+        L.orc_num_global.argtypes = [C.c_int] * 5
         L.orc_num_global.restype = _i64
-        L.orc_maps.argtypes = [C.c_int] * 5 + [_ip, _ip, _ip, _ip, _up]
+        L.orc_maps.argtypes = [C.c_int] * 6 + [_ip, _ip, _ip, _ip, _up]
         L.orc_coords.argtypes = [C.c_int] * 5 + [_dp, _dp]
         L.orc_geom.argtypes = [C.c_int, _i64, _dp, _dp, _dp, C.c_void_p, _dp,
                                _dp, C.POINTER(C.c_double)]
@@ -143,6 +143,7 @@ class Mesh:
     # lumped mass term of the weak form (section 4.2.1): H = alpha(X) B per
     # local node, or None when alpha = 0
     H: np.ndarray | None = None
+    periodic: int = 0    # bit 1 x, 2 y, 4 z
 
     @property
     def n1(self):
@@ -161,17 +162,20 @@ class Mesh:
         return int(self.offsets.shape[0] - 1)
 
 
-def maps(N, ex, ey, ez, dirichlet=1):
+def maps(N, ex, ey, ez, dirichlet=1, periodic=0):
+    """Distinct global-local numbering; ``periodic`` bit 1 x, 2 y, 4 z
+    identifies the faces at 0 and 1 of that direction (no Dirichlet mask
+    there)."""
     n1 = N + 1
     nL = ex * ey * ez * n1 ** 3
-    nG = int(lib().orc_num_global(N, ex, ey, ez))
+    nG = int(lib().orc_num_global(N, ex, ey, ez, int(periodic)))
     l2g = np.zeros(nL, np.int32)
     perm = np.zeros(nL, np.int32)
     offsets = np.zeros(nG + 1, np.int32)
     mult = np.zeros(nL, np.int32)
     bmask = np.zeros(nL, np.uint8)
-    lib().orc_maps(N, ex, ey, ez, int(dirichlet), l2g, perm, offsets, mult,
-                   bmask)
+    lib().orc_maps(N, ex, ey, ez, int(dirichlet), int(periodic), l2g, perm,
+                   offsets, mult, bmask)
     return l2g, perm, offsets, mult, bmask
 
 
@@ -210,14 +214,17 @@ def geom(N, E, w, D, X, kappa=None):
 
 
 def mesh(N, ex, ey, ez, mapping=MAP_AFFINE, dirichlet=1, kappa_params=None,
-         alpha=0.0, alpha_nodal=None):
+         alpha=0.0, alpha_nodal=None, periodic=0):
     """Build everything the operator needs.  ``kappa_params`` is
     ``(omega[M,3], b[M], sigma)`` for kappa = exp(GRF) or None (kappa = 1).
     The mass coefficient alpha(X) of the screened equation is the constant
-    ``alpha`` or, when given, the nodal array ``alpha_nodal`` (E-vector)."""
+    ``alpha`` or, when given, the nodal array ``alpha_nodal`` (E-vector).
+    ``periodic`` (bit 1 x, 2 y, 4 z) makes those directions periodic: each
+    element keeps its own node positions (the copies of a node on the
+    identified faces sit at 0 and at 1)."""
     xi, w = gll(N)
     D = dmat(N, xi)
-    l2g, perm, offsets, mult, bmask = maps(N, ex, ey, ez, dirichlet)
+    l2g, perm, offsets, mult, bmask = maps(N, ex, ey, ez, dirichlet, periodic)
     X = coords(N, ex, ey, ez, mapping, xi)
     kappa = None
     if kappa_params is not None:
@@ -229,7 +236,7 @@ def mesh(N, ex, ey, ez, mapping=MAP_AFFINE, dirichlet=1, kappa_params=None,
     elif alpha != 0.0:
         H = float(alpha) * B
     return Mesh(N, ex, ey, ez, int(dirichlet), int(mapping), xi, w, D, l2g,
-                perm, offsets, mult, bmask, X, G, B, mj, kappa, H)
+                perm, offsets, mult, bmask, X, G, B, mj, kappa, H, int(periodic))
 
 
 def _hptr(m: Mesh):

@@ -121,16 +121,25 @@ void orc_dmat(int N, const double *xi, double *D) {
     }
 }
 
-int64_t orc_num_global(int N, int ex, int ey, int ez) {
-  return (int64_t)(ex * N + 1) * (ey * N + 1) * (ez * N + 1);
+/* Periodic directions (bit 1 x, 2 y, 4 z) identify the faces at 0 and 1:
+ * the lattice coordinate E_d N wraps to 0, so that direction has E_d N
+ * distinct coordinates instead of E_d N + 1 (the global numbering of the
+ * distinct nodes, section 4.2.1, on a periodic box). */
+static int64_t orc_lattice(int E, int N, int per) { return (int64_t)E * N + (per ? 0 : 1); }
+
+int64_t orc_num_global(int N, int ex, int ey, int ez, int periodic) {
+  return orc_lattice(ex, N, periodic & 1) * orc_lattice(ey, N, periodic & 2) *
+         orc_lattice(ez, N, periodic & 4);
 }
 
-void orc_maps(int N, int ex, int ey, int ez, int dirichlet, int32_t *l2g,
-              int32_t *perm, int32_t *offsets, int32_t *mult, uint8_t *bmask) {
+void orc_maps(int N, int ex, int ey, int ez, int dirichlet, int periodic,
+              int32_t *l2g, int32_t *perm, int32_t *offsets, int32_t *mult,
+              uint8_t *bmask) {
   const int n1 = N + 1;
   const int64_t n3 = (int64_t)n1 * n1 * n1;
-  const int64_t Gx = (int64_t)ex * N + 1, Gy = (int64_t)ey * N + 1,
-                Gz = (int64_t)ez * N + 1;
+  const int64_t Gx = orc_lattice(ex, N, periodic & 1),
+                Gy = orc_lattice(ey, N, periodic & 2),
+                Gz = orc_lattice(ez, N, periodic & 4);
   const int64_t E = (int64_t)ex * ey * ez;
   const int64_t nL = E * n3, nG = Gx * Gy * Gz;
 
@@ -140,10 +149,14 @@ void orc_maps(int N, int ex, int ey, int ez, int dirichlet, int32_t *l2g,
       for (int j = 0; j < n1; ++j)
         for (int i = 0; i < n1; ++i) {
           int64_t l = e * n3 + i + (int64_t)n1 * j + (int64_t)n1 * n1 * k;
-          int64_t gx = exi * N + i, gy = eyi * N + j, gz = ezi * N + k;
+          /* the coordinate E_d N of a periodic direction is coordinate 0 */
+          int64_t gx = (exi * N + i) % Gx, gy = (eyi * N + j) % Gy,
+                  gz = (ezi * N + k) % Gz;
           l2g[l] = (int32_t)(gx + Gx * (gy + Gy * gz));
-          int onb = gx == 0 || gx == Gx - 1 || gy == 0 || gy == Gy - 1 ||
-                    gz == 0 || gz == Gz - 1;
+          /* Dirichlet faces: the outer faces of the non-periodic directions */
+          int onb = (!(periodic & 1) && (gx == 0 || gx == Gx - 1)) ||
+                    (!(periodic & 2) && (gy == 0 || gy == Gy - 1)) ||
+                    (!(periodic & 4) && (gz == 0 || gz == Gz - 1));
           bmask[l] = (uint8_t)(dirichlet && onb);
         }
   }

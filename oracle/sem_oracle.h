@@ -43,13 +43,16 @@ int orc_gll(int N, double *xi, double *w);
 /* Nodal derivative matrix D[i*(N+1)+j] = l_j'(xi_i). */
 void orc_dmat(int N, const double *xi, double *D);
 
-int64_t orc_num_global(int N, int ex, int ey, int ez);
+/* Number of distinct global nodes; periodic: bit 1 x, 2 y, 4 z. */
+int64_t orc_num_global(int N, int ex, int ey, int ez, int periodic);
 
 /* Maps: l2g[nL], perm[nL] (local ids sorted by (g,l)), offsets[nG+1],
  * mult[nL] (copies of l's global node), bmask[nL] (1 on Dirichlet nodes,
- * i.e. global nodes on the outer faces when dirichlet != 0). */
-void orc_maps(int N, int ex, int ey, int ez, int dirichlet, int32_t *l2g,
-              int32_t *perm, int32_t *offsets, int32_t *mult, uint8_t *bmask);
+ * i.e. global nodes on the outer faces of the non-periodic directions when
+ * dirichlet != 0).  A periodic direction identifies its faces at 0 and 1. */
+void orc_maps(int N, int ex, int ey, int ez, int dirichlet, int periodic,
+              int32_t *l2g, int32_t *perm, int32_t *offsets, int32_t *mult,
+              uint8_t *bmask);
 
 /* Physical coordinates X[3*nL] (x block, y block, z block) of every local
  * GLL node of the unit cube [0,1]^3 under the chosen mapping. */
