@@ -19,8 +19,9 @@
  *   - n1 = N+1; element e = ex + Ex*(ey + Ey*ez); element-local node
  *     (i,j,k), i fastest; local ("E-vector") index
  *     l = e*n1^3 + i + n1*j + n1^2*k; n_local = E*n1^3.
- *   - global (unique) node g = (ex*N+i) + Gx*((ey*N+j) + Gy*(ez*N+k)),
- *     Gd = Ed*N+1; n_global = Gx*Gy*Gz.
+ *   - global (unique) node g = gx + Gx*(gy + Gy*gz), gx = ex*N+i (y, z
+ *     alike), Gd = Ed*N+1, or Gd = Ed*N with gd taken modulo Gd in a
+ *     periodic direction; n_global = Gx*Gy*Gz.
  *   - Vectors passed to the calls are DEVICE pointers owned by the caller,
  *     contiguous, 256-byte aligned is recommended, in E-vector layout.
  *     Their element type is set by the sem_precision argument:
@@ -115,6 +116,16 @@ typedef struct {
    * on the copies of a global node), finite and >= 0; NULL: the constant
    * alpha above.  Read during sem_setup only. */
   const double *alpha_nodal;
+  /* Periodic directions, bit 1 x, 2 y, 4 z (0: none): the faces at 0 and 1
+   * of that direction are identified (the distinct global-local numbering
+   * of section 4.2.1 then has E_d N node coordinates in it; the Dirichlet
+   * mask covers only the faces of non-periodic directions).  Each element
+   * keeps its own node positions, so the copies of a node on the identified
+   * faces sit at 0 and at 1: the mapping, kappa and the right-hand side
+   * should be periodic (the sine mappings are).  With every direction
+   * periodic (or dirichlet = 0) the operator is positive definite only
+   * with alpha > 0 (section 4.2, equation semPDE). */
+  int32_t periodic;
 } sem_mesh_desc;
 
 /* Right-hand side f(X) for sem_rhs.  HOST pointers. */

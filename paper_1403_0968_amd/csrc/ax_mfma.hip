@@ -572,13 +572,13 @@ __global__ void __launch_bounds__(64 * MW)
       const bool act = e0 + wv < epb && e < sd.E;
       uint16_t gq[6][8];
       load_factors<N1>(l, act, e, G, gq);
-      int64_t gb = 0;
-      if (act) gb = box_origin(sd.box, (uint32_t)e);
+      ElemXYZ c3 = {0u, 0u, 0u};
+      if (act) c3 = box_elem(sd.box, (uint32_t)e);
 #pragma unroll
       for (int t = 0; t < 8; ++t) {
         const int p = l + 64 * t, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
         const bool in = act && i < N1 && j < N1 && k < N1;
-        const float v = in ? u[gb + i + (int64_t)sd.box.Gx * j + sd.box.Gxy * k] : 0.f;
+        const float v = in ? u[box_node(sd.box, c3, i, j, k)] : 0.f;
         const uint16_t hi = f32_to_bf16(v);
         L.u[p] = hi;
         L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
@@ -627,11 +627,11 @@ __global__ void __launch_bounds__(64 * MW9)
       const bool act = e0 + wv < epb && e < sd.E;
       uint16_t gq[2][6][9];
       load_factors9(l, act, e, G, gq);
-      int64_t gb = 0;
-      if (act) gb = box_origin(sd.box, (uint32_t)e);
+      ElemXYZ c3 = {0u, 0u, 0u};
+      if (act) c3 = box_elem(sd.box, (uint32_t)e);
       for (int p = l; p < E9; p += 64) {
         const int i = p % 9, j = (p / 9) % 9, k = p / 81;
-        const float v = act ? u[gb + i + (int64_t)sd.box.Gx * j + sd.box.Gxy * k] : 0.f;
+        const float v = act ? u[box_node(sd.box, c3, i, j, k)] : 0.f;
         const uint16_t hi = f32_to_bf16(v);
         L.u[p] = hi;
         L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));

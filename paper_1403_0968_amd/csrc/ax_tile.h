@@ -103,13 +103,24 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
     // lane c reads the 16-byte row (k, j) = (c / 8, c % 8) of the element
     if (act) urow = *(gp<const u32x4>)(u + e * N3 + 8 * c);
   } else if constexpr (GATHER) {
-    int64_t gb = 0, gk = 0;
+    // the column's global (x, y) offset and the element's first z
+    // coordinate; a coordinate E_d N of a periodic direction wraps to 0
+    int64_t gxy = 0;
+    uint32_t gz0 = 0;
+    int32_t Gz = 0;
+    int64_t Gxy = 0;
     if (act) {
-      gb = box_origin(*box, (uint32_t)e) + i + (int64_t)box->Gx * j;
-      gk = box->Gxy;
+      const ElemXYZ c3 = box_elem(*box, (uint32_t)e);
+      const uint32_t gx = wrap_coord(c3.x * (uint32_t)(N1 - 1) + i, box->Gx);
+      const uint32_t gy = wrap_coord(c3.y * (uint32_t)(N1 - 1) + j, box->Gy);
+      gxy = (int64_t)gx + (int64_t)box->Gx * gy;
+      gz0 = c3.z * (uint32_t)(N1 - 1);
+      Gz = box->Gz;
+      Gxy = box->Gxy;
     }
 #pragma unroll
-    for (int k = 0; k < N1; ++k) ucol[k] = act ? u[gb + k * gk] : TU(0);
+    for (int k = 0; k < N1; ++k)
+      ucol[k] = act ? u[gxy + Gxy * wrap_coord(gz0 + k, Gz)] : TU(0);
   } else {
 #pragma unroll
     for (int k = 0; k < N1; ++k) ucol[k] = act ? u[base + k * NP] : TU(0);

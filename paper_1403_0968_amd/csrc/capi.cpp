@@ -87,6 +87,8 @@ sem_status sem_setup(const sem_mesh_desc *d, void *stream, sem_handle **out) {
     need(std::isfinite(d->alpha) && d->alpha >= 0.0,
          "sem_setup: alpha must be finite and >= 0");
     need(d->kappa_nfeat >= 0, "sem_setup: kappa_nfeat must be >= 0");
+    need(d->periodic >= 0 && d->periodic <= 7,
+         "sem_setup: periodic takes the bits 1 (x), 2 (y), 4 (z)");
     need(d->kappa_nfeat == 0 || (d->kappa_omega && d->kappa_b),
          "sem_setup: kappa features need omega and b");
     h = new sem_handle();

@@ -16,6 +16,7 @@
 // when t is a multiple of N strictly inside (0, E_d N), else to one; the
 // copies of a global node, visited with z outermost and the lower element
 // first in every direction, come out in ascending local index.
+#include <algorithm>
 #include <cmath>
 #include <stdexcept>
 
@@ -94,12 +95,15 @@ RefElem make_ref_elem(int N) {
   return r;
 }
 
-HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet) {
+HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet, int periodic) {
   HostMaps M;
   const int n1 = N + 1;
   const int64_t n3 = (int64_t)n1 * n1 * n1;
-  const int64_t Gx = (int64_t)ex * N + 1, Gy = (int64_t)ey * N + 1,
-                Gz = (int64_t)ez * N + 1;
+  // a periodic direction (bit 1 x, 2 y, 4 z) identifies its faces at 0 and
+  // 1: E_d N coordinates, the coordinate E_d N wrapping to 0
+  const bool px = periodic & 1, py = periodic & 2, pz = periodic & 4;
+  const int64_t Gx = (int64_t)ex * N + (px ? 0 : 1), Gy = (int64_t)ey * N + (py ? 0 : 1),
+                Gz = (int64_t)ez * N + (pz ? 0 : 1);
   const int64_t E = (int64_t)ex * ey * ez;
   M.nL = E * n3;
   M.nG = Gx * Gy * Gz;
@@ -114,17 +118,27 @@ HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet) {
       for (int j = 0; j < n1; ++j)
         for (int i = 0; i < n1; ++i) {
           const int64_t l = e * n3 + i + n1 * j + (int64_t)n1 * n1 * k;
-          const int64_t gx = a * N + i, gy = b * N + j, gz = c * N + k;
+          const int64_t gx = (a * N + i) % Gx, gy = (b * N + j) % Gy,
+                        gz = (c * N + k) % Gz;
           M.l2g[l] = (int32_t)(gx + Gx * (gy + Gy * gz));
-          const bool edge = gx == 0 || gx == Gx - 1 || gy == 0 || gy == Gy - 1 ||
-                            gz == 0 || gz == Gz - 1;
+          const bool edge = (!px && (gx == 0 || gx == Gx - 1)) ||
+                            (!py && (gy == 0 || gy == Gy - 1)) ||
+                            (!pz && (gz == 0 || gz == Gz - 1));
           M.bmask[l] = (uint8_t)(dirichlet && edge);
         }
   }
 
   // per-direction owners of a lattice coordinate: (element, local index),
-  // lower element first
-  auto owners = [N](int64_t t, int64_t Ed, int64_t *el, int *loc) -> int {
+  // lower element first (coordinate 0 of a periodic direction: node 0 of
+  // element 0 and node N of element Ed - 1)
+  auto owners = [N](int64_t t, int64_t Ed, bool per, int64_t *el, int *loc) -> int {
+    if (per && t == 0) {
+      el[0] = 0;
+      loc[0] = 0;
+      el[1] = Ed - 1;
+      loc[1] = N;
+      return 2;
+    }
     if (t % N == 0 && t > 0 && t < Ed * N) {
       el[0] = t / N - 1;
       loc[0] = N;
@@ -147,14 +161,15 @@ HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet) {
   for (int64_t gz = 0; gz < Gz; ++gz) {
     int64_t elz[2], ely[2], elx[2];
     int lz[2], ly[2], lx[2];
-    const int cz = owners(gz, ez, elz, lz);
+    const int cz = owners(gz, ez, pz, elz, lz);
     for (int64_t gy = 0; gy < Gy; ++gy) {
-      const int cy = owners(gy, ey, ely, ly);
+      const int cy = owners(gy, ey, py, ely, ly);
       for (int64_t gx = 0; gx < Gx; ++gx) {
-        const int cx = owners(gx, ex, elx, lx);
+        const int cx = owners(gx, ex, px, elx, lx);
         const int64_t g = gx + Gx * (gy + Gy * gz);
-        const bool onb = gx == 0 || gx == Gx - 1 || gy == 0 || gy == Gy - 1 ||
-                         gz == 0 || gz == Gz - 1;
+        const bool onb = (!px && (gx == 0 || gx == Gx - 1)) ||
+                         (!py && (gy == 0 || gy == Gy - 1)) ||
+                         (!pz && (gz == 0 || gz == Gz - 1));
         const bool masked = dirichlet && onb;
         M.gmask[g] = (uint8_t)masked;
         M.offsets[g] = (int32_t)pos;
@@ -167,6 +182,10 @@ HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet) {
                                 (int64_t)n1 * n1 * lz[qz];
               M.perm[pos++] = (int32_t)l;
             }
+        // ascending local index (a periodic direction with one element
+        // puts its two copies in the same element, which the nesting above
+        // does not order)
+        std::sort(M.perm.begin() + start, M.perm.begin() + pos);
         const int cnt = cx * cy * cz;
         if (masked) {
           for (int64_t q = start; q < pos; ++q) M.masked_lids.push_back(M.perm[q]);

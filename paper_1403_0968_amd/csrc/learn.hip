@@ -503,7 +503,7 @@ static const float *learn_damping_dev(const sem_handle *h) {
 template <class TV, bool UNIQUE, int M, int Q, bool FUSE>
 static void launch_ca(const sem_handle *h, const Learn *L, const TV *r, float *out,
                       TV *zf, const TV *wL, double *epart, hipStream_t s) {
-  const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet) : Box{};
+  const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet, h->periodic) : Box{};
   const int64_t groups = (h->E + CA_WAVES - 1) / CA_WAVES;
   const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * 8);
   hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, M, Q, FUSE>), dim3(grid),

@@ -53,7 +53,8 @@ struct HostMaps {
   std::vector<int32_t> seg_off, seg_ids;    // shared, non-Dirichlet nodes
   std::vector<int32_t> solo_lids;           // single-copy, non-Dirichlet nodes
 };
-HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet);
+// periodic: bit 1 x, 2 y, 4 z (faces at 0 and 1 identified)
+HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet, int periodic);
 
 // ---------------------------------------------------------------------------
 // device buffers
@@ -137,6 +138,7 @@ struct Learn;      // learned-correction buffers (learn.hip)
 
 struct sem_handle {
   int N = 0, n1 = 0, ex = 0, ey = 0, ez = 0, dirichlet = 0, mapping = 0;
+  int periodic = 0;  // bit 1 x, 2 y, 4 z
   int64_t E = 0, nL = 0, nG = 0, n_masked = 0, n_seg = 0, n_solo = 0;
   sem::RefElem ref;
 

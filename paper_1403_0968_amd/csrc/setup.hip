@@ -216,13 +216,14 @@ static void upload(DevBuf &b, const std::vector<T> &v, hipStream_t s) {
 void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
   const int T = 256;
   h->ref = make_ref_elem(d->N);
-  HostMaps M = make_maps(d->N, d->ex, d->ey, d->ez, d->dirichlet);
+  HostMaps M = make_maps(d->N, d->ex, d->ey, d->ez, d->dirichlet, d->periodic);
   h->N = d->N;
   h->n1 = d->N + 1;
   h->ex = d->ex;
   h->ey = d->ey;
   h->ez = d->ez;
   h->dirichlet = d->dirichlet;
+  h->periodic = d->periodic;
   h->mapping = d->mapping;
   h->has_mass = d->alpha_nodal != nullptr || d->alpha != 0.0;
   h->E = (int64_t)d->ex * d->ey * d->ez;

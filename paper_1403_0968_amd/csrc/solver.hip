@@ -77,6 +77,42 @@ __device__ inline void strided_sums(const double *__restrict__ part, int stride,
   }
 }
 
+// sum of the (up to 8) copies of a node, v[4 a + 2 b + c] holding copy a
+// along z, b along y, c along x (+0.0 for an absent copy, which leaves the
+// sum unchanged bit for bit: it starts at +0.0 and so is never -0.0), in
+// ascending local index: the box's direction order (copy_order)
+template <class TV> __device__ inline TV sum_copies(int order, const TV (&v)[8]) {
+  TV s = TV(0);
+#define SEM_SUM3(A, B, C)                                  \
+  _Pragma("unroll") for (int A = 0; A < 2; ++A)            \
+    _Pragma("unroll") for (int B = 0; B < 2; ++B)          \
+      _Pragma("unroll") for (int C = 0; C < 2; ++C) s = s + v[4 * a + 2 * b + c];
+  switch (order) {
+    case 0: {
+      SEM_SUM3(a, b, c)
+      break;
+    }
+    case 1: {
+      SEM_SUM3(b, c, a)
+      break;
+    }
+    case 2: {
+      SEM_SUM3(a, c, b)
+      break;
+    }
+    case 3: {
+      SEM_SUM3(c, a, b)
+      break;
+    }
+    default: {
+      SEM_SUM3(b, a, c)
+      break;
+    }
+  }
+#undef SEM_SUM3
+  return s;
+}
+
 // --------------------------------------------------------------------------
 // vector kernels (persistent over VecItem lists)
 // --------------------------------------------------------------------------
@@ -131,8 +167,7 @@ __global__ void __launch_bounds__(RT)
               const int64_t lid = ok ? copy_lid(bx, nc, a, b, c) : 0;
               v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
             }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) s = s + v[k];
+        s = sum_copies(bx.order, v);
       }
       wG[g] = s;
       if (DOT) acc += (double)p[g] * (double)s;
@@ -238,8 +273,7 @@ __global__ void __launch_bounds__(RT)
               const int64_t lid = ok ? copy_lid(bx, nc, a, b, c) : 0;
               v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
             }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) sw = sw + v[k];
+        sw = sum_copies(bx.order, v);
       }
       return sw;
     };
@@ -853,7 +887,7 @@ static BatchSolve describe(sem_handle *h, int q, void *const v64[NVEC],
   d.E = h->E;
   d.nL = h->nL;
   d.nG = h->nG;
-  d.box = make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet);
+  d.box = make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet, h->periodic);
   d.G64 = h->G64.p;
   d.G32 = h->G32.p;
   d.G16 = h->G16.p;
@@ -1019,7 +1053,7 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
     const int32_t *stop =
         skip_done ? &b->st.as<CgState>()[0].done : (const int32_t *)nullptr;
     launch_ax_solve(h->N, prec, h->E, D, G, H, u, w,
-                    make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet), stop,
+                    make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet, h->periodic), stop,
                     edot ? d.edot : nullptr, b->s);
     return;
   }

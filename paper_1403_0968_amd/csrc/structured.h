@@ -3,7 +3,10 @@
 // lexicographic E_x x E_y x E_z box of order N:
 //   element  e = ex + Ex (ey + Ey ez),
 //   local    l = e n1^3 + i + n1 j + n1^2 k,          n1 = N + 1,
-//   global   g = (ex N + i) + Gx ((ey N + j) + Gy (ez N + k)),  G_d = E_d N + 1.
+//   global   g = gx + Gx (gy + Gy gz),  gx = ex N + i (and y, z alike),
+// with G_d = E_d N + 1 coordinates per direction, or G_d = E_d N in a
+// periodic direction, whose faces at 0 and 1 are identified (the coordinate
+// E_d N wraps to 0).
 // The solvers use it in place of the l2g / perm / offsets arrays (the
 // arrays stay the reference numbering of sem_gs and the exports): a global
 // node's local copies are enumerated in ascending local index, the order
@@ -42,22 +45,45 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
 }
 
 struct Box {
-  int32_t N, n1, Ex, Ey, Ez, Gx, Gy, Gz, dirichlet, pad;
+  int32_t N, n1, Ex, Ey, Ez, Gx, Gy, Gz, dirichlet, periodic;  // periodic: bit 1 x, 2 y, 4 z
+  // order of the copy directions in ascending local index (copy_order)
+  int32_t order, pad;
   int64_t Gxy;
   FastDiv dEx, dEy, dGx, dGxy, dN;
 };
 
-inline Box make_box(int N, int Ex, int Ey, int Ez, int dirichlet) {
+// The copies of a global node are the combinations of at most two copies
+// per direction.  In ascending local index l = e n1^3 + i + n1 j + n1^2 k
+// they come direction by direction, the direction whose two copies differ
+// most in l outermost: copies in different elements differ by at least
+// one element (n1^3 > N (n1^2 + n1 + 1)), z more than y more than x; the
+// two copies of a periodic direction with a single element lie in the
+// same element (at node 0 and N) and differ by N, N n1 or N n1^2 only.
+// Orders (outer to inner): 0 z y x, 1 y x z, 2 z x y, 3 x z y, 4 y z x.
+inline int copy_order(int Ex, int Ey, int Ez, int periodic) {
+  const bool wx = (periodic & 1) && Ex == 1, wy = (periodic & 2) && Ey == 1,
+             wz = (periodic & 4) && Ez == 1;
+  // element-level directions first (z, y, x), then the in-element ones
+  // (z, y, x); an in-element x is innermost in either group
+  if (wz && wy) return wx ? 0 : 3;  // x z y (all three in-element: z y x)
+  if (wz) return wx ? 4 : 1;        // y z x, or y x z
+  if (wy) return wx ? 0 : 2;        // z y x, or z x y
+  return 0;
+}
+
+inline Box make_box(int N, int Ex, int Ey, int Ez, int dirichlet, int periodic) {
   Box b;
   b.N = N;
   b.n1 = N + 1;
   b.Ex = Ex;
   b.Ey = Ey;
   b.Ez = Ez;
-  b.Gx = Ex * N + 1;
-  b.Gy = Ey * N + 1;
-  b.Gz = Ez * N + 1;
+  b.Gx = Ex * N + ((periodic & 1) ? 0 : 1);
+  b.Gy = Ey * N + ((periodic & 2) ? 0 : 1);
+  b.Gz = Ez * N + ((periodic & 4) ? 0 : 1);
   b.dirichlet = dirichlet;
+  b.periodic = periodic;
+  b.order = copy_order(Ex, Ey, Ez, periodic);
   b.pad = 0;
   b.Gxy = (int64_t)b.Gx * b.Gy;
   b.dEx = make_fastdiv((uint32_t)Ex);
@@ -76,20 +102,49 @@ __host__ __device__ inline int64_t box_origin(const Box &b, uint32_t e) {
          (int64_t)b.Gx * ((int64_t)ey * b.N + (int64_t)b.Gy * ((int64_t)ez * b.N));
 }
 
-// the copies of a node along one direction: global coordinate x in [0, E N]
-// lies in element c0 at node index i0 and, when cnt == 2, also in element
-// c0 + 1 at node index 0 (ascending element order)
+// element coordinates (ex, ey, ez) of element e
+struct ElemXYZ {
+  uint32_t x, y, z;
+};
+__host__ __device__ inline ElemXYZ box_elem(const Box &b, uint32_t e) {
+  const uint32_t t = fdiv(e, b.dEx), ex = e - t * (uint32_t)b.Ex;
+  const uint32_t ez = fdiv(t, b.dEy), ey = t - ez * (uint32_t)b.Ey;
+  return {ex, ey, ez};
+}
+
+// lattice coordinate c = e_d N + i (at most G_d) of one direction: in a
+// periodic direction E_d N is coordinate 0; otherwise c < G_d already
+__host__ __device__ inline uint32_t wrap_coord(uint32_t c, int32_t G) {
+  return c == (uint32_t)G ? 0u : c;
+}
+
+// global index of node (i, j, k) of the element at coordinates c
+__host__ __device__ inline int64_t box_node(const Box &b, const ElemXYZ &c, uint32_t i,
+                                            uint32_t j, uint32_t k) {
+  const uint32_t gx = wrap_coord(c.x * (uint32_t)b.N + i, b.Gx);
+  const uint32_t gy = wrap_coord(c.y * (uint32_t)b.N + j, b.Gy);
+  const uint32_t gz = wrap_coord(c.z * (uint32_t)b.N + k, b.Gz);
+  return (int64_t)gx + (int64_t)b.Gx * ((int64_t)gy + (int64_t)b.Gy * gz);
+}
+
+// the copies of a node along one direction, in ascending element order:
+// global coordinate x lies in element c0 at node index i0 and, when
+// cnt == 2, also in element c1 at node index i1
 struct AxisCopies {
-  uint32_t c0, i0;
+  uint32_t c0, i0, c1, i1;
   int cnt;
 };
 
 __host__ __device__ inline AxisCopies axis_copies(uint32_t x, uint32_t E,
-                                                  uint32_t N, const FastDiv &dN) {
+                                                  uint32_t N, const FastDiv &dN,
+                                                  bool periodic) {
+  // periodic: coordinate 0 is node 0 of element 0 and node N of element
+  // E - 1 (the same element when E = 1: node 0 before node N)
+  if (periodic && x == 0) return {0, 0, E - 1, N, 2};
   const uint32_t q = fdiv(x, dN), i = x - q * N;
-  if (q == E) return {E - 1, N, 1};
-  if (i == 0 && q > 0) return {q - 1, N, 2};
-  return {q, i, 1};
+  if (q == E) return {E - 1, N, 0, 0, 1};
+  if (i == 0 && q > 0) return {q - 1, N, q, 0, 2};
+  return {q, i, 0, 0, 1};
 }
 
 struct NodeCopies {
@@ -102,21 +157,24 @@ __host__ __device__ inline NodeCopies node_copies(const Box &b, uint32_t g) {
   const uint32_t rem = g - gz * (uint32_t)b.Gxy;
   const uint32_t gy = fdiv(rem, b.dGx), gx = rem - gy * (uint32_t)b.Gx;
   NodeCopies c;
-  c.x = axis_copies(gx, b.Ex, b.N, b.dN);
-  c.y = axis_copies(gy, b.Ey, b.N, b.dN);
-  c.z = axis_copies(gz, b.Ez, b.N, b.dN);
+  const bool px = b.periodic & 1, py = b.periodic & 2, pz = b.periodic & 4;
+  c.x = axis_copies(gx, b.Ex, b.N, b.dN, px);
+  c.y = axis_copies(gy, b.Ey, b.N, b.dN, py);
+  c.z = axis_copies(gz, b.Ez, b.N, b.dN, pz);
+  // Dirichlet faces: the outer faces of the non-periodic directions
   c.masked = b.dirichlet &&
-             (gx == 0 || gy == 0 || gz == 0 || gx == (uint32_t)b.Gx - 1 ||
-              gy == (uint32_t)b.Gy - 1 || gz == (uint32_t)b.Gz - 1);
+             ((!px && (gx == 0 || gx == (uint32_t)b.Gx - 1)) ||
+              (!py && (gy == 0 || gy == (uint32_t)b.Gy - 1)) ||
+              (!pz && (gz == 0 || gz == (uint32_t)b.Gz - 1)));
   return c;
 }
 
 // local index of copy (a, bb, c) (each 0 or 1, below the counts)
 __host__ __device__ inline int64_t copy_lid(const Box &b, const NodeCopies &nc,
                                             int a, int bb, int c) {
-  const uint32_t ez = nc.z.c0 + a, iz = a ? 0 : nc.z.i0;
-  const uint32_t ey = nc.y.c0 + bb, iy = bb ? 0 : nc.y.i0;
-  const uint32_t ex = nc.x.c0 + c, ix = c ? 0 : nc.x.i0;
+  const uint32_t ez = a ? nc.z.c1 : nc.z.c0, iz = a ? nc.z.i1 : nc.z.i0;
+  const uint32_t ey = bb ? nc.y.c1 : nc.y.c0, iy = bb ? nc.y.i1 : nc.y.i0;
+  const uint32_t ex = c ? nc.x.c1 : nc.x.c0, ix = c ? nc.x.i1 : nc.x.i0;
   const int64_t e = (int64_t)ex + (int64_t)b.Ex * ((int64_t)ey + (int64_t)b.Ey * ez);
   return e * b.n1 * b.n1 * b.n1 + ix + b.n1 * ((int64_t)iy + (int64_t)b.n1 * iz);
 }

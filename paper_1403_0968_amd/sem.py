@@ -49,7 +49,8 @@ class sem_mesh_desc(C.Structure):
                 ("kappa_omega", C.POINTER(C.c_double)),
                 ("kappa_b", C.POINTER(C.c_double)),
                 ("kappa_sigma", C.c_double),
-                ("alpha_nodal", C.POINTER(C.c_double))]
+                ("alpha_nodal", C.POINTER(C.c_double)),
+                ("periodic", C.c_int32)]
 
 
 class sem_source(C.Structure):
@@ -209,13 +210,14 @@ def _dptr(a):
 # ----------------------------------------------------------------------------
 
 def sem_setup(N, ex, ey, ez, mapping=SEM_MAP_AFFINE, dirichlet=1,
-              kappa=None, stream=None, alpha=0.0, alpha_nodal=None):
+              kappa=None, stream=None, alpha=0.0, alpha_nodal=None, periodic=0):
     """kappa: None or (omega[M,3], b[M], sigma).  alpha: constant mass
     coefficient; alpha_nodal: host array of n_local values (replaces the
-    constant).  Returns an opaque handle."""
+    constant).  periodic: bit 1 x, 2 y, 4 z.  Returns an opaque handle."""
     d = sem_mesh_desc()
     d.N, d.ex, d.ey, d.ez = N, ex, ey, ez
     d.dirichlet, d.mapping, d.alpha = int(dirichlet), int(mapping), float(alpha)
+    d.periodic = int(periodic)
     keep = []
     if alpha_nodal is not None:
         al_a, al_p = _dptr(alpha_nodal)

@@ -48,15 +48,15 @@ class Pair:
     """A library handle and the oracle mesh for the same discretisation."""
 
     def __init__(self, sem, N, ex, ey, ez, mapping=0, dirichlet=1, kappa=None,
-                 oracle=True, alpha=0.0, alpha_nodal=None):
+                 oracle=True, alpha=0.0, alpha_nodal=None, periodic=0):
         self.sem = sem
         self.N, self.ex, self.ey, self.ez = N, ex, ey, ez
         self.h = sem.sem_setup(N, ex, ey, ez, mapping=mapping,
                                dirichlet=dirichlet, kappa=kappa, alpha=alpha,
-                               alpha_nodal=alpha_nodal)
+                               alpha_nodal=alpha_nodal, periodic=periodic)
         self.E, self.nL, self.nG = sem.sem_query(self.h)
         self.m = (orc.mesh(N, ex, ey, ez, mapping, dirichlet, kappa,
-                           alpha=alpha, alpha_nodal=alpha_nodal)
+                           alpha=alpha, alpha_nodal=alpha_nodal, periodic=periodic)
                   if oracle else None)
 
     def close(self):
