@@ -467,9 +467,9 @@ def bench_config1(sem, torch):
 
 def bench_gs(sem, torch, h, nL, n=200):
     """sem_gs (FP64) on the benchmark mesh: per-launch statistics and the
-    algorithmic bytes of the gather-scatter lists (shared copies: id 4, read
-    8, write 8; single-copy nodes the same; Dirichlet copies: id 4, write 8;
-    segment offsets 4 per shared node)."""
+    algorithmic bytes of the sorted-map gather-scatter (per global node:
+    offset 4 and mask flag 1; shared copies: id 4, read 8, write 8;
+    single-copy nodes: id 4, read 8; Dirichlet copies: id 4, write 8)."""
     mult = torch.empty(nL, dtype=torch.int32, device="cuda")
     mask = torch.empty(nL, dtype=torch.uint8, device="cuda")
     sem.sem_export(h, sem.SEM_ARR_MULT, mult)
@@ -479,7 +479,8 @@ def bench_gs(sem, torch, h, nL, n=200):
     shared = int((free & (mult > 1)).sum())
     solo = int((free & (mult == 1)).sum())
     segs = int(((free & (mult > 1)).double() / mult.double()).sum().round())
-    byts = 20 * shared + 20 * solo + 12 * masked + 4 * segs
+    _, _, nG = sem.sem_query(h)
+    byts = 5 * nG + 20 * shared + 12 * solo + 12 * masked
     v = torch.rand(nL, dtype=torch.float64, device="cuda")
     for _ in range(20):
         sem.sem_gs(h, sem.SEM_FP64, v)

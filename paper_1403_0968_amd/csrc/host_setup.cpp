@@ -156,7 +156,6 @@ HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet, int periodic) {
   M.offsets.resize(M.nG + 1);
   M.perm.resize(M.nL);
   M.gmask.resize(M.nG);
-  M.seg_off.push_back(0);
   int64_t pos = 0;
   for (int64_t gz = 0; gz < Gz; ++gz) {
     int64_t elz[2], ely[2], elx[2];
@@ -186,15 +185,6 @@ HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet, int periodic) {
         // puts its two copies in the same element, which the nesting above
         // does not order)
         std::sort(M.perm.begin() + start, M.perm.begin() + pos);
-        const int cnt = cx * cy * cz;
-        if (masked) {
-          for (int64_t q = start; q < pos; ++q) M.masked_lids.push_back(M.perm[q]);
-        } else if (cnt > 1) {
-          for (int64_t q = start; q < pos; ++q) M.seg_ids.push_back(M.perm[q]);
-          M.seg_off.push_back((int32_t)M.seg_ids.size());
-        } else {
-          M.solo_lids.push_back(M.perm[start]);
-        }
       }
     }
   }

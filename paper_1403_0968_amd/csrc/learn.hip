@@ -505,7 +505,7 @@ static void launch_ca(const sem_handle *h, const Learn *L, const TV *r, float *o
                       TV *zf, const TV *wL, double *epart, hipStream_t s) {
   const Box box = UNIQUE ? make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet, h->periodic) : Box{};
   const int64_t groups = (h->E + CA_WAVES - 1) / CA_WAVES;
-  const unsigned grid = (unsigned)std::min<int64_t>(groups, 256 * 8);
+  const unsigned grid = (unsigned)groups;
   hipLaunchKernelGGL((k_coarse_apply<TV, UNIQUE, M, Q, FUSE>), dim3(grid),
                      dim3(64 * CA_WAVES), 0, s, h->E, box, L->tab, L->Sc.as<float>(), r,
                      L->Ml.as<float>(), learn_damping_dev(h), out, zf, wL, epart);

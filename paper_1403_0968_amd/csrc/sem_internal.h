@@ -48,10 +48,6 @@ struct HostMaps {
   std::vector<int32_t> l2g, perm, offsets, mult;
   std::vector<uint8_t> bmask;   // per local node, 1 on Dirichlet nodes
   std::vector<uint8_t> gmask;   // per global node
-  // gather-scatter work lists
-  std::vector<int32_t> masked_lids;         // every local copy of a Dirichlet node
-  std::vector<int32_t> seg_off, seg_ids;    // shared, non-Dirichlet nodes
-  std::vector<int32_t> solo_lids;           // single-copy, non-Dirichlet nodes
 };
 // periodic: bit 1 x, 2 y, 4 z (faces at 0 and 1 identified)
 HostMaps make_maps(int N, int ex, int ey, int ez, int dirichlet, int periodic);
@@ -139,12 +135,11 @@ struct Learn;      // learned-correction buffers (learn.hip)
 struct sem_handle {
   int N = 0, n1 = 0, ex = 0, ey = 0, ez = 0, dirichlet = 0, mapping = 0;
   int periodic = 0;  // bit 1 x, 2 y, 4 z
-  int64_t E = 0, nL = 0, nG = 0, n_masked = 0, n_seg = 0, n_solo = 0;
+  int64_t E = 0, nL = 0, nG = 0;
   sem::RefElem ref;
 
   // maps
-  sem::DevBuf l2g, perm, offsets, mult, bmask, gmask, masked_lids, seg_off,
-      seg_ids, solo_lids;
+  sem::DevBuf l2g, perm, offsets, mult, bmask, gmask;
   // reference element on device
   sem::DevBuf D64, D32, D16hi, D16lo;  // D16hi + D16lo: BF16 split of D
   // geometry and preconditioner

@@ -229,9 +229,6 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
   h->E = (int64_t)d->ex * d->ey * d->ez;
   h->nL = M.nL;
   h->nG = M.nG;
-  h->n_masked = (int64_t)M.masked_lids.size();
-  h->n_seg = (int64_t)M.seg_off.size() - 1;
-  h->n_solo = (int64_t)M.solo_lids.size();
 
   upload(h->l2g, M.l2g, s);
   upload(h->perm, M.perm, s);
@@ -239,10 +236,6 @@ void device_setup(sem_handle *h, const sem_mesh_desc *d, hipStream_t s) {
   upload(h->mult, M.mult, s);
   upload(h->bmask, M.bmask, s);
   upload(h->gmask, M.gmask, s);
-  upload(h->masked_lids, M.masked_lids, s);
-  upload(h->seg_off, M.seg_off, s);
-  upload(h->seg_ids, M.seg_ids, s);
-  upload(h->solo_lids, M.solo_lids, s);
   upload(h->D64, h->ref.D, s);
   std::vector<float> D32(h->ref.D.begin(), h->ref.D.end());
   upload(h->D32, D32, s);

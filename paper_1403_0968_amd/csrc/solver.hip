@@ -130,7 +130,7 @@ template <class TD> __device__ inline gp<const TD> dinv_of(const BatchSolve &s,
 
 // w = mask o Q^T wL (sum of copies in ascending local index, from +0: the
 // summation order of sem_gs); optional partial (p, w) per item
-template <class TV, bool DOT>
+template <class TV, bool DOT, bool PER>
 __global__ void __launch_bounds__(RT)
     k_bassemble(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
                 const VecItem *__restrict__ items, int nitems,
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(RT)
     const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
     double acc = 0.0;
     for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
-      const NodeCopies nc = node_copies(bx, (uint32_t)g);
+      const NodeCopies nc = node_copies<PER>(bx, (uint32_t)g);
       TV s = TV(0);
       if (!nc.masked) {
         // all (up to 8) copies loaded at once, predicated on existence, then
@@ -167,7 +167,7 @@ __global__ void __launch_bounds__(RT)
               const int64_t lid = ok ? copy_lid(bx, nc, a, b, c) : 0;
               v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
             }
-        s = sum_copies(bx.order, v);
+        s = sum_copies(PER ? bx.order : 0, v);
       }
       wG[g] = s;
       if (DOT) acc += (double)p[g] * (double)s;
@@ -237,7 +237,7 @@ __global__ void __launch_bounds__(AT)
 // sem_gs sum them), z = dinv r; partials (r, z), (r, r).  FCG (flexible CG
 // with the learned correction, which the next kernel adds to z): partials
 // (r, z), (z, w_G), (r, r).
-template <class TV, class TD, bool FCG>
+template <class TV, class TD, bool FCG, bool PER>
 __global__ void __launch_bounds__(RT)
     k_bupdate_xr_asm(const BatchSolve *__restrict__ sds,
                      const CgState *__restrict__ st,
@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(RT)
     // an absent copy adds +0.0, which leaves the sum unchanged bit for bit
     // (the sum starts at +0.0 and so is never -0.0)
     auto assembled = [&](int64_t g) {
-      const NodeCopies nc = node_copies(bx, (uint32_t)g);
+      const NodeCopies nc = node_copies<PER>(bx, (uint32_t)g);
       TV sw = TV(0);
       if (!nc.masked) {
         TV v[8];
@@ -273,7 +273,7 @@ __global__ void __launch_bounds__(RT)
               const int64_t lid = ok ? copy_lid(bx, nc, a, b, c) : 0;
               v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
             }
-        sw = sum_copies(bx.order, v);
+        sw = sum_copies(PER ? bx.order : 0, v);
       }
       return sw;
     };
@@ -829,6 +829,7 @@ struct sem_batch {
   int nset = 0;                 // order set the operator kernel is built for
   std::vector<int> orders;      // n1 per solve
   std::vector<sem::BatchSolve> hsd;  // host copies of the solve descriptors
+  bool periodic = false;        // a solve of the batch has a periodic direction
   sem::DevBuf sds, st, vitems, vbeg, part, red, active, maxit, scale;
   sem::DevBuf axitems[3];       // per block size 64 / 128 / 256
   int n_ax[3] = {0, 0, 0};
@@ -953,6 +954,7 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
       }
       sds[q] = describe(h, q, v64, v32, W->one64.as<double>(),
                         W->one32.as<float>(), W->edot.as<double>());
+      if (h->periodic != 0) b->periodic = true;
       vbeg[q] = (int32_t)vis.size();
       for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({q, 0, g});
       b->orders.push_back(h->n1);
@@ -1020,6 +1022,19 @@ void destroy_ws(sem_handle *h) {
 // assembly + r update at 11.4M unique nodes: 114 -> 104 us)
 static int vec_grid(const sem_batch *b) { return b->n_vi; }
 
+// launch an assembly kernel in its variant for the batch's boxes: with a
+// periodic direction in any solve (PER_ = true) or without
+#define SEM_PER_LAUNCH(B, KERNEL, ...)                     \
+  do {                                                     \
+    if ((B)->periodic) {                                   \
+      constexpr bool PER_ = true;                          \
+      hipLaunchKernelGGL(KERNEL, __VA_ARGS__);             \
+    } else {                                               \
+      constexpr bool PER_ = false;                         \
+      hipLaunchKernelGGL(KERNEL, __VA_ARGS__);             \
+    }                                                      \
+  } while (0)
+
 // the operator of every solve of the batch, w_L = A_L Q v_src into VWL;
 // edot: the single-solve kernel also stores the element energies (the
 // batched kernel always does)
@@ -1077,7 +1092,7 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
     // no element energies from the matrix-core operator: assembled w and
     // (p, w) first
     bax(b, prec, VP, VWL, 1);
-    hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds,
+    SEM_PER_LAUNCH(b, (k_bassemble<TV, true, PER_>), dim3(g), dim3(RT), 0, b->s, sds,
                        st, vi, nv, part, 1);
     hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
     hipLaunchKernelGGL((k_bupdate_xr<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
@@ -1085,7 +1100,7 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   } else {
     bax(b, prec, VP, VWL, 1, true);
     hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
-    hipLaunchKernelGGL((k_bupdate_xr_asm<TV, TD, false>), dim3(g), dim3(RT), 0, b->s,
+    SEM_PER_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, false, PER_>), dim3(g), dim3(RT), 0, b->s,
                        sds, st, vi, nv, part, jac);
   }
   hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
@@ -1110,7 +1125,7 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
     // no element energies from the matrix-core operator: assembled w and
     // (p, w) first
     bax(b, prec, VP, VWL, 1);
-    hipLaunchKernelGGL((k_bassemble<TV, true>), dim3(g), dim3(RT), 0, b->s, sds,
+    SEM_PER_LAUNCH(b, (k_bassemble<TV, true, PER_>), dim3(g), dim3(RT), 0, b->s, sds,
                        st, vi, nv, part, 1);
     hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
     hipLaunchKernelGGL((k_bupdate_r_only<TV>), dim3(g), dim3(RT), 0, b->s, sds,
@@ -1122,7 +1137,7 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
     // the element terms of (r, c) and (c, w)
     bax(b, prec, VP, VWL, 1, true);
     hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
-    hipLaunchKernelGGL((k_bupdate_xr_asm<TV, TD, true>), dim3(g), dim3(RT), 0,
+    SEM_PER_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, true, PER_>), dim3(g), dim3(RT), 0,
                        b->s, sds, st, vi, nv, part, 1);
     const BatchSolve &d = b->hsd[0];
     learn_apply_fused(h, f32 ? d.v32[VR] : d.v64[VR], f32 ? d.v32[VZ] : d.v64[VZ],
@@ -1197,7 +1212,7 @@ static void init(sem_batch *b, int prec, int jac, bool x0_zero, double tol2) {
   if (!x0_zero) {
     // w = A x (FP64 only)
     bax(b, SEM_FP64, VX, VWL, 0);
-    hipLaunchKernelGGL((k_bassemble<double, false>), dim3(g), dim3(RT), 0, b->s,
+    SEM_PER_LAUNCH(b, (k_bassemble<double, false, PER_>), dim3(g), dim3(RT), 0, b->s,
                        sds, b->st.as<CgState>(), vi, nv, part, 0);
   }
   if (prec == SEM_FP64)
@@ -1221,7 +1236,7 @@ static void residual(sem_batch *b) {
   const int g = vec_grid(b), nv = b->n_vi;
   const int32_t *act = b->active.as<int32_t>();
   bax(b, SEM_FP64, VX, VWL, 0);
-  hipLaunchKernelGGL((k_bassemble<double, false>), dim3(g), dim3(RT), 0, b->s, sds,
+  SEM_PER_LAUNCH(b, (k_bassemble<double, false, PER_>), dim3(g), dim3(RT), 0, b->s, sds,
                      b->st.as<CgState>(), vi, nv, part, 0);
   hipLaunchKernelGGL(k_bresidual, dim3(g), dim3(RT), 0, b->s, sds, act, vi, nv,
                      part);
@@ -1655,6 +1670,7 @@ sem_status pcg_solve_noalloc(sem_handle *h, const sem_solve_opts *o,
   double *one64 = (double *)take((size_t)h->nG * 8);
   double *edot = (double *)take((size_t)h->E * 8);
   b.hsd.assign(1, describe(h, 0, v64, v32, one64, nullptr, edot));
+  b.periodic = h->periodic != 0;
   std::vector<VecItem> vis;
   for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({0, 0, g});
   b.n_vi = (int)vis.size();

@@ -152,12 +152,16 @@ struct NodeCopies {
   bool masked;  // on the Dirichlet boundary
 };
 
+// PER = false: the caller knows that the box has no periodic direction
+// (the compiler then drops the wrap-around cases)
+template <bool PER = true>
 __host__ __device__ inline NodeCopies node_copies(const Box &b, uint32_t g) {
   const uint32_t gz = fdiv(g, b.dGxy);
   const uint32_t rem = g - gz * (uint32_t)b.Gxy;
   const uint32_t gy = fdiv(rem, b.dGx), gx = rem - gy * (uint32_t)b.Gx;
   NodeCopies c;
-  const bool px = b.periodic & 1, py = b.periodic & 2, pz = b.periodic & 4;
+  const bool px = PER && (b.periodic & 1), py = PER && (b.periodic & 2),
+             pz = PER && (b.periodic & 4);
   c.x = axis_copies(gx, b.Ex, b.N, b.dN, px);
   c.y = axis_copies(gy, b.Ey, b.N, b.dN, py);
   c.z = axis_copies(gz, b.Ez, b.N, b.dN, pz);
