@@ -118,9 +118,11 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
       Gz = box->Gz;
       Gxy = box->Gxy;
     }
+    // gz0 + k < G_z below the element's last z node: only that one wraps
+    const int64_t g0 = gxy + Gxy * gz0;
 #pragma unroll
-    for (int k = 0; k < N1; ++k)
-      ucol[k] = act ? u[gxy + Gxy * wrap_coord(gz0 + k, Gz)] : TU(0);
+    for (int k = 0; k < N1 - 1; ++k) ucol[k] = act ? u[g0 + Gxy * k] : TU(0);
+    ucol[N1 - 1] = act ? u[gxy + Gxy * wrap_coord(gz0 + N1 - 1, Gz)] : TU(0);
   } else {
 #pragma unroll
     for (int k = 0; k < N1; ++k) ucol[k] = act ? u[base + k * NP] : TU(0);
