@@ -4,7 +4,11 @@
 
 Every source under ``csrc/`` is compiled by hipcc for gfx950 and linked into
 ``paper_1403_0968_amd/libsem.so``.  Packed-FP32 instructions are disabled
-for device code (``-packed-fp32-ops``).
+for device code (``-packed-fp32-ops``).  The operator sources are compiled
+without machine-level instruction sinking: the element routine issues all of
+an element's loads before its first use of them, and sinking moves loads
+whose only uses lie past a branch (the LDS stores of a partial workgroup)
+down to those uses, which serialises the memory phases of the kernel.
 """
 from __future__ import annotations
 
@@ -24,6 +28,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-result", "-Wno-unknown-pragmas",
           "-I", os.path.join(HERE, "..", "include")]
+
+
+PER_FILE = {f: ["-mllvm", "-disable-machine-sink"]
+            for f in ("ax.hip", "ax_solve.hip")}
 
 
 def _hipcc():
@@ -46,7 +54,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     def compile_one(src):
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [hipcc, *COMMON, *lang, "-c", src, "-o", obj]
+        cmd = [hipcc, *COMMON, *PER_FILE.get(os.path.basename(src), []), *lang,
+               "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         r = subprocess.run(cmd, capture_output=True, text=True)

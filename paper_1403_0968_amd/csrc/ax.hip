@@ -51,7 +51,7 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
   using S = OpShape<N1, sizeof(TC)>;
   __shared__ TC smem[lds_words<N1>(S::EPB)];
   if (stop != nullptr && *stop != 0) return;  // uniform: solver finished
-  ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW, MASS, S::NTG>(
+  ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW, MASS, S::NTG, false, S::PRED>(
       threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, box, smem, H);
 }
 

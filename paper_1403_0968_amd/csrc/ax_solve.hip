@@ -38,7 +38,7 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
   using S = OpShape<N1, sizeof(TC)>;
   __shared__ __align__(16) TC smem[lds_words<N1>(S::EPB)];
   // the done flag of the solve is checked inside, after the loads are issued
-  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG, EDOT>(
+  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG, EDOT, S::PRED>(
       threadIdx.x,
       (sizeof(TV) == 4 ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x) *
           S::EPB,

@@ -39,7 +39,10 @@ template <int N1> constexpr int lds_words(int epb) {
 // and the factors are read with non-temporal loads except at n1 = 2, 3, 5,
 // where one factor column is a short piece of a cache line and the
 // non-temporal hint makes the neighbouring pieces miss again.  FP32 / BF16:
-// 64-thread workgroups.
+// 64-thread workgroups.  PRED: the loads carry the thread's element
+// predicate instead of reading a valid stand-in element (FP64 at n1 = 7 and
+// 9, where the unpredicated loads were 5-7 % slower; elsewhere they are
+// faster, by 12 % at n1 = 2 and 16 % at n1 = 3).
 template <int N1, int BYTES> struct OpShape {
   static constexpr int NP = N1 * N1;
   static constexpr int EPB64 = N1 == 2 ? 32 : N1 == 3 ? 7 : N1 == 4 ? 4
@@ -48,6 +51,7 @@ template <int N1, int BYTES> struct OpShape {
   static constexpr int EPB = BYTES == 8 ? EPB64 : ((64 / NP) > 0 ? 64 / NP : 1);
   static constexpr int THREADS = EPB * NP;
   static constexpr bool NTG = BYTES != 8 || !(N1 == 2 || N1 == 3 || N1 == 5);
+  static constexpr bool PRED = BYTES == 8 && (N1 == 7 || N1 == 9);
 };
 
 // Apply the operator to elements e0 .. e0 + EPB - 1 (those < E) with the
@@ -61,7 +65,8 @@ template <int N1, int BYTES> struct OpShape {
 // search direction p, which vanishes on Dirichlet nodes, and the sum of the
 // element energies is (p, A p) of the assembled operator.
 template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
-          bool NTW, bool MASS = false, bool NTG = true, bool EDOT = false>
+          bool NTW, bool MASS = false, bool NTG = true, bool EDOT = false,
+          bool PRED = false>
 __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
                                         const TC *__restrict__ D_,
                                         const TG *__restrict__ G_,
@@ -82,7 +87,9 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   const gp<double> edot = (gp<double>)edot_;
   constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = N1 + 1;
   constexpr int SL = N1 * N1 * PAD;  // one element's slice stack
-  const int el = t / NP;
+  // n1 = 8: one element per wave (t is the thread index in the workgroup),
+  // so the element index and the gather's box arithmetic are wave-uniform
+  const int el = NP == 64 ? __builtin_amdgcn_readfirstlane(t / NP) : t / NP;
   const bool lane_ok = el < EPB;
   const int elc = lane_ok ? el : 0;
   const int c = t - el * NP;
@@ -90,6 +97,13 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   const int64_t e = e0 + el;
   const bool act = lane_ok && e < E;
   const int64_t base = e * N3 + c;
+  // loads read element ed: e itself, or the workgroup's first element
+  // (always < E) for threads without an element, so that no load needs a
+  // predicate; only the stores are guarded.  PRED = true keeps a predicate
+  // on every load instead (lanes without an element read nothing)
+  const int64_t ed = act ? e : e0;
+  const bool ld_on = !PRED || act;
+  const int64_t based = ed * N3 + c;
   TC *s_u = smem + (0 * EPB + elc) * SL;
   TC *s_r = smem + (1 * EPB + elc) * SL;
   TC *s_s = smem + (2 * EPB + elc) * SL;
@@ -101,39 +115,31 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   u32x4 urow = {0u, 0u, 0u, 0u};
   if constexpr (VECU) {
     // lane c reads the 16-byte row (k, j) = (c / 8, c % 8) of the element
-    if (act) urow = *(gp<const u32x4>)(u + e * N3 + 8 * c);
+    urow = *(gp<const u32x4>)(u + ed * N3 + 8 * c);
   } else if constexpr (GATHER) {
     // the column's global (x, y) offset and the element's first z
     // coordinate; a coordinate E_d N of a periodic direction wraps to 0
-    int64_t gxy = 0;
-    uint32_t gz0 = 0;
-    int32_t Gz = 0;
-    int64_t Gxy = 0;
-    if (act) {
-      const ElemXYZ c3 = box_elem(*box, (uint32_t)e);
-      const uint32_t gx = wrap_coord(c3.x * (uint32_t)(N1 - 1) + i, box->Gx);
-      const uint32_t gy = wrap_coord(c3.y * (uint32_t)(N1 - 1) + j, box->Gy);
-      gxy = (int64_t)gx + (int64_t)box->Gx * gy;
-      gz0 = c3.z * (uint32_t)(N1 - 1);
-      Gz = box->Gz;
-      Gxy = box->Gxy;
-    }
+    const ElemXYZ c3 = box_elem(*box, (uint32_t)ed);
+    const uint32_t gx = wrap_coord(c3.x * (uint32_t)(N1 - 1) + i, box->Gx);
+    const uint32_t gy = wrap_coord(c3.y * (uint32_t)(N1 - 1) + j, box->Gy);
+    const int64_t gxy = (int64_t)gx + (int64_t)box->Gx * gy;
+    const uint32_t gz0 = c3.z * (uint32_t)(N1 - 1);
+    const int64_t Gxy = box->Gxy;
     // gz0 + k < G_z below the element's last z node: only that one wraps
     const int64_t g0 = gxy + Gxy * gz0;
 #pragma unroll
-    for (int k = 0; k < N1 - 1; ++k) ucol[k] = act ? u[g0 + Gxy * k] : TU(0);
-    ucol[N1 - 1] = act ? u[gxy + Gxy * wrap_coord(gz0 + N1 - 1, Gz)] : TU(0);
+    for (int k = 0; k < N1 - 1; ++k) ucol[k] = ld_on ? u[g0 + Gxy * k] : TU(0);
+    ucol[N1 - 1] = ld_on ? u[gxy + Gxy * wrap_coord(gz0 + N1 - 1, box->Gz)] : TU(0);
   } else {
 #pragma unroll
-    for (int k = 0; k < N1; ++k) ucol[k] = act ? u[base + k * NP] : TU(0);
+    for (int k = 0; k < N1; ++k) ucol[k] = ld_on ? u[based + k * NP] : TU(0);
   }
   TG g[6][N1];
   if constexpr (VEC16) {
 #pragma unroll
     for (int q = 0; q < 6; ++q) {
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (act)
-        v = __builtin_nontemporal_load((gp<const u32x4>)(G + e * 6 * N3 + q * N3 + 8 * c));
+      const u32x4 v =
+          __builtin_nontemporal_load((gp<const u32x4>)(G + ed * 6 * N3 + q * N3 + 8 * c));
       const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
@@ -142,20 +148,26 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
       }
     }
   } else {
-    const gp<const TG> Ge = G + e * 6 * N3 + c;
+    const gp<const TG> Ge = G + ed * 6 * N3 + c;
 #pragma unroll
     for (int k = 0; k < N1; ++k)
 #pragma unroll
       for (int q = 0; q < 6; ++q)
-        g[q][k] = act ? (NTG ? ld_stream(Ge + q * N3 + k * NP) : Ge[q * N3 + k * NP])
-                      : TG(0);
+        g[q][k] = !ld_on ? TG(0)
+                  : NTG  ? ld_stream(Ge + q * N3 + k * NP)
+                         : Ge[q * N3 + k * NP];
   }
 
   TG hm[MASS ? N1 : 1];
   if constexpr (MASS) {
 #pragma unroll
-    for (int k = 0; k < N1; ++k) hm[k] = act ? ld_stream(H + base + k * NP) : TG(0);
+    for (int k = 0; k < N1; ++k) hm[k] = ld_on ? ld_stream(H + based + k * NP) : TG(0);
   }
+  // every load above is issued before anything below: without the fence
+  // the scheduler may wait for u (to store it into LDS) before it issues the
+  // factor loads, which halves the bytes in flight (165 -> 201 us, FP64,
+  // 32^3, N = 7)
+  __builtin_amdgcn_sched_barrier(0);
   // a solver's done flag (uniform over the workgroup) is read only now, with
   // the element's loads already in flight: waiting for it before them put a
   // memory round trip in front of every workgroup
