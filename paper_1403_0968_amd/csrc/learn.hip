@@ -309,7 +309,7 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// FUSE (with UNIQUE): the flexible-CG iteration's preconditioner step.  out
+// FUSE (with UNIQUE): the flexible-CG iteration's preconditioner step.  zf
 // is the search vector z of the solve, holding dinv o r on entry; the
 // correction is added to it in place (z = dinv o r + c, as the separate
 // correction-then-sum order gives: c is rounded to FP32 first), and every
@@ -377,6 +377,21 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
     for (int i = 0; i < MR; ++i)
       if (t + 64 * i < KK) Ms[t + 64 * i] = mv[i];
     wave_sync();
+    // FUSE: this element's z and w_I are read now, so that their latency
+    // overlaps the contractions below (with one element per wave the
+    // prefetch of the next element's r and M_e does not apply)
+    TV zv[FUSE ? M : 1], wv[FUSE ? M : 1];
+    if constexpr (FUSE) {
+      if (t < P) {
+        const int64_t g = base(e) + offp;
+        const int64_t l = e * N3 + 1 + (int64_t)N1 * (pj + N1 * pk);
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+          zv[i] = zf[g + i];
+          wv[i] = wL[l + i];
+        }
+      }
+    }
     if (e + stride < E) fetch(e + stride);
     // direction j: lane (a, k) -> s2[k][a + Q b]
     if (t < Q * M) {
@@ -453,15 +468,6 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
 #pragma unroll
       for (int a = 0; a < Q; ++a) v[a] = s1[a * P + t];
       const int64_t g = base(e) + offp;
-      TV zv[FUSE ? M : 1], wv[FUSE ? M : 1];
-      if constexpr (FUSE) {
-        const int64_t l = e * N3 + 1 + (int64_t)N1 * (pj + N1 * pk);
-#pragma unroll
-        for (int i = 0; i < M; ++i) {
-          zv[i] = zf[g + i];
-          wv[i] = wL[l + i];
-        }
-      }
 #pragma unroll
       for (int i = 0; i < M; ++i) {
         float acc = 0.f;
