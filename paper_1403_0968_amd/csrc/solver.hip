@@ -35,6 +35,7 @@
 #include <map>
 #include <mutex>
 #include <set>
+#include <type_traits>
 #include <sstream>
 #include <string>
 
@@ -236,8 +237,97 @@ __global__ void __launch_bounds__(AT)
 // node summed from +0.0 in ascending local index, as the assembly and
 // sem_gs sum them), z = dinv r; partials (r, z), (r, r).  FCG (flexible CG
 // with the learned correction, which the next kernel adds to z): partials
-// (r, z), (z, w_G), (r, r).
-template <class TV, class TD, bool FCG, bool PER>
+// (r, z), (z, w_G), (r, r).  xr_asm_chunk updates the chunk [start, start +
+// VCH) of unique nodes; k_bupdate_xr_asm walks the work items of a batch,
+// k_xr_asm_1 the chunks of a single solve.
+template <class TV, class TD, bool FCG, bool PER, bool W64>
+__device__ __forceinline__ void xr_asm_chunk(const Box &bx, gp<const TV> wL, gp<TV> r,
+                                             gp<TV> z, gp<const TD> dinv, TV alpha,
+                                             int64_t start, int64_t nG, int q, int nitems,
+                                             double *__restrict__ part, double *sm) {
+  const int64_t end = min(start + (int64_t)VCH, nG);
+  // w_G at the node with coordinates pc: all (up to 8) copies loaded at
+  // once, predicated on existence, then summed in ascending local index
+  // (z, y, x copy order); an absent copy adds +0.0, which leaves the sum
+  // unchanged bit for bit (the sum starts at +0.0 and so is never -0.0).
+  // The local indices come from the per-direction terms (32-bit unless
+  // W64: some local index of the batch needs more)
+  using IT = typename std::conditional<W64, int64_t, uint32_t>::type;
+  auto assembled = [&](const Coord3 &pc) {
+    const CopyTerms<IT> ct = copy_terms<IT, PER>(bx, pc);
+    TV sw = TV(0);
+    if (!ct.masked) {
+      TV v[8];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const bool ok = a < ct.z.cnt && b < ct.y.cnt && c < ct.x.cnt;
+            const IT lid = (a ? ct.z.t1 : ct.z.t0) + (b ? ct.y.t1 : ct.y.t0) +
+                           (c ? ct.x.t1 : ct.x.t0);
+            v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
+          }
+      sw = sum_copies(PER ? bx.order : 0, v);
+    }
+    return sw;
+  };
+  double rz = 0.0, rr = 0.0, zw = 0.0;
+  constexpr int K = VCH / RT;
+  const int64_t g0 = start + threadIdx.x;
+  if (g0 + (K - 1) * RT < end) {
+    // a whole chunk: every load of the thread's K nodes before any store
+    // (the compiler cannot know that w_L, r, z and dinv do not overlap)
+    TV sw[K], rv[K];
+    TD dv[K];
+    // the thread's nodes are RT apart: their coordinates advance by carries
+    Coord3 pc = box_coord(bx, (uint32_t)g0);
+    const Coord3 step = box_coord(bx, (uint32_t)RT);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      sw[k] = assembled(pc);
+      rv[k] = r[g0 + k * RT];
+      dv[k] = dinv[g0 + k * RT];
+      box_advance(bx, step, pc);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const TV rn = rv[k] - alpha * sw[k];
+      r[g0 + k * RT] = rn;
+      const TV zn = (TV)(dv[k] * rn);
+      z[g0 + k * RT] = zn;
+      rz += (double)rn * (double)zn;
+      rr += (double)rn * (double)rn;
+      if constexpr (FCG) zw += (double)zn * (double)sw[k];
+    }
+  } else {
+    for (int64_t g = g0; g < end; g += RT) {
+      const TV sg = assembled(box_coord(bx, (uint32_t)g));
+      const TV rn = r[g] - alpha * sg;
+      r[g] = rn;
+      const TV zn = (TV)(dinv[g] * rn);
+      z[g] = zn;
+      rz += (double)rn * (double)zn;
+      rr += (double)rn * (double)rn;
+      if constexpr (FCG) zw += (double)zn * (double)sg;
+    }
+  }
+  const double trz = block_sum<RT>(rz, sm);
+  const double trr = block_sum<RT>(rr, sm);
+  const double tzw = FCG ? block_sum<RT>(zw, sm) : 0.0;
+  if (threadIdx.x == 0) {
+    part[q] = trz;
+    if constexpr (FCG) {
+      part[nitems + q] = tzw;
+      part[2 * nitems + q] = trr;
+    } else {
+      part[nitems + q] = trr;
+    }
+  }
+}
+
+template <class TV, class TD, bool FCG, bool PER, bool W64>
 __global__ void __launch_bounds__(RT)
     k_bupdate_xr_asm(const BatchSolve *__restrict__ sds,
                      const CgState *__restrict__ st,
@@ -248,84 +338,34 @@ __global__ void __launch_bounds__(RT)
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    const Box &bx = sd.box;
-    gp<const TV> wL = vec<TV>(sd, VWL);
-    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ);
-    gp<const TD> dinv = dinv_of<TD>(sd, jac);
-    const TV alpha = (TV)st[it.solve].alpha;
-    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    // w_G at node g: all (up to 8) copies loaded at once, predicated on
-    // existence, then summed in ascending local index (z, y, x copy order);
-    // an absent copy adds +0.0, which leaves the sum unchanged bit for bit
-    // (the sum starts at +0.0 and so is never -0.0)
-    auto assembled = [&](int64_t g) {
-      const NodeCopies nc = node_copies<PER>(bx, (uint32_t)g);
-      TV sw = TV(0);
-      if (!nc.masked) {
-        TV v[8];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int c = 0; c < 2; ++c) {
-              const bool ok = a < nc.z.cnt && b < nc.y.cnt && c < nc.x.cnt;
-              const int64_t lid = ok ? copy_lid(bx, nc, a, b, c) : 0;
-              v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
-            }
-        sw = sum_copies(PER ? bx.order : 0, v);
-      }
-      return sw;
-    };
-    double rz = 0.0, rr = 0.0, zw = 0.0;
-    constexpr int K = VCH / RT;
-    const int64_t g0 = it.start + threadIdx.x;
-    if (g0 + (K - 1) * RT < end) {
-      // a whole chunk: every load of the thread's K nodes before any store
-      // (the compiler cannot know that w_L, r, z and dinv do not overlap)
-      TV sw[K], rv[K];
-      TD dv[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        sw[k] = assembled(g0 + k * RT);
-        rv[k] = r[g0 + k * RT];
-        dv[k] = dinv[g0 + k * RT];
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const TV rn = rv[k] - alpha * sw[k];
-        r[g0 + k * RT] = rn;
-        const TV zn = (TV)(dv[k] * rn);
-        z[g0 + k * RT] = zn;
-        rz += (double)rn * (double)zn;
-        rr += (double)rn * (double)rn;
-        if constexpr (FCG) zw += (double)zn * (double)sw[k];
-      }
-    } else {
-      for (int64_t g = g0; g < end; g += RT) {
-        const TV sg = assembled(g);
-        const TV rn = r[g] - alpha * sg;
-        r[g] = rn;
-        const TV zn = (TV)(dinv[g] * rn);
-        z[g] = zn;
-        rz += (double)rn * (double)zn;
-        rr += (double)rn * (double)rn;
-        if constexpr (FCG) zw += (double)zn * (double)sg;
-      }
-    }
-    const double trz = block_sum<RT>(rz, sm);
-    const double trr = block_sum<RT>(rr, sm);
-    const double tzw = FCG ? block_sum<RT>(zw, sm) : 0.0;
-    if (threadIdx.x == 0) {
-      part[q] = trz;
-      if constexpr (FCG) {
-        part[nitems + q] = tzw;
-        part[2 * nitems + q] = trr;
-      } else {
-        part[nitems + q] = trr;
-      }
-    }
+    xr_asm_chunk<TV, TD, FCG, PER, W64>(
+        sd.box, vec<TV>(sd, VWL), vec<TV>(sd, VR), vec<TV>(sd, VZ), dinv_of<TD>(sd, jac),
+        (TV)st[it.solve].alpha, it.start, sd.nG, q, nitems, part, sm);
   }
+}
+
+// The vectors of a single solve, passed to the kernels of the single-solve
+// iteration by value: a workgroup then reads only the solve's state before
+// its data loads, where the batched kernels first fetch a work item and the
+// solve's descriptor (a chain of dependent loads in front of every chunk)
+template <class TV, class TD> struct Vecs1 {
+  Box box;
+  int64_t nG;
+  const TV *wL;
+  TV *r, *z, *p, *x;
+  const TD *dinv;
+};
+
+template <class TV, class TD, bool FCG, bool PER, bool W64>
+__global__ void __launch_bounds__(RT)
+    k_xr_asm_1(Vecs1<TV, TD> a, const CgState *__restrict__ st, int nitems,
+               double *__restrict__ part) {
+  __shared__ double sm[RT / 64];
+  if (st->done != 0) return;
+  const int q = blockIdx.x;
+  xr_asm_chunk<TV, TD, FCG, PER, W64>(a.box, (gp<const TV>)a.wL, (gp<TV>)a.r,
+                                      (gp<TV>)a.z, (gp<const TD>)a.dinv, (TV)st->alpha,
+                                      (int64_t)q * VCH, a.nG, q, nitems, part, sm);
 }
 
 // r -= alpha w, z = dinv r (w the stored assembled vector); partials (r, z),
@@ -396,6 +436,39 @@ __global__ void __launch_bounds__(RT)
 // x += alpha p with this step's alpha (when k_bbeta found it finite, also
 // on the step that converged), then p = z + beta p while the solve runs
 template <class TV>
+__device__ __forceinline__ void p_chunk(gp<const TV> z, gp<TV> p, gp<TV> x, TV alpha,
+                                        TV beta, bool run, int64_t start, int64_t nG) {
+  const int64_t end = min(start + (int64_t)VCH, nG);
+  constexpr int K = VCH / RT;
+  const int64_t g0 = start + threadIdx.x;
+  if (run && g0 + (K - 1) * RT < end) {
+    // a whole chunk: every load of the thread's K nodes before any store
+    // (the compiler cannot know that x, p and z do not overlap): 78 -> 67
+    // us at 11.4M unique nodes in FP64
+    TV pv[K], xv[K], zv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      pv[k] = p[g0 + k * RT];
+      xv[k] = x[g0 + k * RT];
+      zv[k] = z[g0 + k * RT];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      x[g0 + k * RT] = xv[k] + alpha * pv[k];
+      p[g0 + k * RT] = zv[k] + beta * pv[k];
+    }
+  } else if (run) {
+    for (int64_t g = g0; g < end; g += RT) {
+      const TV pv = p[g];
+      x[g] = x[g] + alpha * pv;
+      p[g] = z[g] + beta * pv;
+    }
+  } else {
+    for (int64_t g = g0; g < end; g += RT) x[g] = x[g] + alpha * p[g];
+  }
+}
+
+template <class TV>
 __global__ void __launch_bounds__(RT)
     k_bupdate_p(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
                 const VecItem *__restrict__ items, int nitems) {
@@ -404,40 +477,19 @@ __global__ void __launch_bounds__(RT)
     const CgState &c = st[it.solve];
     if (c.xupd == 0) continue;  // uniform per item
     const BatchSolve &sd = sds[it.solve];
-    gp<const TV> z = vec<TV>(sd, VZ);
-    gp<TV> p = vec<TV>(sd, VP), x = vec<TV>(sd, VX);
-    const TV alpha = (TV)c.alpha;
-    const TV beta = (TV)c.beta;
-    const bool run = c.done == 0;
-    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    constexpr int K = VCH / RT;
-    const int64_t g0 = it.start + threadIdx.x;
-    if (run && g0 + (K - 1) * RT < end) {
-      // a whole chunk: every load of the thread's K nodes before any store
-      // (the compiler cannot know that x, p and z do not overlap): 78 -> 67
-      // us at 11.4M unique nodes in FP64
-      TV pv[K], xv[K], zv[K];
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        pv[k] = p[g0 + k * RT];
-        xv[k] = x[g0 + k * RT];
-        zv[k] = z[g0 + k * RT];
-      }
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        x[g0 + k * RT] = xv[k] + alpha * pv[k];
-        p[g0 + k * RT] = zv[k] + beta * pv[k];
-      }
-    } else if (run) {
-      for (int64_t g = g0; g < end; g += RT) {
-        const TV pv = p[g];
-        x[g] = x[g] + alpha * pv;
-        p[g] = z[g] + beta * pv;
-      }
-    } else {
-      for (int64_t g = g0; g < end; g += RT) x[g] = x[g] + alpha * p[g];
-    }
+    p_chunk<TV>(vec<TV>(sd, VZ), vec<TV>(sd, VP), vec<TV>(sd, VX), (TV)c.alpha,
+                (TV)c.beta, c.done == 0, it.start, sd.nG);
   }
+}
+
+// the same for the chunks of a single solve
+template <class TV, class TD>
+__global__ void __launch_bounds__(RT)
+    k_p_1(Vecs1<TV, TD> a, const CgState *__restrict__ st) {
+  const CgState &c = *st;
+  if (c.xupd == 0) return;
+  p_chunk<TV>((gp<const TV>)a.z, (gp<TV>)a.p, (gp<TV>)a.x, (TV)c.alpha, (TV)c.beta,
+              c.done == 0, (int64_t)blockIdx.x * VCH, a.nG);
 }
 
 // r = b - w (x0_zero: r = b and x = 0), z = dinv r, p = z; partials of
@@ -830,6 +882,7 @@ struct sem_batch {
   std::vector<int> orders;      // n1 per solve
   std::vector<sem::BatchSolve> hsd;  // host copies of the solve descriptors
   bool periodic = false;        // a solve of the batch has a periodic direction
+  bool wide = false;            // a solve's local indices need 64 bits
   sem::DevBuf sds, st, vitems, vbeg, part, red, active, maxit, scale;
   sem::DevBuf axitems[3];       // per block size 64 / 128 / 256
   int n_ax[3] = {0, 0, 0};
@@ -955,6 +1008,7 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
       sds[q] = describe(h, q, v64, v32, W->one64.as<double>(),
                         W->one32.as<float>(), W->edot.as<double>());
       if (h->periodic != 0) b->periodic = true;
+      if (h->nL > (int64_t)UINT32_MAX) b->wide = true;
       vbeg[q] = (int32_t)vis.size();
       for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({q, 0, g});
       b->orders.push_back(h->n1);
@@ -1035,6 +1089,19 @@ static int vec_grid(const sem_batch *b) { return b->n_vi; }
     }                                                      \
   } while (0)
 
+// the same, with W64_ = true when some local index of the batch needs more
+// than 32 bits
+#define SEM_ASM_LAUNCH(B, KERNEL, ...)                     \
+  do {                                                     \
+    if ((B)->wide) {                                       \
+      constexpr bool W64_ = true;                          \
+      SEM_PER_LAUNCH(B, KERNEL, __VA_ARGS__);              \
+    } else {                                               \
+      constexpr bool W64_ = false;                         \
+      SEM_PER_LAUNCH(B, KERNEL, __VA_ARGS__);              \
+    }                                                      \
+  } while (0)
+
 // the operator of every solve of the batch, w_L = A_L Q v_src into VWL;
 // edot: the single-solve kernel also stores the element energies (the
 // batched kernel always does)
@@ -1080,6 +1147,24 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
              b->axitems[k].as<AxItem>(), n, grid, src, dst, skip_done, b->s);
 }
 
+// the single-solve kernels' view of the batch's one solve
+template <class TV, class TD>
+static Vecs1<TV, TD> vecs1(const sem_batch *b, int jac) {
+  const BatchSolve &d = b->hsd[0];
+  auto v = [&](int i) { return (TV *)(sizeof(TV) == 8 ? d.v64[i] : d.v32[i]); };
+  Vecs1<TV, TD> a;
+  a.box = d.box;
+  a.nG = d.nG;
+  a.wL = v(VWL);
+  a.r = v(VR);
+  a.z = v(VZ);
+  a.p = v(VP);
+  a.x = v(VX);
+  a.dinv = (const TD *)(sizeof(TD) == 8 ? (jac ? (const void *)d.dinv64 : d.one64)
+                                        : (jac ? (const void *)d.dinv32 : d.one32));
+  return a;
+}
+
 template <class TV, class TD>
 static void iteration_t(sem_batch *b, int prec, int jac) {
   const BatchSolve *sds = b->sds.as<BatchSolve>();
@@ -1100,12 +1185,19 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   } else {
     bax(b, prec, VP, VWL, 1, true);
     hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
-    SEM_PER_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, false, PER_>), dim3(g), dim3(RT), 0, b->s,
-                       sds, st, vi, nv, part, jac);
+    if (b->n == 1)
+      SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, false, PER_, W64_>), dim3(nv), dim3(RT), 0,
+                     b->s, vecs1<TV, TD>(b, jac), st, nv, part);
+    else
+      SEM_ASM_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, false, PER_, W64_>), dim3(g), dim3(RT),
+                     0, b->s, sds, st, vi, nv, part, jac);
   }
   hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
-  hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
-                     nv);
+  if (b->n == 1)
+    hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s,
+                       vecs1<TV, TD>(b, jac), st);
+  else
+    hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi, nv);
   SEM_HIP(hipGetLastError());
 }
 
@@ -1137,15 +1229,16 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
     // the element terms of (r, c) and (c, w)
     bax(b, prec, VP, VWL, 1, true);
     hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
-    SEM_PER_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, true, PER_>), dim3(g), dim3(RT), 0,
-                       b->s, sds, st, vi, nv, part, 1);
+    // (the learned correction runs on single solves: nv chunks of one solve)
+    SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, true, PER_, W64_>), dim3(nv), dim3(RT), 0, b->s,
+                   vecs1<TV, TD>(b, 1), st, nv, part);
     const BatchSolve &d = b->hsd[0];
     learn_apply_fused(h, f32 ? d.v32[VR] : d.v64[VR], f32 ? d.v32[VZ] : d.v64[VZ],
                       f32 ? d.v32[VWL] : d.v64[VWL], f32, b->s);
     hipLaunchKernelGGL(k_bbeta_fcg_e, dim3(1), dim3(RT), 0, b->s, st, part, nv,
                        learn_epart(h), (int)h->E);
-    hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
-                       nv);
+    hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s,
+                       vecs1<TV, TD>(b, 1), st);
     SEM_HIP(hipGetLastError());
     return;
   }
@@ -1671,6 +1764,7 @@ sem_status pcg_solve_noalloc(sem_handle *h, const sem_solve_opts *o,
   double *edot = (double *)take((size_t)h->E * 8);
   b.hsd.assign(1, describe(h, 0, v64, v32, one64, nullptr, edot));
   b.periodic = h->periodic != 0;
+  b.wide = h->nL > (int64_t)UINT32_MAX;
   std::vector<VecItem> vis;
   for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({0, 0, g});
   b.n_vi = (int)vis.size();

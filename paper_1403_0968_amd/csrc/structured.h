@@ -46,8 +46,10 @@ __host__ __device__ inline uint32_t fdiv(uint32_t n, const FastDiv &f) {
 
 struct Box {
   int32_t N, n1, Ex, Ey, Ez, Gx, Gy, Gz, dirichlet, periodic;  // periodic: bit 1 x, 2 y, 4 z
-  // order of the copy directions in ascending local index (copy_order)
-  int32_t order, pad;
+  // order of the copy directions in ascending local index (copy_order);
+  // mN = floor(2^32 / N) + 1 (0 for N = 1): the 32-bit quotient by N
+  int32_t order;
+  uint32_t mN;
   int64_t Gxy;
   FastDiv dEx, dEy, dGx, dGxy, dN;
 };
@@ -84,7 +86,7 @@ inline Box make_box(int N, int Ex, int Ey, int Ez, int dirichlet, int periodic) 
   b.dirichlet = dirichlet;
   b.periodic = periodic;
   b.order = copy_order(Ex, Ey, Ez, periodic);
-  b.pad = 0;
+  b.mN = N <= 1 ? 0u : (uint32_t)((1ull << 32) / (uint64_t)N + 1);
   b.Gxy = (int64_t)b.Gx * b.Gy;
   b.dEx = make_fastdiv((uint32_t)Ex);
   b.dEy = make_fastdiv((uint32_t)Ey);
@@ -181,6 +183,95 @@ __host__ __device__ inline int64_t copy_lid(const Box &b, const NodeCopies &nc,
   const uint32_t ex = c ? nc.x.c1 : nc.x.c0, ix = c ? nc.x.i1 : nc.x.i0;
   const int64_t e = (int64_t)ex + (int64_t)b.Ex * ((int64_t)ey + (int64_t)b.Ey * ez);
   return e * b.n1 * b.n1 * b.n1 + ix + b.n1 * ((int64_t)iy + (int64_t)b.n1 * iz);
+}
+
+// ---------------------------------------------------------------------------
+// The same enumeration in a form for the solver kernels, which visit many
+// nodes per thread.  The local index l = e n1^3 + i + n1 j + n1^2 k with
+// e = e_x + E_x (e_y + E_y e_z) is a sum of one term per direction,
+// (e_x n1^3 + i) + (e_y E_x n1^3 + n1 j) + (e_z E_x E_y n1^3 + n1^2 k), so
+// copy (a, b, c) of a node has l = Z[a] + Y[b] + X[c] from the (at most two)
+// copy terms of each direction.  IT is the index type: 32-bit when every
+// local index fits, else 64-bit.
+
+// floor(x / N) by one 32-bit high multiply: with m = floor(2^32 / N) + 1 =
+// (2^32 + d) / N, 0 < d <= N, the error x d / (N 2^32) stays below 1 / N for
+// x < 2^32 / N, which the coordinates (at most E_d N + 1) satisfy
+__host__ __device__ inline uint32_t div_order(const Box &b, uint32_t x) {
+  if (b.mN == 0) return x;
+#ifdef __HIP_DEVICE_COMPILE__
+  return __umulhi(x, b.mN);
+#else
+  return (uint32_t)(((uint64_t)x * b.mN) >> 32);
+#endif
+}
+
+template <class IT> struct AxisTerms {
+  IT t0, t1;  // local-index terms of the first and (cnt == 2) second copy
+  int cnt;
+};
+
+// the cases of axis_copies, as index terms: se = the element stride of the
+// direction in l, sn = its node stride
+template <class IT>
+__host__ __device__ inline AxisTerms<IT> axis_terms(const Box &b, uint32_t x, uint32_t E,
+                                                    bool periodic, IT se, IT sn) {
+  const uint32_t N = (uint32_t)b.N, q = div_order(b, x), i = x - q * N;
+  uint32_t c0 = q, i0 = i, c1 = 0, i1 = 0;
+  int cnt = 1;
+  if (periodic && x == 0) {
+    c0 = 0, i0 = 0, c1 = E - 1, i1 = N, cnt = 2;
+  } else if (q == E) {
+    c0 = E - 1, i0 = N;
+  } else if (i == 0 && q > 0) {
+    c0 = q - 1, i0 = N, c1 = q, cnt = 2;
+  }
+  return {(IT)c0 * se + (IT)i0 * sn, (IT)c1 * se + (IT)i1 * sn, cnt};
+}
+
+struct Coord3 {
+  uint32_t x, y, z;
+};
+
+// global coordinates of node g
+__host__ __device__ inline Coord3 box_coord(const Box &b, uint32_t g) {
+  const uint32_t gz = fdiv(g, b.dGxy);
+  const uint32_t rem = g - gz * (uint32_t)b.Gxy;
+  const uint32_t gy = fdiv(rem, b.dGx);
+  return {rem - gy * (uint32_t)b.Gx, gy, gz};
+}
+
+// advance coordinates by a fixed node step s, given as box_coord(s) (s =
+// z Gxy + y Gx + x with x < G_x, y < G_y): one carry per direction
+__host__ __device__ inline void box_advance(const Box &b, const Coord3 &s, Coord3 &p) {
+  p.x += s.x;
+  const uint32_t cx = p.x >= (uint32_t)b.Gx ? 1u : 0u;
+  p.x -= cx * (uint32_t)b.Gx;
+  p.y += s.y + cx;
+  const uint32_t cy = p.y >= (uint32_t)b.Gy ? 1u : 0u;
+  p.y -= cy * (uint32_t)b.Gy;
+  p.z += s.z + cy;
+}
+
+template <class IT> struct CopyTerms {
+  AxisTerms<IT> x, y, z;
+  bool masked;  // on the Dirichlet boundary
+};
+
+template <class IT, bool PER>
+__host__ __device__ inline CopyTerms<IT> copy_terms(const Box &b, const Coord3 &p) {
+  const bool px = PER && (b.periodic & 1), py = PER && (b.periodic & 2),
+             pz = PER && (b.periodic & 4);
+  const IT n1 = (IT)b.n1, n3 = n1 * n1 * n1;
+  CopyTerms<IT> c;
+  c.x = axis_terms<IT>(b, p.x, (uint32_t)b.Ex, px, n3, (IT)1);
+  c.y = axis_terms<IT>(b, p.y, (uint32_t)b.Ey, py, n3 * (IT)b.Ex, n1);
+  c.z = axis_terms<IT>(b, p.z, (uint32_t)b.Ez, pz, n3 * (IT)b.Ex * (IT)b.Ey, n1 * n1);
+  c.masked = b.dirichlet &&
+             ((!px && (p.x == 0 || p.x == (uint32_t)b.Gx - 1)) ||
+              (!py && (p.y == 0 || p.y == (uint32_t)b.Gy - 1)) ||
+              (!pz && (p.z == 0 || p.z == (uint32_t)b.Gz - 1)));
+  return c;
 }
 
 }  // namespace sem
