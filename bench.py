@@ -467,9 +467,9 @@ def bench_config1(sem, torch):
 
 def bench_gs(sem, torch, h, nL, n=200):
     """sem_gs (FP64) on the benchmark mesh: per-launch statistics and the
-    algorithmic bytes of the sorted-map gather-scatter (per global node:
-    offset 4 and mask flag 1; shared copies: id 4, read 8, write 8;
-    single-copy nodes: id 4, read 8; Dirichlet copies: id 4, write 8)."""
+    algorithmic bytes of the gather-scatter with the copies enumerated in
+    closed form (shared copies: read 8, write 8; single-copy nodes: read 8;
+    Dirichlet copies: write 8)."""
     mult = torch.empty(nL, dtype=torch.int32, device="cuda")
     mask = torch.empty(nL, dtype=torch.uint8, device="cuda")
     sem.sem_export(h, sem.SEM_ARR_MULT, mult)
@@ -480,7 +480,7 @@ def bench_gs(sem, torch, h, nL, n=200):
     solo = int((free & (mult == 1)).sum())
     segs = int(((free & (mult > 1)).double() / mult.double()).sum().round())
     _, _, nG = sem.sem_query(h)
-    byts = 5 * nG + 20 * shared + 12 * solo + 12 * masked
+    byts = 16 * shared + 8 * solo + 8 * masked
     v = torch.rand(nL, dtype=torch.float64, device="cuda")
     for _ in range(20):
         sem.sem_gs(h, sem.SEM_FP64, v)

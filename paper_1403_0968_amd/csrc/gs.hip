@@ -2,19 +2,21 @@
 // E-vectors and unique-node vectors (paper section 4.2.1: distinct
 // global-local node numbering, after Fischer 1991).
 //
-// Atomic-free and deterministic: the sorted map (perm, offsets) lists the
-// local copies of every global node in ascending local index.  One thread
-// per global node loads its offsets, its mask flag, the ids of all its
-// copies (at most 8 on a hexahedral mesh) and then all their values at once,
-// sums them from +0.0 in the listed order and writes the sum back to every
-// copy; a Dirichlet node's copies are set to zero without being read.  A
-// node with one copy receives +0.0 + v, the same one-term sum: the value
-// itself except that -0.0 becomes +0.0, so only that case is written.
-// (Three kernels over separate lists of shared, single-copy and Dirichlet
-// nodes, each thread walking its segment one load after the other, took
-// 125 us at 32^3, N = 7.)
+// Atomic-free and deterministic.  A thread per global node enumerates the
+// node's local copies (at most 8 on a hexahedral mesh) in closed form from
+// the node's box coordinates, loads all their values at once, sums them
+// from +0.0 in ascending local index (the order of the sorted map perm /
+// offsets that the exports hold) and writes the sum back to every copy; a
+// Dirichlet node's copies are set to zero without being read.  A node with
+// one copy receives +0.0 + v, the same one-term sum: the value itself
+// except that -0.0 becomes +0.0, so only that case is written.  (Reading
+// the copies' ids from the sorted map took 90 us at 32^3, N = 7; three
+// kernels over separate lists of shared, single-copy and Dirichlet nodes,
+// each thread walking its segment one load after the other, 125 us.)
 #include "common.h"
 #include "sem_internal.h"
+
+#include <type_traits>
 
 namespace sem {
 
@@ -25,36 +27,58 @@ template <class T> __device__ inline bool same_bits(T a, T b) {
     return __float_as_int(a) == __float_as_int(b);
 }
 
-template <class T>
-__global__ void __launch_bounds__(256)
-    k_gs(int64_t nG, const int32_t *__restrict__ off, const int32_t *__restrict__ perm,
-         const uint8_t *__restrict__ gmask, T *__restrict__ v) {
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (g >= nG) return;
-  const int32_t a = off[g], cnt = off[g + 1] - a;
-  const bool masked = gmask[g] != 0;
-  int32_t id[8];
+// The copies' local indices come from the per-direction terms of
+// structured.h, so the kernel moves only the E-vector.  GS_K nodes per
+// thread, GS_T apart (coordinates advanced by carries), all their copies
+// loaded before any sum is formed.
+constexpr int GS_T = 256, GS_K = 2;  // 1: 68 us, 2: 61 us, 4: 75 us (FP64, 32^3, N = 7)
+
+template <class T, bool PER, bool W64>
+__global__ void __launch_bounds__(GS_T) k_gs_box(Box bx, int64_t nG, T *__restrict__ v_) {
+  const gp<T> v = (gp<T>)v_;
+  using IT = typename std::conditional<W64, int64_t, uint32_t>::type;
+  const int64_t g0 = (int64_t)blockIdx.x * (GS_T * GS_K) + threadIdx.x;
+  Coord3 pc = box_coord(bx, (uint32_t)g0);
+  const Coord3 step = box_coord(bx, (uint32_t)GS_T);
+  IT lid[GS_K][8];
+  T x[GS_K][8];
+  bool live[GS_K][8], masked[GS_K];
+  int cnt[GS_K];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) id[q] = q < cnt ? perm[a + q] : 0;
-  if (masked) {
+  for (int k = 0; k < GS_K; ++k) {
+    const bool act = g0 + k * GS_T < nG;
+    const CopyTerms<IT> ct = copy_terms<IT, PER>(bx, pc);
+    masked[k] = ct.masked;
+    cnt[k] = ct.x.cnt * ct.y.cnt * ct.z.cnt;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q < cnt) v[id[q]] = T(0);
-    return;
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int q = 4 * a + 2 * b + c;
+          live[k][q] = act && a < ct.z.cnt && b < ct.y.cnt && c < ct.x.cnt;
+          lid[k][q] = (a ? ct.z.t1 : ct.z.t0) + (b ? ct.y.t1 : ct.y.t0) +
+                      (c ? ct.x.t1 : ct.x.t0);
+          // a Dirichlet node's copies are not read
+          x[k][q] = live[k][q] && !ct.masked ? v[lid[k][q]] : T(0);
+        }
+    box_advance(bx, step, pc);
   }
-  T x[8];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) x[q] = q < cnt ? v[id[q]] : T(0);
-  // absent copies add +0.0, which leaves a sum that starts at +0.0 unchanged
-  T acc = T(0);
+  for (int k = 0; k < GS_K; ++k) {
+    const T acc = sum_copies(PER ? bx.order : 0, x[k]);
+    if (masked[k]) {
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc = acc + x[q];
-  if (cnt == 1) {
-    if (!same_bits(acc, x[0])) v[id[0]] = acc;
-  } else {
+      for (int q = 0; q < 8; ++q)
+        if (live[k][q]) v[lid[k][q]] = T(0);
+    } else if (cnt[k] == 1) {
+      if (live[k][0] && !same_bits(acc, x[k][0])) v[lid[k][0]] = acc;
+    } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q < cnt) v[id[q]] = acc;
+      for (int q = 0; q < 8; ++q)
+        if (live[k][q]) v[lid[k][q]] = acc;
+    }
   }
 }
 
@@ -62,16 +86,30 @@ static inline unsigned nblk(int64_t n, int t) {
   return (unsigned)((n + t - 1) / t);
 }
 
+template <class T, bool PER>
+static void launch_gs_box(const sem_handle *h, T *v, hipStream_t s) {
+  const Box bx = make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet, h->periodic);
+  const unsigned grid = nblk(h->nG, GS_T * GS_K);
+  if (h->nL > (int64_t)UINT32_MAX)
+    hipLaunchKernelGGL((k_gs_box<T, PER, true>), dim3(grid), dim3(GS_T), 0, s, bx, h->nG, v);
+  else
+    hipLaunchKernelGGL((k_gs_box<T, PER, false>), dim3(grid), dim3(GS_T), 0, s, bx, h->nG,
+                       v);
+}
+
+template <class T> static void launch_gs_box_t(const sem_handle *h, T *v, hipStream_t s) {
+  if (h->periodic != 0)
+    launch_gs_box<T, true>(h, v, s);
+  else
+    launch_gs_box<T, false>(h, v, s);
+}
+
 void launch_gs(sem_handle *h, int prec, void *v, hipStream_t s) {
   if (h->nG == 0) return;
   if (prec == SEM_FP64)
-    hipLaunchKernelGGL(k_gs<double>, dim3(nblk(h->nG, 256)), dim3(256), 0, s, h->nG,
-                       h->offsets.as<int32_t>(), h->perm.as<int32_t>(),
-                       h->gmask.as<uint8_t>(), (double *)v);
+    launch_gs_box_t<double>(h, (double *)v, s);
   else if (prec == SEM_FP32)
-    hipLaunchKernelGGL(k_gs<float>, dim3(nblk(h->nG, 256)), dim3(256), 0, s, h->nG,
-                       h->offsets.as<int32_t>(), h->perm.as<int32_t>(),
-                       h->gmask.as<uint8_t>(), (float *)v);
+    launch_gs_box_t<float>(h, (float *)v, s);
   else
     fail(SEM_ERR_ARG, "sem_gs: precision must be SEM_FP64 or SEM_FP32");
   SEM_HIP(hipGetLastError());

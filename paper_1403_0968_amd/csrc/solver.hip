@@ -78,41 +78,6 @@ __device__ inline void strided_sums(const double *__restrict__ part, int stride,
   }
 }
 
-// sum of the (up to 8) copies of a node, v[4 a + 2 b + c] holding copy a
-// along z, b along y, c along x (+0.0 for an absent copy, which leaves the
-// sum unchanged bit for bit: it starts at +0.0 and so is never -0.0), in
-// ascending local index: the box's direction order (copy_order)
-template <class TV> __device__ inline TV sum_copies(int order, const TV (&v)[8]) {
-  TV s = TV(0);
-#define SEM_SUM3(A, B, C)                                  \
-  _Pragma("unroll") for (int A = 0; A < 2; ++A)            \
-    _Pragma("unroll") for (int B = 0; B < 2; ++B)          \
-      _Pragma("unroll") for (int C = 0; C < 2; ++C) s = s + v[4 * a + 2 * b + c];
-  switch (order) {
-    case 0: {
-      SEM_SUM3(a, b, c)
-      break;
-    }
-    case 1: {
-      SEM_SUM3(b, c, a)
-      break;
-    }
-    case 2: {
-      SEM_SUM3(a, c, b)
-      break;
-    }
-    case 3: {
-      SEM_SUM3(c, a, b)
-      break;
-    }
-    default: {
-      SEM_SUM3(b, a, c)
-      break;
-    }
-  }
-#undef SEM_SUM3
-  return s;
-}
 
 // --------------------------------------------------------------------------
 // vector kernels (persistent over VecItem lists)
