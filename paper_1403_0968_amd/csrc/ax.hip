@@ -49,7 +49,7 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
          const Box *__restrict__ box, const int32_t *__restrict__ stop,
          const TG *__restrict__ H) {
   using S = OpShape<N1, sizeof(TC)>;
-  __shared__ TC smem[lds_words<N1>(S::EPB)];
+  __shared__ __align__(16) TC smem[lds_words<N1, TC>(S::EPB)];
   if (stop != nullptr && *stop != 0) return;  // uniform: solver finished
   ax_tile<N1, S::EPB, TU, TG, TW, TC, GATHER, NTW, MASS, S::NTG, false, S::PRED>(
       threadIdx.x, (int64_t)blockIdx.x * S::EPB, E, D, G, u, w, box, smem, H);
@@ -144,10 +144,10 @@ __global__ void __launch_bounds__(BS)
   }
 }
 
-template <int BS, int... N1s> constexpr int max_lds_words() {
+template <int BS, class TC, int... N1s> constexpr int max_lds_words() {
   int m = 0;
-  ((m = lds_words<N1s>(BTile<BS, N1s>::EPB) > m
-            ? lds_words<N1s>(BTile<BS, N1s>::EPB)
+  ((m = lds_words<N1s, TC>(BTile<BS, N1s>::EPB) > m
+            ? lds_words<N1s, TC>(BTile<BS, N1s>::EPB)
             : m),
    ...);
   return m;
@@ -157,7 +157,7 @@ template <int BS, class TV, class TG, class TC, int... N1s>
 static void launch_bax_set(const BatchSolve *sds, const CgState *st,
                            const AxItem *items, int nitems, int grid, int src,
                            int dst, int skip_done, hipStream_t s) {
-  const size_t lds = (size_t)max_lds_words<BS, N1s...>() * sizeof(TC);
+  const size_t lds = (size_t)max_lds_words<BS, TC, N1s...>() * sizeof(TC);
   hipLaunchKernelGGL((k_bax<BS, TV, TG, TC, N1s...>), dim3(grid), dim3(BS), lds,
                      s, sds, st, items, nitems, src, dst, skip_done);
 }

@@ -36,7 +36,7 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
                const int32_t *__restrict__ stop, const TG *__restrict__ H,
                double *__restrict__ edot) {
   using S = OpShape<N1, sizeof(TC)>;
-  __shared__ __align__(16) TC smem[lds_words<N1>(S::EPB)];
+  __shared__ __align__(16) TC smem[lds_words<N1, TC>(S::EPB)];
   // the done flag of the solve is checked inside, after the loads are issued
   ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG, EDOT, S::PRED>(
       threadIdx.x,

@@ -29,8 +29,16 @@ template <class P> __device__ inline auto ld_stream(P p) {
   return __builtin_nontemporal_load(p);
 }
 
-template <int N1> constexpr int lds_words(int epb) {
-  return 3 * epb * N1 * N1 * (N1 + 1);
+// LDS row pitch of the slice stacks: n1 + 1 (the 8 distinct rows a wave
+// reads at once sit in different banks), or 12 for FP32 arithmetic at n1 =
+// 8, where the r-direction rows are read as two 16-byte vectors: 16-byte
+// aligned rows whose 8 starts 48 bytes apart cover all 32 banks once
+template <int N1, class TC> constexpr int ax_pad() {
+  return (N1 == 8 && sizeof(TC) == 4) ? 12 : N1 + 1;
+}
+
+template <int N1, class TC = double> constexpr int lds_words(int epb) {
+  return 3 * epb * N1 * N1 * ax_pad<N1, TC>();
 }
 
 // Workgroup shape of the operator kernels per order and value size (timed on
@@ -85,7 +93,11 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   const gp<TW> w = (gp<TW>)w_;
   const gp<const TG> H = (gp<const TG>)H_;
   const gp<double> edot = (gp<double>)edot_;
-  constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = N1 + 1;
+  constexpr int NP = N1 * N1, N3 = N1 * NP, PAD = ax_pad<N1, TC>();
+  // FP32 arithmetic at n1 = 8: the rows (k, j, 0..7) of s_u and s_r are
+  // read as two 16-byte vectors
+  constexpr bool VROW = PAD == 12;
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
   constexpr int SL = N1 * N1 * PAD;  // one element's slice stack
   // n1 = 8: one element per wave (t is the thread index in the workgroup),
   // so the element index and the gather's box arithmetic are wave-uniform
@@ -215,9 +227,16 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     TC ur = TC(0), us = TC(0), ut = TC(0);
+    TC rowu[VROW ? N1 : 1];
+    if constexpr (VROW) {
+      const f32x4 a0 = *reinterpret_cast<const f32x4 *>(&s_u[AX_IDX(k, j, 0)]);
+      const f32x4 a1 = *reinterpret_cast<const f32x4 *>(&s_u[AX_IDX(k, j, 4)]);
+      rowu[0] = a0.x, rowu[1] = a0.y, rowu[2] = a0.z, rowu[3] = a0.w;
+      rowu[4] = a1.x, rowu[5] = a1.y, rowu[6] = a1.z, rowu[7] = a1.w;
+    }
 #pragma unroll
     for (int m = 0; m < N1; ++m) {
-      ur += Di[m] * s_u[AX_IDX(k, j, m)];
+      ur += Di[m] * (VROW ? rowu[VROW ? m : 0] : s_u[AX_IDX(k, j, m)]);
       us += Dj[m] * s_u[AX_IDX(k, m, i)];
       ut += D[k * N1 + m] * uc[m];
     }
@@ -243,9 +262,16 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     TC acc = mv[k];
+    TC rowr[VROW ? N1 : 1];
+    if constexpr (VROW) {
+      const f32x4 a0 = *reinterpret_cast<const f32x4 *>(&s_r[AX_IDX(k, j, 0)]);
+      const f32x4 a1 = *reinterpret_cast<const f32x4 *>(&s_r[AX_IDX(k, j, 4)]);
+      rowr[0] = a0.x, rowr[1] = a0.y, rowr[2] = a0.z, rowr[3] = a0.w;
+      rowr[4] = a1.x, rowr[5] = a1.y, rowr[6] = a1.z, rowr[7] = a1.w;
+    }
 #pragma unroll
     for (int m = 0; m < N1; ++m) {
-      acc += DTi[m] * s_r[AX_IDX(k, j, m)];
+      acc += DTi[m] * (VROW ? rowr[VROW ? m : 0] : s_r[AX_IDX(k, j, m)]);
       acc += DTj[m] * s_s[AX_IDX(k, m, i)];
       acc += D[m * N1 + k] * wt[m];
     }
