@@ -546,12 +546,76 @@ void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
 // operator's spread of eigenvalues, and the refinement's contraction grew
 // with the mesh (0.36 per step at 32^3 elements, N = 7).
 // ---------------------------------------------------------------------------
+// the sum of 64 lane values by a fixed butterfly (every lane gets it)
+__device__ inline double wave_sum64(double v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// want_edot: also store every element's energy p_e^T w_e in FP64 (the terms
+// of (p, A p) for the solvers), each lane's column of the FP32 input p times
+// the stored w in ascending k, then the lanes by a fixed butterfly
+// One element of the solvers' operator (gathered FP32 input p, split into
+// two BF16 terms; FP32 output; with edot non-null the element energy).
+// Every wave of the workgroup calls it (act = false: no loads or stores),
+// since the element routine synchronises the workgroup.
+template <int N1, bool SPLIT>
+__device__ inline void solve_elem_mfma(int l, MfmaLdsSplit &L, int64_t e, bool act,
+                                       const Box &box, gp<const float> u, gp<float> w,
+                                       const uint16_t *G, gp<const uint16_t> H,
+                                       m16x4 fh, m16x4 fl, m16x4 bh, m16x4 bl,
+                                       gp<double> edot) {
+  constexpr int NP = N1 * N1, N3 = NP * N1;
+  uint16_t gq[6][8];
+  load_factors<N1>(l, act, e, G, gq);
+  ElemXYZ c3 = {0u, 0u, 0u};
+  if (act) c3 = box_elem(box, (uint32_t)e);
+  float pv[8];  // the lane's column (i, j) = (l % 8, l / 8) of p, k = t
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int p = l + 64 * t, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
+    const bool in = act && i < N1 && j < N1 && k < N1;
+    const float v = in ? u[box_node(box, c3, i, j, k)] : 0.f;
+    pv[t] = v;
+    const uint16_t hi = f32_to_bf16(v);
+    L.u[p] = hi;
+    L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
+  }
+  __syncthreads();
+  mfma_element<N1, SPLIT, true, MfmaLdsSplit>(l, L, gq, fh, fl, bh, bl);
+  // w at node (i, j, k) of the element, as stored (mass term added)
+  auto wval = [&](int i, int j, int k) {
+    const int q = k * 64 + j * 8 + i;
+    float v = L.gr[q];
+    if (H != nullptr)
+      v += bf16_to_f32(H[e * N3 + k * NP + j * N1 + i]) *
+           (bf16_to_f32(L.u[q]) + bf16_to_f32(L.ul[q]));
+    return v;
+  };
+  if (act) {
+    for (int p = l; p < N3; p += 64) w[e * N3 + p] = wval(p % N1, (p / N1) % N1, p / NP);
+  }
+  if (edot != nullptr) {  // uniform
+    const int i = l & 7, j = l >> 3;
+    double cd = 0.0;
+    if (i < N1 && j < N1) {
+#pragma unroll
+      for (int t = 0; t < N1; ++t) cd += (double)pv[t] * (double)wval(i, j, t);
+    }
+    cd = wave_sum64(cd);
+    if (act && l == 0) edot[e] = cd;
+  }
+}
+
+// want_edot: also store every element's energy p_e^T w_e in FP64 (the terms
+// of (p, A p) for the solvers), each lane's column of the FP32 input p times
+// the stored w in ascending k, then the lanes by a fixed butterfly
 template <int N1, bool SPLIT>
 __global__ void __launch_bounds__(64 * MW)
     k_bax_mfma(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
                const AxItem *__restrict__ items, int nitems, int epb, int src,
-               int dst, int skip_done) {
-  constexpr int NP = N1 * N1, N3 = NP * N1;
+               int dst, int skip_done, int want_edot) {
   __shared__ MfmaLdsSplit lds[MW];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   MfmaLdsSplit &L = lds[wv];
@@ -559,45 +623,87 @@ __global__ void __launch_bounds__(64 * MW)
     const AxItem it = items[q];
     if (skip_done && st[it.solve].done != 0) continue;  // uniform per block
     const BatchSolve &sd = sds[it.solve];
-    // global pointers (their address space is not known from the descriptor)
-    const gp<const float> u = (gp<const float>)sd.v32[src];
-    const gp<float> w = (gp<float>)sd.v32[dst];
-    const uint16_t *G = (const uint16_t *)sd.G16;
-    const gp<const uint16_t> H = (gp<const uint16_t>)sd.H16;  // null without a mass term
     m16x4 fh, fl, bh, bl;
     d_operands<N1>(l, (const uint16_t *)sd.D16hi, (const uint16_t *)sd.D16lo, fh,
                    fl, bh, bl);
     for (int e0 = 0; e0 < epb; e0 += MW) {  // uniform per block
       const int64_t e = it.elem0 + e0 + wv;
-      const bool act = e0 + wv < epb && e < sd.E;
-      uint16_t gq[6][8];
-      load_factors<N1>(l, act, e, G, gq);
-      ElemXYZ c3 = {0u, 0u, 0u};
-      if (act) c3 = box_elem(sd.box, (uint32_t)e);
-#pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int p = l + 64 * t, i = p & 7, j = (p >> 3) & 7, k = p >> 6;
-        const bool in = act && i < N1 && j < N1 && k < N1;
-        const float v = in ? u[box_node(sd.box, c3, i, j, k)] : 0.f;
-        const uint16_t hi = f32_to_bf16(v);
-        L.u[p] = hi;
-        L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
-      }
-      __syncthreads();
-      mfma_element<N1, SPLIT, true, MfmaLdsSplit>(l, L, gq, fh, fl, bh, bl);
-      if (act) {
-        for (int p = l; p < N3; p += 64) {
-          const int i = p % N1, j = (p / N1) % N1, k = p / NP;
-          const int q = k * 64 + j * 8 + i;
-          float v = L.gr[q];
-          if (H != nullptr)
-            v += bf16_to_f32(H[e * N3 + p]) *
-                 (bf16_to_f32(L.u[q]) + bf16_to_f32(L.ul[q]));
-          w[e * N3 + p] = v;
-        }
-      }
+      // global pointers (their address space is not known from the descriptor)
+      solve_elem_mfma<N1, SPLIT>(
+          l, L, e, e0 + wv < epb && e < sd.E, sd.box, (gp<const float>)sd.v32[src],
+          (gp<float>)sd.v32[dst], (const uint16_t *)sd.G16, (gp<const uint16_t>)sd.H16,
+          fh, fl, bh, bl, want_edot ? (gp<double>)sd.edot : nullptr);
       __syncthreads();  // L is reused by the next element
     }
+  }
+}
+
+// The same operator for a single solve, every argument passed in (no work
+// item or descriptor to fetch first), one element per wave; a finished
+// solve's workgroups return at once.
+template <int N1, bool SPLIT>
+__global__ void __launch_bounds__(64 * MW)
+    k_ax_mfma_solve(int64_t E, const uint16_t *__restrict__ Dhi,
+                    const uint16_t *__restrict__ Dlo, const uint16_t *__restrict__ G,
+                    const uint16_t *__restrict__ H, const float *__restrict__ u,
+                    float *__restrict__ w, Box box, const int32_t *__restrict__ stop,
+                    double *__restrict__ edot) {
+  __shared__ MfmaLdsSplit lds[MW];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (stop != nullptr && *stop != 0) return;  // uniform: the solve is done
+  m16x4 fh, fl, bh, bl;
+  d_operands<N1>(l, Dhi, Dlo, fh, fl, bh, bl);
+  const int64_t e = (int64_t)blockIdx.x * MW + wv;
+  solve_elem_mfma<N1, SPLIT>(l, lds[wv], e, e < E, box, (gp<const float>)u, (gp<float>)w,
+                             G, (gp<const uint16_t>)H, fh, fl, bh, bl,
+                             (gp<double>)edot);
+}
+
+// one element of the solvers' operator at n1 = 9 (as solve_elem_mfma)
+template <bool SPLIT>
+__device__ inline void solve_elem_mfma9(int l, MfmaLds9 &L, int64_t e, bool act,
+                                        const Box &box, gp<const float> u, gp<float> w,
+                                        const uint16_t *G, gp<const uint16_t> H,
+                                        m16x4 fh, m16x4 fl, m16x4 bh, m16x4 bl,
+                                        gp<double> edot) {
+  uint16_t gq[2][6][9];
+  load_factors9(l, act, e, G, gq);
+  ElemXYZ c3 = {0u, 0u, 0u};
+  if (act) c3 = box_elem(box, (uint32_t)e);
+  constexpr int T9 = (E9 + 63) / 64;
+  float pv[T9];  // p at the lane's nodes p = l + 64 t
+#pragma unroll
+  for (int t = 0; t < T9; ++t) {
+    const int p = l + 64 * t;
+    if (p < E9) {
+      const int i = p % 9, j = (p / 9) % 9, k = p / 81;
+      const float v = act ? u[box_node(box, c3, i, j, k)] : 0.f;
+      pv[t] = v;
+      const uint16_t hi = f32_to_bf16(v);
+      L.u[p] = hi;
+      L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
+    } else {
+      pv[t] = 0.f;
+    }
+  }
+  __syncthreads();
+  mfma_element9<SPLIT, true>(l, L, gq, fh, fl, bh, bl);
+  auto wval = [&](int p) {  // w at node p, as stored (mass term added)
+    float v = L.gr[p];
+    if (H != nullptr)
+      v += bf16_to_f32(H[e * E9 + p]) * (bf16_to_f32(L.u[p]) + bf16_to_f32(L.ul[p]));
+    return v;
+  };
+  if (act) {
+    for (int p = l; p < E9; p += 64) w[e * E9 + p] = wval(p);
+  }
+  if (edot != nullptr) {  // uniform; each lane's nodes in ascending t, then the lanes
+    double cd = 0.0;
+#pragma unroll
+    for (int t = 0; t < T9; ++t)
+      if (l + 64 * t < E9) cd += (double)pv[t] * (double)wval(l + 64 * t);
+    cd = wave_sum64(cd);
+    if (act && l == 0) edot[e] = cd;
   }
 }
 
@@ -607,7 +713,7 @@ template <bool SPLIT>
 __global__ void __launch_bounds__(64 * MW9)
     k_bax_mfma9(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
                 const AxItem *__restrict__ items, int nitems, int epb, int src,
-                int dst, int skip_done) {
+                int dst, int skip_done, int want_edot) {
   __shared__ MfmaLds9 lds[MW9];
   const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
   MfmaLds9 &L = lds[wv];
@@ -615,45 +721,84 @@ __global__ void __launch_bounds__(64 * MW9)
     const AxItem it = items[q];
     if (skip_done && st[it.solve].done != 0) continue;  // uniform per block
     const BatchSolve &sd = sds[it.solve];
-    const gp<const float> u = (gp<const float>)sd.v32[src];
-    const gp<float> w = (gp<float>)sd.v32[dst];
-    const uint16_t *G = (const uint16_t *)sd.G16;
-    const gp<const uint16_t> H = (gp<const uint16_t>)sd.H16;  // null without a mass term
     m16x4 fh, fl, bh, bl;
     d_operands9(l, (const uint16_t *)sd.D16hi, (const uint16_t *)sd.D16lo, fh, fl,
                 bh, bl);
     for (int e0 = 0; e0 < epb; e0 += MW9) {  // uniform per block
       const int64_t e = it.elem0 + e0 + wv;
-      const bool act = e0 + wv < epb && e < sd.E;
-      uint16_t gq[2][6][9];
-      load_factors9(l, act, e, G, gq);
-      ElemXYZ c3 = {0u, 0u, 0u};
-      if (act) c3 = box_elem(sd.box, (uint32_t)e);
-      for (int p = l; p < E9; p += 64) {
-        const int i = p % 9, j = (p / 9) % 9, k = p / 81;
-        const float v = act ? u[box_node(sd.box, c3, i, j, k)] : 0.f;
-        const uint16_t hi = f32_to_bf16(v);
-        L.u[p] = hi;
-        L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
-      }
-      __syncthreads();
-      mfma_element9<SPLIT, true>(l, L, gq, fh, fl, bh, bl);
-      if (act) {
-        for (int p = l; p < E9; p += 64) {
-          float v = L.gr[p];
-          if (H != nullptr)
-            v += bf16_to_f32(H[e * E9 + p]) * (bf16_to_f32(L.u[p]) + bf16_to_f32(L.ul[p]));
-          w[e * E9 + p] = v;
-        }
-      }
+      solve_elem_mfma9<SPLIT>(
+          l, L, e, e0 + wv < epb && e < sd.E, sd.box, (gp<const float>)sd.v32[src],
+          (gp<float>)sd.v32[dst], (const uint16_t *)sd.G16, (gp<const uint16_t>)sd.H16,
+          fh, fl, bh, bl, want_edot ? (gp<double>)sd.edot : nullptr);
       __syncthreads();  // L is reused by the next element
     }
   }
 }
 
+// the single-solve operator at n1 = 9 (as k_ax_mfma_solve)
+template <bool SPLIT>
+__global__ void __launch_bounds__(64 * MW9)
+    k_ax_mfma_solve9(int64_t E, const uint16_t *__restrict__ Dhi,
+                     const uint16_t *__restrict__ Dlo, const uint16_t *__restrict__ G,
+                     const uint16_t *__restrict__ H, const float *__restrict__ u,
+                     float *__restrict__ w, Box box, const int32_t *__restrict__ stop,
+                     double *__restrict__ edot) {
+  __shared__ MfmaLds9 lds[MW9];
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (stop != nullptr && *stop != 0) return;  // uniform: the solve is done
+  m16x4 fh, fl, bh, bl;
+  d_operands9(l, Dhi, Dlo, fh, fl, bh, bl);
+  const int64_t e = (int64_t)blockIdx.x * MW9 + wv;
+  solve_elem_mfma9<SPLIT>(l, lds[wv], e, e < E, box, (gp<const float>)u, (gp<float>)w, G,
+                          (gp<const uint16_t>)H, fh, fl, bh, bl, (gp<double>)edot);
+}
+
+void launch_ax_mfma_solve(int N, bool split, int64_t E, const uint16_t *Dhi,
+                          const uint16_t *Dlo, const uint16_t *G, const uint16_t *H,
+                          const float *u, float *w, const Box &box, const int32_t *stop,
+                          double *edot, hipStream_t s) {
+  if (E <= 0) return;
+  const int n1 = N + 1;
+  if (n1 == 9) {
+    const dim3 g((unsigned)((E + MW9 - 1) / MW9)), b(64 * MW9);
+    if (split)
+      hipLaunchKernelGGL((k_ax_mfma_solve9<true>), g, b, 0, s, E, Dhi, Dlo, G, H, u, w,
+                         box, stop, edot);
+    else
+      hipLaunchKernelGGL((k_ax_mfma_solve9<false>), g, b, 0, s, E, Dhi, Dlo, G, H, u, w,
+                         box, stop, edot);
+    SEM_HIP(hipGetLastError());
+    return;
+  }
+  const dim3 g((unsigned)((E + MW - 1) / MW)), b(64 * MW);
+  switch (n1) {
+#define SEM_AXMS(NN)                                                                  \
+  case NN:                                                                            \
+    if (split)                                                                        \
+      hipLaunchKernelGGL((k_ax_mfma_solve<NN, true>), g, b, 0, s, E, Dhi, Dlo, G, H,  \
+                         u, w, box, stop, edot);                                      \
+    else                                                                              \
+      hipLaunchKernelGGL((k_ax_mfma_solve<NN, false>), g, b, 0, s, E, Dhi, Dlo, G, H, \
+                         u, w, box, stop, edot);                                      \
+    break;
+    SEM_AXMS(2)
+    SEM_AXMS(3)
+    SEM_AXMS(4)
+    SEM_AXMS(5)
+    SEM_AXMS(6)
+    SEM_AXMS(7)
+    SEM_AXMS(8)
+#undef SEM_AXMS
+    default:
+      fail(SEM_ERR_ARG, "solve: the matrix-core operator needs N in 1..8");
+  }
+  SEM_HIP(hipGetLastError());
+}
+
 void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *st,
                      const AxItem *items, int nitems, int epb, int grid, int src,
-                     int dst, int skip_done, hipStream_t s) {
+                     int dst, int skip_done, bool edot, hipStream_t s) {
+  const int want_edot = edot ? 1 : 0;
   if (nitems <= 0) return;
   const dim3 g((unsigned)grid), b(64 * MW);
   switch (n1) {
@@ -661,10 +806,10 @@ void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *s
   case NN:                                                                      \
     if (split)                                                                  \
       hipLaunchKernelGGL((k_bax_mfma<NN, true>), g, b, 0, s, sds, st, items,    \
-                         nitems, epb, src, dst, skip_done);                     \
+                         nitems, epb, src, dst, skip_done, want_edot);          \
     else                                                                        \
       hipLaunchKernelGGL((k_bax_mfma<NN, false>), g, b, 0, s, sds, st, items,   \
-                         nitems, epb, src, dst, skip_done);                     \
+                         nitems, epb, src, dst, skip_done, want_edot);          \
     break;
     SEM_BAXM(2)
     SEM_BAXM(3)
@@ -678,10 +823,10 @@ void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *s
       const dim3 b9(64 * MW9);
       if (split)
         hipLaunchKernelGGL((k_bax_mfma9<true>), g, b9, 0, s, sds, st, items, nitems,
-                           epb, src, dst, skip_done);
+                           epb, src, dst, skip_done, want_edot);
       else
         hipLaunchKernelGGL((k_bax_mfma9<false>), g, b9, 0, s, sds, st, items, nitems,
-                           epb, src, dst, skip_done);
+                           epb, src, dst, skip_done, want_edot);
       break;
     }
     default:

@@ -180,7 +180,13 @@ void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
                     const uint16_t *u, float *w, hipStream_t s);
 void launch_bax_mfma(int n1, bool split, const BatchSolve *sds, const CgState *st,
                      const AxItem *items, int nitems, int epb, int grid, int src,
-                     int dst, int skip_done, hipStream_t s);
+                     int dst, int skip_done, bool edot, hipStream_t s);
+// the matrix-core solver operator of a single solve (gathered FP32 input,
+// FP32 output; element energies into edot when non-null)
+void launch_ax_mfma_solve(int N, bool split, int64_t E, const uint16_t *Dhi,
+                          const uint16_t *Dlo, const uint16_t *G, const uint16_t *H,
+                          const float *u, float *w, const Box &box, const int32_t *stop,
+                          double *edot, hipStream_t s);
 int bax_elements_per_tile(int bs, int n1);
 // smallest workgroup (64, 128, 256) holding every (i, j) column of the
 // largest order of an order set

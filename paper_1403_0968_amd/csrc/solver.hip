@@ -145,26 +145,6 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
-// alpha_s = rz_s / (p, A p)_s, one workgroup per solve
-__global__ void __launch_bounds__(RT)
-    k_balpha(CgState *st, const double *__restrict__ part,
-             const int32_t *__restrict__ vbeg) {
-  __shared__ double sm[RT / 64];
-  const int s = blockIdx.x;
-  if (threadIdx.x == 0) st[s].xupd = 0;  // no x update from an earlier step
-  if (st[s].done != 0) return;
-  double acc[1];
-  strided_sums<1>(part, 0, vbeg[s], vbeg[s + 1], acc);
-  const double pw = block_sum<RT>(acc[0], sm);
-  if (threadIdx.x == 0) {
-    st[s].pw = pw;
-    if (!(pw > 0.0) || !isfinite(pw))
-      st[s].done = 2;
-    else
-      st[s].alpha = st[s].rz / pw;
-  }
-}
-
 // alpha_s = rz_s / (p, A p)_s with (p, A p) the sum of the solve's element
 // energies in element order (strided over the workgroup's threads, then the
 // fixed workgroup sum), one workgroup of AT threads per solve
@@ -331,41 +311,6 @@ __global__ void __launch_bounds__(RT)
   xr_asm_chunk<TV, TD, FCG, PER, W64>(a.box, (gp<const TV>)a.wL, (gp<TV>)a.r,
                                       (gp<TV>)a.z, (gp<const TD>)a.dinv, (TV)st->alpha,
                                       (int64_t)q * VCH, a.nG, q, nitems, part, sm);
-}
-
-// r -= alpha w, z = dinv r (w the stored assembled vector); partials (r, z),
-// (r, r).  The x update waits for k_bupdate_p.
-template <class TV, class TD>
-__global__ void __launch_bounds__(RT)
-    k_bupdate_xr(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
-                 const VecItem *__restrict__ items, int nitems,
-                 double *__restrict__ part, int jac) {
-  __shared__ double sm[RT / 64];
-  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
-    const VecItem it = items[q];
-    if (st[it.solve].done != 0) continue;
-    const BatchSolve &sd = sds[it.solve];
-    gp<TV> r = vec<TV>(sd, VR), z = vec<TV>(sd, VZ);
-    gp<const TV> w = vec<TV>(sd, VW);
-    gp<const TD> dinv = dinv_of<TD>(sd, jac);
-    const TV alpha = (TV)st[it.solve].alpha;
-    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    double rz = 0.0, rr = 0.0;
-    for (int64_t g = it.start + threadIdx.x; g < end; g += RT) {
-      const TV rn = r[g] - alpha * w[g];
-      r[g] = rn;
-      const TV zn = (TV)(dinv[g] * rn);
-      z[g] = zn;
-      rz += (double)rn * (double)zn;
-      rr += (double)rn * (double)rn;
-    }
-    const double trz = block_sum<RT>(rz, sm);
-    const double trr = block_sum<RT>(rr, sm);
-    if (threadIdx.x == 0) {
-      part[q] = trz;
-      part[nitems + q] = trr;
-    }
-  }
 }
 
 // rz, rr per solve -> convergence / beta
@@ -628,26 +573,6 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
-// ---- flexible CG with the learned correction (single solve) -------------
-// r -= alpha w (z comes from the correction below, x from k_bupdate_p)
-template <class TV>
-__global__ void __launch_bounds__(RT)
-    k_bupdate_r_only(const BatchSolve *__restrict__ sds,
-                     const CgState *__restrict__ st,
-                     const VecItem *__restrict__ items, int nitems) {
-  for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
-    const VecItem it = items[q];
-    if (st[it.solve].done != 0) continue;
-    const BatchSolve &sd = sds[it.solve];
-    gp<TV> r = vec<TV>(sd, VR);
-    gp<const TV> w = vec<TV>(sd, VW);
-    const TV alpha = (TV)st[it.solve].alpha;
-    const int64_t end = min(it.start + (int64_t)VCH, sd.nG);
-    for (int64_t g = it.start + threadIdx.x; g < end; g += RT)
-      r[g] = r[g] - alpha * w[g];
-  }
-}
-
 // z = dinv r + c with c the coarse correction on unique nodes (cG); partials
 // (r, z), (z, w), (r, r).  skip_done = 0 during initialisation.
 template <class TV, class TD>
@@ -687,40 +612,10 @@ __global__ void __launch_bounds__(RT)
   }
 }
 
-// beta = -(z, A p) / (p, A p) (Notay's flexible CG with one stored
-// direction); convergence on (r, r)
-__global__ void __launch_bounds__(RT)
-    k_bbeta_fcg(CgState *st, const double *__restrict__ part,
-                const int32_t *__restrict__ vbeg, int nitems) {
-  __shared__ double sm[RT / 64];
-  const int s = blockIdx.x;
-  if (st[s].done != 0) return;
-  double acc[3];
-  strided_sums<3>(part, nitems, vbeg[s], vbeg[s + 1], acc);
-  const double a = acc[0], b = acc[1], c = acc[2];
-  const double rz = block_sum<RT>(a, sm);
-  const double zw = block_sum<RT>(b, sm);
-  const double rr = block_sum<RT>(c, sm);
-  if (threadIdx.x == 0) {
-    CgState &cs = st[s];
-    cs.xupd = 1;  // this step's alpha is finite: x += alpha p follows
-    cs.it += 1;
-    cs.rr = rr;
-    if (!isfinite(rr) || !isfinite(rz) || !isfinite(zw))
-      cs.done = 2;
-    else if (rr <= cs.tol2 * cs.bb)
-      cs.done = 1;
-    else if (cs.it >= cs.maxit)
-      cs.done = 3;
-    else {
-      cs.beta = -zw / cs.pw;
-      cs.rz = rz;
-    }
-  }
-}
-
-// as k_bbeta_fcg for one solve whose correction step stored its element
-// terms of (r, c) and (c, w) in epart ([2][E]): (r, z) and (z, w) add them
+// flexible CG (Notay's, one stored direction): beta = -(z, A p) / (p, A p),
+// convergence on (r, r), for one solve whose correction step stored its
+// element terms of (r, c) and (c, w) in epart ([2][E]): (r, z) and (z, w)
+// are the partials of the r update plus those terms
 __global__ void __launch_bounds__(RT)
     k_bbeta_fcg_e(CgState *st, const double *__restrict__ part, int nitems,
                   const double *__restrict__ epart, int E) {
@@ -1077,11 +972,21 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
     if (b->nset < 2 || b->nset > 9)
       fail(SEM_ERR_ARG, "solve: the matrix-core operator needs solves of one "
                         "order N <= 8");
+    if (b->n == 1) {  // a single solve: every argument passed in
+      const BatchSolve &d = b->hsd[0];
+      const int32_t *stop =
+          skip_done ? &b->st.as<CgState>()[0].done : (const int32_t *)nullptr;
+      launch_ax_mfma_solve(d.N1 - 1, prec == SEM_BF16_MFMA, d.E, (const uint16_t *)d.D16hi,
+                           (const uint16_t *)d.D16lo, (const uint16_t *)d.G16,
+                           (const uint16_t *)d.H16, (const float *)d.v32[src],
+                           (float *)d.v32[dst], d.box, stop, edot ? d.edot : nullptr, b->s);
+      return;
+    }
     const int k = bs_slot(256);
     launch_bax_mfma(b->nset, prec == SEM_BF16_MFMA, b->sds.as<BatchSolve>(),
                     b->st.as<CgState>(), b->axitems[k].as<AxItem>(), b->n_ax[k],
                     bax_elements_per_tile(256, b->nset), b->n_ax[k], src, dst,
-                    skip_done, b->s);
+                    skip_done, edot, b->s);
     return;
   }
   if (b->n == 1) {
@@ -1138,25 +1043,16 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   double *part = b->part.as<double>();
   const int32_t *vbeg = b->vbeg.as<int32_t>();
   const int g = vec_grid(b), nv = b->n_vi, n = b->n;
-  if (prec == SEM_BF16_MFMA || prec == SEM_BF16_PLAIN_D) {
-    // no element energies from the matrix-core operator: assembled w and
-    // (p, w) first
-    bax(b, prec, VP, VWL, 1);
-    SEM_PER_LAUNCH(b, (k_bassemble<TV, true, PER_>), dim3(g), dim3(RT), 0, b->s, sds,
-                       st, vi, nv, part, 1);
-    hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
-    hipLaunchKernelGGL((k_bupdate_xr<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
-                       st, vi, nv, part, jac);
-  } else {
-    bax(b, prec, VP, VWL, 1, true);
-    hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
-    if (b->n == 1)
-      SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, false, PER_, W64_>), dim3(nv), dim3(RT), 0,
-                     b->s, vecs1<TV, TD>(b, jac), st, nv, part);
-    else
-      SEM_ASM_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, false, PER_, W64_>), dim3(g), dim3(RT),
-                     0, b->s, sds, st, vi, nv, part, jac);
-  }
+  // (p, A p) from the operator's element energies (every operator form, the
+  // matrix-core one included, stores them)
+  bax(b, prec, VP, VWL, 1, true);
+  hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
+  if (b->n == 1)
+    SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, false, PER_, W64_>), dim3(nv), dim3(RT), 0,
+                   b->s, vecs1<TV, TD>(b, jac), st, nv, part);
+  else
+    SEM_ASM_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, false, PER_, W64_>), dim3(g), dim3(RT), 0,
+                   b->s, sds, st, vi, nv, part, jac);
   hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
   if (b->n == 1)
     hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s,
@@ -1166,53 +1062,29 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   SEM_HIP(hipGetLastError());
 }
 
-float *learn_cg(sem_handle *h);
-
+// flexible CG with the learned correction (single solves): (p, A p) from the
+// operator's element energies; the r update forms the assembled w, z = dinv r
+// and the partials of (r, z), (z, w), (r, r); the correction step adds c to
+// z on the element interiors and stores the element terms of (r, c) and
+// (c, w)
 template <class TV, class TD>
 static void iteration_fcg_t(sem_batch *b, int prec) {
-  const BatchSolve *sds = b->sds.as<BatchSolve>();
   CgState *st = b->st.as<CgState>();
-  const VecItem *vi = b->vitems.as<VecItem>();
   double *part = b->part.as<double>();
-  const int32_t *vbeg = b->vbeg.as<int32_t>();
-  const int g = vec_grid(b), nv = b->n_vi, n = b->n;
+  const int nv = b->n_vi, n = b->n;
   sem_handle *h = b->hs[0];
   const bool f32 = sizeof(TV) == 4;
-  if (prec == SEM_BF16_MFMA || prec == SEM_BF16_PLAIN_D) {
-    // no element energies from the matrix-core operator: assembled w and
-    // (p, w) first
-    bax(b, prec, VP, VWL, 1);
-    SEM_PER_LAUNCH(b, (k_bassemble<TV, true, PER_>), dim3(g), dim3(RT), 0, b->s, sds,
-                       st, vi, nv, part, 1);
-    hipLaunchKernelGGL(k_balpha, dim3(n), dim3(RT), 0, b->s, st, part, vbeg);
-    hipLaunchKernelGGL((k_bupdate_r_only<TV>), dim3(g), dim3(RT), 0, b->s, sds,
-                       st, vi, nv);
-  } else {
-    // (p, A p) from the operator's element energies; the r update forms the
-    // assembled w, z = dinv r and the partials of (r, z), (z, w), (r, r);
-    // the correction step adds c to z on the element interiors and stores
-    // the element terms of (r, c) and (c, w)
-    bax(b, prec, VP, VWL, 1, true);
-    hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
-    // (the learned correction runs on single solves: nv chunks of one solve)
-    SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, true, PER_, W64_>), dim3(nv), dim3(RT), 0, b->s,
-                   vecs1<TV, TD>(b, 1), st, nv, part);
-    const BatchSolve &d = b->hsd[0];
-    learn_apply_fused(h, f32 ? d.v32[VR] : d.v64[VR], f32 ? d.v32[VZ] : d.v64[VZ],
-                      f32 ? d.v32[VWL] : d.v64[VWL], f32, b->s);
-    hipLaunchKernelGGL(k_bbeta_fcg_e, dim3(1), dim3(RT), 0, b->s, st, part, nv,
-                       learn_epart(h), (int)h->E);
-    hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s,
-                       vecs1<TV, TD>(b, 1), st);
-    SEM_HIP(hipGetLastError());
-    return;
-  }
-  learn_apply(h, f32 ? b->hsd[0].v32[VR] : b->hsd[0].v64[VR], f32, b->s);
-  hipLaunchKernelGGL((k_bprec_learned<TV, TD>), dim3(g), dim3(RT), 0, b->s, sds,
-                     st, vi, nv, learn_cg(h), part, 1);
-  hipLaunchKernelGGL(k_bbeta_fcg, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
-  hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi,
-                     nv);
+  bax(b, prec, VP, VWL, 1, true);
+  hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, b->sds.as<BatchSolve>(), st);
+  SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, true, PER_, W64_>), dim3(nv), dim3(RT), 0, b->s,
+                 vecs1<TV, TD>(b, 1), st, nv, part);
+  const BatchSolve &d = b->hsd[0];
+  learn_apply_fused(h, f32 ? d.v32[VR] : d.v64[VR], f32 ? d.v32[VZ] : d.v64[VZ],
+                    f32 ? d.v32[VWL] : d.v64[VWL], f32, b->s);
+  hipLaunchKernelGGL(k_bbeta_fcg_e, dim3(1), dim3(RT), 0, b->s, st, part, nv,
+                     learn_epart(h), (int)h->E);
+  hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s, vecs1<TV, TD>(b, 1),
+                     st);
   SEM_HIP(hipGetLastError());
 }
 
@@ -1231,6 +1103,8 @@ static void iteration(sem_batch *b, int prec, int jac, int mode = 0) {
   else
     iteration_t<float, float>(b, prec, jac);
 }
+
+float *learn_cg(sem_handle *h);
 
 // after init(): replace z by the learned preconditioner, p = z, rz
 static void init_fcg(sem_batch *b, int prec) {
