@@ -191,3 +191,41 @@ def test_batch_order8_block_holds_an_element(sem, prec, tmp_path):
         sem.sem_batch_destroy(bt)
         for h in hs:
             sem.sem_destroy(h)
+
+
+@pytest.mark.parametrize("N", [5, 8])
+def test_matrix_core_batch_equals_individual_solves_bitwise(sem, N):
+    """A batch of one order around the matrix-core inner operator (the
+    batched persistent kernel) gives the bits of the same solves run alone
+    (the single-solve kernel): both store the element energies in one fixed
+    order, and the update kernels share their per-chunk code."""
+    print(f"[gpu] matrix-core batch vs individual, N = {N}", flush=True)
+    t = torch()
+    hs, bs = [], []
+    for q, n in enumerate((2, 3, 2)):
+        h = sem.sem_setup(N, n, n + q % 2, n, mapping=sem.SEM_MAP_SINE_CYCLIC)
+        _, nL, _ = sem.sem_query(h)
+        b = t.empty(nL, dtype=t.float64, device="cuda")
+        sem.sem_rhs(h, b, sem.SEM_SRC_FOURIER, fourier_modes(seed=1200 + q))
+        hs.append(h)
+        bs.append(b)
+    bt = sem.sem_batch_create(hs)
+    try:
+        kw = dict(rtol=1e-10, maxit=4000, inner_prec=sem.SEM_BF16_MFMA, inner_rtol=1e-2,
+                  check_every=8)
+        xs = [t.zeros_like(b) for b in bs]
+        code, stats = sem.sem_batch_pcg_solve(bt, bs, xs, **kw)
+        t.cuda.synchronize()
+        assert code == 0
+        for q, (h, b) in enumerate(zip(hs, bs)):
+            x1 = t.zeros_like(b)
+            st1 = sem.sem_pcg_solve(h, b, x1, **kw)
+            t.cuda.synchronize()
+            assert stats[q]["iters"] == st1["iters"], (q, stats[q], st1)
+            assert stats[q]["outer_iters"] == st1["outer_iters"]
+            assert stats[q]["final_rel_res"] <= 1e-10
+            assert t.equal(xs[q], x1), q
+    finally:
+        sem.sem_batch_destroy(bt)
+        for h in hs:
+            sem.sem_destroy(h)
