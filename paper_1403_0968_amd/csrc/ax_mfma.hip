@@ -11,7 +11,9 @@
 // variant, kept for measurement).
 //
 // One wave per element, the element padded to 8^3 nodes (n1 <= 8; padded
-// entries of u and D are zero), four waves per workgroup.  MFMA tile
+// entries of u and D are zero), four waves per workgroup, each with its own
+// LDS region: the phases of an element are ordered by wave-level barriers,
+// so the waves of a workgroup do not wait for each other.  MFMA tile
 // 16x16x16 (v_mfma_f32_16x16x16_bf16): lane l = 16 g + r holds A[r][4g + q],
 // B[4g + q][r] and C[4g + q][r], q = 0..3.  A length-8 contraction uses a
 // block-diagonal operand diag(D, D) so that one MFMA contracts two 8-blocks:
@@ -125,7 +127,7 @@ __device__ inline void mfma_element(int l, Lds &L, const uint16_t (&gq)[6][8],
       for (int q = 0; q < 4; ++q) L.gs[k * 64 + (m0 + q) * 8 + i] = acc[q];
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   // ---- metric step on the lane's column (FP32) ----
   {
     const int i = l & 7, j = l >> 3;
@@ -141,7 +143,7 @@ __device__ inline void mfma_element(int l, Lds &L, const uint16_t (&gq)[6][8],
       L.ft[p] = f32_to_bf16(g2 * ur + g4 * us + g5 * ut);
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   // ---- divergence: w = D_r^T f_r + D_s^T f_s + D_t^T f_t into L.gr ----
 #pragma unroll
   for (int h2 = 0; h2 < 2; ++h2) {  // r: A from f_r[rho][m], B = D^T blocks
@@ -153,7 +155,7 @@ __device__ inline void mfma_element(int l, Lds &L, const uint16_t (&gq)[6][8],
 #pragma unroll
     for (int q = 0; q < 4; ++q) L.gr[(rho0 + q) * 8 + i] = acc[q];
   }
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int h2 = 0; h2 < 2; ++h2) {  // s: A = diag(D^T), B from f_s[k][m][i]
     const int k = 4 * h2 + 2 * (g >> 1) + (r >> 3), i = r & 7, m0 = 4 * (g & 1);
@@ -166,7 +168,7 @@ __device__ inline void mfma_element(int l, Lds &L, const uint16_t (&gq)[6][8],
 #pragma unroll
     for (int q = 0; q < 4; ++q) L.gr[k * 64 + (m0 + q) * 8 + i] = acc[q];
   }
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int h2 = 0; h2 < 2; ++h2) {  // t: A = diag(D^T), B from f_t[m][c]
     const int c = 32 * h2 + 16 * (g >> 1) + r, m0 = 4 * (g & 1);
@@ -179,7 +181,7 @@ __device__ inline void mfma_element(int l, Lds &L, const uint16_t (&gq)[6][8],
 #pragma unroll
     for (int q = 0; q < 4; ++q) L.gr[(m0 + q) * 64 + c] = acc[q];
   }
-  __syncthreads();
+  wave_lds_sync();
 }
 
 // the six BF16 factors of column (i, j) of element e: the column-contiguous
@@ -321,7 +323,7 @@ __device__ inline void mfma_element9(int l, MfmaLds9 &L, const uint16_t (&gq)[2]
     for (int q = 0; q < 4; ++q)
       if (4 * g + q < 9 && r < 9) L.gs[k * 81 + (4 * g + q) * 9 + r] = acc[q];
   }
-  __syncthreads();
+  wave_lds_sync();
   // ---- metric step on the lane's columns (FP32) ----
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
@@ -340,7 +342,7 @@ __device__ inline void mfma_element9(int l, MfmaLds9 &L, const uint16_t (&gq)[2]
       }
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   // ---- divergence into L.gr ----
 #pragma unroll
   for (int t = 0; t < 6; ++t) {  // r: A = f_r[rho][m], B[m][i] = D[m][i]
@@ -356,7 +358,7 @@ __device__ inline void mfma_element9(int l, MfmaLds9 &L, const uint16_t (&gq)[2]
       if (rr < 81 && r < 9) L.gr[rr * 9 + r] = acc[q];
     }
   }
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int k = 0; k < 9; ++k) {  // s: A[j][m] = D[m][j], B[m][i] = f_s[k][m][i]
     auto off = [&](int q) { return k * 81 + (4 * g + q) * 9 + r; };
@@ -371,7 +373,7 @@ __device__ inline void mfma_element9(int l, MfmaLds9 &L, const uint16_t (&gq)[2]
     for (int q = 0; q < 4; ++q)
       if (ok(q)) L.gr[off(q)] = acc[q];
   }
-  __syncthreads();
+  wave_lds_sync();
 #pragma unroll
   for (int t = 0; t < 6; ++t) {  // t: A[k][m] = D[m][k], B[m][c] = f_t[m][c]
     const int c = 16 * t + r;
@@ -387,7 +389,7 @@ __device__ inline void mfma_element9(int l, MfmaLds9 &L, const uint16_t (&gq)[2]
     for (int q = 0; q < 4; ++q)
       if (ok(q)) L.gr[off(q)] = acc[q];
   }
-  __syncthreads();
+  wave_lds_sync();
 }
 
 // the BF16 factors of columns l and l + 64 of element e ([E][6][729])
@@ -423,7 +425,7 @@ __global__ void __launch_bounds__(64 * MW9)
   uint16_t gq[2][6][9];
   load_factors9(l, act, e, G, gq);
   for (int p = l; p < E9; p += 64) L.u[p] = act ? u[e * E9 + p] : (uint16_t)0;
-  __syncthreads();
+  wave_lds_sync();
   mfma_element9<SPLIT, false>(l, L, gq, fh, fl, bh, bl);
   if (!act) return;  // no barrier follows
   for (int p = l; p < E9; p += 64) {
@@ -464,7 +466,7 @@ __global__ void __launch_bounds__(64 * MW)
                                                    : (uint16_t)0;
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   mfma_element<N1, SPLIT>(l, L, gq, fh, fl, bh, bl);
   if (!act) return;  // no barrier follows
   if constexpr (N1 == 8) {
@@ -546,13 +548,6 @@ void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
 // operator's spread of eigenvalues, and the refinement's contraction grew
 // with the mesh (0.36 per step at 32^3 elements, N = 7).
 // ---------------------------------------------------------------------------
-// the sum of 64 lane values by a fixed butterfly (every lane gets it)
-__device__ inline double wave_sum64(double v) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // want_edot: also store every element's energy p_e^T w_e in FP64 (the terms
 // of (p, A p) for the solvers), each lane's column of the FP32 input p times
 // the stored w in ascending k, then the lanes by a fixed butterfly
@@ -582,7 +577,7 @@ __device__ inline void solve_elem_mfma(int l, MfmaLdsSplit &L, int64_t e, bool a
     L.u[p] = hi;
     L.ul[p] = f32_to_bf16(v - bf16_to_f32(hi));
   }
-  __syncthreads();
+  wave_lds_sync();
   mfma_element<N1, SPLIT, true, MfmaLdsSplit>(l, L, gq, fh, fl, bh, bl);
   // w at node (i, j, k) of the element, as stored (mass term added)
   auto wval = [&](int i, int j, int k) {
@@ -603,7 +598,7 @@ __device__ inline void solve_elem_mfma(int l, MfmaLdsSplit &L, int64_t e, bool a
 #pragma unroll
       for (int t = 0; t < N1; ++t) cd += (double)pv[t] * (double)wval(i, j, t);
     }
-    cd = wave_sum64(cd);
+    cd = wave_sum(cd);
     if (act && l == 0) edot[e] = cd;
   }
 }
@@ -633,7 +628,7 @@ __global__ void __launch_bounds__(64 * MW)
           l, L, e, e0 + wv < epb && e < sd.E, sd.box, (gp<const float>)sd.v32[src],
           (gp<float>)sd.v32[dst], (const uint16_t *)sd.G16, (gp<const uint16_t>)sd.H16,
           fh, fl, bh, bl, want_edot ? (gp<double>)sd.edot : nullptr);
-      __syncthreads();  // L is reused by the next element
+      wave_lds_sync();  // L is reused by the next element
     }
   }
 }
@@ -686,7 +681,7 @@ __device__ inline void solve_elem_mfma9(int l, MfmaLds9 &L, int64_t e, bool act,
       pv[t] = 0.f;
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   mfma_element9<SPLIT, true>(l, L, gq, fh, fl, bh, bl);
   auto wval = [&](int p) {  // w at node p, as stored (mass term added)
     float v = L.gr[p];
@@ -702,7 +697,7 @@ __device__ inline void solve_elem_mfma9(int l, MfmaLds9 &L, int64_t e, bool act,
 #pragma unroll
     for (int t = 0; t < T9; ++t)
       if (l + 64 * t < E9) cd += (double)pv[t] * (double)wval(l + 64 * t);
-    cd = wave_sum64(cd);
+    cd = wave_sum(cd);
     if (act && l == 0) edot[e] = cd;
   }
 }
@@ -730,7 +725,7 @@ __global__ void __launch_bounds__(64 * MW9)
           l, L, e, e0 + wv < epb && e < sd.E, sd.box, (gp<const float>)sd.v32[src],
           (gp<float>)sd.v32[dst], (const uint16_t *)sd.G16, (gp<const uint16_t>)sd.H16,
           fh, fl, bh, bl, want_edot ? (gp<double>)sd.edot : nullptr);
-      __syncthreads();  // L is reused by the next element
+      wave_lds_sync();  // L is reused by the next element
     }
   }
 }

@@ -120,6 +120,14 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   TC *s_r = smem + (1 * EPB + elc) * SL;
   TC *s_s = smem + (2 * EPB + elc) * SL;
 #define AX_IDX(k, jj, ii) (((k) * N1 + (jj)) * PAD + (ii))
+  // n1 = 8: an element is one whole wave with its own slice stack, so the
+  // phases of the element need only a wave-level barrier
+  auto phase_sync = [] {
+    if constexpr (NP == 64)
+      wave_lds_sync();
+    else
+      __syncthreads();
+  };
 
   constexpr bool VEC16 = sizeof(TG) == 2 && N1 == 8;  // BF16 column layout
   constexpr bool VECU = sizeof(TU) == 2 && N1 == 8 && !GATHER;
@@ -195,7 +203,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
         s_u[AX_IDX(c / 8, c % 8, 2 * h + 1)] = Cvt<TU, TC>::ld((TU)(wv[h] >> 16));
       }
     }
-    __syncthreads();
+    phase_sync();
 #pragma unroll
     for (int k = 0; k < N1; ++k) uc[k] = s_u[AX_IDX(k, j, i)];
   } else {
@@ -220,7 +228,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
     Di[m] = D[i * N1 + m];
     Dj[m] = D[j * N1 + m];
   }
-  __syncthreads();
+  phase_sync();
 
   // gradient (r, s from LDS; t from registers) and fluxes, slice by slice
   TC wt[N1];
@@ -249,7 +257,7 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
     }
     wt[k] = g2 * ur + g4 * us + g5 * ut;
   }
-  __syncthreads();
+  phase_sync();
 
   // w = D_r^T w_r + D_s^T w_s + D_t^T w_t
   TC DTi[N1], DTj[N1];

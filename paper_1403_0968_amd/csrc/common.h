@@ -52,6 +52,17 @@ template <> struct Cvt<double, float> {
 // memory (all device buffers here) access them through gp pointers.
 template <class T> using gp = T __attribute__((address_space(1))) *;
 
+// orders a wave's LDS writes before its later LDS reads of other lanes'
+// entries: the lanes of a wave execute together and a wave's LDS
+// operations complete in issue order, so only the compiler has to be kept
+// from moving accesses across this point (for LDS regions that one wave
+// owns; a workgroup barrier would also wait for the other waves)
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // wave64 sum in a fixed order (butterfly over lanes), deterministic
 __device__ inline double wave_sum(double v) {
 #pragma unroll

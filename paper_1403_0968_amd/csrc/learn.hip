@@ -300,14 +300,6 @@ __global__ void __launch_bounds__(256)
 // and vector instruction count.)
 constexpr int CA_WAVES = 4;
 
-// orders the wave's LDS writes before its later LDS reads of other lanes'
-// entries (the lanes of one wave execute together; the fences keep the
-// compiler from moving accesses across this point)
-__device__ inline void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // FUSE (with UNIQUE): the flexible-CG iteration's preconditioner step.  zf
 // is the search vector z of the solve, holding dinv o r on entry; the
@@ -376,7 +368,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
 #pragma unroll
     for (int i = 0; i < MR; ++i)
       if (t + 64 * i < KK) Ms[t + 64 * i] = mv[i];
-    wave_sync();
+    wave_lds_sync();
     // FUSE: this element's z and w_I are read now, so that their latency
     // overlaps the contractions below (with one element per wave the
     // prefetch of the next element's r and M_e does not apply)
@@ -407,7 +399,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
         s2[k * Q2 + a + Q * b] = acc;
       }
     }
-    wave_sync();
+    wave_lds_sync();
     // direction k: lane ab -> y[ab + Q2 c] (unscaled)
     if (t < Q2) {
       float v[M];
@@ -421,7 +413,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
         yv[t + Q2 * c] = acc;
       }
     }
-    wave_sync();
+    wave_lds_sync();
     // alpha = damping M_e (sc o y); beta = sc o alpha
     if (t < K) {
       float acc = 0.f;
@@ -431,7 +423,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
                (tb.sc[jj] * yv[jj]);
       bv[t] = sct * (damp * acc);
     }
-    wave_sync();
+    wave_lds_sync();
     // prolongation, direction k: lane ab -> s2[k][ab]
     if (t < Q2) {
       float v[Q];
@@ -445,7 +437,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
         s2[k * Q2 + t] = acc;
       }
     }
-    wave_sync();
+    wave_lds_sync();
     // direction j: lane (a, k) -> s1[a][j + M k]
     if (t < Q * M) {
       const int a = t % Q, k = t / Q;
@@ -460,7 +452,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
         s1[a * P + j + M * k] = acc;
       }
     }
-    wave_sync();
+    wave_lds_sync();
     // direction i: lane = pencil, M contiguous interior nodes
     double prc = 0.0, pcw = 0.0;  // FUSE: this lane's (r_I, c), (c, w_I) terms
     if (t < P) {
@@ -496,7 +488,7 @@ __global__ void __launch_bounds__(64 * CA_WAVES)
         const int i = p % N1, j = (p / N1) % N1, k = p / (N1 * N1);
         if (interior_index(i, j, k, N1) < 0) out[e * N3 + p] = 0.f;
       }
-    wave_sync();  // the LDS region is rewritten for the next element
+    wave_lds_sync();  // the LDS region is rewritten for the next element
   }
 }
 
