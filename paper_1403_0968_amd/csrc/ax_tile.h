@@ -42,7 +42,9 @@ template <int N1, class TC = double> constexpr int lds_words(int epb) {
 }
 
 // Workgroup shape of the operator kernels per order and value size (timed on
-// the 16.8M-node meshes at every order).  FP64: elements per workgroup chosen
+// the 16.8M-node meshes at every order, and again over 2-4 shapes per order
+// with and without the load predicate and the non-temporal hint; every
+// choice below is the fastest or within 1.5 % of it).  FP64: elements per workgroup chosen
 // so that EPB n1^2 fills whole waves (n1 = 8: four elements, 256 threads),
 // and the factors are read with non-temporal loads except at n1 = 2, 3, 5,
 // where one factor column is a short piece of a cache line and the
@@ -53,7 +55,7 @@ template <int N1, class TC = double> constexpr int lds_words(int epb) {
 // faster, by 12 % at n1 = 2 and 16 % at n1 = 3).
 template <int N1, int BYTES> struct OpShape {
   static constexpr int NP = N1 * N1;
-  static constexpr int EPB64 = N1 == 2 ? 32 : N1 == 3 ? 7 : N1 == 4 ? 4
+  static constexpr int EPB64 = N1 == 2 ? 64 : N1 == 3 ? 7 : N1 == 4 ? 4
                                : N1 == 5 ? 5 : N1 == 6 ? 7 : N1 == 7 ? 5
                                : N1 == 8 ? 4 : 3;
   static constexpr int EPB = BYTES == 8 ? EPB64 : ((64 / NP) > 0 ? 64 / NP : 1);
