@@ -321,6 +321,77 @@ ITER_BYTES = {"fp64": (48 + 8 + 8, 8 + 16 + 8 + 8 + 40),
               "bf16": (12 + 4 + 4, 4 + 8 + 4 + 4 + 20)}
 
 
+def to_bf16_bits(torch, u32):
+    """BF16 bit patterns (int16) of an FP32 tensor, round to nearest even."""
+    b = (u32.view(torch.int32) + 0x7FFF + ((u32.view(torch.int32) >> 16) & 1)) >> 16
+    return b.to(torch.int16).contiguous()
+
+
+def bench_ax_forward_error(sem, torch, h, nL):
+    """Forward error of the operator in every precision against the oracle's
+    FP64 output on 8 elements of the benchmark mesh (tests/golden, written by
+    a script that runs the oracle only), for a random discontinuous input and
+    a smooth one: max |w - w_oracle| / max |w_oracle| over those elements."""
+    import importlib.util
+    import numpy as np
+    from seminputs import uniform
+    path = os.path.join(ROOT, "tests", "golden", "make_oracle_ax_samples.py")
+    spec = importlib.util.spec_from_file_location("oracle_ax_samples", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    if not os.path.exists(mod.PATH):
+        return None
+    els, ref = mod.read()
+    n3 = (ORDER + 1) ** 3
+    lid = torch.as_tensor((els[:, None] * n3 + np.arange(n3)[None, :]).reshape(-1),
+                          device="cuda")
+    X = torch.empty(3 * nL, dtype=torch.float64, device="cuda")
+    sem.sem_export(h, sem.SEM_ARR_COORDS, X)
+    inputs = {
+        "random": torch.as_tensor(uniform(nL, seed=0), device="cuda"),
+        "smooth": (torch.sin(2 * np.pi * X[:nL]) * torch.sin(2 * np.pi * X[nL:2 * nL])
+                   * torch.sin(2 * np.pi * X[2 * nL:])).contiguous()}
+    del X
+    out = {}
+    w64 = torch.empty(nL, dtype=torch.float64, device="cuda")
+    w32 = torch.empty(nL, dtype=torch.float32, device="cuda")
+    for name, u in inputs.items():
+        r = torch.as_tensor(ref[name], device="cuda")
+        scale = float(r.abs().max())
+        u32 = u.float()
+        ub = to_bf16_bits(torch, u32)
+        for prec, key, uu, ww in ((sem.SEM_FP64, "fp64", u, w64),
+                                  (sem.SEM_FP32, "fp32", u32, w32),
+                                  (sem.SEM_BF16, "bf16", ub, w32),
+                                  (sem.SEM_BF16_MFMA, "bf16_mfma", ub, w32)):
+            sem.sem_ax(h, prec, uu, ww)
+            torch.cuda.synchronize()
+            err = float((ww[lid].double() - r).abs().max()) / scale
+            out.setdefault(key, {})[name] = err
+        del u32, ub
+    del inputs
+    log(f"[bench] operator forward error vs the oracle: {out}")
+    return out
+
+
+def copy_reference(torch, nbytes=1 << 30, reps=20):
+    """What a plain device copy reaches (nbytes read + nbytes written)."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / reps
+    del a, b
+    return {"bytes_per_copy": 2 * nbytes, "us": us, "GBs": 2 * nbytes / (us * 1e-6) / 1e9}
+
+
 def oracle_reference(name):
     """The oracle's reference solution of a solve workload at sampled nodes
     (tests/golden, written by a script that runs the oracle only)."""
@@ -823,8 +894,7 @@ def main():
     u32 = u.float()
     w32 = torch.empty_like(u32)
     ms32 = time_ax(sem, torch, h, sem.SEM_FP32, u32, w32, args.steps, args.warmup)
-    ub = (u32.view(torch.int32) + 0x7FFF + ((u32.view(torch.int32) >> 16) & 1)) >> 16
-    ub = ub.to(torch.int16).contiguous()
+    ub = to_bf16_bits(torch, u32)
     msb = time_ax(sem, torch, h, sem.SEM_BF16, ub, w32, args.steps, args.warmup)
     msm = time_ax(sem, torch, h, sem.SEM_BF16_MFMA, ub, w32, args.steps, args.warmup)
     for name, t_ms, key in (("fp32", ms32, "f32"), ("bf16", msb, "bf16"),
@@ -834,11 +904,16 @@ def main():
             "alg_GBs": BYTES_PER_NODE[key] * nL / (t_ms * 1e-3) / 1e9,
             "frac_hbm": BYTES_PER_NODE[key] * nL / (t_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         log(f"[bench] {name} sem_ax {t_ms * 1e3:.1f} us/launch")
+    del u32, w32, ub
+    extra["forward_error_vs_oracle"] = bench_ax_forward_error(sem, torch, h, nL)
+    copy = copy_reference(torch)
+    copy["operator_frac_of_copy"] = achieved / copy["GBs"]
+    log(f"[bench] device copy {copy}")
 
     pcg = None if args.no_pcg else bench_pcg(sem, torch, h, nL, nG)
     sem.sem_destroy(h)
     config1 = None if args.no_pcg else bench_config1(sem, torch)
-    del u, w, u32, w32, ub
+    del u, w
     sweep = (None if args.no_sweep
              else bench_order_sweep(sem, torch, args.steps, args.warmup))
     fd2d = None if args.no_fd else bench_fd2d(sem, torch, args.steps)
@@ -875,6 +950,7 @@ def main():
             "frac_hbm_median": 64 * nL / (ax_stats["median_us"] * 1e-6) / 1e9
             / HBM_PEAK_GBS},
         "sem_gs_fp64": gs,
+        "hbm_copy_reference": copy,
         "config1": config1,
         "sem_ax_low_precision": extra,
         "order_sweep": sweep,
