@@ -747,6 +747,18 @@ struct sem_batch {
   sem::DevBuf axitems[3];       // per block size 64 / 128 / 256
   int n_ax[3] = {0, 0, 0};
   int n_vi = 0;
+  // The lists of the CG iteration kernels, compacted to the running solves
+  // as solves finish (run_cg rebuilds them whenever the running solves hold
+  // at most half of the listed vector chunks): each running solve keeps its
+  // items in their order, so its partial sums are added as before and its
+  // bits do not change.  Built from host copies of the full lists.
+  sem::DevBuf vitems_c, vbeg_c, axitems_c[3];
+  int n_vi_c = 0, n_ax_c[3] = {0, 0, 0};
+  bool compact = false;         // the iteration kernels use the compacted lists
+  int list_ver = 0;             // version of the compacted lists
+  std::vector<sem::VecItem> h_vis;
+  std::vector<sem::AxItem> h_ax[3];
+  std::vector<int32_t> h_vbeg, h_axbeg[3];  // per-solve item ranges
   int bs[5] = {128, 64, 64, 256, 256};  // operator block size per precision
   int gmul[5] = {0, 0, 0, 0, 0};  // persistent grid = 256 CUs x gmul (0: 1 item/WG)
   sem::CgState *host_st = nullptr;
@@ -762,7 +774,7 @@ struct sem_batch {
   hipStream_t s = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, fence = nullptr;
   struct GraphEntry {
-    int prec, k, jac, mode;
+    int prec, k, jac, mode, ver;  // ver: list version (0: the full lists)
     hipGraphExec_t exec;
   };
   // snapshot recording of solve 0 (training data), FP64 unique vectors
@@ -878,15 +890,26 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
     const int bss[3] = {64, 128, 256};
     for (int k = 0; k < 3; ++k) {
       std::vector<AxItem> ax;
+      b->h_axbeg[k].assign(n + 1, 0);
       for (int q = 0; q < n; ++q) {
+        b->h_axbeg[k][q] = (int32_t)ax.size();
         const int epb = bax_elements_per_tile(bss[k], hs[q]->n1);
         for (int64_t e = 0; e < hs[q]->E; e += epb) ax.push_back({q, 0, e});
       }
+      b->h_axbeg[k][n] = (int32_t)ax.size();
       b->n_ax[k] = (int)ax.size();
       b->axitems[k].alloc(ax.size() * sizeof(AxItem));
       SEM_HIP(hipMemcpy(b->axitems[k].p, ax.data(), ax.size() * sizeof(AxItem),
                         hipMemcpyHostToDevice));
+      if (n > 1) b->axitems_c[k].alloc(ax.size() * sizeof(AxItem));
+      b->h_ax[k] = std::move(ax);
     }
+    if (n > 1) {
+      b->vitems_c.alloc(vis.size() * sizeof(VecItem));
+      b->vbeg_c.alloc((n + 1) * sizeof(int32_t));
+    }
+    b->h_vis = vis;
+    b->h_vbeg = vbeg;
     b->hsd = sds;
     b->sds.alloc(n * sizeof(BatchSolve));
     SEM_HIP(hipMemcpy(b->sds.p, sds.data(), n * sizeof(BatchSolve),
@@ -936,6 +959,20 @@ void destroy_ws(sem_handle *h) {
 // assembly + r update at 11.4M unique nodes: 114 -> 104 us)
 static int vec_grid(const sem_batch *b) { return b->n_vi; }
 
+// the work lists of the CG iteration kernels: compacted while run_cg has
+// built them, else the full lists
+static const VecItem *it_vitems(const sem_batch *b) {
+  return b->compact ? b->vitems_c.as<VecItem>() : b->vitems.as<VecItem>();
+}
+static int it_nvi(const sem_batch *b) { return b->compact ? b->n_vi_c : b->n_vi; }
+static const int32_t *it_vbeg(const sem_batch *b) {
+  return b->compact ? b->vbeg_c.as<int32_t>() : b->vbeg.as<int32_t>();
+}
+static const AxItem *it_axitems(const sem_batch *b, int k) {
+  return b->compact ? b->axitems_c[k].as<AxItem>() : b->axitems[k].as<AxItem>();
+}
+static int it_nax(const sem_batch *b, int k) { return b->compact ? b->n_ax_c[k] : b->n_ax[k]; }
+
 // launch an assembly kernel in its variant for the batch's boxes: with a
 // periodic direction in any solve (PER_ = true) or without
 #define SEM_PER_LAUNCH(B, KERNEL, ...)                     \
@@ -984,8 +1021,8 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
     }
     const int k = bs_slot(256);
     launch_bax_mfma(b->nset, prec == SEM_BF16_MFMA, b->sds.as<BatchSolve>(),
-                    b->st.as<CgState>(), b->axitems[k].as<AxItem>(), b->n_ax[k],
-                    bax_elements_per_tile(256, b->nset), b->n_ax[k], src, dst,
+                    b->st.as<CgState>(), it_axitems(b, k), it_nax(b, k),
+                    bax_elements_per_tile(256, b->nset), it_nax(b, k), src, dst,
                     skip_done, edot, b->s);
     return;
   }
@@ -1011,10 +1048,10 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
   }
   const int bs = b->bs[prec];
   const int k = bs_slot(bs);
-  const int n = b->n_ax[k];
+  const int n = it_nax(b, k);
   const int grid = b->gmul[prec] > 0 ? std::min(n, 256 * b->gmul[prec]) : n;
   launch_bax(prec, bs, b->nset, b->sds.as<BatchSolve>(), b->st.as<CgState>(),
-             b->axitems[k].as<AxItem>(), n, grid, src, dst, skip_done, b->s);
+             it_axitems(b, k), n, grid, src, dst, skip_done, b->s);
 }
 
 // the single-solve kernels' view of the batch's one solve
@@ -1039,10 +1076,10 @@ template <class TV, class TD>
 static void iteration_t(sem_batch *b, int prec, int jac) {
   const BatchSolve *sds = b->sds.as<BatchSolve>();
   CgState *st = b->st.as<CgState>();
-  const VecItem *vi = b->vitems.as<VecItem>();
+  const VecItem *vi = it_vitems(b);
   double *part = b->part.as<double>();
-  const int32_t *vbeg = b->vbeg.as<int32_t>();
-  const int g = vec_grid(b), nv = b->n_vi, n = b->n;
+  const int32_t *vbeg = it_vbeg(b);
+  const int nv = it_nvi(b), g = nv, n = b->n;
   // (p, A p) from the operator's element energies (every operator form, the
   // matrix-core one included, stores them)
   bax(b, prec, VP, VWL, 1, true);
@@ -1194,8 +1231,9 @@ static void upload_active(sem_batch *b, const std::vector<int> &act,
 
 static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac,
                                 int mode) {
+  const int ver = b->compact ? b->list_ver : 0;
   for (auto &g : b->graphs)
-    if (g.prec == prec && g.k == K && g.jac == jac && g.mode == mode)
+    if (g.prec == prec && g.k == K && g.jac == jac && g.mode == mode && g.ver == ver)
       return g.exec;
   hipGraph_t graph;
   SEM_HIP(hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal));
@@ -1210,8 +1248,54 @@ static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac,
   hipGraphExec_t exec;
   SEM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   SEM_HIP(hipGraphDestroy(graph));
-  b->graphs.push_back({prec, K, jac, mode, exec});
+  b->graphs.push_back({prec, K, jac, mode, ver, exec});
   return exec;
+}
+
+// rebuild the iteration kernels' lists from the solves still running
+// (host_st as last polled), when they hold at most half of the vector
+// chunks of the lists in use; earlier compacted graphs are dropped
+static void maybe_compact(sem_batch *b) {
+  if (b->n < 2 || b->h_vis.empty()) return;
+  int64_t run_items = 0;
+  for (int q = 0; q < b->n; ++q)
+    if (b->host_st[q].done == 0) run_items += b->h_vbeg[q + 1] - b->h_vbeg[q];
+  if (run_items == 0 || 2 * run_items > it_nvi(b)) return;
+  std::vector<VecItem> vis;
+  std::vector<int32_t> vbeg(b->n + 1);
+  for (int q = 0; q < b->n; ++q) {
+    vbeg[q] = (int32_t)vis.size();
+    if (b->host_st[q].done == 0)
+      vis.insert(vis.end(), b->h_vis.begin() + b->h_vbeg[q],
+                 b->h_vis.begin() + b->h_vbeg[q + 1]);
+  }
+  vbeg[b->n] = (int32_t)vis.size();
+  SEM_HIP(hipMemcpyAsync(b->vitems_c.p, vis.data(), vis.size() * sizeof(VecItem),
+                         hipMemcpyHostToDevice, b->s));
+  SEM_HIP(hipMemcpyAsync(b->vbeg_c.p, vbeg.data(), vbeg.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, b->s));
+  for (int k = 0; k < 3; ++k) {
+    std::vector<AxItem> ax;
+    for (int q = 0; q < b->n; ++q)
+      if (b->host_st[q].done == 0)
+        ax.insert(ax.end(), b->h_ax[k].begin() + b->h_axbeg[k][q],
+                  b->h_ax[k].begin() + b->h_axbeg[k][q + 1]);
+    SEM_HIP(hipMemcpyAsync(b->axitems_c[k].p, ax.data(), ax.size() * sizeof(AxItem),
+                           hipMemcpyHostToDevice, b->s));
+    b->n_ax_c[k] = (int)ax.size();
+  }
+  // the host vectors are read by the copies above before they go away
+  SEM_HIP(hipStreamSynchronize(b->s));
+  b->n_vi_c = (int)vis.size();
+  for (auto it = b->graphs.begin(); it != b->graphs.end();)
+    if (it->ver != 0) {
+      (void)hipGraphExecDestroy(it->exec);
+      it = b->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  b->list_ver += 1;
+  b->compact = true;
 }
 
 // Run CG iterations until every solve's flag is set.  Returns true when the
@@ -1220,6 +1304,12 @@ static hipGraphExec_t get_graph(sem_batch *b, int prec, int K, int jac,
 // reason to fall back to Jacobi.
 static bool run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o,
                    int mode = 0, bool monitor = false, double ref_rate = 0.0) {
+  // the other passes over a batch (initialisation, residuals) use the full
+  // lists: the compacted ones live for one run of CG iterations
+  struct Restore {
+    sem_batch *b;
+    ~Restore() { b->compact = false; }
+  } restore{b};
   const int K = std::max(1, o->check_every);
   std::vector<std::pair<int, double>> hist;  // (iteration, best rr so far)
   double best = 0.0;
@@ -1255,6 +1345,7 @@ static bool run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o,
           break;
         }
     }
+    if (mode == 0) maybe_compact(b);
     if (o->use_graph)
       SEM_HIP(hipGraphLaunch(get_graph(b, prec, K, jac, mode), b->s));
     else
