@@ -721,7 +721,7 @@ def bench_batch(sem, torch, count=256):
 
 def cpu_baseline(cores, budget_s=15.0):
     """The FP64 oracle (test infrastructure, timed here as a reported
-    baseline only), as it stands, on the GPU machine's host:
+    baseline only), as it stands, on the host of the benchmark machine:
       * its operator on the first 2048 of the 32768 elements of the
         benchmark mesh, all threads (value) and one thread;
       * its Jacobi-PCG: config 1 solved to 1e-8 and 1e-10; configs 2 and 5

@@ -418,8 +418,8 @@ sem_status sem_mlp_loss_grad_factor(sem_mlp *net, const uint16_t *X,
 sem_status sem_mlp_adam(sem_mlp *net, const float *grad, double lr,
                         double beta1, double beta2, double eps, void *stream);
 /* Scale of the section 4.2.2 correction (damping >= 0) and the Jacobi
- * reference rate of the progress judge (log10 residual drop per Jacobi-PCG
- * iteration, <= 0; 0 disables the judge). */
+ * reference rate of the progress check (log10 residual drop per Jacobi-PCG
+ * iteration, <= 0; 0 disables the check). */
 sem_status sem_mlp_set_damping(sem_mlp *net, double damping, double jacobi_rate);
 /* See sem_mlp_set_damping (section 4.2.2 correction). */
 sem_status sem_mlp_get_damping(const sem_mlp *net, double *damping,
@@ -444,7 +444,7 @@ sem_status sem_learn_attach(sem_handle *h, sem_mlp *net);
 
 /* Attach the exact element coarse inverses M_e* (no network) for
  * SEM_PC_LEARNED, with the given damping (finite, >= 0) and no progress
- * judge: the section 4.2.2 correction that the network is trained to
+ * check: the section 4.2.2 correction that the network is trained to
  * imitate, for measuring what the network itself gains or loses.  Replaces
  * an attached network; sem_learn_attach (with a network or NULL) replaces
  * it.  N >= 2, no mass term. */

@@ -1054,7 +1054,7 @@ void learn_train(sem_handle *h, sem_mlp *net, const double *const *bL, int nrhs,
   const bool prev_exact = L->exact;
   const double prev_exact_d = L->exact_damping;
   const double rate = rate_n ? rate_sum / rate_n : 0.0;
-  mlp_set_damping(net, 1.0, 0.0);  // no progress judge while validating
+  mlp_set_damping(net, 1.0, 0.0);  // no progress check while validating
   learn_attach(h, net);
   sem_solve_opts vo{};
   vo.rtol = 1e-6;

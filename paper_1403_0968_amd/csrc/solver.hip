@@ -1327,7 +1327,7 @@ static bool run_cg(sem_batch *b, int prec, int jac, const sem_solve_opts *o,
       // energy norm), so both guards use the smallest residual so far.
       const CgState &c = b->host_st[0];
       best = hist.empty() ? c.rr : std::min(best, c.rr);
-      // progress judge: after 300 iterations the learned solve must have
+      // progress check: after 300 iterations the learned solve must have
       // reduced log10 ||r|| / ||b|| by at least 30% as much as Jacobi-PCG
       // does on average on this operator (ref_rate, measured on the
       // training solves; CG's own rate is uneven, so the bar is low: it

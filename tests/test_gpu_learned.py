@@ -248,7 +248,7 @@ def problem(sem):
                               solve_rtol=1e-11, seed=1)
     print(f"[train] {rep}", flush=True)
     t.cuda.synchronize()
-    # the ablation uses the trained network's damping and progress judge
+    # the ablation uses the trained network's damping and progress check
     sem.sem_mlp_set_damping(untrained, *sem.sem_mlp_get_damping(net))
     yield h, net, untrained, test, kap, rep
     sem.sem_learn_attach(h, None)
