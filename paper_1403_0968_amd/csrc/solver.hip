@@ -1460,7 +1460,7 @@ sem_status batch_solve(sem_batch *b, const sem_solve_opts *o,
     // FP64 iterative refinement: r = b - A64 x; the inner solve (PCG, or
     // flexible CG with the learned correction) solves A_lo d = r / ||r|| with
     // FP32 vectors and an FP32 or BF16-stored operator (FP64 dots and
-    // scalars); x += ||r|| d.  The FP64 true residual judges every step.
+    // scalars); x += ||r|| d.  The FP64 true residual decides every step.
     const int prec = o->inner_prec;
     std::vector<double> rel_prev(n, 1e300);
     std::vector<int> stall(n, 0);
