@@ -130,9 +130,13 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     }
     if (ks + 1 < NK) fetch(ks + 1);
     // fluxes at node 4 ks + kq of element e (zero beyond Np or the mesh)
-    const double u = hu / h, v = hv / h, p = hg * h * h;
-    const double F[3] = {hu, hu * u + p, hu * v};
-    const double G[3] = {hv, hv * u, hv * v + p};
+    // one reciprocal instead of two divisions (at N = 8 the kernel runs one
+    // wave per SIMD, so this vector work does not hide behind another
+    // wave's matrix instructions); hu v = hv u is formed once
+    const double ih = 1.0 / h, u = hu * ih, v = hv * ih, p = hg * h * h;
+    const double huv = hu * v;
+    const double F[3] = {hu, hu * u + p, huv};
+    const double G[3] = {hv, huv, hv * v + p};
     const bool ok = act && 4 * ks + kq < NP;
     double xr[3], xs[3];
 #pragma unroll
