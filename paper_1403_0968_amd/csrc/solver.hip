@@ -39,6 +39,7 @@
 #include <sstream>
 #include <string>
 
+#include "assemble.h"
 #include "common.h"
 #include "sem_internal.h"
 
@@ -191,33 +192,10 @@ __device__ __forceinline__ void xr_asm_chunk(const Box &bx, gp<const TV> wL, gp<
                                              int64_t start, int64_t nG, int q, int nitems,
                                              double *__restrict__ part, double *sm) {
   const int64_t end = min(start + (int64_t)VCH, nG);
-  // w_G at the node with coordinates pc: all (up to 8) copies loaded at
-  // once, predicated on existence, then summed in ascending local index
-  // (z, y, x copy order); an absent copy adds +0.0, which leaves the sum
-  // unchanged bit for bit (the sum starts at +0.0 and so is never -0.0).
-  // The local indices come from the per-direction terms (32-bit unless
-  // W64: some local index of the batch needs more)
+  // w_G at the node with coordinates pc (32-bit local indices unless W64:
+  // some local index of the batch needs more)
   using IT = typename std::conditional<W64, int64_t, uint32_t>::type;
-  auto assembled = [&](const Coord3 &pc) {
-    const CopyTerms<IT> ct = copy_terms<IT, PER>(bx, pc);
-    TV sw = TV(0);
-    if (!ct.masked) {
-      TV v[8];
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const bool ok = a < ct.z.cnt && b < ct.y.cnt && c < ct.x.cnt;
-            const IT lid = (a ? ct.z.t1 : ct.z.t0) + (b ? ct.y.t1 : ct.y.t0) +
-                           (c ? ct.x.t1 : ct.x.t0);
-            v[4 * a + 2 * b + c] = ok ? wL[lid] : TV(0);
-          }
-      sw = sum_copies(PER ? bx.order : 0, v);
-    }
-    return sw;
-  };
+  auto assembled = [&](const Coord3 &pc) { return assemble_node<TV, PER, IT>(bx, wL, pc); };
   double rz = 0.0, rr = 0.0, zw = 0.0;
   constexpr int K = VCH / RT;
   const int64_t g0 = start + threadIdx.x;
