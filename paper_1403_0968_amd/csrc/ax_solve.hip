@@ -17,7 +17,10 @@
 // elements that share nodes of the gathered vector (neighbours along x, y
 // and z) read the shared cache lines through the same L2: 102 -> 94 us at
 // 32^3, N = 7, FP32.  In FP64 the same order was slower (181 -> 186 us), so
-// FP64 keeps the plain order.
+// FP64 keeps the plain order.  The output is stored non-temporally, as in the
+// standalone operator (the E-vector is far larger than the caches): 188 ->
+// 182 us FP64, and the assembly that reads it next got faster too (FP32 56
+// -> 52 us).
 #include "ax_tile.h"
 
 namespace sem {
@@ -38,7 +41,7 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
   using S = OpShape<N1, sizeof(TC)>;
   __shared__ __align__(16) TC smem[lds_words<N1, TC>(S::EPB)];
   // the done flag of the solve is checked inside, after the loads are issued
-  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, false, MASS, S::NTG, EDOT, S::PRED>(
+  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, true, MASS, S::NTG, EDOT, S::PRED>(
       threadIdx.x,
       (sizeof(TV) == 4 ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x) *
           S::EPB,
