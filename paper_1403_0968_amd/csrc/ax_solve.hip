@@ -17,10 +17,10 @@
 // elements that share nodes of the gathered vector (neighbours along x, y
 // and z) read the shared cache lines through the same L2: 102 -> 94 us at
 // 32^3, N = 7, FP32.  In FP64 the same order was slower (181 -> 186 us), so
-// FP64 keeps the plain order.  The output is stored non-temporally, as in the
-// standalone operator (the E-vector is far larger than the caches): 188 ->
-// 182 us FP64, and the assembly that reads it next got faster too (FP32 56
-// -> 52 us).
+// FP64 keeps the plain order.  NTW (a solve whose vectors exceed the
+// last-level cache): the output is stored non-temporally, as in the
+// standalone operator: 188 -> 182 us FP64 at 32^3, N = 7, and the assembly
+// that reads it next got faster too (FP32 56 -> 52 us).
 #include "ax_tile.h"
 
 namespace sem {
@@ -32,7 +32,7 @@ __device__ inline int64_t xcd_run_block(unsigned b, unsigned nb) {
   return (int64_t)x * q + (x < r ? x : r) + k;
 }
 
-template <int N1, class TV, class TG, class TC, bool MASS, bool EDOT>
+template <int N1, class TV, class TG, class TC, bool MASS, bool EDOT, bool NTW>
 __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
     k_ax_solve(int64_t E, const TC *__restrict__ D, const TG *__restrict__ G,
                const TV *__restrict__ u, TV *__restrict__ w, Box box,
@@ -41,15 +41,15 @@ __global__ void __launch_bounds__((OpShape<N1, sizeof(TC)>::THREADS))
   using S = OpShape<N1, sizeof(TC)>;
   __shared__ __align__(16) TC smem[lds_words<N1, TC>(S::EPB)];
   // the done flag of the solve is checked inside, after the loads are issued
-  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, true, MASS, S::NTG, EDOT, S::PRED>(
+  ax_tile<N1, S::EPB, TV, TG, TV, TC, true, NTW, MASS, S::NTG, EDOT, S::PRED>(
       threadIdx.x,
       (sizeof(TV) == 4 ? xcd_run_block(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x) *
           S::EPB,
       E, D, G, u, w, &box, smem, H, edot, stop);
 }
 
-template <int N1, class TV, class TG, class TC, bool MASS>
-static void launch_solve_m(int64_t E, const void *D, const void *G,
+template <int N1, class TV, class TG, class TC, bool MASS, bool NTW>
+static void launch_solve_w(int64_t E, const void *D, const void *G,
                            const void *H, const void *u, void *w, const Box &box,
                            const int32_t *stop, double *edot, hipStream_t s) {
   using S = OpShape<N1, sizeof(TC)>;
@@ -57,49 +57,59 @@ static void launch_solve_m(int64_t E, const void *D, const void *G,
   if (blocks == 0) return;
   const dim3 grid((unsigned)blocks), block(S::THREADS);
   if (edot != nullptr)
-    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, MASS, true>), grid, block, 0, s,
+    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, MASS, true, NTW>), grid, block, 0, s,
                        E, (const TC *)D, (const TG *)G, (const TV *)u, (TV *)w,
                        box, stop, (const TG *)H, edot);
   else
-    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, MASS, false>), grid, block, 0,
+    hipLaunchKernelGGL((k_ax_solve<N1, TV, TG, TC, MASS, false, NTW>), grid, block, 0,
                        s, E, (const TC *)D, (const TG *)G, (const TV *)u, (TV *)w,
                        box, stop, (const TG *)H, edot);
+}
+
+template <int N1, class TV, class TG, class TC, bool MASS>
+static void launch_solve_m(int64_t E, const void *D, const void *G,
+                           const void *H, const void *u, void *w, const Box &box,
+                           const int32_t *stop, double *edot, bool nt, hipStream_t s) {
+  if (nt)
+    launch_solve_w<N1, TV, TG, TC, MASS, true>(E, D, G, H, u, w, box, stop, edot, s);
+  else
+    launch_solve_w<N1, TV, TG, TC, MASS, false>(E, D, G, H, u, w, box, stop, edot, s);
 }
 
 template <int N1, class TV, class TG, class TC>
 static void launch_solve_t(int64_t E, const void *D, const void *G,
                            const void *H, const void *u, void *w, const Box &box,
-                           const int32_t *stop, double *edot, hipStream_t s) {
+                           const int32_t *stop, double *edot, bool nt, hipStream_t s) {
   if (H != nullptr)
-    launch_solve_m<N1, TV, TG, TC, true>(E, D, G, H, u, w, box, stop, edot, s);
+    launch_solve_m<N1, TV, TG, TC, true>(E, D, G, H, u, w, box, stop, edot, nt, s);
   else
-    launch_solve_m<N1, TV, TG, TC, false>(E, D, G, H, u, w, box, stop, edot, s);
+    launch_solve_m<N1, TV, TG, TC, false>(E, D, G, H, u, w, box, stop, edot, nt, s);
 }
 
 template <int N1>
 static void launch_solve_n(int prec, int64_t E, const void *D, const void *G,
                            const void *H, const void *u, void *w, const Box &box,
-                           const int32_t *stop, double *edot, hipStream_t s) {
+                           const int32_t *stop, double *edot, bool nt, hipStream_t s) {
   if (prec == SEM_FP64)
-    launch_solve_t<N1, double, double, double>(E, D, G, H, u, w, box, stop, edot, s);
+    launch_solve_t<N1, double, double, double>(E, D, G, H, u, w, box, stop, edot, nt, s);
   else if (prec == SEM_FP32)
-    launch_solve_t<N1, float, float, float>(E, D, G, H, u, w, box, stop, edot, s);
+    launch_solve_t<N1, float, float, float>(E, D, G, H, u, w, box, stop, edot, nt, s);
   else
-    launch_solve_t<N1, float, uint16_t, float>(E, D, G, H, u, w, box, stop, edot, s);
+    launch_solve_t<N1, float, uint16_t, float>(E, D, G, H, u, w, box, stop, edot, nt, s);
 }
 
 void launch_ax_solve(int N, int prec, int64_t E, const void *D, const void *G,
                      const void *H, const void *u, void *w, const Box &box,
-                     const int32_t *stop, double *edot, hipStream_t s) {
+                     const int32_t *stop, double *edot, bool nt, hipStream_t s) {
   switch (N) {
-    case 1: launch_solve_n<2>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
-    case 2: launch_solve_n<3>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
-    case 3: launch_solve_n<4>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
-    case 4: launch_solve_n<5>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
-    case 5: launch_solve_n<6>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
-    case 6: launch_solve_n<7>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
-    case 7: launch_solve_n<8>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
-    case 8: launch_solve_n<9>(prec, E, D, G, H, u, w, box, stop, edot, s); break;
+    case 1: launch_solve_n<2>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
+    case 2: launch_solve_n<3>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
+    case 3: launch_solve_n<4>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
+    case 4: launch_solve_n<5>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
+    case 5: launch_solve_n<6>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
+    case 6: launch_solve_n<7>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
+    case 7: launch_solve_n<8>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
+    case 8: launch_solve_n<9>(prec, E, D, G, H, u, w, box, stop, edot, nt, s); break;
     default: fail(SEM_ERR_ARG, "solve: N must be in 1..8");
   }
   SEM_HIP(hipGetLastError());

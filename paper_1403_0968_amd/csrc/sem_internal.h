@@ -172,9 +172,10 @@ void launch_precond(sem_handle *h, int pc, int prec, const void *r, void *z,
 void launch_bax(int prec, int bs, int nset, const BatchSolve *sds,
                 const CgState *st, const AxItem *items, int nitems, int grid,
                 int src, int dst, int skip_done, hipStream_t s);
+// nt: store the output with the streaming hint (vectors beyond the caches)
 void launch_ax_solve(int N, int prec, int64_t E, const void *D, const void *G,
                      const void *H, const void *u, void *w, const Box &box,
-                     const int32_t *stop, double *edot, hipStream_t s);
+                     const int32_t *stop, double *edot, bool nt, hipStream_t s);
 void launch_ax_mfma(int N, bool split, int64_t E, const uint16_t *Dhi,
                     const uint16_t *Dlo, const uint16_t *G, const uint16_t *H,
                     const uint16_t *u, float *w, hipStream_t s);

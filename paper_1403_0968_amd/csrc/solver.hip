@@ -186,7 +186,21 @@ __global__ void __launch_bounds__(AT)
 // (r, z), (z, w_G), (r, r).  xr_asm_chunk updates the chunk [start, start +
 // VCH) of unique nodes; k_bupdate_xr_asm walks the work items of a batch,
 // k_xr_asm_1 the chunks of a single solve.
-template <class TV, class TD, bool FCG, bool PER, bool W64>
+// a load / store with the streaming (non-temporal) hint when NT
+template <bool NT, class P> __device__ inline auto ld_h(P p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+template <bool NT, class T, class P> __device__ inline void st_h(T v, P p) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+template <class TV, class TD, bool FCG, bool PER, bool W64, bool NT>
 __device__ __forceinline__ void xr_asm_chunk(const Box &bx, gp<const TV> wL, gp<TV> r,
                                              gp<TV> z, gp<const TD> dinv, TV alpha,
                                              int64_t start, int64_t nG, int q, int nitems,
@@ -202,8 +216,9 @@ __device__ __forceinline__ void xr_asm_chunk(const Box &bx, gp<const TV> wL, gp<
   if (g0 + (K - 1) * RT < end) {
     // a whole chunk: every load of the thread's K nodes before any store
     // (the compiler cannot know that w_L, r, z and dinv do not overlap).
-    // r and dinv stream non-temporally (next read an iteration later), z is
-    // stored normally for the x / p update right after: FP64 100 -> 87 us
+    // NT (a working set beyond the last-level cache): r and dinv stream
+    // non-temporally (next read an iteration later), z is stored normally
+    // for the x / p update right after: FP64 100 -> 87 us at 32^3, N = 7
     TV sw[K], rv[K];
     TD dv[K];
     // the thread's nodes are RT apart: their coordinates advance by carries
@@ -212,14 +227,14 @@ __device__ __forceinline__ void xr_asm_chunk(const Box &bx, gp<const TV> wL, gp<
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       sw[k] = assembled(pc);
-      rv[k] = __builtin_nontemporal_load(r + g0 + k * RT);
-      dv[k] = __builtin_nontemporal_load(dinv + g0 + k * RT);
+      rv[k] = ld_h<NT>(r + g0 + k * RT);
+      dv[k] = ld_h<NT>(dinv + g0 + k * RT);
       box_advance(bx, step, pc);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const TV rn = rv[k] - alpha * sw[k];
-      __builtin_nontemporal_store(rn, r + g0 + k * RT);
+      st_h<NT>(rn, r + g0 + k * RT);
       const TV zn = (TV)(dv[k] * rn);
       z[g0 + k * RT] = zn;
       rz += (double)rn * (double)zn;
@@ -257,15 +272,20 @@ __global__ void __launch_bounds__(RT)
     k_bupdate_xr_asm(const BatchSolve *__restrict__ sds,
                      const CgState *__restrict__ st,
                      const VecItem *__restrict__ items, int nitems,
-                     double *__restrict__ part, int jac) {
+                     double *__restrict__ part, int jac, int nt) {
   __shared__ double sm[RT / 64];
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    xr_asm_chunk<TV, TD, FCG, PER, W64>(
-        sd.box, vec<TV>(sd, VWL), vec<TV>(sd, VR), vec<TV>(sd, VZ), dinv_of<TD>(sd, jac),
-        (TV)st[it.solve].alpha, it.start, sd.nG, q, nitems, part, sm);
+    if (nt)
+      xr_asm_chunk<TV, TD, FCG, PER, W64, true>(
+          sd.box, vec<TV>(sd, VWL), vec<TV>(sd, VR), vec<TV>(sd, VZ), dinv_of<TD>(sd, jac),
+          (TV)st[it.solve].alpha, it.start, sd.nG, q, nitems, part, sm);
+    else
+      xr_asm_chunk<TV, TD, FCG, PER, W64, false>(
+          sd.box, vec<TV>(sd, VWL), vec<TV>(sd, VR), vec<TV>(sd, VZ), dinv_of<TD>(sd, jac),
+          (TV)st[it.solve].alpha, it.start, sd.nG, q, nitems, part, sm);
   }
 }
 
@@ -284,13 +304,18 @@ template <class TV, class TD> struct Vecs1 {
 template <class TV, class TD, bool FCG, bool PER, bool W64>
 __global__ void __launch_bounds__(RT)
     k_xr_asm_1(Vecs1<TV, TD> a, const CgState *__restrict__ st, int nitems,
-               double *__restrict__ part) {
+               double *__restrict__ part, int nt) {
   __shared__ double sm[RT / 64];
   if (st->done != 0) return;
   const int q = blockIdx.x;
-  xr_asm_chunk<TV, TD, FCG, PER, W64>(a.box, (gp<const TV>)a.wL, (gp<TV>)a.r,
-                                      (gp<TV>)a.z, (gp<const TD>)a.dinv, (TV)st->alpha,
-                                      (int64_t)q * VCH, a.nG, q, nitems, part, sm);
+  if (nt)
+    xr_asm_chunk<TV, TD, FCG, PER, W64, true>(
+        a.box, (gp<const TV>)a.wL, (gp<TV>)a.r, (gp<TV>)a.z, (gp<const TD>)a.dinv,
+        (TV)st->alpha, (int64_t)q * VCH, a.nG, q, nitems, part, sm);
+  else
+    xr_asm_chunk<TV, TD, FCG, PER, W64, false>(
+        a.box, (gp<const TV>)a.wL, (gp<TV>)a.r, (gp<TV>)a.z, (gp<const TD>)a.dinv,
+        (TV)st->alpha, (int64_t)q * VCH, a.nG, q, nitems, part, sm);
 }
 
 // rz, rr per solve -> convergence / beta
@@ -325,7 +350,7 @@ __global__ void __launch_bounds__(RT)
 
 // x += alpha p with this step's alpha (when k_bbeta found it finite, also
 // on the step that converged), then p = z + beta p while the solve runs
-template <class TV>
+template <class TV, bool NT>
 __device__ __forceinline__ void p_chunk(gp<const TV> z, gp<TV> p, gp<TV> x, TV alpha,
                                         TV beta, bool run, int64_t start, int64_t nG) {
   const int64_t end = min(start + (int64_t)VCH, nG);
@@ -334,20 +359,20 @@ __device__ __forceinline__ void p_chunk(gp<const TV> z, gp<TV> p, gp<TV> x, TV a
   if (run && g0 + (K - 1) * RT < end) {
     // a whole chunk: every load of the thread's K nodes before any store
     // (the compiler cannot know that x, p and z do not overlap): 78 -> 67
-    // us at 11.4M unique nodes in FP64.  x and z stream non-temporally (x
-    // is next read an iteration later, z not again); p (gathered by the next
-    // operator) keeps the normal hint, so that it can stay in the last-level
-    // cache
+    // us at 11.4M unique nodes in FP64.  NT: x and z stream non-temporally
+    // (x is next read an iteration later, z not again); p (gathered by the
+    // next operator) keeps the normal hint, so that it can stay in the
+    // last-level cache
     TV pv[K], xv[K], zv[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       pv[k] = p[g0 + k * RT];
-      xv[k] = __builtin_nontemporal_load(x + g0 + k * RT);
-      zv[k] = __builtin_nontemporal_load(z + g0 + k * RT);
+      xv[k] = ld_h<NT>(x + g0 + k * RT);
+      zv[k] = ld_h<NT>(z + g0 + k * RT);
     }
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      __builtin_nontemporal_store(xv[k] + alpha * pv[k], x + g0 + k * RT);
+      st_h<NT>(xv[k] + alpha * pv[k], x + g0 + k * RT);
       p[g0 + k * RT] = zv[k] + beta * pv[k];
     }
   } else if (run) {
@@ -364,25 +389,33 @@ __device__ __forceinline__ void p_chunk(gp<const TV> z, gp<TV> p, gp<TV> x, TV a
 template <class TV>
 __global__ void __launch_bounds__(RT)
     k_bupdate_p(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
-                const VecItem *__restrict__ items, int nitems) {
+                const VecItem *__restrict__ items, int nitems, int nt) {
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
     const CgState &c = st[it.solve];
     if (c.xupd == 0) continue;  // uniform per item
     const BatchSolve &sd = sds[it.solve];
-    p_chunk<TV>(vec<TV>(sd, VZ), vec<TV>(sd, VP), vec<TV>(sd, VX), (TV)c.alpha,
-                (TV)c.beta, c.done == 0, it.start, sd.nG);
+    if (nt)
+      p_chunk<TV, true>(vec<TV>(sd, VZ), vec<TV>(sd, VP), vec<TV>(sd, VX), (TV)c.alpha,
+                        (TV)c.beta, c.done == 0, it.start, sd.nG);
+    else
+      p_chunk<TV, false>(vec<TV>(sd, VZ), vec<TV>(sd, VP), vec<TV>(sd, VX), (TV)c.alpha,
+                         (TV)c.beta, c.done == 0, it.start, sd.nG);
   }
 }
 
 // the same for the chunks of a single solve
 template <class TV, class TD>
 __global__ void __launch_bounds__(RT)
-    k_p_1(Vecs1<TV, TD> a, const CgState *__restrict__ st) {
+    k_p_1(Vecs1<TV, TD> a, const CgState *__restrict__ st, int nt) {
   const CgState &c = *st;
   if (c.xupd == 0) return;
-  p_chunk<TV>((gp<const TV>)a.z, (gp<TV>)a.p, (gp<TV>)a.x, (TV)c.alpha, (TV)c.beta,
-              c.done == 0, (int64_t)blockIdx.x * VCH, a.nG);
+  if (nt)
+    p_chunk<TV, true>((gp<const TV>)a.z, (gp<TV>)a.p, (gp<TV>)a.x, (TV)c.alpha, (TV)c.beta,
+                      c.done == 0, (int64_t)blockIdx.x * VCH, a.nG);
+  else
+    p_chunk<TV, false>((gp<const TV>)a.z, (gp<TV>)a.p, (gp<TV>)a.x, (TV)c.alpha,
+                       (TV)c.beta, c.done == 0, (int64_t)blockIdx.x * VCH, a.nG);
 }
 
 // r = b - w (x0_zero: r = b and x = 0), z = dinv r, p = z; partials of
@@ -726,6 +759,7 @@ struct sem_batch {
   std::vector<sem::BatchSolve> hsd;  // host copies of the solve descriptors
   bool periodic = false;        // a solve of the batch has a periodic direction
   bool wide = false;            // a solve's local indices need 64 bits
+  int64_t sum_nG = 0, sum_nL = 0;  // unique and local nodes of all solves
   sem::DevBuf sds, st, vitems, vbeg, part, red, active, maxit, scale;
   sem::DevBuf axitems[3];       // per block size 64 / 128 / 256
   int n_ax[3] = {0, 0, 0};
@@ -864,6 +898,8 @@ sem_batch *batch_create(sem_handle *const *hs, int n) {
                         W->one32.as<float>(), W->edot.as<double>());
       if (h->periodic != 0) b->periodic = true;
       if (h->nL > (int64_t)UINT32_MAX) b->wide = true;
+      b->sum_nG += h->nG;
+      b->sum_nL += h->nL;
       vbeg[q] = (int32_t)vis.size();
       for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({q, 0, g});
       b->orders.push_back(h->n1);
@@ -941,6 +977,16 @@ void destroy_ws(sem_handle *h) {
 // workgroups the last round of chunks runs on part of the chip (FP64
 // assembly + r update at 11.4M unique nodes: 114 -> 104 us)
 static int vec_grid(const sem_batch *b) { return b->n_vi; }
+
+// Streaming (non-temporal) hints on the solver's vectors and operator output
+// when the batch's vectors (about five unique-node vectors and the E-vector,
+// of `tv` bytes per value) exceed half of the 256 MB last-level cache: their
+// next use is then an iteration away and they would not stay cached anyway;
+// smaller solves keep the normal hints and their vectors stay cached.
+constexpr double NT_BYTES = 128.0 * 1024 * 1024;
+static int stream_vectors(const sem_batch *b, size_t tv) {
+  return (double)tv * (5.0 * (double)b->sum_nG + (double)b->sum_nL) > NT_BYTES ? 1 : 0;
+}
 
 // the work lists of the CG iteration kernels: compacted while run_cg has
 // built them, else the full lists
@@ -1026,7 +1072,7 @@ static void bax(sem_batch *b, int prec, int src, int dst, int skip_done,
         skip_done ? &b->st.as<CgState>()[0].done : (const int32_t *)nullptr;
     launch_ax_solve(h->N, prec, h->E, D, G, H, u, w,
                     make_box(h->N, h->ex, h->ey, h->ez, h->dirichlet, h->periodic), stop,
-                    edot ? d.edot : nullptr, b->s);
+                    edot ? d.edot : nullptr, stream_vectors(b, f64 ? 8 : 4) != 0, b->s);
     return;
   }
   const int bs = b->bs[prec];
@@ -1065,20 +1111,21 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   const int nv = it_nvi(b), g = nv, n = b->n;
   // (p, A p) from the operator's element energies (every operator form, the
   // matrix-core one included, stores them)
+  const int nt = stream_vectors(b, sizeof(TV));
   bax(b, prec, VP, VWL, 1, true);
   hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
   if (b->n == 1)
     SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, false, PER_, W64_>), dim3(nv), dim3(RT), 0,
-                   b->s, vecs1<TV, TD>(b, jac), st, nv, part);
+                   b->s, vecs1<TV, TD>(b, jac), st, nv, part, nt);
   else
     SEM_ASM_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, false, PER_, W64_>), dim3(g), dim3(RT), 0,
-                   b->s, sds, st, vi, nv, part, jac);
+                   b->s, sds, st, vi, nv, part, jac, nt);
   hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
   if (b->n == 1)
     hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s,
-                       vecs1<TV, TD>(b, jac), st);
+                       vecs1<TV, TD>(b, jac), st, nt);
   else
-    hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi, nv);
+    hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi, nv, nt);
   SEM_HIP(hipGetLastError());
 }
 
@@ -1094,17 +1141,18 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
   const int nv = b->n_vi, n = b->n;
   sem_handle *h = b->hs[0];
   const bool f32 = sizeof(TV) == 4;
+  const int nt = stream_vectors(b, sizeof(TV));
   bax(b, prec, VP, VWL, 1, true);
   hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, b->sds.as<BatchSolve>(), st);
   SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, true, PER_, W64_>), dim3(nv), dim3(RT), 0, b->s,
-                 vecs1<TV, TD>(b, 1), st, nv, part);
+                 vecs1<TV, TD>(b, 1), st, nv, part, nt);
   const BatchSolve &d = b->hsd[0];
   learn_apply_fused(h, f32 ? d.v32[VR] : d.v64[VR], f32 ? d.v32[VZ] : d.v64[VZ],
                     f32 ? d.v32[VWL] : d.v64[VWL], f32, b->s);
   hipLaunchKernelGGL(k_bbeta_fcg_e, dim3(1), dim3(RT), 0, b->s, st, part, nv,
                      learn_epart(h), (int)h->E);
   hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s, vecs1<TV, TD>(b, 1),
-                     st);
+                     st, nt);
   SEM_HIP(hipGetLastError());
 }
 
@@ -1678,6 +1726,8 @@ sem_status pcg_solve_noalloc(sem_handle *h, const sem_solve_opts *o,
   b.hsd.assign(1, describe(h, 0, v64, v32, one64, nullptr, edot));
   b.periodic = h->periodic != 0;
   b.wide = h->nL > (int64_t)UINT32_MAX;
+  b.sum_nG = h->nG;
+  b.sum_nL = h->nL;
   std::vector<VecItem> vis;
   for (int64_t g = 0; g < h->nG; g += VCH) vis.push_back({0, 0, g});
   b.n_vi = (int)vis.size();
