@@ -29,6 +29,22 @@ template <class P> __device__ inline auto ld_stream(P p) {
   return __builtin_nontemporal_load(p);
 }
 
+// a double moved across the lanes of a wave by a DPP pattern (both halves)
+template <int CTRL> __device__ inline double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// the value of lane `lane` of a wave
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
 // LDS row pitch of the slice stacks: n1 + 1 (the 8 distinct rows a wave
 // reads at once sit in different banks), or 12 for FP32 arithmetic at n1 =
 // 8, where the r-direction rows are read as two 16-byte vectors: 16-byte
@@ -69,9 +85,9 @@ template <int N1, int BYTES> struct OpShape {
 // barriers.  smem holds 3 EPB n1^2 (n1+1) values of TC (8-byte aligned).
 // EDOT = true also stores the element energy edot[e] = u_e^T w_e in FP64,
 // summed in an order fixed by the node indices alone (each (i, j) column
-// over k, then, at n1 = 8, the 64 column sums by a butterfly over c =
-// i + 8 j, otherwise the columns of a row j over i and then the rows over
-// j), so that every tile shape gives the same bits.  Inside the solvers u is the
+// over k, then, at n1 = 8, the 64 column sums in registers by a fixed
+// pattern over the lanes c = i + 8 j, otherwise the columns of a row j over
+// i and then the rows over j), so that every tile shape gives the same bits.  Inside the solvers u is the
 // search direction p, which vanishes on Dirichlet nodes, and the sum of the
 // element energies is (p, A p) of the assembled operator.
 template <int N1, int EPB, class TU, class TG, class TW, class TC, bool GATHER,
@@ -295,12 +311,19 @@ __device__ __forceinline__ void ax_tile(int t, int64_t e0, int64_t E,
   }
   if constexpr (EDOT && NP == 64) {
     // n1 = 8: every element is one whole wave (its 64 columns are the lanes
-    // of a wave in every tile shape), so the column sums are added by a
-    // fixed butterfly over the lanes, without LDS or barriers
+    // of a wave in every tile shape), so the column sums are added in
+    // registers: lane exchanges within quads, then mirrored halves of each
+    // 8 and 16 lanes (each step adds two equal-sized partial sums, and
+    // a + b = b + a, so all lanes of a row hold the same bits), then the
+    // four row sums in order
     double v = cdot;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-    if (act && c == 0) edot[e] = v;
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    const double sum =
+        ((readlane_f64(v, 0) + readlane_f64(v, 16)) + readlane_f64(v, 32)) + readlane_f64(v, 48);
+    if (act && c == 0) edot[e] = sum;
   } else if constexpr (EDOT) {
     // s_u is no longer read after the barrier above: it holds the column
     // sums red[c] (c = i + n1 j) and then the row sums red[NP + j]
