@@ -267,25 +267,20 @@ __device__ __forceinline__ void xr_asm_chunk(const Box &bx, gp<const TV> wL, gp<
   }
 }
 
-template <class TV, class TD, bool FCG, bool PER, bool W64>
+template <class TV, class TD, bool FCG, bool PER, bool W64, bool NT>
 __global__ void __launch_bounds__(RT)
     k_bupdate_xr_asm(const BatchSolve *__restrict__ sds,
                      const CgState *__restrict__ st,
                      const VecItem *__restrict__ items, int nitems,
-                     double *__restrict__ part, int jac, int nt) {
+                     double *__restrict__ part, int jac) {
   __shared__ double sm[RT / 64];
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
     if (st[it.solve].done != 0) continue;
     const BatchSolve &sd = sds[it.solve];
-    if (nt)
-      xr_asm_chunk<TV, TD, FCG, PER, W64, true>(
-          sd.box, vec<TV>(sd, VWL), vec<TV>(sd, VR), vec<TV>(sd, VZ), dinv_of<TD>(sd, jac),
-          (TV)st[it.solve].alpha, it.start, sd.nG, q, nitems, part, sm);
-    else
-      xr_asm_chunk<TV, TD, FCG, PER, W64, false>(
-          sd.box, vec<TV>(sd, VWL), vec<TV>(sd, VR), vec<TV>(sd, VZ), dinv_of<TD>(sd, jac),
-          (TV)st[it.solve].alpha, it.start, sd.nG, q, nitems, part, sm);
+    xr_asm_chunk<TV, TD, FCG, PER, W64, NT>(
+        sd.box, vec<TV>(sd, VWL), vec<TV>(sd, VR), vec<TV>(sd, VZ), dinv_of<TD>(sd, jac),
+        (TV)st[it.solve].alpha, it.start, sd.nG, q, nitems, part, sm);
   }
 }
 
@@ -301,21 +296,17 @@ template <class TV, class TD> struct Vecs1 {
   const TD *dinv;
 };
 
-template <class TV, class TD, bool FCG, bool PER, bool W64>
+template <class TV, class TD, bool FCG, bool PER, bool W64, bool NT>
 __global__ void __launch_bounds__(RT)
     k_xr_asm_1(Vecs1<TV, TD> a, const CgState *__restrict__ st, int nitems,
-               double *__restrict__ part, int nt) {
+               double *__restrict__ part) {
   __shared__ double sm[RT / 64];
   if (st->done != 0) return;
   const int q = blockIdx.x;
-  if (nt)
-    xr_asm_chunk<TV, TD, FCG, PER, W64, true>(
-        a.box, (gp<const TV>)a.wL, (gp<TV>)a.r, (gp<TV>)a.z, (gp<const TD>)a.dinv,
-        (TV)st->alpha, (int64_t)q * VCH, a.nG, q, nitems, part, sm);
-  else
-    xr_asm_chunk<TV, TD, FCG, PER, W64, false>(
-        a.box, (gp<const TV>)a.wL, (gp<TV>)a.r, (gp<TV>)a.z, (gp<const TD>)a.dinv,
-        (TV)st->alpha, (int64_t)q * VCH, a.nG, q, nitems, part, sm);
+  xr_asm_chunk<TV, TD, FCG, PER, W64, NT>(a.box, (gp<const TV>)a.wL, (gp<TV>)a.r,
+                                          (gp<TV>)a.z, (gp<const TD>)a.dinv,
+                                          (TV)st->alpha, (int64_t)q * VCH, a.nG, q,
+                                          nitems, part, sm);
 }
 
 // rz, rr per solve -> convergence / beta
@@ -386,36 +377,28 @@ __device__ __forceinline__ void p_chunk(gp<const TV> z, gp<TV> p, gp<TV> x, TV a
   }
 }
 
-template <class TV>
+template <class TV, bool NT>
 __global__ void __launch_bounds__(RT)
     k_bupdate_p(const BatchSolve *__restrict__ sds, const CgState *__restrict__ st,
-                const VecItem *__restrict__ items, int nitems, int nt) {
+                const VecItem *__restrict__ items, int nitems) {
   for (int q = blockIdx.x; q < nitems; q += gridDim.x) {
     const VecItem it = items[q];
     const CgState &c = st[it.solve];
     if (c.xupd == 0) continue;  // uniform per item
     const BatchSolve &sd = sds[it.solve];
-    if (nt)
-      p_chunk<TV, true>(vec<TV>(sd, VZ), vec<TV>(sd, VP), vec<TV>(sd, VX), (TV)c.alpha,
-                        (TV)c.beta, c.done == 0, it.start, sd.nG);
-    else
-      p_chunk<TV, false>(vec<TV>(sd, VZ), vec<TV>(sd, VP), vec<TV>(sd, VX), (TV)c.alpha,
-                         (TV)c.beta, c.done == 0, it.start, sd.nG);
+    p_chunk<TV, NT>(vec<TV>(sd, VZ), vec<TV>(sd, VP), vec<TV>(sd, VX), (TV)c.alpha,
+                    (TV)c.beta, c.done == 0, it.start, sd.nG);
   }
 }
 
 // the same for the chunks of a single solve
-template <class TV, class TD>
+template <class TV, class TD, bool NT>
 __global__ void __launch_bounds__(RT)
-    k_p_1(Vecs1<TV, TD> a, const CgState *__restrict__ st, int nt) {
+    k_p_1(Vecs1<TV, TD> a, const CgState *__restrict__ st) {
   const CgState &c = *st;
   if (c.xupd == 0) return;
-  if (nt)
-    p_chunk<TV, true>((gp<const TV>)a.z, (gp<TV>)a.p, (gp<TV>)a.x, (TV)c.alpha, (TV)c.beta,
-                      c.done == 0, (int64_t)blockIdx.x * VCH, a.nG);
-  else
-    p_chunk<TV, false>((gp<const TV>)a.z, (gp<TV>)a.p, (gp<TV>)a.x, (TV)c.alpha,
-                       (TV)c.beta, c.done == 0, (int64_t)blockIdx.x * VCH, a.nG);
+  p_chunk<TV, NT>((gp<const TV>)a.z, (gp<TV>)a.p, (gp<TV>)a.x, (TV)c.alpha, (TV)c.beta,
+                  c.done == 0, (int64_t)blockIdx.x * VCH, a.nG);
 }
 
 // r = b - w (x0_zero: r = b and x = 0), z = dinv r, p = z; partials of
@@ -1015,6 +998,19 @@ static int it_nax(const sem_batch *b, int k) { return b->compact ? b->n_ax_c[k] 
     }                                                      \
   } while (0)
 
+// launch a vector kernel in its variant with (NT_ = true) or without the
+// streaming hints (stream_vectors)
+#define SEM_NT_LAUNCH(NT, KERNEL, ...)                     \
+  do {                                                     \
+    if (NT) {                                              \
+      constexpr bool NT_ = true;                           \
+      hipLaunchKernelGGL(KERNEL, __VA_ARGS__);             \
+    } else {                                               \
+      constexpr bool NT_ = false;                          \
+      hipLaunchKernelGGL(KERNEL, __VA_ARGS__);             \
+    }                                                      \
+  } while (0)
+
 // the same, with W64_ = true when some local index of the batch needs more
 // than 32 bits
 #define SEM_ASM_LAUNCH(B, KERNEL, ...)                     \
@@ -1025,6 +1021,19 @@ static int it_nax(const sem_batch *b, int k) { return b->compact ? b->n_ax_c[k] 
     } else {                                               \
       constexpr bool W64_ = false;                         \
       SEM_PER_LAUNCH(B, KERNEL, __VA_ARGS__);              \
+    }                                                      \
+  } while (0)
+
+// the same, also choosing the variant with (NT_ = true) or without the
+// streaming hints
+#define SEM_ASM_NT_LAUNCH(B, NT, KERNEL, ...)              \
+  do {                                                     \
+    if (NT) {                                              \
+      constexpr bool NT_ = true;                           \
+      SEM_ASM_LAUNCH(B, KERNEL, __VA_ARGS__);              \
+    } else {                                               \
+      constexpr bool NT_ = false;                          \
+      SEM_ASM_LAUNCH(B, KERNEL, __VA_ARGS__);              \
     }                                                      \
   } while (0)
 
@@ -1111,21 +1120,21 @@ static void iteration_t(sem_batch *b, int prec, int jac) {
   const int nv = it_nvi(b), g = nv, n = b->n;
   // (p, A p) from the operator's element energies (every operator form, the
   // matrix-core one included, stores them)
-  const int nt = stream_vectors(b, sizeof(TV));
+  const bool nt = stream_vectors(b, sizeof(TV)) != 0;
   bax(b, prec, VP, VWL, 1, true);
   hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, sds, st);
   if (b->n == 1)
-    SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, false, PER_, W64_>), dim3(nv), dim3(RT), 0,
-                   b->s, vecs1<TV, TD>(b, jac), st, nv, part, nt);
+    SEM_ASM_NT_LAUNCH(b, nt, (k_xr_asm_1<TV, TD, false, PER_, W64_, NT_>), dim3(nv),
+                      dim3(RT), 0, b->s, vecs1<TV, TD>(b, jac), st, nv, part);
   else
-    SEM_ASM_LAUNCH(b, (k_bupdate_xr_asm<TV, TD, false, PER_, W64_>), dim3(g), dim3(RT), 0,
-                   b->s, sds, st, vi, nv, part, jac, nt);
+    SEM_ASM_NT_LAUNCH(b, nt, (k_bupdate_xr_asm<TV, TD, false, PER_, W64_, NT_>), dim3(g),
+                      dim3(RT), 0, b->s, sds, st, vi, nv, part, jac);
   hipLaunchKernelGGL(k_bbeta, dim3(n), dim3(RT), 0, b->s, st, part, vbeg, nv);
   if (b->n == 1)
-    hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s,
-                       vecs1<TV, TD>(b, jac), st, nt);
+    SEM_NT_LAUNCH(nt, (k_p_1<TV, TD, NT_>), dim3(nv), dim3(RT), 0, b->s,
+                  vecs1<TV, TD>(b, jac), st);
   else
-    hipLaunchKernelGGL((k_bupdate_p<TV>), dim3(g), dim3(RT), 0, b->s, sds, st, vi, nv, nt);
+    SEM_NT_LAUNCH(nt, (k_bupdate_p<TV, NT_>), dim3(g), dim3(RT), 0, b->s, sds, st, vi, nv);
   SEM_HIP(hipGetLastError());
 }
 
@@ -1141,18 +1150,18 @@ static void iteration_fcg_t(sem_batch *b, int prec) {
   const int nv = b->n_vi, n = b->n;
   sem_handle *h = b->hs[0];
   const bool f32 = sizeof(TV) == 4;
-  const int nt = stream_vectors(b, sizeof(TV));
+  const bool nt = stream_vectors(b, sizeof(TV)) != 0;
   bax(b, prec, VP, VWL, 1, true);
   hipLaunchKernelGGL(k_balpha_e, dim3(n), dim3(AT), 0, b->s, b->sds.as<BatchSolve>(), st);
-  SEM_ASM_LAUNCH(b, (k_xr_asm_1<TV, TD, true, PER_, W64_>), dim3(nv), dim3(RT), 0, b->s,
-                 vecs1<TV, TD>(b, 1), st, nv, part, nt);
+  SEM_ASM_NT_LAUNCH(b, nt, (k_xr_asm_1<TV, TD, true, PER_, W64_, NT_>), dim3(nv), dim3(RT),
+                    0, b->s, vecs1<TV, TD>(b, 1), st, nv, part);
   const BatchSolve &d = b->hsd[0];
   learn_apply_fused(h, f32 ? d.v32[VR] : d.v64[VR], f32 ? d.v32[VZ] : d.v64[VZ],
                     f32 ? d.v32[VWL] : d.v64[VWL], f32, b->s);
   hipLaunchKernelGGL(k_bbeta_fcg_e, dim3(1), dim3(RT), 0, b->s, st, part, nv,
                      learn_epart(h), (int)h->E);
-  hipLaunchKernelGGL((k_p_1<TV, TD>), dim3(nv), dim3(RT), 0, b->s, vecs1<TV, TD>(b, 1),
-                     st, nt);
+  SEM_NT_LAUNCH(nt, (k_p_1<TV, TD, NT_>), dim3(nv), dim3(RT), 0, b->s, vecs1<TV, TD>(b, 1),
+                st);
   SEM_HIP(hipGetLastError());
 }
 
