@@ -8,7 +8,9 @@ for device code (``-packed-fp32-ops``).  The operator sources are compiled
 without machine-level instruction sinking: the element routine issues all of
 an element's loads before its first use of them, and sinking moves loads
 whose only uses lie past a branch (the LDS stores of a partial workgroup)
-down to those uses, which serialises the memory phases of the kernel.
+down to those uses, which serialises the memory phases of the kernel.  The
+DG volume kernel is compiled with the matrix instructions accumulating in
+ordinary vector registers.
 """
 from __future__ import annotations
 
@@ -32,6 +34,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
 
 PER_FILE = {f: ["-mllvm", "-disable-machine-sink"]
             for f in ("ax.hip", "ax_solve.hip")}
+# the DG volume kernel's FP64 matrix instructions accumulate in ordinary
+# vector registers (gfx950's register file is unified), which keeps the
+# compiler from copying loop-carried accumulators between register files
+PER_FILE["dg.hip"] = ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def _hipcc():

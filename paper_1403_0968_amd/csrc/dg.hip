@@ -27,10 +27,14 @@
 // apart.  Timed on the 212,800-element mesh against loading each step's
 // operands just before use (with separate Drw / Dsw accumulators from N = 7):
 // N = 2..8 20.2, 32.7, 55.4, 103, 129, 209, 313 us -> 17.9, 28.6, 44.1,
-// 91.4, 118, 167, 272 us.  The K loop is unrolled completely except at
-// N = 8, where that schedule is slower (373 us, and 294 us against 225 us
-// with the lane-order operator copies) than unrolling by two; at
-// N = 7 the kernel is held to two waves per SIMD's worth of registers.
+// 91.4, 118, 167, 272 us.  The K loop is unrolled completely; at N = 7 the
+// kernel is held to two waves per SIMD's worth of registers.  The
+// accumulators stay in ordinary vector registers (the source is compiled
+// with the matrix instructions' VGPR form): in the accumulation registers
+// the compiler copied the loop-carried ones in and out on every K step of
+// a partly unrolled loop (96 copies per two steps at N = 8), and at N = 8
+// that copying was what kept the K loop from being unrolled completely
+// (N = 6, 8: 79.4, 158.5 -> 74.5, 142.4 us).
 // Measured limits: a dependency-free loop of these instructions reaches
 // about 48 TFLOP/s on this chip (FP64 FMA on the vector units about 66).
 #include "common.h"
@@ -46,7 +50,6 @@ template <int N> struct DgShape {
   static constexpr int NP = (N + 1) * (N + 2) / 2;
   static constexpr int NT = (NP + 15) / 16;  // output row tiles
   static constexpr int NK = (NP + 3) / 4;    // K steps of four nodes
-  static constexpr int UNROLL = N == 8 ? 2 : NK;
   static constexpr int WAVES_PER_EU = N == 7 ? 2 : 1;
 };
 
@@ -97,11 +100,7 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
   // ks is the depth at its output row 16 t + kq + 4 v for ks = 4 t + v: kept
   // for the source term instead of loaded again (N = 4..7: 42.1, 85.0,
   // 109.2, 152.6 -> 39.4, 75.3, 105.5, 144.9 us)
-  constexpr bool KEEP_H = S::UNROLL == NK;
-  double hk[KEEP_H ? NK : 1];
-  // otherwise (N = 8) each lane parks them in LDS slots of its own (read back
-  // by the same lane only, so no barrier): 225 -> 211 us
-  __shared__ double hs[KEEP_H ? 1 : DG_WAVES * NK * 64];
+  double hk[NK];
   double qn[3], an[NT], sn[NT];  // operands of the next K step
   auto fetch = [&](int ks) {
     const int m = min(4 * ks + kq, NP - 1);
@@ -115,13 +114,10 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     }
   };
   fetch(0);
-#pragma unroll S::UNROLL
+#pragma unroll
   for (int ks = 0; ks < NK; ++ks) {
     const double h = qn[0], hu = qn[1], hv = qn[2];
-    if constexpr (KEEP_H)
-      hk[ks] = h;
-    else
-      hs[(wave * NK + ks) * 64 + lane] = h;
+    hk[ks] = h;
     double ar[NT], as[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
@@ -130,9 +126,7 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     }
     if (ks + 1 < NK) fetch(ks + 1);
     // fluxes at node 4 ks + kq of element e (zero beyond Np or the mesh)
-    // one reciprocal instead of two divisions (at N = 8 the kernel runs one
-    // wave per SIMD, so this vector work does not hide behind another
-    // wave's matrix instructions); hu v = hv u is formed once
+    // one reciprocal instead of two divisions; hu v = hv u is formed once
     const double ih = 1.0 / h, u = hu * ih, v = hv * ih, p = hg * h * h;
     const double huv = hu * v;
     const double F[3] = {hu, hu * u + p, huv};
@@ -165,15 +159,10 @@ __global__ void __launch_bounds__(64 * DG_WAVES)
     for (int v = 0; v < 4; ++v) {
       const int r = 16 * t + kq + 4 * v;
       if (r < NP) {
-        double hr;
         // r < Np puts 4 t + v below NK; the clamp only keeps the index in
         // range in code for rows r >= Np, which never runs
         const int KS = 4 * t + v < NK ? 4 * t + v : NK - 1;
-        if constexpr (KEEP_H)
-          hr = hk[KS];
-        else
-          hr = hs[(wave * NK + KS) * 64 + lane];
-        const double gh = g * hr;
+        const double gh = g * hk[KS];
         Re[r * CS] = acc[0][t][v];
         Re[(NP + r) * CS] = acc[1][t][v] - gh * Bx[r * CS];
         Re[(2 * NP + r) * CS] = acc[2][t][v] - gh * By[r * CS];
