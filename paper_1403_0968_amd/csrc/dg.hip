@@ -28,7 +28,8 @@
 // operands just before use (with separate Drw / Dsw accumulators from N = 7):
 // N = 2..8 20.2, 32.7, 55.4, 103, 129, 209, 313 us -> 17.9, 28.6, 44.1,
 // 91.4, 118, 167, 272 us.  The K loop is unrolled completely; at N = 7 the
-// kernel is held to two waves per SIMD's worth of registers.  The
+// kernel is compiled for at least two waves per SIMD (its 166 registers fit
+// three; the hint still shapes the schedule).  The
 // accumulators stay in ordinary vector registers (the source is compiled
 // with the matrix instructions' VGPR form): in the accumulation registers
 // the compiler copied the loop-carried ones in and out on every K step of
