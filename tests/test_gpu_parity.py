@@ -209,8 +209,6 @@ def test_ax_matrix_core_split_derivative(sem, pair):
     two-term BF16 split of D the residue is at the split's 2^-16 level, with
     D rounded to BF16 it is at 2^-9 (the error refinement cannot remove)."""
     m = pair.m
-    if m.N < 2:
-        pytest.skip("N = 1 has D exact in BF16")
     one = np.ones(m.nL)
     scale = np.max(orc.ax_abs(m, one))
     ws = _ax_gpu(sem, pair.h, one, sem.SEM_BF16_MFMA)
@@ -219,7 +217,14 @@ def test_ax_matrix_core_split_derivative(sem, pair):
     es, ep, ev = (np.max(np.abs(w)) / scale for w in (ws, wp, wv))
     print(f"[A 1, N={m.N}] split {es:.2e}, plain {ep:.2e}, VALU FP32-D {ev:.2e}")
     assert es <= 1e-4
-    assert ep >= 10 * es
+    if m.N < 2:
+        # N = 1: D = [[-1/2, 1/2], [-1/2, 1/2]] is exact in BF16, so its low
+        # term vanishes (up to the host's rounding of D) and both forms agree:
+        # A 1 = 0 to the split's level with D rounded as well
+        assert ep <= 1e-4
+        assert np.max(np.abs(ws - wp)) <= 1e-6 * scale
+    else:
+        assert ep >= 10 * es
 
 
 def test_ax_matrix_core_transposed_split(sem, pair):
@@ -231,15 +236,20 @@ def test_ax_matrix_core_transposed_split(sem, pair):
     2^-9 -- this exercises the transposed stage, where A 1 (zero fluxes)
     cannot."""
     m = pair.m
-    if m.N < 3:
-        pytest.skip("at N <= 2 every entry of D is exact in BF16")
     u = uniform(m.nL, seed=15)
     n3 = m.n1 ** 3
     scale = orc.ax_abs(m, np.abs(bf16_round(u)[0])).reshape(m.E, n3).sum(1)
-    ws = _ax_gpu(sem, pair.h, u, sem.SEM_BF16_MFMA).reshape(m.E, n3).sum(1)
-    wp = _ax_gpu(sem, pair.h, u, sem.SEM_BF16_PLAIN_D).reshape(m.E, n3).sum(1)
+    wfs = _ax_gpu(sem, pair.h, u, sem.SEM_BF16_MFMA)
+    wfp = _ax_gpu(sem, pair.h, u, sem.SEM_BF16_PLAIN_D)
+    ws = wfs.reshape(m.E, n3).sum(1)
+    wp = wfp.reshape(m.E, n3).sum(1)
     es = float(np.max(np.abs(ws) / scale))
     ep = float(np.max(np.abs(wp) / scale))
     print(f"[element sums of w, N={m.N}] split {es:.2e}, plain {ep:.2e}")
     assert es <= 1e-4
-    assert ep >= 10 * es
+    if m.N < 3:
+        # at N <= 2 every entry of D is exact in BF16: the split's low term
+        # vanishes (up to the host's rounding of D) and both forms agree
+        assert np.max(np.abs(wfs - wfp)) <= 1e-6 * np.max(np.abs(wfp))
+    else:
+        assert ep >= 10 * es
