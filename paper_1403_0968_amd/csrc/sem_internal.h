@@ -110,7 +110,11 @@ struct VecItem {  // a chunk of unique nodes of one solve
   int32_t solve, pad;
   int64_t start;
 };
-constexpr int VCH = 2048;      // unique nodes per vector item
+// unique nodes per vector item (one workgroup of a vector kernel, four per
+// thread; against 2048 at 32^3 and 24^3, N = 7: FP64 iteration 345.4 ->
+// 342.3 and 164.7 -> 161.3 us, 4^3 mesh 30.8 -> 28.5 us, the loop of 256
+// small solves 10.9 -> 10.3 s; 512 and 4096 were slower)
+constexpr int VCH = 1024;
 constexpr int AX_SET_468 = 100;  // batched operator compiled for n1 in {4,6,8}
 
 }  // namespace sem

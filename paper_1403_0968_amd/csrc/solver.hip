@@ -60,9 +60,9 @@ static_assert(VCH % RT == 0, "chunk must be a multiple of the block");
 template <int NA>
 __device__ inline void strided_sums(const double *__restrict__ part, int stride,
                                     int begin, int end, double (&acc)[NA]) {
-  // 11.4M unique nodes make 5562 chunks: 22 partials per thread, all in
+  // 11.4M unique nodes make 11124 chunks: 44 partials per thread, all in
   // flight at once
-  constexpr int PF = NA >= 3 ? 16 : 24;
+  constexpr int PF = NA >= 3 ? 24 : 48;
 #pragma unroll
   for (int a = 0; a < NA; ++a) acc[a] = 0.0;
   for (int q = begin + (int)threadIdx.x; q < end; q += PF * RT) {
