@@ -209,10 +209,17 @@ def bench_order_sweep(sem, torch, steps, warmup, target_nodes=NE ** 3 * 512):
     return out
 
 
+# launches timed per point of the fd2d and DG sweeps at least: the fixed
+# cost between the start event and the first kernel would otherwise add
+# several us to a 140 us kernel timed over 20 launches
+MIN_SWEEP_LAUNCHES = 100
+
+
 def time_launches(torch, launch, steps, min_warm_s=0.2):
-    """ms per launch of `steps` back-to-back launches on torch's current
-    stream (the stream the library launches on), after >= min_warm_s of
-    warm-up launches."""
+    """ms per launch of max(steps, MIN_SWEEP_LAUNCHES) back-to-back launches
+    on torch's current stream (the stream the library launches on), after
+    >= min_warm_s of warm-up launches."""
+    steps = max(steps, MIN_SWEEP_LAUNCHES)
     t0 = time.perf_counter()
     n = 0
     while time.perf_counter() - t0 < min_warm_s:
